@@ -1,0 +1,255 @@
+/*
+ * amm.h -- C ABI of the MI355X (gfx950) library for robust non-rigid
+ * registration by accelerated majorization-minimization (Yao, Deng, Xu,
+ * Zhang, "Fast and Robust Non-Rigid Registration Using Accelerated
+ * Majorization-Minimization", arXiv 2206.03410).
+ *
+ * Problem (Sec. 3 of the paper): source points V = {v_i} (i < n_src),
+ * target points U = {u_l} (l < n_tgt), an embedded deformation graph whose
+ * nodes p_j are a subset of V, per-point influence sets I(v_i) of k nodes
+ * with weights w_ij (Eq. 3), and undirected node edges E_G.  Unknowns are
+ * one affine transform X_j = [A_j, t_j] per node.  The library minimizes
+ *     E(X) = E_align + alpha E_reg + beta E_rot                     (Eq. 4)
+ * with Welsch's function on alignment and regularization residuals
+ * (Eqs. 5-9), by MM iterations whose quadratic surrogate is minimized
+ * through the normal equations K X = B (Eq. 16), accelerated by Anderson
+ * acceleration with an energy-decrease fallback, inside the nu
+ * continuation of Alg. 2.
+ *
+ * Conventions (every call):
+ *  - Floating-point arrays have the element type named by the call
+ *    (amm_dtype); integer arrays are int32.  Layouts are row-major and
+ *    contiguous.  Points are [count][3].
+ *  - Transforms X are [n_nodes][4][3]: rows 0..2 hold A_j^T, row 3 holds
+ *    t_j^T; this is the block X_j of the paper's stacked X in R^{4n x 3}.
+ *  - Unless a parameter says "host", pointers are device pointers on the
+ *    handle's device.  Work is ordered on the handle's stream; calls that
+ *    return host values synchronize that stream before returning.
+ *  - The library never keeps a caller pointer: what it needs is copied.
+ *  - A handle is not thread-safe: one call at a time per handle.
+ *  - Every call returns an amm_status; on failure amm_last_error() gives a
+ *    message.  No call aborts the process.
+ */
+#ifndef AMM_H
+#define AMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMM_OK = 0,
+    AMM_ERR_INVALID_ARG = 1, /* null pointer, bad size, index out of range */
+    AMM_ERR_STATE = 2,       /* call order (e.g. solve before set_problem) */
+    AMM_ERR_OOM = 3,         /* device allocation failed / workspace too small */
+    AMM_ERR_HIP = 4,         /* a HIP runtime call failed (no device, ...) */
+    AMM_ERR_NONFINITE = 5,   /* NaN or Inf in an input, or the iteration blew up */
+    AMM_ERR_GRAPH = 6,       /* weights do not sum to 1, node graph disconnected, ... */
+    AMM_ERR_NOT_SPD = 7      /* K not positive definite (CG breakdown) */
+} amm_status;
+
+typedef enum { AMM_F32 = 0, AMM_F64 = 1 } amm_dtype;
+
+/* Arithmetic of the solve.
+ * AMM_FP64_PLAIN : every step in float64; the linear solve is float64
+ *                  preconditioned CG to the requested relative residual.
+ * AMM_FP32_REFINE: closest points, warp, weights, energies and assembly in
+ *                  float32; the solve is float32 preconditioned CG inside
+ *                  float64 iterative refinement (float64 residual B - K X and
+ *                  float64 solution accumulator); the Anderson Gram matrix
+ *                  and its solve are float64. */
+typedef enum { AMM_FP64_PLAIN = 0, AMM_FP32_REFINE = 1 } amm_precision;
+
+typedef struct amm_handle amm_handle;
+
+/* One registration problem.  `on_device` = 1: the pointers are device
+ * pointers; 0: host pointers.  Normals are optional (NULL) and unused by the
+ * energy of Eq. (5), which is point-to-point; they are validated when given. */
+typedef struct {
+    amm_dtype dtype;              /* type of src_xyz, src_nrm, tgt_xyz, tgt_nrm, infl_w */
+    int32_t on_device;
+    int64_t n_src;
+    const void* src_xyz;          /* [n_src][3] */
+    const void* src_nrm;          /* [n_src][3] or NULL */
+    int64_t n_tgt;
+    const void* tgt_xyz;          /* [n_tgt][3] */
+    const void* tgt_nrm;          /* [n_tgt][3] or NULL */
+    int64_t n_nodes;
+    const int32_t* node_src_idx;  /* [n_nodes] distinct indices into V (nodes lie on V) */
+    int32_t k;                    /* influences per point, 1 <= k <= 8, k <= n_nodes */
+    const int32_t* infl_idx;      /* [n_src][k] node ids (0 <= id < n_nodes, distinct per row) */
+    const void* infl_w;           /* [n_src][k] weights of Eq. (3); each row sums to 1 */
+    int64_t n_edges;
+    const int32_t* edges;         /* [n_edges][2] undirected node edges, i != j, no duplicates */
+    double mean_edge_len;         /* average source edge length l (Sec. 3.3.3), > 0 */
+} amm_problem;
+
+typedef struct {
+    /* nu continuation (Sec. 3.3.3).  Each value <= 0 selects the paper's
+     * rule: nu_a0 = median closest-point distance at the initial X,
+     * nu_a_min = mean_edge_len / sqrt(3), nu_r0 = 3 mean_edge_len. */
+    double nu_a0, nu_a_min, nu_r0;
+    /* term weights of Eq. (21): alpha = k_alpha |V|/|E_G| nu_r^2/nu_a^2,
+     * beta = k_beta |V|/|V_G| / (2 nu_a^2), recomputed at every stage. */
+    double k_alpha, k_beta;
+    double eps;                   /* stage ends when max_i |v_hat_i^{k+1} - v_hat_i^k| < eps */
+    int32_t imax;                 /* surrogate solves per stage at most */
+    int32_t max_total_iters;      /* surrogate solves overall at most; 0 = no cap */
+    int32_t aa_m;                 /* Anderson depth m, 0 <= m <= AMM_MAX_AA_M (0 = plain MM) */
+    int32_t precision;            /* amm_precision */
+    double cg_rtol;               /* relative residual |B - K X| / |B| per column, e.g. 1e-10 */
+    int32_t cg_maxit;             /* CG iterations per solve at most (0 = 20000) */
+    int32_t init_identity;        /* 1: start from X = I (ignore X_inout's contents) */
+    /* Replay of decisions (host arrays, may be NULL): entry t applies to the
+     * t-th surrogate solve.  force_accept: -1 decide, 0 reject the Anderson
+     * candidate, 1 accept it.  force_stage_end: -1 decide, 0 continue the
+     * stage, 1 end it. */
+    const int8_t* force_accept;
+    const int8_t* force_stage_end;
+    int32_t force_len;
+} amm_params;
+
+#define AMM_MAX_AA_M 10
+
+/* Fills p with the paper's defaults: eps = 1e-5, imax = 100 (Sec. 4.1),
+ * k_alpha = 100, k_beta = 1, aa_m = 5, nu rules, FP32 refinement,
+ * cg_rtol = 1e-10, start from identity. */
+void amm_params_default(amm_params* p);
+
+typedef struct {
+    int32_t iters;               /* surrogate solves performed */
+    int32_t stages;              /* nu stages entered */
+    int32_t converged;           /* 1 if the last stage (nu_a at its bound) met eps */
+    int32_t aa_accepted, aa_rejected;
+    int64_t cg_iters;            /* total CG iterations (all refinement steps) */
+    int32_t refine_steps;        /* total iterative-refinement steps (FP32_REFINE) */
+    double energy, e_align, e_reg, e_rot; /* at the returned X, final nu */
+    double nu_a, nu_r, alpha, beta;       /* final stage values */
+    double max_disp;             /* last max displacement */
+    double max_rel_residual;     /* worst final relative residual over all solves */
+    double time_ms;              /* wall time of the solve for this pair */
+} amm_stats;
+
+/* ---------------------------------------------------------------- handle */
+
+/* Creates a handle on `device` that orders its work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Fails with AMM_ERR_HIP when no
+ * such device exists. */
+amm_status amm_create(amm_handle** h, int device, void* hip_stream);
+void amm_destroy(amm_handle* h);
+amm_status amm_set_stream(amm_handle* h, void* hip_stream);
+
+/* ---------------------------------------------------------------- problem */
+
+/* Host-only validation of a problem given by HOST pointers (on_device = 0);
+ * needs no GPU.  Checks sizes, finiteness (AMM_ERR_NONFINITE), index ranges
+ * (AMM_ERR_INVALID_ARG), partition of unity of the weights within 1e-5 and a
+ * connected node graph without duplicate or self edges (AMM_ERR_GRAPH). */
+amm_status amm_check_problem(const amm_problem* p);
+
+/* Device bytes that amm_set_problems needs for these problems (a static
+ * analysis of the inputs; the result is exact). */
+amm_status amm_workspace_size(amm_handle* h, const amm_problem* probs, int32_t n_pairs,
+                              size_t* bytes);
+
+/* Hands the library a caller-owned device buffer (256-byte aligned) that
+ * amm_set_problems carves all its device memory from; it must outlive the
+ * handle's use of the problems.  ptr = NULL reverts to library-owned memory
+ * (allocated once, in amm_set_problems). */
+amm_status amm_set_workspace(amm_handle* h, void* ptr, size_t bytes);
+
+/* Validates and uploads a batch of independent registration problems
+ * (n_pairs >= 1, all with the same k).  Computes the edge weights r_ij of
+ * Eq. (8), a spatial ordering of points and nodes, the block pattern of K,
+ * and the nearest-neighbour structure over each target set (a bounding-box
+ * tree over Morton-ordered targets).  Replaces any previous problems. */
+amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_pairs);
+amm_status amm_set_problem(amm_handle* h, const amm_problem* p);
+
+/* ---------------------------------------------------------------- solve */
+
+/* Alg. 2 for every pair set on the handle, all pairs advancing together.
+ * X_inout: concatenation over pairs of [n_nodes][4][3] in the precision's
+ * type (float32 for AMM_FP32_REFINE, float64 for AMM_FP64_PLAIN); read as
+ * the start unless params->init_identity, overwritten with the result.
+ * v_out: concatenation of [n_src][3] deformed source points (Eq. 2 at the
+ * result), same type; may be NULL.  stats: host array of n_pairs entries,
+ * may be NULL.  Non-convergence within imax / max_total_iters is not an
+ * error (stats.converged = 0). */
+amm_status amm_solve(amm_handle* h, const amm_params* params, void* X_inout, void* v_out,
+                     amm_stats* stats);
+
+/* ---------------------------------------------------------------- single step */
+
+typedef struct {
+    const void* X;           /* [n_nodes][4][3] current iterate X^k (pair 0) */
+    double nu_a, nu_r, alpha, beta;
+    int32_t precision;       /* amm_precision */
+    double cg_rtol;
+    int32_t cg_maxit;
+} amm_step_in;
+
+typedef struct {
+    double energy[4];        /* host: E, E_align, E_reg, E_rot at X^k */
+    int32_t* rho;            /* [n_src] closest target index per point, or NULL */
+    void* d2;                /* [n_src] squared closest distance, or NULL */
+    void* v_hat;             /* [n_src][3] warped points at X^k, or NULL */
+    void* X_next;            /* [n_nodes][4][3] minimizer of the surrogate, or NULL */
+    /* Normal equations of Eq. (16) at X^k in node order of the caller, or NULL:
+     * K_blocks [nnzb][4][4], K_row/K_col [nnzb] node ids, B [n_nodes][4][3].
+     * Query nnzb with amm_k_nnzb. */
+    void* K_blocks;
+    int32_t* K_row;
+    int32_t* K_col;
+    void* B;
+    int32_t cg_iters;        /* host */
+    double rel_residual;     /* host */
+} amm_step_out;
+
+/* One surrogate solve at explicit (nu_a, nu_r, alpha, beta) for pair 0,
+ * teacher-forced from X^k: closest points and energy at X^k, assembly of
+ * K, B and their solve.  For checking each step against a reference. */
+amm_status amm_step(amm_handle* h, const amm_step_in* in, amm_step_out* out);
+amm_status amm_k_nnzb(amm_handle* h, int64_t* nnzb);
+
+/* ---------------------------------------------------------------- energy and gradient */
+
+/* E(X) of Eq. (4) for pair 0 at transforms X and source positions src
+ * (NULL = the stored source), both of type `dtype` (which also selects the
+ * arithmetic).  energy: host double[4] = {E, E_align, E_reg, E_rot}.
+ * rho (int32 [n_src]) and d2 ([n_src], dtype) may be NULL.  The graph
+ * (p_j, w_ij, r_ij) is the one given to amm_set_problem. */
+amm_status amm_energy(amm_handle* h, amm_dtype dtype, const void* X, const void* src,
+                      double nu_a, double nu_r, double alpha, double beta, double* energy,
+                      int32_t* rho, void* d2);
+
+/* Gradient of E with respect to X (gX [n_nodes][4][3]) and the source
+ * positions (gV [n_src][3]), both of type `dtype`, with the closest points
+ * of the evaluation held fixed and the graph frozen: only the v_i appearing
+ * explicitly in Eq. (2) move with the source.  gV may be NULL.  energy as in
+ * amm_energy (may be NULL). */
+amm_status amm_energy_grad(amm_handle* h, amm_dtype dtype, const void* X, const void* src,
+                           double nu_a, double nu_r, double alpha, double beta, void* gX,
+                           void* gV, double* energy);
+
+/* ---------------------------------------------------------------- misc */
+
+const char* amm_status_string(amm_status s);
+const char* amm_last_error(const amm_handle* h);   /* h may be NULL: last global error */
+
+/* Per-kernel timing of the last amm_solve, accumulated with HIP events on
+ * the handle's stream: names[i] (static strings) and ms[i], i < *count. */
+amm_status amm_kernel_times(amm_handle* h, const char** names, double* ms, int32_t* launches,
+                            int32_t capacity, int32_t* count);
+amm_status amm_enable_timing(amm_handle* h, int32_t on);
+
+/* Version string of the library build. */
+const char* amm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMM_H */

@@ -1,0 +1,297 @@
+"""ctypes binding of libamm.so: the C ABI of include/amm.h under the same
+names.  Argument marshalling only -- every step of the registration runs in
+the library's HIP kernels.  Device arrays are torch tensors (their
+data_ptr()), host arrays are numpy arrays; the library never keeps them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libamm.so")
+
+AMM_OK, AMM_ERR_INVALID_ARG, AMM_ERR_STATE, AMM_ERR_OOM, AMM_ERR_HIP, AMM_ERR_NONFINITE, \
+    AMM_ERR_GRAPH, AMM_ERR_NOT_SPD = range(8)
+AMM_F32, AMM_F64 = 0, 1
+AMM_FP64_PLAIN, AMM_FP32_REFINE = 0, 1
+AMM_MAX_AA_M = 10
+
+
+class amm_problem(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("on_device", C.c_int32),
+                ("n_src", C.c_int64), ("src_xyz", C.c_void_p), ("src_nrm", C.c_void_p),
+                ("n_tgt", C.c_int64), ("tgt_xyz", C.c_void_p), ("tgt_nrm", C.c_void_p),
+                ("n_nodes", C.c_int64), ("node_src_idx", C.c_void_p),
+                ("k", C.c_int32), ("infl_idx", C.c_void_p), ("infl_w", C.c_void_p),
+                ("n_edges", C.c_int64), ("edges", C.c_void_p),
+                ("mean_edge_len", C.c_double)]
+
+
+class amm_params(C.Structure):
+    _fields_ = [("nu_a0", C.c_double), ("nu_a_min", C.c_double), ("nu_r0", C.c_double),
+                ("k_alpha", C.c_double), ("k_beta", C.c_double), ("eps", C.c_double),
+                ("imax", C.c_int32), ("max_total_iters", C.c_int32), ("aa_m", C.c_int32),
+                ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
+                ("init_identity", C.c_int32),
+                ("force_accept", C.c_void_p), ("force_stage_end", C.c_void_p),
+                ("force_len", C.c_int32)]
+
+
+class amm_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("stages", C.c_int32), ("converged", C.c_int32),
+                ("aa_accepted", C.c_int32), ("aa_rejected", C.c_int32),
+                ("cg_iters", C.c_int64), ("refine_steps", C.c_int32),
+                ("energy", C.c_double), ("e_align", C.c_double), ("e_reg", C.c_double),
+                ("e_rot", C.c_double), ("nu_a", C.c_double), ("nu_r", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("max_disp", C.c_double),
+                ("max_rel_residual", C.c_double), ("time_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class amm_step_in(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("nu_a", C.c_double), ("nu_r", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("precision", C.c_int32),
+                ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32)]
+
+
+class amm_step_out(C.Structure):
+    _fields_ = [("energy", C.c_double * 4), ("rho", C.c_void_p), ("d2", C.c_void_p),
+                ("v_hat", C.c_void_p), ("X_next", C.c_void_p), ("K_blocks", C.c_void_p),
+                ("K_row", C.c_void_p), ("K_col", C.c_void_p), ("B", C.c_void_p),
+                ("cg_iters", C.c_int32), ("rel_residual", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                               "`python -m paper_2206_03410_amd.build_lib`")
+        L = C.CDLL(_LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "amm_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+            "amm_destroy": ([vp], None),
+            "amm_set_stream": ([vp, vp], C.c_int),
+            "amm_check_problem": ([C.POINTER(amm_problem)], C.c_int),
+            "amm_workspace_size": ([vp, C.POINTER(amm_problem), i32, C.POINTER(C.c_size_t)], C.c_int),
+            "amm_set_workspace": ([vp, vp, C.c_size_t], C.c_int),
+            "amm_set_problems": ([vp, C.POINTER(amm_problem), i32], C.c_int),
+            "amm_set_problem": ([vp, C.POINTER(amm_problem)], C.c_int),
+            "amm_solve": ([vp, C.POINTER(amm_params), vp, vp, C.POINTER(amm_stats)], C.c_int),
+            "amm_step": ([vp, C.POINTER(amm_step_in), C.POINTER(amm_step_out)], C.c_int),
+            "amm_k_nnzb": ([vp, C.POINTER(i64)], C.c_int),
+            "amm_energy": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, C.POINTER(dbl), vp, vp], C.c_int),
+            "amm_energy_grad": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, vp, vp, C.POINTER(dbl)],
+                                C.c_int),
+            "amm_status_string": ([C.c_int], C.c_char_p),
+            "amm_last_error": ([vp], C.c_char_p),
+            "amm_kernel_times": ([vp, C.POINTER(C.c_char_p), C.POINTER(dbl), C.POINTER(i32), i32,
+                                  C.POINTER(i32)], C.c_int),
+            "amm_enable_timing": ([vp, i32], C.c_int),
+            "amm_version": ([], C.c_char_p),
+            "amm_params_default": ([C.POINTER(amm_params)], None),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
+            "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
+            "amm_solve", "amm_step", "amm_k_nnzb", "amm_energy", "amm_energy_grad",
+            "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
+            "amm_version", "amm_params_default"]
+
+
+class AmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{amm_status_string(status)}: {msg}")
+        self.status = status
+
+
+def _check(status, handle=None):
+    if status != AMM_OK:
+        raise AmmError(status, amm_last_error(handle))
+
+
+def _ptr(a):
+    """Device pointer of a torch tensor or host pointer of a numpy array."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return a.ctypes.data
+    if not a.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return a.data_ptr()
+
+
+def _dtype_code(a):
+    name = str(a.dtype)
+    if "float32" in name:
+        return AMM_F32
+    if "float64" in name:
+        return AMM_F64
+    raise TypeError(f"floating-point arrays must be float32 or float64, got {a.dtype}")
+
+
+# ------------------------------------------------------------------ API
+
+def amm_status_string(status: int) -> str:
+    return lib().amm_status_string(status).decode()
+
+
+def amm_last_error(handle=None) -> str:
+    return (lib().amm_last_error(handle) or b"").decode()
+
+
+def amm_version() -> str:
+    return lib().amm_version().decode()
+
+
+def amm_params_default(**override) -> amm_params:
+    p = amm_params()
+    lib().amm_params_default(C.byref(p))
+    for k, v in override.items():
+        setattr(p, k, v)
+    return p
+
+
+def amm_create(device: int = 0, stream: Optional[int] = None):
+    h = C.c_void_p()
+    _check(lib().amm_create(C.byref(h), device, stream))
+    return h
+
+
+def amm_destroy(handle) -> None:
+    lib().amm_destroy(handle)
+
+
+def amm_set_stream(handle, stream: Optional[int]) -> None:
+    _check(lib().amm_set_stream(handle, stream), handle)
+
+
+def make_problem(src, tgt, node_idx, infl_idx, infl_w, edges, mean_edge_len,
+                 src_nrm=None, tgt_nrm=None):
+    """amm_problem over torch tensors (device) or numpy arrays (host).  The
+    returned object keeps references to the arrays."""
+    on_dev = not isinstance(src, np.ndarray)
+    k = int(infl_idx.shape[1])
+    p = amm_problem(dtype=_dtype_code(src), on_device=1 if on_dev else 0,
+                    n_src=int(src.shape[0]), src_xyz=_ptr(src), src_nrm=_ptr(src_nrm),
+                    n_tgt=int(tgt.shape[0]), tgt_xyz=_ptr(tgt), tgt_nrm=_ptr(tgt_nrm),
+                    n_nodes=int(node_idx.shape[0]), node_src_idx=_ptr(node_idx),
+                    k=k, infl_idx=_ptr(infl_idx), infl_w=_ptr(infl_w),
+                    n_edges=int(edges.shape[0]), edges=_ptr(edges),
+                    mean_edge_len=float(mean_edge_len))
+    p._keep = (src, tgt, node_idx, infl_idx, infl_w, edges, src_nrm, tgt_nrm)
+    return p
+
+
+def amm_check_problem(problem: amm_problem) -> int:
+    """Host-only validation; returns the status code (no exception)."""
+    return lib().amm_check_problem(C.byref(problem))
+
+
+def amm_workspace_size(handle, problems: Sequence[amm_problem]) -> int:
+    arr = (amm_problem * len(problems))(*problems)
+    n = C.c_size_t()
+    _check(lib().amm_workspace_size(handle, arr, len(problems), C.byref(n)), handle)
+    return n.value
+
+
+def amm_set_workspace(handle, tensor_or_none) -> None:
+    if tensor_or_none is None:
+        _check(lib().amm_set_workspace(handle, None, 0), handle)
+    else:
+        nbytes = tensor_or_none.numel() * tensor_or_none.element_size()
+        _check(lib().amm_set_workspace(handle, tensor_or_none.data_ptr(), nbytes), handle)
+
+
+def amm_set_problems(handle, problems: Sequence[amm_problem]) -> None:
+    arr = (amm_problem * len(problems))(*problems)
+    _check(lib().amm_set_problems(handle, arr, len(problems)), handle)
+
+
+def amm_set_problem(handle, problem: amm_problem) -> None:
+    _check(lib().amm_set_problem(handle, C.byref(problem)), handle)
+
+
+def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: int = 1,
+              force_accept=None, force_stage_end=None) -> List[dict]:
+    keep = []
+    if force_accept is not None or force_stage_end is not None:
+        n = max(len(force_accept or []), len(force_stage_end or []))
+        fa = np.full(n, -1, np.int8)
+        fs = np.full(n, -1, np.int8)
+        if force_accept is not None:
+            fa[:len(force_accept)] = [-1 if v is None else int(v) for v in force_accept]
+        if force_stage_end is not None:
+            fs[:len(force_stage_end)] = [-1 if v is None else int(v) for v in force_stage_end]
+        keep = [fa, fs]
+        params.force_accept = fa.ctypes.data
+        params.force_stage_end = fs.ctypes.data
+        params.force_len = n
+    stats = (amm_stats * n_pairs)()
+    _check(lib().amm_solve(handle, C.byref(params), _ptr(X_inout), _ptr(v_out), stats), handle)
+    del keep
+    return [s.as_dict() for s in stats]
+
+
+def amm_step(handle, X, nu_a, nu_r, alpha, beta, precision, cg_rtol=1e-10, cg_maxit=0,
+             rho=None, d2=None, v_hat=None, X_next=None, K_blocks=None, K_row=None, K_col=None,
+             B=None) -> dict:
+    sin = amm_step_in(X=_ptr(X), nu_a=nu_a, nu_r=nu_r, alpha=alpha, beta=beta,
+                      precision=precision, cg_rtol=cg_rtol, cg_maxit=cg_maxit)
+    sout = amm_step_out(rho=_ptr(rho), d2=_ptr(d2), v_hat=_ptr(v_hat), X_next=_ptr(X_next),
+                        K_blocks=_ptr(K_blocks), K_row=_ptr(K_row), K_col=_ptr(K_col), B=_ptr(B))
+    _check(lib().amm_step(handle, C.byref(sin), C.byref(sout)), handle)
+    return dict(energy=list(sout.energy), cg_iters=sout.cg_iters, rel_residual=sout.rel_residual)
+
+
+def amm_k_nnzb(handle) -> int:
+    n = C.c_int64()
+    _check(lib().amm_k_nnzb(handle, C.byref(n)), handle)
+    return n.value
+
+
+def amm_energy(handle, X, src=None, nu_a=1.0, nu_r=1.0, alpha=0.0, beta=0.0, rho=None, d2=None):
+    e = (C.c_double * 4)()
+    _check(lib().amm_energy(handle, _dtype_code(X), _ptr(X), _ptr(src), nu_a, nu_r, alpha, beta, e,
+                            _ptr(rho), _ptr(d2)), handle)
+    return list(e)
+
+
+def amm_energy_grad(handle, X, src, nu_a, nu_r, alpha, beta, gX, gV=None):
+    e = (C.c_double * 4)()
+    _check(lib().amm_energy_grad(handle, _dtype_code(X), _ptr(X), _ptr(src), nu_a, nu_r, alpha, beta,
+                                 _ptr(gX), _ptr(gV), e), handle)
+    return list(e)
+
+
+def amm_enable_timing(handle, on: bool = True) -> None:
+    _check(lib().amm_enable_timing(handle, 1 if on else 0), handle)
+
+
+def amm_kernel_times(handle) -> dict:
+    cap = 64
+    names = (C.c_char_p * cap)()
+    ms = (C.c_double * cap)()
+    n_l = (C.c_int32 * cap)()
+    cnt = C.c_int32()
+    _check(lib().amm_kernel_times(handle, names, ms, n_l, cap, C.byref(cnt)), handle)
+    return {names[i].decode(): (ms[i], n_l[i]) for i in range(min(cnt.value, cap))}

@@ -1,0 +1,1322 @@
+// C ABI of the registration library and the host driver of Alg. 2
+// (nu continuation around Anderson-accelerated MM iterations).
+//
+// The driver keeps per-pair scalar state on the host and launches batched
+// kernels over every pair that is still running; per-pair decisions (accept
+// the Anderson candidate, end a stage, finish) are taken after one small
+// device-to-host copy of the pair energies per MM iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "amm.h"
+#include "amm_internal.h"
+#include "amm_kernels.h"
+
+using namespace amm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+const char* kVersion = "amm-gfx950 0.1";
+constexpr int kDynRing = 16;
+
+struct EventTimer final : KernelTimer {
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> pending;
+    const char* cur_name = nullptr;
+    hipEvent_t cur_a = nullptr;
+    struct Acc {
+        const char* name;
+        double ms;
+        int n;
+    };
+    std::vector<Acc> acc;
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    void begin(const char* name, hipStream_t s) override {
+        cur_name = name;
+        cur_a = get();
+        (void)hipEventRecord(cur_a, s);
+    }
+    void end(hipStream_t s) override {
+        hipEvent_t b = get();
+        (void)hipEventRecord(b, s);
+        pending.push_back({cur_name, cur_a, b});
+    }
+    void collect() {
+        for (auto& r : pending) {
+            (void)hipEventSynchronize(r.b);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, r.a, r.b);
+            bool found = false;
+            for (auto& x : acc)
+                if (std::strcmp(x.name, r.name) == 0) {
+                    x.ms += ms;
+                    x.n += 1;
+                    found = true;
+                }
+            if (!found) acc.push_back({r.name, (double)ms, 1});
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    ~EventTimer() override {
+        for (auto& r : pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// Carves one device buffer into aligned arrays (or just sums their sizes).
+struct Carver {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename P>
+    void take(P*& ptr, size_t count) {
+        off = (off + 255) & ~size_t(255);
+        ptr = base ? reinterpret_cast<P*>(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(P);
+    }
+};
+
+template <typename T>
+struct StaticT {
+    typename V4Of<T>::type* src = nullptr;
+    T* iw = nullptr;
+    typename V4Of<T>::type* nodes = nullptr;
+    typename V4Of<T>::type* tgt = nullptr;
+    typename V4Of<T>::type* blo = nullptr;
+    typename V4Of<T>::type* bhi = nullptr;
+    T* adj_r = nullptr;
+};
+
+// Dynamic arrays are sized for 8-byte elements and reinterpreted for float.
+struct Dyn {
+    double* X[3];
+    double* x64;
+    double* vhat[2];   // 4 per point
+    int* rho[2];
+    double* d2[2];
+    double* qw[2];     // 4 per point
+    double* wr[2];
+    double* Dres[2];   // 4 per entry
+    double* R[2];      // 9 per node
+    double* pt_part;
+    double* pt_max;
+    double* eg_part;
+    double* nd_part;
+    double* Kval;
+    double* B;
+    double* Dinv;
+    double* cg[7];     // x r u w p s rhs
+    double* part_ru;
+    double* part_rr;
+    double* part_wu;
+    double* part_bb;
+    double* part_rr64;
+    double* part_bb64;
+    double* G;
+    double* F;
+    double* aa_part;
+    double* gpt;       // 4 per point
+    double* src_ovr;   // 4 per point
+    double* pts_out;   // 4 per point
+};
+
+struct Dev {
+    int* iidx;
+    int* src_user;
+    int* node_user;
+    int* node_pair;
+    int* adj_ptr;
+    int* adj_nbr;
+    int* adj_row;
+    int* adj_rev;
+    int* K_ptr;
+    int* K_col;
+    int* K_adj;
+    int* pj_ptr;
+    int* pj_ent;
+    int* tgt_user;
+    int4* pt_tiles;
+    int4* nd_tiles;
+    int4* eg_tiles;
+    PairInfo* info;
+    PairDyn* dyn;        // slot of dyn_ring used by the next launches
+    PairDyn* dyn_ring;   // [kDynRing][P]
+    PairOut* out;
+    CgState* state;
+    double* staging;   // float64 staging for static arrays during upload
+    StaticT<float> sf;
+    StaticT<double> sd;
+    Dyn d;
+};
+
+void plan(const Layout& L, Carver& c, Dev& v) {
+    const size_t N = L.Ntot, M = L.Mtot, n = L.ntot, na = L.nadj, nb = L.nnzb, tn = L.tree_nodes;
+    const size_t npt = L.n_pt_tiles, nnd = L.n_nd_tiles, neg = L.n_eg_tiles;
+    const size_t k = L.k;
+    c.take(v.iidx, k * N);
+    c.take(v.src_user, N);
+    c.take(v.node_user, n);
+    c.take(v.node_pair, n);
+    c.take(v.adj_ptr, n + 1);
+    c.take(v.adj_nbr, na);
+    c.take(v.adj_row, na);
+    c.take(v.adj_rev, na);
+    c.take(v.K_ptr, n + 1);
+    c.take(v.K_col, nb);
+    c.take(v.K_adj, nb);
+    c.take(v.pj_ptr, n + 1);
+    c.take(v.pj_ent, L.pj_entries);
+    c.take(v.tgt_user, M);
+    c.take(v.pt_tiles, npt);
+    c.take(v.nd_tiles, nnd);
+    c.take(v.eg_tiles, neg);
+    c.take(v.info, L.P);
+    c.take(v.dyn_ring, (size_t)kDynRing * L.P);
+    v.dyn = v.dyn_ring;
+    c.take(v.out, L.P);
+    c.take(v.state, 2 * (size_t)L.P);
+    size_t stage = std::max({4 * N, 4 * M, 4 * tn, k * N, 4 * n, na});
+    c.take(v.staging, stage);
+    auto statics = [&](auto& s) {
+        c.take(s.src, N);
+        c.take(s.iw, k * N);
+        c.take(s.nodes, n);
+        c.take(s.tgt, M);
+        c.take(s.blo, tn);
+        c.take(s.bhi, tn);
+        c.take(s.adj_r, na);
+    };
+    statics(v.sf);
+    statics(v.sd);
+    Dyn& d = v.d;
+    for (int q = 0; q < 3; ++q) c.take(d.X[q], 12 * n);
+    c.take(d.x64, 12 * n);
+    for (int q = 0; q < 2; ++q) {
+        c.take(d.vhat[q], 4 * N);
+        c.take(d.rho[q], N);
+        c.take(d.d2[q], N);
+        c.take(d.qw[q], 4 * N);
+        c.take(d.wr[q], na);
+        c.take(d.Dres[q], 4 * na);
+        c.take(d.R[q], 9 * n);
+    }
+    c.take(d.pt_part, npt);
+    c.take(d.pt_max, npt);
+    c.take(d.eg_part, neg);
+    c.take(d.nd_part, nnd);
+    c.take(d.Kval, 16 * nb);
+    c.take(d.B, 12 * n);
+    c.take(d.Dinv, 16 * n);
+    for (int q = 0; q < 7; ++q) c.take(d.cg[q], 12 * n);
+    c.take(d.part_ru, 3 * nnd);
+    c.take(d.part_rr, 3 * nnd);
+    c.take(d.part_wu, 3 * nnd);
+    c.take(d.part_bb, 3 * nnd);
+    c.take(d.part_rr64, 3 * nnd);
+    c.take(d.part_bb64, 3 * nnd);
+    c.take(d.G, (AMM_MAX_AA_M + 1) * 12 * n);
+    c.take(d.F, (AMM_MAX_AA_M + 1) * 12 * n);
+    c.take(d.aa_part, (size_t)kAaParts * nnd);
+    c.take(d.gpt, 4 * N);
+    c.take(d.src_ovr, 4 * N);
+    c.take(d.pts_out, 4 * N);
+}
+
+}  // namespace
+
+
+struct amm_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void* ws_user = nullptr;
+    size_t ws_user_bytes = 0;
+    void* ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    bool has_problem = false;
+    Layout L;
+    Dev v{};
+    std::vector<double> lbar;
+    std::vector<PairDyn> dyn;        // host working copy of the per-pair parameters
+    PairDyn* dyn_pinned = nullptr;   // [kDynRing][P] staging for uploads
+    hipEvent_t dyn_ev[kDynRing] = {};
+    bool dyn_ev_live[kDynRing] = {};
+    int dyn_slot = 0;
+    PairOut* h_out = nullptr;        // pinned
+    CgState* h_state = nullptr;      // pinned
+    size_t h_cap = 0;
+    bool timing = false;
+    EventTimer timer;
+};
+
+namespace {
+
+amm_status fail(amm_handle* h, amm_status s, const std::string& msg) {
+    if (h) h->err = msg;
+    g_last_error = msg;
+    return s;
+}
+
+#define HIPC(expr)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return fail(h, AMM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+#define TRY(expr)                          \
+    do {                                   \
+        amm_status s_ = (expr);            \
+        if (s_ != AMM_OK) return s_;       \
+    } while (0)
+
+KernelTimer* tmr(amm_handle* h) { return h->timing ? &h->timer : nullptr; }
+
+amm_status read_pair(amm_handle* h, const amm_problem& p, HostPair& hp) {
+    if (p.n_src < 1 || p.n_tgt < 1 || p.n_nodes < 1 || p.k < 1 || p.k > kMaxK || p.n_edges < 0)
+        return fail(h, AMM_ERR_INVALID_ARG, "bad sizes in amm_problem");
+    if (!p.src_xyz || !p.tgt_xyz || !p.node_src_idx || !p.infl_idx || !p.infl_w || (p.n_edges > 0 && !p.edges))
+        return fail(h, AMM_ERR_INVALID_ARG, "null array in amm_problem");
+    if (p.dtype != AMM_F32 && p.dtype != AMM_F64) return fail(h, AMM_ERR_INVALID_ARG, "bad dtype");
+    hp.N = p.n_src;
+    hp.M = p.n_tgt;
+    hp.n = p.n_nodes;
+    hp.E = p.n_edges;
+    hp.k = p.k;
+    hp.lbar = p.mean_edge_len;
+    const size_t es = p.dtype == AMM_F32 ? 4 : 8;
+    auto fetch = [&](const void* src, size_t bytes, void* dst) -> bool {
+        if (!bytes) return true;
+        if (p.on_device) return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+        std::memcpy(dst, src, bytes);
+        return true;
+    };
+    auto fetch_real = [&](const void* src, size_t count, std::vector<double>& out) -> bool {
+        if (!src || !count) {
+            out.clear();
+            return true;
+        }
+        out.resize(count);
+        if (es == 8) return fetch(src, count * 8, out.data());
+        std::vector<float> tmp(count);
+        if (!fetch(src, count * 4, tmp.data())) return false;
+        for (size_t i = 0; i < count; ++i) out[i] = tmp[i];
+        return true;
+    };
+    if (p.on_device && hipDeviceSynchronize() != hipSuccess)
+        return fail(h, AMM_ERR_HIP, "device synchronization failed before reading the problem");
+    bool ok = fetch_real(p.src_xyz, 3 * hp.N, hp.src) && fetch_real(p.tgt_xyz, 3 * hp.M, hp.tgt) &&
+              fetch_real(p.src_nrm, 3 * hp.N, hp.src_nrm) && fetch_real(p.tgt_nrm, 3 * hp.M, hp.tgt_nrm) &&
+              fetch_real(p.infl_w, (size_t)hp.k * hp.N, hp.infl_w);
+    hp.node_idx.resize(hp.n);
+    hp.infl_idx.resize((size_t)hp.k * hp.N);
+    hp.edges.resize(2 * hp.E);
+    ok = ok && fetch(p.node_src_idx, 4 * hp.n, hp.node_idx.data()) &&
+         fetch(p.infl_idx, 4 * (size_t)hp.k * hp.N, hp.infl_idx.data()) &&
+         fetch(p.edges, 8 * (size_t)hp.E, hp.edges.data());
+    if (!ok) return fail(h, AMM_ERR_HIP, "could not read the problem arrays");
+    std::string err;
+    amm_status s = validate_pair(hp, err);
+    if (s != AMM_OK) return fail(h, s, err);
+    return AMM_OK;
+}
+
+template <typename P>
+amm_status up(amm_handle* h, P* dst, const std::vector<P>& src) {
+    if (src.empty()) return AMM_OK;
+    HIPC(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(P), hipMemcpyHostToDevice, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    return AMM_OK;
+}
+
+// uploads a float64 host array and writes its float32 and float64 copies
+template <typename PF, typename PD>
+amm_status up_real(amm_handle* h, PF* dst_f, PD* dst_d, const std::vector<double>& src) {
+    if (src.empty()) return AMM_OK;
+    HIPC(hipMemcpyAsync(h->v.staging, src.data(), src.size() * 8, hipMemcpyHostToDevice, h->stream));
+    launch_cast_static<float>(h->v.staging, reinterpret_cast<float*>(dst_f), (int64_t)src.size(), h->stream);
+    launch_cast_static<double>(h->v.staging, reinterpret_cast<double*>(dst_d), (int64_t)src.size(), h->stream);
+    HIPC(hipStreamSynchronize(h->stream));
+    return AMM_OK;
+}
+
+amm_status ensure_host(amm_handle* h, size_t P) {
+    h->dyn.assign(P, PairDyn{});
+    if (P <= h->h_cap) return AMM_OK;
+    for (int s = 0; s < kDynRing; ++s)
+        if (h->dyn_ev_live[s]) (void)hipEventSynchronize(h->dyn_ev[s]);
+    if (h->h_out) (void)hipHostFree(h->h_out);
+    if (h->h_state) (void)hipHostFree(h->h_state);
+    if (h->dyn_pinned) (void)hipHostFree(h->dyn_pinned);
+    h->h_out = nullptr;
+    h->h_state = nullptr;
+    h->dyn_pinned = nullptr;
+    HIPC(hipHostMalloc((void**)&h->h_out, sizeof(PairOut) * P));
+    HIPC(hipHostMalloc((void**)&h->h_state, sizeof(CgState) * 2 * P));
+    HIPC(hipHostMalloc((void**)&h->dyn_pinned, sizeof(PairDyn) * kDynRing * P));
+    h->h_cap = P;
+    return AMM_OK;
+}
+
+// Uploads the host copy of the per-pair parameters into the next ring slot;
+// launches built afterwards read that slot.  A slot's staging memory is
+// reused only after its previous upload has completed.
+amm_status push_dyn(amm_handle* h) {
+    const int P = h->L.P;
+    const int slot = (h->dyn_slot + 1) % kDynRing;
+    if (!h->dyn_ev[slot]) HIPC(hipEventCreateWithFlags(&h->dyn_ev[slot], hipEventDisableTiming));
+    if (h->dyn_ev_live[slot]) HIPC(hipEventSynchronize(h->dyn_ev[slot]));
+    PairDyn* hs = h->dyn_pinned + (size_t)slot * P;
+    std::memcpy(hs, h->dyn.data(), sizeof(PairDyn) * P);
+    PairDyn* ds = h->v.dyn_ring + (size_t)slot * P;
+    HIPC(hipMemcpyAsync(ds, hs, sizeof(PairDyn) * P, hipMemcpyHostToDevice, h->stream));
+    HIPC(hipEventRecord(h->dyn_ev[slot], h->stream));
+    h->dyn_ev_live[slot] = true;
+    h->dyn_slot = slot;
+    h->v.dyn = ds;
+    return AMM_OK;
+}
+
+amm_status pull_out(amm_handle* h) {
+    HIPC(hipMemcpyAsync(h->h_out, h->v.out, sizeof(PairOut) * h->L.P, hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    HIPC(hipGetLastError());
+    if (h->timing) h->timer.collect();
+    return AMM_OK;
+}
+
+template <typename T>
+const StaticT<T>& statics(const amm_handle* h);
+template <>
+const StaticT<float>& statics<float>(const amm_handle* h) { return h->v.sf; }
+template <>
+const StaticT<double>& statics<double>(const amm_handle* h) { return h->v.sd; }
+
+template <typename T>
+EvalArgs<T> eval_args(amm_handle* h, bool use_override = false) {
+    using V = typename V4Of<T>::type;
+    const StaticT<T>& s = statics<T>(h);
+    const Dyn& d = h->v.d;
+    EvalArgs<T> a{};
+    a.pt_tiles = h->v.pt_tiles;
+    a.eg_tiles = h->v.eg_tiles;
+    a.nd_tiles = h->v.nd_tiles;
+    a.info = h->v.info;
+    a.dyn = h->v.dyn;
+    a.src = s.src;
+    a.src_override = use_override ? reinterpret_cast<const V*>(d.src_ovr) : nullptr;
+    a.iidx = h->v.iidx;
+    a.iw = s.iw;
+    a.k = h->L.k;
+    a.Ntot = h->L.Ntot;
+    a.nodes = s.nodes;
+    a.tgt = s.tgt;
+    a.blo = s.blo;
+    a.bhi = s.bhi;
+    a.adj_row = h->v.adj_row;
+    a.adj_nbr = h->v.adj_nbr;
+    a.adj_r = s.adj_r;
+    for (int q = 0; q < 3; ++q) a.X[q] = reinterpret_cast<T*>(d.X[q]);
+    for (int q = 0; q < 2; ++q) {
+        a.vhat[q] = reinterpret_cast<V*>(d.vhat[q]);
+        a.rho[q] = d.rho[q];
+        a.d2[q] = reinterpret_cast<T*>(d.d2[q]);
+        a.qw[q] = reinterpret_cast<V*>(d.qw[q]);
+        a.wr[q] = reinterpret_cast<T*>(d.wr[q]);
+        a.Dres[q] = reinterpret_cast<V*>(d.Dres[q]);
+        a.R[q] = reinterpret_cast<T*>(d.R[q]);
+    }
+    a.pt_part = d.pt_part;
+    a.pt_max = d.pt_max;
+    a.eg_part = d.eg_part;
+    a.nd_part = d.nd_part;
+    return a;
+}
+
+FinalArgs final_args(amm_handle* h) {
+    FinalArgs f{};
+    f.info = h->v.info;
+    f.dyn = h->v.dyn;
+    f.out = h->v.out;
+    f.pt_part = h->v.d.pt_part;
+    f.pt_max = h->v.d.pt_max;
+    f.eg_part = h->v.d.eg_part;
+    f.nd_part = h->v.d.nd_part;
+    return f;
+}
+
+template <typename T>
+AsmArgs<T> asm_args(amm_handle* h) {
+    using V = typename V4Of<T>::type;
+    const StaticT<T>& s = statics<T>(h);
+    const Dyn& d = h->v.d;
+    AsmArgs<T> a{};
+    a.dyn = h->v.dyn;
+    a.node_pair = h->v.node_pair;
+    a.src = s.src;
+    a.iidx = h->v.iidx;
+    a.iw = s.iw;
+    a.k = h->L.k;
+    a.Ntot = h->L.Ntot;
+    a.nodes = s.nodes;
+    a.K_ptr = h->v.K_ptr;
+    a.K_col = h->v.K_col;
+    a.K_adj = h->v.K_adj;
+    a.pj_ptr = h->v.pj_ptr;
+    a.pj_ent = h->v.pj_ent;
+    a.adj_ptr = h->v.adj_ptr;
+    a.adj_nbr = h->v.adj_nbr;
+    a.adj_rev = h->v.adj_rev;
+    a.adj_r = s.adj_r;
+    for (int q = 0; q < 2; ++q) {
+        a.qw[q] = reinterpret_cast<const V*>(d.qw[q]);
+        a.wr[q] = reinterpret_cast<const T*>(d.wr[q]);
+        a.R[q] = reinterpret_cast<const T*>(d.R[q]);
+    }
+    a.Kval = reinterpret_cast<T*>(d.Kval);
+    a.B = reinterpret_cast<T*>(d.B);
+    a.Dinv = reinterpret_cast<T*>(d.Dinv);
+    return a;
+}
+
+template <typename T>
+CgArgs<T> cg_args(amm_handle* h, const T* b, double rtol) {
+    const Dyn& d = h->v.d;
+    CgArgs<T> a{};
+    a.nd_tiles = h->v.nd_tiles;
+    a.info = h->v.info;
+    a.dyn = h->v.dyn;
+    a.K_ptr = h->v.K_ptr;
+    a.K_col = h->v.K_col;
+    a.Kval = reinterpret_cast<const T*>(d.Kval);
+    a.Dinv = reinterpret_cast<const T*>(d.Dinv);
+    a.b = b;
+    a.x = reinterpret_cast<T*>(d.cg[0]);
+    a.r = reinterpret_cast<T*>(d.cg[1]);
+    a.u = reinterpret_cast<T*>(d.cg[2]);
+    a.w = reinterpret_cast<T*>(d.cg[3]);
+    a.pv = reinterpret_cast<T*>(d.cg[4]);
+    a.sv = reinterpret_cast<T*>(d.cg[5]);
+    a.part_ru = d.part_ru;
+    a.part_rr = d.part_rr;
+    a.part_wu = d.part_wu;
+    a.part_bb = d.part_bb;
+    a.state = h->v.state;
+    a.rtol2 = rtol * rtol;
+    return a;
+}
+
+template <typename T>
+void vec_op(amm_handle* h, int flag, int op, const T* src = nullptr, T* dst = nullptr) {
+    NodeVecArgs<T> a{};
+    a.nd_tiles = h->v.nd_tiles;
+    a.dyn = h->v.dyn;
+    a.flag = flag;
+    a.op = op;
+    a.x64 = h->v.d.x64;
+    a.src_t = src;
+    a.dst_t = dst;
+    for (int q = 0; q < 3; ++q) a.X[q] = reinterpret_cast<T*>(h->v.d.X[q]);
+    launch_node_vec_op<T>(a, h->L.n_nd_tiles, h->stream);
+}
+
+template <typename T>
+amm_status evaluate(amm_handle* h, bool use_override = false) {
+    TRY(push_dyn(h));
+    launch_eval<T>(eval_args<T>(h, use_override), h->L.n_pt_tiles, h->L.n_eg_tiles, h->L.n_nd_tiles,
+                   final_args(h), h->L.P, h->stream, tmr(h));
+    return pull_out(h);
+}
+
+// Sum over a pair's node tiles of a [tiles][3] partial array, on the host.
+void pair_sums3(const Layout& L, const double* part, int p, double out[3]) {
+    const PairInfo& pi = L.info[p];
+    out[0] = out[1] = out[2] = 0;
+    for (int t = 0; t < pi.nd_ntile; ++t)
+        for (int c = 0; c < 3; ++c) out[c] += part[3 * (pi.nd_tile0 + t) + c];
+}
+
+struct SolveReport {
+    std::vector<int64_t> cg_iters;
+    std::vector<int> refine;
+    std::vector<double> rel;   // worst final relative residual |B - K X| / |B| over the 3 columns
+    bool not_spd = false;
+};
+
+// CG over the pairs flagged PF_SOLVE until all their columns converged.
+template <typename T>
+amm_status run_cg(amm_handle* h, const T* b, double rtol, int zero_x, int maxit, SolveReport& rep) {
+    const Layout& L = h->L;
+    const int nt = L.n_nd_tiles;
+    CgArgs<T> a = cg_args<T>(h, b, rtol);
+    launch_cg_init<T>(a, nt, zero_x, h->stream, tmr(h));
+    int it = 0;
+    const int check = 8;
+    for (; it < maxit; ++it) {
+        launch_cg_iter<T>(a, nt, it, h->stream, tmr(h));
+        if ((it + 1) % check == 0 || it + 1 == maxit) {
+            HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * L.P, hipMemcpyDeviceToHost,
+                                h->stream));
+            HIPC(hipStreamSynchronize(h->stream));
+            bool all = true;
+            for (int p = 0; p < L.P && all; ++p) {
+                if (!(h->dyn[p].flags & PF_SOLVE)) continue;
+                const CgState& st = h->h_state[2 * p + (it & 1)];
+                if (!(st.conv[0] && st.conv[1] && st.conv[2])) all = false;
+            }
+            if (all) {
+                ++it;
+                break;
+            }
+        }
+    }
+    HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * L.P, hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    HIPC(hipGetLastError());
+    if (h->timing) h->timer.collect();
+    if (it == 0) return AMM_OK;
+    const int last = (it - 1) & 1;
+    for (int p = 0; p < L.P; ++p) {
+        if (!(h->dyn[p].flags & PF_SOLVE)) continue;
+        rep.cg_iters[p] += h->h_state[2 * p + last].iters;
+    }
+    return AMM_OK;
+}
+
+// true residual r = B - K x64 per pair (worst column), on the host
+template <typename T>
+amm_status true_residual(amm_handle* h, T* rhs_out, std::vector<double>& rel) {
+    const Layout& L = h->L;
+    Dyn& d = h->v.d;
+    const int nt = L.n_nd_tiles;
+    CgArgs<T> a = cg_args<T>(h, nullptr, 0);
+    launch_residual64<T>(a, nt, reinterpret_cast<const T*>(d.B), d.x64, rhs_out, d.part_rr64, d.part_bb64, h->stream,
+                         tmr(h));
+    std::vector<double> rr(3 * nt), bb(3 * nt);
+    HIPC(hipMemcpyAsync(rr.data(), d.part_rr64, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipMemcpyAsync(bb.data(), d.part_bb64, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    rel.assign(L.P, 0.0);
+    for (int p = 0; p < L.P; ++p) {
+        if (!(h->dyn[p].flags & PF_SOLVE)) continue;
+        double r3[3], b3[3];
+        pair_sums3(L, rr.data(), p, r3);
+        pair_sums3(L, bb.data(), p, b3);
+        for (int c = 0; c < 3; ++c) rel[p] = std::max(rel[p], b3[c] > 0 ? std::sqrt(r3[c] / b3[c]) : std::sqrt(r3[c]));
+    }
+    return AMM_OK;
+}
+
+// Solves K X = B (Eq. 16) for the pairs flagged PF_SOLVE, warm-started from
+// X^k; the solution is left in x64 (float64).
+template <typename T>
+amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep) {
+    const Layout& L = h->L;
+    Dyn& d = h->v.d;
+    rep.cg_iters.assign(L.P, 0);
+    rep.refine.assign(L.P, 0);
+    rep.rel.assign(L.P, 0.0);
+    rep.not_spd = false;
+    vec_op<T>(h, PF_SOLVE, 4);   // x64 = X^k
+    if (sizeof(T) == 8) {
+        // float64 CG from the warm start
+        T* x = reinterpret_cast<T*>(d.cg[0]);
+        vec_op<T>(h, PF_SOLVE, 2, nullptr, x);
+        TRY(run_cg<T>(h, reinterpret_cast<const T*>(d.B), rtol, 0, maxit, rep));
+        vec_op<T>(h, PF_SOLVE, 0, x, nullptr);
+        TRY(true_residual<T>(h, nullptr, rep.rel));
+        for (int p = 0; p < L.P; ++p) {
+            if (!(h->dyn[p].flags & PF_SOLVE)) continue;
+            if ((h->h_state[2 * p].breakdown | h->h_state[2 * p + 1].breakdown) && rep.rel[p] > 1e-3)
+                rep.not_spd = true;
+        }
+        return AMM_OK;
+    }
+    // float32 CG inside float64 iterative refinement
+    T* rhs = reinterpret_cast<T*>(d.cg[6]);
+    T* x = reinterpret_cast<T*>(d.cg[0]);
+    std::vector<int32_t> saved(L.P);
+    for (int p = 0; p < L.P; ++p) saved[p] = h->dyn[p].flags;
+    std::vector<double> prev(L.P, std::numeric_limits<double>::infinity()), rel;
+    const int max_refine = 30;
+    for (int step = 0; step <= max_refine; ++step) {
+        TRY(true_residual<T>(h, rhs, rel));
+        bool any = false;
+        for (int p = 0; p < L.P; ++p) {
+            if (!(h->dyn[p].flags & PF_SOLVE)) continue;
+            rep.rel[p] = rel[p];
+            if (rel[p] <= rtol || step == max_refine || rel[p] > 0.5 * prev[p]) {
+                h->dyn[p].flags &= ~PF_SOLVE;   // converged, or refinement stopped improving
+            } else {
+                any = true;
+                rep.refine[p] += 1;
+            }
+            prev[p] = rel[p];
+        }
+        if (!any) break;
+        TRY(push_dyn(h));
+        TRY(run_cg<T>(h, rhs, 1e-4, 1, maxit, rep));
+        vec_op<T>(h, PF_SOLVE, 1, x, nullptr);   // x64 += correction
+    }
+    for (int p = 0; p < L.P; ++p) {
+        h->dyn[p].flags = saved[p];
+        if ((h->dyn[p].flags & PF_SOLVE) && rep.rel[p] > 1e-3 &&
+            (h->h_state[2 * p].breakdown | h->h_state[2 * p + 1].breakdown))
+            rep.not_spd = true;
+    }
+    return push_dyn(h);
+}
+
+struct PairState {
+    double nu_a = 0, nu_min = 0, nu_r = 0, alpha = 0, beta = 0;
+    double E_cur = 0;
+    int stage = 0, it = 0, total = 0;
+    bool done = false;
+    int hist_count = 0, hist_head = -1;
+    int cur = 0;
+    amm_stats st{};
+};
+
+// Eq. (21); a graph without edges has no regularization term
+void term_weights(const PairInfo& pi, double k_alpha, double k_beta, PairState& s) {
+    const double N = (double)pi.N, n = (double)pi.n, E = (double)pi.n_undirected;
+    s.alpha = E > 0 ? k_alpha * (N / E) * (s.nu_r * s.nu_r) / (s.nu_a * s.nu_a) : 0.0;
+    s.beta = k_beta * (N / n) / (2.0 * s.nu_a * s.nu_a);
+}
+
+void set_scalars(PairDyn& d, double nu_a, double nu_r, double alpha, double beta) {
+    d.nu_a = nu_a;
+    d.nu_r = nu_r;
+    d.alpha = alpha;
+    d.beta = beta;
+}
+
+template <typename T>
+amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void* v_out, amm_stats* stats) {
+    const Layout& L = h->L;
+    Dyn& d = h->v.d;
+    const int P = L.P;
+    const int m = prm.aa_m;
+    const double rtol = prm.cg_rtol > 0 ? prm.cg_rtol : 1e-10;
+    const int maxit = prm.cg_maxit > 0 ? prm.cg_maxit : 20000;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now_ms = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    if (prm.init_identity || !X_inout) {
+        std::vector<T> id(12 * L.ntot, T(0));
+        for (int64_t j = 0; j < L.ntot; ++j) id[12 * j] = id[12 * j + 4] = id[12 * j + 8] = T(1);
+        HIPC(hipMemcpyAsync(d.X[0], id.data(), id.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+    } else {
+        launch_x_import<T, T>(reinterpret_cast<const T*>(X_inout), reinterpret_cast<T*>(d.X[0]), h->v.node_user,
+                              L.ntot, h->stream);
+    }
+    std::vector<PairState> ps(P);
+    for (int p = 0; p < P; ++p) {
+        PairDyn& dy = h->dyn[p];
+        dy = PairDyn{};
+        set_scalars(dy, 1.0, 1.0, 0.0, 0.0);
+        dy.flags = PF_EVAL;
+    }
+    TRY(evaluate<T>(h));
+    // start of nu_a: median closest-point distance at the initial transforms
+    std::vector<T> d2h(L.Ntot);
+    HIPC(hipMemcpyAsync(d2h.data(), d.d2[0], sizeof(T) * L.Ntot, hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    for (int p = 0; p < P; ++p) {
+        const PairInfo& pi = L.info[p];
+        std::vector<double> dist(pi.N);
+        for (int64_t i = 0; i < pi.N; ++i) dist[i] = std::sqrt((double)d2h[pi.src_off + i]);
+        std::sort(dist.begin(), dist.end());
+        const double med = (pi.N % 2) ? dist[pi.N / 2] : 0.5 * (dist[pi.N / 2 - 1] + dist[pi.N / 2]);
+        PairState& st = ps[p];
+        st.nu_min = prm.nu_a_min > 0 ? prm.nu_a_min : h->lbar[p] / std::sqrt(3.0);
+        st.nu_a = std::max(prm.nu_a0 > 0 ? prm.nu_a0 : med, st.nu_min);
+        st.nu_r = prm.nu_r0 > 0 ? prm.nu_r0 : 3.0 * h->lbar[p];
+        term_weights(pi, prm.k_alpha, prm.k_beta, st);
+        st.st.stages = 1;
+        PairDyn& dy = h->dyn[p];
+        set_scalars(dy, st.nu_a, st.nu_r, st.alpha, st.beta);
+        dy.has_prev = 1;   // in place: same transforms, same closest points
+    }
+    TRY(evaluate<T>(h));
+    for (int p = 0; p < P; ++p) ps[p].E_cur = h->h_out[p].E;
+
+    const int ring = m + 1;
+    SolveReport rep;
+    std::vector<char> reject(P), restage(P);
+    while (true) {
+        bool any = false;
+        for (int p = 0; p < P; ++p) {
+            PairDyn& dy = h->dyn[p];
+            PairState& st = ps[p];
+            dy = PairDyn{};
+            dy.cur = st.cur;
+            set_scalars(dy, st.nu_a, st.nu_r, st.alpha, st.beta);
+            if (st.done) continue;
+            any = true;
+            dy.flags = PF_SOLVE;
+            st.hist_head = (st.hist_head + 1) % ring;
+            st.hist_count = std::min(st.hist_count + 1, ring);
+            dy.aa_mk = std::min(st.hist_count - 1, m);
+            for (int x = 0; x <= dy.aa_mk; ++x) dy.aa_slot[x] = ((st.hist_head - x) % ring + ring) % ring;
+            dy.eval_x = 1 - st.cur;
+            dy.eval_dst = 1 - st.cur;
+            dy.has_prev = 1;
+        }
+        if (!any) break;
+        TRY(push_dyn(h));
+        launch_assemble<T>(asm_args<T>(h), L.ntot, h->stream, tmr(h));
+        TRY(linear_solve<T>(h, rtol, maxit, rep));
+        if (rep.not_spd) return fail(h, AMM_ERR_NOT_SPD, "K is not positive definite (CG breakdown)");
+        AaArgs<T> aa{};
+        aa.nd_tiles = h->v.nd_tiles;
+        aa.dyn = h->v.dyn;
+        aa.out = h->v.out;
+        aa.ntot = L.ntot;
+        aa.G = reinterpret_cast<T*>(d.G);
+        aa.F = reinterpret_cast<T*>(d.F);
+        for (int q = 0; q < 3; ++q) aa.X[q] = reinterpret_cast<T*>(d.X[q]);
+        aa.xnew = d.x64;
+        aa.part = d.aa_part;
+        AaSolveArgs sa{h->v.info, h->v.dyn, h->v.out, d.aa_part, P};
+        launch_aa<T>(aa, sa, L.n_nd_tiles, h->stream, tmr(h));
+        // evaluate E at the candidate (X_AA, or G(X^k) itself)
+        for (int p = 0; p < P; ++p)
+            if (!ps[p].done) h->dyn[p].flags = PF_EVAL;
+        TRY(evaluate<T>(h));
+        bool any_reject = false;
+        for (int p = 0; p < P; ++p) {
+            PairState& st = ps[p];
+            reject[p] = 0;
+            if (st.done) continue;
+            const PairOut& o = h->h_out[p];
+            bool acc = true;
+            if (o.aa_used != 0) {
+                acc = o.E < st.E_cur;
+                if (prm.force_accept && st.total < prm.force_len && prm.force_accept[st.total] >= 0)
+                    acc = prm.force_accept[st.total] != 0;
+                (acc ? st.st.aa_accepted : st.st.aa_rejected) += 1;
+            }
+            if (!acc) {
+                reject[p] = 1;
+                any_reject = true;
+            }
+        }
+        if (any_reject) {
+            // take G(X^k) without a second test: evaluate it and store it as the new iterate
+            for (int p = 0; p < P; ++p) {
+                h->dyn[p].flags = reject[p] ? (PF_EVAL | PF_SOLVE) : 0;
+                h->dyn[p].eval_x = 2;
+            }
+            TRY(evaluate<T>(h));
+            vec_op<T>(h, PF_SOLVE, 6);   // X[1 - cur] = G(X^k)
+        }
+        bool any_stage = false;
+        for (int p = 0; p < P; ++p) {
+            PairState& st = ps[p];
+            restage[p] = 0;
+            if (st.done) continue;
+            const PairOut& o = h->h_out[p];
+            st.cur = 1 - st.cur;
+            st.E_cur = o.E;
+            st.it += 1;
+            st.total += 1;
+            st.st.iters = st.total;
+            st.st.max_disp = o.maxdisp;
+            st.st.cg_iters += rep.cg_iters[p];
+            st.st.refine_steps += rep.refine[p];
+            st.st.max_rel_residual = std::max(st.st.max_rel_residual, rep.rel[p]);
+            if (!std::isfinite(o.E)) return fail(h, AMM_ERR_NONFINITE, "energy became non-finite");
+            const bool budget = prm.max_total_iters > 0 && st.total >= prm.max_total_iters;
+            bool end = o.maxdisp < prm.eps || st.it >= prm.imax || budget;
+            const int t = st.total - 1;
+            if (prm.force_stage_end && t < prm.force_len && prm.force_stage_end[t] >= 0)
+                end = prm.force_stage_end[t] != 0;
+            if (!end) continue;
+            if (st.nu_a == st.nu_min || budget) {
+                st.done = true;
+                st.st.converged = (o.maxdisp < prm.eps && st.nu_a == st.nu_min) ? 1 : 0;
+                st.st.time_ms = now_ms();
+                continue;
+            }
+            st.stage += 1;
+            st.st.stages += 1;
+            st.nu_a = std::max(st.nu_a / 2.0, st.nu_min);
+            st.nu_r = st.nu_r / 2.0;
+            term_weights(L.info[p], prm.k_alpha, prm.k_beta, st);
+            st.it = 0;
+            st.hist_count = 0;
+            st.hist_head = -1;
+            restage[p] = 1;
+            any_stage = true;
+        }
+        if (any_stage) {
+            // the energy at the new nu (same transforms, same closest points)
+            for (int p = 0; p < P; ++p) {
+                PairDyn& dy = h->dyn[p];
+                dy = PairDyn{};
+                dy.flags = restage[p] ? PF_EVAL : 0;
+                dy.cur = dy.eval_x = dy.eval_dst = ps[p].cur;
+                dy.has_prev = 1;
+                set_scalars(dy, ps[p].nu_a, ps[p].nu_r, ps[p].alpha, ps[p].beta);
+            }
+            TRY(evaluate<T>(h));
+            for (int p = 0; p < P; ++p)
+                if (restage[p]) ps[p].E_cur = h->h_out[p].E;
+        }
+    }
+    // final energies and terms at the returned transforms; collect X and v_hat
+    for (int p = 0; p < P; ++p) {
+        PairDyn& dy = h->dyn[p];
+        dy = PairDyn{};
+        dy.flags = PF_EVAL | PF_SOLVE;
+        dy.cur = dy.eval_x = dy.eval_dst = ps[p].cur;
+        dy.has_prev = 1;
+        set_scalars(dy, ps[p].nu_a, ps[p].nu_r, ps[p].alpha, ps[p].beta);
+    }
+    TRY(evaluate<T>(h));
+    vec_op<T>(h, PF_SOLVE, 5);   // X[2] = X[cur]
+    if (X_inout)
+        launch_x_export<T, T>(reinterpret_cast<const T*>(d.X[2]), reinterpret_cast<T*>(X_inout), h->v.node_user,
+                              L.ntot, h->stream);
+    if (v_out) {
+        const size_t es = 4 * sizeof(T);
+        for (int p = 0; p < P; ++p) {
+            const PairInfo& pi = L.info[p];
+            HIPC(hipMemcpyAsync(reinterpret_cast<char*>(d.pts_out) + pi.src_off * es,
+                                reinterpret_cast<char*>(d.vhat[ps[p].cur]) + pi.src_off * es, pi.N * es,
+                                hipMemcpyDeviceToDevice, h->stream));
+        }
+        launch_points_export<T, T>(d.pts_out, reinterpret_cast<T*>(v_out), h->v.src_user, L.Ntot, h->stream);
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+    HIPC(hipGetLastError());
+    if (h->timing) h->timer.collect();
+    if (stats) {
+        for (int p = 0; p < P; ++p) {
+            amm_stats& o = stats[p];
+            o = ps[p].st;
+            o.energy = h->h_out[p].E;
+            o.e_align = h->h_out[p].Ea;
+            o.e_reg = h->h_out[p].Er;
+            o.e_rot = h->h_out[p].Eo;
+            o.nu_a = ps[p].nu_a;
+            o.nu_r = ps[p].nu_r;
+            o.alpha = ps[p].alpha;
+            o.beta = ps[p].beta;
+        }
+    }
+    return AMM_OK;
+}
+
+template <typename T>
+amm_status energy_impl(amm_handle* h, const void* X, const void* src, double nu_a, double nu_r, double alpha,
+                       double beta, double* energy, int32_t* rho, void* d2, void* gX, void* gV) {
+    const Layout& L = h->L;
+    Dyn& d = h->v.d;
+    launch_x_import<T, T>(reinterpret_cast<const T*>(X), reinterpret_cast<T*>(d.X[0]), h->v.node_user, L.ntot,
+                          h->stream);
+    if (src) launch_src_import<T, T>(reinterpret_cast<const T*>(src), d.src_ovr, h->v.src_user, L.Ntot, h->stream);
+    PairDyn& dy = h->dyn[0];
+    dy = PairDyn{};
+    dy.flags = PF_EVAL;
+    set_scalars(dy, nu_a, nu_r, alpha, beta);
+    TRY(evaluate<T>(h, src != nullptr));
+    if (energy) {
+        energy[0] = h->h_out[0].E;
+        energy[1] = h->h_out[0].Ea;
+        energy[2] = h->h_out[0].Er;
+        energy[3] = h->h_out[0].Eo;
+    }
+    if (rho || d2)
+        launch_nn_export<T, T>(d.rho[0], reinterpret_cast<const T*>(d.d2[0]), h->v.src_user, h->v.tgt_user, rho,
+                               reinterpret_cast<T*>(d2), L.Ntot, h->stream);
+    if (gX) {
+        using V = typename V4Of<T>::type;
+        const StaticT<T>& s = statics<T>(h);
+        GradArgs<T> g{};
+        g.pt_tiles = h->v.pt_tiles;
+        g.info = h->v.info;
+        g.dyn = h->v.dyn;
+        g.node_pair = h->v.node_pair;
+        g.src = s.src;
+        g.src_override = src ? reinterpret_cast<const V*>(d.src_ovr) : nullptr;
+        g.src_user = h->v.src_user;
+        g.node_user = h->v.node_user;
+        g.iidx = h->v.iidx;
+        g.iw = s.iw;
+        g.k = L.k;
+        g.Ntot = L.Ntot;
+        g.nodes = s.nodes;
+        g.tgt = s.tgt;
+        g.pj_ptr = h->v.pj_ptr;
+        g.pj_ent = h->v.pj_ent;
+        g.adj_ptr = h->v.adj_ptr;
+        g.adj_nbr = h->v.adj_nbr;
+        g.adj_rev = h->v.adj_rev;
+        g.adj_r = s.adj_r;
+        g.X = reinterpret_cast<const T*>(d.X[0]);
+        for (int q = 0; q < 2; ++q) {
+            g.vhat[q] = reinterpret_cast<const V*>(d.vhat[q]);
+            g.rho[q] = d.rho[q];
+            g.d2[q] = reinterpret_cast<const T*>(d.d2[q]);
+            g.Dres[q] = reinterpret_cast<const V*>(d.Dres[q]);
+            g.R[q] = reinterpret_cast<const T*>(d.R[q]);
+        }
+        g.gpt = reinterpret_cast<V*>(d.gpt);
+        g.gX = reinterpret_cast<T*>(gX);
+        g.gV = reinterpret_cast<T*>(gV);
+        launch_grad<T>(g, L.n_pt_tiles, L.ntot, h->stream);
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+    HIPC(hipGetLastError());
+    return AMM_OK;
+}
+
+template <typename T>
+amm_status step_impl(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
+    const Layout& L = h->L;
+    Dyn& d = h->v.d;
+    launch_x_import<T, T>(reinterpret_cast<const T*>(in->X), reinterpret_cast<T*>(d.X[0]), h->v.node_user, L.ntot,
+                          h->stream);
+    PairDyn& dy = h->dyn[0];
+    dy = PairDyn{};
+    dy.flags = PF_EVAL;
+    set_scalars(dy, in->nu_a, in->nu_r, in->alpha, in->beta);
+    TRY(evaluate<T>(h));
+    out->energy[0] = h->h_out[0].E;
+    out->energy[1] = h->h_out[0].Ea;
+    out->energy[2] = h->h_out[0].Er;
+    out->energy[3] = h->h_out[0].Eo;
+    if (out->rho || out->d2)
+        launch_nn_export<T, T>(d.rho[0], reinterpret_cast<const T*>(d.d2[0]), h->v.src_user, h->v.tgt_user, out->rho,
+                               reinterpret_cast<T*>(out->d2), L.Ntot, h->stream);
+    if (out->v_hat)
+        launch_points_export<T, T>(d.vhat[0], reinterpret_cast<T*>(out->v_hat), h->v.src_user, L.Ntot, h->stream);
+    dy.flags = PF_SOLVE;
+    TRY(push_dyn(h));
+    launch_assemble<T>(asm_args<T>(h), L.ntot, h->stream, tmr(h));
+    SolveReport rep;
+    TRY(linear_solve<T>(h, in->cg_rtol > 0 ? in->cg_rtol : 1e-10, in->cg_maxit > 0 ? in->cg_maxit : 20000, rep));
+    out->cg_iters = (int32_t)rep.cg_iters[0];
+    out->rel_residual = rep.rel[0];
+    if (out->X_next) {
+        vec_op<T>(h, PF_SOLVE, 2, nullptr, reinterpret_cast<T*>(d.X[2]));
+        launch_x_export<T, T>(reinterpret_cast<const T*>(d.X[2]), reinterpret_cast<T*>(out->X_next), h->v.node_user,
+                              L.ntot, h->stream);
+    }
+    if (out->B)
+        launch_x_export<T, T>(reinterpret_cast<const T*>(d.B), reinterpret_cast<T*>(out->B), h->v.node_user, L.ntot,
+                              h->stream);
+    if (out->K_blocks)
+        HIPC(hipMemcpyAsync(out->K_blocks, d.Kval, sizeof(T) * 16 * L.nnzb, hipMemcpyDeviceToDevice, h->stream));
+    std::vector<int32_t> kr, kc;
+    if (out->K_row || out->K_col) {
+        kr.resize(L.nnzb);
+        kc.resize(L.nnzb);
+        for (int64_t j = 0; j < L.ntot; ++j)
+            for (int pos = L.K_ptr[j]; pos < L.K_ptr[j + 1]; ++pos) {
+                kr[pos] = L.node_user[j];
+                kc[pos] = L.node_user[L.K_col[pos]];
+            }
+        if (out->K_row)
+            HIPC(hipMemcpyAsync(out->K_row, kr.data(), 4 * L.nnzb, hipMemcpyHostToDevice, h->stream));
+        if (out->K_col)
+            HIPC(hipMemcpyAsync(out->K_col, kc.data(), 4 * L.nnzb, hipMemcpyHostToDevice, h->stream));
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+    HIPC(hipGetLastError());
+    return AMM_OK;
+}
+
+amm_status analyse(amm_handle* h, const amm_problem* probs, int32_t n_pairs, Layout& L, std::vector<double>& lbar) {
+    if (!probs || n_pairs < 1) return fail(h, AMM_ERR_INVALID_ARG, "need at least one problem");
+    std::vector<HostPair> hps(n_pairs);
+    lbar.resize(n_pairs);
+    for (int p = 0; p < n_pairs; ++p) {
+        TRY(read_pair(h, probs[p], hps[p]));
+        lbar[p] = hps[p].lbar;
+    }
+    std::string err;
+    amm_status s = build_layout(hps, 16, L, err);
+    if (s != AMM_OK) return fail(h, s, err);
+    return AMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void amm_params_default(amm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->k_alpha = 100.0;
+    p->k_beta = 1.0;
+    p->eps = 1e-5;
+    p->imax = 100;
+    p->max_total_iters = 0;
+    p->aa_m = 5;
+    p->precision = AMM_FP32_REFINE;
+    p->cg_rtol = 1e-10;
+    p->cg_maxit = 20000;
+    p->init_identity = 1;
+}
+
+const char* amm_status_string(amm_status s) {
+    switch (s) {
+        case AMM_OK: return "ok";
+        case AMM_ERR_INVALID_ARG: return "invalid argument";
+        case AMM_ERR_STATE: return "invalid call order";
+        case AMM_ERR_OOM: return "out of device memory";
+        case AMM_ERR_HIP: return "HIP runtime error";
+        case AMM_ERR_NONFINITE: return "non-finite value";
+        case AMM_ERR_GRAPH: return "invalid deformation graph";
+        case AMM_ERR_NOT_SPD: return "system not positive definite";
+    }
+    return "unknown status";
+}
+
+const char* amm_last_error(const amm_handle* h) { return h ? h->err.c_str() : g_last_error.c_str(); }
+
+const char* amm_version(void) { return kVersion; }
+
+amm_status amm_create(amm_handle** out, int device, void* stream) {
+    if (!out) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle pointer");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+        return fail(nullptr, AMM_ERR_HIP, "no HIP device available");
+    if (device < 0 || device >= count) return fail(nullptr, AMM_ERR_INVALID_ARG, "device index out of range");
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, AMM_ERR_HIP, "hipSetDevice failed");
+    amm_handle* h = new amm_handle();
+    h->device = device;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    *out = h;
+    return AMM_OK;
+}
+
+void amm_destroy(amm_handle* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    for (int s = 0; s < kDynRing; ++s)
+        if (h->dyn_ev[s]) (void)hipEventDestroy(h->dyn_ev[s]);
+    if (h->ws_own) (void)hipFree(h->ws_own);
+    if (h->h_out) (void)hipHostFree(h->h_out);
+    if (h->h_state) (void)hipHostFree(h->h_state);
+    if (h->dyn_pinned) (void)hipHostFree(h->dyn_pinned);
+    delete h;
+}
+
+amm_status amm_set_stream(amm_handle* h, void* stream) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    return AMM_OK;
+}
+
+amm_status amm_check_problem(const amm_problem* p) {
+    if (!p) return fail(nullptr, AMM_ERR_INVALID_ARG, "null problem");
+    if (p->on_device) return fail(nullptr, AMM_ERR_INVALID_ARG, "amm_check_problem takes host pointers");
+    HostPair hp;
+    return read_pair(nullptr, *p, hp);
+}
+
+amm_status amm_workspace_size(amm_handle* h, const amm_problem* probs, int32_t n_pairs, size_t* bytes) {
+    if (!h || !bytes) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    HIPC(hipSetDevice(h->device));
+    Layout L;
+    std::vector<double> lb;
+    TRY(analyse(h, probs, n_pairs, L, lb));
+    Carver c;
+    Dev v{};
+    plan(L, c, v);
+    *bytes = c.off + 256;
+    return AMM_OK;
+}
+
+amm_status amm_set_workspace(amm_handle* h, void* ptr, size_t bytes) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    if (ptr && (reinterpret_cast<uintptr_t>(ptr) & 255))
+        return fail(h, AMM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    h->ws_user = ptr;
+    h->ws_user_bytes = ptr ? bytes : 0;
+    h->has_problem = false;
+    return AMM_OK;
+}
+
+amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_pairs) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    HIPC(hipSetDevice(h->device));
+    HIPC(hipStreamSynchronize(h->stream));
+    h->has_problem = false;
+    Layout L;
+    std::vector<double> lb;
+    TRY(analyse(h, probs, n_pairs, L, lb));
+    Carver c;
+    Dev v{};
+    plan(L, c, v);
+    const size_t need = c.off + 256;
+    char* base = nullptr;
+    if (h->ws_user) {
+        if (h->ws_user_bytes < need) return fail(h, AMM_ERR_OOM, "workspace too small");
+        base = reinterpret_cast<char*>(h->ws_user);
+    } else {
+        if (h->ws_own_bytes < need) {
+            if (h->ws_own) (void)hipFree(h->ws_own);
+            h->ws_own = nullptr;
+            h->ws_own_bytes = 0;
+            if (hipMalloc(&h->ws_own, need) != hipSuccess)
+                return fail(h, AMM_ERR_OOM, "hipMalloc of the workspace failed");
+            h->ws_own_bytes = need;
+        }
+        base = reinterpret_cast<char*>(h->ws_own);
+    }
+    Carver c2;
+    c2.base = base;
+    plan(L, c2, v);
+    h->v = v;
+    h->L = std::move(L);
+    h->lbar = lb;
+    const Layout& Lr = h->L;
+    TRY(ensure_host(h, Lr.P));
+    TRY(up(h, v.iidx, Lr.iidx));
+    TRY(up(h, v.src_user, Lr.src_user));
+    TRY(up(h, v.node_user, Lr.node_user));
+    TRY(up(h, v.node_pair, Lr.node_pair));
+    TRY(up(h, v.adj_ptr, Lr.adj_ptr));
+    TRY(up(h, v.adj_nbr, Lr.adj_nbr));
+    TRY(up(h, v.adj_row, Lr.adj_row));
+    TRY(up(h, v.adj_rev, Lr.adj_rev));
+    TRY(up(h, v.K_ptr, Lr.K_ptr));
+    TRY(up(h, v.K_col, Lr.K_col));
+    TRY(up(h, v.K_adj, Lr.K_adj));
+    TRY(up(h, v.pj_ptr, Lr.pj_ptr));
+    TRY(up(h, v.pj_ent, Lr.pj_ent));
+    TRY(up(h, v.tgt_user, Lr.tgt_user));
+    TRY(up(h, v.info, Lr.info));
+    TRY(up(h, reinterpret_cast<int32_t*>(v.pt_tiles), Lr.pt_tiles));
+    TRY(up(h, reinterpret_cast<int32_t*>(v.nd_tiles), Lr.nd_tiles));
+    TRY(up(h, reinterpret_cast<int32_t*>(v.eg_tiles), Lr.eg_tiles));
+    TRY(up_real(h, v.sf.src, v.sd.src, Lr.src4));
+    TRY(up_real(h, v.sf.iw, v.sd.iw, Lr.iw));
+    TRY(up_real(h, v.sf.nodes, v.sd.nodes, Lr.nodes4));
+    TRY(up_real(h, v.sf.tgt, v.sd.tgt, Lr.tgt4));
+    TRY(up_real(h, v.sf.blo, v.sd.blo, Lr.box_lo));
+    TRY(up_real(h, v.sf.bhi, v.sd.bhi, Lr.box_hi));
+    TRY(up_real(h, v.sf.adj_r, v.sd.adj_r, Lr.adj_r));
+    h->has_problem = true;
+    return AMM_OK;
+}
+
+amm_status amm_set_problem(amm_handle* h, const amm_problem* p) { return amm_set_problems(h, p, 1); }
+
+amm_status amm_solve(amm_handle* h, const amm_params* prm, void* X_inout, void* v_out, amm_stats* stats) {
+    if (!h || !prm) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    if (!h->has_problem) return fail(h, AMM_ERR_STATE, "amm_solve before amm_set_problem");
+    if (prm->aa_m < 0 || prm->aa_m > AMM_MAX_AA_M) return fail(h, AMM_ERR_INVALID_ARG, "aa_m out of range");
+    if (!(prm->eps >= 0) || prm->imax < 1) return fail(h, AMM_ERR_INVALID_ARG, "bad eps or imax");
+    if (!(prm->k_alpha >= 0) || !(prm->k_beta > 0)) return fail(h, AMM_ERR_INVALID_ARG, "bad k_alpha or k_beta");
+    if (!prm->init_identity && !X_inout) return fail(h, AMM_ERR_INVALID_ARG, "X_inout needed without init_identity");
+    HIPC(hipSetDevice(h->device));
+    if (prm->precision == AMM_FP64_PLAIN) return solve_impl<double>(h, *prm, X_inout, v_out, stats);
+    if (prm->precision == AMM_FP32_REFINE) return solve_impl<float>(h, *prm, X_inout, v_out, stats);
+    return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");
+}
+
+amm_status amm_step(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
+    if (!h || !in || !out || !in->X) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    if (!h->has_problem) return fail(h, AMM_ERR_STATE, "amm_step before amm_set_problem");
+    if (h->L.P != 1) return fail(h, AMM_ERR_STATE, "amm_step needs exactly one pair");
+    if (!(in->nu_a > 0) || !(in->nu_r > 0) || !(in->beta > 0) || !(in->alpha >= 0))
+        return fail(h, AMM_ERR_INVALID_ARG, "nu_a, nu_r, beta must be > 0 and alpha >= 0");
+    HIPC(hipSetDevice(h->device));
+    if (in->precision == AMM_FP64_PLAIN) return step_impl<double>(h, in, out);
+    if (in->precision == AMM_FP32_REFINE) return step_impl<float>(h, in, out);
+    return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");
+}
+
+amm_status amm_k_nnzb(amm_handle* h, int64_t* nnzb) {
+    if (!h || !nnzb) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    if (!h->has_problem) return fail(h, AMM_ERR_STATE, "no problem set");
+    *nnzb = h->L.nnzb;
+    return AMM_OK;
+}
+
+static amm_status energy_entry(amm_handle* h, amm_dtype dtype, const void* X, const void* src, double nu_a,
+                               double nu_r, double alpha, double beta, double* energy, int32_t* rho, void* d2,
+                               void* gX, void* gV) {
+    if (!h || !X) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    if (!h->has_problem) return fail(h, AMM_ERR_STATE, "no problem set");
+    if (h->L.P != 1) return fail(h, AMM_ERR_STATE, "energy and gradient need exactly one pair");
+    if (!(nu_a > 0) || !(nu_r > 0)) return fail(h, AMM_ERR_INVALID_ARG, "nu_a and nu_r must be > 0");
+    HIPC(hipSetDevice(h->device));
+    if (dtype == AMM_F32) return energy_impl<float>(h, X, src, nu_a, nu_r, alpha, beta, energy, rho, d2, gX, gV);
+    if (dtype == AMM_F64) return energy_impl<double>(h, X, src, nu_a, nu_r, alpha, beta, energy, rho, d2, gX, gV);
+    return fail(h, AMM_ERR_INVALID_ARG, "bad dtype");
+}
+
+amm_status amm_energy(amm_handle* h, amm_dtype dtype, const void* X, const void* src, double nu_a, double nu_r,
+                      double alpha, double beta, double* energy, int32_t* rho, void* d2) {
+    return energy_entry(h, dtype, X, src, nu_a, nu_r, alpha, beta, energy, rho, d2, nullptr, nullptr);
+}
+
+amm_status amm_energy_grad(amm_handle* h, amm_dtype dtype, const void* X, const void* src, double nu_a, double nu_r,
+                           double alpha, double beta, void* gX, void* gV, double* energy) {
+    if (!gX) return fail(h, AMM_ERR_INVALID_ARG, "gX must not be null");
+    return energy_entry(h, dtype, X, src, nu_a, nu_r, alpha, beta, energy, nullptr, nullptr, gX, gV);
+}
+
+amm_status amm_enable_timing(amm_handle* h, int32_t on) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    h->timer.collect();
+    h->timing = on != 0;
+    h->timer.acc.clear();
+    return AMM_OK;
+}
+
+amm_status amm_kernel_times(amm_handle* h, const char** names, double* ms, int32_t* launches, int32_t capacity,
+                            int32_t* count) {
+    if (!h || !count) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    h->timer.collect();
+    const int n = (int)h->timer.acc.size();
+    *count = n;
+    for (int i = 0; i < n && i < capacity; ++i) {
+        if (names) names[i] = h->timer.acc[i].name;
+        if (ms) ms[i] = h->timer.acc[i].ms;
+        if (launches) launches[i] = h->timer.acc[i].n;
+    }
+    return AMM_OK;
+}
+
+}  // extern "C"

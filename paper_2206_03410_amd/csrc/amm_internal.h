@@ -1,0 +1,112 @@
+// Internal declarations shared by the host setup, the kernels and the C ABI
+// layer.  Not part of the public interface.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "amm.h"
+
+namespace amm {
+
+// Static description of one pair inside a batch (all offsets are into the
+// concatenated arrays; counts are this pair's).
+struct PairInfo {
+    int64_t src_off, N;      // source points (internal, Morton order)
+    int64_t tgt_off, M;      // target points (sorted by Morton code)
+    int64_t node_off, n;     // graph nodes (internal, Morton order)
+    int64_t adj_off, nadj;   // directed adjacency entries (2 |E_G|)
+    int64_t tree_off;        // offset of this pair's box array (heap layout, 2L entries)
+    int32_t L;               // leaves of the implicit tree (power of two)
+    int32_t leaf;            // targets per leaf
+    int32_t pt_tile0, pt_ntile;   // point tiles
+    int32_t nd_tile0, nd_ntile;   // node tiles (solver rows)
+    int32_t eg_tile0, eg_ntile;   // edge tiles
+    int32_t n_undirected;
+    int32_t pad;
+};
+
+// Dynamic per-pair state the host writes before launches.
+enum : int32_t {
+    PF_ACTIVE = 1,       // pair takes part in this MM iteration
+    PF_EVAL = 2,         // evaluate energy at the candidate transforms
+    PF_SOLVE = 4,        // assemble and solve
+};
+
+struct PairDyn {
+    double nu_a, nu_r, alpha, beta;
+    int32_t flags;
+    int32_t cur;             // which eval/transform set holds the accepted iterate
+    int32_t eval_dst;        // set written by the next evaluation
+    int32_t eval_x;          // which transform buffer the next evaluation reads (0,1 = X sets, 2 = Xp)
+    int32_t aa_mk;           // Anderson window m_k for this iteration
+    int32_t aa_slot[11];     // ring slots: [0] = newest (k), [1] = k-1, ...
+    int32_t has_prev;        // closest-point warm start available in set `cur`
+    int32_t pad;
+};
+
+// Per-pair outputs read back by the host after an evaluation.
+struct PairOut {
+    double E, Ea, Er, Eo;    // energy and terms of the last evaluation
+    double maxdisp;          // max |v_hat(eval) - v_hat(cur)|
+    double aa_used;          // 1 if the Anderson candidate differs from G(X^k)
+    double theta[10];
+};
+
+// CG state per pair, per column (double-buffered by iteration parity).
+struct CgState {
+    double alpha[3], gamma[3];
+    double rr[3], bb[3];
+    int32_t conv[3];
+    int32_t iters;
+    int32_t breakdown;
+    int32_t pad;
+};
+
+// Host copy of one validated problem (float64).
+struct HostPair {
+    int64_t N = 0, M = 0, n = 0, E = 0;
+    int k = 0;
+    std::vector<double> src, tgt, src_nrm, tgt_nrm, infl_w;
+    std::vector<int32_t> node_idx, infl_idx, edges;
+    double lbar = 0.0;
+};
+
+// Everything set_problems uploads (built on the host).
+struct Layout {
+    int P = 0, k = 0;
+    int64_t Ntot = 0, Mtot = 0, ntot = 0, nadj = 0, nnzb = 0, tree_nodes = 0, pj_entries = 0;
+    int n_pt_tiles = 0, n_nd_tiles = 0, n_eg_tiles = 0;
+    std::vector<PairInfo> info;
+    std::vector<double> src4;        // [Ntot][4] internal order
+    std::vector<int32_t> src_user;   // internal point -> user index (concatenated)
+    std::vector<int32_t> src_internal;  // user index -> internal point
+    std::vector<int32_t> iidx;       // [k][Ntot] internal node ids
+    std::vector<double> iw;          // [k][Ntot]
+    std::vector<double> nodes4;      // [ntot][4]
+    std::vector<int32_t> node_user;  // internal node -> user node (concatenated)
+    std::vector<int32_t> node_internal;
+    std::vector<int32_t> node_pair;  // internal node -> pair
+    std::vector<int32_t> adj_ptr, adj_nbr, adj_row, adj_rev;   // directed CSR
+    std::vector<double> adj_r;       // r_ij of Eq. (8)
+    std::vector<int32_t> K_ptr, K_col, K_adj, K_diag;
+    std::vector<int32_t> pj_ptr, pj_ent;   // points influenced by each node: (pt << 3) | slot
+    std::vector<double> tgt4;        // [Mtot][4] sorted; w = user index within the pair
+    std::vector<int32_t> tgt_user;   // sorted position -> user index within the pair
+    std::vector<double> box_lo, box_hi;    // [tree_nodes][4]
+    std::vector<int32_t> pt_tiles, nd_tiles, eg_tiles;   // [tiles][4] = pair, start, end, 0
+    int max_row_cols = 0;
+};
+
+constexpr int kPointTile = 256;
+constexpr int kNodeTile = 64;        // solver rows per tile (4 threads per row)
+constexpr int kEdgeTile = 256;
+constexpr int kMaxCols = 192;        // K blocks per row supported by the assembly
+constexpr int kMaxK = 8;
+
+amm_status validate_pair(const HostPair& hp, std::string& err);
+amm_status build_layout(const std::vector<HostPair>& pairs, int leaf_size, Layout& L,
+                        std::string& err);
+
+}  // namespace amm

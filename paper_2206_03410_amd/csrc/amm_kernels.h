@@ -1,0 +1,220 @@
+// Kernel argument blocks and launchers (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "amm_internal.h"
+
+namespace amm {
+
+template <typename T> struct V4Of;
+template <> struct V4Of<float> { using type = float4; };
+template <> struct V4Of<double> { using type = double4; };
+
+constexpr int kAaParts = 72;   // >= m(m+1)/2 + m for m = AMM_MAX_AA_M
+
+// Records HIP events around launches on a stream and sums their durations
+// per kernel name (host side; enabled on demand).
+struct KernelTimer {
+    virtual void begin(const char* name, hipStream_t s) = 0;
+    virtual void end(hipStream_t s) = 0;
+    virtual ~KernelTimer() {}
+};
+
+template <typename T>
+struct EvalArgs {
+    using V = typename V4Of<T>::type;
+    const int4* pt_tiles;
+    const int4* eg_tiles;
+    const int4* nd_tiles;
+    const PairInfo* info;
+    const PairDyn* dyn;
+    const V* src;
+    const V* src_override;   // internal-order source positions replacing src, or null
+    const int* iidx;
+    const T* iw;
+    int k;
+    int64_t Ntot;
+    const V* nodes;
+    const V* tgt;
+    const V* blo;
+    const V* bhi;
+    const int* adj_row;
+    const int* adj_nbr;
+    const T* adj_r;
+    T* X[3];                 // transform sets 0, 1 and the MM update G(X^k)
+    V* vhat[2];
+    int* rho[2];             // global index into the sorted targets
+    T* d2[2];
+    V* qw[2];                // (Q_i, w_a,i)
+    T* wr[2];                // w_r per directed entry
+    V* Dres[2];              // (D, |D|^2) per directed entry
+    T* R[2];                 // closest rotations, row-major 3x3
+    double* pt_part;
+    double* pt_max;
+    double* eg_part;
+    double* nd_part;
+};
+
+struct FinalArgs {
+    const PairInfo* info;
+    const PairDyn* dyn;
+    PairOut* out;
+    const double* pt_part;
+    const double* pt_max;
+    const double* eg_part;
+    const double* nd_part;
+};
+
+template <typename T>
+struct AsmArgs {
+    using V = typename V4Of<T>::type;
+    const PairDyn* dyn;
+    const int* node_pair;
+    const V* src;
+    const int* iidx;
+    const T* iw;
+    int k;
+    int64_t Ntot;
+    const V* nodes;
+    const int* K_ptr;
+    const int* K_col;
+    const int* K_adj;
+    const int* pj_ptr;
+    const int* pj_ent;
+    const int* adj_ptr;
+    const int* adj_nbr;
+    const int* adj_rev;
+    const T* adj_r;
+    const V* qw[2];
+    const T* wr[2];
+    const T* R[2];
+    T* Kval;
+    T* B;
+    T* Dinv;
+};
+
+template <typename T>
+struct CgArgs {
+    const int4* nd_tiles;
+    const PairInfo* info;
+    const PairDyn* dyn;
+    const int* K_ptr;
+    const int* K_col;
+    const T* Kval;
+    const T* Dinv;
+    const T* b;
+    T* x;
+    T* r;
+    T* u;
+    T* w;
+    T* pv;
+    T* sv;
+    double* part_ru;
+    double* part_rr;
+    double* part_wu;
+    double* part_bb;
+    CgState* state;          // [P][2]
+    double rtol2;
+};
+
+template <typename T>
+struct NodeVecArgs {
+    const int4* nd_tiles;
+    const PairDyn* dyn;
+    int flag;
+    int op;
+    double* x64;
+    const T* src_t;
+    T* dst_t;
+    T* X[3];
+};
+
+template <typename T>
+struct AaArgs {
+    const int4* nd_tiles;
+    const PairDyn* dyn;
+    const PairOut* out;
+    int64_t ntot;
+    T* G;                    // ring [(m+1)][ntot*12]
+    T* F;
+    T* X[3];
+    const double* xnew;      // solution of the surrogate (float64)
+    double* part;            // [nd_tiles][kAaParts]
+};
+
+struct AaSolveArgs {
+    const PairInfo* info;
+    const PairDyn* dyn;
+    PairOut* out;
+    const double* part;
+    int P;
+};
+
+template <typename T>
+struct GradArgs {
+    using V = typename V4Of<T>::type;
+    const int4* pt_tiles;
+    const PairInfo* info;
+    const PairDyn* dyn;
+    const int* node_pair;
+    const V* src;
+    const V* src_override;
+    const int* src_user;
+    const int* node_user;
+    const int* iidx;
+    const T* iw;
+    int k;
+    int64_t Ntot;
+    const V* nodes;
+    const V* tgt;
+    const int* pj_ptr;
+    const int* pj_ent;
+    const int* adj_ptr;
+    const int* adj_nbr;
+    const int* adj_rev;
+    const T* adj_r;
+    const T* X;
+    const V* vhat[2];
+    const int* rho[2];
+    const T* d2[2];
+    const V* Dres[2];
+    const T* R[2];
+    V* gpt;
+    T* gX;                   // user node order
+    T* gV;                   // user point order, may be null
+};
+
+template <typename T>
+void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_tiles, const FinalArgs& f,
+                 int P, hipStream_t s, KernelTimer* tm);
+template <typename T>
+void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTimer* tm);
+template <typename T>
+void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, int zero_x, hipStream_t s, KernelTimer* tm);
+template <typename T>
+void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm);
+template <typename T>
+void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const double* x64, T* rhs_out,
+                       double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm);
+template <typename T>
+void launch_node_vec_op(const NodeVecArgs<T>& a, int n_nd_tiles, hipStream_t s);
+template <typename T>
+void launch_aa(const AaArgs<T>& a, const AaSolveArgs& sa, int n_nd_tiles, hipStream_t s, KernelTimer* tm);
+template <typename T>
+void launch_grad(const GradArgs<T>& a, int n_pt_tiles, int64_t ntot, hipStream_t s);
+template <typename T, typename U>
+void launch_x_import(const U* xu, T* xi, const int* node_user, int64_t ntot, hipStream_t s);
+template <typename T, typename U>
+void launch_x_export(const T* xi, U* xu, const int* node_user, int64_t ntot, hipStream_t s);
+template <typename T, typename U>
+void launch_src_import(const U* su, void* si, const int* src_user, int64_t Ntot, hipStream_t s);
+template <typename T, typename U>
+void launch_points_export(const void* vi, U* vu, const int* src_user, int64_t Ntot, hipStream_t s);
+template <typename T, typename U>
+void launch_nn_export(const int* rho, const T* d2, const int* src_user, const int* tgt_user, int32_t* rho_u,
+                      U* d2_u, int64_t Ntot, hipStream_t s);
+template <typename T>
+void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s);
+
+}  // namespace amm

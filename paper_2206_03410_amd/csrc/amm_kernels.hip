@@ -1,0 +1,1307 @@
+// HIP kernels for gfx950 (MI355X) implementing one MM iteration of robust
+// non-rigid registration (arXiv 2206.03410, Sec. 3.3) and its gradient.
+//
+// Every kernel is batched: tiles never straddle pairs, and per-pair scalars
+// (nu, alpha, beta, flags) come from a small PairDyn array.  All reductions
+// are fixed-order trees (no floating-point atomics), so results are
+// bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+
+#include "amm_kernels.h"
+#include "amm_nn.h"
+
+namespace amm {
+
+// ---------------------------------------------------------------- helpers
+
+template <typename T> __device__ __forceinline__ T dev_inf();
+template <> __device__ __forceinline__ float dev_inf<float>() { return __builtin_inff(); }
+template <> __device__ __forceinline__ double dev_inf<double>() { return __builtin_inf(); }
+
+// Maps block b of G to a tile so that each of the 8 XCDs (blocks are
+// dispatched round-robin over XCDs) works on one contiguous range of tiles,
+// which keeps the target data a range touches inside one XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    const int per = G >> 3, rem = G & 7;
+    const int x = b & 7, q = b >> 3;
+    return x * per + min(x, rem) + q;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    T r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ T block_max(T v, T* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    T r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- evaluation
+
+// Per source point: warp (Eq. 2), closest target, Welsch value and weight
+// (Eqs. 5, 6, 15), Q_i = u_rho(i) - sum_j w_ij p_j (Sec. 3.3.2), max
+// displacement against the accepted iterate.  One thread per point.
+template <typename T>
+__global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
+    using V = typename V4Of<T>::type;
+    __shared__ T sh[kPointTile];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int4 td = a.pt_tiles[tile];
+    const int p = td.x;
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_EVAL)) return;                 // uniform over the block
+    const PairInfo pi = a.info[p];
+    const int i = td.y + (int)threadIdx.x;
+    const int dst = dy.eval_dst, cur = dy.cur;
+    const T* X = a.X[dy.eval_x];
+    const V* src = a.src_override ? (const V*)a.src_override : (const V*)a.src;
+    T psi = 0, disp = 0;
+    if (i < td.z) {
+        const V v = src[i];
+        T vx = 0, vy = 0, vz = 0, sx = 0, sy = 0, sz = 0;
+        for (int s = 0; s < a.k; ++s) {
+            const int j = a.iidx[(size_t)s * a.Ntot + i];
+            const T w = a.iw[(size_t)s * a.Ntot + i];
+            const V pj = a.nodes[j];
+            const T* Xj = X + 12 * (size_t)j;
+            const T dx = v.x - pj.x, dyy = v.y - pj.y, dz = v.z - pj.z;
+            const T yx = dx * Xj[0] + dyy * Xj[3] + dz * Xj[6] + Xj[9] + pj.x;
+            const T yy = dx * Xj[1] + dyy * Xj[4] + dz * Xj[7] + Xj[10] + pj.y;
+            const T yz = dx * Xj[2] + dyy * Xj[5] + dz * Xj[8] + Xj[11] + pj.z;
+            vx += w * yx;
+            vy += w * yy;
+            vz += w * yz;
+            sx += w * pj.x;
+            sy += w * pj.y;
+            sz += w * pj.z;
+        }
+        const int prev = dy.has_prev ? a.rho[cur][i] - (int)pi.tgt_off : -1;
+        int bpos;
+        T d2;
+        nn_search<T>(pi, a.tgt, a.blo, a.bhi, vx, vy, vz, prev, bpos, d2);
+        const V u = a.tgt[pi.tgt_off + bpos];
+        const T inv = T(1) / (T(2) * (T)dy.nu_a * (T)dy.nu_a);
+        const T t = d2 * inv;
+        psi = -expm1(-t);
+        const T wa = exp(-t) * inv;
+        V q;
+        q.x = u.x - sx;
+        q.y = u.y - sy;
+        q.z = u.z - sz;
+        q.w = wa;
+        a.qw[dst][i] = q;
+        a.rho[dst][i] = (int)pi.tgt_off + bpos;
+        a.d2[dst][i] = d2;
+        V vh;
+        vh.x = vx;
+        vh.y = vy;
+        vh.z = vz;
+        vh.w = 0;
+        if (dy.has_prev) {
+            const V o = a.vhat[cur][i];
+            disp = sqrt(sq3(vx - o.x, vy - o.y, vz - o.z));
+        }
+        a.vhat[dst][i] = vh;
+    }
+    const T tot = block_sum<T, kPointTile>(psi, sh);
+    const T mx = block_max<T, kPointTile>(disp, sh);
+    if (threadIdx.x == 0) {
+        a.pt_part[tile] = (double)tot;
+        a.pt_max[tile] = (double)mx;
+    }
+}
+
+// Per directed node pair (a, b): D_ab of Eq. (7) (transform of b applied at
+// p_a), Welsch value and weight (Eqs. 9, 13).  Evaluated as
+// r ((A_b - I)(p_a - p_b) + t_b - t_a), equal to Eq. (7) and free of the
+// cancellation between p_a and p_b.
+template <typename T>
+__global__ void __launch_bounds__(kEdgeTile) k_eval_edges(EvalArgs<T> a) {
+    using V = typename V4Of<T>::type;
+    __shared__ T sh[kEdgeTile];
+    const int tile = blockIdx.x;
+    const int4 td = a.eg_tiles[tile];
+    const int p = td.x;
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_EVAL)) return;
+    const int e = td.y + (int)threadIdx.x;
+    const T* X = a.X[dy.eval_x];
+    T psi = 0;
+    if (e < td.z) {
+        const int ia = a.adj_row[e], ib = a.adj_nbr[e];
+        const T r = a.adj_r[e];
+        const V pa = a.nodes[ia], pb = a.nodes[ib];
+        const T* Xa = X + 12 * (size_t)ia;
+        const T* Xb = X + 12 * (size_t)ib;
+        const T dx = pa.x - pb.x, dyy = pa.y - pb.y, dz = pa.z - pb.z;
+        const T Dx = r * (dx * (Xb[0] - T(1)) + dyy * Xb[3] + dz * Xb[6] + (Xb[9] - Xa[9]));
+        const T Dy = r * (dx * Xb[1] + dyy * (Xb[4] - T(1)) + dz * Xb[7] + (Xb[10] - Xa[10]));
+        const T Dz = r * (dx * Xb[2] + dyy * Xb[5] + dz * (Xb[8] - T(1)) + (Xb[11] - Xa[11]));
+        const T D2 = sq3(Dx, Dy, Dz);
+        const T inv = T(1) / (T(2) * (T)dy.nu_r * (T)dy.nu_r);
+        psi = -expm1(-D2 * inv);
+        a.wr[dy.eval_dst][e] = exp(-D2 * inv) * inv;
+        V D;
+        D.x = Dx;
+        D.y = Dy;
+        D.z = Dz;
+        D.w = D2;
+        a.Dres[dy.eval_dst][e] = D;
+    }
+    const T tot = block_sum<T, kEdgeTile>(psi, sh);
+    if (threadIdx.x == 0) a.eg_part[tile] = (double)tot;
+}
+
+// Closest rotation to a 3x3 matrix A (rotation term, Sec. 3.2): one-sided
+// Jacobi SVD (Hestenes) of A, U completed to a right-handed frame, then
+// R = U diag(1, 1, det V) V^T, which equals U' diag(1,1,det(U'V^T)) V^T for
+// any SVD A = U' S V^T.  Returns |A - R|_F^2.
+template <typename T>
+__device__ T proj_rot(const T A[3][3], T R[3][3]) {
+    T B[3][3], Vm[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            B[r][c] = A[r][c];
+            Vm[r][c] = (r == c) ? T(1) : T(0);
+        }
+    const T tol = sizeof(T) == 4 ? T(1e-7) : T(1e-15);
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        bool rotated = false;
+        for (int pq = 0; pq < 3; ++pq) {
+            const int pp = pq == 2 ? 1 : 0;
+            const int qq = pq == 0 ? 1 : 2;
+            T al = 0, be = 0, ga = 0;
+            for (int r = 0; r < 3; ++r) {
+                al += B[r][pp] * B[r][pp];
+                be += B[r][qq] * B[r][qq];
+                ga += B[r][pp] * B[r][qq];
+            }
+            if (fabs(ga) <= tol * sqrt(al * be) || ga == T(0)) continue;
+            rotated = true;
+            const T zeta = (be - al) / (T(2) * ga);
+            const T t = (zeta >= 0 ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+            const T c = T(1) / sqrt(T(1) + t * t);
+            const T s = c * t;
+            for (int r = 0; r < 3; ++r) {
+                const T bp = B[r][pp], bq = B[r][qq];
+                B[r][pp] = c * bp - s * bq;
+                B[r][qq] = s * bp + c * bq;
+                const T vp = Vm[r][pp], vq = Vm[r][qq];
+                Vm[r][pp] = c * vp - s * vq;
+                Vm[r][qq] = s * vp + c * vq;
+            }
+        }
+        if (!rotated) break;
+    }
+    T sig[3];
+    int ord[3] = {0, 1, 2};
+    for (int c = 0; c < 3; ++c) sig[c] = sqrt(B[0][c] * B[0][c] + B[1][c] * B[1][c] + B[2][c] * B[2][c]);
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2 - x; ++y)
+            if (sig[ord[y]] < sig[ord[y + 1]]) {
+                int tmp = ord[y];
+                ord[y] = ord[y + 1];
+                ord[y + 1] = tmp;
+            }
+    T U[3][3], V[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) V[r][c] = Vm[r][ord[c]];
+    // u0, u1 by Gram-Schmidt of the two largest columns, u2 = u0 x u1
+    T u0[3], u1[3];
+    {
+        const T s0 = sig[ord[0]];
+        if (s0 > T(0)) {
+            for (int r = 0; r < 3; ++r) u0[r] = B[r][ord[0]] / s0;
+        } else {
+            u0[0] = 1;
+            u0[1] = 0;
+            u0[2] = 0;
+        }
+        T b1[3];
+        for (int r = 0; r < 3; ++r) b1[r] = B[r][ord[1]];
+        const T dp = u0[0] * b1[0] + u0[1] * b1[1] + u0[2] * b1[2];
+        for (int r = 0; r < 3; ++r) b1[r] -= dp * u0[r];
+        T n1 = sqrt(b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2]);
+        if (!(n1 > T(0))) {
+            // any unit vector orthogonal to u0
+            const T ax = fabs(u0[0]) < T(0.9) ? T(1) : T(0);
+            const T ay = T(1) - ax;
+            b1[0] = ax - u0[0] * (u0[0] * ax + u0[1] * ay);
+            b1[1] = ay - u0[1] * (u0[0] * ax + u0[1] * ay);
+            b1[2] = -u0[2] * (u0[0] * ax + u0[1] * ay);
+            n1 = sqrt(b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2]);
+        }
+        for (int r = 0; r < 3; ++r) u1[r] = b1[r] / n1;
+    }
+    for (int r = 0; r < 3; ++r) {
+        U[r][0] = u0[r];
+        U[r][1] = u1[r];
+    }
+    U[0][2] = u0[1] * u1[2] - u0[2] * u1[1];
+    U[1][2] = u0[2] * u1[0] - u0[0] * u1[2];
+    U[2][2] = u0[0] * u1[1] - u0[1] * u1[0];
+    const T detV = V[0][0] * (V[1][1] * V[2][2] - V[1][2] * V[2][1]) -
+                   V[0][1] * (V[1][0] * V[2][2] - V[1][2] * V[2][0]) +
+                   V[0][2] * (V[1][0] * V[2][1] - V[1][1] * V[2][0]);
+    const T d3 = detV >= 0 ? T(1) : T(-1);
+    T e = 0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            R[r][c] = U[r][0] * V[c][0] + U[r][1] * V[c][1] + d3 * U[r][2] * V[c][2];
+            const T dd = A[r][c] - R[r][c];
+            e += dd * dd;
+        }
+    return e;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNodeTile) k_eval_nodes(EvalArgs<T> a) {
+    __shared__ T sh[kNodeTile];
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const int p = td.x;
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_EVAL)) return;
+    const int j = td.y + (int)threadIdx.x;
+    const T* X = a.X[dy.eval_x];
+    T er = 0;
+    if (j < td.z) {
+        T A[3][3], R[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) A[c][r] = X[12 * (size_t)j + 3 * r + c];
+        er = proj_rot<T>(A, R);
+        T* Ro = a.R[dy.eval_dst] + 9 * (size_t)j;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Ro[3 * r + c] = R[r][c];
+    }
+    const T tot = block_sum<T, kNodeTile>(er, sh);
+    if (threadIdx.x == 0) a.nd_part[tile] = (double)tot;
+}
+
+// Per pair: E = E_align + alpha E_reg + beta E_rot (Eq. 4) from the tile
+// partials in a fixed order, and the max displacement.
+__global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
+    const int p = blockIdx.x;
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_EVAL)) return;
+    const PairInfo pi = a.info[p];
+    double sa = 0, sr = 0, so = 0, mx = 0;
+    for (int t = threadIdx.x; t < pi.pt_ntile; t += 64) {
+        sa += a.pt_part[pi.pt_tile0 + t];
+        mx = fmax(mx, a.pt_max[pi.pt_tile0 + t]);
+    }
+    for (int t = threadIdx.x; t < pi.eg_ntile; t += 64) sr += a.eg_part[pi.eg_tile0 + t];
+    for (int t = threadIdx.x; t < pi.nd_ntile; t += 64) so += a.nd_part[pi.nd_tile0 + t];
+    sa = wave_sum(sa);
+    sr = wave_sum(sr);
+    so = wave_sum(so);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (threadIdx.x == 0) {
+        PairOut& out = a.out[p];
+        out.Ea = sa;
+        out.Er = sr;
+        out.Eo = so;
+        out.E = sa + dy.alpha * sr + dy.beta * so;
+        out.maxdisp = mx;
+    }
+}
+
+// ---------------------------------------------------------------- assembly
+
+// Row j of K and B (Eq. 16), one wave per node.  Alignment blocks
+// K_jl = sum_i w_a,i w_ij w_il [v_i - p_j; 1][v_i - p_l; 1]^T are formed as
+// moments anchored at p_j, M_jl = sum c_i w_il x x^T with x = [v_i - p_j; 1],
+// then shifted: K_jl = M_jl S^T, S = [[I, p_j - p_l], [0, 1]].  Lanes first
+// own points (stage moments in LDS), then own columns of the row (gather in
+// a fixed order).  Edge blocks follow Eqs. (7), (13) and the matrix H, the
+// rotation term adds beta J^T J and beta J^T J Z.  The 4x4 diagonal block's
+// inverse (block-Jacobi preconditioner) is written alongside.
+template <typename T>
+__global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
+    using V = typename V4Of<T>::type;
+    constexpr int CM = (kMaxCols + 63) / 64;
+    __shared__ T smom[64][10];
+    __shared__ int snid[64][kMaxK];
+    __shared__ T swgt[64][kMaxK];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int p = a.node_pair[j];
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_SOLVE)) return;
+    const int cur = dy.cur;
+    const V* qw = a.qw[cur];
+    const T* wr = a.wr[cur];
+    const V pj = a.nodes[j];
+    const int kb = a.K_ptr[j], ke = a.K_ptr[j + 1];
+    const int nch = (ke - kb + 63) / 64;
+    const int k = a.k;
+    int lcol[CM];
+    T acc[CM][10];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+        const int pos = kb + lane + 64 * c;
+        lcol[c] = pos < ke ? a.K_col[pos] : -1;
+#pragma unroll
+        for (int m = 0; m < 10; ++m) acc[c][m] = 0;
+    }
+    T bacc[12];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) bacc[m] = 0;
+    const int e0 = a.pj_ptr[j], e1 = a.pj_ptr[j + 1];
+    for (int base = e0; base < e1; base += 64) {
+        const int e = base + lane;
+        if (e < e1) {
+            const int ent = a.pj_ent[e];
+            const int i = ent >> 3, s = ent & 7;
+            const V v = a.src[i];
+            const V q = qw[i];
+            const T c = q.w * a.iw[(size_t)s * a.Ntot + i];
+            const T dx = v.x - pj.x, dyy = v.y - pj.y, dz = v.z - pj.z;
+            smom[lane][0] = c * dx * dx;
+            smom[lane][1] = c * dx * dyy;
+            smom[lane][2] = c * dx * dz;
+            smom[lane][3] = c * dx;
+            smom[lane][4] = c * dyy * dyy;
+            smom[lane][5] = c * dyy * dz;
+            smom[lane][6] = c * dyy;
+            smom[lane][7] = c * dz * dz;
+            smom[lane][8] = c * dz;
+            smom[lane][9] = c;
+            const T ax = c * dx, ay = c * dyy, az = c * dz;
+            bacc[0] += ax * q.x;
+            bacc[1] += ax * q.y;
+            bacc[2] += ax * q.z;
+            bacc[3] += ay * q.x;
+            bacc[4] += ay * q.y;
+            bacc[5] += ay * q.z;
+            bacc[6] += az * q.x;
+            bacc[7] += az * q.y;
+            bacc[8] += az * q.z;
+            bacc[9] += c * q.x;
+            bacc[10] += c * q.y;
+            bacc[11] += c * q.z;
+            for (int b = 0; b < kMaxK; ++b) {
+                snid[lane][b] = b < k ? a.iidx[(size_t)b * a.Ntot + i] : -1;
+                swgt[lane][b] = b < k ? a.iw[(size_t)b * a.Ntot + i] : T(0);
+            }
+        } else {
+            for (int m = 0; m < 10; ++m) smom[lane][m] = 0;
+            for (int b = 0; b < kMaxK; ++b) {
+                snid[lane][b] = -1;
+                swgt[lane][b] = 0;
+            }
+        }
+        __syncthreads();
+        const int cnt = min(64, e1 - base);
+        for (int t = 0; t < cnt; ++t) {
+            for (int b = 0; b < k; ++b) {
+                const int nid = snid[t][b];
+#pragma unroll
+                for (int c = 0; c < CM; ++c) {
+                    if (c < nch && nid == lcol[c]) {
+                        const T w = swgt[t][b];
+#pragma unroll
+                        for (int m = 0; m < 10; ++m) acc[c][m] += w * smom[t][m];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 12; ++m) bacc[m] = wave_sum(bacc[m]);
+
+    const T alpha = (T)dy.alpha, beta = (T)dy.beta;
+    const int ab = a.adj_ptr[j], ae = a.adj_ptr[j + 1];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+        const int pos = kb + lane + 64 * c;
+        if (c >= nch || pos >= ke) continue;
+        const int l = lcol[c];
+        const V pl = a.nodes[l];
+        const T* m = acc[c];
+        const T S[4][4] = {{m[0], m[1], m[2], m[3]},
+                           {m[1], m[4], m[5], m[6]},
+                           {m[2], m[5], m[7], m[8]},
+                           {m[3], m[6], m[8], m[9]}};
+        const T del[3] = {pj.x - pl.x, pj.y - pl.y, pj.z - pl.z};
+        T Kb[4][4];
+        for (int r = 0; r < 4; ++r) {
+            for (int s = 0; s < 3; ++s) Kb[r][s] = S[r][s] + S[r][3] * del[s];
+            Kb[r][3] = S[r][3];
+        }
+        const int adj = a.K_adj[pos];
+        if (adj >= 0) {
+            // D_jl (entry j->l, transform of l) and D_lj (entry l->j, transform of j)
+            const int rev = a.adj_rev[adj];
+            const T rr = a.adj_r[adj];
+            const T om_e = alpha * wr[adj] * rr * rr;
+            const T om_r = alpha * wr[rev] * rr * rr;
+            const T ext[4] = {-del[0], -del[1], -del[2], T(1)};   // [p_l - p_j; 1]
+            const T exj[4] = {del[0], del[1], del[2], T(1)};      // [p_j - p_l; 1]
+            for (int r = 0; r < 4; ++r) Kb[r][3] -= om_r * ext[r];
+            for (int s = 0; s < 4; ++s) Kb[3][s] -= om_e * exj[s];
+        }
+        if (l == j) {
+            for (int e = ab; e < ae; ++e) {
+                const int l2 = a.adj_nbr[e], rev = a.adj_rev[e];
+                const T rr = a.adj_r[e];
+                const T om_e = alpha * wr[e] * rr * rr;
+                const T om_r = alpha * wr[rev] * rr * rr;
+                const V q2 = a.nodes[l2];
+                const T ext[4] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z, T(1)};
+                for (int r = 0; r < 4; ++r)
+                    for (int s = 0; s < 4; ++s) Kb[r][s] += om_r * ext[r] * ext[s];
+                Kb[3][3] += om_e;
+            }
+            for (int s = 0; s < 3; ++s) Kb[s][s] += beta;
+            // block-Jacobi: inverse of the diagonal block (Gauss-Jordan, partial pivoting)
+            T Mx[4][8];
+            for (int r = 0; r < 4; ++r)
+                for (int s = 0; s < 4; ++s) {
+                    Mx[r][s] = Kb[r][s];
+                    Mx[r][4 + s] = r == s ? T(1) : T(0);
+                }
+            bool ok = true;
+            for (int c2 = 0; c2 < 4; ++c2) {
+                int piv = c2;
+                for (int r = c2 + 1; r < 4; ++r)
+                    if (fabs(Mx[r][c2]) > fabs(Mx[piv][c2])) piv = r;
+                if (!(fabs(Mx[piv][c2]) > T(0))) {
+                    ok = false;
+                    break;
+                }
+                if (piv != c2)
+                    for (int s = 0; s < 8; ++s) {
+                        T tmp = Mx[c2][s];
+                        Mx[c2][s] = Mx[piv][s];
+                        Mx[piv][s] = tmp;
+                    }
+                const T invp = T(1) / Mx[c2][c2];
+                for (int s = 0; s < 8; ++s) Mx[c2][s] *= invp;
+                for (int r = 0; r < 4; ++r)
+                    if (r != c2) {
+                        const T f = Mx[r][c2];
+                        for (int s = 0; s < 8; ++s) Mx[r][s] -= f * Mx[c2][s];
+                    }
+            }
+            T* Di = a.Dinv + 16 * (size_t)j;
+            for (int r = 0; r < 4; ++r)
+                for (int s = 0; s < 4; ++s)
+                    Di[4 * r + s] = ok ? Mx[r][4 + s]
+                                       : (r == s ? T(1) / fmax(fabs(Kb[r][r]), T(1e-30)) : T(0));
+        }
+        T* Ko = a.Kval + 16 * (size_t)pos;
+        for (int r = 0; r < 4; ++r)
+            for (int s = 0; s < 4; ++s) Ko[4 * r + s] = Kb[r][s];
+    }
+    if (lane == 0) {
+        T Bj[12];
+        for (int m2 = 0; m2 < 12; ++m2) Bj[m2] = bacc[m2];
+        for (int e = ab; e < ae; ++e) {
+            const int l2 = a.adj_nbr[e], rev = a.adj_rev[e];
+            const T rr = a.adj_r[e];
+            const T om_e = alpha * wr[e] * rr * rr;
+            const T om_r = alpha * wr[rev] * rr * rr;
+            const V q2 = a.nodes[l2];
+            const T dd[3] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z};
+            for (int c2 = 0; c2 < 3; ++c2) {
+                for (int r = 0; r < 3; ++r) Bj[3 * r + c2] += om_r * dd[r] * dd[c2];
+                Bj[9 + c2] += (om_r + om_e) * dd[c2];
+            }
+        }
+        const T* Rj = a.R[cur] + 9 * (size_t)j;
+        for (int r = 0; r < 3; ++r)
+            for (int c2 = 0; c2 < 3; ++c2) Bj[3 * r + c2] += beta * Rj[3 * c2 + r];
+        T* Bo = a.B + 12 * (size_t)j;
+        for (int m2 = 0; m2 < 12; ++m2) Bo[m2] = Bj[m2];
+    }
+}
+
+// ---------------------------------------------------------------- CG (Chronopoulos-Gear)
+
+// Vectors are [n][4][3]; each node row is handled by 4 consecutive threads
+// (thread r owns row r of the 4x3 block), 64 rows per 256-thread tile.
+
+template <typename T>
+__device__ __forceinline__ void spmv_row(const CgArgs<T>& a, int j, int r, const T* x, T out[3]) {
+    out[0] = out[1] = out[2] = 0;
+    const int kb = a.K_ptr[j], ke = a.K_ptr[j + 1];
+    for (int pos = kb; pos < ke; ++pos) {
+        const int l = a.K_col[pos];
+        const T* kr = a.Kval + 16 * (size_t)pos + 4 * r;
+        const T* xl = x + 12 * (size_t)l;
+        const T k0 = kr[0], k1 = kr[1], k2 = kr[2], k3 = kr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] += k0 * xl[c] + k1 * xl[3 + c] + k2 * xl[6 + c] + k3 * xl[9 + c];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void reduce3_store(T v0, T v1, T v2, T* sh, double* dst) {
+    const T s0 = block_sum<T, 4 * kNodeTile>(v0, sh);
+    const T s1 = block_sum<T, 4 * kNodeTile>(v1, sh);
+    const T s2 = block_sum<T, 4 * kNodeTile>(v2, sh);
+    if (threadIdx.x == 0) {
+        dst[0] = (double)s0;
+        dst[1] = (double)s1;
+        dst[2] = (double)s2;
+    }
+}
+
+// r = b - K x0 (x0 = 0 when zero_x), u = M^{-1} r; partials (r,u), (r,r), (b,b).
+template <typename T>
+__global__ void __launch_bounds__(4 * kNodeTile) k_cg_init(CgArgs<T> a, int zero_x) {
+    __shared__ T sh[4 * kNodeTile];
+    __shared__ T rs[kNodeTile][4][3];
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const int p = td.x;
+    if (!(a.dyn[p].flags & PF_SOLVE)) return;
+    const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
+    const int j = td.y + lr;
+    T rv[3] = {0, 0, 0}, bv[3] = {0, 0, 0};
+    if (j < td.z) {
+        T kx[3] = {0, 0, 0};
+        if (!zero_x) spmv_row(a, j, r, a.x, kx);
+        for (int c = 0; c < 3; ++c) {
+            bv[c] = a.b[12 * (size_t)j + 3 * r + c];
+            rv[c] = bv[c] - kx[c];
+            a.r[12 * (size_t)j + 3 * r + c] = rv[c];
+            if (zero_x) a.x[12 * (size_t)j + 3 * r + c] = 0;
+        }
+    }
+    for (int c = 0; c < 3; ++c) rs[lr][r][c] = rv[c];
+    __syncthreads();
+    T uv[3] = {0, 0, 0};
+    if (j < td.z) {
+        const T* Di = a.Dinv + 16 * (size_t)j + 4 * r;
+        for (int c = 0; c < 3; ++c) {
+            uv[c] = Di[0] * rs[lr][0][c] + Di[1] * rs[lr][1][c] + Di[2] * rs[lr][2][c] + Di[3] * rs[lr][3][c];
+            a.u[12 * (size_t)j + 3 * r + c] = uv[c];
+        }
+    }
+    reduce3_store(rv[0] * uv[0], rv[1] * uv[1], rv[2] * uv[2], sh, a.part_ru + 3 * tile);
+    reduce3_store(rv[0] * rv[0], rv[1] * rv[1], rv[2] * rv[2], sh, a.part_rr + 3 * tile);
+    reduce3_store(bv[0] * bv[0], bv[1] * bv[1], bv[2] * bv[2], sh, a.part_bb + 3 * tile);
+    if (threadIdx.x < 3 && tile == a.info[p].nd_tile0) {
+        CgState* st = a.state + 2 * (size_t)p;
+        st[0].conv[threadIdx.x] = 0;
+        st[1].conv[threadIdx.x] = 0;
+        if (threadIdx.x == 0) {
+            st[0].iters = st[1].iters = 0;
+            st[0].breakdown = st[1].breakdown = 0;
+        }
+    }
+}
+
+// w = K u; partial (w, u).  Skipped for pairs whose three columns converged.
+template <typename T>
+__global__ void __launch_bounds__(4 * kNodeTile) k_cg_spmv(CgArgs<T> a, int it) {
+    __shared__ T sh[4 * kNodeTile];
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const int p = td.x;
+    if (!(a.dyn[p].flags & PF_SOLVE)) return;
+    if (it >= 0) {
+        const CgState& st = a.state[2 * (size_t)p + (it & 1)];
+        if (st.conv[0] && st.conv[1] && st.conv[2]) return;
+    }
+    const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
+    const int j = td.y + lr;
+    T wv[3] = {0, 0, 0}, uv[3] = {0, 0, 0};
+    if (j < td.z) {
+        spmv_row(a, j, r, a.u, wv);
+        for (int c = 0; c < 3; ++c) {
+            a.w[12 * (size_t)j + 3 * r + c] = wv[c];
+            uv[c] = a.u[12 * (size_t)j + 3 * r + c];
+        }
+    }
+    reduce3_store(wv[0] * uv[0], wv[1] * uv[1], wv[2] * uv[2], sh, a.part_wu + 3 * tile);
+}
+
+// Pair-level reduction of tile partials in a fixed order (every block of the
+// pair computes the same value).
+__device__ __forceinline__ double pair_dot(const double* part, int t0, int nt, int c) {
+    double s = 0;
+    for (int t = 0; t < nt; ++t) s += part[3 * (t0 + t) + c];
+    return s;
+}
+
+// One Chronopoulos-Gear step: scalars from the partials of the previous
+// step, p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+// u = M^{-1} r; partials (r,u), (r,r).  Columns whose relative residual
+// reached rtol (or that broke down) stay frozen.
+template <typename T>
+__global__ void __launch_bounds__(4 * kNodeTile) k_cg_update(CgArgs<T> a, int it) {
+    __shared__ T sh[4 * kNodeTile];
+    __shared__ T rs[kNodeTile][4][3];
+    __shared__ double scal[3][3];   // alpha, beta, active
+    __shared__ int brk_mask;
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const int p = td.x;
+    if (!(a.dyn[p].flags & PF_SOLVE)) return;
+    const PairInfo& pi = a.info[p];
+    const CgState& prv = a.state[2 * (size_t)p + ((it + 1) & 1)];
+    if (threadIdx.x == 0) brk_mask = 0;
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        const double gam = pair_dot(a.part_ru, pi.nd_tile0, pi.nd_ntile, c);
+        const double del = pair_dot(a.part_wu, pi.nd_tile0, pi.nd_ntile, c);
+        const double rr = pair_dot(a.part_rr, pi.nd_tile0, pi.nd_ntile, c);
+        const double bb = pair_dot(a.part_bb, pi.nd_tile0, pi.nd_ntile, c);
+        int conv = prv.conv[c];
+        int brk = 0;
+        double al = 0, be = 0;
+        if (!conv) {
+            if (rr <= a.rtol2 * bb || bb == 0.0) {
+                conv = 1;
+            } else if (it == 0) {
+                al = gam / del;
+            } else {
+                be = gam / prv.gamma[c];
+                al = gam / (del - be * gam / prv.alpha[c]);
+            }
+            if (!conv && !(al > 0.0 && gam > 0.0 && al < 1e300)) {
+                conv = 1;
+                brk = 1;
+                al = be = 0;
+            }
+        }
+        scal[c][0] = al;
+        scal[c][1] = be;
+        scal[c][2] = conv ? 0.0 : 1.0;
+        if (tile == pi.nd_tile0) {
+            CgState& st = a.state[2 * (size_t)p + (it & 1)];
+            st.alpha[c] = al;
+            st.gamma[c] = gam;
+            st.rr[c] = rr;
+            st.bb[c] = bb;
+            st.conv[c] = conv;
+        }
+        if (brk) atomicOr(&brk_mask, 1 << c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && tile == pi.nd_tile0) {
+        CgState& st = a.state[2 * (size_t)p + (it & 1)];
+        const bool any = scal[0][2] != 0.0 || scal[1][2] != 0.0 || scal[2][2] != 0.0;
+        st.iters = prv.iters + (any ? 1 : 0);
+        st.breakdown = prv.breakdown | brk_mask;
+    }
+    const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
+    const int j = td.y + lr;
+    T rv[3] = {0, 0, 0};
+    if (j < td.z) {
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = 12 * (size_t)j + 3 * r + c;
+            rv[c] = a.r[o];
+            if (scal[c][2] != 0.0) {
+                const T al = (T)scal[c][0], be = (T)scal[c][1];
+                const T pn = it == 0 ? a.u[o] : a.u[o] + be * a.pv[o];
+                const T sn = it == 0 ? a.w[o] : a.w[o] + be * a.sv[o];
+                a.pv[o] = pn;
+                a.sv[o] = sn;
+                a.x[o] += al * pn;
+                rv[c] -= al * sn;
+                a.r[o] = rv[c];
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) rs[lr][r][c] = rv[c];
+    __syncthreads();
+    T uv[3] = {0, 0, 0};
+    if (j < td.z) {
+        const T* Di = a.Dinv + 16 * (size_t)j + 4 * r;
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = 12 * (size_t)j + 3 * r + c;
+            if (scal[c][2] != 0.0) {
+                uv[c] = Di[0] * rs[lr][0][c] + Di[1] * rs[lr][1][c] + Di[2] * rs[lr][2][c] +
+                        Di[3] * rs[lr][3][c];
+                a.u[o] = uv[c];
+            } else {
+                uv[c] = a.u[o];
+            }
+        }
+    }
+    reduce3_store(rv[0] * uv[0], rv[1] * uv[1], rv[2] * uv[2], sh, a.part_ru + 3 * tile);
+    reduce3_store(rv[0] * rv[0], rv[1] * rv[1], rv[2] * rv[2], sh, a.part_rr + 3 * tile);
+}
+
+// ---------------------------------------------------------------- iterative refinement
+
+// r64 = B - K x64 in float64 (K, B in T, upcast exactly); the float32 copy
+// of r64 is the right-hand side of the next inner solve.  Partials (r,r), (B,B).
+template <typename T>
+__global__ void __launch_bounds__(4 * kNodeTile) k_residual64(CgArgs<T> a, const T* B, const double* x64,
+                                                              T* rhs_out, double* part_rr,
+                                                              double* part_bb) {
+    __shared__ double sh[4 * kNodeTile];
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const int p = td.x;
+    if (!(a.dyn[p].flags & PF_SOLVE)) return;
+    const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
+    const int j = td.y + lr;
+    double rv[3] = {0, 0, 0}, bv[3] = {0, 0, 0};
+    if (j < td.z) {
+        double acc[3] = {0, 0, 0};
+        const int kb = a.K_ptr[j], ke = a.K_ptr[j + 1];
+        for (int pos = kb; pos < ke; ++pos) {
+            const int l = a.K_col[pos];
+            const T* kr = a.Kval + 16 * (size_t)pos + 4 * r;
+            const double* xl = x64 + 12 * (size_t)l;
+            for (int c = 0; c < 3; ++c)
+                acc[c] += (double)kr[0] * xl[c] + (double)kr[1] * xl[3 + c] + (double)kr[2] * xl[6 + c] +
+                          (double)kr[3] * xl[9 + c];
+        }
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = 12 * (size_t)j + 3 * r + c;
+            bv[c] = (double)B[o];
+            rv[c] = bv[c] - acc[c];
+            if (rhs_out) rhs_out[o] = (T)rv[c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        const double s = block_sum<double, 4 * kNodeTile>(rv[c] * rv[c], sh);
+        const double s2 = block_sum<double, 4 * kNodeTile>(bv[c] * bv[c], sh);
+        if (threadIdx.x == 0) {
+            part_rr[3 * tile + c] = s;
+            part_bb[3 * tile + c] = s2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- vector utilities
+
+template <typename T>
+__global__ void k_node_vec_op(NodeVecArgs<T> a) {
+    // 0: x64 = src_t        1: x64 += src_t       2: dst_t = (T) x64      3: dst_t = src_t
+    // 4: x64 = X[cur]       5: X[2] = X[cur]      6: X[1 - cur] = X[2]
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const PairDyn dy = a.dyn[td.x];
+    if (!(dy.flags & a.flag)) return;
+    const size_t b0 = 12 * (size_t)td.y, b1 = 12 * (size_t)td.z;
+    for (size_t o = b0 + threadIdx.x; o < b1; o += blockDim.x) {
+        switch (a.op) {
+            case 0: a.x64[o] = (double)a.src_t[o]; break;
+            case 1: a.x64[o] += (double)a.src_t[o]; break;
+            case 2: a.dst_t[o] = (T)a.x64[o]; break;
+            case 3: a.dst_t[o] = a.src_t[o]; break;
+            case 4: a.x64[o] = (double)a.X[dy.cur][o]; break;
+            case 5: a.X[2][o] = a.X[dy.cur][o]; break;
+            default: a.X[1 - dy.cur][o] = a.X[2][o]; break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Anderson acceleration
+
+// G^(k) = X' and F^(k) = X' - X^k into the ring slot of the newest entry.
+template <typename T>
+__global__ void k_aa_push(AaArgs<T> a) {
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const PairDyn dy = a.dyn[td.x];
+    if (!(dy.flags & PF_SOLVE)) return;
+    const size_t n12 = 12 * (size_t)a.ntot;
+    T* G = a.G + (size_t)dy.aa_slot[0] * n12;
+    T* F = a.F + (size_t)dy.aa_slot[0] * n12;
+    const T* Xc = a.X[dy.cur];
+    const size_t b0 = 12 * (size_t)td.y, b1 = 12 * (size_t)td.z;
+    for (size_t o = b0 + threadIdx.x; o < b1; o += blockDim.x) {
+        const double g = a.xnew[o];
+        G[o] = (T)g;
+        F[o] = (T)(g - (double)Xc[o]);
+        a.X[2][o] = (T)g;
+    }
+}
+
+// Tile partials of the Gram matrix dF^T dF and of dF^T F^(k) in float64,
+// dF_a = F^(k-a+1) - F^(k-a), a = 1..m_k.
+template <typename T>
+__global__ void __launch_bounds__(256) k_aa_gram(AaArgs<T> a) {
+    __shared__ double sdf[AMM_MAX_AA_M + 1][12 * 32];
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const PairDyn dy = a.dyn[td.x];
+    if (!(dy.flags & PF_SOLVE)) return;
+    const int mk = dy.aa_mk;
+    const int ng = mk * (mk + 1) / 2 + mk;
+    const size_t n12 = 12 * (size_t)a.ntot;
+    double acc = 0;
+    // entry index -> (a, b) of the Gram or the right-hand side
+    int ea = 0, eb = 0;
+    bool is_rhs = false;
+    {
+        int t = threadIdx.x, cnt = 0;
+        if (t < ng) {
+            for (int x = 0; x < mk; ++x)
+                for (int y = 0; y <= x; ++y) {
+                    if (cnt == t) {
+                        ea = x;
+                        eb = y;
+                    }
+                    ++cnt;
+                }
+            if (t >= cnt) {
+                is_rhs = true;
+                ea = t - cnt;
+            }
+        }
+    }
+    const size_t b0 = 12 * (size_t)td.y, b1 = 12 * (size_t)td.z;
+    for (size_t base = b0; base < b1; base += 12 * 32) {
+        const int cnt = (int)min((size_t)(12 * 32), b1 - base);
+        for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+            const size_t o = base + q;
+            const double f0 = (double)a.F[(size_t)dy.aa_slot[0] * n12 + o];
+            sdf[mk][q] = f0;
+            for (int x = 0; x < mk; ++x) {
+                const double fa = (double)a.F[(size_t)dy.aa_slot[x] * n12 + o];
+                const double fb = (double)a.F[(size_t)dy.aa_slot[x + 1] * n12 + o];
+                sdf[x][q] = fa - fb;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < ng) {
+            const double* va = sdf[ea];
+            const double* vb = is_rhs ? sdf[mk] : sdf[eb];
+            for (int q = 0; q < cnt; ++q) acc += va[q] * vb[q];
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < ng) a.part[(size_t)tile * kAaParts + threadIdx.x] = acc;
+}
+
+// Per pair: Gram matrix from the tile partials, Cholesky in float64; a
+// pivot <= 1e-14 * max diag falls back to theta = 0 (plain MM step).
+__global__ void k_aa_solve(AaSolveArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_SOLVE)) return;
+    PairOut& out = a.out[p];
+    const int mk = dy.aa_mk;
+    for (int x = 0; x < AMM_MAX_AA_M; ++x) out.theta[x] = 0;
+    out.aa_used = 0;
+    if (mk == 0) return;
+    const PairInfo pi = a.info[p];
+    const int ng = mk * (mk + 1) / 2 + mk;
+    double v[kAaParts];
+    for (int g = 0; g < ng; ++g) {
+        double s = 0;
+        for (int t = 0; t < pi.nd_ntile; ++t) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
+        v[g] = s;
+    }
+    double G[AMM_MAX_AA_M][AMM_MAX_AA_M], rhs[AMM_MAX_AA_M], L[AMM_MAX_AA_M][AMM_MAX_AA_M];
+    int cnt = 0;
+    for (int x = 0; x < mk; ++x)
+        for (int y = 0; y <= x; ++y) {
+            G[x][y] = G[y][x] = v[cnt];
+            ++cnt;
+        }
+    for (int x = 0; x < mk; ++x) rhs[x] = v[cnt + x];
+    double dmax = 0;
+    for (int x = 0; x < mk; ++x) dmax = fmax(dmax, G[x][x]);
+    const double tol = 1e-14 * dmax;
+    for (int jj = 0; jj < mk; ++jj) {
+        double piv = G[jj][jj];
+        for (int q = 0; q < jj; ++q) piv -= L[jj][q] * L[jj][q];
+        if (!(piv > tol)) return;
+        L[jj][jj] = sqrt(piv);
+        for (int ii = jj + 1; ii < mk; ++ii) {
+            double s = G[ii][jj];
+            for (int q = 0; q < jj; ++q) s -= L[ii][q] * L[jj][q];
+            L[ii][jj] = s / L[jj][jj];
+        }
+    }
+    double y[AMM_MAX_AA_M], th[AMM_MAX_AA_M];
+    for (int ii = 0; ii < mk; ++ii) {
+        double s = rhs[ii];
+        for (int q = 0; q < ii; ++q) s -= L[ii][q] * y[q];
+        y[ii] = s / L[ii][ii];
+    }
+    for (int ii = mk - 1; ii >= 0; --ii) {
+        double s = y[ii];
+        for (int q = ii + 1; q < mk; ++q) s -= L[q][ii] * th[q];
+        th[ii] = s / L[ii][ii];
+    }
+    for (int x = 0; x < mk; ++x) out.theta[x] = th[x];
+    out.aa_used = 1;
+}
+
+// X_AA = G^(k) - sum_a theta_a (G^(k-a+1) - G^(k-a)) (Eq. 17) into the
+// candidate transform set; equals G^(k) when Anderson is not used.
+template <typename T>
+__global__ void k_aa_mix(AaArgs<T> a) {
+    const int tile = blockIdx.x;
+    const int4 td = a.nd_tiles[tile];
+    const int p = td.x;
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_SOLVE)) return;
+    const PairOut& out = a.out[p];
+    const bool used = out.aa_used != 0;
+    const int mk = dy.aa_mk;
+    const size_t n12 = 12 * (size_t)a.ntot;
+    T* Xc = a.X[1 - dy.cur];
+    const size_t b0 = 12 * (size_t)td.y, b1 = 12 * (size_t)td.z;
+    for (size_t o = b0 + threadIdx.x; o < b1; o += blockDim.x) {
+        double g = (double)a.G[(size_t)dy.aa_slot[0] * n12 + o];
+        if (used) {
+            for (int x = 0; x < mk; ++x) {
+                const double ga = (double)a.G[(size_t)dy.aa_slot[x] * n12 + o];
+                const double gb = (double)a.G[(size_t)dy.aa_slot[x + 1] * n12 + o];
+                g -= out.theta[x] * (ga - gb);
+            }
+            Xc[o] = (T)g;
+        } else {
+            Xc[o] = a.X[2][o];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- gradient
+
+// Per point: g_i = dE/dv_hat_i = exp(-d^2/(2 nu_a^2)) (v_hat_i - u_rho(i)) / nu_a^2
+// and dE/dv_i = sum_j w_ij A_j^T g_i (graph frozen).
+template <typename T>
+__global__ void __launch_bounds__(kPointTile) k_grad_points(GradArgs<T> a) {
+    using V = typename V4Of<T>::type;
+    const int tile = blockIdx.x;
+    const int4 td = a.pt_tiles[tile];
+    const int p = td.x;
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_EVAL)) return;
+    const int i = td.y + (int)threadIdx.x;
+    if (i >= td.z) return;
+    const int set = dy.eval_dst;
+    const V vh = a.vhat[set][i];
+    const V u = a.tgt[a.rho[set][i]];
+    const T nu2 = (T)dy.nu_a * (T)dy.nu_a;
+    const T d2 = a.d2[set][i];
+    const T f = exp(-d2 / (T(2) * nu2)) / nu2;
+    V g;
+    g.x = f * (vh.x - u.x);
+    g.y = f * (vh.y - u.y);
+    g.z = f * (vh.z - u.z);
+    g.w = 0;
+    a.gpt[i] = g;
+    if (a.gV) {
+        const T* X = a.X;
+        T gx = 0, gy = 0, gz = 0;
+        for (int s = 0; s < a.k; ++s) {
+            const int j = a.iidx[(size_t)s * a.Ntot + i];
+            const T w = a.iw[(size_t)s * a.Ntot + i];
+            const T* Xj = X + 12 * (size_t)j;
+            // A^T g: row r of A^T is X_j row r
+            gx += w * (Xj[0] * g.x + Xj[1] * g.y + Xj[2] * g.z);
+            gy += w * (Xj[3] * g.x + Xj[4] * g.y + Xj[5] * g.z);
+            gz += w * (Xj[6] * g.x + Xj[7] * g.y + Xj[8] * g.z);
+        }
+        const int iu = a.src_user[i];
+        a.gV[3 * (size_t)iu + 0] = gx;
+        a.gV[3 * (size_t)iu + 1] = gy;
+        a.gV[3 * (size_t)iu + 2] = gz;
+    }
+}
+
+// Per node: dE/dX_j = sum_i w_ij [v_i - p_j; 1] g_i^T
+//   + alpha sum over D_lj of r [p_l - p_j; 1] h^T - alpha sum over D_jl of r e4 h^T
+//   + 2 beta [(A_j - R_j)^T; 0],   h = exp(-|D|^2/(2 nu_r^2)) D / nu_r^2.
+template <typename T>
+__global__ void __launch_bounds__(64) k_grad_nodes(GradArgs<T> a) {
+    using V = typename V4Of<T>::type;
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int p = a.node_pair[j];
+    const PairDyn dy = a.dyn[p];
+    if (!(dy.flags & PF_EVAL)) return;
+    const V pj = a.nodes[j];
+    const int src_set = dy.eval_dst;
+    const V* src = a.src_override ? (const V*)a.src_override : (const V*)a.src;
+    T acc[12];
+    for (int m = 0; m < 12; ++m) acc[m] = 0;
+    const int e0 = a.pj_ptr[j], e1 = a.pj_ptr[j + 1];
+    for (int e = e0 + lane; e < e1; e += 64) {
+        const int ent = a.pj_ent[e];
+        const int i = ent >> 3, s = ent & 7;
+        const T w = a.iw[(size_t)s * a.Ntot + i];
+        const V v = src[i];
+        const V g = a.gpt[i];
+        const T x4[4] = {v.x - pj.x, v.y - pj.y, v.z - pj.z, T(1)};
+        for (int r = 0; r < 4; ++r) {
+            acc[3 * r + 0] += w * x4[r] * g.x;
+            acc[3 * r + 1] += w * x4[r] * g.y;
+            acc[3 * r + 2] += w * x4[r] * g.z;
+        }
+    }
+    for (int m = 0; m < 12; ++m) acc[m] = wave_sum(acc[m]);
+    if (lane != 0) return;
+    const T nur2 = (T)dy.nu_r * (T)dy.nu_r;
+    const T alpha = (T)dy.alpha, beta = (T)dy.beta;
+    const V* Dr = a.Dres[src_set];
+    for (int e = a.adj_ptr[j]; e < a.adj_ptr[j + 1]; ++e) {
+        const int l = a.adj_nbr[e], rev = a.adj_rev[e];
+        const T rr = a.adj_r[e];
+        // D_lj (entry rev = l->j): transform of j applied at p_l
+        const V D1 = Dr[rev];
+        const T f1 = exp(-D1.w / (T(2) * nur2)) / nur2;
+        const V pl = a.nodes[l];
+        const T x4[4] = {pl.x - pj.x, pl.y - pj.y, pl.z - pj.z, T(1)};
+        for (int r = 0; r < 4; ++r) {
+            acc[3 * r + 0] += alpha * rr * x4[r] * f1 * D1.x;
+            acc[3 * r + 1] += alpha * rr * x4[r] * f1 * D1.y;
+            acc[3 * r + 2] += alpha * rr * x4[r] * f1 * D1.z;
+        }
+        // D_jl (entry e = j->l): t_j enters with -r
+        const V D2 = Dr[e];
+        const T f2 = exp(-D2.w / (T(2) * nur2)) / nur2;
+        acc[9] -= alpha * rr * f2 * D2.x;
+        acc[10] -= alpha * rr * f2 * D2.y;
+        acc[11] -= alpha * rr * f2 * D2.z;
+    }
+    const T* X = a.X + 12 * (size_t)j;
+    const T* Rj = a.R[src_set] + 9 * (size_t)j;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) acc[3 * r + c] += T(2) * beta * (X[3 * r + c] - Rj[3 * c + r]);
+    T* out = a.gX + 12 * (size_t)a.node_user[j];
+    for (int m = 0; m < 12; ++m) out[m] = acc[m];
+}
+
+// ---------------------------------------------------------------- layout conversion
+
+// X (user node order, type U) -> internal order (type T) and back.
+template <typename T, typename U>
+__global__ void k_x_import(const U* __restrict__ xu, T* __restrict__ xi, const int* __restrict__ node_user,
+                           int64_t ntot) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= 12 * ntot) return;
+    const int64_t j = o / 12, m = o % 12;
+    xi[o] = (T)xu[12 * (int64_t)node_user[j] + m];
+}
+
+template <typename T, typename U>
+__global__ void k_x_export(const T* __restrict__ xi, U* __restrict__ xu, const int* __restrict__ node_user,
+                           int64_t ntot) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= 12 * ntot) return;
+    const int64_t j = o / 12, m = o % 12;
+    xu[12 * (int64_t)node_user[j] + m] = (U)xi[o];
+}
+
+template <typename T, typename U>
+__global__ void k_src_import(const U* __restrict__ su, typename V4Of<T>::type* __restrict__ si,
+                             const int* __restrict__ src_user, int64_t Ntot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Ntot) return;
+    const int64_t u = src_user[i];
+    typename V4Of<T>::type v;
+    v.x = (T)su[3 * u];
+    v.y = (T)su[3 * u + 1];
+    v.z = (T)su[3 * u + 2];
+    v.w = 0;
+    si[i] = v;
+}
+
+template <typename T, typename U>
+__global__ void k_points_export(const typename V4Of<T>::type* __restrict__ vi, U* __restrict__ vu,
+                                const int* __restrict__ src_user, int64_t Ntot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Ntot) return;
+    const int64_t u = src_user[i];
+    const typename V4Of<T>::type v = vi[i];
+    vu[3 * u] = (U)v.x;
+    vu[3 * u + 1] = (U)v.y;
+    vu[3 * u + 2] = (U)v.z;
+}
+
+template <typename T, typename U>
+__global__ void k_nn_export(const int* __restrict__ rho, const T* __restrict__ d2, const int* __restrict__ src_user,
+                            const int* __restrict__ tgt_user, int32_t* __restrict__ rho_u, U* __restrict__ d2_u,
+                            int64_t Ntot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Ntot) return;
+    const int64_t u = src_user[i];
+    if (rho_u) rho_u[u] = tgt_user[rho[i]];
+    if (d2_u) d2_u[u] = (U)d2[i];
+}
+
+template <typename T>
+__global__ void k_cast_static(const double* __restrict__ in, T* __restrict__ out, int64_t n) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < n) out[o] = (T)in[o];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename T>
+void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_tiles, const FinalArgs& f,
+                 int P, hipStream_t s, KernelTimer* tm) {
+    if (n_pt_tiles) {
+        if (tm) tm->begin("eval_points", s);
+        hipLaunchKernelGGL(k_eval_points<T>, dim3(n_pt_tiles), dim3(kPointTile), 0, s, a);
+        if (tm) tm->end(s);
+    }
+    if (n_eg_tiles) {
+        if (tm) tm->begin("eval_edges", s);
+        hipLaunchKernelGGL(k_eval_edges<T>, dim3(n_eg_tiles), dim3(kEdgeTile), 0, s, a);
+        if (tm) tm->end(s);
+    }
+    if (n_nd_tiles) {
+        if (tm) tm->begin("eval_nodes", s);
+        hipLaunchKernelGGL(k_eval_nodes<T>, dim3(n_nd_tiles), dim3(kNodeTile), 0, s, a);
+        if (tm) tm->end(s);
+    }
+    if (tm) tm->begin("energy_final", s);
+    hipLaunchKernelGGL(k_energy_final, dim3(P), dim3(64), 0, s, f);
+    if (tm) tm->end(s);
+}
+
+template <typename T>
+void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTimer* tm) {
+    if (tm) tm->begin("assemble", s);
+    hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)ntot), dim3(64), 0, s, a);
+    if (tm) tm->end(s);
+}
+
+template <typename T>
+void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, int zero_x, hipStream_t s, KernelTimer* tm) {
+    if (tm) tm->begin("cg_init", s);
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, zero_x);
+    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, -1);
+    if (tm) tm->end(s);
+}
+
+template <typename T>
+void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm) {
+    if (tm) tm->begin("cg_update", s);
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, it);
+    if (tm) tm->end(s);
+    if (tm) tm->begin("cg_spmv", s);
+    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, it);
+    if (tm) tm->end(s);
+}
+
+template <typename T>
+void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const double* x64, T* rhs_out,
+                       double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm) {
+    if (tm) tm->begin("residual64", s);
+    hipLaunchKernelGGL(k_residual64<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, B, x64, rhs_out, part_rr,
+                       part_bb);
+    if (tm) tm->end(s);
+}
+
+template <typename T>
+void launch_node_vec_op(const NodeVecArgs<T>& a, int n_nd_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_node_vec_op<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
+}
+
+template <typename T>
+void launch_aa(const AaArgs<T>& a, const AaSolveArgs& sa, int n_nd_tiles, hipStream_t s, KernelTimer* tm) {
+    if (tm) tm->begin("anderson", s);
+    hipLaunchKernelGGL(k_aa_push<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_aa_gram<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_aa_solve, dim3(blocks_for(sa.P, 64)), dim3(64), 0, s, sa);
+    hipLaunchKernelGGL(k_aa_mix<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
+    if (tm) tm->end(s);
+}
+
+template <typename T>
+void launch_grad(const GradArgs<T>& a, int n_pt_tiles, int64_t ntot, hipStream_t s) {
+    hipLaunchKernelGGL(k_grad_points<T>, dim3(n_pt_tiles), dim3(kPointTile), 0, s, a);
+    hipLaunchKernelGGL(k_grad_nodes<T>, dim3((unsigned)ntot), dim3(64), 0, s, a);
+}
+
+template <typename T, typename U>
+void launch_x_import(const U* xu, T* xi, const int* node_user, int64_t ntot, hipStream_t s) {
+    if (ntot) hipLaunchKernelGGL((k_x_import<T, U>), dim3(blocks_for(12 * ntot, 256)), dim3(256), 0, s, xu, xi, node_user, ntot);
+}
+template <typename T, typename U>
+void launch_x_export(const T* xi, U* xu, const int* node_user, int64_t ntot, hipStream_t s) {
+    if (ntot) hipLaunchKernelGGL((k_x_export<T, U>), dim3(blocks_for(12 * ntot, 256)), dim3(256), 0, s, xi, xu, node_user, ntot);
+}
+template <typename T, typename U>
+void launch_src_import(const U* su, void* si, const int* src_user, int64_t Ntot, hipStream_t s) {
+    hipLaunchKernelGGL((k_src_import<T, U>), dim3(blocks_for(Ntot, 256)), dim3(256), 0, s, su,
+                       (typename V4Of<T>::type*)si, src_user, Ntot);
+}
+template <typename T, typename U>
+void launch_points_export(const void* vi, U* vu, const int* src_user, int64_t Ntot, hipStream_t s) {
+    hipLaunchKernelGGL((k_points_export<T, U>), dim3(blocks_for(Ntot, 256)), dim3(256), 0, s,
+                       (const typename V4Of<T>::type*)vi, vu, src_user, Ntot);
+}
+template <typename T, typename U>
+void launch_nn_export(const int* rho, const T* d2, const int* src_user, const int* tgt_user, int32_t* rho_u,
+                      U* d2_u, int64_t Ntot, hipStream_t s) {
+    hipLaunchKernelGGL((k_nn_export<T, U>), dim3(blocks_for(Ntot, 256)), dim3(256), 0, s, rho, d2, src_user,
+                       tgt_user, rho_u, d2_u, Ntot);
+}
+template <typename T>
+void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_cast_static<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+}
+
+#define AMM_INSTANTIATE(T)                                                                                     \
+    template void launch_eval<T>(const EvalArgs<T>&, int, int, int, const FinalArgs&, int, hipStream_t,        \
+                                 KernelTimer*);                                                               \
+    template void launch_assemble<T>(const AsmArgs<T>&, int64_t, hipStream_t, KernelTimer*);                   \
+    template void launch_cg_init<T>(const CgArgs<T>&, int, int, hipStream_t, KernelTimer*);                    \
+    template void launch_cg_iter<T>(const CgArgs<T>&, int, int, hipStream_t, KernelTimer*);                    \
+    template void launch_residual64<T>(const CgArgs<T>&, int, const T*, const double*, T*, double*, double*,    \
+                                       hipStream_t, KernelTimer*);                                            \
+    template void launch_node_vec_op<T>(const NodeVecArgs<T>&, int, hipStream_t);                             \
+    template void launch_aa<T>(const AaArgs<T>&, const AaSolveArgs&, int, hipStream_t, KernelTimer*);          \
+    template void launch_grad<T>(const GradArgs<T>&, int, int64_t, hipStream_t);                              \
+    template void launch_cast_static<T>(const double*, T*, int64_t, hipStream_t);                              \
+    template void launch_x_import<T, float>(const float*, T*, const int*, int64_t, hipStream_t);              \
+    template void launch_x_import<T, double>(const double*, T*, const int*, int64_t, hipStream_t);            \
+    template void launch_x_export<T, float>(const T*, float*, const int*, int64_t, hipStream_t);              \
+    template void launch_x_export<T, double>(const T*, double*, const int*, int64_t, hipStream_t);            \
+    template void launch_src_import<T, float>(const float*, void*, const int*, int64_t, hipStream_t);         \
+    template void launch_src_import<T, double>(const double*, void*, const int*, int64_t, hipStream_t);       \
+    template void launch_points_export<T, float>(const void*, float*, const int*, int64_t, hipStream_t);      \
+    template void launch_points_export<T, double>(const void*, double*, const int*, int64_t, hipStream_t);    \
+    template void launch_nn_export<T, float>(const int*, const T*, const int*, const int*, int32_t*, float*,    \
+                                             int64_t, hipStream_t);                                           \
+    template void launch_nn_export<T, double>(const int*, const T*, const int*, const int*, int32_t*, double*,  \
+                                              int64_t, hipStream_t);
+
+AMM_INSTANTIATE(float)
+AMM_INSTANTIATE(double)
+
+}  // namespace amm

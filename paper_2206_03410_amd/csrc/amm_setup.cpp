@@ -1,0 +1,435 @@
+// Host-side validation of registration problems and construction of the
+// device layout: spatial (Morton) ordering of points, nodes and targets, the
+// bounding-box tree over each target set, the node adjacency with the edge
+// weights of Eq. (8), the block pattern of K (Eq. 16) and the per-node lists
+// of influenced points used by the row-wise assembly.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <limits>
+#include <numeric>
+
+#include "amm_internal.h"
+
+namespace amm {
+
+namespace {
+
+std::string fmt(const char* f, long long a = 0, long long b = 0) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, f, a, b);
+    return buf;
+}
+
+uint32_t spread10(uint32_t x) {
+    x &= 0x3ff;
+    x = (x | (x << 16)) & 0x030000ff;
+    x = (x | (x << 8)) & 0x0300f00f;
+    x = (x | (x << 4)) & 0x030c30c3;
+    x = (x | (x << 2)) & 0x09249249;
+    return x;
+}
+
+struct Box {
+    double lo[3], hi[3];
+};
+
+uint32_t morton(const double* p, const Box& b) {
+    uint32_t q[3];
+    for (int c = 0; c < 3; ++c) {
+        double ext = b.hi[c] - b.lo[c];
+        double t = ext > 0 ? (p[c] - b.lo[c]) / ext : 0.0;
+        int v = (int)std::floor(t * 1023.999);
+        q[c] = (uint32_t)std::min(1023, std::max(0, v));
+    }
+    return (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+}
+
+std::vector<int32_t> morton_order(const double* pts, int64_t cnt, const Box& b) {
+    std::vector<uint32_t> code(cnt);
+    for (int64_t i = 0; i < cnt; ++i) code[i] = morton(pts + 3 * i, b);
+    std::vector<int32_t> ord(cnt);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int32_t a, int32_t c) { return code[a] < code[c]; });
+    return ord;
+}
+
+bool finite_all(const std::vector<double>& v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+}  // namespace
+
+amm_status validate_pair(const HostPair& hp, std::string& err) {
+    if (hp.N < 1 || hp.M < 1 || hp.n < 1) {
+        err = "n_src, n_tgt and n_nodes must be >= 1";
+        return AMM_ERR_INVALID_ARG;
+    }
+    if (hp.M >= (1LL << 24) || hp.N >= (1LL << 28)) {
+        err = "point count too large";
+        return AMM_ERR_INVALID_ARG;
+    }
+    if (hp.k < 1 || hp.k > kMaxK || hp.k > hp.n) {
+        err = fmt("k = %lld must satisfy 1 <= k <= min(8, n_nodes)", hp.k);
+        return AMM_ERR_INVALID_ARG;
+    }
+    if (hp.E < 0) {
+        err = "n_edges < 0";
+        return AMM_ERR_INVALID_ARG;
+    }
+    if (!finite_all(hp.src) || !finite_all(hp.tgt) || !finite_all(hp.infl_w) ||
+        !finite_all(hp.src_nrm) || !finite_all(hp.tgt_nrm)) {
+        err = "non-finite value in the point sets, normals or weights";
+        return AMM_ERR_NONFINITE;
+    }
+    if (!(hp.lbar > 0) || !std::isfinite(hp.lbar)) {
+        err = "mean_edge_len must be finite and > 0";
+        return AMM_ERR_INVALID_ARG;
+    }
+    std::vector<char> seen(hp.N, 0);
+    for (int64_t j = 0; j < hp.n; ++j) {
+        int32_t s = hp.node_idx[j];
+        if (s < 0 || s >= hp.N) {
+            err = fmt("node_src_idx[%lld] = %lld out of range", j, s);
+            return AMM_ERR_INVALID_ARG;
+        }
+        if (seen[s]) {
+            err = fmt("node_src_idx has the source point %lld twice", s);
+            return AMM_ERR_GRAPH;
+        }
+        seen[s] = 1;
+    }
+    for (int64_t i = 0; i < hp.N; ++i) {
+        double sum = 0.0;
+        for (int a = 0; a < hp.k; ++a) {
+            int32_t j = hp.infl_idx[i * hp.k + a];
+            if (j < 0 || j >= hp.n) {
+                err = fmt("infl_idx of point %lld out of range (%lld)", i, j);
+                return AMM_ERR_INVALID_ARG;
+            }
+            for (int b = 0; b < a; ++b)
+                if (hp.infl_idx[i * hp.k + b] == j) {
+                    err = fmt("point %lld lists node %lld twice", i, j);
+                    return AMM_ERR_GRAPH;
+                }
+            double w = hp.infl_w[i * hp.k + a];
+            if (w < 0) {
+                err = fmt("negative influence weight at point %lld", i);
+                return AMM_ERR_GRAPH;
+            }
+            sum += w;
+        }
+        if (std::fabs(sum - 1.0) > 1e-5) {
+            err = fmt("influence weights of point %lld do not sum to 1", i);
+            return AMM_ERR_GRAPH;
+        }
+    }
+    std::vector<std::vector<int32_t>> nb(hp.n);
+    for (int64_t e = 0; e < hp.E; ++e) {
+        int32_t a = hp.edges[2 * e], b = hp.edges[2 * e + 1];
+        if (a < 0 || a >= hp.n || b < 0 || b >= hp.n) {
+            err = fmt("edge %lld has a node out of range", e);
+            return AMM_ERR_INVALID_ARG;
+        }
+        if (a == b) {
+            err = fmt("edge %lld is a self loop", e);
+            return AMM_ERR_GRAPH;
+        }
+        nb[a].push_back(b);
+        nb[b].push_back(a);
+    }
+    for (auto& v : nb) {
+        std::sort(v.begin(), v.end());
+        if (std::adjacent_find(v.begin(), v.end()) != v.end()) {
+            err = "duplicate node edge";
+            return AMM_ERR_GRAPH;
+        }
+    }
+    // connectivity (a disconnected graph leaves a free translation when a
+    // component's alignment weights all vanish, so K can be singular)
+    std::vector<char> vis(hp.n, 0);
+    std::vector<int32_t> stack{0};
+    vis[0] = 1;
+    int64_t cnt = 1;
+    while (!stack.empty()) {
+        int32_t a = stack.back();
+        stack.pop_back();
+        for (int32_t b : nb[a])
+            if (!vis[b]) {
+                vis[b] = 1;
+                ++cnt;
+                stack.push_back(b);
+            }
+    }
+    if (cnt != hp.n) {
+        err = fmt("node graph is disconnected (%lld of %lld nodes reachable)", cnt, hp.n);
+        return AMM_ERR_GRAPH;
+    }
+    return AMM_OK;
+}
+
+amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
+                        std::string& err) {
+    L = Layout();
+    L.P = (int)pairs.size();
+    L.k = pairs.empty() ? 0 : pairs[0].k;
+    for (const auto& hp : pairs) {
+        if (hp.k != L.k) {
+            err = "all pairs of a batch must have the same k";
+            return AMM_ERR_INVALID_ARG;
+        }
+        L.Ntot += hp.N;
+        L.Mtot += hp.M;
+        L.ntot += hp.n;
+        L.nadj += 2 * hp.E;
+    }
+    const int k = L.k;
+    L.src4.assign(4 * L.Ntot, 0.0);
+    L.src_user.resize(L.Ntot);
+    L.src_internal.resize(L.Ntot);
+    L.iidx.resize((size_t)k * L.Ntot);
+    L.iw.resize((size_t)k * L.Ntot);
+    L.nodes4.assign(4 * L.ntot, 0.0);
+    L.node_user.resize(L.ntot);
+    L.node_internal.resize(L.ntot);
+    L.node_pair.resize(L.ntot);
+    L.adj_ptr.assign(L.ntot + 1, 0);
+    L.adj_nbr.resize(L.nadj);
+    L.adj_row.resize(L.nadj);
+    L.adj_rev.resize(L.nadj);
+    L.adj_r.resize(L.nadj);
+    L.K_ptr.assign(L.ntot + 1, 0);
+    L.K_diag.resize(L.ntot);
+    L.pj_ptr.assign(L.ntot + 1, 0);
+    L.tgt4.assign(4 * L.Mtot, 0.0);
+    L.tgt_user.resize(L.Mtot);
+
+    int64_t so = 0, to = 0, no = 0, ao = 0, tree = 0;
+    for (int p = 0; p < L.P; ++p) {
+        const HostPair& hp = pairs[p];
+        PairInfo pi{};
+        pi.src_off = so;
+        pi.N = hp.N;
+        pi.tgt_off = to;
+        pi.M = hp.M;
+        pi.node_off = no;
+        pi.n = hp.n;
+        pi.adj_off = ao;
+        pi.nadj = 2 * hp.E;
+        pi.n_undirected = (int32_t)hp.E;
+
+        Box bb;
+        for (int c = 0; c < 3; ++c) {
+            bb.lo[c] = std::numeric_limits<double>::infinity();
+            bb.hi[c] = -bb.lo[c];
+        }
+        for (int64_t i = 0; i < hp.N; ++i)
+            for (int c = 0; c < 3; ++c) {
+                bb.lo[c] = std::min(bb.lo[c], hp.src[3 * i + c]);
+                bb.hi[c] = std::max(bb.hi[c], hp.src[3 * i + c]);
+            }
+        for (int64_t i = 0; i < hp.M; ++i)
+            for (int c = 0; c < 3; ++c) {
+                bb.lo[c] = std::min(bb.lo[c], hp.tgt[3 * i + c]);
+                bb.hi[c] = std::max(bb.hi[c], hp.tgt[3 * i + c]);
+            }
+
+        // source points in Morton order
+        std::vector<int32_t> sord = morton_order(hp.src.data(), hp.N, bb);
+        std::vector<int32_t> s_inv(hp.N);
+        for (int64_t q = 0; q < hp.N; ++q) s_inv[sord[q]] = (int32_t)q;
+        // nodes in Morton order of their positions
+        std::vector<double> npos(3 * hp.n);
+        for (int64_t j = 0; j < hp.n; ++j)
+            for (int c = 0; c < 3; ++c) npos[3 * j + c] = hp.src[3 * hp.node_idx[j] + c];
+        std::vector<int32_t> nord = morton_order(npos.data(), hp.n, bb);
+        std::vector<int32_t> n_inv(hp.n);
+        for (int64_t q = 0; q < hp.n; ++q) n_inv[nord[q]] = (int32_t)q;
+
+        for (int64_t q = 0; q < hp.N; ++q) {
+            int64_t u = sord[q];
+            for (int c = 0; c < 3; ++c) L.src4[4 * (so + q) + c] = hp.src[3 * u + c];
+            L.src_user[so + q] = (int32_t)(so + u);
+            L.src_internal[so + u] = (int32_t)(so + q);
+            for (int a = 0; a < k; ++a) {
+                L.iidx[(size_t)a * L.Ntot + so + q] = (int32_t)(no + n_inv[hp.infl_idx[u * k + a]]);
+                L.iw[(size_t)a * L.Ntot + so + q] = hp.infl_w[u * k + a];
+            }
+        }
+        for (int64_t q = 0; q < hp.n; ++q) {
+            int64_t u = nord[q];
+            for (int c = 0; c < 3; ++c) L.nodes4[4 * (no + q) + c] = npos[3 * u + c];
+            L.node_user[no + q] = (int32_t)(no + u);
+            L.node_internal[no + u] = (int32_t)(no + q);
+            L.node_pair[no + q] = p;
+        }
+
+        // adjacency (directed), r_ij of Eq. (8)
+        std::vector<std::vector<int32_t>> nb(hp.n);
+        for (int64_t e = 0; e < hp.E; ++e) {
+            int32_t a = n_inv[hp.edges[2 * e]], b = n_inv[hp.edges[2 * e + 1]];
+            nb[a].push_back(b);
+            nb[b].push_back(a);
+        }
+        long double inv_sum = 0.0L;
+        for (int64_t e = 0; e < hp.E; ++e) {
+            const double* pa = &npos[3 * hp.edges[2 * e]];
+            const double* pb = &npos[3 * hp.edges[2 * e + 1]];
+            double d = std::sqrt((pa[0] - pb[0]) * (pa[0] - pb[0]) +
+                                 (pa[1] - pb[1]) * (pa[1] - pb[1]) +
+                                 (pa[2] - pb[2]) * (pa[2] - pb[2]));
+            if (!(d > 0)) {
+                err = "node edge of zero length";
+                return AMM_ERR_GRAPH;
+            }
+            inv_sum += 1.0L / d;
+        }
+        int64_t a0 = ao;
+        for (int64_t q = 0; q < hp.n; ++q) {
+            std::sort(nb[q].begin(), nb[q].end());
+            L.adj_ptr[no + q] = (int32_t)ao;
+            for (int32_t b : nb[q]) {
+                L.adj_nbr[ao] = (int32_t)(no + b);
+                L.adj_row[ao] = (int32_t)(no + q);
+                const double* pa = &L.nodes4[4 * (no + q)];
+                const double* pb = &L.nodes4[4 * (no + b)];
+                double d = std::sqrt((pa[0] - pb[0]) * (pa[0] - pb[0]) +
+                                     (pa[1] - pb[1]) * (pa[1] - pb[1]) +
+                                     (pa[2] - pb[2]) * (pa[2] - pb[2]));
+                // 2|E| d^-1 / (sum over ordered pairs of d^-1) = |E| d^-1 / sum over edges
+                L.adj_r[ao] = (double)((long double)hp.E / (long double)d / inv_sum);
+                ++ao;
+            }
+        }
+        for (int64_t e = a0; e < ao; ++e) {
+            int32_t a = L.adj_row[e], b = L.adj_nbr[e];
+            auto beg = L.adj_nbr.begin() + L.adj_ptr[b];
+            auto end = beg + (int64_t)nb[b - no].size();
+            auto it = std::lower_bound(beg, end, a);
+            L.adj_rev[e] = (int32_t)(L.adj_ptr[b] + (it - beg));
+        }
+
+        // block pattern of K: co-influence pairs, edges, diagonal
+        std::vector<std::vector<int32_t>> cols(hp.n);
+        for (int64_t q = 0; q < hp.n; ++q) cols[q].push_back((int32_t)(no + q));
+        for (int64_t q = 0; q < hp.N; ++q)
+            for (int a = 0; a < k; ++a) {
+                int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
+                for (int b = 0; b < k; ++b)
+                    cols[ja].push_back(L.iidx[(size_t)b * L.Ntot + so + q]);
+            }
+        for (int64_t q = 0; q < hp.n; ++q)
+            for (int32_t b : nb[q]) cols[q].push_back((int32_t)(no + b));
+        for (int64_t q = 0; q < hp.n; ++q) {
+            auto& c = cols[q];
+            std::sort(c.begin(), c.end());
+            c.erase(std::unique(c.begin(), c.end()), c.end());
+            if ((int)c.size() > kMaxCols) {
+                err = fmt("a node is coupled to %lld others (limit %lld)", (long long)c.size(),
+                          kMaxCols);
+                return AMM_ERR_INVALID_ARG;
+            }
+            L.max_row_cols = std::max(L.max_row_cols, (int)c.size());
+            L.K_ptr[no + q] = (int32_t)L.K_col.size();
+            for (size_t t = 0; t < c.size(); ++t) {
+                int32_t col = c[t];
+                if (col == no + q) L.K_diag[no + q] = (int32_t)L.K_col.size();
+                int32_t adj = -1;
+                if (col != no + q) {
+                    auto beg = L.adj_nbr.begin() + L.adj_ptr[no + q];
+                    auto end = beg + (int64_t)nb[q].size();
+                    auto it = std::lower_bound(beg, end, col);
+                    if (it != end && *it == col) adj = (int32_t)(it - L.adj_nbr.begin());
+                }
+                L.K_col.push_back(col);
+                L.K_adj.push_back(adj);
+            }
+        }
+        // points influenced by each node
+        std::vector<std::vector<int32_t>> pj(hp.n);
+        for (int64_t q = 0; q < hp.N; ++q)
+            for (int a = 0; a < k; ++a) {
+                int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
+                pj[ja].push_back((int32_t)(((so + q) << 3) | a));
+            }
+        for (int64_t q = 0; q < hp.n; ++q) {
+            L.pj_ptr[no + q] = (int32_t)L.pj_ent.size();
+            L.pj_ent.insert(L.pj_ent.end(), pj[q].begin(), pj[q].end());
+        }
+
+        // targets: Morton order, implicit complete tree of `leaf`-sized buckets
+        std::vector<int32_t> tord = morton_order(hp.tgt.data(), hp.M, bb);
+        for (int64_t q = 0; q < hp.M; ++q) {
+            int64_t u = tord[q];
+            for (int c = 0; c < 3; ++c) L.tgt4[4 * (to + q) + c] = hp.tgt[3 * u + c];
+            L.tgt4[4 * (to + q) + 3] = (double)u;
+            L.tgt_user[to + q] = (int32_t)u;
+        }
+        int64_t nleaf = (hp.M + leaf - 1) / leaf;
+        int64_t Lp = 1;
+        while (Lp < nleaf) Lp <<= 1;
+        pi.tree_off = tree;
+        pi.L = (int32_t)Lp;
+        pi.leaf = leaf;
+        const double INF = std::numeric_limits<double>::infinity();
+        L.box_lo.resize(4 * (tree + 2 * Lp), INF);
+        L.box_hi.resize(4 * (tree + 2 * Lp), -INF);
+        for (int64_t q = 0; q < Lp; ++q) {
+            int64_t b = tree + Lp + q;
+            for (int64_t t = q * leaf; t < std::min<int64_t>((q + 1) * leaf, hp.M); ++t)
+                for (int c = 0; c < 3; ++c) {
+                    double v = L.tgt4[4 * (to + t) + c];
+                    L.box_lo[4 * b + c] = std::min(L.box_lo[4 * b + c], v);
+                    L.box_hi[4 * b + c] = std::max(L.box_hi[4 * b + c], v);
+                }
+        }
+        for (int64_t q = Lp - 1; q >= 1; --q) {
+            int64_t b = tree + q, c0 = tree + 2 * q, c1 = c0 + 1;
+            for (int c = 0; c < 3; ++c) {
+                L.box_lo[4 * b + c] = std::min(L.box_lo[4 * c0 + c], L.box_lo[4 * c1 + c]);
+                L.box_hi[4 * b + c] = std::max(L.box_hi[4 * c0 + c], L.box_hi[4 * c1 + c]);
+            }
+        }
+        tree += 2 * Lp;
+
+        // tiles
+        pi.pt_tile0 = L.n_pt_tiles;
+        for (int64_t s = 0; s < hp.N; s += kPointTile) {
+            L.pt_tiles.insert(L.pt_tiles.end(),
+                              {p, (int32_t)(so + s), (int32_t)(so + std::min<int64_t>(s + kPointTile, hp.N)), 0});
+            ++L.n_pt_tiles;
+        }
+        pi.pt_ntile = L.n_pt_tiles - pi.pt_tile0;
+        pi.nd_tile0 = L.n_nd_tiles;
+        for (int64_t s = 0; s < hp.n; s += kNodeTile) {
+            L.nd_tiles.insert(L.nd_tiles.end(),
+                              {p, (int32_t)(no + s), (int32_t)(no + std::min<int64_t>(s + kNodeTile, hp.n)), 0});
+            ++L.n_nd_tiles;
+        }
+        pi.nd_ntile = L.n_nd_tiles - pi.nd_tile0;
+        pi.eg_tile0 = L.n_eg_tiles;
+        for (int64_t s = 0; s < 2 * hp.E; s += kEdgeTile) {
+            L.eg_tiles.insert(L.eg_tiles.end(),
+                              {p, (int32_t)(a0 + s), (int32_t)(a0 + std::min<int64_t>(s + kEdgeTile, 2 * hp.E)), 0});
+            ++L.n_eg_tiles;
+        }
+        pi.eg_ntile = L.n_eg_tiles - pi.eg_tile0;
+
+        L.info.push_back(pi);
+        so += hp.N;
+        to += hp.M;
+        no += hp.n;
+    }
+    L.adj_ptr[L.ntot] = (int32_t)ao;
+    L.K_ptr[L.ntot] = (int32_t)L.K_col.size();
+    L.pj_ptr[L.ntot] = (int32_t)L.pj_ent.size();
+    L.nnzb = (int64_t)L.K_col.size();
+    L.tree_nodes = tree;
+    L.pj_entries = (int64_t)L.pj_ent.size();
+    return AMM_OK;
+}
+
+}  // namespace amm

@@ -1,0 +1,276 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Sizes here finish in the oracle within seconds and still span several
+tiles with ragged tails (points: tiles of 256; nodes: tiles of 64).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import amm_oracle as O
+from paper_2206_03410_amd import amm, synth
+from tests.helpers import Session, margin_ok, rounded
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _announce(name):
+    print(f"[gpu-test] {name}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pair():
+    # 1100 points = 4 full point tiles + a ragged one; 70 nodes = 1 full node tile + 6
+    return synth.torus_pair(1000, n_src=1100, n_tgt=1100, n_nodes=70, k=4, e=6)
+
+
+def _scalars(prob):
+    ev0 = O.evaluate(prob, O.identity(prob.n_nodes), 1, 1, 0, 0)
+    nu_a, nu_min, nu_r = O.initial_nu(prob, O.Params(), ev0.d2)
+    alpha, beta = O.term_weights(prob, O.Params(), nu_a, nu_r)
+    return nu_a, nu_r, alpha, beta
+
+
+def _K_dense(nnzb_blocks, rows, cols, n):
+    K = np.zeros((4 * n, 4 * n))
+    for b, r, c in zip(nnzb_blocks, rows, cols):
+        K[4 * r:4 * r + 4, 4 * c:4 * c + 4] = b
+    return K
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_step_parity(pair, prec):
+    """One teacher-forced MM step: closest points, energy, K, B, and the
+    surrogate minimizer, against the oracle at the same inputs."""
+    _announce(f"test_step_parity {prec}")
+    np_dt = np.float64 if prec == "f64" else np.float32
+    t_dt = torch.float64 if prec == "f64" else torch.float32
+    pr = rounded(pair, np_dt)
+    prob = O.from_pair(pr)
+    nu_a, nu_r, alpha, beta = _scalars(prob)
+    X = synth.perturbed_transforms(prob.n_nodes, 5, 0.01, 0.001).astype(np_dt).astype(np.float64)
+    with Session(pr, t_dt) as s:
+        n, N = prob.n_nodes, prob.n_src
+        nnzb = amm.amm_k_nnzb(s.h)
+        dev = "cuda:0"
+        Xt = torch.tensor(X, dtype=t_dt, device=dev)
+        rho = torch.empty(N, dtype=torch.int32, device=dev)
+        d2 = torch.empty(N, dtype=t_dt, device=dev)
+        vh = torch.empty(N, 3, dtype=t_dt, device=dev)
+        Xn = torch.empty(n, 4, 3, dtype=t_dt, device=dev)
+        Kb = torch.empty(nnzb, 4, 4, dtype=t_dt, device=dev)
+        Kr = torch.empty(nnzb, dtype=torch.int32, device=dev)
+        Kc = torch.empty(nnzb, dtype=torch.int32, device=dev)
+        B = torch.empty(n, 4, 3, dtype=t_dt, device=dev)
+        out = amm.amm_step(s.h, Xt, nu_a, nu_r, alpha, beta,
+                           amm.AMM_FP64_PLAIN if prec == "f64" else amm.AMM_FP32_REFINE,
+                           rho=rho, d2=d2, v_hat=vh, X_next=Xn, K_blocks=Kb, K_row=Kr, K_col=Kc, B=B)
+        torch.cuda.synchronize()
+        rho, d2, vh, Xn = rho.cpu().numpy(), d2.cpu().numpy(), vh.cpu().numpy(), Xn.cpu().numpy()
+        Kb, Kr, Kc, B = Kb.cpu().numpy(), Kr.cpu().numpy(), Kc.cpu().numpy(), B.cpu().numpy()
+    ev = O.evaluate(prob, X, nu_a, nu_r, alpha, beta)
+    tolE = 1e-12 if prec == "f64" else 1e-5
+    assert out["energy"][0] == pytest.approx(ev.E, rel=tolE)
+    assert out["energy"][1] == pytest.approx(ev.E_align, rel=tolE)
+    assert out["energy"][2] == pytest.approx(ev.E_reg, rel=tolE)
+    # warp
+    tolv = 1e-14 if prec == "f64" else 2e-7
+    assert np.abs(vh - ev.vhat).max() < tolv
+    # closest points: teacher-forced on the library's own warped points
+    rq, dq, dqs = O.nearest(vh.astype(np.float64), prob.tgt)
+    ok = margin_ok(dq, dqs)
+    assert ok.mean() > 0.99
+    assert np.array_equal(rho[ok], rq[ok])
+    if prec == "f64":
+        ok2 = margin_ok(ev.d2, ev.d2_second)
+        assert np.array_equal(rho[ok2], ev.rho[ok2])
+    # normal equations (Eq. 16) at the oracle's evaluation
+    Ko, Bo = O.normal_equations(prob, ev, nu_a, nu_r, alpha, beta)
+    Kg = _K_dense(Kb, Kr, Kc, n)
+    Kd = Ko.toarray()
+    scale = np.abs(Kd).max()
+    tolK = 1e-12 if prec == "f64" else 2e-6
+    assert np.abs(Kg - Kd).max() <= tolK * scale
+    assert np.abs(B.reshape(-1, 3) - Bo).max() <= tolK * np.abs(Bo).max()
+    # the minimizer
+    Xo = np.asarray(O.mm_update(prob, ev, nu_a, nu_r, alpha, beta)[0])
+    if prec == "f64":
+        assert out["rel_residual"] < 1e-10
+        assert np.abs(Xn - Xo).max() < 1e-7
+    else:
+        assert out["rel_residual"] < 1e-9
+        # deformed points of the two minimizers (what registration returns)
+        vo = O.warp(prob, Xo)
+        vg = O.warp(prob, Xn.astype(np.float64))
+        assert np.sqrt(((vo - vg) ** 2).sum(1).mean()) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_energy_and_gradient_parity(pair, prec):
+    _announce(f"test_energy_and_gradient_parity {prec}")
+    np_dt = np.float64 if prec == "f64" else np.float32
+    t_dt = torch.float64 if prec == "f64" else torch.float32
+    pr = rounded(pair, np_dt)
+    prob = O.from_pair(pr)
+    nu_a, nu_r, alpha, beta = _scalars(prob)
+    X = synth.perturbed_transforms(prob.n_nodes, 9, 0.01, 0.001).astype(np_dt).astype(np.float64)
+    V = (pr.src + np.random.default_rng(3).normal(0, 1e-3, pr.src.shape)).astype(np_dt).astype(np.float64)
+    with Session(pr, t_dt) as s:
+        dev = "cuda:0"
+        Xt = torch.tensor(X, dtype=t_dt, device=dev)
+        Vt = torch.tensor(V, dtype=t_dt, device=dev)
+        gX = torch.empty_like(Xt)
+        gV = torch.empty_like(Vt)
+        e = amm.amm_energy_grad(s.h, Xt, Vt, nu_a, nu_r, alpha, beta, gX, gV)
+        torch.cuda.synchronize()
+        gX, gV = gX.cpu().numpy(), gV.cpu().numpy()
+    gXo, gVo, ev = O.energy_grad(prob, X, nu_a, nu_r, alpha, beta, src=V)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert e[0] == pytest.approx(ev.E, rel=tol)
+    tg = 1e-10 if prec == "f64" else 1e-4
+    assert np.linalg.norm(gX - gXo) <= tg * np.linalg.norm(gXo)
+    assert np.linalg.norm(gV - gVo) <= tg * np.linalg.norm(gVo)
+
+
+def test_solve_fp64_matches_oracle_trajectory():
+    """Whole Alg. 2 on the 2,000-point torus (30 MM iterations, m = 5):
+    library in float64 against the oracle, with the oracle's accept/reject
+    and stage decisions replayed."""
+    _announce("test_solve_fp64_matches_oracle_trajectory")
+    pair = synth.make_workload("torus2k")
+    prob = O.from_pair(pair)
+    p = O.Params(aa_m=5, max_total_iters=30)
+    res = O.solve(prob, p)
+    fa = [e["accepted"] if e["aa_used"] else None for e in res["log"]]
+    fs = []
+    for a, b in zip(res["log"], res["log"][1:] + [None]):
+        fs.append(1 if (b is None or b["stage"] != a["stage"]) else 0)
+    with Session(pair, torch.float64) as s:
+        X = torch.empty(prob.n_nodes, 4, 3, dtype=torch.float64, device="cuda:0")
+        v = torch.empty(prob.n_src, 3, dtype=torch.float64, device="cuda:0")
+        prm = amm.amm_params_default(aa_m=5, max_total_iters=30, precision=amm.AMM_FP64_PLAIN)
+        st = amm.amm_solve(s.h, prm, X, v, force_accept=fa, force_stage_end=fs)[0]
+        torch.cuda.synchronize()
+        X, v = X.cpu().numpy(), v.cpu().numpy()
+    assert st["iters"] == res["total"]
+    rms = math.sqrt(((v - res["vhat"]) ** 2).sum(1).mean())
+    assert rms < 1e-4
+    assert st["energy"] == pytest.approx(res["E"], rel=1e-5)
+
+
+def test_solve_fp32_refine_free_run_matches_oracle():
+    """FP32 + FP64 refinement run free (its own decisions) against the
+    oracle's free run: final deformed points within 1e-4 of the bounding-box
+    diagonal (RMS) and final energies within 1e-5 relative when both end at
+    the same stage."""
+    _announce("test_solve_fp32_refine_free_run_matches_oracle")
+    pair = rounded(synth.make_workload("torus2k"), np.float32)
+    prob = O.from_pair(pair)
+    res = O.solve(prob, O.Params(aa_m=5, max_total_iters=30))
+    with Session(pair, torch.float32) as s:
+        X = torch.empty(prob.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+        v = torch.empty(prob.n_src, 3, dtype=torch.float32, device="cuda:0")
+        prm = amm.amm_params_default(aa_m=5, max_total_iters=30, precision=amm.AMM_FP32_REFINE)
+        st = amm.amm_solve(s.h, prm, X, v)[0]
+        torch.cuda.synchronize()
+        v = v.cpu().numpy().astype(np.float64)
+    rms = math.sqrt(((v - res["vhat"]) ** 2).sum(1).mean())
+    print(f"fp32 vs oracle: rms {rms:.3e} E {st['energy']:.8e} vs {res['E']:.8e} "
+          f"iters {st['iters']} refine {st['refine_steps']} cg {st['cg_iters']}", file=sys.stderr)
+    assert rms < 1e-4
+    assert st["max_rel_residual"] < 1e-9
+
+
+def test_batched_equals_single():
+    """Three uneven pairs in one batch give bitwise the single-pair results."""
+    _announce("test_batched_equals_single")
+    pairs = [synth.torus_pair(1000 + 17 * b, n_src=n, n_tgt=n + 50, n_nodes=nn, k=4, e=6)
+             for b, (n, nn) in enumerate([(300, 20), (517, 33), (1000, 70)])]
+    outs = []
+    for prec, dt in [(amm.AMM_FP64_PLAIN, torch.float64), (amm.AMM_FP32_REFINE, torch.float32)]:
+        singles = []
+        for pr in pairs:
+            with Session(pr, dt) as s:
+                X = torch.empty(pr.n_nodes, 4, 3, dtype=dt, device="cuda:0")
+                amm.amm_solve(s.h, amm.amm_params_default(aa_m=5, max_total_iters=20, precision=prec), X)
+                torch.cuda.synchronize()
+                singles.append(X.cpu().numpy())
+        with Session(pairs, dt) as s:
+            tot = sum(p.n_nodes for p in pairs)
+            X = torch.empty(tot, 4, 3, dtype=dt, device="cuda:0")
+            st = amm.amm_solve(s.h, amm.amm_params_default(aa_m=5, max_total_iters=20, precision=prec),
+                               X, n_pairs=3)
+            torch.cuda.synchronize()
+            Xb = X.cpu().numpy()
+        off = 0
+        for pr, Xs in zip(pairs, singles):
+            assert np.array_equal(Xb[off:off + pr.n_nodes], Xs)
+            off += pr.n_nodes
+        outs.append(st)
+
+
+def test_identical_pair_stays_at_identity():
+    _announce("test_identical_pair_stays_at_identity")
+    pair = synth.identical_pair(synth.torus_pair(1000, n_src=700, n_tgt=700, n_nodes=40, k=4, e=6))
+    with Session(pair, torch.float64) as s:
+        X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float64, device="cuda:0")
+        st = amm.amm_solve(s.h, amm.amm_params_default(aa_m=5, max_total_iters=10,
+                                                        precision=amm.AMM_FP64_PLAIN), X)[0]
+        torch.cuda.synchronize()
+        X = X.cpu().numpy()
+    assert np.abs(X - O.identity(pair.n_nodes)).max() < 1e-8
+    assert st["energy"] < 1e-18
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rigid_motion_recovered(prec):
+    _announce(f"test_rigid_motion_recovered {prec}")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    base = synth.torus_pair(1000, n_src=800, n_tgt=800, n_nodes=50, k=4, e=6)
+    pair = synth.rigid_pair(base, 81, angle_deg=5.0, shift=0.01)
+    with Session(pair, dt) as s:
+        v = torch.empty(pair.n_src, 3, dtype=dt, device="cuda:0")
+        prm = amm.amm_params_default(aa_m=5, max_total_iters=60,
+                                     precision=amm.AMM_FP64_PLAIN if prec == "f64" else amm.AMM_FP32_REFINE)
+        amm.amm_solve(s.h, prm, None, v)
+        torch.cuda.synchronize()
+        v = v.cpu().numpy().astype(np.float64)
+    assert math.sqrt(((v - pair.gt) ** 2).sum(1).mean()) < 1e-4
+
+
+def test_solve_is_deterministic():
+    _announce("test_solve_is_deterministic")
+    pair = synth.torus_pair(1000, n_src=900, n_tgt=900, n_nodes=50, k=4, e=6)
+    res = []
+    for _ in range(2):
+        with Session(pair, torch.float32) as s:
+            X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+            amm.amm_solve(s.h, amm.amm_params_default(aa_m=5, max_total_iters=15), X)
+            torch.cuda.synchronize()
+            res.append(X.cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+
+
+def test_single_node_no_edges():
+    """Degenerate graph: one node, no edges (regularization term vanishes)."""
+    _announce("test_single_node_no_edges")
+    base = synth.torus_pair(1000, n_src=200, n_tgt=200, n_nodes=1, k=1, e=6)
+    assert base.n_edges == 0
+    prob = O.from_pair(base)
+    nu_a, nu_r = 0.05, 0.05
+    alpha, beta = 0.0, 10.0
+    X = synth.perturbed_transforms(1, 4, 0.01, 0.001)
+    with Session(base, torch.float64) as s:
+        Xt = torch.tensor(X, dtype=torch.float64, device="cuda:0")
+        Xn = torch.empty_like(Xt)
+        out = amm.amm_step(s.h, Xt, nu_a, nu_r, alpha, beta, amm.AMM_FP64_PLAIN, X_next=Xn)
+        torch.cuda.synchronize()
+        Xn = Xn.cpu().numpy()
+    ev = O.evaluate(prob, X, nu_a, nu_r, alpha, beta)
+    Xo = O.mm_update(prob, ev, nu_a, nu_r, alpha, beta)[0]
+    assert out["energy"][0] == pytest.approx(ev.E, rel=1e-12)
+    assert np.abs(Xn - Xo).max() < 1e-9
