@@ -1,0 +1,271 @@
+"""Benchmark: MM iterations/s of accelerated-MM non-rigid registration on one
+MI355X, FP32 + FP64 refinement against the plain FP64 path, on the seeded
+200,000-point workload (spherical-harmonic surface, l <= 16, articulated
+warp, 15% outliers, 30% overlap cut; 4,000 nodes, k = 6, 10-NN edges;
+50 MM iterations, Anderson m = 6).  Optionally the 64-pair batched workload
+(pairs/s).  Prints one JSON line.
+
+A "step" is one MM iteration of Alg. 2 over the whole hot path: surrogate
+assembly, linear solve, Anderson mixing, energy evaluation of the candidate
+(warp, closest points, Welsch terms) and the fallback re-evaluation.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(pair, T):
+    """Bytes each kernel group must move per launch (inputs read once,
+    outputs written once), for element size T."""
+    N, M, n, k = pair.n_src, pair.n_tgt, pair.n_nodes, pair.k
+    nadj = 2 * pair.n_edges
+    nnzb = pair.nnzb
+    return {
+        # v, infl (idx+w), previous rho, accepted v_hat; writes v_hat, rho, d2, (e, w_a); targets once
+        "eval_points": N * (3 * T + k * (4 + T) + 4 + 3 * T + 3 * T + 4 + T + 4 * T) + 3 * T * M,
+        # node pairs, r, X of both ends; writes w_r, D
+        "eval_edges": nadj * (8 + T + 2 * 12 * T + T + 4 * T),
+        "eval_nodes": n * (9 * T + 9 * T),
+        # points once (v, e, w_a, influences), X, w_r, D, R; writes K, B, r, D^-1
+        "assemble": N * (3 * T + 4 * T + k * (4 + T)) + 12 * T * n + nadj * 5 * T + 9 * T * n
+                    + 16 * T * nnzb + 4 * nnzb + 4 * (n + 1) + 12 * T * n * 2 + 16 * T * n,
+        # K once, u read, w written
+        "cg_spmv": 16 * T * nnzb + 4 * nnzb + 4 * (n + 1) + 12 * T * n * 2,
+        # reads r u w p s x D^-1, writes p s x r u
+        "cg_update": 12 * T * n * 11 + 16 * T * n,
+        "residual64": 16 * T * nnzb + 4 * nnzb + 12 * 8 * n + 12 * T * n * 3,
+    }
+
+
+def load_pair(name):
+    from paper_2206_03410_amd import synth
+    t = time.time()
+    pair = synth.make_workload(name)
+    log(f"[bench] generated {name}: N={pair.n_src} M={pair.n_tgt} n={pair.n_nodes} "
+        f"k={pair.k} edges={pair.n_edges} in {time.time() - t:.1f}s")
+    return pair
+
+
+def gpu_problem(amm, torch, pair):
+    dev = "cuda:0"
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    return amm.make_problem(t(pair.src, torch.float64), t(pair.tgt, torch.float64),
+                            t(pair.node_idx, torch.int32), t(pair.infl_idx, torch.int32),
+                            t(pair.infl_w, torch.float64), t(pair.edges, torch.int32),
+                            pair.mean_edge_len)
+
+
+def run_solve(amm, torch, h, pair, prec, iters, aa_m, timing=None):
+    dt = torch.float32 if prec == amm.AMM_FP32_REFINE else torch.float64
+    X = torch.empty(pair.n_nodes, 4, 3, dtype=dt, device="cuda:0")
+    v = torch.empty(pair.n_src, 3, dtype=dt, device="cuda:0")
+    prm = amm.amm_params_default(aa_m=aa_m, max_total_iters=iters, precision=prec)
+    if timing is not None:
+        amm.amm_enable_timing(h, True, timing or None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = amm.amm_solve(h, prm, X, v)[0]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = amm.amm_kernel_times(h) if timing is not None else {}
+    if timing is not None:
+        amm.amm_enable_timing(h, False)
+    return st, wall, v.cpu().numpy().astype(np.float64), kt
+
+
+def cpu_baseline(pair, sample=1000):
+    """The FP64 oracle on the same workload, one MM iteration: warp, Welsch
+    terms, rotations, sparse-LU surrogate solve and Anderson mixing timed in
+    full; brute-force closest points timed on `sample` queries and scaled to
+    all N."""
+    from oracle import amm_oracle as O
+    threads = min(16, len(os.sched_getaffinity(0)))
+    prob = O.from_pair(pair)
+    X = O.identity(prob.n_nodes)
+    p = O.Params(aa_m=6)
+    t = time.perf_counter()
+    vh = O.warp(prob, X)
+    t_warp = time.perf_counter() - t
+    rng = np.random.default_rng(0)
+    idx = rng.choice(prob.n_src, sample, replace=False)
+    t = time.perf_counter()
+    rho_s, d2_s, _ = O.nearest(vh[idx], prob.tgt, threads=threads)
+    t_nn = (time.perf_counter() - t) * prob.n_src / sample
+    # closest points of all queries for the rest of the iteration (kd-tree, not timed)
+    from scipy.spatial import cKDTree
+    dd, ii = cKDTree(prob.tgt).query(vh, 2)
+    t = time.perf_counter()
+    D = O.reg_residuals(prob, X)
+    R, er = O.proj_rotation(X[:, :3, :].transpose(0, 2, 1))
+    ev0 = O.Eval(X, vh, ii[:, 0], dd[:, 0] ** 2, dd[:, 1] ** 2, D, R, er, 0, 0, 0, 0)
+    nu_a, nu_min, nu_r = O.initial_nu(prob, p, ev0.d2)
+    alpha, beta = O.term_weights(prob, p, nu_a, nu_r)
+    ev = O.rescore(prob, ev0, nu_a, nu_r, alpha, beta)
+    t_terms = time.perf_counter() - t
+    t = time.perf_counter()
+    Xn, _, _ = O.mm_update(prob, ev, nu_a, nu_r, alpha, beta)
+    t_solve = time.perf_counter() - t
+    t = time.perf_counter()
+    hG = [X.reshape(-1) + 0.0, Xn.reshape(-1)]
+    hF = [np.zeros(X.size), (Xn - X).reshape(-1)]
+    O.anderson(hG, hF, 6)
+    t_aa = time.perf_counter() - t
+    per_iter = t_warp + t_nn + t_terms + t_solve + t_aa
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {
+        "value": 1.0 / per_iter, "unit": "MM iterations/s", "cores": threads, "kind": "oracle",
+        "sample": (f"one FP64 oracle MM iteration on the same 200k workload: warp, Welsch terms, "
+                   f"rotations, sparse-LU surrogate solve and Anderson step in full; brute-force "
+                   f"closest points on {sample} of {prob.n_src} queries, scaled x{prob.n_src // sample}"),
+        "stage_s": {"warp": t_warp, "closest_points_scaled": t_nn, "terms": t_terms,
+                    "surrogate_solve": t_solve, "anderson": t_aa},
+        "cpu_model": cpu, "host": platform.node(),
+    }
+
+
+def batched_run(amm, torch, n_pairs, aa_m):
+    from paper_2206_03410_amd import synth
+    t = time.time()
+    pairs = synth.batch_pairs(n_pairs=n_pairs)
+    log(f"[bench] generated {n_pairs} pairs ({sum(p.n_src for p in pairs)} points) in "
+        f"{time.time() - t:.1f}s")
+    h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        probs = [gpu_problem(amm, torch, p) for p in pairs]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        amm.amm_set_problems(h, probs)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t
+        tot_nodes = sum(p.n_nodes for p in pairs)
+        X = torch.empty(tot_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+        prm = amm.amm_params_default(aa_m=aa_m, precision=amm.AMM_FP32_REFINE)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = amm.amm_solve(h, prm, X, None, n_pairs=n_pairs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+    finally:
+        amm.amm_destroy(h)
+    per = np.array([s["time_ms"] for s in st])
+    return {"pairs": n_pairs, "points": int(sum(p.n_src for p in pairs)),
+            "pairs_per_s": n_pairs / wall, "wall_s": wall, "setup_s": t_setup,
+            "p50_pair_ms": float(np.percentile(per, 50)), "p99_pair_ms": float(np.percentile(per, 99)),
+            "iters_total": int(sum(s["iters"] for s in st)),
+            "converged": int(sum(s["converged"] for s in st))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50, help="MM iterations in the timed solve")
+    ap.add_argument("--warmup", type=int, default=5, help="MM iterations in the untimed warm-up solve")
+    ap.add_argument("--workload", default="sh200k")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batched", type=int, default=0, help="also run this many batched pairs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the registration "
+              "hot path runs on a single device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2206_03410_amd import amm, synth
+
+    pair = load_pair(args.workload)
+    aa_m = synth.WORKLOADS[args.workload]["aa_m"]
+    h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        amm.amm_set_problem(h, gpu_problem(amm, torch, pair))
+        pair.nnzb = amm.amm_k_nnzb(h)
+        # warm-up, every kernel group timed (per-stage breakdown, dominant kernel)
+        st_w, wall_w, _, kt_w = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.warmup, aa_m,
+                                          timing="")
+        dom = max(kt_w, key=lambda k: kt_w[k][0])
+        log(f"[bench] warm-up {args.warmup} iters {wall_w * 1e3:.1f} ms; kernel groups: "
+            + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in sorted(kt_w.items(), key=lambda x: -x[1][0])))
+        # timed FP32 + refinement, HIP events around the dominant group only
+        st32, wall32, v32, kt32 = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m,
+                                            timing=dom)
+        log(f"[bench] fp32+refine: {st32['iters']} iters in {wall32:.3f}s; cg {st32['cg_iters']} "
+            f"refine {st32['refine_steps']} rel.res {st32['max_rel_residual']:.1e}")
+        plain = None
+        if not args.no_plain:
+            st64, wall64, v64, _ = run_solve(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.steps, aa_m)
+            log(f"[bench] fp64 plain: {st64['iters']} iters in {wall64:.3f}s; cg {st64['cg_iters']}")
+            rm32 = math.sqrt(((v32 - pair.gt) ** 2).sum(1).mean())
+            rm64 = math.sqrt(((v64 - pair.gt) ** 2).sum(1).mean())
+            plain = {"iters_per_s": st64["iters"] / wall64, "ms_per_iter": 1e3 * wall64 / st64["iters"],
+                     "iters": st64["iters"], "cg_iters": st64["cg_iters"],
+                     "rmse_gt_fp32": rm32, "rmse_gt_fp64": rm64,
+                     "equal_error": abs(rm32 - rm64) <= max(1e-4, 0.01 * rm64),
+                     "speedup_fp32_refine": (st32["iters"] / wall32) / (st64["iters"] / wall64)}
+    finally:
+        amm.amm_destroy(h)
+
+    T = 4
+    ab = algorithmic_bytes(pair, T)
+    ms_tot, nl = kt32[dom]
+    avg_s = ms_tot / nl * 1e-3
+    achieved = ab[dom] / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6, "launches": nl}
+    stages = {k: {"ms_per_iter": v[0] / max(st_w["iters"], 1), "launches": v[1],
+                  "GBps": (ab[k] / (v[0] / v[1] * 1e-3) / 1e9) if k in ab else None}
+              for k, v in kt_w.items()}
+    out = {
+        "metric": "MM iterations/s at 200k points, FP32+refine vs plain; batched pairs/s at equal err",
+        "value": st32["iters"] / wall32, "unit": "MM iterations/s", "n_gpus": 1,
+        "steps": st32["iters"], "warmup": args.warmup, "ms_per_step": 1e3 * wall32 / st32["iters"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {pair.n_src} source / {pair.n_tgt} target points, "
+                               f"{pair.n_nodes} nodes, k={pair.k}, {pair.n_edges} node edges, "
+                               f"{args.steps} MM iterations, Anderson m={aa_m}, FP32 + FP64 refinement "
+                               f"to relative residual 1e-10",
+                   "n_src": pair.n_src, "n_tgt": pair.n_tgt, "n_nodes": pair.n_nodes, "k": pair.k,
+                   "n_edges": pair.n_edges, "nnzb": pair.nnzb},
+        "roofline": roofline,
+        "plain_fp64": plain,
+        "stages_warmup": stages,
+        "solve": {"cg_iters": st32["cg_iters"], "refine_steps": st32["refine_steps"],
+                  "aa_accepted": st32["aa_accepted"], "aa_rejected": st32["aa_rejected"],
+                  "energy": st32["energy"], "max_rel_residual": st32["max_rel_residual"]},
+    }
+    if args.batched:
+        out["batched"] = batched_run(amm, torch, args.batched, 5)
+    if not args.no_cpu:
+        t = time.time()
+        out["cpu_baseline"] = cpu_baseline(pair)
+        log(f"[bench] cpu baseline in {time.time() - t:.1f}s")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

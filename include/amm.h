@@ -133,6 +133,20 @@ typedef struct {
     double time_ms;              /* wall time of the solve for this pair */
 } amm_stats;
 
+/* One MM iteration (one surrogate solve) of one pair, as decided by Alg. 2. */
+typedef struct {
+    int32_t pair, iter, stage, m_k;
+    int32_t aa_used;             /* the Anderson candidate differs from G(X^k) */
+    int32_t accepted;            /* 1 accepted, 0 rejected (G(X^k) taken), -1 not tested */
+    int32_t cg_iters, refine_steps;
+    double energy_before;        /* E(X^k) */
+    double energy_candidate;     /* E of the candidate that was evaluated first */
+    double energy_after;         /* E(X^{k+1}) */
+    double max_disp;             /* max_i |v_hat^{k+1} - v_hat^k| */
+    double nu_a, nu_r, alpha, beta;
+    double rel_residual;         /* |B - K X'| / |B| of the solve (worst column) */
+} amm_iter_record;
+
 /* ---------------------------------------------------------------- handle */
 
 /* Creates a handle on `device` that orders its work on `hip_stream`
@@ -181,6 +195,11 @@ amm_status amm_set_problem(amm_handle* h, const amm_problem* p);
  * error (stats.converged = 0). */
 amm_status amm_solve(amm_handle* h, const amm_params* params, void* X_inout, void* v_out,
                      amm_stats* stats);
+
+/* Per-iteration record of the last amm_solve, all pairs in the order the
+ * iterations completed: out[i] for i < min(*count, capacity) (out may be
+ * NULL to query the count). */
+amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, int32_t* count);
 
 /* ---------------------------------------------------------------- single step */
 
@@ -240,11 +259,17 @@ amm_status amm_energy_grad(amm_handle* h, amm_dtype dtype, const void* X, const 
 const char* amm_status_string(amm_status s);
 const char* amm_last_error(const amm_handle* h);   /* h may be NULL: last global error */
 
-/* Per-kernel timing of the last amm_solve, accumulated with HIP events on
- * the handle's stream: names[i] (static strings) and ms[i], i < *count. */
+/* Kernel timing with HIP events recorded on the handle's stream around each
+ * launch group (names: "eval_points", "eval_edges", "eval_nodes",
+ * "energy_final", "assemble", "cg_init", "cg_update", "cg_spmv",
+ * "residual64", "anderson").  amm_enable_timing(h, 1, NULL) times every
+ * group, (h, 1, name) only that group, (h, 0, NULL) stops; enabling clears
+ * the totals.  amm_kernel_times returns, per group seen since, the summed
+ * milliseconds and the launch count: names[i], ms[i], launches[i] for
+ * i < min(*count, capacity). */
+amm_status amm_enable_timing(amm_handle* h, int32_t on, const char* only);
 amm_status amm_kernel_times(amm_handle* h, const char** names, double* ms, int32_t* launches,
                             int32_t capacity, int32_t* count);
-amm_status amm_enable_timing(amm_handle* h, int32_t on);
 
 /* Version string of the library build. */
 const char* amm_version(void);

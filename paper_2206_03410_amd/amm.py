@@ -53,6 +53,18 @@ class amm_stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class amm_iter_record(C.Structure):
+    _fields_ = [("pair", C.c_int32), ("iter", C.c_int32), ("stage", C.c_int32), ("m_k", C.c_int32),
+                ("aa_used", C.c_int32), ("accepted", C.c_int32), ("cg_iters", C.c_int32),
+                ("refine_steps", C.c_int32), ("energy_before", C.c_double),
+                ("energy_candidate", C.c_double), ("energy_after", C.c_double),
+                ("max_disp", C.c_double), ("nu_a", C.c_double), ("nu_r", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class amm_step_in(C.Structure):
     _fields_ = [("X", C.c_void_p), ("nu_a", C.c_double), ("nu_r", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("precision", C.c_int32),
@@ -90,6 +102,7 @@ def lib():
             "amm_solve": ([vp, C.POINTER(amm_params), vp, vp, C.POINTER(amm_stats)], C.c_int),
             "amm_step": ([vp, C.POINTER(amm_step_in), C.POINTER(amm_step_out)], C.c_int),
             "amm_k_nnzb": ([vp, C.POINTER(i64)], C.c_int),
+            "amm_iter_log": ([vp, C.POINTER(amm_iter_record), i32, C.POINTER(i32)], C.c_int),
             "amm_energy": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, C.POINTER(dbl), vp, vp], C.c_int),
             "amm_energy_grad": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, vp, vp, C.POINTER(dbl)],
                                 C.c_int),
@@ -97,7 +110,7 @@ def lib():
             "amm_last_error": ([vp], C.c_char_p),
             "amm_kernel_times": ([vp, C.POINTER(C.c_char_p), C.POINTER(dbl), C.POINTER(i32), i32,
                                   C.POINTER(i32)], C.c_int),
-            "amm_enable_timing": ([vp, i32], C.c_int),
+            "amm_enable_timing": ([vp, i32, C.c_char_p], C.c_int),
             "amm_version": ([], C.c_char_p),
             "amm_params_default": ([C.POINTER(amm_params)], None),
         }
@@ -111,7 +124,7 @@ def lib():
 
 EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
-            "amm_solve", "amm_step", "amm_k_nnzb", "amm_energy", "amm_energy_grad",
+            "amm_solve", "amm_step", "amm_k_nnzb", "amm_iter_log", "amm_energy", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
 
@@ -263,6 +276,14 @@ def amm_step(handle, X, nu_a, nu_r, alpha, beta, precision, cg_rtol=1e-10, cg_ma
     return dict(energy=list(sout.energy), cg_iters=sout.cg_iters, rel_residual=sout.rel_residual)
 
 
+def amm_iter_log(handle) -> List[dict]:
+    n = C.c_int32()
+    _check(lib().amm_iter_log(handle, None, 0, C.byref(n)), handle)
+    arr = (amm_iter_record * max(n.value, 1))()
+    _check(lib().amm_iter_log(handle, arr, n.value, C.byref(n)), handle)
+    return [arr[i].as_dict() for i in range(n.value)]
+
+
 def amm_k_nnzb(handle) -> int:
     n = C.c_int64()
     _check(lib().amm_k_nnzb(handle, C.byref(n)), handle)
@@ -283,8 +304,8 @@ def amm_energy_grad(handle, X, src, nu_a, nu_r, alpha, beta, gX, gV=None):
     return list(e)
 
 
-def amm_enable_timing(handle, on: bool = True) -> None:
-    _check(lib().amm_enable_timing(handle, 1 if on else 0), handle)
+def amm_enable_timing(handle, on: bool = True, only: Optional[str] = None) -> None:
+    _check(lib().amm_enable_timing(handle, 1 if on else 0, only.encode() if only else None), handle)
 
 
 def amm_kernel_times(handle) -> dict:

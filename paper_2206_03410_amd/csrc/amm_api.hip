@@ -39,6 +39,8 @@ struct EventTimer final : KernelTimer {
     std::vector<Rec> pending;
     const char* cur_name = nullptr;
     hipEvent_t cur_a = nullptr;
+    std::string only;        // time only launches of this kernel group (empty: all)
+    bool skip = false;
     struct Acc {
         const char* name;
         double ms;
@@ -57,11 +59,14 @@ struct EventTimer final : KernelTimer {
         return e;
     }
     void begin(const char* name, hipStream_t s) override {
+        skip = !only.empty() && only != name;
+        if (skip) return;
         cur_name = name;
         cur_a = get();
         (void)hipEventRecord(cur_a, s);
     }
     void end(hipStream_t s) override {
+        if (skip) return;
         hipEvent_t b = get();
         (void)hipEventRecord(b, s);
         pending.push_back({cur_name, cur_a, b});
@@ -133,6 +138,7 @@ struct Dyn {
     double* nd_part;
     double* Kval;
     double* B;
+    double* rvec;
     double* Dinv;
     double* cg[7];     // x r u w p s rhs
     double* part_ru;
@@ -235,6 +241,7 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(d.nd_part, nnd);
     c.take(d.Kval, 16 * nb);
     c.take(d.B, 12 * n);
+    c.take(d.rvec, 12 * n);
     c.take(d.Dinv, 16 * n);
     for (int q = 0; q < 7; ++q) c.take(d.cg[q], 12 * n);
     c.take(d.part_ru, 3 * nnd);
@@ -276,6 +283,7 @@ struct amm_handle {
     size_t h_cap = 0;
     bool timing = false;
     EventTimer timer;
+    std::vector<amm_iter_record> iter_log;
 };
 
 namespace {
@@ -500,16 +508,19 @@ AsmArgs<T> asm_args(amm_handle* h) {
     for (int q = 0; q < 2; ++q) {
         a.qw[q] = reinterpret_cast<const V*>(d.qw[q]);
         a.wr[q] = reinterpret_cast<const T*>(d.wr[q]);
+        a.Dres[q] = reinterpret_cast<const V*>(d.Dres[q]);
         a.R[q] = reinterpret_cast<const T*>(d.R[q]);
+        a.X[q] = reinterpret_cast<const T*>(d.X[q]);
     }
     a.Kval = reinterpret_cast<T*>(d.Kval);
     a.B = reinterpret_cast<T*>(d.B);
+    a.rvec = reinterpret_cast<T*>(d.rvec);
     a.Dinv = reinterpret_cast<T*>(d.Dinv);
     return a;
 }
 
 template <typename T>
-CgArgs<T> cg_args(amm_handle* h, const T* b, double rtol) {
+CgArgs<T> cg_args(amm_handle* h, const T* b, const T* bnorm, double rtol) {
     const Dyn& d = h->v.d;
     CgArgs<T> a{};
     a.nd_tiles = h->v.nd_tiles;
@@ -520,6 +531,7 @@ CgArgs<T> cg_args(amm_handle* h, const T* b, double rtol) {
     a.Kval = reinterpret_cast<const T*>(d.Kval);
     a.Dinv = reinterpret_cast<const T*>(d.Dinv);
     a.b = b;
+    a.bnorm = bnorm;
     a.x = reinterpret_cast<T*>(d.cg[0]);
     a.r = reinterpret_cast<T*>(d.cg[1]);
     a.u = reinterpret_cast<T*>(d.cg[2]);
@@ -574,10 +586,10 @@ struct SolveReport {
 
 // CG over the pairs flagged PF_SOLVE until all their columns converged.
 template <typename T>
-amm_status run_cg(amm_handle* h, const T* b, double rtol, int zero_x, int maxit, SolveReport& rep) {
+amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int zero_x, int maxit, SolveReport& rep) {
     const Layout& L = h->L;
     const int nt = L.n_nd_tiles;
-    CgArgs<T> a = cg_args<T>(h, b, rtol);
+    CgArgs<T> a = cg_args<T>(h, b, bnorm, rtol);
     launch_cg_init<T>(a, nt, zero_x, h->stream, tmr(h));
     int it = 0;
     const int check = 8;
@@ -612,15 +624,16 @@ amm_status run_cg(amm_handle* h, const T* b, double rtol, int zero_x, int maxit,
     return AMM_OK;
 }
 
-// true residual r = B - K x64 per pair (worst column), on the host
+// true residual |r - K dx| / |B| per pair (worst column) of the increment
+// system K dx = r = B - K X^k, i.e. |B - K X'| / |B| for X' = X^k + dx.
 template <typename T>
 amm_status true_residual(amm_handle* h, T* rhs_out, std::vector<double>& rel) {
     const Layout& L = h->L;
     Dyn& d = h->v.d;
     const int nt = L.n_nd_tiles;
-    CgArgs<T> a = cg_args<T>(h, nullptr, 0);
-    launch_residual64<T>(a, nt, reinterpret_cast<const T*>(d.B), d.x64, rhs_out, d.part_rr64, d.part_bb64, h->stream,
-                         tmr(h));
+    CgArgs<T> a = cg_args<T>(h, nullptr, nullptr, 0);
+    launch_residual64<T>(a, nt, reinterpret_cast<const T*>(d.rvec), reinterpret_cast<const T*>(d.B), d.x64, rhs_out,
+                         d.part_rr64, d.part_bb64, h->stream, tmr(h));
     std::vector<double> rr(3 * nt), bb(3 * nt);
     HIPC(hipMemcpyAsync(rr.data(), d.part_rr64, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, h->stream));
     HIPC(hipMemcpyAsync(bb.data(), d.part_bb64, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, h->stream));
@@ -636,8 +649,10 @@ amm_status true_residual(amm_handle* h, T* rhs_out, std::vector<double>& rel) {
     return AMM_OK;
 }
 
-// Solves K X = B (Eq. 16) for the pairs flagged PF_SOLVE, warm-started from
-// X^k; the solution is left in x64 (float64).
+// Solves the normal equations K X' = B (Eq. 16) for the pairs flagged
+// PF_SOLVE as the increment system K dx = r (r = B - K X^k, assembled in
+// residual form), X' = X^k + dx; dx is left in x64 (float64).  The stopping
+// test is |B - K X'| <= rtol |B| per column.
 template <typename T>
 amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep) {
     const Layout& L = h->L;
@@ -646,12 +661,13 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
     rep.refine.assign(L.P, 0);
     rep.rel.assign(L.P, 0.0);
     rep.not_spd = false;
-    vec_op<T>(h, PF_SOLVE, 4);   // x64 = X^k
+    const T* r = reinterpret_cast<const T*>(d.rvec);
+    const T* B = reinterpret_cast<const T*>(d.B);
+    T* x = reinterpret_cast<T*>(d.cg[0]);
+    vec_op<T>(h, PF_SOLVE, 7);   // dx = 0
     if (sizeof(T) == 8) {
-        // float64 CG from the warm start
-        T* x = reinterpret_cast<T*>(d.cg[0]);
-        vec_op<T>(h, PF_SOLVE, 2, nullptr, x);
-        TRY(run_cg<T>(h, reinterpret_cast<const T*>(d.B), rtol, 0, maxit, rep));
+        // float64 CG on K dx = r
+        TRY(run_cg<T>(h, r, B, rtol, 1, maxit, rep));
         vec_op<T>(h, PF_SOLVE, 0, x, nullptr);
         TRY(true_residual<T>(h, nullptr, rep.rel));
         for (int p = 0; p < L.P; ++p) {
@@ -663,7 +679,6 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
     }
     // float32 CG inside float64 iterative refinement
     T* rhs = reinterpret_cast<T*>(d.cg[6]);
-    T* x = reinterpret_cast<T*>(d.cg[0]);
     std::vector<int32_t> saved(L.P);
     for (int p = 0; p < L.P; ++p) saved[p] = h->dyn[p].flags;
     std::vector<double> prev(L.P, std::numeric_limits<double>::infinity()), rel;
@@ -679,16 +694,19 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
             } else {
                 any = true;
                 rep.refine[p] += 1;
+                // reduce the residual just past the target, within float32 reach
+                h->dyn[p].cg_rtol = std::min(0.25, std::max(1e-5, 0.5 * rtol / rel[p]));
             }
             prev[p] = rel[p];
         }
         if (!any) break;
         TRY(push_dyn(h));
-        TRY(run_cg<T>(h, rhs, 1e-4, 1, maxit, rep));
-        vec_op<T>(h, PF_SOLVE, 1, x, nullptr);   // x64 += correction
+        TRY(run_cg<T>(h, rhs, nullptr, 1e-4, 1, maxit, rep));
+        vec_op<T>(h, PF_SOLVE, 1, x, nullptr);   // dx += correction
     }
     for (int p = 0; p < L.P; ++p) {
         h->dyn[p].flags = saved[p];
+        h->dyn[p].cg_rtol = 0;
         if ((h->dyn[p].flags & PF_SOLVE) && rep.rel[p] > 1e-3 &&
             (h->h_state[2 * p].breakdown | h->h_state[2 * p + 1].breakdown))
             rep.not_spd = true;
@@ -775,6 +793,8 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
     const int ring = m + 1;
     SolveReport rep;
     std::vector<char> reject(P), restage(P);
+    std::vector<amm_iter_record> rec(P);
+    h->iter_log.clear();
     while (true) {
         bool any = false;
         for (int p = 0; p < P; ++p) {
@@ -805,9 +825,9 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
         aa.out = h->v.out;
         aa.ntot = L.ntot;
         aa.G = reinterpret_cast<T*>(d.G);
-        aa.F = reinterpret_cast<T*>(d.F);
+        aa.F = d.F;
         for (int q = 0; q < 3; ++q) aa.X[q] = reinterpret_cast<T*>(d.X[q]);
-        aa.xnew = d.x64;
+        aa.dx = d.x64;
         aa.part = d.aa_part;
         AaSolveArgs sa{h->v.info, h->v.dyn, h->v.out, d.aa_part, P};
         launch_aa<T>(aa, sa, L.n_nd_tiles, h->stream, tmr(h));
@@ -821,6 +841,22 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
             reject[p] = 0;
             if (st.done) continue;
             const PairOut& o = h->h_out[p];
+            amm_iter_record& r = rec[p];
+            r = amm_iter_record{};
+            r.pair = p;
+            r.iter = st.total;
+            r.stage = st.stage;
+            r.m_k = h->dyn[p].aa_mk;
+            r.aa_used = o.aa_used != 0;
+            r.energy_before = st.E_cur;
+            r.energy_candidate = o.E;
+            r.cg_iters = (int32_t)rep.cg_iters[p];
+            r.refine_steps = rep.refine[p];
+            r.rel_residual = rep.rel[p];
+            r.nu_a = st.nu_a;
+            r.nu_r = st.nu_r;
+            r.alpha = st.alpha;
+            r.beta = st.beta;
             bool acc = true;
             if (o.aa_used != 0) {
                 acc = o.E < st.E_cur;
@@ -828,6 +864,7 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
                     acc = prm.force_accept[st.total] != 0;
                 (acc ? st.st.aa_accepted : st.st.aa_rejected) += 1;
             }
+            r.accepted = o.aa_used != 0 ? (acc ? 1 : 0) : -1;
             if (!acc) {
                 reject[p] = 1;
                 any_reject = true;
@@ -857,6 +894,9 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
             st.st.cg_iters += rep.cg_iters[p];
             st.st.refine_steps += rep.refine[p];
             st.st.max_rel_residual = std::max(st.st.max_rel_residual, rep.rel[p]);
+            rec[p].energy_after = o.E;
+            rec[p].max_disp = o.maxdisp;
+            h->iter_log.push_back(rec[p]);
             if (!std::isfinite(o.E)) return fail(h, AMM_ERR_NONFINITE, "energy became non-finite");
             const bool budget = prm.max_total_iters > 0 && st.total >= prm.max_total_iters;
             bool end = o.maxdisp < prm.eps || st.it >= prm.imax || budget;
@@ -991,6 +1031,7 @@ amm_status energy_impl(amm_handle* h, const void* X, const void* src, double nu_
             g.vhat[q] = reinterpret_cast<const V*>(d.vhat[q]);
             g.rho[q] = d.rho[q];
             g.d2[q] = reinterpret_cast<const T*>(d.d2[q]);
+            g.qw[q] = reinterpret_cast<const V*>(d.qw[q]);
             g.Dres[q] = reinterpret_cast<const V*>(d.Dres[q]);
             g.R[q] = reinterpret_cast<const T*>(d.R[q]);
         }
@@ -1032,7 +1073,7 @@ amm_status step_impl(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     out->cg_iters = (int32_t)rep.cg_iters[0];
     out->rel_residual = rep.rel[0];
     if (out->X_next) {
-        vec_op<T>(h, PF_SOLVE, 2, nullptr, reinterpret_cast<T*>(d.X[2]));
+        vec_op<T>(h, PF_SOLVE, 8);   // X' = X^k + dx
         launch_x_export<T, T>(reinterpret_cast<const T*>(d.X[2]), reinterpret_cast<T*>(out->X_next), h->v.node_user,
                               L.ntot, h->stream);
     }
@@ -1266,6 +1307,13 @@ amm_status amm_step(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");
 }
 
+amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, int32_t* count) {
+    if (!h || !count) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    *count = (int32_t)h->iter_log.size();
+    for (int32_t i = 0; i < *count && i < capacity && out; ++i) out[i] = h->iter_log[i];
+    return AMM_OK;
+}
+
 amm_status amm_k_nnzb(amm_handle* h, int64_t* nnzb) {
     if (!h || !nnzb) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
     if (!h->has_problem) return fail(h, AMM_ERR_STATE, "no problem set");
@@ -1297,10 +1345,11 @@ amm_status amm_energy_grad(amm_handle* h, amm_dtype dtype, const void* X, const 
     return energy_entry(h, dtype, X, src, nu_a, nu_r, alpha, beta, energy, nullptr, nullptr, gX, gV);
 }
 
-amm_status amm_enable_timing(amm_handle* h, int32_t on) {
+amm_status amm_enable_timing(amm_handle* h, int32_t on, const char* only) {
     if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
     h->timer.collect();
     h->timing = on != 0;
+    h->timer.only = only ? only : "";
     h->timer.acc.clear();
     return AMM_OK;
 }

@@ -44,6 +44,7 @@ struct PairDyn {
     int32_t aa_slot[11];     // ring slots: [0] = newest (k), [1] = k-1, ...
     int32_t has_prev;        // closest-point warm start available in set `cur`
     int32_t pad;
+    double cg_rtol;          // CG stopping tolerance of this pair (0: the launch's)
 };
 
 // Per-pair outputs read back by the host after an evaluation.
@@ -100,7 +101,7 @@ struct Layout {
 };
 
 constexpr int kPointTile = 256;
-constexpr int kNodeTile = 64;        // solver rows per tile (4 threads per row)
+constexpr int kNodeTile = 16;        // solver rows per tile (4 threads per row: one wave)
 constexpr int kEdgeTile = 256;
 constexpr int kMaxCols = 192;        // K blocks per row supported by the assembly
 constexpr int kMaxK = 8;

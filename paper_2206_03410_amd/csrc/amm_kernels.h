@@ -46,7 +46,7 @@ struct EvalArgs {
     V* vhat[2];
     int* rho[2];             // global index into the sorted targets
     T* d2[2];
-    V* qw[2];                // (Q_i, w_a,i)
+    V* qw[2];                // (e_i = v_hat_i - u_rho(i), w_a,i)
     T* wr[2];                // w_r per directed entry
     V* Dres[2];              // (D, |D|^2) per directed entry
     T* R[2];                 // closest rotations, row-major 3x3
@@ -86,11 +86,14 @@ struct AsmArgs {
     const int* adj_nbr;
     const int* adj_rev;
     const T* adj_r;
-    const V* qw[2];
+    const V* qw[2];          // (e_i = v_hat_i - u_rho(i), w_a,i)
     const T* wr[2];
+    const V* Dres[2];
     const T* R[2];
+    const T* X[2];
     T* Kval;
     T* B;
+    T* rvec;                 // r = B - K X^k
     T* Dinv;
 };
 
@@ -104,6 +107,7 @@ struct CgArgs {
     const T* Kval;
     const T* Dinv;
     const T* b;
+    const T* bnorm;          // vector whose norm scales the stopping test (null: b)
     T* x;
     T* r;
     T* u;
@@ -137,9 +141,9 @@ struct AaArgs {
     const PairOut* out;
     int64_t ntot;
     T* G;                    // ring [(m+1)][ntot*12]
-    T* F;
+    double* F;               // residual history in float64: its differences cancel
     T* X[3];
-    const double* xnew;      // solution of the surrogate (float64)
+    const double* dx;        // increment X' - X^k (float64)
     double* part;            // [nd_tiles][kAaParts]
 };
 
@@ -178,6 +182,7 @@ struct GradArgs {
     const V* vhat[2];
     const int* rho[2];
     const T* d2[2];
+    const V* qw[2];
     const V* Dres[2];
     const T* R[2];
     V* gpt;
@@ -195,8 +200,8 @@ void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, int zero_x, hipStream_t 
 template <typename T>
 void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm);
 template <typename T>
-void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const double* x64, T* rhs_out,
-                       double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm);
+void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const T* Bn, const double* x64,
+                       T* rhs_out, double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm);
 template <typename T>
 void launch_node_vec_op(const NodeVecArgs<T>& a, int n_nd_tiles, hipStream_t s);
 template <typename T>

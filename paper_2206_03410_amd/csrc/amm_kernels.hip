@@ -68,8 +68,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 // ---------------------------------------------------------------- evaluation
 
 // Per source point: warp (Eq. 2), closest target, Welsch value and weight
-// (Eqs. 5, 6, 15), Q_i = u_rho(i) - sum_j w_ij p_j (Sec. 3.3.2), max
-// displacement against the accepted iterate.  One thread per point.
+// (Eqs. 5, 6, 15), the alignment residual e_i = v_hat_i - u_rho(i), and the
+// max displacement against the accepted iterate.  One thread per point.
 template <typename T>
 __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     using V = typename V4Of<T>::type;
@@ -87,22 +87,25 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     T psi = 0, disp = 0;
     if (i < td.z) {
         const V v = src[i];
-        T vx = 0, vy = 0, vz = 0, sx = 0, sy = 0, sz = 0;
+        // v_hat (absolute, for the search) and, for the residual, the small
+        // parts sum_j w_ij ((A_j - I)(v_i - p_j) + t_j) and sum_j w_ij
+        T vx = 0, vy = 0, vz = 0, sx = 0, sy = 0, sz = 0, sw = 0;
         for (int s = 0; s < a.k; ++s) {
             const int j = a.iidx[(size_t)s * a.Ntot + i];
             const T w = a.iw[(size_t)s * a.Ntot + i];
             const V pj = a.nodes[j];
             const T* Xj = X + 12 * (size_t)j;
             const T dx = v.x - pj.x, dyy = v.y - pj.y, dz = v.z - pj.z;
-            const T yx = dx * Xj[0] + dyy * Xj[3] + dz * Xj[6] + Xj[9] + pj.x;
-            const T yy = dx * Xj[1] + dyy * Xj[4] + dz * Xj[7] + Xj[10] + pj.y;
-            const T yz = dx * Xj[2] + dyy * Xj[5] + dz * Xj[8] + Xj[11] + pj.z;
-            vx += w * yx;
-            vy += w * yy;
-            vz += w * yz;
-            sx += w * pj.x;
-            sy += w * pj.y;
-            sz += w * pj.z;
+            const T gx = dx * (Xj[0] - T(1)) + dyy * Xj[3] + dz * Xj[6] + Xj[9];
+            const T gy = dx * Xj[1] + dyy * (Xj[4] - T(1)) + dz * Xj[7] + Xj[10];
+            const T gz = dx * Xj[2] + dyy * Xj[5] + dz * (Xj[8] - T(1)) + Xj[11];
+            vx += w * (dx * Xj[0] + dyy * Xj[3] + dz * Xj[6] + Xj[9] + pj.x);
+            vy += w * (dx * Xj[1] + dyy * Xj[4] + dz * Xj[7] + Xj[10] + pj.y);
+            vz += w * (dx * Xj[2] + dyy * Xj[5] + dz * Xj[8] + Xj[11] + pj.z);
+            sx += w * gx;
+            sy += w * gy;
+            sz += w * gz;
+            sw += w;
         }
         const int prev = dy.has_prev ? a.rho[cur][i] - (int)pi.tgt_off : -1;
         int bpos;
@@ -113,10 +116,12 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
         const T t = d2 * inv;
         psi = -expm1(-t);
         const T wa = exp(-t) * inv;
+        // e_i = v_hat_i - u_rho(i) = sum_j w_ij ((A_j - I) d_ij + t_j) + (sum_j w_ij)(v_i - u)
+        // (Eq. 2 rearranged): every operand is small, so e_i keeps its relative accuracy
         V q;
-        q.x = u.x - sx;
-        q.y = u.y - sy;
-        q.z = u.z - sz;
+        q.x = sx + sw * (v.x - u.x);
+        q.y = sy + sw * (v.y - u.y);
+        q.z = sz + sw * (v.z - u.z);
         q.w = wa;
         a.qw[dst][i] = q;
         a.rho[dst][i] = (int)pi.tgt_off + bpos;
@@ -338,14 +343,19 @@ __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
 
 // ---------------------------------------------------------------- assembly
 
-// Row j of K and B (Eq. 16), one wave per node.  Alignment blocks
-// K_jl = sum_i w_a,i w_ij w_il [v_i - p_j; 1][v_i - p_l; 1]^T are formed as
-// moments anchored at p_j, M_jl = sum c_i w_il x x^T with x = [v_i - p_j; 1],
-// then shifted: K_jl = M_jl S^T, S = [[I, p_j - p_l], [0, 1]].  Lanes first
-// own points (stage moments in LDS), then own columns of the row (gather in
-// a fixed order).  Edge blocks follow Eqs. (7), (13) and the matrix H, the
-// rotation term adds beta J^T J and beta J^T J Z.  The 4x4 diagonal block's
-// inverse (block-Jacobi preconditioner) is written alongside.
+// Row j of K and B (Eq. 16) and of the residual r = B - K X^k, one wave per
+// node.  Alignment blocks K_jl = sum_i w_a,i w_ij w_il [v_i - p_j; 1]
+// [v_i - p_l; 1]^T are formed as moments anchored at p_j,
+// M_jl = sum c_i w_il x x^T with x = [v_i - p_j; 1], then shifted:
+// K_jl = M_jl S^T, S = [[I, p_j - p_l], [0, 1]].  Lanes first own points
+// (stage moments in LDS), then own columns of the row (gather in a fixed
+// order).  Edge blocks follow Eqs. (7), (13) and the matrix H; the rotation
+// term adds beta J^T J.  The residual is assembled from the residuals at
+// X^k themselves -- r = -sum w_a F^T e - alpha sum w_r H^T D + beta J(Z - X^k)
+// -- instead of as the difference B - K X^k of two large rounded
+// quantities, so its relative accuracy does not degrade as the iteration
+// converges; B = r + K X^k.  The inverse of the 4x4 diagonal block
+// (block-Jacobi preconditioner) is written alongside.
 template <typename T>
 __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     using V = typename V4Of<T>::type;
@@ -374,9 +384,9 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
 #pragma unroll
         for (int m = 0; m < 10; ++m) acc[c][m] = 0;
     }
-    T bacc[12];
+    T racc[12];
 #pragma unroll
-    for (int m = 0; m < 12; ++m) bacc[m] = 0;
+    for (int m = 0; m < 12; ++m) racc[m] = 0;
     const int e0 = a.pj_ptr[j], e1 = a.pj_ptr[j + 1];
     for (int base = e0; base < e1; base += 64) {
         const int e = base + lane;
@@ -397,19 +407,20 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
             smom[lane][7] = c * dz * dz;
             smom[lane][8] = c * dz;
             smom[lane][9] = c;
+            // alignment part of -r: c [v_i - p_j; 1] e_i^T
             const T ax = c * dx, ay = c * dyy, az = c * dz;
-            bacc[0] += ax * q.x;
-            bacc[1] += ax * q.y;
-            bacc[2] += ax * q.z;
-            bacc[3] += ay * q.x;
-            bacc[4] += ay * q.y;
-            bacc[5] += ay * q.z;
-            bacc[6] += az * q.x;
-            bacc[7] += az * q.y;
-            bacc[8] += az * q.z;
-            bacc[9] += c * q.x;
-            bacc[10] += c * q.y;
-            bacc[11] += c * q.z;
+            racc[0] += ax * q.x;
+            racc[1] += ax * q.y;
+            racc[2] += ax * q.z;
+            racc[3] += ay * q.x;
+            racc[4] += ay * q.y;
+            racc[5] += ay * q.z;
+            racc[6] += az * q.x;
+            racc[7] += az * q.y;
+            racc[8] += az * q.z;
+            racc[9] += c * q.x;
+            racc[10] += c * q.y;
+            racc[11] += c * q.z;
             for (int b = 0; b < kMaxK; ++b) {
                 snid[lane][b] = b < k ? a.iidx[(size_t)b * a.Ntot + i] : -1;
                 swgt[lane][b] = b < k ? a.iw[(size_t)b * a.Ntot + i] : T(0);
@@ -439,10 +450,14 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
         __syncthreads();
     }
 #pragma unroll
-    for (int m = 0; m < 12; ++m) bacc[m] = wave_sum(bacc[m]);
+    for (int m = 0; m < 12; ++m) racc[m] = wave_sum(racc[m]);
 
     const T alpha = (T)dy.alpha, beta = (T)dy.beta;
     const int ab = a.adj_ptr[j], ae = a.adj_ptr[j + 1];
+    const T* Xk = a.X[cur];
+    T kx[12];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) kx[m] = 0;
 #pragma unroll
     for (int c = 0; c < CM; ++c) {
         const int pos = kb + lane + 64 * c;
@@ -524,27 +539,49 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
         T* Ko = a.Kval + 16 * (size_t)pos;
         for (int r = 0; r < 4; ++r)
             for (int s = 0; s < 4; ++s) Ko[4 * r + s] = Kb[r][s];
+        // (K X^k)_j contribution of this column block
+        const T* Xl = Xk + 12 * (size_t)l;
+        for (int r = 0; r < 4; ++r)
+            for (int c2 = 0; c2 < 3; ++c2)
+                kx[3 * r + c2] += Kb[r][0] * Xl[c2] + Kb[r][1] * Xl[3 + c2] + Kb[r][2] * Xl[6 + c2] +
+                                  Kb[r][3] * Xl[9 + c2];
     }
+#pragma unroll
+    for (int m = 0; m < 12; ++m) kx[m] = wave_sum(kx[m]);
     if (lane == 0) {
-        T Bj[12];
-        for (int m2 = 0; m2 < 12; ++m2) Bj[m2] = bacc[m2];
+        T rj[12];
+        for (int m2 = 0; m2 < 12; ++m2) rj[m2] = -racc[m2];
+        const typename V4Of<T>::type* Dr = a.Dres[cur];
         for (int e = ab; e < ae; ++e) {
             const int l2 = a.adj_nbr[e], rev = a.adj_rev[e];
             const T rr = a.adj_r[e];
-            const T om_e = alpha * wr[e] * rr * rr;
-            const T om_r = alpha * wr[rev] * rr * rr;
             const V q2 = a.nodes[l2];
-            const T dd[3] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z};
-            for (int c2 = 0; c2 < 3; ++c2) {
-                for (int r = 0; r < 3; ++r) Bj[3 * r + c2] += om_r * dd[r] * dd[c2];
-                Bj[9 + c2] += (om_r + om_e) * dd[c2];
+            const T ext[4] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z, T(1)};   // [p_l - p_j; 1]
+            // D_lj (entry rev): H block of j is r [p_l - p_j; 1]
+            const V D1 = Dr[rev];
+            const T f1 = alpha * wr[rev] * rr;
+            for (int r = 0; r < 4; ++r) {
+                rj[3 * r + 0] -= f1 * ext[r] * D1.x;
+                rj[3 * r + 1] -= f1 * ext[r] * D1.y;
+                rj[3 * r + 2] -= f1 * ext[r] * D1.z;
             }
+            // D_jl (entry e): H block of j is -r e4
+            const V D2 = Dr[e];
+            const T f2 = alpha * wr[e] * rr;
+            rj[9] += f2 * D2.x;
+            rj[10] += f2 * D2.y;
+            rj[11] += f2 * D2.z;
         }
         const T* Rj = a.R[cur] + 9 * (size_t)j;
+        const T* Xj = Xk + 12 * (size_t)j;
         for (int r = 0; r < 3; ++r)
-            for (int c2 = 0; c2 < 3; ++c2) Bj[3 * r + c2] += beta * Rj[3 * c2 + r];
+            for (int c2 = 0; c2 < 3; ++c2) rj[3 * r + c2] += beta * (Rj[3 * c2 + r] - Xj[3 * r + c2]);
+        T* Ro = a.rvec + 12 * (size_t)j;
         T* Bo = a.B + 12 * (size_t)j;
-        for (int m2 = 0; m2 < 12; ++m2) Bo[m2] = Bj[m2];
+        for (int m2 = 0; m2 < 12; ++m2) {
+            Ro[m2] = rj[m2];
+            Bo[m2] = rj[m2] + kx[m2];
+        }
     }
 }
 
@@ -579,7 +616,8 @@ __device__ __forceinline__ void reduce3_store(T v0, T v1, T v2, T* sh, double* d
     }
 }
 
-// r = b - K x0 (x0 = 0 when zero_x), u = M^{-1} r; partials (r,u), (r,r), (b,b).
+// r = b - K x0 (x0 = 0 when zero_x), u = M^{-1} r; partials (r,u), (r,r) and
+// (n,n) of the vector n that scales the stopping test (b, or a.bnorm).
 template <typename T>
 __global__ void __launch_bounds__(4 * kNodeTile) k_cg_init(CgArgs<T> a, int zero_x) {
     __shared__ T sh[4 * kNodeTile];
@@ -595,8 +633,9 @@ __global__ void __launch_bounds__(4 * kNodeTile) k_cg_init(CgArgs<T> a, int zero
         T kx[3] = {0, 0, 0};
         if (!zero_x) spmv_row(a, j, r, a.x, kx);
         for (int c = 0; c < 3; ++c) {
-            bv[c] = a.b[12 * (size_t)j + 3 * r + c];
-            rv[c] = bv[c] - kx[c];
+            const T bc = a.b[12 * (size_t)j + 3 * r + c];
+            bv[c] = a.bnorm ? a.bnorm[12 * (size_t)j + 3 * r + c] : bc;
+            rv[c] = bc - kx[c];
             a.r[12 * (size_t)j + 3 * r + c] = rv[c];
             if (zero_x) a.x[12 * (size_t)j + 3 * r + c] = 0;
         }
@@ -650,14 +689,6 @@ __global__ void __launch_bounds__(4 * kNodeTile) k_cg_spmv(CgArgs<T> a, int it) 
     reduce3_store(wv[0] * uv[0], wv[1] * uv[1], wv[2] * uv[2], sh, a.part_wu + 3 * tile);
 }
 
-// Pair-level reduction of tile partials in a fixed order (every block of the
-// pair computes the same value).
-__device__ __forceinline__ double pair_dot(const double* part, int t0, int nt, int c) {
-    double s = 0;
-    for (int t = 0; t < nt; ++t) s += part[3 * (t0 + t) + c];
-    return s;
-}
-
 // One Chronopoulos-Gear step: scalars from the partials of the previous
 // step, p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s,
 // u = M^{-1} r; partials (r,u), (r,r).  Columns whose relative residual
@@ -667,26 +698,53 @@ __global__ void __launch_bounds__(4 * kNodeTile) k_cg_update(CgArgs<T> a, int it
     __shared__ T sh[4 * kNodeTile];
     __shared__ T rs[kNodeTile][4][3];
     __shared__ double scal[3][3];   // alpha, beta, active
+    __shared__ double red[12];      // pair sums: (r,u), (w,u), (r,r), (n,n) per column
     __shared__ int brk_mask;
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
     const int p = td.x;
-    if (!(a.dyn[p].flags & PF_SOLVE)) return;
+    const PairDyn& dy = a.dyn[p];
+    if (!(dy.flags & PF_SOLVE)) return;
     const PairInfo& pi = a.info[p];
     const CgState& prv = a.state[2 * (size_t)p + ((it + 1) & 1)];
-    if (threadIdx.x == 0) brk_mask = 0;
+    {
+        // pair-level sums of the tile partials: lane l takes tiles l, l+64, ...,
+        // then a fixed butterfly (every block of the pair gets the same values)
+        const int lane = threadIdx.x;
+        double v[12];
+#pragma unroll
+        for (int m = 0; m < 12; ++m) v[m] = 0;
+        for (int t = lane; t < pi.nd_ntile; t += 64) {
+            const size_t o = 3 * (size_t)(pi.nd_tile0 + t);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[c] += a.part_ru[o + c];
+                v[3 + c] += a.part_wu[o + c];
+                v[6 + c] += a.part_rr[o + c];
+                v[9 + c] += a.part_bb[o + c];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 12; ++m) v[m] = wave_sum(v[m]);
+        if (lane == 0) {
+#pragma unroll
+            for (int m = 0; m < 12; ++m) red[m] = v[m];
+            brk_mask = 0;
+        }
+    }
     __syncthreads();
+    const double rtol2 = dy.cg_rtol > 0 ? dy.cg_rtol * dy.cg_rtol : a.rtol2;
     if (threadIdx.x < 3) {
         const int c = threadIdx.x;
-        const double gam = pair_dot(a.part_ru, pi.nd_tile0, pi.nd_ntile, c);
-        const double del = pair_dot(a.part_wu, pi.nd_tile0, pi.nd_ntile, c);
-        const double rr = pair_dot(a.part_rr, pi.nd_tile0, pi.nd_ntile, c);
-        const double bb = pair_dot(a.part_bb, pi.nd_tile0, pi.nd_ntile, c);
+        const double gam = red[c];
+        const double del = red[3 + c];
+        const double rr = red[6 + c];
+        const double bb = red[9 + c];
         int conv = prv.conv[c];
         int brk = 0;
         double al = 0, be = 0;
         if (!conv) {
-            if (rr <= a.rtol2 * bb || bb == 0.0) {
+            if (rr <= rtol2 * bb || bb == 0.0) {
                 conv = 1;
             } else if (it == 0) {
                 al = gam / del;
@@ -761,11 +819,12 @@ __global__ void __launch_bounds__(4 * kNodeTile) k_cg_update(CgArgs<T> a, int it
 
 // ---------------------------------------------------------------- iterative refinement
 
-// r64 = B - K x64 in float64 (K, B in T, upcast exactly); the float32 copy
-// of r64 is the right-hand side of the next inner solve.  Partials (r,r), (B,B).
+// res64 = rhs - K x64 in float64 (K, rhs in T, upcast exactly); the T copy of
+// res64 is the right-hand side of the next inner solve.  Partials (res,res)
+// and (n,n) of the vector n that scales the stopping test.
 template <typename T>
-__global__ void __launch_bounds__(4 * kNodeTile) k_residual64(CgArgs<T> a, const T* B, const double* x64,
-                                                              T* rhs_out, double* part_rr,
+__global__ void __launch_bounds__(4 * kNodeTile) k_residual64(CgArgs<T> a, const T* B, const T* Bn,
+                                                              const double* x64, T* rhs_out, double* part_rr,
                                                               double* part_bb) {
     __shared__ double sh[4 * kNodeTile];
     const int tile = blockIdx.x;
@@ -788,8 +847,8 @@ __global__ void __launch_bounds__(4 * kNodeTile) k_residual64(CgArgs<T> a, const
         }
         for (int c = 0; c < 3; ++c) {
             const size_t o = 12 * (size_t)j + 3 * r + c;
-            bv[c] = (double)B[o];
-            rv[c] = bv[c] - acc[c];
+            bv[c] = (double)Bn[o];
+            rv[c] = (double)B[o] - acc[c];
             if (rhs_out) rhs_out[o] = (T)rv[c];
         }
     }
@@ -809,6 +868,7 @@ template <typename T>
 __global__ void k_node_vec_op(NodeVecArgs<T> a) {
     // 0: x64 = src_t        1: x64 += src_t       2: dst_t = (T) x64      3: dst_t = src_t
     // 4: x64 = X[cur]       5: X[2] = X[cur]      6: X[1 - cur] = X[2]
+    // 7: x64 = 0            8: X[2] = X[cur] + x64
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
     const PairDyn dy = a.dyn[td.x];
@@ -822,14 +882,17 @@ __global__ void k_node_vec_op(NodeVecArgs<T> a) {
             case 3: a.dst_t[o] = a.src_t[o]; break;
             case 4: a.x64[o] = (double)a.X[dy.cur][o]; break;
             case 5: a.X[2][o] = a.X[dy.cur][o]; break;
-            default: a.X[1 - dy.cur][o] = a.X[2][o]; break;
+            case 6: a.X[1 - dy.cur][o] = a.X[2][o]; break;
+            case 7: a.x64[o] = 0.0; break;
+            default: a.X[2][o] = (T)((double)a.X[dy.cur][o] + a.x64[o]); break;
         }
     }
 }
 
 // ---------------------------------------------------------------- Anderson acceleration
 
-// G^(k) = X' and F^(k) = X' - X^k into the ring slot of the newest entry.
+// G^(k) = X' = X^k + dX and F^(k) = dX into the ring slot of the newest
+// entry; X' also goes to transform set 2.
 template <typename T>
 __global__ void k_aa_push(AaArgs<T> a) {
     const int tile = blockIdx.x;
@@ -838,14 +901,15 @@ __global__ void k_aa_push(AaArgs<T> a) {
     if (!(dy.flags & PF_SOLVE)) return;
     const size_t n12 = 12 * (size_t)a.ntot;
     T* G = a.G + (size_t)dy.aa_slot[0] * n12;
-    T* F = a.F + (size_t)dy.aa_slot[0] * n12;
+    double* F = a.F + (size_t)dy.aa_slot[0] * n12;
     const T* Xc = a.X[dy.cur];
     const size_t b0 = 12 * (size_t)td.y, b1 = 12 * (size_t)td.z;
     for (size_t o = b0 + threadIdx.x; o < b1; o += blockDim.x) {
-        const double g = a.xnew[o];
-        G[o] = (T)g;
-        F[o] = (T)(g - (double)Xc[o]);
-        a.X[2][o] = (T)g;
+        const double dx = a.dx[o];
+        const T g = (T)((double)Xc[o] + dx);
+        G[o] = g;
+        F[o] = dx;
+        a.X[2][o] = g;
     }
 }
 
@@ -1008,15 +1072,12 @@ __global__ void __launch_bounds__(kPointTile) k_grad_points(GradArgs<T> a) {
     const int i = td.y + (int)threadIdx.x;
     if (i >= td.z) return;
     const int set = dy.eval_dst;
-    const V vh = a.vhat[set][i];
-    const V u = a.tgt[a.rho[set][i]];
-    const T nu2 = (T)dy.nu_a * (T)dy.nu_a;
-    const T d2 = a.d2[set][i];
-    const T f = exp(-d2 / (T(2) * nu2)) / nu2;
+    const V e = a.qw[set][i];   // (v_hat_i - u_rho(i), w_a,i = exp(-d^2/(2 nu^2)) / (2 nu^2))
+    const T f = T(2) * e.w;
     V g;
-    g.x = f * (vh.x - u.x);
-    g.y = f * (vh.y - u.y);
-    g.z = f * (vh.z - u.z);
+    g.x = f * e.x;
+    g.y = f * e.y;
+    g.z = f * e.z;
     g.w = 0;
     a.gpt[i] = g;
     if (a.gV) {
@@ -1218,26 +1279,26 @@ void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, K
 }
 
 template <typename T>
-void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const double* x64, T* rhs_out,
-                       double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm) {
+void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const T* Bn, const double* x64,
+                       T* rhs_out, double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm) {
     if (tm) tm->begin("residual64", s);
-    hipLaunchKernelGGL(k_residual64<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, B, x64, rhs_out, part_rr,
-                       part_bb);
+    hipLaunchKernelGGL(k_residual64<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, B, Bn, x64, rhs_out,
+                       part_rr, part_bb);
     if (tm) tm->end(s);
 }
 
 template <typename T>
 void launch_node_vec_op(const NodeVecArgs<T>& a, int n_nd_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_node_vec_op<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_node_vec_op<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a);
 }
 
 template <typename T>
 void launch_aa(const AaArgs<T>& a, const AaSolveArgs& sa, int n_nd_tiles, hipStream_t s, KernelTimer* tm) {
     if (tm) tm->begin("anderson", s);
-    hipLaunchKernelGGL(k_aa_push<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_aa_push<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a);
     hipLaunchKernelGGL(k_aa_gram<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_aa_solve, dim3(blocks_for(sa.P, 64)), dim3(64), 0, s, sa);
-    hipLaunchKernelGGL(k_aa_mix<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_aa_mix<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a);
     if (tm) tm->end(s);
 }
 
@@ -1282,8 +1343,8 @@ void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s) {
     template void launch_assemble<T>(const AsmArgs<T>&, int64_t, hipStream_t, KernelTimer*);                   \
     template void launch_cg_init<T>(const CgArgs<T>&, int, int, hipStream_t, KernelTimer*);                    \
     template void launch_cg_iter<T>(const CgArgs<T>&, int, int, hipStream_t, KernelTimer*);                    \
-    template void launch_residual64<T>(const CgArgs<T>&, int, const T*, const double*, T*, double*, double*,    \
-                                       hipStream_t, KernelTimer*);                                            \
+    template void launch_residual64<T>(const CgArgs<T>&, int, const T*, const T*, const double*, T*, double*,  \
+                                       double*, hipStream_t, KernelTimer*);                                   \
     template void launch_node_vec_op<T>(const NodeVecArgs<T>&, int, hipStream_t);                             \
     template void launch_aa<T>(const AaArgs<T>&, const AaSolveArgs&, int, hipStream_t, KernelTimer*);          \
     template void launch_grad<T>(const GradArgs<T>&, int, int64_t, hipStream_t);                              \

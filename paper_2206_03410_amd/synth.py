@@ -38,7 +38,6 @@ import numpy as np
 from scipy import sparse
 from scipy.sparse import csgraph
 from scipy.spatial import cKDTree
-from scipy.special import sph_harm_y
 
 # sub-stream offsets of a pair's base seed
 _S_SRC, _S_TGT, _S_WARP, _S_NOISE, _S_OUT, _S_CUT = range(6)
@@ -110,20 +109,36 @@ def torus_points(n: int, rng: np.random.Generator, R: float = 1.0, r: float = 0.
 
 
 def _real_sh_basis(dirs: np.ndarray, lmax: int) -> np.ndarray:
-    """Real orthonormal spherical harmonics up to degree lmax at unit dirs.
-    Returns (len(dirs), (lmax+1)^2)."""
-    polar = np.arccos(np.clip(dirs[:, 2], -1.0, 1.0))
-    azim = np.arctan2(dirs[:, 1], dirs[:, 0])
+    """Real orthonormal spherical harmonics up to degree lmax at unit dirs,
+    from the fully normalized associated Legendre recurrence (columns ordered
+    l = 0..lmax, m = -l..l).  Returns (len(dirs), (lmax+1)^2)."""
+    z = np.clip(dirs[:, 2], -1.0, 1.0)
+    st = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    n = dirs.shape[0]
+    P = {}                                   # normalized P_l^m(z), m >= 0
+    pmm = np.full(n, math.sqrt(1.0 / (4.0 * math.pi)))
+    for m in range(lmax + 1):
+        if m > 0:
+            pmm = -math.sqrt((2 * m + 1) / (2.0 * m)) * st * pmm
+        P[(m, m)] = pmm
+        if m + 1 <= lmax:
+            P[(m + 1, m)] = math.sqrt(2 * m + 3) * z * pmm
+        for l in range(m + 2, lmax + 1):
+            a = math.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+            b = math.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+            P[(l, m)] = a * (z * P[(l - 1, m)] - b * P[(l - 2, m)])
     cols = []
+    cosm = [np.cos(m * phi) for m in range(lmax + 1)]
+    sinm = [np.sin(m * phi) for m in range(lmax + 1)]
     for l in range(lmax + 1):
         for m in range(-l, l + 1):
-            y = sph_harm_y(l, abs(m), polar, azim)
             if m < 0:
-                cols.append(math.sqrt(2.0) * ((-1) ** m) * y.imag)
+                cols.append(math.sqrt(2.0) * P[(l, -m)] * sinm[-m])
             elif m == 0:
-                cols.append(y.real)
+                cols.append(P[(l, 0)])
             else:
-                cols.append(math.sqrt(2.0) * ((-1) ** m) * y.real)
+                cols.append(math.sqrt(2.0) * P[(l, m)] * cosm[m])
     return np.stack(cols, 1)
 
 
@@ -221,16 +236,25 @@ class ArticulatedWarp:
 # --------------------------------------------------------------------------
 
 def farthest_point_sampling(pts: np.ndarray, n: int, start: int = 0) -> np.ndarray:
-    """Euclidean FPS starting at `start`; ties go to the lowest index."""
+    """Euclidean FPS starting at `start`; ties go to the lowest index.  Each
+    new node can only lower the distance of points within the current
+    largest distance, so only that ball (found with a kd-tree) is updated."""
     N = pts.shape[0]
     n = min(n, N)
     idx = np.empty(n, np.int64)
     d = np.full(N, np.inf)
+    tree = cKDTree(pts)
     cur = start
     for s in range(n):
         idx[s] = cur
-        diff = pts - pts[cur]
-        np.minimum(d, np.einsum("ij,ij->i", diff, diff), out=d)
+        dmax = float(np.max(d))
+        if np.isfinite(dmax):
+            near = np.asarray(tree.query_ball_point(pts[cur], math.sqrt(dmax) * (1 + 1e-9) + 1e-300))
+        else:
+            near = np.arange(N)
+        if near.size:
+            diff = pts[near] - pts[cur]
+            d[near] = np.minimum(d[near], np.einsum("ij,ij->i", diff, diff))
         cur = int(np.argmax(d))
     return idx
 

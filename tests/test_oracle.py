@@ -463,3 +463,26 @@ def test_solver_forced_rejections_keep_monotone(small_pair):
         if e["aa_used"]:
             assert e["accepted"] is False
         assert e["E_after"] <= e["E_before"] * (1 + 1e-12)
+
+
+def test_anderson_trajectory_amplifies_perturbations_plain_mm_damps_them(small_pair):
+    """Sensitivity of Alg. 2 itself (not of any implementation): with the
+    same accept/reject decisions replayed, a 1e-7 perturbation of the start
+    grows along an Anderson-accelerated trajectory, while plain MM (a
+    contraction near the fixed point) shrinks it.  This bounds how long two
+    runs in different arithmetic can track each other step for step."""
+    prob = O.from_pair(small_pair)
+    p = O.Params(aa_m=5, max_total_iters=40)
+    res = O.solve(prob, p, log_evals=True)
+    fa = [e["accepted"] if e["aa_used"] else None for e in res["log"]]
+    rng = np.random.default_rng(1)
+    X0 = O.identity(prob.n_nodes) + 1e-7 * rng.standard_normal((prob.n_nodes, 4, 3))
+    r2 = O.solve(prob, p, X0=X0, force=fa, log_evals=True)
+    d0 = math.sqrt(((O.warp(prob, X0) - prob.src) ** 2).sum(1).mean())
+    d_aa = math.sqrt(((O.warp(prob, res["log"][-1]["X"]) - O.warp(prob, r2["log"][-1]["X"])) ** 2).sum(1).mean())
+    p0 = O.Params(aa_m=0, max_total_iters=40)
+    m0 = O.solve(prob, p0, log_evals=True)
+    m1 = O.solve(prob, p0, X0=X0, log_evals=True)
+    d_mm = math.sqrt(((O.warp(prob, m0["log"][-1]["X"]) - O.warp(prob, m1["log"][-1]["X"])) ** 2).sum(1).mean())
+    assert d_mm < d0
+    assert d_aa > 10 * d0
