@@ -46,10 +46,10 @@ def algorithmic_bytes(pair, T):
         # points once (v, e, w_a, influences), X, w_r, D, R; writes K, B, r, D^-1
         "assemble": N * (3 * T + 4 * T + k * (4 + T)) + 12 * T * n + nadj * 5 * T + 9 * T * n
                     + 16 * T * nnzb + 4 * nnzb + 4 * (n + 1) + 12 * T * n * 2 + 16 * T * n,
-        # K once, u read, w written
-        "cg_spmv": 16 * T * nnzb + 4 * nnzb + 4 * (n + 1) + 12 * T * n * 2,
-        # reads r u w p s x D^-1, writes p s x r u
-        "cg_update": 12 * T * n * 11 + 16 * T * n,
+        # one fused CG step: K and its column indices once; r u w s p x and D^-1 of the
+        # rows read; p x written and the next r u w s written
+        "cg_step": 16 * T * nnzb + 4 * nnzb + 4 * (n + 1) + 12 * T * n * 6 + 16 * T * n
+                   + 12 * T * n * 6,
         "residual64": 16 * T * nnzb + 4 * nnzb + 12 * 8 * n + 12 * T * n * 3,
     }
 
@@ -236,8 +236,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6, "launches": nl}
+    abw = ab
     stages = {k: {"ms_per_iter": v[0] / max(st_w["iters"], 1), "launches": v[1],
-                  "GBps": (ab[k] / (v[0] / v[1] * 1e-3) / 1e9) if k in ab else None}
+                  "GBps": (abw[k] / (v[0] / v[1] * 1e-3) / 1e9) if k in abw else None}
               for k, v in kt_w.items()}
     out = {
         "metric": "MM iterations/s at 200k points, FP32+refine vs plain; batched pairs/s at equal err",

@@ -140,10 +140,10 @@ struct Dyn {
     double* B;
     double* rvec;
     double* Dinv;
-    double* cg[7];     // x r u w p s rhs
-    double* part_ru;
-    double* part_rr;
-    double* part_wu;
+    double* cg[11];    // x p r0 r1 u0 u1 w0 w1 s0 s1 rhs
+    double* part_ru[2];
+    double* part_rr[2];
+    double* part_wu[2];
     double* part_bb;
     double* part_rr64;
     double* part_bb64;
@@ -243,10 +243,12 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(d.B, 12 * n);
     c.take(d.rvec, 12 * n);
     c.take(d.Dinv, 16 * n);
-    for (int q = 0; q < 7; ++q) c.take(d.cg[q], 12 * n);
-    c.take(d.part_ru, 3 * nnd);
-    c.take(d.part_rr, 3 * nnd);
-    c.take(d.part_wu, 3 * nnd);
+    for (int q = 0; q < 11; ++q) c.take(d.cg[q], 12 * n);
+    for (int q = 0; q < 2; ++q) {
+        c.take(d.part_ru[q], 3 * nnd);
+        c.take(d.part_rr[q], 3 * nnd);
+        c.take(d.part_wu[q], 3 * nnd);
+    }
     c.take(d.part_bb, 3 * nnd);
     c.take(d.part_rr64, 3 * nnd);
     c.take(d.part_bb64, 3 * nnd);
@@ -533,14 +535,16 @@ CgArgs<T> cg_args(amm_handle* h, const T* b, const T* bnorm, double rtol) {
     a.b = b;
     a.bnorm = bnorm;
     a.x = reinterpret_cast<T*>(d.cg[0]);
-    a.r = reinterpret_cast<T*>(d.cg[1]);
-    a.u = reinterpret_cast<T*>(d.cg[2]);
-    a.w = reinterpret_cast<T*>(d.cg[3]);
-    a.pv = reinterpret_cast<T*>(d.cg[4]);
-    a.sv = reinterpret_cast<T*>(d.cg[5]);
-    a.part_ru = d.part_ru;
-    a.part_rr = d.part_rr;
-    a.part_wu = d.part_wu;
+    a.pv = reinterpret_cast<T*>(d.cg[1]);
+    for (int q = 0; q < 2; ++q) {
+        a.r[q] = reinterpret_cast<T*>(d.cg[2 + q]);
+        a.u[q] = reinterpret_cast<T*>(d.cg[4 + q]);
+        a.w[q] = reinterpret_cast<T*>(d.cg[6 + q]);
+        a.s[q] = reinterpret_cast<T*>(d.cg[8 + q]);
+        a.part_ru[q] = d.part_ru[q];
+        a.part_rr[q] = d.part_rr[q];
+        a.part_wu[q] = d.part_wu[q];
+    }
     a.part_bb = d.part_bb;
     a.state = h->v.state;
     a.rtol2 = rtol * rtol;
@@ -582,15 +586,18 @@ struct SolveReport {
     std::vector<int> refine;
     std::vector<double> rel;   // worst final relative residual |B - K X| / |B| over the 3 columns
     bool not_spd = false;
+    int bad_pair = -1;
 };
 
-// CG over the pairs flagged PF_SOLVE until all their columns converged.
+// CG over the pairs flagged PF_SOLVE until all their columns converged; the
+// host checks the per-pair state every few steps.  Adds each pair's
+// iteration count to rep.
 template <typename T>
-amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int zero_x, int maxit, SolveReport& rep) {
+amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int maxit, SolveReport& rep) {
     const Layout& L = h->L;
     const int nt = L.n_nd_tiles;
     CgArgs<T> a = cg_args<T>(h, b, bnorm, rtol);
-    launch_cg_init<T>(a, nt, zero_x, h->stream, tmr(h));
+    launch_cg_init<T>(a, nt, h->stream, tmr(h));
     int it = 0;
     const int check = 8;
     for (; it < maxit; ++it) {
@@ -667,18 +674,20 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
     vec_op<T>(h, PF_SOLVE, 7);   // dx = 0
     if (sizeof(T) == 8) {
         // float64 CG on K dx = r
-        TRY(run_cg<T>(h, r, B, rtol, 1, maxit, rep));
+        TRY(run_cg<T>(h, r, B, rtol, maxit, rep));
         vec_op<T>(h, PF_SOLVE, 0, x, nullptr);
         TRY(true_residual<T>(h, nullptr, rep.rel));
         for (int p = 0; p < L.P; ++p) {
             if (!(h->dyn[p].flags & PF_SOLVE)) continue;
-            if ((h->h_state[2 * p].breakdown | h->h_state[2 * p + 1].breakdown) && rep.rel[p] > 1e-3)
+            if ((h->h_state[2 * p].breakdown | h->h_state[2 * p + 1].breakdown) && rep.rel[p] > 1e-3) {
                 rep.not_spd = true;
+                rep.bad_pair = p;
+            }
         }
         return AMM_OK;
     }
     // float32 CG inside float64 iterative refinement
-    T* rhs = reinterpret_cast<T*>(d.cg[6]);
+    T* rhs = reinterpret_cast<T*>(d.cg[10]);
     std::vector<int32_t> saved(L.P);
     for (int p = 0; p < L.P; ++p) saved[p] = h->dyn[p].flags;
     std::vector<double> prev(L.P, std::numeric_limits<double>::infinity()), rel;
@@ -701,15 +710,17 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
         }
         if (!any) break;
         TRY(push_dyn(h));
-        TRY(run_cg<T>(h, rhs, nullptr, 1e-4, 1, maxit, rep));
+        TRY(run_cg<T>(h, rhs, nullptr, 1e-4, maxit, rep));
         vec_op<T>(h, PF_SOLVE, 1, x, nullptr);   // dx += correction
     }
     for (int p = 0; p < L.P; ++p) {
         h->dyn[p].flags = saved[p];
         h->dyn[p].cg_rtol = 0;
         if ((h->dyn[p].flags & PF_SOLVE) && rep.rel[p] > 1e-3 &&
-            (h->h_state[2 * p].breakdown | h->h_state[2 * p + 1].breakdown))
+            (h->h_state[2 * p].breakdown | h->h_state[2 * p + 1].breakdown)) {
             rep.not_spd = true;
+            rep.bad_pair = p;
+        }
     }
     return push_dyn(h);
 }
@@ -818,7 +829,11 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
         TRY(push_dyn(h));
         launch_assemble<T>(asm_args<T>(h), L.ntot, h->stream, tmr(h));
         TRY(linear_solve<T>(h, rtol, maxit, rep));
-        if (rep.not_spd) return fail(h, AMM_ERR_NOT_SPD, "K is not positive definite (CG breakdown)");
+        if (rep.not_spd)
+            return fail(h, AMM_ERR_NOT_SPD,
+                        "K is not positive definite (CG breakdown) in pair " + std::to_string(rep.bad_pair) +
+                            " at MM iteration " + std::to_string(ps[rep.bad_pair].total) + ", relative residual " +
+                            std::to_string(rep.rel[rep.bad_pair]));
         AaArgs<T> aa{};
         aa.nd_tiles = h->v.nd_tiles;
         aa.dyn = h->v.dyn;

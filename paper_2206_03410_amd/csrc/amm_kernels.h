@@ -49,7 +49,7 @@ struct EvalArgs {
     V* qw[2];                // (e_i = v_hat_i - u_rho(i), w_a,i)
     T* wr[2];                // w_r per directed entry
     V* Dres[2];              // (D, |D|^2) per directed entry
-    T* R[2];                 // closest rotations, row-major 3x3
+    T* R[2];                 // proj(A_j) - A_j, row-major 3x3
     double* pt_part;
     double* pt_max;
     double* eg_part;
@@ -109,14 +109,14 @@ struct CgArgs {
     const T* b;
     const T* bnorm;          // vector whose norm scales the stopping test (null: b)
     T* x;
-    T* r;
-    T* u;
-    T* w;
     T* pv;
-    T* sv;
-    double* part_ru;
-    double* part_rr;
-    double* part_wu;
+    T* r[2];                 // r, u, w, s double-buffered by step parity
+    T* u[2];
+    T* w[2];
+    T* s[2];
+    double* part_ru[2];      // tile partials of the vectors of each parity
+    double* part_wu[2];
+    double* part_rr[2];
     double* part_bb;
     CgState* state;          // [P][2]
     double rtol2;
@@ -195,8 +195,10 @@ void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_
                  int P, hipStream_t s, KernelTimer* tm);
 template <typename T>
 void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTimer* tm);
+// CG on K x = b from x = 0 for the pairs flagged PF_SOLVE: the start
+// (r = b, u = M^{-1} r, w = K u), then one update + one product per step.
 template <typename T>
-void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, int zero_x, hipStream_t s, KernelTimer* tm);
+void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, hipStream_t s, KernelTimer* tm);
 template <typename T>
 void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm);
 template <typename T>

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <algorithm>
 #include <climits>
 
 #include "amm_kernels.h"
@@ -288,9 +289,14 @@ __device__ T proj_rot(const T A[3][3], T R[3][3]) {
     return e;
 }
 
+// Per node: closest rotation and |A_j - proj(A_j)|_F^2, in float64 for both
+// arithmetics (A_j is exact in float64): A_j lies within ~1e-3 of a rotation,
+// so float32 rounding of proj(A_j) would be amplified in the squared
+// difference.  Stores proj(A_j) - A_j (small, accurate in T) for the
+// assembly and the gradient.
 template <typename T>
 __global__ void __launch_bounds__(kNodeTile) k_eval_nodes(EvalArgs<T> a) {
-    __shared__ T sh[kNodeTile];
+    __shared__ double sh[kNodeTile];
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
     const int p = td.x;
@@ -298,18 +304,18 @@ __global__ void __launch_bounds__(kNodeTile) k_eval_nodes(EvalArgs<T> a) {
     if (!(dy.flags & PF_EVAL)) return;
     const int j = td.y + (int)threadIdx.x;
     const T* X = a.X[dy.eval_x];
-    T er = 0;
+    double er = 0;
     if (j < td.z) {
-        T A[3][3], R[3][3];
+        double A[3][3], R[3][3];
         for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) A[c][r] = X[12 * (size_t)j + 3 * r + c];
-        er = proj_rot<T>(A, R);
+            for (int c = 0; c < 3; ++c) A[c][r] = (double)X[12 * (size_t)j + 3 * r + c];
+        er = proj_rot<double>(A, R);
         T* Ro = a.R[dy.eval_dst] + 9 * (size_t)j;
         for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) Ro[3 * r + c] = R[r][c];
+            for (int c = 0; c < 3; ++c) Ro[3 * r + c] = (T)(R[r][c] - A[r][c]);
     }
-    const T tot = block_sum<T, kNodeTile>(er, sh);
-    if (threadIdx.x == 0) a.nd_part[tile] = (double)tot;
+    const double tot = block_sum<double, kNodeTile>(er, sh);
+    if (threadIdx.x == 0) a.nd_part[tile] = tot;
 }
 
 // Per pair: E = E_align + alpha E_reg + beta E_rot (Eq. 4) from the tile
@@ -343,6 +349,58 @@ __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
 
 // ---------------------------------------------------------------- assembly
 
+// Inverse of a symmetric positive definite 4x4 block (the block-Jacobi
+// preconditioner) through its Cholesky factor, fully unrolled; a
+// non-positive pivot falls back to the inverse of the diagonal.
+template <typename T>
+__device__ __forceinline__ void spd_inverse4(const T K[4][4], T* out) {
+    T L[4][4] = {};
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        T d = K[c][c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < c) d -= L[c][q] * L[c][q];
+        ok = ok && d > T(0);
+        const T lc = sqrt(fmax(d, T(1e-300)));
+        L[c][c] = lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (r > c) {
+                T v = K[r][c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < c) v -= L[r][q] * L[c][q];
+                L[r][c] = v / lc;
+            }
+    }
+    // W = L^{-1} (lower triangular), then K^{-1} = W^T W
+    T W[4][4] = {};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        W[c][c] = T(1) / L[c][c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (r > c) {
+                T v = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q >= c && q < r) v -= L[r][q] * W[q][c];
+                W[r][c] = v / L[r][r];
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            T v = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v += W[q][r] * W[q][c];
+            out[4 * r + c] = ok ? v : (r == c ? T(1) / fmax(fabs(K[r][r]), T(1e-30)) : T(0));
+        }
+}
+
 // Row j of K and B (Eq. 16) and of the residual r = B - K X^k, one wave per
 // node.  Alignment blocks K_jl = sum_i w_a,i w_ij w_il [v_i - p_j; 1]
 // [v_i - p_l; 1]^T are formed as moments anchored at p_j,
@@ -359,9 +417,10 @@ __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     using V = typename V4Of<T>::type;
-    constexpr int CM = (kMaxCols + 63) / 64;
+    __shared__ int scol[kMaxCols];            // the row's column node ids (sorted)
+    __shared__ T sacc[kMaxCols][10];          // moment sums per column block
     __shared__ T smom[64][10];
-    __shared__ int snid[64][kMaxK];
+    __shared__ int spos[64][kMaxK];           // column position of each influence of a staged point
     __shared__ T swgt[64][kMaxK];
     const int j = blockIdx.x;
     const int lane = threadIdx.x;
@@ -373,21 +432,20 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     const T* wr = a.wr[cur];
     const V pj = a.nodes[j];
     const int kb = a.K_ptr[j], ke = a.K_ptr[j + 1];
-    const int nch = (ke - kb + 63) / 64;
+    const int ncol = ke - kb;
     const int k = a.k;
-    int lcol[CM];
-    T acc[CM][10];
+    for (int c = lane; c < ncol; c += 64) {
+        scol[c] = a.K_col[kb + c];
 #pragma unroll
-    for (int c = 0; c < CM; ++c) {
-        const int pos = kb + lane + 64 * c;
-        lcol[c] = pos < ke ? a.K_col[pos] : -1;
-#pragma unroll
-        for (int m = 0; m < 10; ++m) acc[c][m] = 0;
+        for (int m = 0; m < 10; ++m) sacc[c][m] = 0;
     }
+    // lane l scatters moment m = l % 10 of influence b = l / 10 (60 lanes for k = 6)
+    const int my_b = lane / 10, my_m = lane % 10;
     T racc[12];
 #pragma unroll
     for (int m = 0; m < 12; ++m) racc[m] = 0;
     const int e0 = a.pj_ptr[j], e1 = a.pj_ptr[j + 1];
+    __syncthreads();
     for (int base = e0; base < e1; base += 64) {
         const int e = base + lane;
         if (e < e1) {
@@ -421,30 +479,30 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
             racc[9] += c * q.x;
             racc[10] += c * q.y;
             racc[11] += c * q.z;
-            for (int b = 0; b < kMaxK; ++b) {
-                snid[lane][b] = b < k ? a.iidx[(size_t)b * a.Ntot + i] : -1;
-                swgt[lane][b] = b < k ? a.iw[(size_t)b * a.Ntot + i] : T(0);
-            }
-        } else {
-            for (int m = 0; m < 10; ++m) smom[lane][m] = 0;
-            for (int b = 0; b < kMaxK; ++b) {
-                snid[lane][b] = -1;
-                swgt[lane][b] = 0;
+            for (int b = 0; b < k; ++b) {
+                const int nid = a.iidx[(size_t)b * a.Ntot + i];
+                int lo = 0, hi = ncol - 1;   // the node is in the row's pattern by construction
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (scol[mid] < nid)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                spos[lane][b] = lo;
+                swgt[lane][b] = a.iw[(size_t)b * a.Ntot + i];
             }
         }
         __syncthreads();
+        // scatter, one staged point after the other: for a fixed point the k
+        // influences land in k distinct column blocks, so the 10k lanes write
+        // distinct cells; the order over points is fixed
         const int cnt = min(64, e1 - base);
-        for (int t = 0; t < cnt; ++t) {
-            for (int b = 0; b < k; ++b) {
-                const int nid = snid[t][b];
-#pragma unroll
-                for (int c = 0; c < CM; ++c) {
-                    if (c < nch && nid == lcol[c]) {
-                        const T w = swgt[t][b];
-#pragma unroll
-                        for (int m = 0; m < 10; ++m) acc[c][m] += w * smom[t][m];
-                    }
-                }
+        if (my_b < k) {
+            for (int t = 0; t < cnt; ++t) {
+                T* cell = &sacc[spos[t][my_b]][my_m];
+                *cell += swgt[t][my_b] * smom[t][my_m];
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this write lands before the next read
             }
         }
         __syncthreads();
@@ -458,13 +516,11 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     T kx[12];
 #pragma unroll
     for (int m = 0; m < 12; ++m) kx[m] = 0;
-#pragma unroll
-    for (int c = 0; c < CM; ++c) {
-        const int pos = kb + lane + 64 * c;
-        if (c >= nch || pos >= ke) continue;
-        const int l = lcol[c];
+    for (int cp = lane; cp < ncol; cp += 64) {
+        const int pos = kb + cp;
+        const int l = scol[cp];
         const V pl = a.nodes[l];
-        const T* m = acc[c];
+        const T* m = sacc[cp];
         const T S[4][4] = {{m[0], m[1], m[2], m[3]},
                            {m[1], m[4], m[5], m[6]},
                            {m[2], m[5], m[7], m[8]},
@@ -500,41 +556,7 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
                 Kb[3][3] += om_e;
             }
             for (int s = 0; s < 3; ++s) Kb[s][s] += beta;
-            // block-Jacobi: inverse of the diagonal block (Gauss-Jordan, partial pivoting)
-            T Mx[4][8];
-            for (int r = 0; r < 4; ++r)
-                for (int s = 0; s < 4; ++s) {
-                    Mx[r][s] = Kb[r][s];
-                    Mx[r][4 + s] = r == s ? T(1) : T(0);
-                }
-            bool ok = true;
-            for (int c2 = 0; c2 < 4; ++c2) {
-                int piv = c2;
-                for (int r = c2 + 1; r < 4; ++r)
-                    if (fabs(Mx[r][c2]) > fabs(Mx[piv][c2])) piv = r;
-                if (!(fabs(Mx[piv][c2]) > T(0))) {
-                    ok = false;
-                    break;
-                }
-                if (piv != c2)
-                    for (int s = 0; s < 8; ++s) {
-                        T tmp = Mx[c2][s];
-                        Mx[c2][s] = Mx[piv][s];
-                        Mx[piv][s] = tmp;
-                    }
-                const T invp = T(1) / Mx[c2][c2];
-                for (int s = 0; s < 8; ++s) Mx[c2][s] *= invp;
-                for (int r = 0; r < 4; ++r)
-                    if (r != c2) {
-                        const T f = Mx[r][c2];
-                        for (int s = 0; s < 8; ++s) Mx[r][s] -= f * Mx[c2][s];
-                    }
-            }
-            T* Di = a.Dinv + 16 * (size_t)j;
-            for (int r = 0; r < 4; ++r)
-                for (int s = 0; s < 4; ++s)
-                    Di[4 * r + s] = ok ? Mx[r][4 + s]
-                                       : (r == s ? T(1) / fmax(fabs(Kb[r][r]), T(1e-30)) : T(0));
+            spd_inverse4<T>(Kb, a.Dinv + 16 * (size_t)j);
         }
         T* Ko = a.Kval + 16 * (size_t)pos;
         for (int r = 0; r < 4; ++r)
@@ -572,10 +594,10 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
             rj[10] += f2 * D2.y;
             rj[11] += f2 * D2.z;
         }
-        const T* Rj = a.R[cur] + 9 * (size_t)j;
-        const T* Xj = Xk + 12 * (size_t)j;
+        // rotation term: beta J (Z - X^k), row r of block j = beta (proj(A_j) - A_j)^T
+        const T* Rd = a.R[cur] + 9 * (size_t)j;
         for (int r = 0; r < 3; ++r)
-            for (int c2 = 0; c2 < 3; ++c2) rj[3 * r + c2] += beta * (Rj[3 * c2 + r] - Xj[3 * r + c2]);
+            for (int c2 = 0; c2 < 3; ++c2) rj[3 * r + c2] += beta * Rd[3 * c2 + r];
         T* Ro = a.rvec + 12 * (size_t)j;
         T* Bo = a.B + 12 * (size_t)j;
         for (int m2 = 0; m2 < 12; ++m2) {
@@ -587,234 +609,284 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
 
 // ---------------------------------------------------------------- CG (Chronopoulos-Gear)
 
-// Vectors are [n][4][3]; each node row is handled by 4 consecutive threads
-// (thread r owns row r of the 4x3 block), 64 rows per 256-thread tile.
+// Vectors are [n][4][3] like X.  One kernel per CG step over solver tiles of
+// 16 node rows, 256 threads (16 lanes per row).  A step needs the new u of
+// every column node of its rows; instead of a separate launch after the
+// update, each lane recomputes u_l for the column block it multiplies from
+// the previous step's r, w, s (read-only in this step: r, u, w, s and the
+// partials are double-buffered by step parity).  The recomputation uses the
+// same operations as the owner's update, so both give identical values.
 
 template <typename T>
-__device__ __forceinline__ void spmv_row(const CgArgs<T>& a, int j, int r, const T* x, T out[3]) {
-    out[0] = out[1] = out[2] = 0;
-    const int kb = a.K_ptr[j], ke = a.K_ptr[j + 1];
-    for (int pos = kb; pos < ke; ++pos) {
-        const int l = a.K_col[pos];
-        const T* kr = a.Kval + 16 * (size_t)pos + 4 * r;
-        const T* xl = x + 12 * (size_t)l;
-        const T k0 = kr[0], k1 = kr[1], k2 = kr[2], k3 = kr[3];
+struct CgVec {
+    T v[12];
+};
+
+// Pair sums of the tile partials (lanes over tiles, fixed order) -> red[12]:
+// (r,u), (w,u), (r,r), (n,n) per column.
+template <typename T>
+__device__ __forceinline__ void cg_pair_sums(const CgArgs<T>& a, const PairInfo& pi, int par, double* red,
+                                             double (*wred)[12]) {
+    double v[12];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] += k0 * xl[c] + k1 * xl[3 + c] + k2 * xl[6 + c] + k3 * xl[9 + c];
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void reduce3_store(T v0, T v1, T v2, T* sh, double* dst) {
-    const T s0 = block_sum<T, 4 * kNodeTile>(v0, sh);
-    const T s1 = block_sum<T, 4 * kNodeTile>(v1, sh);
-    const T s2 = block_sum<T, 4 * kNodeTile>(v2, sh);
-    if (threadIdx.x == 0) {
-        dst[0] = (double)s0;
-        dst[1] = (double)s1;
-        dst[2] = (double)s2;
-    }
-}
-
-// r = b - K x0 (x0 = 0 when zero_x), u = M^{-1} r; partials (r,u), (r,r) and
-// (n,n) of the vector n that scales the stopping test (b, or a.bnorm).
-template <typename T>
-__global__ void __launch_bounds__(4 * kNodeTile) k_cg_init(CgArgs<T> a, int zero_x) {
-    __shared__ T sh[4 * kNodeTile];
-    __shared__ T rs[kNodeTile][4][3];
-    const int tile = blockIdx.x;
-    const int4 td = a.nd_tiles[tile];
-    const int p = td.x;
-    if (!(a.dyn[p].flags & PF_SOLVE)) return;
-    const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
-    const int j = td.y + lr;
-    T rv[3] = {0, 0, 0}, bv[3] = {0, 0, 0};
-    if (j < td.z) {
-        T kx[3] = {0, 0, 0};
-        if (!zero_x) spmv_row(a, j, r, a.x, kx);
+    for (int m = 0; m < 12; ++m) v[m] = 0;
+    for (int t = threadIdx.x; t < pi.nd_ntile; t += blockDim.x) {
+        const size_t o = 3 * (size_t)(pi.nd_tile0 + t);
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T bc = a.b[12 * (size_t)j + 3 * r + c];
-            bv[c] = a.bnorm ? a.bnorm[12 * (size_t)j + 3 * r + c] : bc;
-            rv[c] = bc - kx[c];
-            a.r[12 * (size_t)j + 3 * r + c] = rv[c];
-            if (zero_x) a.x[12 * (size_t)j + 3 * r + c] = 0;
+            v[c] += a.part_ru[par][o + c];
+            v[3 + c] += a.part_wu[par][o + c];
+            v[6 + c] += a.part_rr[par][o + c];
+            v[9 + c] += a.part_bb[o + c];
         }
     }
-    for (int c = 0; c < 3; ++c) rs[lr][r][c] = rv[c];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) v[m] = wave_sum(v[m]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int m = 0; m < 12; ++m) wred[threadIdx.x >> 6][m] = v[m];
     __syncthreads();
-    T uv[3] = {0, 0, 0};
-    if (j < td.z) {
-        const T* Di = a.Dinv + 16 * (size_t)j + 4 * r;
-        for (int c = 0; c < 3; ++c) {
-            uv[c] = Di[0] * rs[lr][0][c] + Di[1] * rs[lr][1][c] + Di[2] * rs[lr][2][c] + Di[3] * rs[lr][3][c];
-            a.u[12 * (size_t)j + 3 * r + c] = uv[c];
-        }
-    }
-    reduce3_store(rv[0] * uv[0], rv[1] * uv[1], rv[2] * uv[2], sh, a.part_ru + 3 * tile);
-    reduce3_store(rv[0] * rv[0], rv[1] * rv[1], rv[2] * rv[2], sh, a.part_rr + 3 * tile);
-    reduce3_store(bv[0] * bv[0], bv[1] * bv[1], bv[2] * bv[2], sh, a.part_bb + 3 * tile);
-    if (threadIdx.x < 3 && tile == a.info[p].nd_tile0) {
-        CgState* st = a.state + 2 * (size_t)p;
-        st[0].conv[threadIdx.x] = 0;
-        st[1].conv[threadIdx.x] = 0;
-        if (threadIdx.x == 0) {
-            st[0].iters = st[1].iters = 0;
-            st[0].breakdown = st[1].breakdown = 0;
-        }
-    }
+    if (threadIdx.x < 12) red[threadIdx.x] = ((wred[0][threadIdx.x] + wred[1][threadIdx.x]) + wred[2][threadIdx.x]) +
+                                             wred[3][threadIdx.x];
+    __syncthreads();
 }
 
-// w = K u; partial (w, u).  Skipped for pairs whose three columns converged.
+// u_l of step it+1 from the step-it vectors of node l:
+// r' = r - alpha (w + beta s), u' = D_l^{-1} r' (columns with active = 0 keep r).
 template <typename T>
-__global__ void __launch_bounds__(4 * kNodeTile) k_cg_spmv(CgArgs<T> a, int it) {
-    __shared__ T sh[4 * kNodeTile];
-    const int tile = blockIdx.x;
-    const int4 td = a.nd_tiles[tile];
-    const int p = td.x;
-    if (!(a.dyn[p].flags & PF_SOLVE)) return;
-    if (it >= 0) {
-        const CgState& st = a.state[2 * (size_t)p + (it & 1)];
-        if (st.conv[0] && st.conv[1] && st.conv[2]) return;
-    }
-    const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
-    const int j = td.y + lr;
-    T wv[3] = {0, 0, 0}, uv[3] = {0, 0, 0};
-    if (j < td.z) {
-        spmv_row(a, j, r, a.u, wv);
-        for (int c = 0; c < 3; ++c) {
-            a.w[12 * (size_t)j + 3 * r + c] = wv[c];
-            uv[c] = a.u[12 * (size_t)j + 3 * r + c];
+__device__ __forceinline__ void cg_new_u(const CgArgs<T>& a, int l, int par, const T al[3], const T be[3],
+                                         const bool act[3], bool first, T u[12]) {
+    const size_t o = 12 * (size_t)l;
+    T rn[12];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+        const int c = m % 3;
+        const T r0 = a.r[par][o + m];
+        if (act[c]) {
+            const T sn = first ? a.w[par][o + m] : a.w[par][o + m] + be[c] * a.s[par][o + m];
+            rn[m] = r0 - al[c] * sn;
+        } else {
+            rn[m] = r0;
         }
     }
-    reduce3_store(wv[0] * uv[0], wv[1] * uv[1], wv[2] * uv[2], sh, a.part_wu + 3 * tile);
+    const T* Di = a.Dinv + 16 * (size_t)l;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            u[3 * q + c] = Di[4 * q] * rn[c] + Di[4 * q + 1] * rn[3 + c] + Di[4 * q + 2] * rn[6 + c] +
+                           Di[4 * q + 3] * rn[9 + c];
 }
 
-// One Chronopoulos-Gear step: scalars from the partials of the previous
-// step, p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s,
-// u = M^{-1} r; partials (r,u), (r,r).  Columns whose relative residual
-// reached rtol (or that broke down) stay frozen.
+// One CG step (it >= 0), or the start (it = -1: r = b, u = M^{-1} b, w = K u,
+// x = 0).  Writes the new r, u, w, s into buffer (it+1) & 1 (the start into
+// buffer 0) and the tile partials of the new vectors.
 template <typename T>
-__global__ void __launch_bounds__(4 * kNodeTile) k_cg_update(CgArgs<T> a, int it) {
-    __shared__ T sh[4 * kNodeTile];
-    __shared__ T rs[kNodeTile][4][3];
+__global__ void __launch_bounds__(16 * kNodeTile) k_cg_step(CgArgs<T> a, int it) {
+    __shared__ double red[12];
+    __shared__ double wred[4][12];
     __shared__ double scal[3][3];   // alpha, beta, active
-    __shared__ double red[12];      // pair sums: (r,u), (w,u), (r,r), (n,n) per column
     __shared__ int brk_mask;
+    __shared__ T rs[kNodeTile][12];
+    __shared__ T ys[kNodeTile][12];
+    __shared__ T part[4][9];
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
     const int p = td.x;
     const PairDyn& dy = a.dyn[p];
     if (!(dy.flags & PF_SOLVE)) return;
     const PairInfo& pi = a.info[p];
-    const CgState& prv = a.state[2 * (size_t)p + ((it + 1) & 1)];
-    {
-        // pair-level sums of the tile partials: lane l takes tiles l, l+64, ...,
-        // then a fixed butterfly (every block of the pair gets the same values)
-        const int lane = threadIdx.x;
-        double v[12];
-#pragma unroll
-        for (int m = 0; m < 12; ++m) v[m] = 0;
-        for (int t = lane; t < pi.nd_ntile; t += 64) {
-            const size_t o = 3 * (size_t)(pi.nd_tile0 + t);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                v[c] += a.part_ru[o + c];
-                v[3 + c] += a.part_wu[o + c];
-                v[6 + c] += a.part_rr[o + c];
-                v[9 + c] += a.part_bb[o + c];
-            }
+    const bool start = it < 0;
+    const int par = start ? 0 : (it & 1);          // buffer read
+    const int nxt = start ? 0 : ((it + 1) & 1);    // buffer written
+    if (!start) {
+        const CgState& prv = a.state[2 * (size_t)p + ((it + 1) & 1)];
+        if (prv.conv[0] && prv.conv[1] && prv.conv[2]) {
+            // converged before this step: x is final and no later step reads the
+            // vectors; carry the state to this step's slot
+            if (threadIdx.x == 0 && tile == pi.nd_tile0) a.state[2 * (size_t)p + (it & 1)] = prv;
+            return;
         }
-#pragma unroll
-        for (int m = 0; m < 12; ++m) v[m] = wave_sum(v[m]);
-        if (lane == 0) {
-#pragma unroll
-            for (int m = 0; m < 12; ++m) red[m] = v[m];
-            brk_mask = 0;
-        }
-    }
-    __syncthreads();
-    const double rtol2 = dy.cg_rtol > 0 ? dy.cg_rtol * dy.cg_rtol : a.rtol2;
-    if (threadIdx.x < 3) {
-        const int c = threadIdx.x;
-        const double gam = red[c];
-        const double del = red[3 + c];
-        const double rr = red[6 + c];
-        const double bb = red[9 + c];
-        int conv = prv.conv[c];
-        int brk = 0;
-        double al = 0, be = 0;
-        if (!conv) {
-            if (rr <= rtol2 * bb || bb == 0.0) {
-                conv = 1;
-            } else if (it == 0) {
-                al = gam / del;
-            } else {
-                be = gam / prv.gamma[c];
-                al = gam / (del - be * gam / prv.alpha[c]);
+        cg_pair_sums(a, pi, par, red, wred);
+        if (threadIdx.x == 0) brk_mask = 0;
+        __syncthreads();
+        const double rtol2 = dy.cg_rtol > 0 ? dy.cg_rtol * dy.cg_rtol : a.rtol2;
+        if (threadIdx.x < 3) {
+            const int c = threadIdx.x;
+            const double gam = red[c], del = red[3 + c], rr = red[6 + c], bb = red[9 + c];
+            int conv = prv.conv[c];
+            int brk = 0;
+            double al = 0, be = 0;
+            if (!conv) {
+                if (rr <= rtol2 * bb || bb == 0.0) {
+                    conv = 1;
+                } else if (it == 0) {
+                    al = gam / del;
+                } else {
+                    be = gam / prv.gamma[c];
+                    al = gam / (del - be * gam / prv.alpha[c]);
+                }
+                if (!conv && !(al > 0.0 && gam > 0.0 && al < 1e300)) {
+                    conv = 1;
+                    brk = 1;
+                    al = be = 0;
+                }
             }
-            if (!conv && !(al > 0.0 && gam > 0.0 && al < 1e300)) {
-                conv = 1;
-                brk = 1;
-                al = be = 0;
+            scal[c][0] = al;
+            scal[c][1] = be;
+            scal[c][2] = conv ? 0.0 : 1.0;
+            if (tile == pi.nd_tile0) {
+                CgState& st = a.state[2 * (size_t)p + (it & 1)];
+                st.alpha[c] = al;
+                st.gamma[c] = gam;
+                st.rr[c] = rr;
+                st.bb[c] = bb;
+                st.conv[c] = conv;
             }
+            if (brk) atomicOr(&brk_mask, 1 << c);
         }
-        scal[c][0] = al;
-        scal[c][1] = be;
-        scal[c][2] = conv ? 0.0 : 1.0;
-        if (tile == pi.nd_tile0) {
+        __syncthreads();
+        if (threadIdx.x == 0 && tile == pi.nd_tile0) {
             CgState& st = a.state[2 * (size_t)p + (it & 1)];
-            st.alpha[c] = al;
-            st.gamma[c] = gam;
-            st.rr[c] = rr;
-            st.bb[c] = bb;
-            st.conv[c] = conv;
+            const bool any = scal[0][2] != 0.0 || scal[1][2] != 0.0 || scal[2][2] != 0.0;
+            st.iters = prv.iters + (any ? 1 : 0);
+            st.breakdown = prv.breakdown | brk_mask;
         }
-        if (brk) atomicOr(&brk_mask, 1 << c);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && tile == pi.nd_tile0) {
-        CgState& st = a.state[2 * (size_t)p + (it & 1)];
-        const bool any = scal[0][2] != 0.0 || scal[1][2] != 0.0 || scal[2][2] != 0.0;
-        st.iters = prv.iters + (any ? 1 : 0);
-        st.breakdown = prv.breakdown | brk_mask;
-    }
-    const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
-    const int j = td.y + lr;
-    T rv[3] = {0, 0, 0};
-    if (j < td.z) {
-        for (int c = 0; c < 3; ++c) {
-            const size_t o = 12 * (size_t)j + 3 * r + c;
-            rv[c] = a.r[o];
-            if (scal[c][2] != 0.0) {
-                const T al = (T)scal[c][0], be = (T)scal[c][1];
-                const T pn = it == 0 ? a.u[o] : a.u[o] + be * a.pv[o];
-                const T sn = it == 0 ? a.w[o] : a.w[o] + be * a.sv[o];
-                a.pv[o] = pn;
-                a.sv[o] = sn;
-                a.x[o] += al * pn;
-                rv[c] -= al * sn;
-                a.r[o] = rv[c];
+    } else {
+        if (threadIdx.x < 3) {
+            scal[threadIdx.x][0] = scal[threadIdx.x][1] = 0;
+            scal[threadIdx.x][2] = 1.0;
+        }
+        if (threadIdx.x < 3 && tile == pi.nd_tile0) {
+            CgState* st = a.state + 2 * (size_t)p;
+            st[0].conv[threadIdx.x] = 0;
+            st[1].conv[threadIdx.x] = 0;
+            if (threadIdx.x == 0) {
+                st[0].iters = st[1].iters = 0;
+                st[0].breakdown = st[1].breakdown = 0;
             }
         }
+        __syncthreads();
     }
-    for (int c = 0; c < 3; ++c) rs[lr][r][c] = rv[c];
-    __syncthreads();
-    T uv[3] = {0, 0, 0};
-    if (j < td.z) {
-        const T* Di = a.Dinv + 16 * (size_t)j + 4 * r;
-        for (int c = 0; c < 3; ++c) {
-            const size_t o = 12 * (size_t)j + 3 * r + c;
-            if (scal[c][2] != 0.0) {
-                uv[c] = Di[0] * rs[lr][0][c] + Di[1] * rs[lr][1][c] + Di[2] * rs[lr][2][c] +
-                        Di[3] * rs[lr][3][c];
-                a.u[o] = uv[c];
+    T al[3], be[3];
+    bool act[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        al[c] = (T)scal[c][0];
+        be[c] = (T)scal[c][1];
+        act[c] = scal[c][2] != 0.0;
+    }
+    const bool first = it <= 0;
+    const int row = threadIdx.x >> 4, lane = threadIdx.x & 15;
+    const int j = td.y + row;
+    const bool live = j < td.z;
+    // own rows, element m = lane < 12: p, s, x, r
+    if (live && lane < 12) {
+        const size_t o = 12 * (size_t)j + lane;
+        const int c = lane % 3;
+        T rn;
+        if (start) {
+            rn = a.b[o];
+            a.x[o] = 0;
+            a.s[nxt][o] = 0;
+        } else if (act[c]) {
+            const T pn = first ? a.u[par][o] : a.u[par][o] + be[c] * a.pv[o];
+            const T sn = first ? a.w[par][o] : a.w[par][o] + be[c] * a.s[par][o];
+            a.pv[o] = pn;
+            a.s[nxt][o] = sn;
+            a.x[o] += al[c] * pn;
+            rn = a.r[par][o] - al[c] * sn;
+        } else {
+            rn = a.r[par][o];
+            a.s[nxt][o] = a.s[par][o];
+        }
+        a.r[nxt][o] = rn;
+        rs[row][lane] = rn;
+    }
+    // w = K u' with u' recomputed for every column block
+    T y[12];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) y[m] = 0;
+    if (live) {
+        const int ke = a.K_ptr[j + 1];
+        for (int pos = a.K_ptr[j] + lane; pos < ke; pos += 16) {
+            const int l = a.K_col[pos];
+            T ul[12];
+            if (start) {
+                const T* bl = a.b + 12 * (size_t)l;
+                const T* Di = a.Dinv + 16 * (size_t)l;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        ul[3 * q + c] = Di[4 * q] * bl[c] + Di[4 * q + 1] * bl[3 + c] + Di[4 * q + 2] * bl[6 + c] +
+                                        Di[4 * q + 3] * bl[9 + c];
             } else {
-                uv[c] = a.u[o];
+                cg_new_u(a, l, par, al, be, act, first, ul);
             }
+            const T* kb = a.Kval + 16 * (size_t)pos;
+            T kv[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) kv[m] = kb[m];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    y[3 * q + c] += kv[4 * q] * ul[c] + kv[4 * q + 1] * ul[3 + c] + kv[4 * q + 2] * ul[6 + c] +
+                                    kv[4 * q + 3] * ul[9 + c];
         }
     }
-    reduce3_store(rv[0] * uv[0], rv[1] * uv[1], rv[2] * uv[2], sh, a.part_ru + 3 * tile);
-    reduce3_store(rv[0] * rv[0], rv[1] * rv[1], rv[2] * rv[2], sh, a.part_rr + 3 * tile);
+#pragma unroll
+    for (int m = 0; m < 12; ++m)
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) y[m] += __shfl_xor(y[m], o, 16);
+    if (lane == 0)
+#pragma unroll
+        for (int m = 0; m < 12; ++m) ys[row][m] = y[m];
+    __syncthreads();
+    // own rows: u' = D^{-1} r', write u', w', partials of the new vectors
+    T pc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // (r,u), (w,u), (r,r) per column
+    if (live && lane < 12) {
+        const size_t o = 12 * (size_t)j + lane;
+        const int q = lane / 3, c = lane % 3;
+        const T* Di = a.Dinv + 16 * (size_t)j + 4 * q;
+        const T un = Di[0] * rs[row][c] + Di[1] * rs[row][3 + c] + Di[2] * rs[row][6 + c] + Di[3] * rs[row][9 + c];
+        const T wn = ys[row][lane];
+        a.u[nxt][o] = un;
+        a.w[nxt][o] = wn;
+        const T rn = rs[row][lane];
+        pc[c] = rn * un;
+        pc[3 + c] = wn * un;
+        pc[6 + c] = rn * rn;
+    }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) pc[m] = wave_sum(pc[m]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int m = 0; m < 9; ++m) part[threadIdx.x >> 6][m] = pc[m];
+    // the start also records (n,n) of the vector scaling the stopping test
+    T bn[3] = {0, 0, 0};
+    if (start) {
+        if (live && lane < 12) {
+            const size_t o = 12 * (size_t)j + lane;
+            const T v = a.bnorm ? a.bnorm[o] : a.b[o];
+            bn[lane % 3] = v * v;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bn[c] = wave_sum(bn[c]);
+    }
+    __syncthreads();
+    if (start && (threadIdx.x & 63) == 0)
+        for (int c = 0; c < 3; ++c) wred[threadIdx.x >> 6][c] = (double)bn[c];
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int m = threadIdx.x, c = m % 3;
+        const double v = (double)(((part[0][m] + part[1][m]) + part[2][m]) + part[3][m]);
+        double* dst = m < 3 ? a.part_ru[nxt] : (m < 6 ? a.part_wu[nxt] : a.part_rr[nxt]);
+        dst[3 * tile + c] = v;
+        if (start && m < 3)
+            a.part_bb[3 * tile + c] = ((wred[0][c] + wred[1][c]) + wred[2][c]) + wred[3][c];
+    }
 }
 
 // ---------------------------------------------------------------- iterative refinement
@@ -897,7 +969,7 @@ template <typename T>
 __global__ void k_aa_push(AaArgs<T> a) {
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
-    const PairDyn dy = a.dyn[td.x];
+    const PairDyn& dy = a.dyn[td.x];
     if (!(dy.flags & PF_SOLVE)) return;
     const size_t n12 = 12 * (size_t)a.ntot;
     T* G = a.G + (size_t)dy.aa_slot[0] * n12;
@@ -920,7 +992,7 @@ __global__ void __launch_bounds__(256) k_aa_gram(AaArgs<T> a) {
     __shared__ double sdf[AMM_MAX_AA_M + 1][12 * 32];
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
-    const PairDyn dy = a.dyn[td.x];
+    const PairDyn& dy = a.dyn[td.x];
     if (!(dy.flags & PF_SOLVE)) return;
     const int mk = dy.aa_mk;
     const int ng = mk * (mk + 1) / 2 + mk;
@@ -972,24 +1044,27 @@ __global__ void __launch_bounds__(256) k_aa_gram(AaArgs<T> a) {
 
 // Per pair: Gram matrix from the tile partials, Cholesky in float64; a
 // pivot <= 1e-14 * max diag falls back to theta = 0 (plain MM step).
-__global__ void k_aa_solve(AaSolveArgs a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.P) return;
+__global__ void __launch_bounds__(64) k_aa_solve(AaSolveArgs a) {
+    __shared__ double v[kAaParts];
+    const int p = blockIdx.x;
     const PairDyn dy = a.dyn[p];
     if (!(dy.flags & PF_SOLVE)) return;
     PairOut& out = a.out[p];
     const int mk = dy.aa_mk;
+    const PairInfo pi = a.info[p];
+    const int ng = mk * (mk + 1) / 2 + mk;
+    // pair sums of the tile partials: lanes over tiles, fixed butterfly
+    for (int g = 0; g < ng; ++g) {
+        double s = 0;
+        for (int t = threadIdx.x; t < pi.nd_ntile; t += 64) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) v[g] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     for (int x = 0; x < AMM_MAX_AA_M; ++x) out.theta[x] = 0;
     out.aa_used = 0;
     if (mk == 0) return;
-    const PairInfo pi = a.info[p];
-    const int ng = mk * (mk + 1) / 2 + mk;
-    double v[kAaParts];
-    for (int g = 0; g < ng; ++g) {
-        double s = 0;
-        for (int t = 0; t < pi.nd_ntile; ++t) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
-        v[g] = s;
-    }
     double G[AMM_MAX_AA_M][AMM_MAX_AA_M], rhs[AMM_MAX_AA_M], L[AMM_MAX_AA_M][AMM_MAX_AA_M];
     int cnt = 0;
     for (int x = 0; x < mk; ++x)
@@ -1034,7 +1109,7 @@ __global__ void k_aa_mix(AaArgs<T> a) {
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
     const int p = td.x;
-    const PairDyn dy = a.dyn[p];
+    const PairDyn& dy = a.dyn[p];
     if (!(dy.flags & PF_SOLVE)) return;
     const PairOut& out = a.out[p];
     const bool used = out.aa_used != 0;
@@ -1154,10 +1229,9 @@ __global__ void __launch_bounds__(64) k_grad_nodes(GradArgs<T> a) {
         acc[10] -= alpha * rr * f2 * D2.y;
         acc[11] -= alpha * rr * f2 * D2.z;
     }
-    const T* X = a.X + 12 * (size_t)j;
-    const T* Rj = a.R[src_set] + 9 * (size_t)j;
+    const T* Rd = a.R[src_set] + 9 * (size_t)j;   // proj(A_j) - A_j
     for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) acc[3 * r + c] += T(2) * beta * (X[3 * r + c] - Rj[3 * c + r]);
+        for (int c = 0; c < 3; ++c) acc[3 * r + c] -= T(2) * beta * Rd[3 * c + r];
     T* out = a.gX + 12 * (size_t)a.node_user[j];
     for (int m = 0; m < 12; ++m) out[m] = acc[m];
 }
@@ -1261,20 +1335,16 @@ void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTim
 }
 
 template <typename T>
-void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, int zero_x, hipStream_t s, KernelTimer* tm) {
+void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, hipStream_t s, KernelTimer* tm) {
     if (tm) tm->begin("cg_init", s);
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, zero_x);
-    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, -1);
+    hipLaunchKernelGGL(k_cg_step<T>, dim3(n_nd_tiles), dim3(16 * kNodeTile), 0, s, a, -1);
     if (tm) tm->end(s);
 }
 
 template <typename T>
 void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm) {
-    if (tm) tm->begin("cg_update", s);
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, it);
-    if (tm) tm->end(s);
-    if (tm) tm->begin("cg_spmv", s);
-    hipLaunchKernelGGL(k_cg_spmv<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, it);
+    if (tm) tm->begin("cg_step", s);
+    hipLaunchKernelGGL(k_cg_step<T>, dim3(n_nd_tiles), dim3(16 * kNodeTile), 0, s, a, it);
     if (tm) tm->end(s);
 }
 
@@ -1297,7 +1367,7 @@ void launch_aa(const AaArgs<T>& a, const AaSolveArgs& sa, int n_nd_tiles, hipStr
     if (tm) tm->begin("anderson", s);
     hipLaunchKernelGGL(k_aa_push<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a);
     hipLaunchKernelGGL(k_aa_gram<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_aa_solve, dim3(blocks_for(sa.P, 64)), dim3(64), 0, s, sa);
+    hipLaunchKernelGGL(k_aa_solve, dim3(sa.P), dim3(64), 0, s, sa);
     hipLaunchKernelGGL(k_aa_mix<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a);
     if (tm) tm->end(s);
 }
@@ -1341,7 +1411,7 @@ void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s) {
     template void launch_eval<T>(const EvalArgs<T>&, int, int, int, const FinalArgs&, int, hipStream_t,        \
                                  KernelTimer*);                                                               \
     template void launch_assemble<T>(const AsmArgs<T>&, int64_t, hipStream_t, KernelTimer*);                   \
-    template void launch_cg_init<T>(const CgArgs<T>&, int, int, hipStream_t, KernelTimer*);                    \
+    template void launch_cg_init<T>(const CgArgs<T>&, int, hipStream_t, KernelTimer*);                         \
     template void launch_cg_iter<T>(const CgArgs<T>&, int, int, hipStream_t, KernelTimer*);                    \
     template void launch_residual64<T>(const CgArgs<T>&, int, const T*, const T*, const double*, T*, double*,  \
                                        double*, hipStream_t, KernelTimer*);                                   \
