@@ -29,6 +29,7 @@ thread_local std::string g_last_error;
 
 const char* kVersion = "amm-gfx950 0.1";
 constexpr int kDynRing = 16;
+constexpr int kCgRing = 4;
 
 struct EventTimer final : KernelTimer {
     struct Rec {
@@ -282,6 +283,8 @@ struct amm_handle {
     int dyn_slot = 0;
     PairOut* h_out = nullptr;        // pinned
     CgState* h_state = nullptr;      // pinned
+    CgState* cg_ring = nullptr;      // pinned [kCgRing][2P] asynchronous copies of the CG state
+    hipEvent_t cg_ev[kCgRing] = {};
     size_t h_cap = 0;
     bool timing = false;
     EventTimer timer;
@@ -387,9 +390,14 @@ amm_status ensure_host(amm_handle* h, size_t P) {
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);
     if (h->dyn_pinned) (void)hipHostFree(h->dyn_pinned);
+    if (h->cg_ring) (void)hipHostFree(h->cg_ring);
     h->h_out = nullptr;
     h->h_state = nullptr;
     h->dyn_pinned = nullptr;
+    h->cg_ring = nullptr;
+    for (int s = 0; s < kCgRing; ++s)
+        if (!h->cg_ev[s]) HIPC(hipEventCreateWithFlags(&h->cg_ev[s], hipEventDisableTiming));
+    HIPC(hipHostMalloc((void**)&h->cg_ring, sizeof(CgState) * 2 * P * kCgRing));
     HIPC(hipHostMalloc((void**)&h->h_out, sizeof(PairOut) * P));
     HIPC(hipHostMalloc((void**)&h->h_state, sizeof(CgState) * 2 * P));
     HIPC(hipHostMalloc((void**)&h->dyn_pinned, sizeof(PairDyn) * kDynRing * P));
@@ -589,44 +597,69 @@ struct SolveReport {
     int bad_pair = -1;
 };
 
-// CG over the pairs flagged PF_SOLVE until all their columns converged; the
-// host checks the per-pair state every few steps.  Adds each pair's
-// iteration count to rep.
+// CG over the pairs flagged PF_SOLVE until all their columns converged.
+// The host never waits on the device inside the loop: every few steps it
+// queues an asynchronous copy of the per-pair CG state into a pinned ring
+// slot and polls the oldest slot's event; once a polled copy shows every
+// pair converged it stops launching (steps already queued return at once
+// for converged pairs).  Adds each pair's iteration count to rep.
 template <typename T>
 amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int maxit, SolveReport& rep) {
     const Layout& L = h->L;
     const int nt = L.n_nd_tiles;
+    const int P = L.P;
     CgArgs<T> a = cg_args<T>(h, b, bnorm, rtol);
     launch_cg_init<T>(a, nt, h->stream, tmr(h));
-    int it = 0;
-    const int check = 8;
-    for (; it < maxit; ++it) {
+    constexpr int kPoll = 8;
+    struct Pending {
+        int slot, it;
+    };
+    std::vector<Pending> pending;
+    int next_slot = 0;
+    auto converged_in = [&](int slot, int it) {
+        const CgState* st = h->cg_ring + (size_t)slot * 2 * P;
+        for (int p = 0; p < P; ++p) {
+            if (!(h->dyn[p].flags & PF_SOLVE)) continue;
+            const CgState& s2 = st[2 * p + (it & 1)];
+            if (!(s2.conv[0] && s2.conv[1] && s2.conv[2])) return false;
+        }
+        return true;
+    };
+    bool done = false;
+    int launched = 0;
+    for (int it = 0; it < maxit && !done; ++it) {
         launch_cg_iter<T>(a, nt, it, h->stream, tmr(h));
-        if ((it + 1) % check == 0 || it + 1 == maxit) {
-            HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * L.P, hipMemcpyDeviceToHost,
-                                h->stream));
-            HIPC(hipStreamSynchronize(h->stream));
-            bool all = true;
-            for (int p = 0; p < L.P && all; ++p) {
-                if (!(h->dyn[p].flags & PF_SOLVE)) continue;
-                const CgState& st = h->h_state[2 * p + (it & 1)];
-                if (!(st.conv[0] && st.conv[1] && st.conv[2])) all = false;
+        launched = it + 1;
+        if ((it + 1) % kPoll == 0) {
+            if ((int)pending.size() == kCgRing) {
+                // ring full: wait for the oldest copy
+                HIPC(hipEventSynchronize(h->cg_ev[pending.front().slot]));
             }
-            if (all) {
-                ++it;
-                break;
+            while (!pending.empty()) {
+                const hipError_t q = hipEventQuery(h->cg_ev[pending.front().slot]);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess) return fail(h, AMM_ERR_HIP, "hipEventQuery failed in the CG loop");
+                if (converged_in(pending.front().slot, pending.front().it)) done = true;
+                pending.erase(pending.begin());
             }
+            if (done) break;
+            const int slot = next_slot;
+            next_slot = (next_slot + 1) % kCgRing;
+            HIPC(hipMemcpyAsync(h->cg_ring + (size_t)slot * 2 * P, h->v.state, sizeof(CgState) * 2 * P,
+                                hipMemcpyDeviceToHost, h->stream));
+            HIPC(hipEventRecord(h->cg_ev[slot], h->stream));
+            pending.push_back({slot, it});
         }
     }
-    HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * L.P, hipMemcpyDeviceToHost, h->stream));
+    const int last = launched - 1;
+    HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * P, hipMemcpyDeviceToHost, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
     HIPC(hipGetLastError());
     if (h->timing) h->timer.collect();
-    if (it == 0) return AMM_OK;
-    const int last = (it - 1) & 1;
-    for (int p = 0; p < L.P; ++p) {
+    if (last < 0) return AMM_OK;
+    for (int p = 0; p < P; ++p) {
         if (!(h->dyn[p].flags & PF_SOLVE)) continue;
-        rep.cg_iters[p] += h->h_state[2 * p + last].iters;
+        rep.cg_iters[p] += h->h_state[2 * p + (last & 1)].iters;
     }
     return AMM_OK;
 }
@@ -1188,6 +1221,9 @@ void amm_destroy(amm_handle* h) {
     (void)hipStreamSynchronize(h->stream);
     for (int s = 0; s < kDynRing; ++s)
         if (h->dyn_ev[s]) (void)hipEventDestroy(h->dyn_ev[s]);
+    for (int s = 0; s < kCgRing; ++s)
+        if (h->cg_ev[s]) (void)hipEventDestroy(h->cg_ev[s]);
+    if (h->cg_ring) (void)hipHostFree(h->cg_ring);
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);
