@@ -159,9 +159,11 @@ amm_status amm_set_stream(amm_handle* h, void* hip_stream);
 /* ---------------------------------------------------------------- problem */
 
 /* Host-only validation of a problem given by HOST pointers (on_device = 0);
- * needs no GPU.  Checks sizes, finiteness (AMM_ERR_NONFINITE), index ranges
- * (AMM_ERR_INVALID_ARG), partition of unity of the weights within 1e-5 and a
- * connected node graph without duplicate or self edges (AMM_ERR_GRAPH). */
+ * needs no GPU.  Checks sizes and index ranges (AMM_ERR_INVALID_ARG),
+ * finiteness (AMM_ERR_NONFINITE), and the structure (AMM_ERR_GRAPH): distinct
+ * node indices, distinct influences per point with non-negative weights that
+ * sum to 1 within 1e-5, and a connected node graph without duplicate or self
+ * edges. */
 amm_status amm_check_problem(const amm_problem* p);
 
 /* Device bytes that amm_set_problems needs for these problems (a static
