@@ -263,7 +263,7 @@ const char* amm_last_error(const amm_handle* h);   /* h may be NULL: last global
 
 /* Kernel timing with HIP events recorded on the handle's stream around each
  * launch group (names: "eval_points", "eval_edges", "eval_nodes",
- * "energy_final", "assemble", "cg_init", "cg_update", "cg_spmv",
+ * "energy_final", "assemble", "cg_init", "cg_step",
  * "residual64", "anderson").  amm_enable_timing(h, 1, NULL) times every
  * group, (h, 1, name) only that group, (h, 0, NULL) stops; enabling clears
  * the totals.  amm_kernel_times returns, per group seen since, the summed

@@ -89,8 +89,10 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     if (i < td.z) {
         const V v = src[i];
         // v_hat (absolute, for the search) and, for the residual, the small
-        // parts sum_j w_ij ((A_j - I)(v_i - p_j) + t_j) and sum_j w_ij
-        T vx = 0, vy = 0, vz = 0, sx = 0, sy = 0, sz = 0, sw = 0;
+        // parts sum_j w_ij ((A_j - I)(v_i - p_j) + t_j) and sum_j w_ij - 1
+        // (the weights' sum in float64: exact for k <= 8 terms)
+        T vx = 0, vy = 0, vz = 0, sx = 0, sy = 0, sz = 0;
+        double sw = 0;
         for (int s = 0; s < a.k; ++s) {
             const int j = a.iidx[(size_t)s * a.Ntot + i];
             const T w = a.iw[(size_t)s * a.Ntot + i];
@@ -106,23 +108,27 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
             sx += w * gx;
             sy += w * gy;
             sz += w * gz;
-            sw += w;
+            sw += (double)w;
         }
+        const T sw1 = (T)(sw - 1.0);
         const int prev = dy.has_prev ? a.rho[cur][i] - (int)pi.tgt_off : -1;
         int bpos;
         T d2;
         nn_search<T>(pi, a.tgt, a.blo, a.bhi, vx, vy, vz, prev, bpos, d2);
         const V u = a.tgt[pi.tgt_off + bpos];
+        // e_i = v_hat_i - u_rho(i)
+        //     = sum_j w_ij ((A_j - I) d_ij + t_j) + (v_i - u) + (sum_j w_ij - 1) v_i
+        // (Eq. 2 rearranged): every operand is small, so e_i keeps its relative
+        // accuracy where v_hat_i - u would cancel; d^2 is taken from it
+        V q;
+        q.x = sx + (v.x - u.x) + sw1 * v.x;
+        q.y = sy + (v.y - u.y) + sw1 * v.y;
+        q.z = sz + (v.z - u.z) + sw1 * v.z;
+        d2 = sq3(q.x, q.y, q.z);
         const T inv = T(1) / (T(2) * (T)dy.nu_a * (T)dy.nu_a);
         const T t = d2 * inv;
         psi = -expm1(-t);
         const T wa = exp(-t) * inv;
-        // e_i = v_hat_i - u_rho(i) = sum_j w_ij ((A_j - I) d_ij + t_j) + (sum_j w_ij)(v_i - u)
-        // (Eq. 2 rearranged): every operand is small, so e_i keeps its relative accuracy
-        V q;
-        q.x = sx + sw * (v.x - u.x);
-        q.y = sy + sw * (v.y - u.y);
-        q.z = sz + sw * (v.z - u.z);
         q.w = wa;
         a.qw[dst][i] = q;
         a.rho[dst][i] = (int)pi.tgt_off + bpos;

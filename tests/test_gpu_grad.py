@@ -1,0 +1,201 @@
+"""Differentiable form: the hand-written adjoint behind the autograd wrapper,
+against the oracle's analytic gradient and FP64 central finite differences of
+the oracle's energy (100,000-point pair, 2,000 nodes, k = 4)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import amm_oracle as O
+from paper_2206_03410_amd import amm, synth
+from paper_2206_03410_amd.autograd import robust_energy
+from tests.helpers import Session, rounded
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(name):
+    print(f"[gpu-test] {name}", file=sys.stderr, flush=True)
+
+
+def _kdtree_nn(tgt):
+    # exact closest points from scipy's k-d tree (an independent library
+    # routine; the oracle's brute-force search is pinned against it)
+    from scipy.spatial import cKDTree
+    tree = cKDTree(tgt)
+
+    def nn(q, _tgt):
+        d, i = tree.query(q, k=2)
+        return i[:, 0].astype(np.int64), d[:, 0] ** 2, d[:, 1] ** 2
+    return nn
+
+
+def _scalars(prob, nn):
+    """Sec. 3.3.3 start values and Eq. (21) weights at X = I."""
+    p = O.Params()
+    _, d2, _ = nn(prob.src, prob.tgt)
+    nu_a, _, nu_r = O.initial_nu(prob, p, d2)
+    alpha, beta = O.term_weights(prob, p, nu_a, nu_r)
+    return nu_a, nu_r, alpha, beta
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_autograd_matches_entry_point(small_pair, prec):
+    _announce(f"test_autograd_matches_entry_point {prec}")
+    t_dt = torch.float64 if prec == "f64" else torch.float32
+    np_dt = np.float64 if prec == "f64" else np.float32
+    pr = rounded(small_pair, np_dt)
+    prob = O.from_pair(pr)
+    sc = _scalars(prob, _kdtree_nn(prob.tgt))
+    X0 = synth.perturbed_transforms(prob.n_nodes, 5, 0.01, 0.001)
+    with Session(pr, t_dt) as s:
+        X = torch.tensor(X0, dtype=t_dt, device="cuda:0", requires_grad=True)
+        V = torch.tensor(pr.src, dtype=t_dt, device="cuda:0", requires_grad=True)
+        E = robust_energy(s.h, X, V, nu_a=sc[0], nu_r=sc[1], alpha=sc[2], beta=sc[3])
+        (2.5 * E).backward()
+        gX = torch.empty_like(X)
+        gV = torch.empty_like(V)
+        e = amm.amm_energy_grad(s.h, X.detach(), V.detach(), *sc, gX, gV)
+        with torch.no_grad():
+            E2 = robust_energy(s.h, X, None, nu_a=sc[0], nu_r=sc[1], alpha=sc[2], beta=sc[3])
+        torch.cuda.synchronize()
+        assert E.item() == e[0] == E2.item()
+        assert torch.equal(X.grad, 2.5 * gX)
+        assert torch.equal(V.grad, 2.5 * gV)
+        # only X differentiated: no source gradient is formed
+        X.grad = None
+        E3 = robust_energy(s.h, X, None, nu_a=sc[0], nu_r=sc[1], alpha=sc[2], beta=sc[3])
+        E3.backward()
+        assert torch.equal(X.grad, gX)
+
+
+class _LocalEnergy:
+    """Terms of E (Eq. 4) that one coordinate of X or V can change, in FP64
+    with the oracle's primitives (exact closest points recomputed for the
+    affected points only)."""
+
+    def __init__(self, prob, X, V, sc, nn):
+        self.prob, self.X, self.V, self.nn = prob, X, V, nn
+        self.nu_a, self.nu_r, self.alpha, self.beta = sc
+        self.de = prob.dir_edges
+
+    def _align(self, X, V, pts):
+        vh = O.warp(self.prob, X, V)[pts]
+        rho, d2, _ = self.nn(vh, self.prob.tgt)
+        return math.fsum(O.welsch(d2, self.nu_a)), rho
+
+    def node_coord(self, j, r, c, h):
+        pts = np.nonzero((self.prob.infl_idx == j).any(1))[0]
+        eds = np.nonzero((self.de[:, 0] == j) | (self.de[:, 1] == j))[0]
+        vals, rhos = [], []
+        for sgn in (1.0, -1.0):
+            X = self.X.copy()
+            X[j, r, c] += sgn * h
+            ea, rho = self._align(X, self.V, pts)
+            D = O.reg_residuals(self.prob, X)[eds]
+            er = math.fsum(O.welsch((D ** 2).sum(1), self.nu_r))
+            _, erot = O.proj_rotation(X[j:j + 1, :3, :].transpose(0, 2, 1))
+            vals.append(ea + self.alpha * er + self.beta * float(erot[0]))
+            rhos.append(rho)
+        return (vals[0] - vals[1]) / (2 * h), np.array_equal(rhos[0], rhos[1])
+
+    def point_coord(self, i, c, h):
+        vals, rhos = [], []
+        for sgn in (1.0, -1.0):
+            V = self.V.copy()
+            V[i, c] += sgn * h
+            ea, rho = self._align(self.X, V, np.array([i]))
+            vals.append(ea)
+            rhos.append(rho)
+        return (vals[0] - vals[1]) / (2 * h), np.array_equal(rhos[0], rhos[1])
+
+
+def _grad100k_fp32(X_np, sc, pr):
+    with Session(pr, torch.float32) as s:
+        X = torch.tensor(X_np, dtype=torch.float32, device="cuda:0", requires_grad=True)
+        V = torch.tensor(pr.src, dtype=torch.float32, device="cuda:0", requires_grad=True)
+        E = robust_energy(s.h, X, V, nu_a=sc[0], nu_r=sc[1], alpha=sc[2], beta=sc[3])
+        E.backward()
+        torch.cuda.synchronize()
+        return E.item(), X.grad.cpu().numpy().astype(np.float64), V.grad.cpu().numpy().astype(np.float64)
+
+
+def _elementwise_ok(g, g_ref, scale, rel=1e-4):
+    # |g - g_ref| <= rel * max(|g_ref|, 1e-3 * rms of the whole reference gradient)
+    return np.abs(g - g_ref) <= rel * np.maximum(np.abs(g_ref), 1e-3 * scale)
+
+
+def test_gradient_grad100k_vs_oracle_and_finite_differences():
+    """At X = I + delta (delta_A ~ N(0, 0.01), delta_t ~ N(0, 0.001)),
+    float32 adjoint with float32 accumulation: normwise within 1e-4 of the
+    oracle's FP64 analytic gradient, and per coordinate within 1e-4 of FP64
+    central differences (h = 1e-6) on 100 coordinates of X and 100 of V."""
+    _announce("test_gradient_grad100k_vs_oracle_and_finite_differences")
+    pair = synth.make_workload("grad100k")
+    pr = rounded(pair, np.float32)
+    prob = O.from_pair(pr)
+    nn = _kdtree_nn(prob.tgt)
+    sc = _scalars(prob, nn)
+    X = synth.perturbed_transforms(prob.n_nodes, 5005, 0.01, 0.001).astype(np.float32).astype(np.float64)
+    V = pr.src
+    E, gX, gV = _grad100k_fp32(X, sc, pr)
+    ev = O.evaluate(prob, X, *sc, src=V, nn=nn)
+    gXo, gVo, _ = O.energy_grad(prob, X, *sc, src=V, ev=ev)
+    assert E == pytest.approx(ev.E, rel=1e-5)
+    assert np.linalg.norm(gX - gXo) <= 1e-4 * np.linalg.norm(gXo)
+    assert np.linalg.norm(gV - gVo) <= 1e-4 * np.linalg.norm(gVo)
+
+    loc = _LocalEnergy(prob, X, V, sc, nn)
+    rng = np.random.default_rng(5006)
+    h = 1e-6
+    sx = math.sqrt((gXo ** 2).mean())
+    sv = math.sqrt((gVo ** 2).mean())
+    checked_x = checked_v = 0
+    while checked_x < 100:
+        j, r, c = int(rng.integers(prob.n_nodes)), int(rng.integers(4)), int(rng.integers(3))
+        fd, stable = loc.node_coord(j, r, c, h)
+        if not stable:
+            continue     # a closest point changes within +-h: resample
+        assert _elementwise_ok(gX[j, r, c], fd, sx), (j, r, c, gX[j, r, c], fd)
+        assert _elementwise_ok(gXo[j, r, c], fd, sx), (j, r, c, gXo[j, r, c], fd)
+        checked_x += 1
+    while checked_v < 100:
+        i, c = int(rng.integers(prob.n_src)), int(rng.integers(3))
+        fd, stable = loc.point_coord(i, c, h)
+        if not stable:
+            continue
+        assert _elementwise_ok(gV[i, c], fd, sv), (i, c, gV[i, c], fd)
+        assert _elementwise_ok(gVo[i, c], fd, sv), (i, c, gVo[i, c], fd)
+        checked_v += 1
+
+
+def test_gradient_grad100k_at_converged_transforms():
+    """At the transforms Alg. 2 returns (float32 + refinement, final stage's
+    nu, alpha, beta): the float32 adjoint against the oracle's FP64 analytic
+    gradient at the same (float32) X, normwise within 1e-4.  Near a
+    stationary point the alignment and regularization parts of dE/dX largely
+    cancel, so this is the harder case for float32 accumulation."""
+    _announce("test_gradient_grad100k_at_converged_transforms")
+    pair = synth.make_workload("grad100k")
+    pr = rounded(pair, np.float32)
+    prob = O.from_pair(pr)
+    with Session(pr, torch.float32) as s:
+        X = torch.empty(prob.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+        st = amm.amm_solve(s.h, amm.amm_params_default(aa_m=5), X, None)[0]
+        torch.cuda.synchronize()
+    Xs = X.cpu().numpy().astype(np.float64)
+    sc = (st["nu_a"], st["nu_r"], st["alpha"], st["beta"])
+    E, gX, gV = _grad100k_fp32(Xs, sc, pr)
+    nn = _kdtree_nn(prob.tgt)
+    ev = O.evaluate(prob, Xs, *sc, src=pr.src, nn=nn)
+    gXo, gVo, _ = O.energy_grad(prob, Xs, *sc, src=pr.src, ev=ev)
+    ex = np.linalg.norm(gX - gXo) / np.linalg.norm(gXo)
+    evv = np.linalg.norm(gV - gVo) / np.linalg.norm(gVo)
+    print(f"[grad at X*] iters {st['iters']} converged {st['converged']} E {E} vs {ev.E} "
+          f"|gX| {np.linalg.norm(gXo):.4e} rel {ex:.3e}  |gV| {np.linalg.norm(gVo):.4e} rel {evv:.3e}",
+          file=sys.stderr, flush=True)
+    assert E == pytest.approx(ev.E, rel=1e-5)
+    assert ex <= 1e-4 and evv <= 1e-4
