@@ -63,6 +63,13 @@ typedef enum { AMM_F32 = 0, AMM_F64 = 1 } amm_dtype;
  *                  and its solve are float64. */
 typedef enum { AMM_FP64_PLAIN = 0, AMM_FP32_REFINE = 1 } amm_precision;
 
+/* Preconditioner of the CG solve of Eq. (16).  Block Jacobi inverts the 4x4
+ * diagonal blocks of K (one per node and column).  Two-level adds a coarse
+ * correction P A_c^{-1} P^T, A_c = P^T K P, over one affine field per
+ * aggregate of spatially consecutive graph nodes (at most 32 aggregates per
+ * pair): the same solution, several times fewer CG iterations. */
+typedef enum { AMM_PRECOND_TWO_LEVEL = 0, AMM_PRECOND_BLOCK_JACOBI = 1 } amm_precond;
+
 typedef struct amm_handle amm_handle;
 
 /* One registration problem.  `on_device` = 1: the pointers are device
@@ -110,6 +117,7 @@ typedef struct {
     const int8_t* force_accept;
     const int8_t* force_stage_end;
     int32_t force_len;
+    int32_t cg_precond;           /* amm_precond (0 = two-level, the default) */
 } amm_params;
 
 #define AMM_MAX_AA_M 10
@@ -211,6 +219,7 @@ typedef struct {
     int32_t precision;       /* amm_precision */
     double cg_rtol;
     int32_t cg_maxit;
+    int32_t cg_precond;      /* amm_precond */
 } amm_step_in;
 
 typedef struct {
@@ -263,7 +272,7 @@ const char* amm_last_error(const amm_handle* h);   /* h may be NULL: last global
 
 /* Kernel timing with HIP events recorded on the handle's stream around each
  * launch group (names: "eval_points", "eval_edges", "eval_nodes",
- * "energy_final", "assemble", "cg_init", "cg_step",
+ * "energy_final", "assemble", "coarse_matrix", "coarse_invert", "cg_init", "cg_step",
  * "residual64", "anderson").  amm_enable_timing(h, 1, NULL) times every
  * group, (h, 1, name) only that group, (h, 0, NULL) stops; enabling clears
  * the totals.  amm_kernel_times returns, per group seen since, the summed

@@ -17,6 +17,7 @@ AMM_OK, AMM_ERR_INVALID_ARG, AMM_ERR_STATE, AMM_ERR_OOM, AMM_ERR_HIP, AMM_ERR_NO
     AMM_ERR_GRAPH, AMM_ERR_NOT_SPD = range(8)
 AMM_F32, AMM_F64 = 0, 1
 AMM_FP64_PLAIN, AMM_FP32_REFINE = 0, 1
+AMM_PRECOND_TWO_LEVEL, AMM_PRECOND_BLOCK_JACOBI = 0, 1
 AMM_MAX_AA_M = 10
 
 
@@ -37,7 +38,7 @@ class amm_params(C.Structure):
                 ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
                 ("init_identity", C.c_int32),
                 ("force_accept", C.c_void_p), ("force_stage_end", C.c_void_p),
-                ("force_len", C.c_int32)]
+                ("force_len", C.c_int32), ("cg_precond", C.c_int32)]
 
 
 class amm_stats(C.Structure):
@@ -68,7 +69,7 @@ class amm_iter_record(C.Structure):
 class amm_step_in(C.Structure):
     _fields_ = [("X", C.c_void_p), ("nu_a", C.c_double), ("nu_r", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("precision", C.c_int32),
-                ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32)]
+                ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("cg_precond", C.c_int32)]
 
 
 class amm_step_out(C.Structure):
@@ -266,10 +267,10 @@ def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: int
 
 
 def amm_step(handle, X, nu_a, nu_r, alpha, beta, precision, cg_rtol=1e-10, cg_maxit=0,
-             rho=None, d2=None, v_hat=None, X_next=None, K_blocks=None, K_row=None, K_col=None,
+             cg_precond=AMM_PRECOND_TWO_LEVEL, rho=None, d2=None, v_hat=None, X_next=None, K_blocks=None, K_row=None, K_col=None,
              B=None) -> dict:
     sin = amm_step_in(X=_ptr(X), nu_a=nu_a, nu_r=nu_r, alpha=alpha, beta=beta,
-                      precision=precision, cg_rtol=cg_rtol, cg_maxit=cg_maxit)
+                      precision=precision, cg_rtol=cg_rtol, cg_maxit=cg_maxit, cg_precond=cg_precond)
     sout = amm_step_out(rho=_ptr(rho), d2=_ptr(d2), v_hat=_ptr(v_hat), X_next=_ptr(X_next),
                         K_blocks=_ptr(K_blocks), K_row=_ptr(K_row), K_col=_ptr(K_col), B=_ptr(B))
     _check(lib().amm_step(handle, C.byref(sin), C.byref(sout)), handle)

@@ -120,6 +120,7 @@ struct StaticT {
     typename V4Of<T>::type* blo = nullptr;
     typename V4Of<T>::type* bhi = nullptr;
     T* adj_r = nullptr;
+    typename V4Of<T>::type* node_rel = nullptr;
 };
 
 // Dynamic arrays are sized for 8-byte elements and reinterpreted for float.
@@ -142,10 +143,13 @@ struct Dyn {
     double* rvec;
     double* Dinv;
     double* cg[11];    // x p r0 r1 u0 u1 w0 w1 s0 s1 rhs
-    double* part_ru[2];
-    double* part_rr[2];
-    double* part_wu[2];
+    double* part[2];   // [nd_tiles][kCgPart]
     double* part_bb;
+    double* gr[2];     // [nagg][12]
+    double* gs[2];
+    double* Ac_tile;   // [nd_tiles][kCoarseMaxAgg][16]
+    double* Ac;        // float64 coarse matrices
+    double* Ainv;
     double* part_rr64;
     double* part_bb64;
     double* G;
@@ -174,6 +178,9 @@ struct Dev {
     int4* pt_tiles;
     int4* nd_tiles;
     int4* eg_tiles;
+    int4* aggs;
+    int* tile_agg_ptr;
+    int* tile_agg;
     PairInfo* info;
     PairDyn* dyn;        // slot of dyn_ring used by the next launches
     PairDyn* dyn_ring;   // [kDynRing][P]
@@ -206,6 +213,9 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(v.pt_tiles, npt);
     c.take(v.nd_tiles, nnd);
     c.take(v.eg_tiles, neg);
+    c.take(v.aggs, (size_t)L.nagg);
+    c.take(v.tile_agg_ptr, nnd + 1);
+    c.take(v.tile_agg, L.tile_agg.size());
     c.take(v.info, L.P);
     c.take(v.dyn_ring, (size_t)kDynRing * L.P);
     v.dyn = v.dyn_ring;
@@ -221,6 +231,7 @@ void plan(const Layout& L, Carver& c, Dev& v) {
         c.take(s.blo, tn);
         c.take(s.bhi, tn);
         c.take(s.adj_r, na);
+        c.take(s.node_rel, n);
     };
     statics(v.sf);
     statics(v.sd);
@@ -246,11 +257,14 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(d.Dinv, 16 * n);
     for (int q = 0; q < 11; ++q) c.take(d.cg[q], 12 * n);
     for (int q = 0; q < 2; ++q) {
-        c.take(d.part_ru[q], 3 * nnd);
-        c.take(d.part_rr[q], 3 * nnd);
-        c.take(d.part_wu[q], 3 * nnd);
+        c.take(d.part[q], (size_t)kCgPart * nnd);
+        c.take(d.gr[q], 12 * (size_t)L.nagg);
+        c.take(d.gs[q], 12 * (size_t)L.nagg);
     }
     c.take(d.part_bb, 3 * nnd);
+    c.take(d.Ac_tile, nnd * kCoarseMaxAgg * 16);
+    c.take(d.Ac, (size_t)L.ainv_size);
+    c.take(d.Ainv, (size_t)L.ainv_size);
     c.take(d.part_rr64, 3 * nnd);
     c.take(d.part_bb64, 3 * nnd);
     c.take(d.G, (AMM_MAX_AA_M + 1) * 12 * n);
@@ -287,6 +301,7 @@ struct amm_handle {
     hipEvent_t cg_ev[kCgRing] = {};
     size_t h_cap = 0;
     bool timing = false;
+    bool cg_coarse = true;           // two-level CG preconditioner
     EventTimer timer;
     std::vector<amm_iter_record> iter_log;
 };
@@ -549,13 +564,38 @@ CgArgs<T> cg_args(amm_handle* h, const T* b, const T* bnorm, double rtol) {
         a.u[q] = reinterpret_cast<T*>(d.cg[4 + q]);
         a.w[q] = reinterpret_cast<T*>(d.cg[6 + q]);
         a.s[q] = reinterpret_cast<T*>(d.cg[8 + q]);
-        a.part_ru[q] = d.part_ru[q];
-        a.part_rr[q] = d.part_rr[q];
-        a.part_wu[q] = d.part_wu[q];
+        a.part[q] = d.part[q];
+        a.gr[q] = reinterpret_cast<T*>(d.gr[q]);
+        a.gs[q] = reinterpret_cast<T*>(d.gs[q]);
     }
     a.part_bb = d.part_bb;
     a.state = h->v.state;
     a.rtol2 = rtol * rtol;
+    a.coarse = h->cg_coarse ? 1 : 0;
+    a.Ainv = reinterpret_cast<const T*>(d.Ainv);
+    a.node_rel = statics<T>(h).node_rel;
+    a.tile_agg_ptr = h->v.tile_agg_ptr;
+    a.tile_agg = h->v.tile_agg;
+    return a;
+}
+
+template <typename T>
+CoarseArgs<T> coarse_args(amm_handle* h) {
+    const Dyn& d = h->v.d;
+    CoarseArgs<T> a{};
+    a.aggs = h->v.aggs;
+    a.nd_tiles = h->v.nd_tiles;
+    a.tile_agg_ptr = h->v.tile_agg_ptr;
+    a.tile_agg = h->v.tile_agg;
+    a.info = h->v.info;
+    a.dyn = h->v.dyn;
+    a.K_ptr = h->v.K_ptr;
+    a.K_col = h->v.K_col;
+    a.Kval = reinterpret_cast<const T*>(d.Kval);
+    a.node_rel = statics<T>(h).node_rel;
+    a.Ac_tile = d.Ac_tile;
+    a.Ac = d.Ac;
+    a.Ainv = reinterpret_cast<T*>(d.Ainv);
     return a;
 }
 
@@ -701,6 +741,7 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
     rep.refine.assign(L.P, 0);
     rep.rel.assign(L.P, 0.0);
     rep.not_spd = false;
+    if (h->cg_coarse) launch_coarse<T>(coarse_args<T>(h), L.n_nd_tiles, L.nagg, L.P, h->stream, tmr(h));
     const T* r = reinterpret_cast<const T*>(d.rvec);
     const T* B = reinterpret_cast<const T*>(d.B);
     T* x = reinterpret_cast<T*>(d.cg[0]);
@@ -1327,6 +1368,10 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up_real(h, v.sf.blo, v.sd.blo, Lr.box_lo));
     TRY(up_real(h, v.sf.bhi, v.sd.bhi, Lr.box_hi));
     TRY(up_real(h, v.sf.adj_r, v.sd.adj_r, Lr.adj_r));
+    TRY(up_real(h, v.sf.node_rel, v.sd.node_rel, Lr.node_rel));
+    TRY(up(h, reinterpret_cast<int32_t*>(v.aggs), Lr.aggs));
+    TRY(up(h, v.tile_agg_ptr, Lr.tile_agg_ptr));
+    TRY(up(h, v.tile_agg, Lr.tile_agg));
     h->has_problem = true;
     return AMM_OK;
 }
@@ -1340,7 +1385,10 @@ amm_status amm_solve(amm_handle* h, const amm_params* prm, void* X_inout, void* 
     if (!(prm->eps >= 0) || prm->imax < 1) return fail(h, AMM_ERR_INVALID_ARG, "bad eps or imax");
     if (!(prm->k_alpha >= 0) || !(prm->k_beta > 0)) return fail(h, AMM_ERR_INVALID_ARG, "bad k_alpha or k_beta");
     if (!prm->init_identity && !X_inout) return fail(h, AMM_ERR_INVALID_ARG, "X_inout needed without init_identity");
+    if (prm->cg_precond != AMM_PRECOND_TWO_LEVEL && prm->cg_precond != AMM_PRECOND_BLOCK_JACOBI)
+        return fail(h, AMM_ERR_INVALID_ARG, "bad cg_precond");
     HIPC(hipSetDevice(h->device));
+    h->cg_coarse = prm->cg_precond == AMM_PRECOND_TWO_LEVEL;
     if (prm->precision == AMM_FP64_PLAIN) return solve_impl<double>(h, *prm, X_inout, v_out, stats);
     if (prm->precision == AMM_FP32_REFINE) return solve_impl<float>(h, *prm, X_inout, v_out, stats);
     return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");
@@ -1352,7 +1400,10 @@ amm_status amm_step(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     if (h->L.P != 1) return fail(h, AMM_ERR_STATE, "amm_step needs exactly one pair");
     if (!(in->nu_a > 0) || !(in->nu_r > 0) || !(in->beta > 0) || !(in->alpha >= 0))
         return fail(h, AMM_ERR_INVALID_ARG, "nu_a, nu_r, beta must be > 0 and alpha >= 0");
+    if (in->cg_precond != AMM_PRECOND_TWO_LEVEL && in->cg_precond != AMM_PRECOND_BLOCK_JACOBI)
+        return fail(h, AMM_ERR_INVALID_ARG, "bad cg_precond");
     HIPC(hipSetDevice(h->device));
+    h->cg_coarse = in->cg_precond == AMM_PRECOND_TWO_LEVEL;
     if (in->precision == AMM_FP64_PLAIN) return step_impl<double>(h, in, out);
     if (in->precision == AMM_FP32_REFINE) return step_impl<float>(h, in, out);
     return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");

@@ -24,7 +24,12 @@ struct PairInfo {
     int32_t nd_tile0, nd_ntile;   // node tiles (solver rows)
     int32_t eg_tile0, eg_ntile;   // edge tiles
     int32_t n_undirected;
-    int32_t pad;
+    // coarse level of the CG preconditioner: aggregates of 2^agg_shift
+    // consecutive (Morton-ordered) nodes, agg0 = first global aggregate,
+    // nagg <= kCoarseMaxAgg; the dense inverse of the coarse matrix (order
+    // 4 nagg) starts at ainv_off
+    int32_t agg0, nagg, agg_shift;
+    int64_t ainv_off;
 };
 
 // Dynamic per-pair state the host writes before launches.
@@ -98,6 +103,13 @@ struct Layout {
     std::vector<double> box_lo, box_hi;    // [tree_nodes][4]
     std::vector<int32_t> pt_tiles, nd_tiles, eg_tiles;   // [tiles][4] = pair, start, end, 0
     int max_row_cols = 0;
+    // coarse level: per aggregate (pair, first node, end node, pair-local id),
+    // node position minus its aggregate's centroid, and per node tile the
+    // sorted pair-local aggregates that its rows of K touch
+    int64_t nagg = 0, ainv_size = 0;
+    std::vector<int32_t> aggs;       // [nagg][4]
+    std::vector<double> node_rel;    // [ntot][4]
+    std::vector<int32_t> tile_agg_ptr, tile_agg;
 };
 
 constexpr int kPointTile = 256;
@@ -105,6 +117,8 @@ constexpr int kNodeTile = 16;        // solver rows per tile (4 threads per row:
 constexpr int kEdgeTile = 256;
 constexpr int kMaxCols = 192;        // K blocks per row supported by the assembly
 constexpr int kMaxK = 8;
+constexpr int kCoarseMaxAgg = 32;    // aggregates per pair (coarse order <= 128)
+constexpr int kAggMinShift = 6;      // at least 64 nodes (4 node tiles) per aggregate
 
 amm_status validate_pair(const HostPair& hp, std::string& err);
 amm_status build_layout(const std::vector<HostPair>& pairs, int leaf_size, Layout& L,

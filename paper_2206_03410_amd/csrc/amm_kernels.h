@@ -97,8 +97,13 @@ struct AsmArgs {
     T* Dinv;
 };
 
+// Per solver tile, per step parity: (r,u), (w,u), (r,r) per column, then the
+// tile's part of P^T w (12 values, [4][3]) for the coarse level.
+constexpr int kCgPart = 21;
+
 template <typename T>
 struct CgArgs {
+    using V = typename V4Of<T>::type;
     const int4* nd_tiles;
     const PairInfo* info;
     const PairDyn* dyn;
@@ -114,12 +119,37 @@ struct CgArgs {
     T* u[2];
     T* w[2];
     T* s[2];
-    double* part_ru[2];      // tile partials of the vectors of each parity
-    double* part_wu[2];
-    double* part_rr[2];
-    double* part_bb;
+    double* part[2];         // [tile][kCgPart] partials of the vectors of each parity
+    double* part_bb;         // [tile][3] (n,n) of the stopping-test scale
     CgState* state;          // [P][2]
     double rtol2;
+    // two-level preconditioner (coarse = 1): M^{-1} = D^{-1} + P A_c^{-1} P^T
+    // with an affine field per aggregate of nodes
+    int coarse;
+    const T* Ainv;           // per pair, dense inverse of A_c = P^T K P (row-major)
+    const V* node_rel;       // node position minus its aggregate's centroid
+    const int* tile_agg_ptr; // aggregates (pair-local) each tile's rows of K touch
+    const int* tile_agg;
+    T* gr[2];                // [nagg][12] P^T r per aggregate
+    T* gs[2];                // [nagg][12] P^T s per aggregate
+};
+
+template <typename T>
+struct CoarseArgs {
+    using V = typename V4Of<T>::type;
+    const int4* aggs;        // [nagg] pair, first node, end node, pair-local id
+    const int4* nd_tiles;
+    const int* tile_agg_ptr;
+    const int* tile_agg;
+    const PairInfo* info;
+    const PairDyn* dyn;
+    const int* K_ptr;
+    const int* K_col;
+    const T* Kval;
+    const V* node_rel;
+    double* Ac_tile;         // [nd_tiles][kCoarseMaxAgg][16] per-tile partial coarse rows
+    double* Ac;              // float64 coarse matrices
+    T* Ainv;
 };
 
 template <typename T>
@@ -196,11 +226,14 @@ void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_
 template <typename T>
 void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTimer* tm);
 // CG on K x = b from x = 0 for the pairs flagged PF_SOLVE: the start
-// (r = b, u = M^{-1} r, w = K u), then one update + one product per step.
+// (r = b, u = M^{-1} r, w = K u), then one fused update + product per step.
 template <typename T>
 void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, hipStream_t s, KernelTimer* tm);
 template <typename T>
 void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm);
+// Coarse matrices A_c = P^T K P and their inverses for the pairs flagged PF_SOLVE.
+template <typename T>
+void launch_coarse(const CoarseArgs<T>& a, int n_nd_tiles, int64_t nagg, int P, hipStream_t s, KernelTimer* tm);
 template <typename T>
 void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const T* Bn, const double* x64,
                        T* rhs_out, double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm);

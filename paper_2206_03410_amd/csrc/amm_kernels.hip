@@ -11,60 +11,11 @@
 #include <algorithm>
 #include <climits>
 
+#include "amm_device.h"
 #include "amm_kernels.h"
 #include "amm_nn.h"
 
 namespace amm {
-
-// ---------------------------------------------------------------- helpers
-
-template <typename T> __device__ __forceinline__ T dev_inf();
-template <> __device__ __forceinline__ float dev_inf<float>() { return __builtin_inff(); }
-template <> __device__ __forceinline__ double dev_inf<double>() { return __builtin_inf(); }
-
-// Maps block b of G to a tile so that each of the 8 XCDs (blocks are
-// dispatched round-robin over XCDs) works on one contiguous range of tiles,
-// which keeps the target data a range touches inside one XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int G) {
-    const int per = G >> 3, rem = G & 7;
-    const int x = b & 7, q = b >> 3;
-    return x * per + min(x, rem) + q;
-}
-
-template <typename T, int NT>
-__device__ __forceinline__ T block_sum(T v, T* sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    T r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-template <typename T, int NT>
-__device__ __forceinline__ T block_max(T v, T* sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
-    }
-    T r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // ---------------------------------------------------------------- evaluation
 
@@ -355,57 +306,6 @@ __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
 
 // ---------------------------------------------------------------- assembly
 
-// Inverse of a symmetric positive definite 4x4 block (the block-Jacobi
-// preconditioner) through its Cholesky factor, fully unrolled; a
-// non-positive pivot falls back to the inverse of the diagonal.
-template <typename T>
-__device__ __forceinline__ void spd_inverse4(const T K[4][4], T* out) {
-    T L[4][4] = {};
-    bool ok = true;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        T d = K[c][c];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q < c) d -= L[c][q] * L[c][q];
-        ok = ok && d > T(0);
-        const T lc = sqrt(fmax(d, T(1e-300)));
-        L[c][c] = lc;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (r > c) {
-                T v = K[r][c];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (q < c) v -= L[r][q] * L[c][q];
-                L[r][c] = v / lc;
-            }
-    }
-    // W = L^{-1} (lower triangular), then K^{-1} = W^T W
-    T W[4][4] = {};
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        W[c][c] = T(1) / L[c][c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (r > c) {
-                T v = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (q >= c && q < r) v -= L[r][q] * W[q][c];
-                W[r][c] = v / L[r][r];
-            }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            T v = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v += W[q][r] * W[q][c];
-            out[4 * r + c] = ok ? v : (r == c ? T(1) / fmax(fabs(K[r][r]), T(1e-30)) : T(0));
-        }
-}
 
 // Row j of K and B (Eq. 16) and of the residual r = B - K X^k, one wave per
 // node.  Alignment blocks K_jl = sum_i w_a,i w_ij w_il [v_i - p_j; 1]
@@ -610,288 +510,6 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
             Ro[m2] = rj[m2];
             Bo[m2] = rj[m2] + kx[m2];
         }
-    }
-}
-
-// ---------------------------------------------------------------- CG (Chronopoulos-Gear)
-
-// Vectors are [n][4][3] like X.  One kernel per CG step over solver tiles of
-// 16 node rows, 256 threads (16 lanes per row).  A step needs the new u of
-// every column node of its rows; instead of a separate launch after the
-// update, each lane recomputes u_l for the column block it multiplies from
-// the previous step's r, w, s (read-only in this step: r, u, w, s and the
-// partials are double-buffered by step parity).  The recomputation uses the
-// same operations as the owner's update, so both give identical values.
-
-template <typename T>
-struct CgVec {
-    T v[12];
-};
-
-// Pair sums of the tile partials (lanes over tiles, fixed order) -> red[12]:
-// (r,u), (w,u), (r,r), (n,n) per column.
-template <typename T>
-__device__ __forceinline__ void cg_pair_sums(const CgArgs<T>& a, const PairInfo& pi, int par, double* red,
-                                             double (*wred)[12]) {
-    double v[12];
-#pragma unroll
-    for (int m = 0; m < 12; ++m) v[m] = 0;
-    for (int t = threadIdx.x; t < pi.nd_ntile; t += blockDim.x) {
-        const size_t o = 3 * (size_t)(pi.nd_tile0 + t);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            v[c] += a.part_ru[par][o + c];
-            v[3 + c] += a.part_wu[par][o + c];
-            v[6 + c] += a.part_rr[par][o + c];
-            v[9 + c] += a.part_bb[o + c];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < 12; ++m) v[m] = wave_sum(v[m]);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int m = 0; m < 12; ++m) wred[threadIdx.x >> 6][m] = v[m];
-    __syncthreads();
-    if (threadIdx.x < 12) red[threadIdx.x] = ((wred[0][threadIdx.x] + wred[1][threadIdx.x]) + wred[2][threadIdx.x]) +
-                                             wred[3][threadIdx.x];
-    __syncthreads();
-}
-
-// u_l of step it+1 from the step-it vectors of node l:
-// r' = r - alpha (w + beta s), u' = D_l^{-1} r' (columns with active = 0 keep r).
-template <typename T>
-__device__ __forceinline__ void cg_new_u(const CgArgs<T>& a, int l, int par, const T al[3], const T be[3],
-                                         const bool act[3], bool first, T u[12]) {
-    const size_t o = 12 * (size_t)l;
-    T rn[12];
-#pragma unroll
-    for (int m = 0; m < 12; ++m) {
-        const int c = m % 3;
-        const T r0 = a.r[par][o + m];
-        if (act[c]) {
-            const T sn = first ? a.w[par][o + m] : a.w[par][o + m] + be[c] * a.s[par][o + m];
-            rn[m] = r0 - al[c] * sn;
-        } else {
-            rn[m] = r0;
-        }
-    }
-    const T* Di = a.Dinv + 16 * (size_t)l;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            u[3 * q + c] = Di[4 * q] * rn[c] + Di[4 * q + 1] * rn[3 + c] + Di[4 * q + 2] * rn[6 + c] +
-                           Di[4 * q + 3] * rn[9 + c];
-}
-
-// One CG step (it >= 0), or the start (it = -1: r = b, u = M^{-1} b, w = K u,
-// x = 0).  Writes the new r, u, w, s into buffer (it+1) & 1 (the start into
-// buffer 0) and the tile partials of the new vectors.
-template <typename T>
-__global__ void __launch_bounds__(16 * kNodeTile) k_cg_step(CgArgs<T> a, int it) {
-    __shared__ double red[12];
-    __shared__ double wred[4][12];
-    __shared__ double scal[3][3];   // alpha, beta, active
-    __shared__ int brk_mask;
-    __shared__ T rs[kNodeTile][12];
-    __shared__ T ys[kNodeTile][12];
-    __shared__ T part[4][9];
-    const int tile = blockIdx.x;
-    const int4 td = a.nd_tiles[tile];
-    const int p = td.x;
-    const PairDyn& dy = a.dyn[p];
-    if (!(dy.flags & PF_SOLVE)) return;
-    const PairInfo& pi = a.info[p];
-    const bool start = it < 0;
-    const int par = start ? 0 : (it & 1);          // buffer read
-    const int nxt = start ? 0 : ((it + 1) & 1);    // buffer written
-    if (!start) {
-        const CgState& prv = a.state[2 * (size_t)p + ((it + 1) & 1)];
-        if (prv.conv[0] && prv.conv[1] && prv.conv[2]) {
-            // converged before this step: x is final and no later step reads the
-            // vectors; carry the state to this step's slot
-            if (threadIdx.x == 0 && tile == pi.nd_tile0) a.state[2 * (size_t)p + (it & 1)] = prv;
-            return;
-        }
-        cg_pair_sums(a, pi, par, red, wred);
-        if (threadIdx.x == 0) brk_mask = 0;
-        __syncthreads();
-        const double rtol2 = dy.cg_rtol > 0 ? dy.cg_rtol * dy.cg_rtol : a.rtol2;
-        if (threadIdx.x < 3) {
-            const int c = threadIdx.x;
-            const double gam = red[c], del = red[3 + c], rr = red[6 + c], bb = red[9 + c];
-            int conv = prv.conv[c];
-            int brk = 0;
-            double al = 0, be = 0;
-            if (!conv) {
-                if (rr <= rtol2 * bb || bb == 0.0) {
-                    conv = 1;
-                } else if (it == 0) {
-                    al = gam / del;
-                } else {
-                    be = gam / prv.gamma[c];
-                    al = gam / (del - be * gam / prv.alpha[c]);
-                }
-                if (!conv && !(al > 0.0 && gam > 0.0 && al < 1e300)) {
-                    conv = 1;
-                    brk = 1;
-                    al = be = 0;
-                }
-            }
-            scal[c][0] = al;
-            scal[c][1] = be;
-            scal[c][2] = conv ? 0.0 : 1.0;
-            if (tile == pi.nd_tile0) {
-                CgState& st = a.state[2 * (size_t)p + (it & 1)];
-                st.alpha[c] = al;
-                st.gamma[c] = gam;
-                st.rr[c] = rr;
-                st.bb[c] = bb;
-                st.conv[c] = conv;
-            }
-            if (brk) atomicOr(&brk_mask, 1 << c);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && tile == pi.nd_tile0) {
-            CgState& st = a.state[2 * (size_t)p + (it & 1)];
-            const bool any = scal[0][2] != 0.0 || scal[1][2] != 0.0 || scal[2][2] != 0.0;
-            st.iters = prv.iters + (any ? 1 : 0);
-            st.breakdown = prv.breakdown | brk_mask;
-        }
-    } else {
-        if (threadIdx.x < 3) {
-            scal[threadIdx.x][0] = scal[threadIdx.x][1] = 0;
-            scal[threadIdx.x][2] = 1.0;
-        }
-        if (threadIdx.x < 3 && tile == pi.nd_tile0) {
-            CgState* st = a.state + 2 * (size_t)p;
-            st[0].conv[threadIdx.x] = 0;
-            st[1].conv[threadIdx.x] = 0;
-            if (threadIdx.x == 0) {
-                st[0].iters = st[1].iters = 0;
-                st[0].breakdown = st[1].breakdown = 0;
-            }
-        }
-        __syncthreads();
-    }
-    T al[3], be[3];
-    bool act[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        al[c] = (T)scal[c][0];
-        be[c] = (T)scal[c][1];
-        act[c] = scal[c][2] != 0.0;
-    }
-    const bool first = it <= 0;
-    const int row = threadIdx.x >> 4, lane = threadIdx.x & 15;
-    const int j = td.y + row;
-    const bool live = j < td.z;
-    // own rows, element m = lane < 12: p, s, x, r
-    if (live && lane < 12) {
-        const size_t o = 12 * (size_t)j + lane;
-        const int c = lane % 3;
-        T rn;
-        if (start) {
-            rn = a.b[o];
-            a.x[o] = 0;
-            a.s[nxt][o] = 0;
-        } else if (act[c]) {
-            const T pn = first ? a.u[par][o] : a.u[par][o] + be[c] * a.pv[o];
-            const T sn = first ? a.w[par][o] : a.w[par][o] + be[c] * a.s[par][o];
-            a.pv[o] = pn;
-            a.s[nxt][o] = sn;
-            a.x[o] += al[c] * pn;
-            rn = a.r[par][o] - al[c] * sn;
-        } else {
-            rn = a.r[par][o];
-            a.s[nxt][o] = a.s[par][o];
-        }
-        a.r[nxt][o] = rn;
-        rs[row][lane] = rn;
-    }
-    // w = K u' with u' recomputed for every column block
-    T y[12];
-#pragma unroll
-    for (int m = 0; m < 12; ++m) y[m] = 0;
-    if (live) {
-        const int ke = a.K_ptr[j + 1];
-        for (int pos = a.K_ptr[j] + lane; pos < ke; pos += 16) {
-            const int l = a.K_col[pos];
-            T ul[12];
-            if (start) {
-                const T* bl = a.b + 12 * (size_t)l;
-                const T* Di = a.Dinv + 16 * (size_t)l;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        ul[3 * q + c] = Di[4 * q] * bl[c] + Di[4 * q + 1] * bl[3 + c] + Di[4 * q + 2] * bl[6 + c] +
-                                        Di[4 * q + 3] * bl[9 + c];
-            } else {
-                cg_new_u(a, l, par, al, be, act, first, ul);
-            }
-            const T* kb = a.Kval + 16 * (size_t)pos;
-            T kv[16];
-#pragma unroll
-            for (int m = 0; m < 16; ++m) kv[m] = kb[m];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    y[3 * q + c] += kv[4 * q] * ul[c] + kv[4 * q + 1] * ul[3 + c] + kv[4 * q + 2] * ul[6 + c] +
-                                    kv[4 * q + 3] * ul[9 + c];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < 12; ++m)
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) y[m] += __shfl_xor(y[m], o, 16);
-    if (lane == 0)
-#pragma unroll
-        for (int m = 0; m < 12; ++m) ys[row][m] = y[m];
-    __syncthreads();
-    // own rows: u' = D^{-1} r', write u', w', partials of the new vectors
-    T pc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // (r,u), (w,u), (r,r) per column
-    if (live && lane < 12) {
-        const size_t o = 12 * (size_t)j + lane;
-        const int q = lane / 3, c = lane % 3;
-        const T* Di = a.Dinv + 16 * (size_t)j + 4 * q;
-        const T un = Di[0] * rs[row][c] + Di[1] * rs[row][3 + c] + Di[2] * rs[row][6 + c] + Di[3] * rs[row][9 + c];
-        const T wn = ys[row][lane];
-        a.u[nxt][o] = un;
-        a.w[nxt][o] = wn;
-        const T rn = rs[row][lane];
-        pc[c] = rn * un;
-        pc[3 + c] = wn * un;
-        pc[6 + c] = rn * rn;
-    }
-#pragma unroll
-    for (int m = 0; m < 9; ++m) pc[m] = wave_sum(pc[m]);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int m = 0; m < 9; ++m) part[threadIdx.x >> 6][m] = pc[m];
-    // the start also records (n,n) of the vector scaling the stopping test
-    T bn[3] = {0, 0, 0};
-    if (start) {
-        if (live && lane < 12) {
-            const size_t o = 12 * (size_t)j + lane;
-            const T v = a.bnorm ? a.bnorm[o] : a.b[o];
-            bn[lane % 3] = v * v;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) bn[c] = wave_sum(bn[c]);
-    }
-    __syncthreads();
-    if (start && (threadIdx.x & 63) == 0)
-        for (int c = 0; c < 3; ++c) wred[threadIdx.x >> 6][c] = (double)bn[c];
-    __syncthreads();
-    if (threadIdx.x < 9) {
-        const int m = threadIdx.x, c = m % 3;
-        const double v = (double)(((part[0][m] + part[1][m]) + part[2][m]) + part[3][m]);
-        double* dst = m < 3 ? a.part_ru[nxt] : (m < 6 ? a.part_wu[nxt] : a.part_rr[nxt]);
-        dst[3 * tile + c] = v;
-        if (start && m < 3)
-            a.part_bb[3 * tile + c] = ((wred[0][c] + wred[1][c]) + wred[2][c]) + wred[3][c];
     }
 }
 
@@ -1341,20 +959,6 @@ void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTim
 }
 
 template <typename T>
-void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, hipStream_t s, KernelTimer* tm) {
-    if (tm) tm->begin("cg_init", s);
-    hipLaunchKernelGGL(k_cg_step<T>, dim3(n_nd_tiles), dim3(16 * kNodeTile), 0, s, a, -1);
-    if (tm) tm->end(s);
-}
-
-template <typename T>
-void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm) {
-    if (tm) tm->begin("cg_step", s);
-    hipLaunchKernelGGL(k_cg_step<T>, dim3(n_nd_tiles), dim3(16 * kNodeTile), 0, s, a, it);
-    if (tm) tm->end(s);
-}
-
-template <typename T>
 void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const T* Bn, const double* x64,
                        T* rhs_out, double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm) {
     if (tm) tm->begin("residual64", s);
@@ -1417,8 +1021,6 @@ void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s) {
     template void launch_eval<T>(const EvalArgs<T>&, int, int, int, const FinalArgs&, int, hipStream_t,        \
                                  KernelTimer*);                                                               \
     template void launch_assemble<T>(const AsmArgs<T>&, int64_t, hipStream_t, KernelTimer*);                   \
-    template void launch_cg_init<T>(const CgArgs<T>&, int, hipStream_t, KernelTimer*);                         \
-    template void launch_cg_iter<T>(const CgArgs<T>&, int, int, hipStream_t, KernelTimer*);                    \
     template void launch_residual64<T>(const CgArgs<T>&, int, const T*, const T*, const double*, T*, double*,  \
                                        double*, hipStream_t, KernelTimer*);                                   \
     template void launch_node_vec_op<T>(const NodeVecArgs<T>&, int, hipStream_t);                             \

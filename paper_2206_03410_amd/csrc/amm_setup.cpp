@@ -410,6 +410,40 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
             ++L.n_nd_tiles;
         }
         pi.nd_ntile = L.n_nd_tiles - pi.nd_tile0;
+
+        // coarse aggregates: the fewest power-of-two runs of whole node tiles
+        // that leave at most kCoarseMaxAgg of them
+        int shift = kAggMinShift;
+        while (((hp.n + (int64_t(1) << shift) - 1) >> shift) > kCoarseMaxAgg) ++shift;
+        const int64_t per = int64_t(1) << shift;
+        pi.agg_shift = shift;
+        pi.nagg = (int32_t)((hp.n + per - 1) / per);
+        pi.agg0 = (int32_t)L.nagg;
+        pi.ainv_off = L.ainv_size;
+        L.ainv_size += (int64_t)(4 * pi.nagg) * (4 * pi.nagg);
+        L.node_rel.resize(4 * L.ntot, 0.0);
+        for (int32_t a = 0; a < pi.nagg; ++a) {
+            const int64_t s0 = a * per, s1 = std::min<int64_t>(s0 + per, hp.n);
+            double ctr[3] = {0, 0, 0};
+            for (int64_t q = s0; q < s1; ++q)
+                for (int c = 0; c < 3; ++c) ctr[c] += L.nodes4[4 * (no + q) + c];
+            for (int c = 0; c < 3; ++c) ctr[c] /= (double)(s1 - s0);
+            for (int64_t q = s0; q < s1; ++q)
+                for (int c = 0; c < 3; ++c) L.node_rel[4 * (no + q) + c] = L.nodes4[4 * (no + q) + c] - ctr[c];
+            L.aggs.insert(L.aggs.end(), {p, (int32_t)(no + s0), (int32_t)(no + s1), a});
+        }
+        L.nagg += pi.nagg;
+        for (int32_t t = 0; t < pi.nd_ntile; ++t) {
+            if (L.tile_agg_ptr.empty()) L.tile_agg_ptr.push_back(0);
+            std::vector<int32_t> ag;
+            for (int64_t q = (int64_t)t * kNodeTile; q < std::min<int64_t>((int64_t)(t + 1) * kNodeTile, hp.n); ++q)
+                for (int32_t e = L.K_ptr[no + q]; e < (q + 1 < hp.n ? L.K_ptr[no + q + 1] : (int32_t)L.K_col.size()); ++e)
+                    ag.push_back((int32_t)((L.K_col[e] - no) >> shift));
+            std::sort(ag.begin(), ag.end());
+            ag.erase(std::unique(ag.begin(), ag.end()), ag.end());
+            L.tile_agg.insert(L.tile_agg.end(), ag.begin(), ag.end());
+            L.tile_agg_ptr.push_back((int32_t)L.tile_agg.size());
+        }
         pi.eg_tile0 = L.n_eg_tiles;
         for (int64_t s = 0; s < 2 * hp.E; s += kEdgeTile) {
             L.eg_tiles.insert(L.eg_tiles.end(),

@@ -1,7 +1,8 @@
 """Parity of the HIP library (through the C ABI) with the FP64 oracle.
 
 Sizes here finish in the oracle within seconds and still span several
-tiles with ragged tails (points: tiles of 256; nodes: tiles of 64).
+tiles with ragged tails (points: tiles of 256; nodes: tiles of 16, coarse
+aggregates of 64 nodes).
 """
 import math
 import sys
@@ -24,7 +25,8 @@ def _announce(name):
 
 @pytest.fixture(scope="module")
 def pair():
-    # 1100 points = 4 full point tiles + a ragged one; 70 nodes = 1 full node tile + 6
+    # 1100 points = 4 full point tiles + a ragged one; 70 nodes = 4 full node
+    # tiles + a ragged one, one full coarse aggregate + a ragged one
     return synth.torus_pair(1000, n_src=1100, n_tgt=1100, n_nodes=70, k=4, e=6)
 
 
@@ -42,11 +44,14 @@ def _K_dense(nnzb_blocks, rows, cols, n):
     return K
 
 
+@pytest.mark.parametrize("precond", ["two_level", "block_jacobi"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_step_parity(pair, prec):
+def test_step_parity(pair, prec, precond):
     """One teacher-forced MM step: closest points, energy, K, B, and the
-    surrogate minimizer, against the oracle at the same inputs."""
-    _announce(f"test_step_parity {prec}")
+    surrogate minimizer, against the oracle at the same inputs (either CG
+    preconditioner: both must reach the same minimizer)."""
+    _announce(f"test_step_parity {prec} {precond}")
+    pc = amm.AMM_PRECOND_TWO_LEVEL if precond == "two_level" else amm.AMM_PRECOND_BLOCK_JACOBI
     np_dt = np.float64 if prec == "f64" else np.float32
     t_dt = torch.float64 if prec == "f64" else torch.float32
     pr = rounded(pair, np_dt)
@@ -67,7 +72,7 @@ def test_step_parity(pair, prec):
         Kc = torch.empty(nnzb, dtype=torch.int32, device=dev)
         B = torch.empty(n, 4, 3, dtype=t_dt, device=dev)
         out = amm.amm_step(s.h, Xt, nu_a, nu_r, alpha, beta,
-                           amm.AMM_FP64_PLAIN if prec == "f64" else amm.AMM_FP32_REFINE,
+                           amm.AMM_FP64_PLAIN if prec == "f64" else amm.AMM_FP32_REFINE, cg_precond=pc,
                            rho=rho, d2=d2, v_hat=vh, X_next=Xn, K_blocks=Kb, K_row=Kr, K_col=Kc, B=B)
         torch.cuda.synchronize()
         rho, d2, vh, Xn = rho.cpu().numpy(), d2.cpu().numpy(), vh.cpu().numpy(), Xn.cpu().numpy()
