@@ -11,8 +11,8 @@
  * one affine transform X_j = [A_j, t_j] per node.  The library minimizes
  *     E(X) = E_align + alpha E_reg + beta E_rot                     (Eq. 4)
  * with Welsch's function on alignment and regularization residuals
- * (Eqs. 5-9), by MM iterations whose quadratic surrogate is minimized
- * through the normal equations K X = B (Eq. 16), accelerated by Anderson
+ * (Eqs. 5-10), by MM iterations whose quadratic surrogate is minimized
+ * through the normal equations K X = B (Eq. 21), accelerated by Anderson
  * acceleration with an energy-decrease fallback, inside the nu
  * continuation of Alg. 2.
  *
@@ -63,7 +63,7 @@ typedef enum { AMM_F32 = 0, AMM_F64 = 1 } amm_dtype;
  *                  and its solve are float64. */
 typedef enum { AMM_FP64_PLAIN = 0, AMM_FP32_REFINE = 1 } amm_precision;
 
-/* Preconditioner of the CG solve of Eq. (16).  Block Jacobi inverts the 4x4
+/* Preconditioner of the CG solve of Eq. (21).  Block Jacobi inverts the 4x4
  * diagonal blocks of K (one per node and column).  Two-level adds a coarse
  * correction P A_c^{-1} P^T, A_c = P^T K P, over one affine field per
  * aggregate of spatially consecutive graph nodes (at most 32 aggregates per
@@ -99,7 +99,7 @@ typedef struct {
      * rule: nu_a0 = median closest-point distance at the initial X,
      * nu_a_min = mean_edge_len / sqrt(3), nu_r0 = 3 mean_edge_len. */
     double nu_a0, nu_a_min, nu_r0;
-    /* term weights of Eq. (21): alpha = k_alpha |V|/|E_G| nu_r^2/nu_a^2,
+    /* term weights of Eq. (26): alpha = k_alpha |V|/|E_G| nu_r^2/nu_a^2,
      * beta = k_beta |V|/|V_G| / (2 nu_a^2), recomputed at every stage. */
     double k_alpha, k_beta;
     double eps;                   /* stage ends when max_i |v_hat_i^{k+1} - v_hat_i^k| < eps */
@@ -228,7 +228,7 @@ typedef struct {
     void* d2;                /* [n_src] squared closest distance, or NULL */
     void* v_hat;             /* [n_src][3] warped points at X^k, or NULL */
     void* X_next;            /* [n_nodes][4][3] minimizer of the surrogate, or NULL */
-    /* Normal equations of Eq. (16) at X^k in node order of the caller, or NULL:
+    /* Normal equations of Eq. (21) at X^k in node order of the caller, or NULL:
      * K_blocks [nnzb][4][4], K_row/K_col [nnzb] node ids, B [n_nodes][4][3].
      * Query nnzb with amm_k_nnzb. */
     void* K_blocks;

@@ -15,10 +15,10 @@ Everything is float64 numpy/scipy, written step by step from the paper:
 * edge normalization weights r_ij ............. Eq. (8)
 * projection onto SO(3) ....................... Sec. 3.2 (rotation term)
 * quadratic surrogate, matrix form, normal
-  equations K X = B ........................... Sec. 3.3.1-3.3.2, Eqs. (12)-(16)
+  equations K X = B ........................... Sec. 3.3.1-3.3.2, Eqs. (13)-(21)
 * nu continuation ............................. Sec. 3.3.3
-* Anderson acceleration + energy fallback ..... Sec. 3.3.4, Eqs. (17)-(18), Alg. 2
-* weight rule for alpha, beta ................. Eq. (21)
+* Anderson acceleration + energy fallback ..... Sec. 3.3.4, Eqs. (22)-(23), Alg. 2
+* weight rule for alpha, beta ................. Eq. (26)
 
 Readings taken where the paper is silent or garbled are listed with the
 functions that take them (search for "Reading").  The gradient of the energy
@@ -132,14 +132,14 @@ def welsch(x2, nu):
 
 
 def welsch_weight(y2, nu):
-    """Coefficient of x^2 in the surrogate of Eq. (12) at y:
+    """Coefficient of x^2 in the surrogate of Eq. (13) at y:
     (1 - psi(y)) / (2 nu^2) = exp(-y^2/(2 nu^2)) / (2 nu^2).  These are the
     squared entries of W_a and W_r in Sec. 3.3.2."""
     return np.exp(-np.asarray(y2, np.float64) / (2.0 * nu * nu)) / (2.0 * nu * nu)
 
 
 def welsch_surrogate(x, y, nu):
-    """Eq. (12): psi(x|y) = psi(y) + (1 - psi(y))/(2 nu^2) (x^2 - y^2)."""
+    """Eq. (13): psi(x|y) = psi(y) + (1 - psi(y))/(2 nu^2) (x^2 - y^2)."""
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
     return welsch(y * y, nu) + welsch_weight(y * y, nu) * (x * x - y * y)
@@ -267,7 +267,7 @@ def rescore(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta) -> Eval:
 
 
 # --------------------------------------------------------------------------
-# surrogate in matrix form and its minimizer (Sec. 3.3.2, Eq. 16)
+# surrogate in matrix form and its minimizer (Sec. 3.3.2, Eq. 21)
 # --------------------------------------------------------------------------
 
 def matrices(prob: Problem, ev: Eval, nu_a: float, nu_r: float):
@@ -302,7 +302,7 @@ def matrices(prob: Problem, ev: Eval, nu_a: float, nu_r: float):
 
 
 def normal_equations(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta):
-    """Eq. (16): K = F^T W_a^2 F + alpha H^T W_r^2 H + beta J^T J,
+    """Eq. (21): K = F^T W_a^2 F + alpha H^T W_r^2 H + beta J^T J,
     B = F^T W_a^2 Q + alpha H^T W_r^2 Y + beta J^T J Z."""
     F, Q, wa, H, Y, wr, J, Z = matrices(prob, ev, nu_a, nu_r)
     Wa = sp.diags(wa)
@@ -313,7 +313,7 @@ def normal_equations(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta):
 
 
 def mm_update(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta):
-    """Minimizer of the quadratic surrogate: solve K X = B (Eq. 16) with one
+    """Minimizer of the quadratic surrogate: solve K X = B (Eq. 21) with one
     sparse LU factorization and three right-hand sides."""
     K, B = normal_equations(prob, ev, nu_a, nu_r, alpha, beta)
     lu = spla.splu(K)
@@ -323,9 +323,9 @@ def mm_update(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta):
 
 def surrogate_value(prob: Problem, X: np.ndarray, ev: Eval, nu_a, nu_r, alpha, beta,
                     src: Optional[np.ndarray] = None) -> float:
-    """Full surrogate E(X | X^k) with the constants of Eq. (12) kept, so that
-    it equals E at X^k: alignment with fixed u^k (Eqs. 12, 14-15),
-    regularization (Eq. 13) and rotation with fixed proj(A^k)."""
+    """Full surrogate E(X | X^k) with the constants of Eq. (13) kept, so that
+    it equals E at X^k: alignment with fixed u^k (Eqs. 13, 15-16),
+    regularization (Eq. 14) and rotation with fixed proj(A^k)."""
     vhat = warp(prob, X, src)
     u = prob.tgt[ev.rho]
     x2 = ((vhat - u) ** 2).sum(1)
@@ -367,7 +367,7 @@ def _cholesky_solve(G: np.ndarray, b: np.ndarray, rel_pivot: float = 1e-14):
 
 
 def anderson(hist_G: List[np.ndarray], hist_F: List[np.ndarray], m: int):
-    """Eqs. (17)-(18), standard type-II Anderson acceleration over the last
+    """Eqs. (22)-(23), standard type-II Anderson acceleration over the last
     m_k + 1 entries of the history (G^(k) = G(X^(k)), F^(k) = G^(k) - X^(k)):
     theta = argmin |F^k - sum_j theta_j (F^(k-j+1) - F^(k-j))|^2, then
     X_AA = G^k - sum_j theta_j (G^(k-j+1) - G^(k-j)).
@@ -391,7 +391,7 @@ def anderson(hist_G: List[np.ndarray], hist_F: List[np.ndarray], m: int):
 
 
 # --------------------------------------------------------------------------
-# parameters (Sec. 3.3.3, Eq. 21)
+# parameters (Sec. 3.3.3, Eq. 26)
 # --------------------------------------------------------------------------
 
 @dataclasses.dataclass
@@ -408,7 +408,7 @@ class Params:
 
 
 def term_weights(prob: Problem, p: Params, nu_a: float, nu_r: float):
-    """Eq. (21): alpha = k_alpha |V|/|E_G| nu_r^2/nu_a^2,
+    """Eq. (26): alpha = k_alpha |V|/|E_G| nu_r^2/nu_a^2,
     beta = k_beta |V|/|V_G| / (2 nu_a^2).  Reading: recomputed at every nu
     stage."""
     N, n, E = prob.n_src, prob.n_nodes, prob.n_undirected
@@ -452,7 +452,7 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
       solves in the stage; the whole solve ends after the stage whose nu_a
       equals its lower bound, or when the solve budget is used up;
     * at every new stage nu_a = max(nu_a/2, lower bound), nu_r = nu_r/2,
-      alpha and beta follow Eq. (21), the history is cleared.
+      alpha and beta follow Eq. (26), the history is cleared.
     `force[t]` overrides the accept/reject decision of solve t (replay)."""
     X = identity(prob.n_nodes) if X0 is None else np.array(X0, np.float64)
     ev0 = evaluate(prob, X, 1.0, 1.0, 0.0, 0.0, nn=nn)

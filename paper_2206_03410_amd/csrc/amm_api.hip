@@ -729,7 +729,7 @@ amm_status true_residual(amm_handle* h, T* rhs_out, std::vector<double>& rel) {
     return AMM_OK;
 }
 
-// Solves the normal equations K X' = B (Eq. 16) for the pairs flagged
+// Solves the normal equations K X' = B (Eq. 21) for the pairs flagged
 // PF_SOLVE as the increment system K dx = r (r = B - K X^k, assembled in
 // residual form), X' = X^k + dx; dx is left in x64 (float64).  The stopping
 // test is |B - K X'| <= rtol |B| per column.
@@ -809,7 +809,7 @@ struct PairState {
     amm_stats st{};
 };
 
-// Eq. (21); a graph without edges has no regularization term
+// Eq. (26); a graph without edges has no regularization term
 void term_weights(const PairInfo& pi, double k_alpha, double k_beta, PairState& s) {
     const double N = (double)pi.N, n = (double)pi.n, E = (double)pi.n_undirected;
     s.alpha = E > 0 ? k_alpha * (N / E) * (s.nu_r * s.nu_r) / (s.nu_a * s.nu_a) : 0.0;

@@ -1,5 +1,5 @@
 // Preconditioned conjugate gradients for the normal equations K X = B of
-// Eq. (16) -- three right-hand sides sharing K -- batched over pairs, and the
+// Eq. (21) -- three right-hand sides sharing K -- batched over pairs, and the
 // coarse level of its preconditioner.
 //
 // CG variant: Chronopoulos-Gear, one reduction phase per step.  With
@@ -23,7 +23,7 @@
 // gets A_j = M, t_j = (M - I) p_j + b, i.e. per column the 4-vector of
 // node j is P_j (m, b') with P_j = [[I, 0], [d_j^T, 1]], d_j = p_j - centroid.
 // These fields are the smooth modes that block Jacobi damps slowest (the
-// regularization term of Eq. (10) vanishes on a common affine map).  P^T r
+// regularization term of Eq. (9) vanishes on a common affine map).  P^T r
 // of the new residual is carried by the recurrences
 //   P^T s_i = P^T w_i + beta P^T s_{i-1},  P^T r_{i+1} = P^T r_i - alpha P^T s_i,
 // whose P^T w term is a tile partial of the previous step, so the coarse

@@ -20,7 +20,7 @@ namespace amm {
 // ---------------------------------------------------------------- evaluation
 
 // Per source point: warp (Eq. 2), closest target, Welsch value and weight
-// (Eqs. 5, 6, 15), the alignment residual e_i = v_hat_i - u_rho(i), and the
+// (Eqs. 5, 6 and the weight w_a of Eq. 16), the alignment residual e_i = v_hat_i - u_rho(i), and the
 // max displacement against the accepted iterate.  One thread per point.
 template <typename T>
 __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
 }
 
 // Per directed node pair (a, b): D_ab of Eq. (7) (transform of b applied at
-// p_a), Welsch value and weight (Eqs. 9, 13).  Evaluated as
+// p_a), Welsch value and weight (Eqs. 9, 14).  Evaluated as
 // r ((A_b - I)(p_a - p_b) + t_b - t_a), equal to Eq. (7) and free of the
 // cancellation between p_a and p_b.
 template <typename T>
@@ -307,13 +307,13 @@ __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
 // ---------------------------------------------------------------- assembly
 
 
-// Row j of K and B (Eq. 16) and of the residual r = B - K X^k, one wave per
+// Row j of K and B (Eq. 21) and of the residual r = B - K X^k, one wave per
 // node.  Alignment blocks K_jl = sum_i w_a,i w_ij w_il [v_i - p_j; 1]
 // [v_i - p_l; 1]^T are formed as moments anchored at p_j,
 // M_jl = sum c_i w_il x x^T with x = [v_i - p_j; 1], then shifted:
 // K_jl = M_jl S^T, S = [[I, p_j - p_l], [0, 1]].  Lanes first own points
 // (stage moments in LDS), then own columns of the row (gather in a fixed
-// order).  Edge blocks follow Eqs. (7), (13) and the matrix H; the rotation
+// order).  Edge blocks follow Eqs. (7), (14) and the matrix H; the rotation
 // term adds beta J^T J.  The residual is assembled from the residuals at
 // X^k themselves -- r = -sum w_a F^T e - alpha sum w_r H^T D + beta J(Z - X^k)
 // -- instead of as the difference B - K X^k of two large rounded
@@ -726,7 +726,7 @@ __global__ void __launch_bounds__(64) k_aa_solve(AaSolveArgs a) {
     out.aa_used = 1;
 }
 
-// X_AA = G^(k) - sum_a theta_a (G^(k-a+1) - G^(k-a)) (Eq. 17) into the
+// X_AA = G^(k) - sum_a theta_a (G^(k-a+1) - G^(k-a)) (Eq. 23) into the
 // candidate transform set; equals G^(k) when Anderson is not used.
 template <typename T>
 __global__ void k_aa_mix(AaArgs<T> a) {

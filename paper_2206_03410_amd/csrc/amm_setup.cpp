@@ -1,7 +1,7 @@
 // Host-side validation of registration problems and construction of the
 // device layout: spatial (Morton) ordering of points, nodes and targets, the
 // bounding-box tree over each target set, the node adjacency with the edge
-// weights of Eq. (8), the block pattern of K (Eq. 16) and the per-node lists
+// weights of Eq. (8), the block pattern of K (Eq. 21) and the per-node lists
 // of influenced points used by the row-wise assembly.
 #include <algorithm>
 #include <cmath>

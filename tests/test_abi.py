@@ -40,7 +40,7 @@ def test_status_strings_and_version():
 def test_params_default_are_the_paper_values():
     p = amm.amm_params_default()
     assert p.eps == 1e-5 and p.imax == 100           # Sec. 4.1
-    assert p.k_alpha == 100.0 and p.k_beta == 1.0     # Eq. (21) scales
+    assert p.k_alpha == 100.0 and p.k_beta == 1.0     # Eq. (26) scales
     assert p.nu_a0 <= 0 and p.nu_a_min <= 0 and p.nu_r0 <= 0   # Sec. 3.3.3 rules
     assert p.cg_rtol == 1e-10
     assert p.precision == amm.AMM_FP32_REFINE

@@ -34,7 +34,7 @@ def _kdtree_nn(tgt):
 
 
 def _scalars(prob, nn):
-    """Sec. 3.3.3 start values and Eq. (21) weights at X = I."""
+    """Sec. 3.3.3 start values and Eq. (26) weights at X = I."""
     p = O.Params()
     _, d2, _ = nn(prob.src, prob.tgt)
     nu_a, _, nu_r = O.initial_nu(prob, p, d2)

@@ -93,7 +93,7 @@ def test_step_parity(pair, prec, precond):
     if prec == "f64":
         ok2 = margin_ok(ev.d2, ev.d2_second)
         assert np.array_equal(rho[ok2], ev.rho[ok2])
-    # normal equations (Eq. 16) at the oracle's evaluation
+    # normal equations (Eq. 21) at the oracle's evaluation
     Ko, Bo = O.normal_equations(prob, ev, nu_a, nu_r, alpha, beta)
     Kg = _K_dense(Kb, Kr, Kc, n)
     Kd = Ko.toarray()
@@ -215,7 +215,7 @@ def test_solve_free_run_equal_error(prec):
     The stopping test (max displacement < eps) fires during a slow drift, so
     where each run stops is a discrete decision taken at the margin; the
     runs are compared on their registration error against the ground-truth
-    warp (Eq. 20): equal within max(1e-4 diag, 1%)."""
+    warp (Eq. 25): equal within max(1e-4 diag, 1%)."""
     _announce(f"test_solve_free_run_equal_error {prec}")
     np_dt = np.float64 if prec == "f64" else np.float32
     dt = torch.float64 if prec == "f64" else torch.float32

@@ -17,7 +17,7 @@ from paper_2206_03410_amd import synth
 
 
 # --------------------------------------------------------------------------
-# Welsch function, Eq. (6), and its surrogate, Eq. (12)
+# Welsch function, Eq. (6), and its surrogate, Eq. (13)
 # --------------------------------------------------------------------------
 
 def test_welsch_closed_form_values():
@@ -202,7 +202,7 @@ def test_rigid_motion_is_zero_energy_state(small_pair):
 
 
 # --------------------------------------------------------------------------
-# the surrogate and its minimizer (Eqs. 12-16)
+# the surrogate and its minimizer (Eqs. 13-21)
 # --------------------------------------------------------------------------
 
 def _stage_scalars(prob, p=O.Params()):
@@ -282,7 +282,7 @@ def test_dense_lstsq_matches_sparse_solve(small_prob):
 
 
 def test_large_nu_limit_is_l2_least_squares(small_prob):
-    """With Eq. (21) scaling and nu_a = nu_r -> infinity, the MM step is the
+    """With Eq. (26) scaling and nu_a = nu_r -> infinity, the MM step is the
     l2 problem of Sec. 4.2 with weights 1, k_a |V|/|E_G|, k_b |V|/|V_G|.
     The l2 rows are built here from the warp's Jacobian (by exact finite
     differences of the warp and of Eq. 7, both linear), not from F and H."""
@@ -406,7 +406,7 @@ def test_energy_grad_matches_central_differences(small_prob):
 
 
 def test_energy_grad_equals_surrogate_gradient_at_tangent_point(small_prob):
-    """The surrogate is tangent to E at X^k (Eq. 12), so grad E(X^k) =
+    """The surrogate is tangent to E at X^k (Eq. 13), so grad E(X^k) =
     2 (K X^k - B)."""
     prob = small_prob
     nu_a, nu_r, alpha, beta = _stage_scalars(prob)
