@@ -73,6 +73,7 @@ def gpu_problem(amm, torch, pair):
 
 
 def run_solve(amm, torch, h, pair, prec, iters, aa_m, timing=None):
+    """One solve from X = I with a budget of `iters` MM iterations."""
     dt = torch.float32 if prec == amm.AMM_FP32_REFINE else torch.float64
     X = torch.empty(pair.n_nodes, 4, 3, dtype=dt, device="cuda:0")
     v = torch.empty(pair.n_src, 3, dtype=dt, device="cuda:0")
@@ -88,6 +89,33 @@ def run_solve(amm, torch, h, pair, prec, iters, aa_m, timing=None):
     if timing is not None:
         amm.amm_enable_timing(h, False)
     return st, wall, v.cpu().numpy().astype(np.float64), kt
+
+
+def timed_steps(amm, torch, h, pair, prec, steps, aa_m, repeats):
+    """Exactly `steps` MM iterations per timed region: solves from X = I run
+    back to back (a solve that converges early is followed by another, the
+    last one capped at the remaining budget), bracketed by device
+    synchronizations.  Returns the per-region wall times, the first solve's
+    stats and the CG/refinement totals of one region."""
+    dt = torch.float32 if prec == amm.AMM_FP32_REFINE else torch.float64
+    X = torch.empty(pair.n_nodes, 4, 3, dtype=dt, device="cuda:0")
+    walls, first, totals = [], None, None
+    for r in range(repeats):
+        done, cg, refine, solves = 0, 0, 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < steps:
+            prm = amm.amm_params_default(aa_m=aa_m, max_total_iters=steps - done, precision=prec)
+            st = amm.amm_solve(h, prm, X, None)[0]
+            first = first or st
+            done += st["iters"]
+            cg += st["cg_iters"]
+            refine += st["refine_steps"]
+            solves += 1
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        totals = {"cg_iters": cg, "refine_steps": refine, "solves": solves}
+    return walls, first, totals
 
 
 def cpu_baseline(pair, sample=1000):
@@ -199,32 +227,41 @@ def main():
 
     pair = load_pair(args.workload)
     aa_m = synth.WORKLOADS[args.workload]["aa_m"]
+    repeats = 5
     h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
     try:
         amm.amm_set_problem(h, gpu_problem(amm, torch, pair))
         pair.nnzb = amm.amm_k_nnzb(h)
-        # warm-up, every kernel group timed (per-stage breakdown, dominant kernel)
+        # warm-up: every kernel group timed (per-stage breakdown, dominant kernel)
         st_w, wall_w, _, kt_w = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.warmup, aa_m,
                                           timing="")
+        run_solve(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.warmup, aa_m)
         dom = max(kt_w, key=lambda k: kt_w[k][0])
         log(f"[bench] warm-up {args.warmup} iters {wall_w * 1e3:.1f} ms; kernel groups: "
             + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in sorted(kt_w.items(), key=lambda x: -x[1][0])))
-        # timed FP32 + refinement, HIP events around the dominant group only
-        st32, wall32, v32, kt32 = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m,
-                                            timing=dom)
-        log(f"[bench] fp32+refine: {st32['iters']} iters in {wall32:.3f}s; cg {st32['cg_iters']} "
-            f"refine {st32['refine_steps']} rel.res {st32['max_rel_residual']:.1e}")
+        # timed: exactly `steps` MM iterations per region, median of `repeats` regions
+        w32, st32, tot32 = timed_steps(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m, repeats)
+        wall32 = float(np.median(w32))
+        log(f"[bench] fp32+refine: {args.steps} iters, median {wall32:.4f}s of {['%.4f' % w for w in w32]}; "
+            f"{tot32['solves']} solve(s), cg {tot32['cg_iters']} refine {tot32['refine_steps']}")
+        # the dominant kernel's own duration (events on its dispatches) and the
+        # deformed points for the error comparison, one more (untimed) solve
+        _, _, v32, kt32 = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m, timing=dom)
         plain = None
         if not args.no_plain:
-            st64, wall64, v64, _ = run_solve(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.steps, aa_m)
-            log(f"[bench] fp64 plain: {st64['iters']} iters in {wall64:.3f}s; cg {st64['cg_iters']}")
+            w64, st64, tot64 = timed_steps(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.steps, aa_m, repeats)
+            _, _, v64, _ = run_solve(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.steps, aa_m)
+            wall64 = float(np.median(w64))
+            log(f"[bench] fp64 plain: {args.steps} iters, median {wall64:.4f}s; {tot64['solves']} solve(s), "
+                f"cg {tot64['cg_iters']}")
             rm32 = math.sqrt(((v32 - pair.gt) ** 2).sum(1).mean())
             rm64 = math.sqrt(((v64 - pair.gt) ** 2).sum(1).mean())
-            plain = {"iters_per_s": st64["iters"] / wall64, "ms_per_iter": 1e3 * wall64 / st64["iters"],
-                     "iters": st64["iters"], "cg_iters": st64["cg_iters"],
+            plain = {"iters_per_s": args.steps / wall64, "ms_per_iter": 1e3 * wall64 / args.steps,
+                     "region_s": w64, "solves": tot64["solves"], "cg_iters": tot64["cg_iters"],
+                     "first_solve_iters": st64["iters"],
                      "rmse_gt_fp32": rm32, "rmse_gt_fp64": rm64,
                      "equal_error": abs(rm32 - rm64) <= max(1e-4, 0.01 * rm64),
-                     "speedup_fp32_refine": (st32["iters"] / wall32) / (st64["iters"] / wall64)}
+                     "speedup_fp32_refine": wall64 / wall32}
     finally:
         amm.amm_destroy(h)
 
@@ -242,20 +279,23 @@ def main():
               for k, v in kt_w.items()}
     out = {
         "metric": "MM iterations/s at 200k points, FP32+refine vs plain; batched pairs/s at equal err",
-        "value": st32["iters"] / wall32, "unit": "MM iterations/s", "n_gpus": 1,
-        "steps": st32["iters"], "warmup": args.warmup, "ms_per_step": 1e3 * wall32 / st32["iters"],
+        "value": args.steps / wall32, "unit": "MM iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall32 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {pair.n_src} source / {pair.n_tgt} target points, "
                                f"{pair.n_nodes} nodes, k={pair.k}, {pair.n_edges} node edges, "
-                               f"{args.steps} MM iterations, Anderson m={aa_m}, FP32 + FP64 refinement "
-                               f"to relative residual 1e-10",
+                               f"{args.steps} MM iterations per timed region (solves from X = I back to "
+                               f"back), Anderson m={aa_m}, FP32 + FP64 refinement to relative residual 1e-10, "
+                               f"median of {repeats} regions",
                    "n_src": pair.n_src, "n_tgt": pair.n_tgt, "n_nodes": pair.n_nodes, "k": pair.k,
                    "n_edges": pair.n_edges, "nnzb": pair.nnzb},
         "roofline": roofline,
         "plain_fp64": plain,
         "stages_warmup": stages,
-        "solve": {"cg_iters": st32["cg_iters"], "refine_steps": st32["refine_steps"],
+        "timed_regions_s": w32,
+        "solve": {"first_solve_iters": st32["iters"], "solves_per_region": tot32["solves"],
+                  "cg_iters_per_region": tot32["cg_iters"], "refine_steps_per_region": tot32["refine_steps"],
                   "aa_accepted": st32["aa_accepted"], "aa_rejected": st32["aa_rejected"],
                   "energy": st32["energy"], "max_rel_residual": st32["max_rel_residual"]},
     }

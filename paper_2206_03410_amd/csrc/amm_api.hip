@@ -8,7 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,7 +31,7 @@ thread_local std::string g_last_error;
 
 const char* kVersion = "amm-gfx950 0.1";
 constexpr int kDynRing = 16;
-constexpr int kCgRing = 4;
+constexpr int kCgLookahead = 4;   // CG steps in flight ahead of the last one completed
 
 struct EventTimer final : KernelTimer {
     struct Rec {
@@ -71,6 +73,13 @@ struct EventTimer final : KernelTimer {
         hipEvent_t b = get();
         (void)hipEventRecord(b, s);
         pending.push_back({cur_name, cur_a, b});
+    }
+    bool dispatch(const char* name, hipEvent_t* start, hipEvent_t* stop) override {
+        if (!only.empty() && only != name) return false;
+        *start = get();
+        *stop = get();
+        pending.push_back({name, *start, *stop});
+        return true;
     }
     void collect() {
         for (auto& r : pending) {
@@ -297,8 +306,11 @@ struct amm_handle {
     int dyn_slot = 0;
     PairOut* h_out = nullptr;        // pinned
     CgState* h_state = nullptr;      // pinned
-    CgState* cg_ring = nullptr;      // pinned [kCgRing][2P] asynchronous copies of the CG state
-    hipEvent_t cg_ev[kCgRing] = {};
+    // CG progress written by the step kernels straight into coherent pinned
+    // host memory: [2p] = last step completed, [2p+1] = step at which all
+    // three columns had converged (-1 while not)
+    int* prog = nullptr;
+    int* prog_dev = nullptr;
     size_t h_cap = 0;
     bool timing = false;
     bool cg_coarse = true;           // two-level CG preconditioner
@@ -405,14 +417,13 @@ amm_status ensure_host(amm_handle* h, size_t P) {
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);
     if (h->dyn_pinned) (void)hipHostFree(h->dyn_pinned);
-    if (h->cg_ring) (void)hipHostFree(h->cg_ring);
+    if (h->prog) (void)hipHostFree(h->prog);
     h->h_out = nullptr;
     h->h_state = nullptr;
     h->dyn_pinned = nullptr;
-    h->cg_ring = nullptr;
-    for (int s = 0; s < kCgRing; ++s)
-        if (!h->cg_ev[s]) HIPC(hipEventCreateWithFlags(&h->cg_ev[s], hipEventDisableTiming));
-    HIPC(hipHostMalloc((void**)&h->cg_ring, sizeof(CgState) * 2 * P * kCgRing));
+    h->prog = nullptr;
+    HIPC(hipHostMalloc((void**)&h->prog, sizeof(int) * 2 * P, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPC(hipHostGetDevicePointer((void**)&h->prog_dev, h->prog, 0));
     HIPC(hipHostMalloc((void**)&h->h_out, sizeof(PairOut) * P));
     HIPC(hipHostMalloc((void**)&h->h_state, sizeof(CgState) * 2 * P));
     HIPC(hipHostMalloc((void**)&h->dyn_pinned, sizeof(PairDyn) * kDynRing * P));
@@ -576,6 +587,7 @@ CgArgs<T> cg_args(amm_handle* h, const T* b, const T* bnorm, double rtol) {
     a.node_rel = statics<T>(h).node_rel;
     a.tile_agg_ptr = h->v.tile_agg_ptr;
     a.tile_agg = h->v.tile_agg;
+    a.prog = h->prog_dev;
     return a;
 }
 
@@ -638,58 +650,53 @@ struct SolveReport {
 };
 
 // CG over the pairs flagged PF_SOLVE until all their columns converged.
-// The host never waits on the device inside the loop: every few steps it
-// queues an asynchronous copy of the per-pair CG state into a pinned ring
-// slot and polls the oldest slot's event; once a polled copy shows every
-// pair converged it stops launching (steps already queued return at once
-// for converged pairs).  Adds each pair's iteration count to rep.
+// The host never copies state back inside the loop: the step kernels report
+// their progress in coherent pinned host memory, and the host keeps at most
+// kCgLookahead steps in flight, stopping as soon as every pair reports
+// convergence (steps already queued return at once for converged pairs).
+// Adds each pair's iteration count to rep.
 template <typename T>
 amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int maxit, SolveReport& rep) {
     const Layout& L = h->L;
     const int nt = L.n_nd_tiles;
     const int P = L.P;
+    volatile int* pg = h->prog;
+    for (int p = 0; p < P; ++p) {
+        pg[2 * p] = -2;
+        pg[2 * p + 1] = -1;
+    }
+    std::atomic_thread_fence(std::memory_order_seq_cst);
     CgArgs<T> a = cg_args<T>(h, b, bnorm, rtol);
     launch_cg_init<T>(a, nt, h->stream, tmr(h));
-    constexpr int kPoll = 8;
-    struct Pending {
-        int slot, it;
-    };
-    std::vector<Pending> pending;
-    int next_slot = 0;
-    auto converged_in = [&](int slot, int it) {
-        const CgState* st = h->cg_ring + (size_t)slot * 2 * P;
-        for (int p = 0; p < P; ++p) {
-            if (!(h->dyn[p].flags & PF_SOLVE)) continue;
-            const CgState& s2 = st[2 * p + (it & 1)];
-            if (!(s2.conv[0] && s2.conv[1] && s2.conv[2])) return false;
-        }
+    auto all_converged = [&]() {
+        for (int p = 0; p < P; ++p)
+            if ((h->dyn[p].flags & PF_SOLVE) && pg[2 * p + 1] < 0) return false;
         return true;
     };
-    bool done = false;
+    auto slowest = [&]() {
+        int m = INT_MAX;
+        for (int p = 0; p < P; ++p)
+            if ((h->dyn[p].flags & PF_SOLVE) && pg[2 * p + 1] < 0) m = std::min(m, (int)pg[2 * p]);
+        return m;
+    };
     int launched = 0;
+    bool done = false;
     for (int it = 0; it < maxit && !done; ++it) {
+        if (it > 0 && all_converged()) break;
+        const auto t_wait = std::chrono::steady_clock::now();
+        while (it - slowest() > kCgLookahead) {
+            if (all_converged()) {
+                done = true;
+                break;
+            }
+            if (std::chrono::steady_clock::now() - t_wait > std::chrono::seconds(60)) {
+                (void)hipStreamSynchronize(h->stream);
+                return fail(h, AMM_ERR_HIP, "CG steps made no progress for 60 s");
+            }
+        }
+        if (done) break;
         launch_cg_iter<T>(a, nt, it, h->stream, tmr(h));
         launched = it + 1;
-        if ((it + 1) % kPoll == 0) {
-            if ((int)pending.size() == kCgRing) {
-                // ring full: wait for the oldest copy
-                HIPC(hipEventSynchronize(h->cg_ev[pending.front().slot]));
-            }
-            while (!pending.empty()) {
-                const hipError_t q = hipEventQuery(h->cg_ev[pending.front().slot]);
-                if (q == hipErrorNotReady) break;
-                if (q != hipSuccess) return fail(h, AMM_ERR_HIP, "hipEventQuery failed in the CG loop");
-                if (converged_in(pending.front().slot, pending.front().it)) done = true;
-                pending.erase(pending.begin());
-            }
-            if (done) break;
-            const int slot = next_slot;
-            next_slot = (next_slot + 1) % kCgRing;
-            HIPC(hipMemcpyAsync(h->cg_ring + (size_t)slot * 2 * P, h->v.state, sizeof(CgState) * 2 * P,
-                                hipMemcpyDeviceToHost, h->stream));
-            HIPC(hipEventRecord(h->cg_ev[slot], h->stream));
-            pending.push_back({slot, it});
-        }
     }
     const int last = launched - 1;
     HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * P, hipMemcpyDeviceToHost, h->stream));
@@ -778,7 +785,7 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
                 any = true;
                 rep.refine[p] += 1;
                 // reduce the residual just past the target, within float32 reach
-                h->dyn[p].cg_rtol = std::min(0.25, std::max(1e-5, 0.5 * rtol / rel[p]));
+                h->dyn[p].cg_rtol = std::min(0.25, std::max(1e-6, 0.5 * rtol / rel[p]));
             }
             prev[p] = rel[p];
         }
@@ -1262,9 +1269,7 @@ void amm_destroy(amm_handle* h) {
     (void)hipStreamSynchronize(h->stream);
     for (int s = 0; s < kDynRing; ++s)
         if (h->dyn_ev[s]) (void)hipEventDestroy(h->dyn_ev[s]);
-    for (int s = 0; s < kCgRing; ++s)
-        if (h->cg_ev[s]) (void)hipEventDestroy(h->cg_ev[s]);
-    if (h->cg_ring) (void)hipHostFree(h->cg_ring);
+    if (h->prog) (void)hipHostFree(h->prog);
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);

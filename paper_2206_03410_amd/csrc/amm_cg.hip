@@ -129,7 +129,10 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
         if (prv->conv[0] && prv->conv[1] && prv->conv[2]) {
             // converged before this step: x is final and no later step reads
             // the vectors; carry the state to this step's slot
-            if (tid == 0 && tile == a.info[p].nd_tile0) a.state[2 * (size_t)p + (it & 1)] = *prv;
+            if (tid == 0 && tile == a.info[p].nd_tile0) {
+                a.state[2 * (size_t)p + (it & 1)] = *prv;
+                reinterpret_cast<volatile int*>(a.prog)[2 * p] = it;
+            }
             return;
         }
     }
@@ -244,6 +247,10 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             const bool any = scal[0][2] != 0.0 || scal[1][2] != 0.0 || scal[2][2] != 0.0;
             st.iters = prv->iters + (any ? 1 : 0);
             st.breakdown = prv->breakdown | brk_mask;
+            // progress for the host (coherent pinned memory)
+            volatile int* pg = a.prog + 2 * p;
+            if (!any) pg[1] = it;
+            pg[0] = it;
         }
     } else {
         if (tid < 3) {
@@ -720,12 +727,10 @@ void launch_cg_init(const CgArgs<T>& a, int n_nd_tiles, hipStream_t s, KernelTim
 
 template <typename T>
 void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, KernelTimer* tm) {
-    if (tm) tm->begin("cg_step", s);
     if (a.coarse)
-        hipLaunchKernelGGL((k_cg<T, true, false>), dim3(n_nd_tiles), dim3(kCgThreads), 0, s, a, it);
+        launch_one(tm, "cg_step", k_cg<T, true, false>, dim3(n_nd_tiles), dim3(kCgThreads), s, a, it);
     else
-        hipLaunchKernelGGL((k_cg<T, false, false>), dim3(n_nd_tiles), dim3(kCgThreads), 0, s, a, it);
-    if (tm) tm->end(s);
+        launch_one(tm, "cg_step", k_cg<T, false, false>, dim3(n_nd_tiles), dim3(kCgThreads), s, a, it);
 }
 
 template <typename T>

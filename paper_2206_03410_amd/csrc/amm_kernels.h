@@ -1,6 +1,7 @@
 // Kernel argument blocks and launchers (internal).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "amm_internal.h"
@@ -18,8 +19,25 @@ constexpr int kAaParts = 72;   // >= m(m+1)/2 + m for m = AMM_MAX_AA_M
 struct KernelTimer {
     virtual void begin(const char* name, hipStream_t s) = 0;
     virtual void end(hipStream_t s) = 0;
+    // Events to attach to the next single-kernel dispatch of group `name`
+    // (false: the group is not timed).
+    virtual bool dispatch(const char* name, hipEvent_t* start, hipEvent_t* stop) = 0;
     virtual ~KernelTimer() {}
 };
+
+// Launches one kernel.  When the timer times `name`, the start and stop
+// events ride on the dispatch packet itself (hipExtLaunchKernel), so the
+// measured time is the kernel's own execution, without the host's launch
+// latency that events recorded around the launch would include.
+template <typename F, typename... Args>
+void launch_one(KernelTimer* tm, const char* name, F kernel, dim3 grid, dim3 block, hipStream_t s,
+                Args... args) {
+    hipEvent_t e0, e1;
+    if (tm && tm->dispatch(name, &e0, &e1))
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 template <typename T>
 struct EvalArgs {
@@ -132,6 +150,7 @@ struct CgArgs {
     const int* tile_agg;
     T* gr[2];                // [nagg][12] P^T r per aggregate
     T* gs[2];                // [nagg][12] P^T s per aggregate
+    int* prog;               // host-visible [P][2]: last step completed, step of convergence
 };
 
 template <typename T>

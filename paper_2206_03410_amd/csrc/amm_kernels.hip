@@ -666,9 +666,12 @@ __global__ void __launch_bounds__(256) k_aa_gram(AaArgs<T> a) {
     if ((int)threadIdx.x < ng) a.part[(size_t)tile * kAaParts + threadIdx.x] = acc;
 }
 
-// Per pair: Gram matrix from the tile partials, Cholesky in float64; a
-// pivot <= 1e-14 * max diag falls back to theta = 0 (plain MM step).
+// Per pair: Gram matrix from the tile partials (one lane per entry, tiles
+// in order), Cholesky in float64; a pivot <= 1e-14 * max diag falls back to
+// theta = 0 (plain MM step).  The factorization is unrolled over the
+// largest window with compile-time indices, so it stays in registers.
 __global__ void __launch_bounds__(64) k_aa_solve(AaSolveArgs a) {
+    constexpr int M = AMM_MAX_AA_M;
     __shared__ double v[kAaParts];
     const int p = blockIdx.x;
     const PairDyn dy = a.dyn[p];
@@ -677,52 +680,68 @@ __global__ void __launch_bounds__(64) k_aa_solve(AaSolveArgs a) {
     const int mk = dy.aa_mk;
     const PairInfo pi = a.info[p];
     const int ng = mk * (mk + 1) / 2 + mk;
-    // pair sums of the tile partials: lanes over tiles, fixed butterfly
-    for (int g = 0; g < ng; ++g) {
+    for (int g = threadIdx.x; g < ng; g += 64) {
         double s = 0;
-        for (int t = threadIdx.x; t < pi.nd_ntile; t += 64) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
-        s = wave_sum(s);
-        if (threadIdx.x == 0) v[g] = s;
+        for (int t = 0; t < pi.nd_ntile; ++t) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
+        v[g] = s;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int x = 0; x < AMM_MAX_AA_M; ++x) out.theta[x] = 0;
+    for (int x = 0; x < M; ++x) out.theta[x] = 0;
     out.aa_used = 0;
     if (mk == 0) return;
-    double G[AMM_MAX_AA_M][AMM_MAX_AA_M], rhs[AMM_MAX_AA_M], L[AMM_MAX_AA_M][AMM_MAX_AA_M];
-    int cnt = 0;
-    for (int x = 0; x < mk; ++x)
-        for (int y = 0; y <= x; ++y) {
-            G[x][y] = G[y][x] = v[cnt];
-            ++cnt;
-        }
-    for (int x = 0; x < mk; ++x) rhs[x] = v[cnt + x];
+    // packed lower triangle: G[x][y] (y <= x) = v[x (x + 1) / 2 + y]; rhs = v[mk(mk+1)/2 + x]
     double dmax = 0;
-    for (int x = 0; x < mk; ++x) dmax = fmax(dmax, G[x][x]);
+#pragma unroll
+    for (int x = 0; x < M; ++x)
+        if (x < mk) dmax = fmax(dmax, v[x * (x + 1) / 2 + x]);
     const double tol = 1e-14 * dmax;
-    for (int jj = 0; jj < mk; ++jj) {
-        double piv = G[jj][jj];
-        for (int q = 0; q < jj; ++q) piv -= L[jj][q] * L[jj][q];
-        if (!(piv > tol)) return;
-        L[jj][jj] = sqrt(piv);
-        for (int ii = jj + 1; ii < mk; ++ii) {
-            double s = G[ii][jj];
-            for (int q = 0; q < jj; ++q) s -= L[ii][q] * L[jj][q];
-            L[ii][jj] = s / L[jj][jj];
+    double L[M][M];
+    bool ok = true;
+#pragma unroll
+    for (int jj = 0; jj < M; ++jj) {
+        if (jj < mk) {
+            double piv = v[jj * (jj + 1) / 2 + jj];
+#pragma unroll
+            for (int q = 0; q < jj; ++q) piv -= L[jj][q] * L[jj][q];
+            ok = ok && piv > tol;
+            L[jj][jj] = sqrt(fmax(piv, 1e-300));
+#pragma unroll
+            for (int ii = jj + 1; ii < M; ++ii) {
+                if (ii < mk) {
+                    double sv = v[ii * (ii + 1) / 2 + jj];
+#pragma unroll
+                    for (int q = 0; q < jj; ++q) sv -= L[ii][q] * L[jj][q];
+                    L[ii][jj] = sv / L[jj][jj];
+                }
+            }
         }
     }
-    double y[AMM_MAX_AA_M], th[AMM_MAX_AA_M];
-    for (int ii = 0; ii < mk; ++ii) {
-        double s = rhs[ii];
-        for (int q = 0; q < ii; ++q) s -= L[ii][q] * y[q];
-        y[ii] = s / L[ii][ii];
+    if (!ok) return;
+    const int r0 = mk * (mk + 1) / 2;
+    double y[M], th[M];
+#pragma unroll
+    for (int ii = 0; ii < M; ++ii) {
+        if (ii < mk) {
+            double sv = v[r0 + ii];
+#pragma unroll
+            for (int q = 0; q < ii; ++q) sv -= L[ii][q] * y[q];
+            y[ii] = sv / L[ii][ii];
+        }
     }
-    for (int ii = mk - 1; ii >= 0; --ii) {
-        double s = y[ii];
-        for (int q = ii + 1; q < mk; ++q) s -= L[q][ii] * th[q];
-        th[ii] = s / L[ii][ii];
+#pragma unroll
+    for (int ii = M - 1; ii >= 0; --ii) {
+        if (ii < mk) {
+            double sv = y[ii];
+#pragma unroll
+            for (int q = ii + 1; q < M; ++q)
+                if (q < mk) sv -= L[q][ii] * th[q];
+            th[ii] = sv / L[ii][ii];
+        }
     }
-    for (int x = 0; x < mk; ++x) out.theta[x] = th[x];
+#pragma unroll
+    for (int x = 0; x < M; ++x)
+        if (x < mk) out.theta[x] = th[x];
     out.aa_used = 1;
 }
 
@@ -932,30 +951,20 @@ template <typename T>
 void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_tiles, const FinalArgs& f,
                  int P, hipStream_t s, KernelTimer* tm) {
     if (n_pt_tiles) {
-        if (tm) tm->begin("eval_points", s);
-        hipLaunchKernelGGL(k_eval_points<T>, dim3(n_pt_tiles), dim3(kPointTile), 0, s, a);
-        if (tm) tm->end(s);
+        launch_one(tm, "eval_points", k_eval_points<T>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
     }
     if (n_eg_tiles) {
-        if (tm) tm->begin("eval_edges", s);
-        hipLaunchKernelGGL(k_eval_edges<T>, dim3(n_eg_tiles), dim3(kEdgeTile), 0, s, a);
-        if (tm) tm->end(s);
+        launch_one(tm, "eval_edges", k_eval_edges<T>, dim3(n_eg_tiles), dim3(kEdgeTile), s, a);
     }
     if (n_nd_tiles) {
-        if (tm) tm->begin("eval_nodes", s);
-        hipLaunchKernelGGL(k_eval_nodes<T>, dim3(n_nd_tiles), dim3(kNodeTile), 0, s, a);
-        if (tm) tm->end(s);
+        launch_one(tm, "eval_nodes", k_eval_nodes<T>, dim3(n_nd_tiles), dim3(kNodeTile), s, a);
     }
-    if (tm) tm->begin("energy_final", s);
-    hipLaunchKernelGGL(k_energy_final, dim3(P), dim3(64), 0, s, f);
-    if (tm) tm->end(s);
+    launch_one(tm, "energy_final", k_energy_final, dim3(P), dim3(64), s, f);
 }
 
 template <typename T>
 void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTimer* tm) {
-    if (tm) tm->begin("assemble", s);
-    hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)ntot), dim3(64), 0, s, a);
-    if (tm) tm->end(s);
+    launch_one(tm, "assemble", k_assemble<T>, dim3((unsigned)ntot), dim3(64), s, a);
 }
 
 template <typename T>
