@@ -207,6 +207,20 @@ def batched_run(amm, torch, n_pairs, aa_m):
             "converged": int(sum(s["converged"] for s in st))}
 
 
+def copy_calibration():
+    """A plain device copy of known size, for scaling the HBM traffic
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiled run: each of the 5
+    copies reads and writes 256 MiB."""
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n, "copies": 5}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,7 +230,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batched", type=int, default=0, help="also run this many batched pairs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain-copy kernel that scales the traffic counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the registration "
               "hot path runs on a single device)", file=sys.stderr)

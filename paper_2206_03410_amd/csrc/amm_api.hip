@@ -31,7 +31,7 @@ thread_local std::string g_last_error;
 
 const char* kVersion = "amm-gfx950 0.1";
 constexpr int kDynRing = 16;
-constexpr int kCgLookahead = 4;   // CG steps in flight ahead of the last one completed
+constexpr int kCgLookahead = 6;   // CG steps in flight ahead of the last one reported (every 4th)
 
 struct EventTimer final : KernelTimer {
     struct Rec {

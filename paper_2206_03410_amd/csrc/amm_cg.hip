@@ -129,10 +129,7 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
         if (prv->conv[0] && prv->conv[1] && prv->conv[2]) {
             // converged before this step: x is final and no later step reads
             // the vectors; carry the state to this step's slot
-            if (tid == 0 && tile == a.info[p].nd_tile0) {
-                a.state[2 * (size_t)p + (it & 1)] = *prv;
-                reinterpret_cast<volatile int*>(a.prog)[2 * p] = it;
-            }
+            if (tid == 0 && tile == a.info[p].nd_tile0) a.state[2 * (size_t)p + (it & 1)] = *prv;
             return;
         }
     }
@@ -247,10 +244,12 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             const bool any = scal[0][2] != 0.0 || scal[1][2] != 0.0 || scal[2][2] != 0.0;
             st.iters = prv->iters + (any ? 1 : 0);
             st.breakdown = prv->breakdown | brk_mask;
-            // progress for the host (coherent pinned memory)
+            // progress for the host (coherent pinned memory), every 4th step
+            // and at convergence: a store to host memory delays the kernel's
+            // completion, so most steps skip it
             volatile int* pg = a.prog + 2 * p;
             if (!any) pg[1] = it;
-            pg[0] = it;
+            if (!any || (it & 3) == 3) pg[0] = it;
         }
     } else {
         if (tid < 3) {

@@ -670,9 +670,11 @@ __global__ void __launch_bounds__(256) k_aa_gram(AaArgs<T> a) {
 // in order), Cholesky in float64; a pivot <= 1e-14 * max diag falls back to
 // theta = 0 (plain MM step).  The factorization is unrolled over the
 // largest window with compile-time indices, so it stays in registers.
-__global__ void __launch_bounds__(64) k_aa_solve(AaSolveArgs a) {
+__global__ void __launch_bounds__(512) k_aa_solve(AaSolveArgs a) {
     constexpr int M = AMM_MAX_AA_M;
+    constexpr int NG = 8;    // tile groups
     __shared__ double v[kAaParts];
+    __shared__ double vg[NG][kAaParts];
     const int p = blockIdx.x;
     const PairDyn dy = a.dyn[p];
     if (!(dy.flags & PF_SOLVE)) return;
@@ -680,10 +682,20 @@ __global__ void __launch_bounds__(64) k_aa_solve(AaSolveArgs a) {
     const int mk = dy.aa_mk;
     const PairInfo pi = a.info[p];
     const int ng = mk * (mk + 1) / 2 + mk;
-    for (int g = threadIdx.x; g < ng; g += 64) {
+    // entry g of group grp sums tiles grp, grp + NG, ...; the groups are then
+    // added in order
+    for (int e = threadIdx.x; e < NG * kAaParts; e += 512) {
+        const int grp = e / kAaParts, g = e - grp * kAaParts;
         double s = 0;
-        for (int t = 0; t < pi.nd_ntile; ++t) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
-        v[g] = s;
+        if (g < ng)
+            for (int t = grp; t < pi.nd_ntile; t += NG) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
+        vg[grp][g] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ng) {
+        double s = 0;
+        for (int grp = 0; grp < NG; ++grp) s += vg[grp][threadIdx.x];
+        v[threadIdx.x] = s;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -986,7 +998,7 @@ void launch_aa(const AaArgs<T>& a, const AaSolveArgs& sa, int n_nd_tiles, hipStr
     if (tm) tm->begin("anderson", s);
     hipLaunchKernelGGL(k_aa_push<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a);
     hipLaunchKernelGGL(k_aa_gram<T>, dim3(n_nd_tiles), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_aa_solve, dim3(sa.P), dim3(64), 0, s, sa);
+    hipLaunchKernelGGL(k_aa_solve, dim3(sa.P), dim3(512), 0, s, sa);
     hipLaunchKernelGGL(k_aa_mix<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a);
     if (tm) tm->end(s);
 }
