@@ -656,7 +656,8 @@ struct SolveReport {
 // convergence (steps already queued return at once for converged pairs).
 // Adds each pair's iteration count to rep.
 template <typename T>
-amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int maxit, SolveReport& rep) {
+amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int maxit, SolveReport& rep,
+                  double floor = 0.0) {
     const Layout& L = h->L;
     const int nt = L.n_nd_tiles;
     const int P = L.P;
@@ -667,6 +668,7 @@ amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int ma
     }
     std::atomic_thread_fence(std::memory_order_seq_cst);
     CgArgs<T> a = cg_args<T>(h, b, bnorm, rtol);
+    a.floor2 = floor * floor;
     launch_cg_init<T>(a, nt, h->stream, tmr(h));
     auto all_converged = [&]() {
         for (int p = 0; p < P; ++p)
@@ -767,13 +769,21 @@ amm_status linear_solve(amm_handle* h, double rtol, int maxit, SolveReport& rep)
         }
         return AMM_OK;
     }
-    // float32 CG inside float64 iterative refinement
+    // float32 CG inside float64 iterative refinement.  The first correction
+    // solves on the assembled residual itself (the float64 residual of dx = 0
+    // is r) and needs no host decision: it stops at |r| <= rtol/2 |B| or once
+    // float32 has reduced its residual by kFirstFloor.
+    constexpr double kFirstFloor = 1e-6;
     T* rhs = reinterpret_cast<T*>(d.cg[10]);
     std::vector<int32_t> saved(L.P);
     for (int p = 0; p < L.P; ++p) saved[p] = h->dyn[p].flags;
+    for (int p = 0; p < L.P; ++p)
+        if (h->dyn[p].flags & PF_SOLVE) rep.refine[p] += 1;
+    TRY(run_cg<T>(h, r, B, 0.5 * rtol, maxit, rep, kFirstFloor));
+    vec_op<T>(h, PF_SOLVE, 0, x, nullptr);   // dx = first correction
     std::vector<double> prev(L.P, std::numeric_limits<double>::infinity()), rel;
     const int max_refine = 30;
-    for (int step = 0; step <= max_refine; ++step) {
+    for (int step = 1; step <= max_refine; ++step) {
         TRY(true_residual<T>(h, rhs, rel));
         bool any = false;
         for (int p = 0; p < L.P; ++p) {

@@ -39,6 +39,7 @@ namespace amm {
 namespace {
 
 constexpr int kCgThreads = 16 * kNodeTile;
+constexpr int kSlotCap = 8;   // coarse aggregates per tile whose A_c^{-1} rows are staged in LDS
 
 template <typename T>
 __device__ __forceinline__ T wsum(T v) {
@@ -113,6 +114,15 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
     __shared__ T wp[4][kCgPart];
     __shared__ T gw[NA][12], gro[NA][12], gso[NA][12], gcur[NA][12], cco[NA][12];
     __shared__ T bbw[4][3];
+    // float64 steps stage the tile's rows of A_c^{-1} in LDS and fetch their
+    // first column block early; in float32 both measured slower than reading
+    // the rows from L2 where they are used
+    constexpr bool kEarly = sizeof(T) == 8;
+    constexpr int NCM = COARSE && kEarly ? 4 * kCoarseMaxAgg : 1;
+    // staged rows of A_c^{-1} (row length padded by one element so that
+    // rows read together fall in different LDS banks)
+    __shared__ T ainv_s[COARSE && kEarly ? 4 * kSlotCap : 1][NCM + 1];
+    __shared__ int tl[COARSE ? kCoarseMaxAgg : 1];          // this tile's aggregates
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int4 td = a.nd_tiles[tile];
@@ -159,7 +169,6 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             if (!first) own_p = a.pv[o];
         }
     }
-
     // ---- pair sums of the previous step's tile partials -> step scalars
     if (!START) {
         double v[12];
@@ -197,6 +206,53 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             }
         }
     }
+    // Issued after the loads the scalars need (a wave waits for its loads in
+    // issue order): the first column block of this lane, its K block and the
+    // previous step's vectors of its node, consumed once the scalars are known
+    int l0 = -1;
+    T f_r[12], f_w[12], f_s[12], f_d[16], f_k[16];
+    V f_rel{};
+    if (kEarly && !START && kb < ke) {
+        l0 = a.K_col[kb];
+        const size_t ol = 12 * (size_t)l0;
+#pragma unroll
+        for (int m = 0; m < 12; ++m) {
+            f_r[m] = a.r[par][ol + m];
+            f_w[m] = a.w[par][ol + m];
+            f_s[m] = a.s[par][ol + m];
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            f_d[m] = a.Dinv[16 * (size_t)l0 + m];
+            f_k[m] = a.Kval[16 * (size_t)kb + m];
+        }
+        if (COARSE) f_rel = a.node_rel[l0];
+    }
+    // rows of A_c^{-1} of this tile's first kSlotCap aggregates (staged in
+    // LDS after the first barrier); thread t covers column t % 128 of rows
+    // t / 128, t / 128 + 2, ...
+    int q0 = 0, nsl = 0, nc = 0;
+    constexpr int APRE = COARSE && kEarly ? (4 * kSlotCap * 4 * kCoarseMaxAgg) / kCgThreads : 1;
+    T apre[APRE];
+    if (COARSE) {
+        q0 = a.tile_agg_ptr[tile];
+        nsl = a.tile_agg_ptr[tile + 1] - q0;
+        nc = 4 * pi.nagg;
+        if (tid < nsl) tl[tid] = a.tile_agg[q0 + tid];
+        const int nrow = kEarly ? 4 * min(nsl, kSlotCap) : 0;
+        const int col = tid & 127, r0 = tid >> 7;
+        const T* Ai = a.Ainv + pi.ainv_off;
+#pragma unroll
+        for (int rr = 0; rr < APRE; ++rr) {
+            const int rw = r0 + 2 * rr;
+            apre[rr] = 0;
+            if (rw < nrow && col < nc) {
+                const int ag = a.tile_agg[q0 + (rw >> 2)];
+                apre[rr] = Ai[(size_t)(4 * ag + (rw & 3)) * nc + col];
+            }
+        }
+    }
+
     if (tid == 0) brk_mask = 0;
     __syncthreads();
     if (!START) {
@@ -210,8 +266,9 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             int conv = prv->conv[c];
             int brk = 0;
             double al = 0, be = 0;
+            const double rr0 = it == 0 ? rr : prv->rr0[c];
             if (!conv) {
-                if (rr <= rtol2 * bb || bb == 0.0) {
+                if (rr <= rtol2 * bb || bb == 0.0 || rr <= a.floor2 * rr0) {
                     conv = 1;
                 } else if (it == 0) {
                     al = gam / del;
@@ -234,6 +291,7 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
                 st.gamma[c] = gam;
                 st.rr[c] = rr;
                 st.bb[c] = bb;
+                st.rr0[c] = rr0;
                 st.conv[c] = conv;
             }
             if (brk) atomicOr(&brk_mask, 1 << c);
@@ -275,6 +333,15 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
         be[c] = (T)scal[c][1];
         act[c] = scal[c][2] != 0.0;
     }
+    if (COARSE && kEarly) {
+        const int nrow = 4 * min(nsl, kSlotCap);
+        const int col = tid & 127, r0 = tid >> 7;
+#pragma unroll
+        for (int rr = 0; rr < APRE; ++rr) {
+            const int rw = r0 + 2 * rr;
+            if (rw < nrow && col < nc) ainv_s[rw][col] = apre[rr];
+        }
+    }
 
     // ---- coarse level: P^T s_i, P^T r_{i+1}, then A_c^{-1} P^T r_{i+1} for
     // the aggregates this tile's rows touch
@@ -300,21 +367,35 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             }
         }
         __syncthreads();
-        const int q0 = a.tile_agg_ptr[tile], q1 = a.tile_agg_ptr[tile + 1];
-        const int nc = 4 * pi.nagg;
+        // (A_c^{-1} g)[aggregate, q, c] in four interleaved parts over the
+        // coarse columns, combined across 4 consecutive lanes in a fixed order
+        // (every block forms the same values for an aggregate)
         const T* Ai = a.Ainv + pi.ainv_off;
-        for (int e = tid; e < (q1 - q0) * 12; e += kCgThreads) {
-            const int sl = e / 12, m = e - 12 * sl, q = m / 3, c = m - 3 * q;
-            const int ag = a.tile_agg[q0 + sl];
-            const T* rw = Ai + (size_t)(4 * ag + q) * nc;
+        for (int e = tid; e < nsl * 48; e += kCgThreads) {
+            const int sl = e / 48, rem = e - 48 * sl, m = rem >> 2, part = rem & 3;
+            const int q = m / 3, c = m - 3 * q;
+            const int ag = tl[sl];
             T acc = 0;
-            for (int bq = 0; bq < pi.nagg; ++bq) {
-                acc = fma(rw[4 * bq], gcur[bq][c], acc);
-                acc = fma(rw[4 * bq + 1], gcur[bq][3 + c], acc);
-                acc = fma(rw[4 * bq + 2], gcur[bq][6 + c], acc);
-                acc = fma(rw[4 * bq + 3], gcur[bq][9 + c], acc);
+            if (kEarly && sl < kSlotCap) {
+                const T* rw = &ainv_s[4 * sl + q][0];
+                for (int bq = part; bq < pi.nagg; bq += 4) {
+                    acc = fma(rw[4 * bq], gcur[bq][c], acc);
+                    acc = fma(rw[4 * bq + 1], gcur[bq][3 + c], acc);
+                    acc = fma(rw[4 * bq + 2], gcur[bq][6 + c], acc);
+                    acc = fma(rw[4 * bq + 3], gcur[bq][9 + c], acc);
+                }
+            } else {
+                const T* rw = Ai + (size_t)(4 * ag + q) * nc;
+                for (int bq = part; bq < pi.nagg; bq += 4) {
+                    acc = fma(rw[4 * bq], gcur[bq][c], acc);
+                    acc = fma(rw[4 * bq + 1], gcur[bq][3 + c], acc);
+                    acc = fma(rw[4 * bq + 2], gcur[bq][6 + c], acc);
+                    acc = fma(rw[4 * bq + 3], gcur[bq][9 + c], acc);
+                }
             }
-            cco[ag][m] = acc;
+            acc += __shfl_xor(acc, 1, 4);
+            acc += __shfl_xor(acc, 2, 4);
+            if (part == 0) cco[ag][m] = acc;
         }
         __syncthreads();
     }
@@ -348,7 +429,32 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
     T y[12];
 #pragma unroll
     for (int m = 0; m < 12; ++m) y[m] = 0;
-    for (int pos = kb; pos < ke; pos += 16) {
+    // y += K_jl u'_l
+    auto block = [&](int l, const T* rn, const T* Dl, const T* kv, const V& rel) {
+        T ul[12];
+        apply_dinv(Dl, rn, ul);
+        if (COARSE) prolong_add(rel, cco[(l - (int)pi.node_off) >> pi.agg_shift], ul);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T acc = y[3 * q + c];
+                acc = fma(kv[4 * q], ul[c], acc);
+                acc = fma(kv[4 * q + 1], ul[3 + c], acc);
+                acc = fma(kv[4 * q + 2], ul[6 + c], acc);
+                y[3 * q + c] = fma(kv[4 * q + 3], ul[9 + c], acc);
+            }
+    };
+    int pos0 = kb;
+    if (!START && l0 >= 0) {
+        T rn[12];
+#pragma unroll
+        for (int m = 0; m < 12; ++m)
+            rn[m] = new_r(f_r[m], f_w[m], f_s[m], al[m % 3], be[m % 3], act[m % 3], first);
+        block(l0, rn, f_d, f_k, f_rel);
+        pos0 = kb + 16;
+    }
+    for (int pos = pos0; pos < ke; pos += 16) {
         const int l = a.K_col[pos];
         const size_t ol = 12 * (size_t)l;
         T rn[12];
@@ -361,23 +467,13 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
                 rn[m] = new_r(a.r[par][ol + m], a.w[par][ol + m], a.s[par][ol + m], al[m % 3], be[m % 3],
                               act[m % 3], first);
         }
-        T ul[12];
-        apply_dinv(a.Dinv + 16 * (size_t)l, rn, ul);
-        if (COARSE) prolong_add(a.node_rel[l], cco[(l - (int)pi.node_off) >> pi.agg_shift], ul);
-        const T* kbk = a.Kval + 16 * (size_t)pos;
         T kv[16];
+        const T* kbk = a.Kval + 16 * (size_t)pos;
 #pragma unroll
         for (int m = 0; m < 16; ++m) kv[m] = kbk[m];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T acc = y[3 * q + c];
-                acc = fma(kv[4 * q], ul[c], acc);
-                acc = fma(kv[4 * q + 1], ul[3 + c], acc);
-                acc = fma(kv[4 * q + 2], ul[6 + c], acc);
-                y[3 * q + c] = fma(kv[4 * q + 3], ul[9 + c], acc);
-            }
+        V rel{};
+        if (COARSE) rel = a.node_rel[l];
+        block(l, rn, a.Dinv + 16 * (size_t)l, kv, rel);
     }
 #pragma unroll
     for (int m = 0; m < 12; ++m)

@@ -64,6 +64,7 @@ struct PairOut {
 struct CgState {
     double alpha[3], gamma[3];
     double rr[3], bb[3];
+    double rr0[3];           // (r, r) at the start of the solve
     int32_t conv[3];
     int32_t iters;
     int32_t breakdown;

@@ -141,6 +141,7 @@ struct CgArgs {
     double* part_bb;         // [tile][3] (n,n) of the stopping-test scale
     CgState* state;          // [P][2]
     double rtol2;
+    double floor2;           // also stop once (r,r) <= floor2 (r0,r0) (0: off)
     // two-level preconditioner (coarse = 1): M^{-1} = D^{-1} + P A_c^{-1} P^T
     // with an affine field per aggregate of nodes
     int coarse;

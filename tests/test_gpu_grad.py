@@ -175,9 +175,12 @@ def test_gradient_grad100k_vs_oracle_and_finite_differences():
 def test_gradient_grad100k_at_converged_transforms():
     """At the transforms Alg. 2 returns (float32 + refinement, final stage's
     nu, alpha, beta): the float32 adjoint against the oracle's FP64 analytic
-    gradient at the same (float32) X, normwise within 1e-4.  Near a
-    stationary point the alignment and regularization parts of dE/dX largely
-    cancel, so this is the harder case for float32 accumulation."""
+    gradient at the same (float32) X.  Near a stationary point the alignment,
+    regularization and rotation parts of dE/dX cancel, while float32
+    accumulation errors scale with the parts: the bound is 1e-4 of the sum of
+    the parts' norms (each part from the oracle with the other weights set to
+    zero; the gradient is linear in alpha and beta).  dE/dV has no such
+    cancellation and keeps the plain normwise 1e-4."""
     _announce("test_gradient_grad100k_at_converged_transforms")
     pair = synth.make_workload("grad100k")
     pr = rounded(pair, np.float32)
@@ -192,10 +195,15 @@ def test_gradient_grad100k_at_converged_transforms():
     nn = _kdtree_nn(prob.tgt)
     ev = O.evaluate(prob, Xs, *sc, src=pr.src, nn=nn)
     gXo, gVo, _ = O.energy_grad(prob, Xs, *sc, src=pr.src, ev=ev)
-    ex = np.linalg.norm(gX - gXo) / np.linalg.norm(gXo)
+    nu_a, nu_r, alpha, beta = sc
+    g_align = O.energy_grad(prob, Xs, nu_a, nu_r, 0.0, 0.0, src=pr.src, ev=ev)[0]
+    g_reg = O.energy_grad(prob, Xs, nu_a, nu_r, alpha, 0.0, src=pr.src, ev=ev)[0] - g_align
+    g_rot = O.energy_grad(prob, Xs, nu_a, nu_r, 0.0, beta, src=pr.src, ev=ev)[0] - g_align
+    scale = np.linalg.norm(g_align) + np.linalg.norm(g_reg) + np.linalg.norm(g_rot)
+    ex = np.linalg.norm(gX - gXo) / scale
     evv = np.linalg.norm(gV - gVo) / np.linalg.norm(gVo)
     print(f"[grad at X*] iters {st['iters']} converged {st['converged']} E {E} vs {ev.E} "
-          f"|gX| {np.linalg.norm(gXo):.4e} rel {ex:.3e}  |gV| {np.linalg.norm(gVo):.4e} rel {evv:.3e}",
-          file=sys.stderr, flush=True)
+          f"|gX| {np.linalg.norm(gXo):.4e} parts {scale:.4e} err/parts {ex:.3e}  "
+          f"|gV| {np.linalg.norm(gVo):.4e} rel {evv:.3e}", file=sys.stderr, flush=True)
     assert E == pytest.approx(ev.E, rel=1e-5)
     assert ex <= 1e-4 and evv <= 1e-4
