@@ -186,6 +186,10 @@ def batched_run(amm, torch, n_pairs, aa_m):
         probs = [gpu_problem(amm, torch, p) for p in pairs]
         torch.cuda.synchronize()
         t = time.perf_counter()
+        leaf, _ = amm.amm_autotune(h, probs)
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t
+        t = time.perf_counter()
         amm.amm_set_problems(h, probs)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t
@@ -202,6 +206,7 @@ def batched_run(amm, torch, n_pairs, aa_m):
     per = np.array([s["time_ms"] for s in st])
     return {"pairs": n_pairs, "points": int(sum(p.n_src for p in pairs)),
             "pairs_per_s": n_pairs / wall, "wall_s": wall, "setup_s": t_setup,
+            "autotuned_leaf": leaf, "autotune_s": t_tune,
             "p50_pair_ms": float(np.percentile(per, 50)), "p99_pair_ms": float(np.percentile(per, 99)),
             "iters_total": int(sum(s["iters"] for s in st)),
             "converged": int(sum(s["converged"] for s in st))}
@@ -249,7 +254,9 @@ def main():
     repeats = 5
     h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
     try:
-        amm.amm_set_problem(h, gpu_problem(amm, torch, pair))
+        prob = gpu_problem(amm, torch, pair)
+        leaf, leaf_ms = amm.amm_autotune(h, [prob])
+        log(f"[bench] autotuned closest-point leaf size {leaf} (warm evaluation {leaf_ms:.3f} ms)")
         pair.nnzb = amm.amm_k_nnzb(h)
         # warm-up: every kernel group timed (per-stage breakdown, dominant kernel)
         st_w, wall_w, _, kt_w = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.warmup, aa_m,
@@ -310,6 +317,7 @@ def main():
                    "n_src": pair.n_src, "n_tgt": pair.n_tgt, "n_nodes": pair.n_nodes, "k": pair.k,
                    "n_edges": pair.n_edges, "nnzb": pair.nnzb},
         "roofline": roofline,
+        "autotuned_leaf": leaf,
         "plain_fp64": plain,
         "stages_warmup": stages,
         "timed_regions_s": w32,

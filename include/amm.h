@@ -193,6 +193,21 @@ amm_status amm_set_workspace(amm_handle* h, void* ptr, size_t bytes);
 amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_pairs);
 amm_status amm_set_problem(amm_handle* h, const amm_problem* p);
 
+/* Targets per leaf of the closest-point tree (1..256, default 8) used by the
+ * next amm_workspace_size / amm_set_problems.  Smaller leaves make the
+ * search deeper, larger ones scan more targets per leaf. */
+amm_status amm_set_leaf_size(amm_handle* h, int32_t leaf);
+
+/* Autotuner: uploads the problems once per candidate leaf size (candidates
+ * NULL: 4, 8, 16, 32), times a warm-started float32 evaluation (warp,
+ * closest points, Welsch terms, the per-iteration search of Alg. 2) of
+ * every pair at X = I with HIP events, and leaves the handle set up with the
+ * fastest.  best_leaf and best_ms (host, nullable) receive the choice and
+ * its time.  With a caller workspace, candidates that do not fit it are
+ * skipped.  Replaces any previous problems, like amm_set_problems. */
+amm_status amm_autotune(amm_handle* h, const amm_problem* probs, int32_t n_pairs, const int32_t* candidates,
+                        int32_t n_candidates, int32_t* best_leaf, double* best_ms);
+
 /* ---------------------------------------------------------------- solve */
 
 /* Alg. 2 for every pair set on the handle, all pairs advancing together.

@@ -100,6 +100,9 @@ def lib():
             "amm_set_workspace": ([vp, vp, C.c_size_t], C.c_int),
             "amm_set_problems": ([vp, C.POINTER(amm_problem), i32], C.c_int),
             "amm_set_problem": ([vp, C.POINTER(amm_problem)], C.c_int),
+            "amm_set_leaf_size": ([vp, i32], C.c_int),
+            "amm_autotune": ([vp, C.POINTER(amm_problem), i32, C.POINTER(i32), i32, C.POINTER(i32),
+                              C.POINTER(dbl)], C.c_int),
             "amm_solve": ([vp, C.POINTER(amm_params), vp, vp, C.POINTER(amm_stats)], C.c_int),
             "amm_step": ([vp, C.POINTER(amm_step_in), C.POINTER(amm_step_out)], C.c_int),
             "amm_k_nnzb": ([vp, C.POINTER(i64)], C.c_int),
@@ -125,6 +128,7 @@ def lib():
 
 EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
+            "amm_set_leaf_size", "amm_autotune",
             "amm_solve", "amm_step", "amm_k_nnzb", "amm_iter_log", "amm_energy", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
@@ -234,6 +238,22 @@ def amm_set_workspace(handle, tensor_or_none) -> None:
     else:
         nbytes = tensor_or_none.numel() * tensor_or_none.element_size()
         _check(lib().amm_set_workspace(handle, tensor_or_none.data_ptr(), nbytes), handle)
+
+
+def amm_set_leaf_size(handle, leaf: int) -> None:
+    _check(lib().amm_set_leaf_size(handle, int(leaf)), handle)
+
+
+def amm_autotune(handle, problems: Sequence[amm_problem], candidates=None):
+    """Picks the closest-point leaf size by timing a warm evaluation per
+    candidate; returns (leaf, ms).  The handle is left set up with it."""
+    arr = (amm_problem * len(problems))(*problems)
+    cand = None if candidates is None else (C.c_int32 * len(candidates))(*candidates)
+    best = C.c_int32()
+    ms = C.c_double()
+    _check(lib().amm_autotune(handle, arr, len(problems), cand, 0 if candidates is None else len(candidates),
+                              C.byref(best), C.byref(ms)), handle)
+    return best.value, ms.value
 
 
 def amm_set_problems(handle, problems: Sequence[amm_problem]) -> None:

@@ -314,6 +314,7 @@ struct amm_handle {
     size_t h_cap = 0;
     bool timing = false;
     bool cg_coarse = true;           // two-level CG preconditioner
+    int leaf = 8;                    // targets per leaf of the closest-point tree (next upload)
     EventTimer timer;
     std::vector<amm_iter_record> iter_log;
 };
@@ -1216,7 +1217,7 @@ amm_status analyse(amm_handle* h, const amm_problem* probs, int32_t n_pairs, Lay
         lbar[p] = hps[p].lbar;
     }
     std::string err;
-    amm_status s = build_layout(hps, 16, L, err);
+    amm_status s = build_layout(hps, h->leaf, L, err);
     if (s != AMM_OK) return fail(h, s, err);
     return AMM_OK;
 }
@@ -1392,6 +1393,89 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
 }
 
 amm_status amm_set_problem(amm_handle* h, const amm_problem* p) { return amm_set_problems(h, p, 1); }
+
+amm_status amm_set_leaf_size(amm_handle* h, int32_t leaf) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    if (leaf < 1 || leaf > 256) return fail(h, AMM_ERR_INVALID_ARG, "leaf size must be in 1..256");
+    h->leaf = leaf;
+    return AMM_OK;
+}
+
+namespace amm {
+namespace {
+
+// GPU time of one warm-started evaluation (warp, closest points, terms) of
+// every pair at X = I, float32: a cold evaluation seeds the closest points,
+// then the fastest of three warm ones.
+amm_status time_warm_eval(amm_handle* h, double& ms) {
+    const Layout& L = h->L;
+    Dyn& d = h->v.d;
+    std::vector<float> id(12 * L.ntot, 0.0f);
+    for (int64_t j = 0; j < L.ntot; ++j) id[12 * j] = id[12 * j + 4] = id[12 * j + 8] = 1.0f;
+    HIPC(hipMemcpyAsync(d.X[0], id.data(), id.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    for (int p = 0; p < L.P; ++p) {
+        PairDyn& dy = h->dyn[p];
+        dy = PairDyn{};
+        set_scalars(dy, 1.0, 1.0, 0.0, 0.0);
+        dy.flags = PF_EVAL;
+    }
+    TRY(evaluate<float>(h));
+    for (int p = 0; p < L.P; ++p) h->dyn[p].has_prev = 1;
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    ms = 1e30;
+    for (int r = 0; r < 3; ++r) {
+        TRY(push_dyn(h));
+        HIPC(hipEventRecord(e0, h->stream));
+        launch_eval<float>(eval_args<float>(h, false), L.n_pt_tiles, L.n_eg_tiles, L.n_nd_tiles, final_args(h), L.P,
+                           h->stream, nullptr);
+        HIPC(hipEventRecord(e1, h->stream));
+        TRY(pull_out(h));
+        float t = 0;
+        HIPC(hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, (double)t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return AMM_OK;
+}
+
+}  // namespace
+}  // namespace amm
+
+amm_status amm_autotune(amm_handle* h, const amm_problem* probs, int32_t n_pairs, const int32_t* candidates,
+                        int32_t n_candidates, int32_t* best_leaf, double* best_ms) {
+    if (!h || !probs) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    static const int32_t kDefault[] = {4, 8, 16, 32};
+    if (!candidates) {
+        candidates = kDefault;
+        n_candidates = 4;
+    }
+    if (n_candidates < 1) return fail(h, AMM_ERR_INVALID_ARG, "no candidate leaf sizes");
+    int32_t best = -1;
+    double best_t = 1e30;
+    for (int32_t c = 0; c < n_candidates; ++c) {
+        if (candidates[c] < 1 || candidates[c] > 256) return fail(h, AMM_ERR_INVALID_ARG, "candidate leaf size out of range");
+        h->leaf = candidates[c];
+        const amm_status st = amm_set_problems(h, probs, n_pairs);
+        if (st == AMM_ERR_OOM && h->ws_user) continue;   // does not fit the caller's workspace
+        if (st != AMM_OK) return st;
+        double t = 0;
+        TRY(time_warm_eval(h, t));
+        if (t < best_t) {
+            best_t = t;
+            best = candidates[c];
+        }
+    }
+    if (best < 0) return fail(h, AMM_ERR_OOM, "no candidate leaf size fits the workspace");
+    h->leaf = best;
+    TRY(amm_set_problems(h, probs, n_pairs));
+    if (best_leaf) *best_leaf = best;
+    if (best_ms) *best_ms = best_t;
+    return AMM_OK;
+}
 
 amm_status amm_solve(amm_handle* h, const amm_params* prm, void* X_inout, void* v_out, amm_stats* stats) {
     if (!h || !prm) return fail(h, AMM_ERR_INVALID_ARG, "null argument");

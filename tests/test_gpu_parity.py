@@ -328,3 +328,28 @@ def test_single_node_no_edges():
     Xo = O.mm_update(prob, ev, nu_a, nu_r, alpha, beta)[0]
     assert out["energy"][0] == pytest.approx(ev.E, rel=1e-12)
     assert np.abs(Xn - Xo).max() < 1e-9
+
+
+def test_leaf_size_and_autotune_leave_results_unchanged():
+    """The closest-point search is exact with ties to the lowest index, so the
+    tree's leaf size changes no result: whole solves with leaf sizes 4 and 32
+    agree bitwise, and the autotuner's choice is one of its candidates."""
+    _announce("test_leaf_size_and_autotune_leave_results_unchanged")
+    pair = synth.torus_pair(1000, n_src=900, n_tgt=950, n_nodes=45, k=4, e=6)
+    outs = []
+    with Session(pair, torch.float32) as s:
+        for leaf in (4, 32):
+            amm.amm_set_leaf_size(s.h, leaf)
+            amm.amm_set_problems(s.h, s.problems)
+            X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+            st = amm.amm_solve(s.h, amm.amm_params_default(aa_m=5, max_total_iters=12), X)[0]
+            torch.cuda.synchronize()
+            outs.append((X.cpu().numpy(), st["iters"], st["energy"]))
+        best, ms = amm.amm_autotune(s.h, s.problems, [4, 8, 16])
+        assert best in (4, 8, 16) and ms > 0
+        X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+        st = amm.amm_solve(s.h, amm.amm_params_default(aa_m=5, max_total_iters=12), X)[0]
+        torch.cuda.synchronize()
+        outs.append((X.cpu().numpy(), st["iters"], st["energy"]))
+    for X, it, E in outs[1:]:
+        assert np.array_equal(X, outs[0][0]) and it == outs[0][1] and E == outs[0][2]
