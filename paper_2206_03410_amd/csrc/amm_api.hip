@@ -274,8 +274,8 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(d.Ac_tile, nnd * kCoarseMaxAgg * 16);
     c.take(d.Ac, (size_t)L.ainv_size);
     c.take(d.Ainv, (size_t)L.ainv_size);
-    c.take(d.part_rr64, 3 * nnd);
-    c.take(d.part_bb64, 3 * nnd);
+    c.take(d.part_rr64, 6 * nnd);   // (r,r) then (n,n): read back in one copy
+    d.part_bb64 = d.part_rr64 ? d.part_rr64 + 3 * nnd : nullptr;
     c.take(d.G, (AMM_MAX_AA_M + 1) * 12 * n);
     c.take(d.F, (AMM_MAX_AA_M + 1) * 12 * n);
     c.take(d.aa_part, (size_t)kAaParts * nnd);
@@ -309,8 +309,11 @@ struct amm_handle {
     // CG progress written by the step kernels straight into coherent pinned
     // host memory: [2p] = last step completed, [2p+1] = step at which all
     // three columns had converged (-1 while not)
-    int* prog = nullptr;
-    int* prog_dev = nullptr;
+    long long* prog = nullptr;
+    long long* prog_dev = nullptr;
+    double* h_scratch = nullptr;     // pinned, grown on demand (small read-backs)
+    hipEvent_t sync_ev = nullptr;    // recorded to wait for the stream by polling
+    size_t h_scratch_cap = 0;
     size_t h_cap = 0;
     bool timing = false;
     bool cg_coarse = true;           // two-level CG preconditioner
@@ -423,7 +426,7 @@ amm_status ensure_host(amm_handle* h, size_t P) {
     h->h_state = nullptr;
     h->dyn_pinned = nullptr;
     h->prog = nullptr;
-    HIPC(hipHostMalloc((void**)&h->prog, sizeof(int) * 2 * P, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPC(hipHostMalloc((void**)&h->prog, sizeof(long long) * 2 * P, hipHostMallocMapped | hipHostMallocCoherent));
     HIPC(hipHostGetDevicePointer((void**)&h->prog_dev, h->prog, 0));
     HIPC(hipHostMalloc((void**)&h->h_out, sizeof(PairOut) * P));
     HIPC(hipHostMalloc((void**)&h->h_state, sizeof(CgState) * 2 * P));
@@ -451,9 +454,26 @@ amm_status push_dyn(amm_handle* h) {
     return AMM_OK;
 }
 
+// Waits for the handle's stream.  The host is usually waiting for a short
+// tail of work: polling an event for up to 2 ms wakes it far sooner than a
+// blocking wait; longer waits fall back to blocking.
+amm_status sync_spin(amm_handle* h) {
+    if (!h->sync_ev) HIPC(hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming));
+    HIPC(hipEventRecord(h->sync_ev, h->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    while (true) {
+        const hipError_t q = hipEventQuery(h->sync_ev);
+        if (q == hipSuccess) return AMM_OK;
+        if (q != hipErrorNotReady) return fail(h, AMM_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+    }
+    HIPC(hipEventSynchronize(h->sync_ev));
+    return AMM_OK;
+}
+
 amm_status pull_out(amm_handle* h) {
     HIPC(hipMemcpyAsync(h->h_out, h->v.out, sizeof(PairOut) * h->L.P, hipMemcpyDeviceToHost, h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
+    TRY(sync_spin(h));
     HIPC(hipGetLastError());
     if (h->timing) h->timer.collect();
     return AMM_OK;
@@ -662,7 +682,7 @@ amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int ma
     const Layout& L = h->L;
     const int nt = L.n_nd_tiles;
     const int P = L.P;
-    volatile int* pg = h->prog;
+    volatile long long* pg = h->prog;
     for (int p = 0; p < P; ++p) {
         pg[2 * p] = -2;
         pg[2 * p + 1] = -1;
@@ -671,21 +691,26 @@ amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int ma
     CgArgs<T> a = cg_args<T>(h, b, bnorm, rtol);
     a.floor2 = floor * floor;
     launch_cg_init<T>(a, nt, h->stream, tmr(h));
+    // the step at which pair p converged (low 32 bits of its word), or -1
+    auto conv_step = [&](int p) { return (int)(unsigned)(pg[2 * p + 1] & 0xffffffffll); };
     auto all_converged = [&]() {
         for (int p = 0; p < P; ++p)
-            if ((h->dyn[p].flags & PF_SOLVE) && pg[2 * p + 1] < 0) return false;
+            if ((h->dyn[p].flags & PF_SOLVE) && conv_step(p) < 0) return false;
         return true;
     };
     auto slowest = [&]() {
-        int m = INT_MAX;
+        long long m = LLONG_MAX;
         for (int p = 0; p < P; ++p)
-            if ((h->dyn[p].flags & PF_SOLVE) && pg[2 * p + 1] < 0) m = std::min(m, (int)pg[2 * p]);
+            if ((h->dyn[p].flags & PF_SOLVE) && conv_step(p) < 0) m = std::min(m, (long long)pg[2 * p]);
         return m;
     };
     int launched = 0;
     bool done = false;
     for (int it = 0; it < maxit && !done; ++it) {
-        if (it > 0 && all_converged()) break;
+        if (it > 0 && all_converged()) {
+            done = true;
+            break;
+        }
         const auto t_wait = std::chrono::steady_clock::now();
         while (it - slowest() > kCgLookahead) {
             if (all_converged()) {
@@ -701,21 +726,48 @@ amm_status run_cg(amm_handle* h, const T* b, const T* bnorm, double rtol, int ma
         launch_cg_iter<T>(a, nt, it, h->stream, tmr(h));
         launched = it + 1;
     }
-    const int last = launched - 1;
-    HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * P, hipMemcpyDeviceToHost, h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
     HIPC(hipGetLastError());
-    if (h->timing) h->timer.collect();
-    if (last < 0) return AMM_OK;
+    if (!done) {
+        // the step budget ran out before every pair converged: wait for the
+        // queued steps and read the state back
+        HIPC(hipMemcpyAsync(h->h_state, h->v.state, sizeof(CgState) * 2 * P, hipMemcpyDeviceToHost, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+        if (h->timing) h->timer.collect();
+        if (launched == 0) return AMM_OK;
+        const int last = launched - 1;
+        for (int p = 0; p < P; ++p) {
+            if (!(h->dyn[p].flags & PF_SOLVE)) continue;
+            rep.cg_iters[p] += h->h_state[2 * p + (last & 1)].iters;
+        }
+        return AMM_OK;
+    }
+    // every pair converged: iterations and breakdown flags come with the
+    // convergence word, no read-back needed
     for (int p = 0; p < P; ++p) {
         if (!(h->dyn[p].flags & PF_SOLVE)) continue;
-        rep.cg_iters[p] += h->h_state[2 * p + (last & 1)].iters;
+        const long long w = pg[2 * p + 1];
+        rep.cg_iters[p] += (int)((w >> 32) & 0x0fffffff);
+        const int brk = (int)((w >> 60) & 7);
+        h->h_state[2 * p].breakdown = h->h_state[2 * p + 1].breakdown = brk;
     }
     return AMM_OK;
 }
 
 // true residual |r - K dx| / |B| per pair (worst column) of the increment
 // system K dx = r = B - K X^k, i.e. |B - K X'| / |B| for X' = X^k + dx.
+// Grows the handle's pinned host scratch to at least `bytes`.  Callers
+// synchronize before reusing it, so no copy into the old buffer is pending.
+amm_status pinned_scratch(amm_handle* h, size_t bytes) {
+    const size_t need = (bytes + 7) / 8;
+    if (h->h_scratch_cap >= need) return AMM_OK;
+    if (h->h_scratch) (void)hipHostFree(h->h_scratch);
+    h->h_scratch = nullptr;
+    h->h_scratch_cap = 0;
+    HIPC(hipHostMalloc((void**)&h->h_scratch, sizeof(double) * need));
+    h->h_scratch_cap = need;
+    return AMM_OK;
+}
+
 template <typename T>
 amm_status true_residual(amm_handle* h, T* rhs_out, std::vector<double>& rel) {
     const Layout& L = h->L;
@@ -724,16 +776,19 @@ amm_status true_residual(amm_handle* h, T* rhs_out, std::vector<double>& rel) {
     CgArgs<T> a = cg_args<T>(h, nullptr, nullptr, 0);
     launch_residual64<T>(a, nt, reinterpret_cast<const T*>(d.rvec), reinterpret_cast<const T*>(d.B), d.x64, rhs_out,
                          d.part_rr64, d.part_bb64, h->stream, tmr(h));
-    std::vector<double> rr(3 * nt), bb(3 * nt);
-    HIPC(hipMemcpyAsync(rr.data(), d.part_rr64, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, h->stream));
-    HIPC(hipMemcpyAsync(bb.data(), d.part_bb64, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
+    // read back into pinned memory (a pageable destination makes the copy
+    // synchronous and staged)
+    TRY(pinned_scratch(h, sizeof(double) * 6 * nt));
+    double* rr = h->h_scratch;
+    double* bb = h->h_scratch + 3 * nt;
+    HIPC(hipMemcpyAsync(rr, d.part_rr64, sizeof(double) * 6 * nt, hipMemcpyDeviceToHost, h->stream));
+    TRY(sync_spin(h));
     rel.assign(L.P, 0.0);
     for (int p = 0; p < L.P; ++p) {
         if (!(h->dyn[p].flags & PF_SOLVE)) continue;
         double r3[3], b3[3];
-        pair_sums3(L, rr.data(), p, r3);
-        pair_sums3(L, bb.data(), p, b3);
+        pair_sums3(L, rr, p, r3);
+        pair_sums3(L, bb, p, b3);
         for (int c = 0; c < 3; ++c) rel[p] = std::max(rel[p], b3[c] > 0 ? std::sqrt(r3[c] / b3[c]) : std::sqrt(r3[c]));
     }
     return AMM_OK;
@@ -853,15 +908,6 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
     auto now_ms = [&]() {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     };
-    if (prm.init_identity || !X_inout) {
-        std::vector<T> id(12 * L.ntot, T(0));
-        for (int64_t j = 0; j < L.ntot; ++j) id[12 * j] = id[12 * j + 4] = id[12 * j + 8] = T(1);
-        HIPC(hipMemcpyAsync(d.X[0], id.data(), id.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
-        HIPC(hipStreamSynchronize(h->stream));
-    } else {
-        launch_x_import<T, T>(reinterpret_cast<const T*>(X_inout), reinterpret_cast<T*>(d.X[0]), h->v.node_user,
-                              L.ntot, h->stream);
-    }
     std::vector<PairState> ps(P);
     for (int p = 0; p < P; ++p) {
         PairDyn& dy = h->dyn[p];
@@ -869,17 +915,33 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
         set_scalars(dy, 1.0, 1.0, 0.0, 0.0);
         dy.flags = PF_EVAL;
     }
+    if (prm.init_identity || !X_inout) {
+        TRY(push_dyn(h));
+        vec_op<T>(h, PF_EVAL, 9);   // X[0] = identity
+    } else {
+        launch_x_import<T, T>(reinterpret_cast<const T*>(X_inout), reinterpret_cast<T*>(d.X[0]), h->v.node_user,
+                              L.ntot, h->stream);
+    }
     TRY(evaluate<T>(h));
     // start of nu_a: median closest-point distance at the initial transforms
-    std::vector<T> d2h(L.Ntot);
-    HIPC(hipMemcpyAsync(d2h.data(), d.d2[0], sizeof(T) * L.Ntot, hipMemcpyDeviceToHost, h->stream));
+    TRY(pinned_scratch(h, sizeof(T) * L.Ntot));
+    const T* d2h = reinterpret_cast<const T*>(h->h_scratch);
+    HIPC(hipMemcpyAsync(h->h_scratch, d.d2[0], sizeof(T) * L.Ntot, hipMemcpyDeviceToHost, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
+    std::vector<double> dist;
     for (int p = 0; p < P; ++p) {
         const PairInfo& pi = L.info[p];
-        std::vector<double> dist(pi.N);
-        for (int64_t i = 0; i < pi.N; ++i) dist[i] = std::sqrt((double)d2h[pi.src_off + i]);
-        std::sort(dist.begin(), dist.end());
-        const double med = (pi.N % 2) ? dist[pi.N / 2] : 0.5 * (dist[pi.N / 2 - 1] + dist[pi.N / 2]);
+        // median of the distances (the mean of the two middle ones for even
+        // N) by selection on d^2: the square root keeps the order
+        double med = 0.0;
+        if (!(prm.nu_a0 > 0)) {
+            dist.assign(d2h + pi.src_off, d2h + pi.src_off + pi.N);
+            const int64_t mid = pi.N / 2;
+            std::nth_element(dist.begin(), dist.begin() + mid, dist.end());
+            const double hi = std::sqrt(dist[mid]);
+            med = hi;
+            if (pi.N % 2 == 0) med = 0.5 * (std::sqrt(*std::max_element(dist.begin(), dist.begin() + mid)) + hi);
+        }
         PairState& st = ps[p];
         st.nu_min = prm.nu_a_min > 0 ? prm.nu_a_min : h->lbar[p] / std::sqrt(3.0);
         st.nu_a = std::max(prm.nu_a0 > 0 ? prm.nu_a0 : med, st.nu_min);
@@ -1281,6 +1343,8 @@ void amm_destroy(amm_handle* h) {
     for (int s = 0; s < kDynRing; ++s)
         if (h->dyn_ev[s]) (void)hipEventDestroy(h->dyn_ev[s]);
     if (h->prog) (void)hipHostFree(h->prog);
+    if (h->h_scratch) (void)hipHostFree(h->h_scratch);
+    if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);

@@ -304,9 +304,12 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             st.breakdown = prv->breakdown | brk_mask;
             // progress for the host (coherent pinned memory), every 4th step
             // and at convergence: a store to host memory delays the kernel's
-            // completion, so most steps skip it
-            volatile int* pg = a.prog + 2 * p;
-            if (!any) pg[1] = it;
+            // completion, so most steps skip it.  The convergence word carries
+            // the iteration count and breakdown flags in the same store.
+            volatile long long* pg = a.prog + 2 * p;
+            if (!any)
+                pg[1] = ((long long)st.iters << 32) | ((long long)(st.breakdown & 7) << 60) |
+                        (long long)(unsigned)it;
             if (!any || (it & 3) == 3) pg[0] = it;
         }
     } else {

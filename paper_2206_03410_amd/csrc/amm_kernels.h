@@ -151,7 +151,9 @@ struct CgArgs {
     const int* tile_agg;
     T* gr[2];                // [nagg][12] P^T r per aggregate
     T* gs[2];                // [nagg][12] P^T s per aggregate
-    int* prog;               // host-visible [P][2]: last step completed, step of convergence
+    // host-visible [P][2]: last step reported; at convergence one 64-bit word
+    // (iterations << 32) | (breakdown << 60) | step of convergence
+    long long* prog;
 };
 
 template <typename T>

@@ -564,7 +564,7 @@ template <typename T>
 __global__ void k_node_vec_op(NodeVecArgs<T> a) {
     // 0: x64 = src_t        1: x64 += src_t       2: dst_t = (T) x64      3: dst_t = src_t
     // 4: x64 = X[cur]       5: X[2] = X[cur]      6: X[1 - cur] = X[2]
-    // 7: x64 = 0            8: X[2] = X[cur] + x64
+    // 7: x64 = 0            8: X[2] = X[cur] + x64   9: X[0] = identity
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
     const PairDyn dy = a.dyn[td.x];
@@ -580,7 +580,12 @@ __global__ void k_node_vec_op(NodeVecArgs<T> a) {
             case 5: a.X[2][o] = a.X[dy.cur][o]; break;
             case 6: a.X[1 - dy.cur][o] = a.X[2][o]; break;
             case 7: a.x64[o] = 0.0; break;
-            default: a.X[2][o] = (T)((double)a.X[dy.cur][o] + a.x64[o]); break;
+            case 8: a.X[2][o] = (T)((double)a.X[dy.cur][o] + a.x64[o]); break;
+            default: {
+                const int m = (int)(o % 12);
+                a.X[0][o] = (m == 0 || m == 4 || m == 8) ? T(1) : T(0);
+                break;
+            }
         }
     }
 }
