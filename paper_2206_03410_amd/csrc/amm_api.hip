@@ -31,7 +31,7 @@ thread_local std::string g_last_error;
 
 const char* kVersion = "amm-gfx950 0.1";
 constexpr int kDynRing = 16;
-constexpr int kCgLookahead = 6;   // CG steps in flight ahead of the last one reported (every 4th)
+constexpr int kCgLookahead = 10;  // CG steps in flight ahead of the last one reported (every 4th)
 
 struct EventTimer final : KernelTimer {
     struct Rec {
@@ -300,9 +300,6 @@ struct amm_handle {
     Dev v{};
     std::vector<double> lbar;
     std::vector<PairDyn> dyn;        // host working copy of the per-pair parameters
-    PairDyn* dyn_pinned = nullptr;   // [kDynRing][P] staging for uploads
-    hipEvent_t dyn_ev[kDynRing] = {};
-    bool dyn_ev_live[kDynRing] = {};
     int dyn_slot = 0;
     PairOut* h_out = nullptr;        // pinned
     CgState* h_state = nullptr;      // pinned
@@ -416,39 +413,36 @@ amm_status up_real(amm_handle* h, PF* dst_f, PD* dst_d, const std::vector<double
 amm_status ensure_host(amm_handle* h, size_t P) {
     h->dyn.assign(P, PairDyn{});
     if (P <= h->h_cap) return AMM_OK;
-    for (int s = 0; s < kDynRing; ++s)
-        if (h->dyn_ev_live[s]) (void)hipEventSynchronize(h->dyn_ev[s]);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);
-    if (h->dyn_pinned) (void)hipHostFree(h->dyn_pinned);
     if (h->prog) (void)hipHostFree(h->prog);
     h->h_out = nullptr;
     h->h_state = nullptr;
-    h->dyn_pinned = nullptr;
     h->prog = nullptr;
     HIPC(hipHostMalloc((void**)&h->prog, sizeof(long long) * 2 * P, hipHostMallocMapped | hipHostMallocCoherent));
     HIPC(hipHostGetDevicePointer((void**)&h->prog_dev, h->prog, 0));
     HIPC(hipHostMalloc((void**)&h->h_out, sizeof(PairOut) * P));
     HIPC(hipHostMalloc((void**)&h->h_state, sizeof(CgState) * 2 * P));
-    HIPC(hipHostMalloc((void**)&h->dyn_pinned, sizeof(PairDyn) * kDynRing * P));
     h->h_cap = P;
     return AMM_OK;
 }
 
-// Uploads the host copy of the per-pair parameters into the next ring slot;
-// launches built afterwards read that slot.  A slot's staging memory is
-// reused only after its previous upload has completed.
+// Uploads the host copy of the per-pair parameters into the next ring slot,
+// stream-ordered, through the arguments of a copy kernel (captured at
+// launch, so the host copy may change right after); launches built
+// afterwards read that slot.
 amm_status push_dyn(amm_handle* h) {
     const int P = h->L.P;
     const int slot = (h->dyn_slot + 1) % kDynRing;
-    if (!h->dyn_ev[slot]) HIPC(hipEventCreateWithFlags(&h->dyn_ev[slot], hipEventDisableTiming));
-    if (h->dyn_ev_live[slot]) HIPC(hipEventSynchronize(h->dyn_ev[slot]));
-    PairDyn* hs = h->dyn_pinned + (size_t)slot * P;
-    std::memcpy(hs, h->dyn.data(), sizeof(PairDyn) * P);
     PairDyn* ds = h->v.dyn_ring + (size_t)slot * P;
-    HIPC(hipMemcpyAsync(ds, hs, sizeof(PairDyn) * P, hipMemcpyHostToDevice, h->stream));
-    HIPC(hipEventRecord(h->dyn_ev[slot], h->stream));
-    h->dyn_ev_live[slot] = true;
+    for (int b = 0; b < P; b += kDynPerLaunch) {
+        DynPack pk;
+        pk.n = std::min(kDynPerLaunch, P - b);
+        std::memcpy(pk.d, h->dyn.data() + b, sizeof(PairDyn) * pk.n);
+        pk.dst = ds + b;
+        launch_dyn_set(pk, h->stream);
+    }
+    HIPC(hipGetLastError());
     h->dyn_slot = slot;
     h->v.dyn = ds;
     return AMM_OK;
@@ -1340,15 +1334,12 @@ void amm_destroy(amm_handle* h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
-    for (int s = 0; s < kDynRing; ++s)
-        if (h->dyn_ev[s]) (void)hipEventDestroy(h->dyn_ev[s]);
     if (h->prog) (void)hipHostFree(h->prog);
     if (h->h_scratch) (void)hipHostFree(h->h_scratch);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);
-    if (h->dyn_pinned) (void)hipHostFree(h->dyn_pinned);
     delete h;
 }
 

@@ -242,6 +242,16 @@ struct GradArgs {
     T* gV;                   // user point order, may be null
 };
 
+// Per-pair parameters carried to the device in the kernel arguments of a
+// small copy kernel (no host-memory access by the GPU, no blit).
+constexpr int kDynPerLaunch = 32;
+struct DynPack {
+    PairDyn d[kDynPerLaunch];
+    PairDyn* dst;
+    int n;
+};
+void launch_dyn_set(const DynPack& pk, hipStream_t s);
+
 template <typename T>
 void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_tiles, const FinalArgs& f,
                  int P, hipStream_t s, KernelTimer* tm);

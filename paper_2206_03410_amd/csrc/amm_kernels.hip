@@ -1043,6 +1043,18 @@ void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_cast_static<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
 
+__global__ void __launch_bounds__(64) k_dyn_set(DynPack pk) {
+    static_assert(sizeof(PairDyn) % 4 == 0, "PairDyn is copied in 32-bit words");
+    const int words = pk.n * (int)(sizeof(PairDyn) / 4);
+    const unsigned* src = reinterpret_cast<const unsigned*>(pk.d);
+    unsigned* dst = reinterpret_cast<unsigned*>(pk.dst);
+    for (int i = threadIdx.x; i < words; i += 64) dst[i] = src[i];
+}
+
+void launch_dyn_set(const DynPack& pk, hipStream_t s) {
+    hipLaunchKernelGGL(k_dyn_set, dim3(1), dim3(64), 0, s, pk);
+}
+
 #define AMM_INSTANTIATE(T)                                                                                     \
     template void launch_eval<T>(const EvalArgs<T>&, int, int, int, const FinalArgs&, int, hipStream_t,        \
                                  KernelTimer*);                                                               \
