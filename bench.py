@@ -26,6 +26,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch averaged over a run of this
+# benchmark), each divided by what the same counter reads for a plain copy of
+# known size (profiles/sh200k_hbm_traffic_counters.txt).  Valid only for the
+# kernel sources they were taken on: a change to those files voids them.
+MEASURED_TRAFFIC = {
+    "cg_step": {"fetch_kib": 3829.1, "fetch_per_byte": 131084.5 / 262144.0,
+                "write_kib": 957.9, "write_per_byte": 262144.0 / 262144.0,
+                "sources": {"paper_2206_03410_amd/csrc/amm_cg.hip": "da148c6656b3dbd4",
+                            "paper_2206_03410_amd/csrc/amm_device.h": "86a73d4ac31fa5fe",
+                            "paper_2206_03410_amd/csrc/amm_kernels.h": "000e8b96825afb9c"}},
+}
+
+
+def measured_traffic(group):
+    """Bytes per launch from the counters, or None if the kernel changed."""
+    import hashlib
+    m = MEASURED_TRAFFIC.get(group)
+    if m is None:
+        return None
+    for path, h in m["sources"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != h:
+                return None
+    return 1024.0 * (m["fetch_kib"] / m["fetch_per_byte"] + m["write_kib"] / m["write_per_byte"])
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -118,7 +144,7 @@ def timed_steps(amm, torch, h, pair, prec, steps, aa_m, repeats):
     return walls, first, totals
 
 
-def cpu_baseline(pair, sample=1000):
+def cpu_baseline(pair, sample=40000):
     """The FP64 oracle on the same workload, one MM iteration: warp, Welsch
     terms, rotations, sparse-LU surrogate solve and Anderson mixing timed in
     full; brute-force closest points timed on `sample` queries and scaled to
@@ -297,7 +323,7 @@ def main():
     avg_s = ms_tot / nl * 1e-3
     achieved = ab[dom] / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6, "launches": nl}
     abw = ab
     stages = {k: {"ms_per_iter": v[0] / max(st_w["iters"], 1), "launches": v[1],

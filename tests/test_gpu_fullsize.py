@@ -1,0 +1,100 @@
+"""Parity at the full workload sizes, in the precision and launch shape the
+benchmark times: sampled outputs the oracle computes one by one, and
+properties that hold at any size."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import amm_oracle as O
+from paper_2206_03410_amd import amm, synth
+from tests.helpers import Session, margin_ok, rounded
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(name):
+    print(f"[gpu-test] {name}", file=sys.stderr, flush=True)
+
+
+def _kdtree_nn(tgt):
+    # exact closest points from scipy's k-d tree (the oracle's brute-force
+    # search is pinned against it)
+    from scipy.spatial import cKDTree
+    tree = cKDTree(tgt)
+
+    def nn(q, _tgt):
+        d, i = tree.query(q, k=2)
+        return i[:, 0].astype(np.int64), d[:, 0] ** 2, d[:, 1] ** 2
+    return nn
+
+
+def test_sh200k_step_sampled_against_oracle():
+    """One float32 + refinement MM step on the 200,000-point workload at
+    X = I + delta: energy within 1e-5 relative of the oracle's FP64 energy;
+    closest points of 2,000 sampled queries equal the oracle's brute force
+    on the library's own warped points wherever the best and second-best
+    distances differ by more than 1e-6 relative; the deformed points of the
+    surrogate minimizer within 1e-4 (bounding-box diagonal units) RMS of the
+    oracle's sparse-LU minimizer."""
+    _announce("test_sh200k_step_sampled_against_oracle")
+    pair = synth.make_workload("sh200k")
+    pr = rounded(pair, np.float32)
+    prob = O.from_pair(pr)
+    nn = _kdtree_nn(prob.tgt)
+    p = O.Params(aa_m=6)
+    _, d2i, _ = nn(prob.src, prob.tgt)
+    nu_a, _, nu_r = O.initial_nu(prob, p, d2i)
+    alpha, beta = O.term_weights(prob, p, nu_a, nu_r)
+    X = synth.perturbed_transforms(prob.n_nodes, 7007, 0.01, 0.001).astype(np.float32).astype(np.float64)
+    n, N = prob.n_nodes, prob.n_src
+    with Session(pr, torch.float32) as s:
+        dev = "cuda:0"
+        Xt = torch.tensor(X, dtype=torch.float32, device=dev)
+        rho = torch.empty(N, dtype=torch.int32, device=dev)
+        d2 = torch.empty(N, dtype=torch.float32, device=dev)
+        vh = torch.empty(N, 3, dtype=torch.float32, device=dev)
+        Xn = torch.empty(n, 4, 3, dtype=torch.float32, device=dev)
+        out = amm.amm_step(s.h, Xt, nu_a, nu_r, alpha, beta, amm.AMM_FP32_REFINE,
+                           rho=rho, d2=d2, v_hat=vh, X_next=Xn)
+        torch.cuda.synchronize()
+        rho, vh, Xn = rho.cpu().numpy(), vh.cpu().numpy().astype(np.float64), Xn.cpu().numpy()
+    ev = O.evaluate(prob, X, nu_a, nu_r, alpha, beta, nn=nn)
+    assert out["energy"][0] == pytest.approx(ev.E, rel=1e-5)
+    assert out["rel_residual"] < 1e-9
+    idx = np.random.default_rng(7008).choice(N, 2000, replace=False)
+    rq, dq, dqs = O.nearest(vh[idx], prob.tgt, threads=8)
+    ok = margin_ok(dq, dqs)
+    assert ok.mean() > 0.99
+    assert np.array_equal(rho[idx][ok], rq[ok])
+    Xo = np.asarray(O.mm_update(prob, ev, nu_a, nu_r, alpha, beta)[0])
+    vo = O.warp(prob, Xo)
+    vg = O.warp(prob, Xn.astype(np.float64))
+    assert np.sqrt(((vo - vg) ** 2).sum(1).mean()) < 1e-4
+
+
+def test_batch64_equals_single_solves():
+    """The 64-pair batch (uneven sizes, float32 + refinement, Alg. 2's own
+    termination): every pair converges, and sampled pairs solved inside the
+    batch equal the same pairs solved alone, bitwise."""
+    _announce("test_batch64_equals_single_solves")
+    pairs = synth.batch_pairs(n_pairs=64)
+    prm = dict(aa_m=5, precision=amm.AMM_FP32_REFINE)
+    with Session(pairs, torch.float32) as s:
+        tot = sum(pp.n_nodes for pp in pairs)
+        X = torch.empty(tot, 4, 3, dtype=torch.float32, device="cuda:0")
+        st = amm.amm_solve(s.h, amm.amm_params_default(**prm), X, n_pairs=len(pairs))
+        torch.cuda.synchronize()
+        Xb = X.cpu().numpy()
+    assert all(t["converged"] == 1 for t in st)
+    offs = np.concatenate([[0], np.cumsum([pp.n_nodes for pp in pairs])])
+    for b in (0, 31, 63):
+        with Session(pairs[b], torch.float32) as s:
+            X = torch.empty(pairs[b].n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+            st1 = amm.amm_solve(s.h, amm.amm_params_default(**prm), X)[0]
+            torch.cuda.synchronize()
+            Xs = X.cpu().numpy()
+        assert st1["iters"] == st[b]["iters"]
+        assert np.array_equal(Xb[offs[b]:offs[b + 1]], Xs)
