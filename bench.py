@@ -162,9 +162,12 @@ def cpu_baseline(pair, sample=40000):
     t = time.perf_counter()
     rho_s, d2_s, _ = O.nearest(vh[idx], prob.tgt, threads=threads)
     t_nn = (time.perf_counter() - t) * prob.n_src / sample
-    # closest points of all queries for the rest of the iteration (kd-tree, not timed)
+    # closest points of all queries for the rest of the iteration by scipy's
+    # exact k-d tree, timed as a second CPU reference for this stage
     from scipy.spatial import cKDTree
-    dd, ii = cKDTree(prob.tgt).query(vh, 2)
+    t = time.perf_counter()
+    dd, ii = cKDTree(prob.tgt).query(vh, 2, workers=threads)
+    t_kd = time.perf_counter() - t
     t = time.perf_counter()
     D = O.reg_residuals(prob, X)
     R, er = O.proj_rotation(X[:, :3, :].transpose(0, 2, 1))
@@ -197,6 +200,7 @@ def cpu_baseline(pair, sample=40000):
                    f"closest points on {sample} of {prob.n_src} queries, scaled x{prob.n_src // sample}"),
         "stage_s": {"warp": t_warp, "closest_points_scaled": t_nn, "terms": t_terms,
                     "surrogate_solve": t_solve, "anderson": t_aa},
+        "closest_points_kdtree_s": t_kd,
         "cpu_model": cpu, "host": platform.node(),
     }
 
@@ -236,6 +240,56 @@ def batched_run(amm, torch, n_pairs, aa_m):
             "p50_pair_ms": float(np.percentile(per, 50)), "p99_pair_ms": float(np.percentile(per, 99)),
             "iters_total": int(sum(s["iters"] for s in st)),
             "converged": int(sum(s["converged"] for s in st))}
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Attainable HBM bandwidth of a plain device-to-device copy (read +
+    write bytes per second), median of `reps` copies of `nbytes`."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    return 2 * nbytes / float(np.median(ts)) / 1e9
+
+
+def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
+    """Work of the exact closest-point search over one FP32 solve (counted in
+    a separate, untimed solve) against the eval_points kernel's measured
+    average launch time.  Candidate traffic per launch = queries x (12 B
+    warped query + 8 B outputs) + box tests x 32 B (two float4 corners) +
+    distance evaluations x 16 B (one float4 target)."""
+    amm.amm_count_nn_work(h, True)
+    try:
+        run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, steps, aa_m)
+        w = amm.amm_nn_work(h)
+    finally:
+        amm.amm_count_nn_work(h, False)
+    launches = max(1, round(w["queries"] / pair.n_src))
+    q, bx, de = (w[k] / launches for k in ("queries", "box_tests", "distance_evals"))
+    t = eval_ms / eval_launches * 1e-3
+    cand = q * (12 + 8) + bx * 32 + de * 16
+    comp = pair.n_src * (12 + 4 + 4) + 12 * pair.n_tgt
+    flops = 8 * de + 12 * bx
+    return {"kernel": "eval_points", "avg_launch_us": t * 1e6, "queries_per_launch": q,
+            "box_tests_per_query": bx / q, "distance_evals_per_query": de / q,
+            "compulsory_GBps": comp / t / 1e9,
+            "candidate_traffic_GBps": cand / t / 1e9,
+            "candidate_traffic_frac": cand / t / 1e9 / HBM_PEAK_GBS,
+            "distance_evals_per_s": de / t,
+            "search_flops_frac_fp32_valu": flops / t / 157.3e12,
+            "definition": "candidate traffic = queries x (12 B warped point + 8 B closest index and "
+                          "squared distance) + box lower-bound tests x 32 B + target distance "
+                          "evaluations x 16 B, per launch, over the kernel's average launch time; "
+                          "flops: 8 per distance evaluation, 12 per box test"}
 
 
 def copy_calibration():
@@ -314,6 +368,15 @@ def main():
                      "rmse_gt_fp32": rm32, "rmse_gt_fp64": rm64,
                      "equal_error": abs(rm32 - rm64) <= max(1e-4, 0.01 * rm64),
                      "speedup_fp32_refine": wall64 / wall32}
+        # the search's average launch time over the same solve that is counted
+        _, _, _, kt_e = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m,
+                                  timing="eval_points")
+        nn = nn_search_report(amm, torch, h, pair, aa_m, args.steps, *kt_e["eval_points"])
+        log(f"[bench] closest points: {nn['box_tests_per_query']:.1f} box tests and "
+            f"{nn['distance_evals_per_query']:.1f} distance evaluations per query; candidate traffic "
+            f"{nn['candidate_traffic_GBps']:.0f} GB/s")
+        copy_gbs = copy_bandwidth(torch)
+        log(f"[bench] plain device copy {copy_gbs:.0f} GB/s")
     finally:
         amm.amm_destroy(h)
 
@@ -324,7 +387,8 @@ def main():
     achieved = ab[dom] / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                "bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6, "launches": nl}
+                "bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6, "launches": nl,
+                "attainable_copy_GBps": copy_gbs}
     abw = ab
     stages = {k: {"ms_per_iter": v[0] / max(st_w["iters"], 1), "launches": v[1],
                   "GBps": (abw[k] / (v[0] / v[1] * 1e-3) / 1e9) if k in abw else None}
@@ -346,6 +410,7 @@ def main():
         "autotuned_leaf": leaf,
         "plain_fp64": plain,
         "stages_warmup": stages,
+        "closest_points": nn,
         "timed_regions_s": w32,
         "solve": {"first_solve_iters": st32["iters"], "solves_per_region": tot32["solves"],
                   "cg_iters_per_region": tot32["cg_iters"], "refine_steps_per_region": tot32["refine_steps"],

@@ -70,6 +70,30 @@ typedef enum { AMM_FP64_PLAIN = 0, AMM_FP32_REFINE = 1 } amm_precision;
  * pair): the same solution, several times fewer CG iterations. */
 typedef enum { AMM_PRECOND_TWO_LEVEL = 0, AMM_PRECOND_BLOCK_JACOBI = 1 } amm_precond;
 
+/* Robust terms.  WELSCH is the method (Eqs. 5, 9 with the surrogate weights
+ * of Eqs. 13-16).  The other two are the squared-norm variants of Sec. 4.1:
+ * L2 uses unit weights on every alignment residual and a plain squared norm
+ * on the regularization residuals; L2_TRUNC keeps weight 1 only for points
+ * whose closest-point distance is below 3 nu_a (0 otherwise), which is MM on
+ * the truncated quadratic min(|e|^2, 9 nu_a^2), with the same squared-norm
+ * regularization.  Both squared-norm variants weight the terms by
+ * alpha = k_alpha |V|/|E_G| and beta = k_beta |V|/|V_G| (the small-residual
+ * scale of Eq. 26's Welsch weighting). */
+typedef enum { AMM_ROBUST_WELSCH = 0, AMM_ROBUST_L2 = 1, AMM_ROBUST_L2_TRUNC = 2 } amm_robust;
+
+/* nu schedule.  DYNAMIC is the continuation of Sec. 3.3.3.  The fixed modes
+ * are Sec. 4.1's Welsch-fmax / -fmin / -fmed: (nu_a, nu_r) held for one
+ * stage at the largest, the smallest, or the mean of the two, of the values
+ * the dynamic update would reach from the same start (nu_a halves down to
+ * its bound, nu_r halves with it).  With AMM_ROBUST_L2 there is no parameter
+ * and the solve runs one stage. */
+typedef enum {
+    AMM_NU_DYNAMIC = 0,
+    AMM_NU_FIXED_MAX = 1,
+    AMM_NU_FIXED_MIN = 2,
+    AMM_NU_FIXED_MED = 3
+} amm_nu_mode;
+
 typedef struct amm_handle amm_handle;
 
 /* One registration problem.  `on_device` = 1: the pointers are device
@@ -118,6 +142,8 @@ typedef struct {
     const int8_t* force_stage_end;
     int32_t force_len;
     int32_t cg_precond;           /* amm_precond (0 = two-level, the default) */
+    int32_t robust;               /* amm_robust (0 = Welsch, the method) */
+    int32_t nu_mode;              /* amm_nu_mode (0 = dynamic, the method) */
 } amm_params;
 
 #define AMM_MAX_AA_M 10
@@ -226,6 +252,19 @@ amm_status amm_solve(amm_handle* h, const amm_params* params, void* X_inout, voi
  * NULL to query the count). */
 amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, int32_t* count);
 
+/* Work counters of the closest-point search (Sec. 3.2's correspondence
+ * step), for reporting how much target data an exact search examines.
+ * amm_count_nn_work(h, 1) zeroes the counters and switches every later
+ * evaluation (solve, step, energy) to a counting variant of its kernel,
+ * which is slower; 0 switches back and frees them.  amm_set_problems also
+ * switches counting off.  amm_nn_work returns, since counting was switched
+ * on: the queries searched, the bounding-box lower-bound tests (each reads
+ * two box corners) and the target distance evaluations (each reads one
+ * target).  Errors: AMM_ERR_STATE before a problem is set, or when
+ * counting is off. */
+amm_status amm_count_nn_work(amm_handle* h, int32_t enable);
+amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals);
+
 /* ---------------------------------------------------------------- single step */
 
 typedef struct {
@@ -235,6 +274,7 @@ typedef struct {
     double cg_rtol;
     int32_t cg_maxit;
     int32_t cg_precond;      /* amm_precond */
+    int32_t robust;          /* amm_robust; nu_a, alpha, beta are taken as given */
 } amm_step_in;
 
 typedef struct {

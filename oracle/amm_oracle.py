@@ -19,6 +19,8 @@ Everything is float64 numpy/scipy, written step by step from the paper:
 * nu continuation ............................. Sec. 3.3.3
 * Anderson acceleration + energy fallback ..... Sec. 3.3.4, Eqs. (22)-(23), Alg. 2
 * weight rule for alpha, beta ................. Eq. (26)
+* squared-norm and fixed-nu variants .......... Sec. 4.1 (effect of the Welsch
+  function and of the nu update)
 
 Readings taken where the paper is silent or garbled are listed with the
 functions that take them (search for "Reading").  The gradient of the energy
@@ -138,6 +140,56 @@ def welsch_weight(y2, nu):
     return np.exp(-np.asarray(y2, np.float64) / (2.0 * nu * nu)) / (2.0 * nu * nu)
 
 
+# Robust-term variants of Sec. 4.1.  "welsch" is the method itself; "l2"
+# replaces both Welsch functions by squared norms with unit weights
+# ("l2-norm"); "l2r" keeps unit weights only for alignment residuals shorter
+# than 3 nu_a and zero otherwise, with squared norms on the regularization
+# ("l2-norm-r").
+ROBUST = ("welsch", "l2", "l2r")
+
+
+def align_penalty(x2, nu, robust="welsch"):
+    """Per-point alignment term as a function of the squared distance.
+    Reading for "l2r": the 0/1 weight rule is the MM weight of the truncated
+    quadratic min(x^2, (3 nu)^2) (a constant majorizes it where the residual
+    is at least 3 nu, x^2 elsewhere), which is the energy that this variant
+    decreases."""
+    x2 = np.asarray(x2, np.float64)
+    if robust == "welsch":
+        return welsch(x2, nu)
+    if robust == "l2":
+        return x2.copy()
+    if robust == "l2r":
+        return np.minimum(x2, 9.0 * nu * nu)
+    raise ValueError(robust)
+
+
+def align_weight(y2, nu, robust="welsch"):
+    """Coefficient of x^2 in the alignment surrogate at y (squared entries of
+    W_a): the Welsch weight of Eq. (13), 1 for "l2", and for "l2r" 1 where
+    |y| < 3 nu and 0 elsewhere."""
+    y2 = np.asarray(y2, np.float64)
+    if robust == "welsch":
+        return welsch_weight(y2, nu)
+    if robust == "l2":
+        return np.ones_like(y2)
+    if robust == "l2r":
+        return (y2 < 9.0 * nu * nu).astype(np.float64)
+    raise ValueError(robust)
+
+
+def reg_penalty(x2, nu, robust="welsch"):
+    """Regularization term per directed edge: Eq. (9)'s Welsch value, or the
+    squared norm in both squared-norm variants."""
+    return welsch(x2, nu) if robust == "welsch" else np.asarray(x2, np.float64).copy()
+
+
+def reg_weight(y2, nu, robust="welsch"):
+    """Squared entries of W_r: Eq. (14)'s Welsch weight, or 1."""
+    y2 = np.asarray(y2, np.float64)
+    return welsch_weight(y2, nu) if robust == "welsch" else np.ones_like(y2)
+
+
 def welsch_surrogate(x, y, nu):
     """Eq. (13): psi(x|y) = psi(y) + (1 - psi(y))/(2 nu^2) (x^2 - y^2)."""
     x = np.asarray(x, np.float64)
@@ -245,24 +297,25 @@ class Eval:
 
 
 def evaluate(prob: Problem, X: np.ndarray, nu_a: float, nu_r: float, alpha: float,
-             beta: float, src: Optional[np.ndarray] = None, nn=None) -> Eval:
+             beta: float, src: Optional[np.ndarray] = None, nn=None, robust="welsch") -> Eval:
     """E(X) = E_align + alpha E_reg + beta E_rot (Eq. 4) with Eqs. (5), (9)
-    and the rotation term; the closest points are recomputed at X."""
+    and the rotation term; the closest points are recomputed at X.  Other
+    `robust` variants swap the per-term functions (Sec. 4.1)."""
     vhat = warp(prob, X, src)
     rho, d2, d2s = (nn or nearest)(vhat, prob.tgt)
     D = reg_residuals(prob, X)
     R, e_rot = proj_rotation(X[:, :3, :].transpose(0, 2, 1))
-    Ea = math.fsum(welsch(d2, nu_a))
-    Er = math.fsum(welsch((D ** 2).sum(1), nu_r))
+    Ea = math.fsum(align_penalty(d2, nu_a, robust))
+    Er = math.fsum(reg_penalty((D ** 2).sum(1), nu_r, robust))
     Eo = math.fsum(e_rot)
     return Eval(X, vhat, rho, d2, d2s, D, R, e_rot, Ea, Er, Eo, Ea + alpha * Er + beta * Eo)
 
 
-def rescore(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta) -> Eval:
+def rescore(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta, robust="welsch") -> Eval:
     """Energy of the same X at other (nu, alpha, beta): closest points and
     rotations do not depend on them."""
-    Ea = math.fsum(welsch(ev.d2, nu_a))
-    Er = math.fsum(welsch((ev.D ** 2).sum(1), nu_r))
+    Ea = math.fsum(align_penalty(ev.d2, nu_a, robust))
+    Er = math.fsum(reg_penalty((ev.D ** 2).sum(1), nu_r, robust))
     return dataclasses.replace(ev, E_align=Ea, E_reg=Er, E=Ea + alpha * Er + beta * ev.E_rot)
 
 
@@ -270,7 +323,7 @@ def rescore(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta) -> Eval:
 # surrogate in matrix form and its minimizer (Sec. 3.3.2, Eq. 21)
 # --------------------------------------------------------------------------
 
-def matrices(prob: Problem, ev: Eval, nu_a: float, nu_r: float):
+def matrices(prob: Problem, ev: Eval, nu_a: float, nu_r: float, robust="welsch"):
     """Build F, Q, W_a^2 (as a vector), H, Y, W_r^2, J, Z of Sec. 3.3.2 at the
     evaluation point ev (its closest points u^k, residuals D^k, rotations)."""
     N, n, k = prob.n_src, prob.n_nodes, prob.infl_idx.shape[1]
@@ -280,7 +333,7 @@ def matrices(prob: Problem, ev: Eval, nu_a: float, nu_r: float):
     blk = np.concatenate([d, np.ones((N, k, 1))], 2) * prob.infl_w[:, :, None]
     F = sp.csr_matrix((blk.reshape(-1), (rows, cols)), shape=(N, 4 * n))
     Q = prob.tgt[ev.rho] - np.einsum("nk,nkc->nc", prob.infl_w, prob.nodes[prob.infl_idx])
-    wa = welsch_weight(ev.d2, nu_a)
+    wa = align_weight(ev.d2, nu_a, robust)
 
     i = prob.dir_edges[:, 0]
     j = prob.dir_edges[:, 1]
@@ -292,7 +345,7 @@ def matrices(prob: Problem, ev: Eval, nu_a: float, nu_r: float):
     hv = np.concatenate([r[:, None] * dp, r[:, None], -r[:, None]], 1).reshape(-1)
     H = sp.csr_matrix((hv, (hr, hc)), shape=(h, 4 * n))
     Y = r[:, None] * dp
-    wr = welsch_weight((ev.D ** 2).sum(1), nu_r)
+    wr = reg_weight((ev.D ** 2).sum(1), nu_r, robust)
 
     jd = np.tile(np.array([1.0, 1.0, 1.0, 0.0]), n)
     J = sp.diags(jd)
@@ -301,10 +354,10 @@ def matrices(prob: Problem, ev: Eval, nu_a: float, nu_r: float):
     return F, Q, wa, H, Y, wr, J, Z.reshape(4 * n, 3)
 
 
-def normal_equations(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta):
+def normal_equations(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta, robust="welsch"):
     """Eq. (21): K = F^T W_a^2 F + alpha H^T W_r^2 H + beta J^T J,
     B = F^T W_a^2 Q + alpha H^T W_r^2 Y + beta J^T J Z."""
-    F, Q, wa, H, Y, wr, J, Z = matrices(prob, ev, nu_a, nu_r)
+    F, Q, wa, H, Y, wr, J, Z = matrices(prob, ev, nu_a, nu_r, robust)
     Wa = sp.diags(wa)
     Wr = sp.diags(wr)
     K = (F.T @ Wa @ F + alpha * (H.T @ Wr @ H) + beta * (J.T @ J)).tocsc()
@@ -312,27 +365,27 @@ def normal_equations(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta):
     return K, np.asarray(B)
 
 
-def mm_update(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta):
+def mm_update(prob: Problem, ev: Eval, nu_a, nu_r, alpha, beta, robust="welsch"):
     """Minimizer of the quadratic surrogate: solve K X = B (Eq. 21) with one
     sparse LU factorization and three right-hand sides."""
-    K, B = normal_equations(prob, ev, nu_a, nu_r, alpha, beta)
+    K, B = normal_equations(prob, ev, nu_a, nu_r, alpha, beta, robust)
     lu = spla.splu(K)
     Xn = lu.solve(B)
     return Xn.reshape(prob.n_nodes, 4, 3), K, B
 
 
 def surrogate_value(prob: Problem, X: np.ndarray, ev: Eval, nu_a, nu_r, alpha, beta,
-                    src: Optional[np.ndarray] = None) -> float:
+                    src: Optional[np.ndarray] = None, robust="welsch") -> float:
     """Full surrogate E(X | X^k) with the constants of Eq. (13) kept, so that
     it equals E at X^k: alignment with fixed u^k (Eqs. 13, 15-16),
     regularization (Eq. 14) and rotation with fixed proj(A^k)."""
     vhat = warp(prob, X, src)
     u = prob.tgt[ev.rho]
     x2 = ((vhat - u) ** 2).sum(1)
-    Sa = math.fsum(welsch(ev.d2, nu_a) + welsch_weight(ev.d2, nu_a) * (x2 - ev.d2))
+    Sa = math.fsum(align_penalty(ev.d2, nu_a, robust) + align_weight(ev.d2, nu_a, robust) * (x2 - ev.d2))
     D = reg_residuals(prob, X)
     y2 = (ev.D ** 2).sum(1)
-    Sr = math.fsum(welsch(y2, nu_r) + welsch_weight(y2, nu_r) * ((D ** 2).sum(1) - y2))
+    Sr = math.fsum(reg_penalty(y2, nu_r, robust) + reg_weight(y2, nu_r, robust) * ((D ** 2).sum(1) - y2))
     A = X[:, :3, :].transpose(0, 2, 1)
     So = math.fsum(((A - ev.R) ** 2).sum((1, 2)))
     return Sa + alpha * Sr + beta * So
@@ -405,13 +458,22 @@ class Params:
     nu_a0: float = 0.0         # <= 0: median closest-point distance at X = I
     nu_a_min: float = 0.0      # <= 0: mean edge length / sqrt(3)
     nu_r0: float = 0.0         # <= 0: 3 * mean edge length
+    robust: str = "welsch"     # one of ROBUST (Sec. 4.1 variants)
+    nu_mode: str = "dynamic"   # "dynamic" or the fixed "max", "min", "med" (Sec. 4.1)
 
 
 def term_weights(prob: Problem, p: Params, nu_a: float, nu_r: float):
     """Eq. (26): alpha = k_alpha |V|/|E_G| nu_r^2/nu_a^2,
     beta = k_beta |V|/|V_G| / (2 nu_a^2).  Reading: recomputed at every nu
-    stage."""
+    stage.
+
+    Reading for the squared-norm variants (Sec. 4.1 names no weights): the
+    Welsch energy scaled by 2 nu_a^2 tends, for small residuals, to
+    sum |e|^2 + k_alpha |V|/|E_G| sum |D|^2 + k_beta |V|/|V_G| E_rot, so
+    alpha = k_alpha |V|/|E_G| and beta = k_beta |V|/|V_G| there."""
     N, n, E = prob.n_src, prob.n_nodes, prob.n_undirected
+    if p.robust != "welsch":
+        return p.k_alpha * (N / E), p.k_beta * (N / n)
     alpha = p.k_alpha * (N / E) * (nu_r * nu_r) / (nu_a * nu_a)
     beta = p.k_beta * (N / n) / (2.0 * nu_a * nu_a)
     return alpha, beta
@@ -428,6 +490,32 @@ def initial_nu(prob: Problem, p: Params, d2_at_identity: np.ndarray):
     nu_a = max(nu_a, nu_min)
     nu_r = p.nu_r0 if p.nu_r0 > 0 else 3.0 * lbar
     return nu_a, nu_min, nu_r
+
+
+def nu_schedule(nu_a, nu_min, nu_r):
+    """The (nu_a, nu_r) of every stage of the dynamic update (Sec. 3.3.3):
+    nu_a halves down to its bound, nu_r halves with it."""
+    out = [(nu_a, nu_r)]
+    while nu_a != nu_min:
+        nu_a = max(nu_a / 2.0, nu_min)
+        nu_r = nu_r / 2.0
+        out.append((nu_a, nu_r))
+    return out
+
+
+def fixed_nu(nu_a, nu_min, nu_r, mode):
+    """Sec. 4.1's fixed-parameter variants: both parameters held at the
+    largest ("max"), smallest ("min") or midway ("med") values that the
+    dynamic update would reach from this start."""
+    sch = nu_schedule(nu_a, nu_min, nu_r)
+    (a_hi, r_hi), (a_lo, r_lo) = sch[0], sch[-1]
+    if mode == "max":
+        return a_hi, r_hi
+    if mode == "min":
+        return a_lo, r_lo
+    if mode == "med":
+        return 0.5 * (a_hi + a_lo), 0.5 * (r_hi + r_lo)
+    raise ValueError(mode)
 
 
 # --------------------------------------------------------------------------
@@ -452,13 +540,22 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
       solves in the stage; the whole solve ends after the stage whose nu_a
       equals its lower bound, or when the solve budget is used up;
     * at every new stage nu_a = max(nu_a/2, lower bound), nu_r = nu_r/2,
-      alpha and beta follow Eq. (26), the history is cleared.
+      alpha and beta follow Eq. (26), the history is cleared;
+    * Sec. 4.1 variants: a fixed nu_mode holds (nu_a, nu_r) at fixed_nu's
+      values for one stage; "l2" has no parameter to update and runs one
+      stage; "l2r" follows the dynamic update of nu_a like the method.
     `force[t]` overrides the accept/reject decision of solve t (replay)."""
+    rb = p.robust
     X = identity(prob.n_nodes) if X0 is None else np.array(X0, np.float64)
     ev0 = evaluate(prob, X, 1.0, 1.0, 0.0, 0.0, nn=nn)
     nu_a, nu_min, nu_r = initial_nu(prob, p, ev0.d2)
+    if p.nu_mode != "dynamic":
+        nu_a, nu_r = fixed_nu(nu_a, nu_min, nu_r, p.nu_mode)
+        nu_min = nu_a
+    if rb == "l2":
+        nu_min = nu_a
     alpha, beta = term_weights(prob, p, nu_a, nu_r)
-    ev = rescore(prob, ev0, nu_a, nu_r, alpha, beta)
+    ev = rescore(prob, ev0, nu_a, nu_r, alpha, beta, rb)
     log = []
     total = 0
     stage = 0
@@ -467,7 +564,7 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
         hist_F: List[np.ndarray] = []
         it = 0
         while True:
-            Xn, _, _ = mm_update(prob, ev, nu_a, nu_r, alpha, beta)
+            Xn, _, _ = mm_update(prob, ev, nu_a, nu_r, alpha, beta, rb)
             hist_G.append(Xn.reshape(-1).copy())
             hist_F.append((Xn - X).reshape(-1))
             if len(hist_G) > p.aa_m + 1:
@@ -477,7 +574,7 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
             E_before = ev.E
             E_cand = None
             if used:
-                ev_c = evaluate(prob, xaa.reshape(X.shape), nu_a, nu_r, alpha, beta, nn=nn)
+                ev_c = evaluate(prob, xaa.reshape(X.shape), nu_a, nu_r, alpha, beta, nn=nn, robust=rb)
                 E_cand = ev_c.E
                 acc = ev_c.E < ev.E
                 if force is not None and total < len(force) and force[total] is not None:
@@ -485,10 +582,10 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
                 if acc:
                     ev_n = ev_c
                 else:
-                    ev_n = evaluate(prob, Xn, nu_a, nu_r, alpha, beta, nn=nn)
+                    ev_n = evaluate(prob, Xn, nu_a, nu_r, alpha, beta, nn=nn, robust=rb)
             else:
                 acc = True
-                ev_n = evaluate(prob, Xn, nu_a, nu_r, alpha, beta, nn=nn)
+                ev_n = evaluate(prob, Xn, nu_a, nu_r, alpha, beta, nn=nn, robust=rb)
             disp = float(np.sqrt(((ev_n.vhat - ev.vhat) ** 2).sum(1).max()))
             entry = dict(total=total, stage=stage, it=it, nu_a=nu_a, nu_r=nu_r, alpha=alpha,
                          beta=beta, E_before=E_before, E_cand=E_cand, aa_used=used,
@@ -509,7 +606,7 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
         nu_a = max(nu_a / 2.0, nu_min)
         nu_r = nu_r / 2.0
         alpha, beta = term_weights(prob, p, nu_a, nu_r)
-        ev = rescore(prob, ev, nu_a, nu_r, alpha, beta)
+        ev = rescore(prob, ev, nu_a, nu_r, alpha, beta, rb)
     return dict(X=X, vhat=ev.vhat, E=ev.E, log=log, total=total, stages=stage + 1,
                 nu_a=nu_a, nu_r=nu_r, eval=ev)
 

@@ -18,6 +18,8 @@ AMM_OK, AMM_ERR_INVALID_ARG, AMM_ERR_STATE, AMM_ERR_OOM, AMM_ERR_HIP, AMM_ERR_NO
 AMM_F32, AMM_F64 = 0, 1
 AMM_FP64_PLAIN, AMM_FP32_REFINE = 0, 1
 AMM_PRECOND_TWO_LEVEL, AMM_PRECOND_BLOCK_JACOBI = 0, 1
+AMM_ROBUST_WELSCH, AMM_ROBUST_L2, AMM_ROBUST_L2_TRUNC = 0, 1, 2
+AMM_NU_DYNAMIC, AMM_NU_FIXED_MAX, AMM_NU_FIXED_MIN, AMM_NU_FIXED_MED = 0, 1, 2, 3
 AMM_MAX_AA_M = 10
 
 
@@ -38,7 +40,8 @@ class amm_params(C.Structure):
                 ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
                 ("init_identity", C.c_int32),
                 ("force_accept", C.c_void_p), ("force_stage_end", C.c_void_p),
-                ("force_len", C.c_int32), ("cg_precond", C.c_int32)]
+                ("force_len", C.c_int32), ("cg_precond", C.c_int32), ("robust", C.c_int32),
+                ("nu_mode", C.c_int32)]
 
 
 class amm_stats(C.Structure):
@@ -69,7 +72,8 @@ class amm_iter_record(C.Structure):
 class amm_step_in(C.Structure):
     _fields_ = [("X", C.c_void_p), ("nu_a", C.c_double), ("nu_r", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("precision", C.c_int32),
-                ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("cg_precond", C.c_int32)]
+                ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("cg_precond", C.c_int32),
+                ("robust", C.c_int32)]
 
 
 class amm_step_out(C.Structure):
@@ -101,6 +105,8 @@ def lib():
             "amm_set_problems": ([vp, C.POINTER(amm_problem), i32], C.c_int),
             "amm_set_problem": ([vp, C.POINTER(amm_problem)], C.c_int),
             "amm_set_leaf_size": ([vp, i32], C.c_int),
+            "amm_count_nn_work": ([vp, i32], C.c_int),
+            "amm_nn_work": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
             "amm_autotune": ([vp, C.POINTER(amm_problem), i32, C.POINTER(i32), i32, C.POINTER(i32),
                               C.POINTER(dbl)], C.c_int),
             "amm_solve": ([vp, C.POINTER(amm_params), vp, vp, C.POINTER(amm_stats)], C.c_int),
@@ -128,7 +134,7 @@ def lib():
 
 EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
-            "amm_set_leaf_size", "amm_autotune",
+            "amm_set_leaf_size", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
             "amm_solve", "amm_step", "amm_k_nnzb", "amm_iter_log", "amm_energy", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
@@ -244,6 +250,18 @@ def amm_set_leaf_size(handle, leaf: int) -> None:
     _check(lib().amm_set_leaf_size(handle, int(leaf)), handle)
 
 
+def amm_count_nn_work(handle, enable: bool) -> None:
+    _check(lib().amm_count_nn_work(handle, 1 if enable else 0), handle)
+
+
+def amm_nn_work(handle) -> dict:
+    """Totals since counting was switched on: queries, box tests, distance
+    evaluations of the closest-point search."""
+    q, b, d = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().amm_nn_work(handle, C.byref(q), C.byref(b), C.byref(d)), handle)
+    return dict(queries=q.value, box_tests=b.value, distance_evals=d.value)
+
+
 def amm_autotune(handle, problems: Sequence[amm_problem], candidates=None):
     """Picks the closest-point leaf size by timing a warm evaluation per
     candidate; returns (leaf, ms).  The handle is left set up with it."""
@@ -288,9 +306,10 @@ def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: int
 
 def amm_step(handle, X, nu_a, nu_r, alpha, beta, precision, cg_rtol=1e-10, cg_maxit=0,
              cg_precond=AMM_PRECOND_TWO_LEVEL, rho=None, d2=None, v_hat=None, X_next=None, K_blocks=None, K_row=None, K_col=None,
-             B=None) -> dict:
+             B=None, robust=AMM_ROBUST_WELSCH) -> dict:
     sin = amm_step_in(X=_ptr(X), nu_a=nu_a, nu_r=nu_r, alpha=alpha, beta=beta,
-                      precision=precision, cg_rtol=cg_rtol, cg_maxit=cg_maxit, cg_precond=cg_precond)
+                      precision=precision, cg_rtol=cg_rtol, cg_maxit=cg_maxit, cg_precond=cg_precond,
+                      robust=robust)
     sout = amm_step_out(rho=_ptr(rho), d2=_ptr(d2), v_hat=_ptr(v_hat), X_next=_ptr(X_next),
                         K_blocks=_ptr(K_blocks), K_row=_ptr(K_row), K_col=_ptr(K_col), B=_ptr(B))
     _check(lib().amm_step(handle, C.byref(sin), C.byref(sout)), handle)

@@ -124,6 +124,7 @@ template <typename T>
 struct StaticT {
     typename V4Of<T>::type* src = nullptr;
     T* iw = nullptr;
+    T* iw_pt = nullptr;
     typename V4Of<T>::type* nodes = nullptr;
     typename V4Of<T>::type* tgt = nullptr;
     typename V4Of<T>::type* blo = nullptr;
@@ -183,6 +184,7 @@ struct Dev {
     int* K_adj;
     int* pj_ptr;
     int* pj_ent;
+    uint64_t* pj_pos;
     int* tgt_user;
     int4* pt_tiles;
     int4* nd_tiles;
@@ -218,6 +220,7 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(v.K_adj, nb);
     c.take(v.pj_ptr, n + 1);
     c.take(v.pj_ent, L.pj_entries);
+    c.take(v.pj_pos, L.pj_entries);
     c.take(v.tgt_user, M);
     c.take(v.pt_tiles, npt);
     c.take(v.nd_tiles, nnd);
@@ -230,11 +233,12 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     v.dyn = v.dyn_ring;
     c.take(v.out, L.P);
     c.take(v.state, 2 * (size_t)L.P);
-    size_t stage = std::max({4 * N, 4 * M, 4 * tn, k * N, 4 * n, na});
+    size_t stage = std::max({4 * N, 4 * M, 4 * tn, (size_t)kMaxK * N, 4 * n, na});
     c.take(v.staging, stage);
     auto statics = [&](auto& s) {
         c.take(s.src, N);
         c.take(s.iw, k * N);
+        c.take(s.iw_pt, (size_t)kMaxK * N);
         c.take(s.nodes, n);
         c.take(s.tgt, M);
         c.take(s.blo, tn);
@@ -315,6 +319,8 @@ struct amm_handle {
     bool timing = false;
     bool cg_coarse = true;           // two-level CG preconditioner
     int leaf = 8;                    // targets per leaf of the closest-point tree (next upload)
+    long long* nn_work = nullptr;    // [n_pt_tiles][3] search counters while counting is on
+    int nn_work_tiles = 0;
     EventTimer timer;
     std::vector<amm_iter_record> iter_log;
 };
@@ -518,6 +524,7 @@ EvalArgs<T> eval_args(amm_handle* h, bool use_override = false) {
     a.pt_max = d.pt_max;
     a.eg_part = d.eg_part;
     a.nd_part = d.nd_part;
+    a.nn_work = h->nn_work;
     return a;
 }
 
@@ -552,6 +559,8 @@ AsmArgs<T> asm_args(amm_handle* h) {
     a.K_adj = h->v.K_adj;
     a.pj_ptr = h->v.pj_ptr;
     a.pj_ent = h->v.pj_ent;
+    a.pj_pos = h->v.pj_pos;
+    a.iw_pt = s.iw_pt;
     a.adj_ptr = h->v.adj_ptr;
     a.adj_nbr = h->v.adj_nbr;
     a.adj_rev = h->v.adj_rev;
@@ -876,14 +885,43 @@ struct PairState {
     amm_stats st{};
 };
 
-// Eq. (26); a graph without edges has no regularization term
-void term_weights(const PairInfo& pi, double k_alpha, double k_beta, PairState& s) {
+// Eq. (26); a graph without edges has no regularization term.  The
+// squared-norm variants take the small-residual scale of the Welsch terms
+// (the Welsch energy times 2 nu_a^2): alpha = k_alpha |V|/|E_G|,
+// beta = k_beta |V|/|V_G|.
+void term_weights(const PairInfo& pi, double k_alpha, double k_beta, int robust, PairState& s) {
     const double N = (double)pi.N, n = (double)pi.n, E = (double)pi.n_undirected;
+    if (robust != AMM_ROBUST_WELSCH) {
+        s.alpha = E > 0 ? k_alpha * (N / E) : 0.0;
+        s.beta = k_beta * (N / n);
+        return;
+    }
     s.alpha = E > 0 ? k_alpha * (N / E) * (s.nu_r * s.nu_r) / (s.nu_a * s.nu_a) : 0.0;
     s.beta = k_beta * (N / n) / (2.0 * s.nu_a * s.nu_a);
 }
 
-void set_scalars(PairDyn& d, double nu_a, double nu_r, double alpha, double beta) {
+// Sec. 4.1's fixed-parameter variants: the largest, smallest or midway
+// (nu_a, nu_r) of the dynamic update from this start (nu_a halves down to
+// nu_min, nu_r halves with it); the stage bound becomes the fixed nu_a so
+// that the solve runs one stage.
+void fix_nu(int mode, PairState& s) {
+    double a = s.nu_a, r = s.nu_r;
+    while (a != s.nu_min) {
+        a = std::max(a / 2.0, s.nu_min);
+        r = r / 2.0;
+    }
+    if (mode == AMM_NU_FIXED_MIN) {
+        s.nu_a = a;
+        s.nu_r = r;
+    } else if (mode == AMM_NU_FIXED_MED) {
+        s.nu_a = 0.5 * (s.nu_a + a);
+        s.nu_r = 0.5 * (s.nu_r + r);
+    }
+    s.nu_min = s.nu_a;
+}
+
+void set_scalars(PairDyn& d, double nu_a, double nu_r, double alpha, double beta, int robust = AMM_ROBUST_WELSCH) {
+    d.robust = robust;
     d.nu_a = nu_a;
     d.nu_r = nu_r;
     d.alpha = alpha;
@@ -906,7 +944,7 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
     for (int p = 0; p < P; ++p) {
         PairDyn& dy = h->dyn[p];
         dy = PairDyn{};
-        set_scalars(dy, 1.0, 1.0, 0.0, 0.0);
+        set_scalars(dy, 1.0, 1.0, 0.0, 0.0, prm.robust);
         dy.flags = PF_EVAL;
     }
     if (prm.init_identity || !X_inout) {
@@ -940,10 +978,12 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
         st.nu_min = prm.nu_a_min > 0 ? prm.nu_a_min : h->lbar[p] / std::sqrt(3.0);
         st.nu_a = std::max(prm.nu_a0 > 0 ? prm.nu_a0 : med, st.nu_min);
         st.nu_r = prm.nu_r0 > 0 ? prm.nu_r0 : 3.0 * h->lbar[p];
-        term_weights(pi, prm.k_alpha, prm.k_beta, st);
+        if (prm.nu_mode != AMM_NU_DYNAMIC) fix_nu(prm.nu_mode, st);
+        if (prm.robust == AMM_ROBUST_L2) st.nu_min = st.nu_a;   // nothing to update: one stage
+        term_weights(pi, prm.k_alpha, prm.k_beta, prm.robust, st);
         st.st.stages = 1;
         PairDyn& dy = h->dyn[p];
-        set_scalars(dy, st.nu_a, st.nu_r, st.alpha, st.beta);
+        set_scalars(dy, st.nu_a, st.nu_r, st.alpha, st.beta, prm.robust);
         dy.has_prev = 1;   // in place: same transforms, same closest points
     }
     TRY(evaluate<T>(h));
@@ -961,7 +1001,7 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
             PairState& st = ps[p];
             dy = PairDyn{};
             dy.cur = st.cur;
-            set_scalars(dy, st.nu_a, st.nu_r, st.alpha, st.beta);
+            set_scalars(dy, st.nu_a, st.nu_r, st.alpha, st.beta, prm.robust);
             if (st.done) continue;
             any = true;
             dy.flags = PF_SOLVE;
@@ -1077,7 +1117,7 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
             st.st.stages += 1;
             st.nu_a = std::max(st.nu_a / 2.0, st.nu_min);
             st.nu_r = st.nu_r / 2.0;
-            term_weights(L.info[p], prm.k_alpha, prm.k_beta, st);
+            term_weights(L.info[p], prm.k_alpha, prm.k_beta, prm.robust, st);
             st.it = 0;
             st.hist_count = 0;
             st.hist_head = -1;
@@ -1092,7 +1132,7 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
                 dy.flags = restage[p] ? PF_EVAL : 0;
                 dy.cur = dy.eval_x = dy.eval_dst = ps[p].cur;
                 dy.has_prev = 1;
-                set_scalars(dy, ps[p].nu_a, ps[p].nu_r, ps[p].alpha, ps[p].beta);
+                set_scalars(dy, ps[p].nu_a, ps[p].nu_r, ps[p].alpha, ps[p].beta, prm.robust);
             }
             TRY(evaluate<T>(h));
             for (int p = 0; p < P; ++p)
@@ -1106,7 +1146,7 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
         dy.flags = PF_EVAL | PF_SOLVE;
         dy.cur = dy.eval_x = dy.eval_dst = ps[p].cur;
         dy.has_prev = 1;
-        set_scalars(dy, ps[p].nu_a, ps[p].nu_r, ps[p].alpha, ps[p].beta);
+        set_scalars(dy, ps[p].nu_a, ps[p].nu_r, ps[p].alpha, ps[p].beta, prm.robust);
     }
     TRY(evaluate<T>(h));
     vec_op<T>(h, PF_SOLVE, 5);   // X[2] = X[cur]
@@ -1217,7 +1257,7 @@ amm_status step_impl(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     PairDyn& dy = h->dyn[0];
     dy = PairDyn{};
     dy.flags = PF_EVAL;
-    set_scalars(dy, in->nu_a, in->nu_r, in->alpha, in->beta);
+    set_scalars(dy, in->nu_a, in->nu_r, in->alpha, in->beta, in->robust);
     TRY(evaluate<T>(h));
     out->energy[0] = h->h_out[0].E;
     out->energy[1] = h->h_out[0].Ea;
@@ -1335,6 +1375,7 @@ void amm_destroy(amm_handle* h) {
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
     if (h->prog) (void)hipHostFree(h->prog);
+    if (h->nn_work) (void)hipFree(h->nn_work);
     if (h->h_scratch) (void)hipHostFree(h->h_scratch);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
     if (h->ws_own) (void)hipFree(h->ws_own);
@@ -1384,6 +1425,12 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     HIPC(hipSetDevice(h->device));
     HIPC(hipStreamSynchronize(h->stream));
     h->has_problem = false;
+    if (h->nn_work) {
+        // the counters are sized for the previous problems' tiles
+        (void)hipFree(h->nn_work);
+        h->nn_work = nullptr;
+        h->nn_work_tiles = 0;
+    }
     Layout L;
     std::vector<double> lb;
     TRY(analyse(h, probs, n_pairs, L, lb));
@@ -1427,6 +1474,7 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up(h, v.K_adj, Lr.K_adj));
     TRY(up(h, v.pj_ptr, Lr.pj_ptr));
     TRY(up(h, v.pj_ent, Lr.pj_ent));
+    TRY(up(h, v.pj_pos, Lr.pj_pos));
     TRY(up(h, v.tgt_user, Lr.tgt_user));
     TRY(up(h, v.info, Lr.info));
     TRY(up(h, reinterpret_cast<int32_t*>(v.pt_tiles), Lr.pt_tiles));
@@ -1434,6 +1482,7 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up(h, reinterpret_cast<int32_t*>(v.eg_tiles), Lr.eg_tiles));
     TRY(up_real(h, v.sf.src, v.sd.src, Lr.src4));
     TRY(up_real(h, v.sf.iw, v.sd.iw, Lr.iw));
+    TRY(up_real(h, v.sf.iw_pt, v.sd.iw_pt, Lr.iw_pt));
     TRY(up_real(h, v.sf.nodes, v.sd.nodes, Lr.nodes4));
     TRY(up_real(h, v.sf.tgt, v.sd.tgt, Lr.tgt4));
     TRY(up_real(h, v.sf.blo, v.sd.blo, Lr.box_lo));
@@ -1541,6 +1590,10 @@ amm_status amm_solve(amm_handle* h, const amm_params* prm, void* X_inout, void* 
     if (!prm->init_identity && !X_inout) return fail(h, AMM_ERR_INVALID_ARG, "X_inout needed without init_identity");
     if (prm->cg_precond != AMM_PRECOND_TWO_LEVEL && prm->cg_precond != AMM_PRECOND_BLOCK_JACOBI)
         return fail(h, AMM_ERR_INVALID_ARG, "bad cg_precond");
+    if (prm->robust < AMM_ROBUST_WELSCH || prm->robust > AMM_ROBUST_L2_TRUNC)
+        return fail(h, AMM_ERR_INVALID_ARG, "bad robust");
+    if (prm->nu_mode < AMM_NU_DYNAMIC || prm->nu_mode > AMM_NU_FIXED_MED)
+        return fail(h, AMM_ERR_INVALID_ARG, "bad nu_mode");
     HIPC(hipSetDevice(h->device));
     h->cg_coarse = prm->cg_precond == AMM_PRECOND_TWO_LEVEL;
     if (prm->precision == AMM_FP64_PLAIN) return solve_impl<double>(h, *prm, X_inout, v_out, stats);
@@ -1556,11 +1609,52 @@ amm_status amm_step(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
         return fail(h, AMM_ERR_INVALID_ARG, "nu_a, nu_r, beta must be > 0 and alpha >= 0");
     if (in->cg_precond != AMM_PRECOND_TWO_LEVEL && in->cg_precond != AMM_PRECOND_BLOCK_JACOBI)
         return fail(h, AMM_ERR_INVALID_ARG, "bad cg_precond");
+    if (in->robust < AMM_ROBUST_WELSCH || in->robust > AMM_ROBUST_L2_TRUNC)
+        return fail(h, AMM_ERR_INVALID_ARG, "bad robust");
     HIPC(hipSetDevice(h->device));
     h->cg_coarse = in->cg_precond == AMM_PRECOND_TWO_LEVEL;
     if (in->precision == AMM_FP64_PLAIN) return step_impl<double>(h, in, out);
     if (in->precision == AMM_FP32_REFINE) return step_impl<float>(h, in, out);
     return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");
+}
+
+amm_status amm_count_nn_work(amm_handle* h, int32_t enable) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    if (!h->has_problem) return fail(h, AMM_ERR_STATE, "amm_count_nn_work before amm_set_problem");
+    HIPC(hipSetDevice(h->device));
+    HIPC(hipStreamSynchronize(h->stream));
+    if (h->nn_work) (void)hipFree(h->nn_work);
+    h->nn_work = nullptr;
+    h->nn_work_tiles = 0;
+    if (!enable) return AMM_OK;
+    const size_t bytes = sizeof(long long) * 3 * std::max(h->L.n_pt_tiles, 1);
+    if (hipMalloc((void**)&h->nn_work, bytes) != hipSuccess) {
+        h->nn_work = nullptr;
+        return fail(h, AMM_ERR_OOM, "search counters");
+    }
+    HIPC(hipMemsetAsync(h->nn_work, 0, bytes, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    h->nn_work_tiles = h->L.n_pt_tiles;
+    return AMM_OK;
+}
+
+amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals) {
+    if (!h || !queries || !box_tests || !distance_evals) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    if (!h->nn_work) return fail(h, AMM_ERR_STATE, "search counting is off");
+    HIPC(hipSetDevice(h->device));
+    std::vector<long long> c(3 * (size_t)h->nn_work_tiles);
+    HIPC(hipMemcpyAsync(c.data(), h->nn_work, sizeof(long long) * c.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    long long q = 0, b = 0, d = 0;
+    for (int t = 0; t < h->nn_work_tiles; ++t) {
+        q += c[3 * t];
+        b += c[3 * t + 1];
+        d += c[3 * t + 2];
+    }
+    *queries = q;
+    *box_tests = b;
+    *distance_evals = d;
+    return AMM_OK;
 }
 
 amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, int32_t* count) {

@@ -48,7 +48,7 @@ struct PairDyn {
     int32_t aa_mk;           // Anderson window m_k for this iteration
     int32_t aa_slot[11];     // ring slots: [0] = newest (k), [1] = k-1, ...
     int32_t has_prev;        // closest-point warm start available in set `cur`
-    int32_t pad;
+    int32_t robust;          // amm_robust
     double cg_rtol;          // CG stopping tolerance of this pair (0: the launch's)
 };
 
@@ -91,6 +91,7 @@ struct Layout {
     std::vector<int32_t> src_internal;  // user index -> internal point
     std::vector<int32_t> iidx;       // [k][Ntot] internal node ids
     std::vector<double> iw;          // [k][Ntot]
+    std::vector<double> iw_pt;       // [Ntot][kMaxK] the same weights point-major, zero padded
     std::vector<double> nodes4;      // [ntot][4]
     std::vector<int32_t> node_user;  // internal node -> user node (concatenated)
     std::vector<int32_t> node_internal;
@@ -99,6 +100,9 @@ struct Layout {
     std::vector<double> adj_r;       // r_ij of Eq. (8)
     std::vector<int32_t> K_ptr, K_col, K_adj, K_diag;
     std::vector<int32_t> pj_ptr, pj_ent;   // points influenced by each node: (pt << 3) | slot
+    // per point-list entry of row j: byte b = position, within row j's column
+    // list, of the point's influence b
+    std::vector<uint64_t> pj_pos;
     std::vector<double> tgt4;        // [Mtot][4] sorted; w = user index within the pair
     std::vector<int32_t> tgt_user;   // sorted position -> user index within the pair
     std::vector<double> box_lo, box_hi;    // [tree_nodes][4]
@@ -117,6 +121,7 @@ constexpr int kPointTile = 256;
 constexpr int kNodeTile = 16;        // solver rows per tile (4 threads per row: one wave)
 constexpr int kEdgeTile = 256;
 constexpr int kMaxCols = 192;        // K blocks per row supported by the assembly
+static_assert(kMaxCols <= 256, "column positions are stored in one byte");
 constexpr int kMaxK = 8;
 constexpr int kCoarseMaxAgg = 32;    // aggregates per pair (coarse order <= 128)
 constexpr int kAggMinShift = 6;      // at least 64 nodes (4 node tiles) per aggregate

@@ -72,6 +72,7 @@ struct EvalArgs {
     double* pt_max;
     double* eg_part;
     double* nd_part;
+    long long* nn_work;      // per point tile: queries, box tests, distance evaluations (or null)
 };
 
 struct FinalArgs {
@@ -100,6 +101,8 @@ struct AsmArgs {
     const int* K_adj;
     const int* pj_ptr;
     const int* pj_ent;
+    const uint64_t* pj_pos;  // per entry: byte b = column position of influence b
+    const T* iw_pt;          // [Ntot][kMaxK] influence weights, point-major
     const int* adj_ptr;
     const int* adj_nbr;
     const int* adj_rev;

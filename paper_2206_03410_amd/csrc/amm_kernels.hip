@@ -20,12 +20,16 @@ namespace amm {
 // ---------------------------------------------------------------- evaluation
 
 // Per source point: warp (Eq. 2), closest target, Welsch value and weight
-// (Eqs. 5, 6 and the weight w_a of Eq. 16), the alignment residual e_i = v_hat_i - u_rho(i), and the
-// max displacement against the accepted iterate.  One thread per point.
-template <typename T>
+// (Eqs. 5, 6 and the weight w_a of Eq. 16) or those of a squared-norm
+// variant of Sec. 4.1, the alignment residual e_i = v_hat_i - u_rho(i), and
+// the max displacement against the accepted iterate.  One thread per point.
+// COUNT adds the search's work to the tile's counters (reporting only).
+template <typename T, bool COUNT>
 __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     using V = typename V4Of<T>::type;
     __shared__ T sh[kPointTile];
+    __shared__ long long shc[COUNT ? kPointTile : 1];
+    NnWork wk{0, 0};
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int4 td = a.pt_tiles[tile];
     const int p = td.x;
@@ -65,7 +69,7 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
         const int prev = dy.has_prev ? a.rho[cur][i] - (int)pi.tgt_off : -1;
         int bpos;
         T d2;
-        nn_search<T>(pi, a.tgt, a.blo, a.bhi, vx, vy, vz, prev, bpos, d2);
+        nn_search<T, V, COUNT>(pi, a.tgt, a.blo, a.bhi, vx, vy, vz, prev, bpos, d2, &wk);
         const V u = a.tgt[pi.tgt_off + bpos];
         // e_i = v_hat_i - u_rho(i)
         //     = sum_j w_ij ((A_j - I) d_ij + t_j) + (v_i - u) + (sum_j w_ij - 1) v_i
@@ -76,10 +80,22 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
         q.y = sy + (v.y - u.y) + sw1 * v.y;
         q.z = sz + (v.z - u.z) + sw1 * v.z;
         d2 = sq3(q.x, q.y, q.z);
-        const T inv = T(1) / (T(2) * (T)dy.nu_a * (T)dy.nu_a);
-        const T t = d2 * inv;
-        psi = -expm1(-t);
-        const T wa = exp(-t) * inv;
+        T wa;
+        if (dy.robust == AMM_ROBUST_WELSCH) {
+            const T inv = T(1) / (T(2) * (T)dy.nu_a * (T)dy.nu_a);
+            const T t = d2 * inv;
+            psi = -expm1(-t);
+            wa = exp(-t) * inv;
+        } else if (dy.robust == AMM_ROBUST_L2) {
+            psi = d2;
+            wa = T(1);
+        } else {
+            // truncated quadratic: weight 1 inside 3 nu_a, constant outside
+            const T tau2 = T(9) * (T)dy.nu_a * (T)dy.nu_a;
+            const bool in = d2 < tau2;
+            psi = in ? d2 : tau2;
+            wa = in ? T(1) : T(0);
+        }
         q.w = wa;
         a.qw[dst][i] = q;
         a.rho[dst][i] = (int)pi.tgt_off + bpos;
@@ -100,6 +116,17 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     if (threadIdx.x == 0) {
         a.pt_part[tile] = (double)tot;
         a.pt_max[tile] = (double)mx;
+    }
+    if constexpr (COUNT) {
+        const long long nb = block_sum<long long, kPointTile>(wk.boxes, shc);
+        const long long np = block_sum<long long, kPointTile>(wk.points, shc);
+        if (threadIdx.x == 0) {
+            // one block per tile and launch, launches in stream order
+            long long* c = a.nn_work + 3 * (size_t)tile;
+            c[0] += td.z - td.y;
+            c[1] += nb;
+            c[2] += np;
+        }
     }
 }
 
@@ -130,9 +157,15 @@ __global__ void __launch_bounds__(kEdgeTile) k_eval_edges(EvalArgs<T> a) {
         const T Dy = r * (dx * Xb[1] + dyy * (Xb[4] - T(1)) + dz * Xb[7] + (Xb[10] - Xa[10]));
         const T Dz = r * (dx * Xb[2] + dyy * Xb[5] + dz * (Xb[8] - T(1)) + (Xb[11] - Xa[11]));
         const T D2 = sq3(Dx, Dy, Dz);
-        const T inv = T(1) / (T(2) * (T)dy.nu_r * (T)dy.nu_r);
-        psi = -expm1(-D2 * inv);
-        a.wr[dy.eval_dst][e] = exp(-D2 * inv) * inv;
+        if (dy.robust == AMM_ROBUST_WELSCH) {
+            const T inv = T(1) / (T(2) * (T)dy.nu_r * (T)dy.nu_r);
+            psi = -expm1(-D2 * inv);
+            a.wr[dy.eval_dst][e] = exp(-D2 * inv) * inv;
+        } else {
+            // both squared-norm variants: plain |D|^2, unit weight
+            psi = D2;
+            a.wr[dy.eval_dst][e] = T(1);
+        }
         V D;
         D.x = Dx;
         D.y = Dy;
@@ -356,10 +389,17 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
         const int e = base + lane;
         if (e < e1) {
             const int ent = a.pj_ent[e];
+            const uint64_t pos = a.pj_pos[e];
             const int i = ent >> 3, s = ent & 7;
             const V v = a.src[i];
             const V q = qw[i];
-            const T c = q.w * a.iw[(size_t)s * a.Ntot + i];
+            const V* wp = reinterpret_cast<const V*>(a.iw_pt + (size_t)kMaxK * i);
+            const V w0 = wp[0], w1 = wp[1];
+            const T wv[kMaxK] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+            T ws = wv[0];
+#pragma unroll
+            for (int b = 1; b < kMaxK; ++b) ws = s == b ? wv[b] : ws;
+            const T c = q.w * ws;
             const T dx = v.x - pj.x, dyy = v.y - pj.y, dz = v.z - pj.z;
             smom[lane][0] = c * dx * dx;
             smom[lane][1] = c * dx * dyy;
@@ -385,30 +425,23 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
             racc[9] += c * q.x;
             racc[10] += c * q.y;
             racc[11] += c * q.z;
-            for (int b = 0; b < k; ++b) {
-                const int nid = a.iidx[(size_t)b * a.Ntot + i];
-                int lo = 0, hi = ncol - 1;   // the node is in the row's pattern by construction
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (scol[mid] < nid)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                spos[lane][b] = lo;
-                swgt[lane][b] = a.iw[(size_t)b * a.Ntot + i];
+#pragma unroll
+            for (int b = 0; b < kMaxK; ++b) {
+                spos[lane][b] = (int)((pos >> (8 * b)) & 255u);
+                swgt[lane][b] = wv[b];
             }
         }
         __syncthreads();
         // scatter, one staged point after the other: for a fixed point the k
         // influences land in k distinct column blocks, so the 10k lanes write
-        // distinct cells; the order over points is fixed
+        // distinct cells; the order over points is fixed.  A wave's LDS
+        // operations complete in issue order, so the read of a cell in step
+        // t + 1 sees the write of step t.
         const int cnt = min(64, e1 - base);
         if (my_b < k) {
             for (int t = 0; t < cnt; ++t) {
                 T* cell = &sacc[spos[t][my_b]][my_m];
                 *cell += swgt[t][my_b] * smom[t][my_m];
-                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this write lands before the next read
             }
         }
         __syncthreads();
@@ -968,7 +1001,10 @@ template <typename T>
 void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_tiles, const FinalArgs& f,
                  int P, hipStream_t s, KernelTimer* tm) {
     if (n_pt_tiles) {
-        launch_one(tm, "eval_points", k_eval_points<T>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
+        if (a.nn_work)
+            launch_one(tm, "eval_points", k_eval_points<T, true>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
+        else
+            launch_one(tm, "eval_points", k_eval_points<T, false>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
     }
     if (n_eg_tiles) {
         launch_one(tm, "eval_edges", k_eval_edges<T>, dim3(n_eg_tiles), dim3(kEdgeTile), s, a);

@@ -36,18 +36,27 @@ __host__ __device__ inline T box_d2(const V& lo, const V& hi, T qx, T qy, T qz) 
 
 // ---------------------------------------------------------------- closest point
 
+// Work of one search, counted only where asked for (COUNT = true): box
+// lower-bound tests and target distance evaluations.
+struct NnWork {
+    int boxes;
+    int points;
+};
+
 // Exact closest target of query q among the pair's targets, by depth-first
 // traversal of the implicit complete binary tree of boxes (heap layout: node
 // 1 is the root, children 2i and 2i+1, leaves L..2L-1 each holding `leaf`
 // consecutive Morton-sorted targets).  Near child first; pending far
 // children are kept as one bit per level (no stack).  `prev` (a target
 // position from the previous evaluation, or -1) seeds the bound.  Ties in
-// distance go to the lowest user target index (stored in .w).
-template <typename T, typename V>
+// distance go to the lowest user target index (stored in .w).  With COUNT,
+// `work` accumulates the box tests and distance evaluations.
+template <typename T, typename V, bool COUNT = false>
 __host__ __device__ inline void nn_search(const PairInfo& pi, const V* __restrict__ tgt,
                                           const V* __restrict__ blo,
                                           const V* __restrict__ bhi, T qx, T qy,
-                                          T qz, int prev, int& best_pos, T& best_d2) {
+                                          T qz, int prev, int& best_pos, T& best_d2,
+                                          NnWork* work = nullptr) {
     const V* lo = blo + pi.tree_off;
     const V* hi = bhi + pi.tree_off;
     const V* tg = tgt + pi.tgt_off;
@@ -61,6 +70,7 @@ __host__ __device__ inline void nn_search(const PairInfo& pi, const V* __restric
         bd = sq3(u.x - qx, u.y - qy, u.z - qz);
         bid = (int)u.w;
         bpos = prev;
+        if constexpr (COUNT) work->points += 1;
     }
     unsigned node = 1, trail = 0;
     int depth = 0;
@@ -69,6 +79,7 @@ __host__ __device__ inline void nn_search(const PairInfo& pi, const V* __restric
             const unsigned c0 = node << 1, c1 = c0 | 1u;
             const T d0 = box_d2<T>(lo[c0], hi[c0], qx, qy, qz);
             const T d1 = box_d2<T>(lo[c1], hi[c1], qx, qy, qz);
+            if constexpr (COUNT) work->boxes += 2;
             const bool first0 = d0 <= d1;
             const T dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
             if (dn <= bd) {
@@ -80,6 +91,7 @@ __host__ __device__ inline void nn_search(const PairInfo& pi, const V* __restric
         } else {
             const int s = (int)(node - L) * LB;
             const int e = min(s + LB, M);
+            if constexpr (COUNT) work->points += e - s;
             for (int t = s; t < e; ++t) {
                 V u = tg[t];
                 T d = sq3(u.x - qx, u.y - qy, u.z - qz);
@@ -97,6 +109,7 @@ __host__ __device__ inline void nn_search(const PairInfo& pi, const V* __restric
             trail &= ~(1u << lvl);
             node = (node >> (depth - lvl)) ^ 1u;
             depth = lvl;
+            if constexpr (COUNT) work->boxes += 1;
             if (box_d2<T>(lo[node], hi[node], qx, qy, qz) <= bd) {
                 next = true;
                 break;

@@ -192,6 +192,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.src_internal.resize(L.Ntot);
     L.iidx.resize((size_t)k * L.Ntot);
     L.iw.resize((size_t)k * L.Ntot);
+    L.iw_pt.assign((size_t)kMaxK * L.Ntot, 0.0);
     L.nodes4.assign(4 * L.ntot, 0.0);
     L.node_user.resize(L.ntot);
     L.node_internal.resize(L.ntot);
@@ -257,6 +258,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
             for (int a = 0; a < k; ++a) {
                 L.iidx[(size_t)a * L.Ntot + so + q] = (int32_t)(no + n_inv[hp.infl_idx[u * k + a]]);
                 L.iw[(size_t)a * L.Ntot + so + q] = hp.infl_w[u * k + a];
+                L.iw_pt[(size_t)(so + q) * kMaxK + a] = hp.infl_w[u * k + a];
             }
         }
         for (int64_t q = 0; q < hp.n; ++q) {
@@ -358,6 +360,17 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         for (int64_t q = 0; q < hp.n; ++q) {
             L.pj_ptr[no + q] = (int32_t)L.pj_ent.size();
             L.pj_ent.insert(L.pj_ent.end(), pj[q].begin(), pj[q].end());
+            const auto& c = cols[q];
+            for (int32_t ent : pj[q]) {
+                const int64_t i = ent >> 3;
+                uint64_t pos = 0;
+                for (int b = 0; b < k; ++b) {
+                    const int32_t nid = L.iidx[(size_t)b * L.Ntot + i];
+                    const uint64_t at = (uint64_t)(std::lower_bound(c.begin(), c.end(), nid) - c.begin());
+                    pos |= at << (8 * b);
+                }
+                L.pj_pos.push_back(pos);
+            }
         }
 
         // targets: Morton order, implicit complete tree of `leaf`-sized buckets

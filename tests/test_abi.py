@@ -24,6 +24,36 @@ def test_header_declares_the_binding_names():
     assert set(declared_functions()) == set(amm.EXPORTED)
 
 
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's typedef of the same name."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [getattr(amm, n) for n in ("amm_problem", "amm_params", "amm_stats", "amm_iter_record",
+                                         "amm_step_in", "amm_step_out")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "amm.h"', "int main(void) {"]
+    for st in structs:
+        lines.append(f'printf("{st.__name__} size %zu\\n", sizeof({st.__name__}));')
+        for f in st._fields_:
+            lines.append(f'printf("{st.__name__} {f[0]} %zu\\n", offsetof({st.__name__}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for st in structs:
+        assert got[(st.__name__, "size")] == C.sizeof(st), st.__name__
+        for f in st._fields_:
+            assert got[(st.__name__, f[0])] == getattr(st, f[0]).offset, (st.__name__, f[0])
+
+
 def test_library_exports_every_declared_symbol():
     L = C.CDLL(amm._LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(L, n)]

@@ -353,3 +353,33 @@ def test_leaf_size_and_autotune_leave_results_unchanged():
         outs.append((X.cpu().numpy(), st["iters"], st["energy"]))
     for X, it, E in outs[1:]:
         assert np.array_equal(X, outs[0][0]) and it == outs[0][1] and E == outs[0][2]
+
+
+def test_nn_work_counters(pair):
+    """Counting the search's work leaves every result unchanged (bitwise),
+    counts each query once per evaluation, examines at least one target per
+    query and never more than all targets, and is reproducible."""
+    _announce("test_nn_work_counters")
+    prob = O.from_pair(pair)
+    X = torch.tensor(synth.perturbed_transforms(prob.n_nodes, 61, 0.01, 0.001), device="cuda:0")
+    with Session(pair, torch.float64) as s:
+        N = prob.n_src
+        rho0 = torch.empty(N, dtype=torch.int32, device="cuda:0")
+        e0 = amm.amm_energy(s.h, X, None, 0.05, 0.1, 1.0, 1.0, rho=rho0)
+        amm.amm_count_nn_work(s.h, True)
+        got = []
+        for _ in range(2):
+            rho1 = torch.empty(N, dtype=torch.int32, device="cuda:0")
+            e1 = amm.amm_energy(s.h, X, None, 0.05, 0.1, 1.0, 1.0, rho=rho1)
+            assert e1 == e0
+            assert torch.equal(rho0, rho1)
+            got.append(amm.amm_nn_work(s.h))
+        amm.amm_count_nn_work(s.h, False)
+        with pytest.raises(amm.AmmError):
+            amm.amm_nn_work(s.h)
+    w1, w2 = got
+    assert w1["queries"] == N and w2["queries"] == 2 * N
+    assert w2["box_tests"] == 2 * w1["box_tests"]
+    assert w2["distance_evals"] == 2 * w1["distance_evals"]
+    assert N <= w1["distance_evals"] <= N * pair.n_tgt
+    assert w1["box_tests"] >= 2 * N

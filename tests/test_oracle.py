@@ -281,21 +281,15 @@ def test_dense_lstsq_matches_sparse_solve(small_prob):
     assert np.abs(Xl - Xn.reshape(-1, 3)).max() < 1e-8 * max(1.0, np.abs(Xl).max())
 
 
-def test_large_nu_limit_is_l2_least_squares(small_prob):
-    """With Eq. (26) scaling and nu_a = nu_r -> infinity, the MM step is the
-    l2 problem of Sec. 4.2 with weights 1, k_a |V|/|E_G|, k_b |V|/|V_G|.
-    The l2 rows are built here from the warp's Jacobian (by exact finite
-    differences of the warp and of Eq. 7, both linear), not from F and H."""
-    prob = small_prob
-    p = O.Params()
-    nu = 1e6
-    alpha, beta = O.term_weights(prob, p, nu, nu)
-    Xk = O.identity(prob.n_nodes)
-    ev = O.evaluate(prob, Xk, nu, nu, alpha, beta)
-    Xn, _, _ = O.mm_update(prob, ev, nu, nu, alpha, beta)
+def _l2_lstsq(prob, Xk, u, row_w=None, k_alpha=100.0, k_beta=1.0):
+    """Minimizer of sum_i row_w_i |v_hat_i(X) - u_i|^2 + k_a |V|/|E_G| sum |D|^2
+    + k_b |V|/|V_G| sum |A_j - proj(A_j^k)|^2, built from the Jacobians of
+    the warp and of Eq. 7 (exact finite differences of two linear maps) and
+    solved by dense least squares; no part of it comes from F, H or K."""
     n = prob.n_nodes
     N, E = prob.n_src, prob.n_undirected
-    # Jacobians of warp and D with respect to the 4n rows of X (3 columns share them)
+    w = np.ones(N) if row_w is None else np.asarray(row_w, np.float64)
+    sw = np.sqrt(w)
     nv = 4 * n
     Jw = np.zeros((N, nv))
     Jd = np.zeros((prob.dir_edges.shape[0], nv))
@@ -307,23 +301,136 @@ def test_large_nu_limit_is_l2_least_squares(small_prob):
         Xe.reshape(nv, 3)[c, 0] = 1.0
         Jw[:, c] = O.warp(prob, Xe)[:, 0] - w0
         Jd[:, c] = O.reg_residuals(prob, Xe)[:, 0] - d0
-    u = prob.tgt[ev.rho]
-    lhs = [Jw, math.sqrt(p.k_alpha * N / E) * Jd]
+    ca, cb = math.sqrt(k_alpha * N / E), math.sqrt(k_beta * N / n)
     R, _ = O.proj_rotation(Xk[:, :3, :].transpose(0, 2, 1))
     Jr = np.zeros((3 * n, nv))
     for j in range(n):
         for a in range(3):
             Jr[3 * j + a, 4 * j + a] = 1.0
-    lhs.append(math.sqrt(p.k_beta * N / n) * Jr)
+    lhs = np.concatenate([sw[:, None] * Jw, ca * Jd, cb * Jr], 0)
     cols = []
     for c in range(3):
         w_off = O.warp(prob, Z0)[:, c]
         d_off = O.reg_residuals(prob, Z0)[:, c]
-        rhs = np.concatenate([u[:, c] - w_off, -math.sqrt(p.k_alpha * N / E) * d_off,
-                              math.sqrt(p.k_beta * N / n) * R[:, c, :].reshape(-1)])
-        cols.append(np.linalg.lstsq(np.concatenate(lhs, 0), rhs, rcond=None)[0])
-    Xl = np.stack(cols, 1)
+        rhs = np.concatenate([sw * (u[:, c] - w_off), -ca * d_off, cb * R[:, c, :].reshape(-1)])
+        cols.append(np.linalg.lstsq(lhs, rhs, rcond=None)[0])
+    return np.stack(cols, 1)
+
+
+def test_large_nu_limit_is_l2_least_squares(small_prob):
+    """With Eq. (26) scaling and nu_a = nu_r -> infinity, the MM step is the
+    squared-norm problem with weights 1, k_a |V|/|E_G|, k_b |V|/|V_G|."""
+    prob = small_prob
+    p = O.Params()
+    nu = 1e6
+    alpha, beta = O.term_weights(prob, p, nu, nu)
+    Xk = O.identity(prob.n_nodes)
+    ev = O.evaluate(prob, Xk, nu, nu, alpha, beta)
+    Xn, _, _ = O.mm_update(prob, ev, nu, nu, alpha, beta)
+    Xl = _l2_lstsq(prob, Xk, prob.tgt[ev.rho])
     assert np.abs(Xl - Xn.reshape(-1, 3)).max() < 1e-7
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.1 variants: squared norms and fixed nu
+# --------------------------------------------------------------------------
+
+def test_l2_variant_step_is_least_squares(small_prob):
+    """"l2-norm": unit alignment weights and plain squared regularization;
+    one MM step from a perturbed X^k is the least-squares minimizer with the
+    closest points and rotations of X^k held fixed."""
+    prob = small_prob
+    p = O.Params(robust="l2")
+    alpha, beta = O.term_weights(prob, p, 0.3, 0.2)
+    assert alpha == pytest.approx(100.0 * prob.n_src / prob.n_undirected, rel=1e-15)
+    assert beta == pytest.approx(prob.n_src / prob.n_nodes, rel=1e-15)
+    Xk = synth.perturbed_transforms(prob.n_nodes, 91, 0.02, 0.003)
+    ev = O.evaluate(prob, Xk, 0.3, 0.2, alpha, beta, robust="l2")
+    assert ev.E_align == pytest.approx(math.fsum(ev.d2), rel=1e-14)
+    assert ev.E_reg == pytest.approx(math.fsum((ev.D ** 2).sum(1)), rel=1e-14)
+    Xn, _, _ = O.mm_update(prob, ev, 0.3, 0.2, alpha, beta, robust="l2")
+    Xl = _l2_lstsq(prob, Xk, prob.tgt[ev.rho])
+    assert np.abs(Xl - Xn.reshape(-1, 3)).max() < 1e-8
+
+
+def test_l2r_variant_step_drops_far_points(small_prob):
+    """"l2-norm-r": a point takes weight 1 when its closest-point distance is
+    below 3 nu_a and 0 otherwise (counted here point by point); the step is
+    the least-squares minimizer over the kept points."""
+    prob = small_prob
+    p = O.Params(robust="l2r")
+    Xk = synth.perturbed_transforms(prob.n_nodes, 92, 0.02, 0.003)
+    ev0 = O.evaluate(prob, Xk, 1.0, 1.0, 0.0, 0.0)
+    nu = float(np.median(np.sqrt(ev0.d2))) / 3.0        # about half the points kept
+    alpha, beta = O.term_weights(prob, p, nu, nu)
+    ev = O.evaluate(prob, Xk, nu, nu, alpha, beta, robust="l2r")
+    keep = np.array([1.0 if math.sqrt(d) < 3.0 * nu else 0.0 for d in ev.d2])
+    assert 0.3 < keep.mean() < 0.7
+    Ea = math.fsum(d if k else 9.0 * nu * nu for d, k in zip(ev.d2, keep))
+    assert ev.E_align == pytest.approx(Ea, rel=1e-14)
+    Xn, _, _ = O.mm_update(prob, ev, nu, nu, alpha, beta, robust="l2r")
+    Xl = _l2_lstsq(prob, Xk, prob.tgt[ev.rho], row_w=keep)
+    assert np.abs(Xl - Xn.reshape(-1, 3)).max() < 1e-8
+
+
+def test_l2r_surrogate_majorizes_truncated_energy(small_prob):
+    """The 0/1 rule is an MM weight: the surrogate touches the truncated
+    energy at X^k and lies above it nearby (closest points recomputed)."""
+    prob = small_prob
+    Xk = synth.perturbed_transforms(prob.n_nodes, 93, 0.02, 0.003)
+    ev0 = O.evaluate(prob, Xk, 1.0, 1.0, 0.0, 0.0)
+    nu = float(np.median(np.sqrt(ev0.d2))) / 3.0
+    alpha, beta = O.term_weights(prob, O.Params(robust="l2r"), nu, nu)
+    ev = O.evaluate(prob, Xk, nu, nu, alpha, beta, robust="l2r")
+    S = lambda X: O.surrogate_value(prob, X, ev, nu, nu, alpha, beta, robust="l2r")
+    assert S(Xk) == pytest.approx(ev.E, rel=1e-13)
+    rng = np.random.default_rng(94)
+    for s in [1e-4, 1e-3, 1e-2]:
+        X = Xk + rng.normal(size=Xk.shape) * s
+        Ex = O.evaluate(prob, X, nu, nu, alpha, beta, robust="l2r").E
+        assert S(X) >= Ex - 1e-12 * abs(Ex)
+
+
+def test_l2r_with_wide_threshold_equals_l2(small_prob):
+    prob = small_prob
+    p = O.Params(robust="l2")
+    alpha, beta = O.term_weights(prob, p, 1.0, 1.0)
+    ev = O.evaluate(prob, O.identity(prob.n_nodes), 1e3, 1e3, alpha, beta, robust="l2r")
+    X1, _, _ = O.mm_update(prob, ev, 1e3, 1e3, alpha, beta, robust="l2r")
+    X2, _, _ = O.mm_update(prob, ev, 1e3, 1e3, alpha, beta, robust="l2")
+    assert np.array_equal(X1, X2)
+
+
+def test_fixed_nu_values_are_the_dynamic_extremes(small_pair):
+    """Welsch-fmax/fmin/fmed: the parameters that the dynamic run (Alg. 2's
+    stage loop) actually visits bound the fixed values, and a fixed run keeps
+    them for one stage."""
+    prob = O.from_pair(synth.rigid_pair(small_pair, 81, angle_deg=20.0, shift=0.1))
+    dyn = O.solve(prob, O.Params(aa_m=5, imax=3))
+    seen = sorted({(e["nu_a"], e["nu_r"]) for e in dyn["log"]}, reverse=True)
+    assert len(seen) >= 3
+    ev0 = O.evaluate(prob, O.identity(prob.n_nodes), 1.0, 1.0, 0.0, 0.0)
+    a0, amin, r0 = O.initial_nu(prob, O.Params(), ev0.d2)
+    assert O.fixed_nu(a0, amin, r0, "max") == seen[0]
+    assert O.fixed_nu(a0, amin, r0, "min") == seen[-1]
+    med = O.fixed_nu(a0, amin, r0, "med")
+    assert med == (0.5 * (seen[0][0] + seen[-1][0]), 0.5 * (seen[0][1] + seen[-1][1]))
+    for mode, want in (("max", seen[0]), ("min", seen[-1]), ("med", med)):
+        res = O.solve(prob, O.Params(aa_m=5, imax=4, nu_mode=mode))
+        assert res["stages"] == 1
+        assert {(e["nu_a"], e["nu_r"]) for e in res["log"]} == {want}
+
+
+@pytest.mark.parametrize("robust,nu_mode", [("l2", "dynamic"), ("l2r", "dynamic"),
+                                            ("welsch", "max"), ("welsch", "min"),
+                                            ("welsch", "med")])
+def test_variant_solvers_never_increase_energy(small_pair, robust, nu_mode):
+    prob = O.from_pair(small_pair)
+    res = O.solve(prob, O.Params(aa_m=5, max_total_iters=10, robust=robust, nu_mode=nu_mode))
+    for e in res["log"]:
+        assert e["E_after"] <= e["E_before"] * (1 + 1e-12) + 1e-300
+    if robust == "l2":
+        assert res["stages"] == 1
 
 
 # --------------------------------------------------------------------------
