@@ -361,7 +361,8 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     __shared__ T smom[64][10];
     __shared__ int spos[64][kMaxK];           // column position of each influence of a staged point
     __shared__ T swgt[64][kMaxK];
-    const int j = blockIdx.x;
+    // neighbouring nodes share most of their points: keep them on one XCD
+    const int j = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     const int p = a.node_pair[j];
     const PairDyn dy = a.dyn[p];
@@ -873,7 +874,8 @@ __global__ void __launch_bounds__(kPointTile) k_grad_points(GradArgs<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_grad_nodes(GradArgs<T> a) {
     using V = typename V4Of<T>::type;
-    const int j = blockIdx.x;
+    // neighbouring nodes share most of their points: keep them on one XCD
+    const int j = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     const int p = a.node_pair[j];
     const PairDyn dy = a.dyn[p];
