@@ -111,8 +111,10 @@ typedef struct {
     int64_t n_nodes;
     const int32_t* node_src_idx;  /* [n_nodes] distinct indices into V (nodes lie on V) */
     int32_t k;                    /* influences per point, 1 <= k <= 8, k <= n_nodes */
-    const int32_t* infl_idx;      /* [n_src][k] node ids (0 <= id < n_nodes, distinct per row) */
-    const void* infl_w;           /* [n_src][k] weights of Eq. (3); each row sums to 1 */
+    const int32_t* infl_idx;      /* [n_src][k] node ids (0 <= id < n_nodes, distinct per row);
+                                   * -1 marks an unused slot (a point with fewer than k
+                                   * influencing nodes); every point needs one used slot */
+    const void* infl_w;           /* [n_src][k] weights of Eq. (3), 0 in unused slots; each row sums to 1 */
     int64_t n_edges;
     const int32_t* edges;         /* [n_edges][2] undirected node edges, i != j, no duplicates */
     double mean_edge_len;         /* average source edge length l (Sec. 3.3.3), > 0 */
@@ -193,11 +195,12 @@ amm_status amm_set_stream(amm_handle* h, void* hip_stream);
 /* ---------------------------------------------------------------- problem */
 
 /* Host-only validation of a problem given by HOST pointers (on_device = 0);
- * needs no GPU.  Checks sizes and index ranges (AMM_ERR_INVALID_ARG),
- * finiteness (AMM_ERR_NONFINITE), and the structure (AMM_ERR_GRAPH): distinct
- * node indices, distinct influences per point with non-negative weights that
- * sum to 1 within 1e-5, and a connected node graph without duplicate or self
- * edges. */
+ * needs no GPU.  Checks sizes and index ranges, and that unused influence
+ * slots (-1) carry weight 0 (AMM_ERR_INVALID_ARG), finiteness
+ * (AMM_ERR_NONFINITE), and the structure (AMM_ERR_GRAPH): distinct node
+ * indices, at least one and distinct influences per point with non-negative
+ * weights that sum to 1 within 1e-5, and a connected node graph without
+ * duplicate or self edges. */
 amm_status amm_check_problem(const amm_problem* p);
 
 /* Device bytes that amm_set_problems needs for these problems (a static
@@ -264,6 +267,55 @@ amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, i
  * counting is off. */
 amm_status amm_count_nn_work(amm_handle* h, int32_t enable);
 amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals);
+
+/* ---------------------------------------------------------------- graph construction */
+
+/* Deformation graph of Sec. 3.1 (Alg. 1) built on the device, with
+ * Euclidean distance in place of the geodesic one: the source points are
+ * ordered along their principal axis (largest eigenvalue of the covariance;
+ * the axis component of largest magnitude taken positive, equal projections
+ * in index order); in that order a point becomes a node when no earlier node
+ * lies strictly within R of it; each point is influenced by the nodes
+ * strictly within R, weighted by Eq. (3); nodes that influence a common
+ * point are joined by an edge.  Node ids follow the order of insertion.
+ * Each point keeps its k nearest influencing nodes (ties to the lower node
+ * id) with the weights renormalized over them, so that the result feeds
+ * amm_problem directly; unused slots are -1 with weight 0, and edges come
+ * from kept slots.  The mean edge length l (Sec. 3.3.3) is that of the
+ * symmetrized, deduplicated 6-nearest-neighbour graph of the source points. */
+typedef struct {
+    amm_dtype dtype;          /* type of src_xyz and of the weights amm_graph_copy writes */
+    const void* src_xyz;      /* DEVICE pointer, [n_src][3] */
+    int64_t n_src;            /* >= 2 */
+    double radius;            /* R; <= 0 selects radius_factor * l */
+    double radius_factor;     /* used when radius <= 0; <= 0 selects 5 (Sec. 4.1) */
+    int32_t k;                /* influence slots per point, 1 <= k <= 8 */
+} amm_graph_in;
+
+typedef struct {
+    int64_t n_nodes, n_edges;
+    double radius;            /* R used */
+    double mean_edge_len;     /* l */
+    int64_t n_capped;         /* points with more than k nodes within R */
+    int32_t max_influences;   /* most nodes within R of one point */
+    int32_t rounds;           /* parallel rounds the node selection took */
+} amm_graph_info;
+
+/* Builds the graph of the given points on the handle's device and stream
+ * and keeps it in the handle (replacing an earlier one) until
+ * amm_graph_copy fetches it.  The node selection equals the sequential
+ * greedy pass exactly: a point is decided as soon as every earlier point
+ * within R is, in rounds that run until none is left.  Needs no problem set.
+ * Errors: AMM_ERR_INVALID_ARG (sizes, k, a non-positive R),
+ * AMM_ERR_NONFINITE, AMM_ERR_OOM, AMM_ERR_HIP. */
+amm_status amm_build_graph(amm_handle* h, const amm_graph_in* in, amm_graph_info* info);
+
+/* Copies the last built graph into caller-owned DEVICE buffers (any may be
+ * NULL): node_src_idx [n_nodes], infl_idx [n_src][k], infl_w [n_src][k] in the
+ * build's dtype, edges [n_edges][2] (i < j, sorted).  AMM_ERR_STATE if no
+ * graph was built. */
+amm_status amm_graph_copy(amm_handle* h, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w,
+                          int32_t* edges);
 
 /* ---------------------------------------------------------------- single step */
 

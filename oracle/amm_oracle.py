@@ -67,6 +67,15 @@ class Problem:
         self.node_idx = np.asarray(self.node_idx, np.int64)
         self.infl_idx = np.asarray(self.infl_idx, np.int64)
         self.infl_w = np.asarray(self.infl_w, np.float64)
+        # A point with fewer influencing nodes than slots marks the rest -1
+        # (weight 0).  Such a slot is absent from Eq. (2)'s sum; it is
+        # pointed at the row's first node so that every gather stays valid,
+        # and its zero weight removes it from every sum and matrix entry.
+        pad = self.infl_idx < 0
+        if pad.any():
+            assert np.all(self.infl_w[pad] == 0.0)
+            first = self.infl_idx[np.arange(self.infl_idx.shape[0]), np.argmax(~pad, 1)]
+            self.infl_idx = np.where(pad, first[:, None], self.infl_idx)
         self.edges = np.asarray(self.edges, np.int64).reshape(-1, 2)
         self.nodes = self.src[self.node_idx]
         self.dir_edges = directed_edges(self.edges)

@@ -69,6 +69,20 @@ class amm_iter_record(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class amm_graph_in(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("src_xyz", C.c_void_p), ("n_src", C.c_int64), ("radius", C.c_double),
+                ("radius_factor", C.c_double), ("k", C.c_int32)]
+
+
+class amm_graph_info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_edges", C.c_int64), ("radius", C.c_double),
+                ("mean_edge_len", C.c_double), ("n_capped", C.c_int64), ("max_influences", C.c_int32),
+                ("rounds", C.c_int32)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
 class amm_step_in(C.Structure):
     _fields_ = [("X", C.c_void_p), ("nu_a", C.c_double), ("nu_r", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("precision", C.c_int32),
@@ -106,6 +120,8 @@ def lib():
             "amm_set_problem": ([vp, C.POINTER(amm_problem)], C.c_int),
             "amm_set_leaf_size": ([vp, i32], C.c_int),
             "amm_count_nn_work": ([vp, i32], C.c_int),
+            "amm_build_graph": ([vp, C.POINTER(amm_graph_in), C.POINTER(amm_graph_info)], C.c_int),
+            "amm_graph_copy": ([vp, vp, vp, vp, vp], C.c_int),
             "amm_nn_work": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
             "amm_autotune": ([vp, C.POINTER(amm_problem), i32, C.POINTER(i32), i32, C.POINTER(i32),
                               C.POINTER(dbl)], C.c_int),
@@ -135,6 +151,7 @@ def lib():
 EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
             "amm_set_leaf_size", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
+            "amm_build_graph", "amm_graph_copy",
             "amm_solve", "amm_step", "amm_k_nnzb", "amm_iter_log", "amm_energy", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
@@ -248,6 +265,35 @@ def amm_set_workspace(handle, tensor_or_none) -> None:
 
 def amm_set_leaf_size(handle, leaf: int) -> None:
     _check(lib().amm_set_leaf_size(handle, int(leaf)), handle)
+
+
+def amm_build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0) -> dict:
+    """Alg. 1 on the device for the source points `src` (a cuda tensor
+    [N][3], float32 or float64); returns the build's info.  Fetch the graph
+    with amm_graph_copy."""
+    gin = amm_graph_in(dtype=_dtype_code(src), src_xyz=_ptr(src), n_src=src.shape[0], radius=radius,
+                       radius_factor=radius_factor, k=k)
+    info = amm_graph_info()
+    _check(lib().amm_build_graph(handle, C.byref(gin), C.byref(info)), handle)
+    return info.as_dict()
+
+
+def amm_graph_copy(handle, node_src_idx=None, infl_idx=None, infl_w=None, edges=None) -> None:
+    _check(lib().amm_graph_copy(handle, _ptr(node_src_idx), _ptr(infl_idx), _ptr(infl_w), _ptr(edges)), handle)
+
+
+def build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0):
+    """amm_build_graph + amm_graph_copy into new tensors on src's device:
+    (info, node_src_idx [n], infl_idx [N][k], infl_w [N][k], edges [E][2])."""
+    import torch
+    info = amm_build_graph(handle, src, k, radius, radius_factor)
+    dev = src.device
+    node = torch.empty(info["n_nodes"], dtype=torch.int32, device=dev)
+    idx = torch.empty(src.shape[0], k, dtype=torch.int32, device=dev)
+    w = torch.empty(src.shape[0], k, dtype=src.dtype, device=dev)
+    edges = torch.empty(max(info["n_edges"], 1), 2, dtype=torch.int32, device=dev)[:info["n_edges"]]
+    amm_graph_copy(handle, node, idx, w, edges)
+    return info, node, idx, w, edges
 
 
 def amm_count_nn_work(handle, enable: bool) -> None:

@@ -321,6 +321,7 @@ struct amm_handle {
     int leaf = 8;                    // targets per leaf of the closest-point tree (next upload)
     long long* nn_work = nullptr;    // [n_pt_tiles][3] search counters while counting is on
     int nn_work_tiles = 0;
+    GraphBuild* graph = nullptr;     // last amm_build_graph result
     EventTimer timer;
     std::vector<amm_iter_record> iter_log;
 };
@@ -1376,6 +1377,7 @@ void amm_destroy(amm_handle* h) {
     (void)hipStreamSynchronize(h->stream);
     if (h->prog) (void)hipHostFree(h->prog);
     if (h->nn_work) (void)hipFree(h->nn_work);
+    if (h->graph) graph_release(h->graph);
     if (h->h_scratch) (void)hipHostFree(h->h_scratch);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
     if (h->ws_own) (void)hipFree(h->ws_own);
@@ -1616,6 +1618,29 @@ amm_status amm_step(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     if (in->precision == AMM_FP64_PLAIN) return step_impl<double>(h, in, out);
     if (in->precision == AMM_FP32_REFINE) return step_impl<float>(h, in, out);
     return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");
+}
+
+amm_status amm_build_graph(amm_handle* h, const amm_graph_in* in, amm_graph_info* info) {
+    if (!h || !in) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    HIPC(hipSetDevice(h->device));
+    GraphBuild* g = nullptr;
+    std::string err;
+    const amm_status st = graph_build(h->stream, *in, info, &g, err);
+    if (st != AMM_OK) return fail(h, st, err);
+    if (h->graph) graph_release(h->graph);
+    h->graph = g;
+    return AMM_OK;
+}
+
+amm_status amm_graph_copy(amm_handle* h, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w, int32_t* edges) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    if (!h->graph) return fail(h, AMM_ERR_STATE, "amm_graph_copy before amm_build_graph");
+    HIPC(hipSetDevice(h->device));
+    std::string err;
+    const amm_status st = graph_copy(h->graph, h->stream, node_src_idx, infl_idx, infl_w, edges, err);
+    if (st != AMM_OK) return fail(h, st, err);
+    HIPC(hipStreamSynchronize(h->stream));
+    return AMM_OK;
 }
 
 amm_status amm_count_nn_work(amm_handle* h, int32_t enable) {

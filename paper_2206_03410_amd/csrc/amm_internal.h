@@ -92,6 +92,7 @@ struct Layout {
     std::vector<int32_t> iidx;       // [k][Ntot] internal node ids
     std::vector<double> iw;          // [k][Ntot]
     std::vector<double> iw_pt;       // [Ntot][kMaxK] the same weights point-major, zero padded
+    std::vector<uint8_t> ipad;       // [k][Ntot] 1 = unused slot (host only)
     std::vector<double> nodes4;      // [ntot][4]
     std::vector<int32_t> node_user;  // internal node -> user node (concatenated)
     std::vector<int32_t> node_internal;
@@ -121,7 +122,17 @@ constexpr int kPointTile = 256;
 constexpr int kNodeTile = 16;        // solver rows per tile (4 threads per row: one wave)
 constexpr int kEdgeTile = 256;
 constexpr int kMaxCols = 192;        // K blocks per row supported by the assembly
-static_assert(kMaxCols <= 256, "column positions are stored in one byte");
+static_assert(kMaxCols < 255, "column positions are stored in one byte");
+constexpr unsigned kPosUnused = 255;  // column byte of an unused influence slot
+
+// Device-built deformation graph (Alg. 1), kept by a handle between
+// amm_build_graph and amm_graph_copy.  stream is a hipStream_t.
+struct GraphBuild;
+void graph_release(GraphBuild* g);
+amm_status graph_build(void* stream, const amm_graph_in& in, amm_graph_info* info, GraphBuild** out,
+                       std::string& err);
+amm_status graph_copy(const GraphBuild* g, void* stream, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w,
+                      int32_t* edges, std::string& err);
 constexpr int kMaxK = 8;
 constexpr int kCoarseMaxAgg = 32;    // aggregates per pair (coarse order <= 128)
 constexpr int kAggMinShift = 6;      // at least 64 nodes (4 node tiles) per aggregate

@@ -357,7 +357,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     using V = typename V4Of<T>::type;
     __shared__ int scol[kMaxCols];            // the row's column node ids (sorted)
-    __shared__ T sacc[kMaxCols][10];          // moment sums per column block
+    __shared__ T sacc[kMaxCols + 1][10];      // moment sums per column block (+ a sink row)
     __shared__ T smom[64][10];
     __shared__ int spos[64][kMaxK];           // column position of each influence of a staged point
     __shared__ T swgt[64][kMaxK];
@@ -428,7 +428,9 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
             racc[11] += c * q.z;
 #pragma unroll
             for (int b = 0; b < kMaxK; ++b) {
-                spos[lane][b] = (int)((pos >> (8 * b)) & 255u);
+                // an unused slot (weight 0) adds into the sink row, never read
+                const unsigned cb = (unsigned)(pos >> (8 * b)) & 255u;
+                spos[lane][b] = cb == kPosUnused ? kMaxCols : (int)cb;
                 swgt[lane][b] = wv[b];
             }
         }

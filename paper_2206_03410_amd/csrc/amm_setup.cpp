@@ -104,8 +104,17 @@ amm_status validate_pair(const HostPair& hp, std::string& err) {
     }
     for (int64_t i = 0; i < hp.N; ++i) {
         double sum = 0.0;
+        int real = 0;
         for (int a = 0; a < hp.k; ++a) {
             int32_t j = hp.infl_idx[i * hp.k + a];
+            double w = hp.infl_w[i * hp.k + a];
+            if (j == -1) {   // unused slot
+                if (w != 0.0) {
+                    err = fmt("unused influence slot (index -1) of point %lld has a nonzero weight", i);
+                    return AMM_ERR_INVALID_ARG;
+                }
+                continue;
+            }
             if (j < 0 || j >= hp.n) {
                 err = fmt("infl_idx of point %lld out of range (%lld)", i, j);
                 return AMM_ERR_INVALID_ARG;
@@ -115,12 +124,16 @@ amm_status validate_pair(const HostPair& hp, std::string& err) {
                     err = fmt("point %lld lists node %lld twice", i, j);
                     return AMM_ERR_GRAPH;
                 }
-            double w = hp.infl_w[i * hp.k + a];
             if (w < 0) {
                 err = fmt("negative influence weight at point %lld", i);
                 return AMM_ERR_GRAPH;
             }
             sum += w;
+            ++real;
+        }
+        if (real == 0) {
+            err = fmt("point %lld has no influencing node", i);
+            return AMM_ERR_GRAPH;
         }
         if (std::fabs(sum - 1.0) > 1e-5) {
             err = fmt("influence weights of point %lld do not sum to 1", i);
@@ -192,6 +205,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.src_internal.resize(L.Ntot);
     L.iidx.resize((size_t)k * L.Ntot);
     L.iw.resize((size_t)k * L.Ntot);
+    L.ipad.assign((size_t)k * L.Ntot, 0);
     L.iw_pt.assign((size_t)kMaxK * L.Ntot, 0.0);
     L.nodes4.assign(4 * L.ntot, 0.0);
     L.node_user.resize(L.ntot);
@@ -255,10 +269,19 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
             for (int c = 0; c < 3; ++c) L.src4[4 * (so + q) + c] = hp.src[3 * u + c];
             L.src_user[so + q] = (int32_t)(so + u);
             L.src_internal[so + u] = (int32_t)(so + q);
+            // an unused slot points at the point's first influencing node with
+            // weight 0, so the kernels read valid data and add nothing; it takes
+            // no part in K's pattern or the node point lists
+            int a0 = 0;
+            while (hp.infl_idx[u * k + a0] == -1) ++a0;
             for (int a = 0; a < k; ++a) {
-                L.iidx[(size_t)a * L.Ntot + so + q] = (int32_t)(no + n_inv[hp.infl_idx[u * k + a]]);
-                L.iw[(size_t)a * L.Ntot + so + q] = hp.infl_w[u * k + a];
-                L.iw_pt[(size_t)(so + q) * kMaxK + a] = hp.infl_w[u * k + a];
+                const bool pad = hp.infl_idx[u * k + a] == -1;
+                const int32_t j = hp.infl_idx[u * k + (pad ? a0 : a)];
+                const double w = pad ? 0.0 : hp.infl_w[u * k + a];
+                L.iidx[(size_t)a * L.Ntot + so + q] = (int32_t)(no + n_inv[j]);
+                L.ipad[(size_t)a * L.Ntot + so + q] = pad ? 1 : 0;
+                L.iw[(size_t)a * L.Ntot + so + q] = w;
+                L.iw_pt[(size_t)(so + q) * kMaxK + a] = w;
             }
         }
         for (int64_t q = 0; q < hp.n; ++q) {
@@ -319,9 +342,10 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         for (int64_t q = 0; q < hp.n; ++q) cols[q].push_back((int32_t)(no + q));
         for (int64_t q = 0; q < hp.N; ++q)
             for (int a = 0; a < k; ++a) {
+                if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
                 int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
                 for (int b = 0; b < k; ++b)
-                    cols[ja].push_back(L.iidx[(size_t)b * L.Ntot + so + q]);
+                    if (!L.ipad[(size_t)b * L.Ntot + so + q]) cols[ja].push_back(L.iidx[(size_t)b * L.Ntot + so + q]);
             }
         for (int64_t q = 0; q < hp.n; ++q)
             for (int32_t b : nb[q]) cols[q].push_back((int32_t)(no + b));
@@ -354,6 +378,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         std::vector<std::vector<int32_t>> pj(hp.n);
         for (int64_t q = 0; q < hp.N; ++q)
             for (int a = 0; a < k; ++a) {
+                if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
                 int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
                 pj[ja].push_back((int32_t)(((so + q) << 3) | a));
             }
@@ -365,8 +390,11 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
                 const int64_t i = ent >> 3;
                 uint64_t pos = 0;
                 for (int b = 0; b < k; ++b) {
-                    const int32_t nid = L.iidx[(size_t)b * L.Ntot + i];
-                    const uint64_t at = (uint64_t)(std::lower_bound(c.begin(), c.end(), nid) - c.begin());
+                    uint64_t at = kPosUnused;
+                    if (!L.ipad[(size_t)b * L.Ntot + i]) {
+                        const int32_t nid = L.iidx[(size_t)b * L.Ntot + i];
+                        at = (uint64_t)(std::lower_bound(c.begin(), c.end(), nid) - c.begin());
+                    }
                     pos |= at << (8 * b);
                 }
                 L.pj_pos.push_back(pos);

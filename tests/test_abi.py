@@ -33,7 +33,7 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = [getattr(amm, n) for n in ("amm_problem", "amm_params", "amm_stats", "amm_iter_record",
-                                         "amm_step_in", "amm_step_out")]
+                                         "amm_step_in", "amm_step_out", "amm_graph_in", "amm_graph_info")]
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "amm.h"', "int main(void) {"]
     for st in structs:
         lines.append(f'printf("{st.__name__} size %zu\\n", sizeof({st.__name__}));')
@@ -142,6 +142,31 @@ def test_check_index_ranges(small_pair):
         a["mean_edge_len"] = 0.0
     for fn in (infl_oob, infl_neg, node_oob, edge_oob, lbar):
         assert _mutated(small_pair, fn) == amm.AMM_ERR_INVALID_ARG, fn.__name__
+
+
+def test_check_unused_influence_slots(small_pair):
+    """-1 marks an unused slot: accepted with weight 0, rejected with a
+    nonzero weight or below -1, and a point needs one used slot."""
+    def pad_ok(a):
+        w = a["infl_w"][2]
+        a["infl_idx"][2, 3] = -1
+        w[3] = 0.0
+        w /= w.sum()
+
+    def pad_weight(a):
+        a["infl_idx"][2, 3] = -1
+
+    def minus_two(a):
+        a["infl_idx"][2, 3] = -2
+        a["infl_w"][2, 3] = 0.0
+
+    def all_unused(a):
+        a["infl_idx"][2, :] = -1
+        a["infl_w"][2, :] = 0.0
+    assert _mutated(small_pair, pad_ok) == amm.AMM_OK
+    assert _mutated(small_pair, pad_weight) == amm.AMM_ERR_INVALID_ARG
+    assert _mutated(small_pair, minus_two) == amm.AMM_ERR_INVALID_ARG
+    assert _mutated(small_pair, all_unused) == amm.AMM_ERR_GRAPH
 
 
 def test_check_graph_structure(small_pair):

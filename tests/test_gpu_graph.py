@@ -1,0 +1,146 @@
+"""Parity of the device graph builder (Alg. 1 with Euclidean distance)
+with the graph oracle, and a registration run on a graph it built."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import amm_oracle as O
+from oracle import graph_oracle as G
+from paper_2206_03410_amd import amm, synth
+from tests.helpers import Session
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _announce(name):
+    print(f"[gpu-test] {name}", file=sys.stderr, flush=True)
+
+
+def _handle():
+    return amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
+
+
+def _axis_margin(V):
+    """Smallest gap between consecutive projections, relative to their
+    spread: the order is a decision both sides take in float64."""
+    m, a = G.principal_axis(V)
+    t = np.sort((V - m) @ a)
+    return np.diff(t).min() / (t[-1] - t[0])
+
+
+def _check_against_oracle(V, k, got, radius=None, w_tol=1e-12):
+    info, node, idx, w, edges = got
+    lbar = G.mean_edge_length(V)
+    R = radius if radius else 5.0 * lbar
+    ref = G.build_graph(V, R, k)
+    assert info["mean_edge_len"] == pytest.approx(lbar, rel=1e-12)
+    assert info["radius"] == pytest.approx(R, rel=1e-12)
+    assert np.array_equal(node.cpu().numpy(), ref["node_idx"])
+    assert np.array_equal(idx.cpu().numpy(), ref["infl_idx"])
+    assert np.abs(w.cpu().numpy().astype(np.float64) - ref["infl_w"]).max() <= w_tol
+    assert np.array_equal(edges.cpu().numpy(), ref["edges"])
+    assert info["n_capped"] == ref["n_capped"]
+    assert info["max_influences"] == ref["max_influences"]
+    return ref
+
+
+@pytest.mark.parametrize("case", ["torus700_k4", "torus2k_k3", "sh50k_k6"])
+def test_graph_matches_oracle(case):
+    """Nodes, influence indices and edges bit-exact, weights within 1e-12,
+    mean edge length and R = 5 l within 1e-12 relative."""
+    _announce(f"test_graph_matches_oracle {case}")
+    if case == "torus700_k4":
+        V, k = synth.torus_pair(1000, n_src=700, n_tgt=10, n_nodes=20, k=4, e=6).src, 4
+    elif case == "torus2k_k3":
+        V, k = synth.make_workload("torus2k").src, 3
+    else:
+        V, k = synth.make_workload("sh50k").src, 6
+    assert _axis_margin(V) > 1e-12
+    h = _handle()
+    try:
+        got = amm.build_graph(h, torch.tensor(V, device="cuda:0"), k)
+        torch.cuda.synchronize()
+    finally:
+        amm.amm_destroy(h)
+    print(f"{case}: {got[0]}", file=sys.stderr)
+    ref = _check_against_oracle(V, k, got)
+    if case == "torus2k_k3":
+        assert ref["n_capped"] > 0          # the k cap is exercised
+
+
+def test_graph_float32_input_and_explicit_radius():
+    """float32 points (the oracle sees the same rounded values) and a given
+    R: same integers, float32 weights within float32 rounding."""
+    _announce("test_graph_float32_input_and_explicit_radius")
+    V = synth.make_workload("torus2k").src.astype(np.float32)
+    R = 0.05
+    h = _handle()
+    try:
+        got = amm.build_graph(h, torch.tensor(V, device="cuda:0"), 4, radius=R)
+        torch.cuda.synchronize()
+    finally:
+        amm.amm_destroy(h)
+    _check_against_oracle(V.astype(np.float64), 4, got, radius=R, w_tol=1e-6)
+
+
+def test_graph_arguments_are_validated():
+    _announce("test_graph_arguments_are_validated")
+    V = torch.tensor(synth.make_workload("torus2k").src[:100], device="cuda:0")
+    h = _handle()
+    try:
+        for kw in (dict(k=0), dict(k=9)):
+            with pytest.raises(amm.AmmError) as ei:
+                amm.amm_build_graph(h, V, **kw)
+            assert ei.value.status == amm.AMM_ERR_INVALID_ARG
+        with pytest.raises(amm.AmmError) as ei:
+            amm.amm_build_graph(h, V[:1], 4)
+        assert ei.value.status == amm.AMM_ERR_INVALID_ARG
+        bad = V.clone()
+        bad[5, 1] = float("nan")
+        with pytest.raises(amm.AmmError) as ei:
+            amm.amm_build_graph(h, bad, 4)
+        assert ei.value.status == amm.AMM_ERR_NONFINITE
+        with pytest.raises(amm.AmmError) as ei:
+            amm.amm_graph_copy(h)
+        assert ei.value.status == amm.AMM_ERR_STATE
+    finally:
+        amm.amm_destroy(h)
+
+
+def test_registration_on_a_built_graph():
+    """The graph built on the device, with unused influence slots, drives
+    Alg. 2 (float64, 15 MM iterations, decisions replayed) to the oracle's
+    trajectory on the same graph."""
+    _announce("test_registration_on_a_built_graph")
+    import dataclasses
+    base = synth.make_workload("torus2k")
+    k = 4
+    h = _handle()
+    try:
+        info, node, idx, w, edges = amm.build_graph(h, torch.tensor(base.src, device="cuda:0"), k)
+        torch.cuda.synchronize()
+    finally:
+        amm.amm_destroy(h)
+    pair = dataclasses.replace(base, node_idx=node.cpu().numpy(), infl_idx=idx.cpu().numpy(),
+                               infl_w=w.cpu().numpy(), edges=edges.cpu().numpy(),
+                               mean_edge_len=info["mean_edge_len"])
+    assert (pair.infl_idx < 0).any()        # unused slots are exercised
+    prob = O.from_pair(pair)
+    p = O.Params(aa_m=5, max_total_iters=15)
+    res = O.solve(prob, p)
+    fa = [e["accepted"] if e["aa_used"] else None for e in res["log"]]
+    fs = [1 if (b is None or b["stage"] != a["stage"]) else 0
+          for a, b in zip(res["log"], res["log"][1:] + [None])]
+    with Session(pair, torch.float64) as s:
+        v = torch.empty(prob.n_src, 3, dtype=torch.float64, device="cuda:0")
+        prm = amm.amm_params_default(aa_m=5, max_total_iters=15, precision=amm.AMM_FP64_PLAIN)
+        st = amm.amm_solve(s.h, prm, None, v, force_accept=fa, force_stage_end=fs)[0]
+        torch.cuda.synchronize()
+        v = v.cpu().numpy()
+    assert st["iters"] == res["total"]
+    assert st["energy"] == pytest.approx(res["E"], rel=1e-5)
+    assert math.sqrt(((v - res["vhat"]) ** 2).sum(1).mean()) < 1e-5

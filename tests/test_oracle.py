@@ -179,6 +179,38 @@ def test_nearest_ties_go_to_lowest_index():
 # energy special cases
 # --------------------------------------------------------------------------
 
+def test_unused_influence_slots_equal_fewer_slots(small_pair):
+    """A slot marked -1 (weight 0) is absent: the problem equals the one
+    without that slot, through the warp, the energy and the MM step."""
+    import dataclasses
+    k = small_pair.infl_idx.shape[1]
+    w3 = small_pair.infl_w[:, :k - 1] / small_pair.infl_w[:, :k - 1].sum(1, keepdims=True)
+    fewer = dataclasses.replace(small_pair, infl_idx=small_pair.infl_idx[:, :k - 1].copy(), infl_w=w3)
+    idx = small_pair.infl_idx.copy()
+    w = small_pair.infl_w.copy()
+    idx[::2, k - 1] = -1                 # every other point loses its last slot
+    w[::2, :k - 1] = w3[::2]
+    w[::2, k - 1] = 0.0
+    mixed = dataclasses.replace(small_pair, infl_idx=idx, infl_w=w)
+    # the reference: points with a padded slot take their k-1 slots, the others all k
+    pa, pb = O.from_pair(mixed), O.from_pair(fewer)
+    X = synth.perturbed_transforms(pa.n_nodes, 95, 0.02, 0.003)
+    va, vb, vf = O.warp(pa, X), O.warp(pb, X), O.warp(O.from_pair(small_pair), X)
+    assert np.abs(va[::2] - vb[::2]).max() < 1e-15
+    assert np.array_equal(va[1::2], vf[1::2])
+    nu_a, nu_r, alpha, beta = _stage_scalars(pa)
+    ev = O.evaluate(pa, X, nu_a, nu_r, alpha, beta)
+    # the rows of F (Sec. 3.3.2) of padded points hold their k-1 real slots only
+    F = O.matrices(pa, ev, nu_a, nu_r)[0]
+    Fd = F.toarray()
+    for i in range(0, pa.n_src, 2):
+        for s in range(k - 1):
+            j = small_pair.infl_idx[i, s]
+            d = np.append(pa.src[i] - pa.nodes[j], 1.0)
+            assert np.allclose(Fd[i, 4 * j:4 * j + 4], w3[i, s] * d, rtol=0, atol=1e-15)
+    assert np.abs(Fd[::2].sum(1) - (np.einsum("nk,nkc->n", w3[::2], pa.src[::2, None, :] - pa.nodes[small_pair.infl_idx[::2, :k - 1]]) + 1)).max() < 1e-12
+
+
 def test_identical_pair_zero_energy_and_fixed_point(small_pair):
     pair = synth.identical_pair(small_pair)
     prob = O.from_pair(pair)
