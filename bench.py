@@ -309,6 +309,78 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
                           "flops: 8 per distance evaluation, 12 per box test"}
 
 
+def graph_build_report(amm, torch, h, pair, k, with_cpu):
+    """Device construction of the deformation graph (Alg. 1, Euclidean R =
+    5 l) on the workload's source points: wall time of amm_build_graph (it
+    synchronizes internally), median of 3 after one untimed build; with the
+    CPU leg, the oracle's sequential pass on the same points."""
+    src = torch.tensor(pair.src, device="cuda:0")
+    amm.amm_build_graph(h, src, k)
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = amm.amm_build_graph(h, src, k)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    out = {"gpu_ms": 1e3 * float(np.median(ts)), "k": k, **info}
+    if with_cpu:
+        from oracle import graph_oracle as G
+        t = time.perf_counter()
+        lbar = G.mean_edge_length(pair.src)
+        g = G.build_graph(pair.src, 5.0 * lbar, k)
+        out["cpu_oracle_s"] = time.perf_counter() - t
+        out["cpu_oracle_nodes_equal"] = len(g["node_idx"]) == info["n_nodes"]
+    return out
+
+
+def sequence_run(amm, torch, n_frames):
+    """Template tracking (the frame i -> i + 2 sequences of Sec. 4): one
+    50,000-point template registered to target frames 2, 4, ..., each solve
+    run to Alg. 2's own termination in FP32 + refinement; the targets of the
+    set-up pair are swapped between frames (amm_set_targets).  Warm: each
+    frame starts from the previous frame's transforms; cold: from X = I."""
+    from paper_2206_03410_amd import synth
+    t0 = time.time()
+    seq = synth.sh_sequence(6000, 50000, n_frames=n_frames, n_nodes=1000, k=4, e=8)
+    log(f"[bench] generated the tracking sequence ({n_frames} frames) in {time.time() - t0:.1f}s")
+    tpl = seq.template
+    out = {"workload": f"{tpl.n_src} template points, {tpl.n_nodes} nodes, k=4, target frames "
+                       f"{seq.frame_ids}, FP32 + refinement, Anderson m=5, Alg. 2 termination per frame"}
+    h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        amm.amm_set_problems(h, [gpu_problem(amm, torch, tpl)])
+        for mode in ("warm", "cold", "warm"):
+            X = torch.empty(tpl.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+            v = torch.empty(tpl.n_src, 3, dtype=torch.float32, device="cuda:0")
+            rows = []
+            for f, tgt in enumerate(seq.frames):
+                amm.amm_set_targets(h, 0, torch.tensor(tgt, device="cuda:0"))
+                prm = amm.amm_params_default(aa_m=5, precision=amm.AMM_FP32_REFINE,
+                                             init_identity=1 if (mode == "cold" or f == 0) else 0)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st = amm.amm_solve(h, prm, X, v)[0]
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                rm = math.sqrt(((v.cpu().numpy().astype(np.float64) - seq.gts[f]) ** 2).sum(1).mean())
+                rows.append({"iters": st["iters"], "ms": 1e3 * dt, "rmse_gt": rm, "converged": st["converged"]})
+            out[mode] = {"frames_per_s": len(rows) / (sum(r["ms"] for r in rows) * 1e-3),
+                         "total_iters": sum(r["iters"] for r in rows),
+                         "ms_per_frame": [round(r["ms"], 2) for r in rows],
+                         "iters_per_frame": [r["iters"] for r in rows],
+                         "rmse_gt": [r["rmse_gt"] for r in rows],
+                         "all_converged": all(r["converged"] == 1 for r in rows)}
+    finally:
+        amm.amm_destroy(h)
+    w, c = out["warm"], out["cold"]
+    out["equal_error"] = all(abs(a - b) <= max(1e-4, 0.01 * b) for a, b in zip(w["rmse_gt"], c["rmse_gt"]))
+    out["speedup_warm"] = w["frames_per_s"] / c["frames_per_s"]
+    log(f"[bench] tracking: warm {w['frames_per_s']:.1f} frames/s ({w['total_iters']} MM iterations), "
+        f"cold {c['frames_per_s']:.1f} frames/s ({c['total_iters']}), equal error {out['equal_error']}")
+    return out
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling the HBM traffic
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run: each of the 5
@@ -331,7 +403,9 @@ def main():
     ap.add_argument("--workload", default="sh200k")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batched", type=int, default=0, help="also run this many batched pairs")
+    ap.add_argument("--batched", type=int, default=64, help="pairs of the batched run (0 = skip)")
+    ap.add_argument("--sequence", type=int, default=8,
+                    help="target frames of the tracking run (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain-copy kernel that scales the traffic counters")
     args = ap.parse_args()
@@ -397,6 +471,9 @@ def main():
             f"{nn['candidate_traffic_GBps']:.0f} GB/s")
         copy_gbs = copy_bandwidth(torch)
         log(f"[bench] plain device copy {copy_gbs:.0f} GB/s")
+        graph = graph_build_report(amm, torch, h, pair, pair.k, not args.no_cpu)
+        log(f"[bench] graph build (Alg. 1): {graph['gpu_ms']:.1f} ms on the GPU, {graph['n_nodes']} nodes, "
+            f"{graph['rounds']} rounds" + (f"; oracle {graph['cpu_oracle_s']:.1f} s" if 'cpu_oracle_s' in graph else ""))
     finally:
         amm.amm_destroy(h)
 
@@ -435,6 +512,7 @@ def main():
         "plain_fp64": plain,
         "stages_warmup": stages,
         "closest_points": nn,
+        "graph_build": graph,
         "timed_regions_s": w32,
         "solve": {"first_solve_iters": st32["iters"], "solves_per_region": tot32["solves"],
                   "cg_iters_per_region": tot32["cg_iters"], "refine_steps_per_region": tot32["refine_steps"],
@@ -443,6 +521,8 @@ def main():
     }
     if args.batched:
         out["batched"] = batched_run(amm, torch, args.batched, 5)
+    if args.sequence:
+        out["tracking"] = sequence_run(amm, torch, args.sequence)
     if not args.no_cpu:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(pair)

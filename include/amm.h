@@ -203,6 +203,18 @@ amm_status amm_set_stream(amm_handle* h, void* hip_stream);
  * duplicate or self edges. */
 amm_status amm_check_problem(const amm_problem* p);
 
+/* Replaces the target points of pair `pair` (0-based within the last
+ * amm_set_problems batch) by n_tgt new ones of the same count, keeping the
+ * source side (graph, pattern of K, point lists, coarse aggregates) as it
+ * is; only the pair's search tree is rebuilt.  For registering one template
+ * to a sequence of frames (Sec. 4's sequences) without a new upload.  The
+ * result equals a new amm_set_problems with the new targets.  Pointers are
+ * device pointers when on_device = 1.  Errors: AMM_ERR_STATE before a
+ * problem is set, AMM_ERR_INVALID_ARG (pair, count, dtype, null),
+ * AMM_ERR_NONFINITE. */
+amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const void* tgt_xyz, int64_t n_tgt,
+                           int32_t on_device);
+
 /* Device bytes that amm_set_problems needs for these problems (a static
  * analysis of the inputs; the result is exact). */
 amm_status amm_workspace_size(amm_handle* h, const amm_problem* probs, int32_t n_pairs,

@@ -121,6 +121,7 @@ def lib():
             "amm_set_leaf_size": ([vp, i32], C.c_int),
             "amm_count_nn_work": ([vp, i32], C.c_int),
             "amm_build_graph": ([vp, C.POINTER(amm_graph_in), C.POINTER(amm_graph_info)], C.c_int),
+            "amm_set_targets": ([vp, i32, C.c_int, vp, i64, i32], C.c_int),
             "amm_graph_copy": ([vp, vp, vp, vp, vp], C.c_int),
             "amm_nn_work": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
             "amm_autotune": ([vp, C.POINTER(amm_problem), i32, C.POINTER(i32), i32, C.POINTER(i32),
@@ -151,7 +152,7 @@ def lib():
 EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
             "amm_set_leaf_size", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
-            "amm_build_graph", "amm_graph_copy",
+            "amm_build_graph", "amm_graph_copy", "amm_set_targets",
             "amm_solve", "amm_step", "amm_k_nnzb", "amm_iter_log", "amm_energy", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
@@ -265,6 +266,13 @@ def amm_set_workspace(handle, tensor_or_none) -> None:
 
 def amm_set_leaf_size(handle, leaf: int) -> None:
     _check(lib().amm_set_leaf_size(handle, int(leaf)), handle)
+
+
+def amm_set_targets(handle, pair: int, tgt) -> None:
+    """New target points (same count) for one pair of the handle's batch; tgt
+    is a cuda tensor or a numpy array [M][3]."""
+    on_dev = 0 if isinstance(tgt, np.ndarray) else 1
+    _check(lib().amm_set_targets(handle, int(pair), _dtype_code(tgt), _ptr(tgt), tgt.shape[0], on_dev), handle)
 
 
 def amm_build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0) -> dict:

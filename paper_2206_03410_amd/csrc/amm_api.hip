@@ -1620,6 +1620,57 @@ amm_status amm_step(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     return fail(h, AMM_ERR_INVALID_ARG, "unknown precision");
 }
 
+amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const void* tgt_xyz, int64_t n_tgt,
+                           int32_t on_device) {
+    if (!h || !tgt_xyz) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    if (!h->has_problem) return fail(h, AMM_ERR_STATE, "amm_set_targets before amm_set_problem");
+    if (pair < 0 || pair >= h->L.P) return fail(h, AMM_ERR_INVALID_ARG, "pair out of range");
+    if (dtype != AMM_F32 && dtype != AMM_F64) return fail(h, AMM_ERR_INVALID_ARG, "bad dtype");
+    PairInfo& pi = h->L.info[pair];
+    if (n_tgt != pi.M) return fail(h, AMM_ERR_INVALID_ARG, "n_tgt must equal the pair's target count");
+    HIPC(hipSetDevice(h->device));
+    HIPC(hipStreamSynchronize(h->stream));   // nothing may still read the old targets
+    std::vector<double> tgt(3 * (size_t)n_tgt);
+    const size_t es = dtype == AMM_F32 ? 4 : 8;
+    std::vector<char> raw(es * tgt.size());
+    if (on_device) {
+        HIPC(hipDeviceSynchronize());
+        HIPC(hipMemcpy(raw.data(), tgt_xyz, raw.size(), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(raw.data(), tgt_xyz, raw.size());
+    }
+    for (size_t i = 0; i < tgt.size(); ++i) {
+        tgt[i] = es == 8 ? reinterpret_cast<const double*>(raw.data())[i]
+                         : (double)reinterpret_cast<const float*>(raw.data())[i];
+        if (!std::isfinite(tgt[i])) return fail(h, AMM_ERR_NONFINITE, "non-finite target coordinate");
+    }
+    TargetLayout tl;
+    target_layout(tgt.data(), n_tgt, pi.leaf, tl);
+    if (tl.L != pi.L) return fail(h, AMM_ERR_STATE, "target tree shape changed");
+    Layout& L = h->L;
+    std::copy(tl.tgt4.begin(), tl.tgt4.end(), L.tgt4.begin() + 4 * pi.tgt_off);
+    std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + pi.tgt_off);
+    std::copy(tl.box_lo.begin(), tl.box_lo.end(), L.box_lo.begin() + 4 * pi.tree_off);
+    std::copy(tl.box_hi.begin(), tl.box_hi.end(), L.box_hi.begin() + 4 * pi.tree_off);
+    Dev& v = h->v;
+    HIPC(hipMemcpyAsync(v.tgt_user + pi.tgt_off, tl.tgt_user.data(), sizeof(int32_t) * n_tgt,
+                        hipMemcpyHostToDevice, h->stream));
+    auto put = [&](float* df, double* dd, const std::vector<double>& src) -> amm_status {
+        HIPC(hipMemcpyAsync(v.staging, src.data(), src.size() * 8, hipMemcpyHostToDevice, h->stream));
+        launch_cast_static<float>(v.staging, df, (int64_t)src.size(), h->stream);
+        launch_cast_static<double>(v.staging, dd, (int64_t)src.size(), h->stream);
+        HIPC(hipStreamSynchronize(h->stream));
+        return AMM_OK;
+    };
+    TRY(put(reinterpret_cast<float*>(v.sf.tgt + pi.tgt_off), reinterpret_cast<double*>(v.sd.tgt + pi.tgt_off),
+            tl.tgt4));
+    TRY(put(reinterpret_cast<float*>(v.sf.blo + pi.tree_off), reinterpret_cast<double*>(v.sd.blo + pi.tree_off),
+            tl.box_lo));
+    TRY(put(reinterpret_cast<float*>(v.sf.bhi + pi.tree_off), reinterpret_cast<double*>(v.sd.bhi + pi.tree_off),
+            tl.box_hi));
+    return AMM_OK;
+}
+
 amm_status amm_build_graph(amm_handle* h, const amm_graph_in* in, amm_graph_info* info) {
     if (!h || !in) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
     HIPC(hipSetDevice(h->device));

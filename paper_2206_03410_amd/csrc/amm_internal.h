@@ -125,6 +125,16 @@ constexpr int kMaxCols = 192;        // K blocks per row supported by the assemb
 static_assert(kMaxCols < 255, "column positions are stored in one byte");
 constexpr unsigned kPosUnused = 255;  // column byte of an unused influence slot
 
+// One pair's targets in search order: [M][4] (w = user index), the user
+// index per position, and the implicit complete box tree over leaf-sized
+// buckets ([2L][4], node 1 the root).
+struct TargetLayout {
+    std::vector<double> tgt4, box_lo, box_hi;
+    std::vector<int32_t> tgt_user;
+    int32_t L = 0;
+};
+void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out);
+
 // Device-built deformation graph (Alg. 1), kept by a handle between
 // amm_build_graph and amm_graph_copy.  stream is a hipStream_t.
 struct GraphBuild;

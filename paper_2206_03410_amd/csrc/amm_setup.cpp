@@ -55,6 +55,20 @@ std::vector<int32_t> morton_order(const double* pts, int64_t cnt, const Box& b) 
     return ord;
 }
 
+Box bounds(const double* pts, int64_t cnt) {
+    Box b;
+    for (int c = 0; c < 3; ++c) {
+        b.lo[c] = std::numeric_limits<double>::infinity();
+        b.hi[c] = -b.lo[c];
+    }
+    for (int64_t i = 0; i < cnt; ++i)
+        for (int c = 0; c < 3; ++c) {
+            b.lo[c] = std::min(b.lo[c], pts[3 * i + c]);
+            b.hi[c] = std::max(b.hi[c], pts[3 * i + c]);
+        }
+    return b;
+}
+
 bool finite_all(const std::vector<double>& v) {
     for (double x : v)
         if (!std::isfinite(x)) return false;
@@ -236,21 +250,9 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         pi.nadj = 2 * hp.E;
         pi.n_undirected = (int32_t)hp.E;
 
-        Box bb;
-        for (int c = 0; c < 3; ++c) {
-            bb.lo[c] = std::numeric_limits<double>::infinity();
-            bb.hi[c] = -bb.lo[c];
-        }
-        for (int64_t i = 0; i < hp.N; ++i)
-            for (int c = 0; c < 3; ++c) {
-                bb.lo[c] = std::min(bb.lo[c], hp.src[3 * i + c]);
-                bb.hi[c] = std::max(bb.hi[c], hp.src[3 * i + c]);
-            }
-        for (int64_t i = 0; i < hp.M; ++i)
-            for (int c = 0; c < 3; ++c) {
-                bb.lo[c] = std::min(bb.lo[c], hp.tgt[3 * i + c]);
-                bb.hi[c] = std::max(bb.hi[c], hp.tgt[3 * i + c]);
-            }
+        // sources and nodes are ordered within the sources' box, targets
+        // within their own (so that new targets leave the source side as is)
+        const Box bb = bounds(hp.src.data(), hp.N);
 
         // source points in Morton order
         std::vector<int32_t> sord = morton_order(hp.src.data(), hp.N, bb);
@@ -402,39 +404,18 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         }
 
         // targets: Morton order, implicit complete tree of `leaf`-sized buckets
-        std::vector<int32_t> tord = morton_order(hp.tgt.data(), hp.M, bb);
-        for (int64_t q = 0; q < hp.M; ++q) {
-            int64_t u = tord[q];
-            for (int c = 0; c < 3; ++c) L.tgt4[4 * (to + q) + c] = hp.tgt[3 * u + c];
-            L.tgt4[4 * (to + q) + 3] = (double)u;
-            L.tgt_user[to + q] = (int32_t)u;
+        {
+            TargetLayout tl;
+            target_layout(hp.tgt.data(), hp.M, leaf, tl);
+            std::copy(tl.tgt4.begin(), tl.tgt4.end(), L.tgt4.begin() + 4 * to);
+            std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + to);
+            pi.tree_off = tree;
+            pi.L = tl.L;
+            pi.leaf = leaf;
+            L.box_lo.insert(L.box_lo.end(), tl.box_lo.begin(), tl.box_lo.end());
+            L.box_hi.insert(L.box_hi.end(), tl.box_hi.begin(), tl.box_hi.end());
+            tree += 2 * (int64_t)tl.L;
         }
-        int64_t nleaf = (hp.M + leaf - 1) / leaf;
-        int64_t Lp = 1;
-        while (Lp < nleaf) Lp <<= 1;
-        pi.tree_off = tree;
-        pi.L = (int32_t)Lp;
-        pi.leaf = leaf;
-        const double INF = std::numeric_limits<double>::infinity();
-        L.box_lo.resize(4 * (tree + 2 * Lp), INF);
-        L.box_hi.resize(4 * (tree + 2 * Lp), -INF);
-        for (int64_t q = 0; q < Lp; ++q) {
-            int64_t b = tree + Lp + q;
-            for (int64_t t = q * leaf; t < std::min<int64_t>((q + 1) * leaf, hp.M); ++t)
-                for (int c = 0; c < 3; ++c) {
-                    double v = L.tgt4[4 * (to + t) + c];
-                    L.box_lo[4 * b + c] = std::min(L.box_lo[4 * b + c], v);
-                    L.box_hi[4 * b + c] = std::max(L.box_hi[4 * b + c], v);
-                }
-        }
-        for (int64_t q = Lp - 1; q >= 1; --q) {
-            int64_t b = tree + q, c0 = tree + 2 * q, c1 = c0 + 1;
-            for (int c = 0; c < 3; ++c) {
-                L.box_lo[4 * b + c] = std::min(L.box_lo[4 * c0 + c], L.box_lo[4 * c1 + c]);
-                L.box_hi[4 * b + c] = std::max(L.box_hi[4 * c0 + c], L.box_hi[4 * c1 + c]);
-            }
-        }
-        tree += 2 * Lp;
 
         // tiles
         pi.pt_tile0 = L.n_pt_tiles;
@@ -505,6 +486,42 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.tree_nodes = tree;
     L.pj_entries = (int64_t)L.pj_ent.size();
     return AMM_OK;
+}
+
+void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out) {
+    const Box bb = bounds(tgt, M);
+    std::vector<int32_t> tord = morton_order(tgt, M, bb);
+    out.tgt4.assign(4 * (size_t)M, 0.0);
+    out.tgt_user.resize(M);
+    for (int64_t q = 0; q < M; ++q) {
+        const int64_t u = tord[q];
+        for (int c = 0; c < 3; ++c) out.tgt4[4 * q + c] = tgt[3 * u + c];
+        out.tgt4[4 * q + 3] = (double)u;
+        out.tgt_user[q] = (int32_t)u;
+    }
+    const int64_t nleaf = (M + leaf - 1) / leaf;
+    int64_t Lp = 1;
+    while (Lp < nleaf) Lp <<= 1;
+    out.L = (int32_t)Lp;
+    const double INF = std::numeric_limits<double>::infinity();
+    out.box_lo.assign(4 * 2 * (size_t)Lp, INF);
+    out.box_hi.assign(4 * 2 * (size_t)Lp, -INF);
+    for (int64_t q = 0; q < Lp; ++q) {
+        const int64_t b = Lp + q;
+        for (int64_t t = q * leaf; t < std::min<int64_t>((q + 1) * leaf, M); ++t)
+            for (int c = 0; c < 3; ++c) {
+                const double v = out.tgt4[4 * t + c];
+                out.box_lo[4 * b + c] = std::min(out.box_lo[4 * b + c], v);
+                out.box_hi[4 * b + c] = std::max(out.box_hi[4 * b + c], v);
+            }
+    }
+    for (int64_t q = Lp - 1; q >= 1; --q) {
+        const int64_t b = q, c0 = 2 * q, c1 = c0 + 1;
+        for (int c = 0; c < 3; ++c) {
+            out.box_lo[4 * b + c] = std::min(out.box_lo[4 * c0 + c], out.box_lo[4 * c1 + c]);
+            out.box_hi[4 * b + c] = std::max(out.box_hi[4 * c0 + c], out.box_hi[4 * c1 + c]);
+        }
+    }
 }
 
 }  // namespace amm

@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Optional
+from typing import List, Optional
 
 import numpy as np
 from scipy import sparse
@@ -398,6 +398,53 @@ def sh_pair(seed: int, n_src: int, n_tgt: Optional[int] = None, lmax=8, outlier_
     if normals:
         tgt_nrm = np.concatenate([tn, np.zeros((n_tgt - n_in, 3))], 0)
     return _finish(f"sh{n_src}", src, tgt_all, warp(src), n_nodes, k, e, src_n, tgt_nrm)
+
+
+@dataclasses.dataclass
+class Sequence:
+    """A template (frame 0's source points and deformation graph) and target
+    frames of the same surface bent ever further, all in one scaling."""
+    template: Pair                  # template.tgt = the first target frame
+    frames: List[np.ndarray]        # target points of frames step, 2 step, ...
+    gts: List[np.ndarray]           # ground truth: the template warped to each frame
+    frame_ids: List[int]
+
+
+def sh_sequence(seed: int, n_src: int, n_frames: int = 8, step: int = 2, lmax=8, deg_per_frame=2.5,
+                outlier_frac=0.05, noise=0.003, n_nodes=1000, k=4, e=8) -> Sequence:
+    """Sequence-tracking workload (the paper's frame i -> i + 2 protocol,
+    Sec. 4): one spherical-harmonic surface under an articulated warp whose
+    angle grows by `deg_per_frame` per frame; target frames step, 2 step, ...
+    are resampled independently with noise and uniform outliers; the
+    template is frame 0's surface sampled at n_src points."""
+    surf = SHSurface(lmax, _rng(seed, _S_SRC))
+    src, _ = surf.points(uniform_dirs(n_src, _rng(seed, _S_SRC + 100)), False)
+    wrng = _rng(seed, _S_WARP)
+    base = ArticulatedWarp(wrng, angle_deg=0.0)
+    ids = [step * (f + 1) for f in range(n_frames)]
+    frames, gts = [], []
+    for f, t in enumerate(ids):
+        w = ArticulatedWarp(_rng(seed, _S_WARP), angle_deg=deg_per_frame * t)
+        assert np.allclose(w.a, base.a) and np.allclose(w.axis, base.axis)
+        n_in = n_src - int(round(outlier_frac * n_src))
+        dirs = uniform_dirs(n_in, _rng(seed + 7 * t, _S_TGT))
+        pts, _ = surf.points(dirs, False)
+        tgt = w(pts) + _rng(seed + 7 * t, _S_NOISE).normal(0.0, noise, pts.shape)
+        lo, hi = tgt.min(0), tgt.max(0)
+        outl = _rng(seed + 7 * t, _S_OUT).uniform(lo, hi, (n_src - n_in, 3))
+        frames.append(np.concatenate([tgt, outl], 0))
+        gts.append(w(src))
+    allp = np.concatenate([src] + frames, 0)
+    lo, hi = allp.min(0), allp.max(0)
+    c = 0.5 * (lo + hi)
+    sc = 1.0 / float(np.linalg.norm(hi - lo))
+    src = (src - c) * sc
+    frames = [(fr - c) * sc for fr in frames]
+    gts = [(g - c) * sc for g in gts]
+    node_idx, infl_idx, infl_w, edges = build_graph(src, n_nodes, k, e)
+    tpl = Pair(src=src, tgt=frames[0], gt=gts[0], node_idx=node_idx, infl_idx=infl_idx, infl_w=infl_w,
+               edges=edges, mean_edge_len=mean_knn_edge_length(src), scale=1.0 / sc, name=f"seq{n_src}")
+    return Sequence(tpl, frames, gts, ids)
 
 
 # The five workloads (sizes, graph shape and iteration budgets).
