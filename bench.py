@@ -240,6 +240,16 @@ def batched_run(amm, torch, n_pairs, aa_m):
         amm.amm_set_problems(h, probs)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t
+        # device graph construction (Alg. 1) of every pair, one call per pair
+        srcs = [torch.tensor(p.src, device="cuda:0") for p in pairs]
+        amm.amm_build_graph(h, srcs[0], 4)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g_nodes = 0
+        for sp in srcs:
+            g_nodes += amm.amm_build_graph(h, sp, 4)["n_nodes"]
+        torch.cuda.synchronize()
+        t_graph = time.perf_counter() - t
         tot_nodes = sum(p.n_nodes for p in pairs)
         X = torch.empty(tot_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
         prm = amm.amm_params_default(aa_m=aa_m, precision=amm.AMM_FP32_REFINE)
@@ -254,6 +264,7 @@ def batched_run(amm, torch, n_pairs, aa_m):
     return {"pairs": n_pairs, "points": int(sum(p.n_src for p in pairs)),
             "pairs_per_s": n_pairs / wall, "wall_s": wall, "setup_s": t_setup,
             "autotuned_leaf": leaf, "autotune_s": t_tune,
+            "graph_build_s": t_graph, "graph_build_nodes": g_nodes,
             "p50_pair_ms": float(np.percentile(per, 50)), "p99_pair_ms": float(np.percentile(per, 99)),
             "iters_total": int(sum(s["iters"] for s in st)),
             "converged": int(sum(s["converged"] for s in st))}
@@ -381,6 +392,34 @@ def sequence_run(amm, torch, n_frames):
     return out
 
 
+def variants_run(amm, torch, h, pair, steps, aa_m):
+    """The Sec. 4.1 variants on the workload: each solve from X = I for
+    `steps` MM iterations (FP32 + refinement), its rate and its registration
+    error against the ground truth (Eq. 25, scaled units)."""
+    runs = {"welsch": (amm.AMM_ROBUST_WELSCH, amm.AMM_NU_DYNAMIC), "l2": (amm.AMM_ROBUST_L2, amm.AMM_NU_DYNAMIC),
+            "l2r": (amm.AMM_ROBUST_L2_TRUNC, amm.AMM_NU_DYNAMIC),
+            "welsch_fmax": (amm.AMM_ROBUST_WELSCH, amm.AMM_NU_FIXED_MAX),
+            "welsch_fmin": (amm.AMM_ROBUST_WELSCH, amm.AMM_NU_FIXED_MIN),
+            "welsch_fmed": (amm.AMM_ROBUST_WELSCH, amm.AMM_NU_FIXED_MED)}
+    out = {}
+    X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+    v = torch.empty(pair.n_src, 3, dtype=torch.float32, device="cuda:0")
+    for name, (rb, nm) in runs.items():
+        prm = amm.amm_params_default(aa_m=aa_m, max_total_iters=steps, precision=amm.AMM_FP32_REFINE,
+                                     robust=rb, nu_mode=nm)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = amm.amm_solve(h, prm, X, v)[0]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        rm = math.sqrt(((v.cpu().numpy().astype(np.float64) - pair.gt) ** 2).sum(1).mean())
+        out[name] = {"iters": st["iters"], "iters_per_s": st["iters"] / dt, "rmse_gt": rm,
+                     "stages": st["stages"], "energy": st["energy"]}
+    log("[bench] variants: " + ", ".join(f"{k} {v['iters_per_s']:.0f} it/s rmse {v['rmse_gt']:.4f}"
+                                        for k, v in out.items()))
+    return out
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling the HBM traffic
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run: each of the 5
@@ -471,6 +510,7 @@ def main():
             f"{nn['candidate_traffic_GBps']:.0f} GB/s")
         copy_gbs = copy_bandwidth(torch)
         log(f"[bench] plain device copy {copy_gbs:.0f} GB/s")
+        variants = variants_run(amm, torch, h, pair, args.steps, aa_m)
         graph = graph_build_report(amm, torch, h, pair, pair.k, not args.no_cpu)
         log(f"[bench] graph build (Alg. 1): {graph['gpu_ms']:.1f} ms on the GPU, {graph['n_nodes']} nodes, "
             f"{graph['rounds']} rounds" + (f"; oracle {graph['cpu_oracle_s']:.1f} s" if 'cpu_oracle_s' in graph else ""))
@@ -513,6 +553,7 @@ def main():
         "stages_warmup": stages,
         "closest_points": nn,
         "graph_build": graph,
+        "variants": variants,
         "timed_regions_s": w32,
         "solve": {"first_solve_iters": st32["iters"], "solves_per_region": tot32["solves"],
                   "cg_iters_per_region": tot32["cg_iters"], "refine_steps_per_region": tot32["refine_steps"],
