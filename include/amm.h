@@ -322,10 +322,20 @@ typedef struct {
  * AMM_ERR_NONFINITE, AMM_ERR_OOM, AMM_ERR_HIP. */
 amm_status amm_build_graph(amm_handle* h, const amm_graph_in* in, amm_graph_info* info);
 
-/* Copies the last built graph into caller-owned DEVICE buffers (any may be
- * NULL): node_src_idx [n_nodes], infl_idx [n_src][k], infl_w [n_src][k] in the
- * build's dtype, edges [n_edges][2] (i < j, sorted).  AMM_ERR_STATE if no
- * graph was built. */
+/* The same for n_sets independent point sets (the pairs of a batch) in one
+ * pass: every round of the node selection, every sort and scan covers all
+ * sets; each set's result equals its own amm_build_graph.  k and dtype must
+ * agree over the sets; info receives n_sets records. */
+amm_status amm_build_graphs(amm_handle* h, const amm_graph_in* in, int32_t n_sets, amm_graph_info* info);
+
+/* Copies set `set` (0 for amm_build_graph) of the last build into
+ * caller-owned DEVICE buffers (any may be NULL): node_src_idx [n_nodes]
+ * (indices into the set's points), infl_idx [n_src][k] (the set's node ids),
+ * infl_w [n_src][k] in the build's dtype, edges [n_edges][2] (i < j,
+ * sorted).  AMM_ERR_STATE if no graph was built, AMM_ERR_INVALID_ARG for a
+ * set out of range. */
+amm_status amm_graph_copy_set(amm_handle* h, int32_t set, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w,
+                              int32_t* edges);
 amm_status amm_graph_copy(amm_handle* h, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w,
                           int32_t* edges);
 

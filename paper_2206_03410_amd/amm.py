@@ -123,6 +123,8 @@ def lib():
             "amm_build_graph": ([vp, C.POINTER(amm_graph_in), C.POINTER(amm_graph_info)], C.c_int),
             "amm_set_targets": ([vp, i32, C.c_int, vp, i64, i32], C.c_int),
             "amm_graph_copy": ([vp, vp, vp, vp, vp], C.c_int),
+            "amm_build_graphs": ([vp, C.POINTER(amm_graph_in), i32, C.POINTER(amm_graph_info)], C.c_int),
+            "amm_graph_copy_set": ([vp, i32, vp, vp, vp, vp], C.c_int),
             "amm_nn_work": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
             "amm_autotune": ([vp, C.POINTER(amm_problem), i32, C.POINTER(i32), i32, C.POINTER(i32),
                               C.POINTER(dbl)], C.c_int),
@@ -152,7 +154,7 @@ def lib():
 EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
             "amm_set_leaf_size", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
-            "amm_build_graph", "amm_graph_copy", "amm_set_targets",
+            "amm_build_graph", "amm_graph_copy", "amm_set_targets", "amm_build_graphs", "amm_graph_copy_set",
             "amm_solve", "amm_step", "amm_k_nnzb", "amm_iter_log", "amm_energy", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
@@ -288,6 +290,39 @@ def amm_build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: flo
 
 def amm_graph_copy(handle, node_src_idx=None, infl_idx=None, infl_w=None, edges=None) -> None:
     _check(lib().amm_graph_copy(handle, _ptr(node_src_idx), _ptr(infl_idx), _ptr(infl_w), _ptr(edges)), handle)
+
+
+def amm_build_graphs(handle, srcs, k: int, radius: float = 0.0, radius_factor: float = 0.0) -> list:
+    """Alg. 1 for several point sets (cuda tensors [N_s][3], one dtype) in one
+    pass; returns one info dict per set."""
+    n = len(srcs)
+    gin = (amm_graph_in * n)(*[amm_graph_in(dtype=_dtype_code(sp), src_xyz=_ptr(sp), n_src=sp.shape[0],
+                                            radius=radius, radius_factor=radius_factor, k=k) for sp in srcs])
+    info = (amm_graph_info * n)()
+    _check(lib().amm_build_graphs(handle, gin, n, info), handle)
+    return [i.as_dict() for i in info]
+
+
+def amm_graph_copy_set(handle, set_index: int, node_src_idx=None, infl_idx=None, infl_w=None, edges=None) -> None:
+    _check(lib().amm_graph_copy_set(handle, int(set_index), _ptr(node_src_idx), _ptr(infl_idx), _ptr(infl_w),
+                                    _ptr(edges)), handle)
+
+
+def build_graphs(handle, srcs, k: int, radius: float = 0.0, radius_factor: float = 0.0):
+    """amm_build_graphs + per-set copies into new tensors: a list of
+    (info, node_src_idx, infl_idx, infl_w, edges)."""
+    import torch
+    infos = amm_build_graphs(handle, srcs, k, radius, radius_factor)
+    out = []
+    for s, (sp, info) in enumerate(zip(srcs, infos)):
+        dev = sp.device
+        node = torch.empty(info["n_nodes"], dtype=torch.int32, device=dev)
+        idx = torch.empty(sp.shape[0], k, dtype=torch.int32, device=dev)
+        w = torch.empty(sp.shape[0], k, dtype=sp.dtype, device=dev)
+        edges = torch.empty(max(info["n_edges"], 1), 2, dtype=torch.int32, device=dev)[:info["n_edges"]]
+        amm_graph_copy_set(handle, s, node, idx, w, edges)
+        out.append((info, node, idx, w, edges))
+    return out
 
 
 def build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0):

@@ -1671,27 +1671,36 @@ amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const v
     return AMM_OK;
 }
 
-amm_status amm_build_graph(amm_handle* h, const amm_graph_in* in, amm_graph_info* info) {
+amm_status amm_build_graphs(amm_handle* h, const amm_graph_in* in, int32_t n_sets, amm_graph_info* info) {
     if (!h || !in) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
     HIPC(hipSetDevice(h->device));
     GraphBuild* g = nullptr;
     std::string err;
-    const amm_status st = graph_build(h->stream, *in, info, &g, err);
+    const amm_status st = graph_build(h->stream, in, n_sets, info, &g, err);
     if (st != AMM_OK) return fail(h, st, err);
     if (h->graph) graph_release(h->graph);
     h->graph = g;
     return AMM_OK;
 }
 
-amm_status amm_graph_copy(amm_handle* h, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w, int32_t* edges) {
+amm_status amm_build_graph(amm_handle* h, const amm_graph_in* in, amm_graph_info* info) {
+    return amm_build_graphs(h, in, 1, info);
+}
+
+amm_status amm_graph_copy_set(amm_handle* h, int32_t set, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w,
+                              int32_t* edges) {
     if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
     if (!h->graph) return fail(h, AMM_ERR_STATE, "amm_graph_copy before amm_build_graph");
     HIPC(hipSetDevice(h->device));
     std::string err;
-    const amm_status st = graph_copy(h->graph, h->stream, node_src_idx, infl_idx, infl_w, edges, err);
+    const amm_status st = graph_copy(h->graph, h->stream, set, node_src_idx, infl_idx, infl_w, edges, err);
     if (st != AMM_OK) return fail(h, st, err);
     HIPC(hipStreamSynchronize(h->stream));
     return AMM_OK;
+}
+
+amm_status amm_graph_copy(amm_handle* h, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w, int32_t* edges) {
+    return amm_graph_copy_set(h, 0, node_src_idx, infl_idx, infl_w, edges);
 }
 
 amm_status amm_count_nn_work(amm_handle* h, int32_t enable) {

@@ -1,21 +1,25 @@
 // Deformation-graph construction of Sec. 3.1 (Alg. 1) on the device, with
-// Euclidean distance in place of the geodesic one.
+// Euclidean distance in place of the geodesic one, for one or many point
+// sets (independent registration pairs) at once.
 //
-// Alg. 1 walks the source points in the order of their projection onto the
-// principal axis and makes a point a node when no earlier node lies within
-// R of it.  That is the lexicographically first maximal independent set of
-// the graph "distance < R" under this order, which is unique: a point's
-// decision depends only on the decisions of the earlier points within R.  It
-// is computed here in rounds over all points: a point becomes covered as
-// soon as an earlier neighbour is a node, and a node as soon as all its
-// earlier neighbours are covered.  Each round decides at least the earliest
-// undecided point, and the result equals the sequential pass exactly.
+// Alg. 1 walks a set's source points in the order of their projection onto
+// the principal axis and makes a point a node when no earlier node lies
+// within R of it.  That is the lexicographically first maximal independent
+// set of the graph "distance < R" under this order, which is unique: a
+// point's decision depends only on the decisions of the earlier points
+// within R.  It is computed here in rounds over all points of all sets: a
+// point becomes covered as soon as an earlier neighbour is a node, and a
+// node as soon as all its earlier neighbours are covered.  Each round
+// decides at least the earliest undecided point of every set, and the
+// result equals the sequential pass exactly.
 //
-// Neighbour queries use a uniform grid stored as points sorted by cell key
-// (a stable radix sort), with each occupied cell's 27 neighbour ranges
-// precomputed.  "Within R" is ((dx*dx + dy*dy) + dz*dz) < R*R in float64
-// with every operation rounded on its own (no contraction), so that the
-// integer decisions of the graph match a plain float64 evaluation.
+// Neighbour queries use a uniform grid per set, stored as points sorted by
+// (set, cell) keys (a stable radix sort), with each occupied cell's 27
+// neighbour ranges precomputed.  "Within R" is ((dx*dx + dy*dy) + dz*dz) <
+// R*R in float64 with every operation rounded on its own (no contraction),
+// so that the integer decisions of the graph match a plain float64
+// evaluation.  Sets are concatenated; every key carries the set in its high
+// bits, so no query crosses sets.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -37,6 +41,9 @@ namespace {
 constexpr int kGT = 256;
 constexpr int kKnn = 6;                       // neighbours of the mean-edge-length graph
 constexpr uint64_t kNoKey = ~uint64_t(0);
+constexpr int kSetShift = 44;                 // cell keys: set << 44 | cell
+constexpr uint64_t kCellMask = (uint64_t(1) << kSetShift) - 1;
+constexpr int kMaxSets = 1 << (64 - kSetShift - 1);
 
 #define TRY_STATUS(x)                   \
     do {                                \
@@ -44,13 +51,13 @@ constexpr uint64_t kNoKey = ~uint64_t(0);
         if (s_ != AMM_OK) return s_;    \
     } while (0)
 
-#define GCHK(x)                                                   \
-    do {                                                          \
-        hipError_t e_ = (x);                                      \
-        if (e_ != hipSuccess) {                                   \
-            err = std::string(#x) + ": " + hipGetErrorString(e_); \
+#define GCHK(x)                                                          \
+    do {                                                                 \
+        hipError_t e_ = (x);                                             \
+        if (e_ != hipSuccess) {                                          \
+            err = std::string(#x) + ": " + hipGetErrorString(e_);        \
             return e_ == hipErrorOutOfMemory ? AMM_ERR_OOM : AMM_ERR_HIP; \
-        }                                                         \
+        }                                                                \
     } while (0)
 
 __device__ __forceinline__ double gd2(const double4& a, const double4& b) {
@@ -89,81 +96,104 @@ __device__ __forceinline__ double bext(double v, double* sh) {
     return r;
 }
 
-// ---------------------------------------------------------------- statistics
+struct GridDims {
+    double x0, y0, z0, h;
+    int64_t nx, ny, nz;
+};
 
-// Source points as double4, and per block: min, max and sum of x, y, z and
-// the count of non-finite coordinates.
+// ---------------------------------------------------------------- per-set statistics
+
 template <typename T>
-__global__ void __launch_bounds__(kGT) k_g_load(const T* __restrict__ v, double4* __restrict__ P, int64_t N,
-                                                double* __restrict__ part) {
-    __shared__ double sh[kGT];
+__global__ void __launch_bounds__(kGT) k_g_load(const T* __restrict__ v, double4* __restrict__ P, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    double x = 0, y = 0, z = 0, bad = 0;
-    const bool live = i < N;
-    if (live) {
-        x = (double)v[3 * i];
-        y = (double)v[3 * i + 1];
-        z = (double)v[3 * i + 2];
-        bad = (std::isfinite(x) && std::isfinite(y) && std::isfinite(z)) ? 0.0 : 1.0;
-        P[i] = make_double4(x, y, z, 0.0);
+    if (i < n) P[i] = make_double4((double)v[3 * i], (double)v[3 * i + 1], (double)v[3 * i + 2], 0.0);
+}
+
+// Set of every concatenated point.
+__global__ void __launch_bounds__(kGT) k_g_setid(const int64_t* __restrict__ off, int n_sets, int64_t N,
+                                                 int* __restrict__ sid) {
+    const int64_t i = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (i >= N) return;
+    int lo = 0, hi = n_sets - 1;
+    while (lo < hi) {   // last set whose offset is <= i
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
+    sid[i] = lo;
+}
+
+// One block per set: bounding box, sum, and sum of (v - mean)(v - mean)^T
+// (xx, xy, xz, yy, yz, zz), in a fixed order.  A non-finite coordinate
+// makes the sums non-finite.
+__global__ void __launch_bounds__(kGT) k_g_setstats(const double4* __restrict__ P, const int64_t* __restrict__ off,
+                                                    double* __restrict__ stats) {
+    __shared__ double sh[kGT];
+    const int s = blockIdx.x;
+    const int64_t a = off[s], b = off[s + 1];
     const double inf = __builtin_inf();
-    double r[10];
-    r[0] = bext<kGT, false>(live ? x : inf, sh);
-    r[1] = bext<kGT, false>(live ? y : inf, sh);
-    r[2] = bext<kGT, false>(live ? z : inf, sh);
-    r[3] = bext<kGT, true>(live ? x : -inf, sh);
-    r[4] = bext<kGT, true>(live ? y : -inf, sh);
-    r[5] = bext<kGT, true>(live ? z : -inf, sh);
-    r[6] = bsum<kGT>(x, sh);
-    r[7] = bsum<kGT>(y, sh);
-    r[8] = bsum<kGT>(z, sh);
-    r[9] = bsum<kGT>(bad, sh);
-    if (threadIdx.x < 10) {
-        double o = r[0];
-#pragma unroll
-        for (int m = 1; m < 10; ++m) o = (int)threadIdx.x == m ? r[m] : o;
-        part[10 * (size_t)blockIdx.x + threadIdx.x] = o;
-    }
-}
-
-// Per block: sum of (v - m)(v - m)^T (xx, xy, xz, yy, yz, zz).
-__global__ void __launch_bounds__(kGT) k_g_cov(const double4* __restrict__ P, int64_t N, double mx, double my,
-                                               double mz, double* __restrict__ part) {
-    __shared__ double sh[kGT];
-    const int64_t i = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    double dx = 0, dy = 0, dz = 0;
-    if (i < N) {
+    double lo[3] = {inf, inf, inf}, hi[3] = {-inf, -inf, -inf}, sm[3] = {0, 0, 0};
+    for (int64_t i = a + threadIdx.x; i < b; i += kGT) {
         const double4 p = P[i];
-        dx = p.x - mx;
-        dy = p.y - my;
-        dz = p.z - mz;
-    }
-    double r[6];
-    r[0] = bsum<kGT>(dx * dx, sh);
-    r[1] = bsum<kGT>(dx * dy, sh);
-    r[2] = bsum<kGT>(dx * dz, sh);
-    r[3] = bsum<kGT>(dy * dy, sh);
-    r[4] = bsum<kGT>(dy * dz, sh);
-    r[5] = bsum<kGT>(dz * dz, sh);
-    if (threadIdx.x < 6) {
-        double o = r[0];
+        const double c[3] = {p.x, p.y, p.z};
 #pragma unroll
-        for (int m = 1; m < 6; ++m) o = (int)threadIdx.x == m ? r[m] : o;
-        part[6 * (size_t)blockIdx.x + threadIdx.x] = o;
+        for (int q = 0; q < 3; ++q) {
+            lo[q] = fmin(lo[q], c[q]);
+            hi[q] = fmax(hi[q], c[q]);
+            sm[q] += c[q];
+        }
+    }
+    double r[9];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        r[q] = bext<kGT, false>(lo[q], sh);
+        r[3 + q] = bext<kGT, true>(hi[q], sh);
+        r[6 + q] = bsum<kGT>(sm[q], sh);
+    }
+    const double n = (double)(b - a);
+    const double m[3] = {r[6] / n, r[7] / n, r[8] / n};
+    double cv[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = a + threadIdx.x; i < b; i += kGT) {
+        const double4 p = P[i];
+        const double dx = p.x - m[0], dy = p.y - m[1], dz = p.z - m[2];
+        cv[0] += dx * dx;
+        cv[1] += dx * dy;
+        cv[2] += dx * dz;
+        cv[3] += dy * dy;
+        cv[4] += dy * dz;
+        cv[5] += dz * dz;
+    }
+    double c6[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c6[q] = bsum<kGT>(cv[q], sh);
+    if (threadIdx.x == 0) {
+        double* o = stats + 15 * (size_t)s;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) o[q] = r[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[9 + q] = c6[q];
     }
 }
 
-// Projection onto the principal axis (+0.0 folds -0.0 into +0.0, so that
-// equal projections sort by index).
-__global__ void __launch_bounds__(kGT) k_g_project(const double4* __restrict__ P, int64_t N, double mx,
-                                                   double my, double mz, double ax, double ay, double az,
+// Projection onto the set's principal axis (+0.0 folds -0.0 into +0.0, so
+// that equal projections sort by index).  ax[s] = (mean, axis).
+__global__ void __launch_bounds__(kGT) k_g_project(const double4* __restrict__ P, const int* __restrict__ sid,
+                                                   const double* __restrict__ ax, int64_t N,
                                                    double* __restrict__ key, int* __restrict__ val) {
     const int64_t i = (int64_t)blockIdx.x * kGT + threadIdx.x;
     if (i >= N) return;
     const double4 p = P[i];
-    key[i] = ((p.x - mx) * ax + (p.y - my) * ay + (p.z - mz) * az) + 0.0;
+    const double* a = ax + 6 * (size_t)sid[i];
+    key[i] = ((p.x - a[0]) * a[3] + (p.y - a[1]) * a[4] + (p.z - a[2]) * a[5]) + 0.0;
     val[i] = (int)i;
+}
+
+__global__ void __launch_bounds__(kGT) k_g_take(const int* __restrict__ idx, const int* __restrict__ src, int64_t N,
+                                                int* __restrict__ dst) {
+    const int64_t p = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (p < N) dst[p] = src[idx[p]];
 }
 
 __global__ void __launch_bounds__(kGT) k_g_invert(const int* __restrict__ order, int* __restrict__ rank, int64_t N) {
@@ -171,39 +201,41 @@ __global__ void __launch_bounds__(kGT) k_g_invert(const int* __restrict__ order,
     if (s < N) rank[order[s]] = (int)s;
 }
 
-// ---------------------------------------------------------------- sorted-cell grid
-
-struct GridDims {
-    double x0, y0, z0, h;
-    int64_t nx, ny, nz;
-};
+// ---------------------------------------------------------------- sorted-cell grids
 
 __device__ __forceinline__ int64_t cell_coord(double v, double v0, double h, int64_t n) {
     int64_t c = (int64_t)floor((v - v0) / h);
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
-__global__ void __launch_bounds__(kGT) k_g_cellkey(const double4* __restrict__ P, int64_t N, GridDims g,
+__device__ __forceinline__ uint64_t cell_key(int set, const GridDims& g, int64_t x, int64_t y, int64_t z) {
+    return ((uint64_t)set << kSetShift) | (uint64_t)((z * g.ny + y) * g.nx + x);
+}
+
+__global__ void __launch_bounds__(kGT) k_g_cellkey(const double4* __restrict__ P, const int* __restrict__ sid,
+                                                   const GridDims* __restrict__ gd, int64_t N,
                                                    uint64_t* __restrict__ key, int* __restrict__ val) {
     const int64_t i = (int64_t)blockIdx.x * kGT + threadIdx.x;
     if (i >= N) return;
     const double4 p = P[i];
-    const int64_t cx = cell_coord(p.x, g.x0, g.h, g.nx), cy = cell_coord(p.y, g.y0, g.h, g.ny),
-                  cz = cell_coord(p.z, g.z0, g.h, g.nz);
-    key[i] = (uint64_t)((cz * g.ny + cy) * g.nx + cx);
+    const int s = sid[i];
+    const GridDims g = gd[s];
+    key[i] = cell_key(s, g, cell_coord(p.x, g.x0, g.h, g.nx), cell_coord(p.y, g.y0, g.h, g.ny),
+                      cell_coord(p.z, g.z0, g.h, g.nz));
     val[i] = (int)i;
 }
 
-// Points in cell order: position, rank along the axis, and 1 at the first
-// point of every occupied cell.
+// Points in cell order: position, set, rank along the axis (when given),
+// and 1 at the first point of every occupied cell.
 __global__ void __launch_bounds__(kGT) k_g_gather(const uint64_t* __restrict__ ck, const int* __restrict__ cp,
-                                                  const double4* __restrict__ P, const int* __restrict__ rank,
-                                                  int64_t N, double4* __restrict__ Ps, int* __restrict__ rs,
-                                                  int* __restrict__ head) {
+                                                  const double4* __restrict__ P, const int* __restrict__ sid,
+                                                  const int* __restrict__ rank, int64_t N, double4* __restrict__ Ps,
+                                                  int* __restrict__ ss, int* __restrict__ rs, int* __restrict__ head) {
     const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
     if (s >= N) return;
     const int i = cp[s];
     Ps[s] = P[i];
+    ss[s] = sid[i];
     if (rs) rs[s] = rank[i];
     head[s] = (s == 0 || ck[s] != ck[s - 1]) ? 1 : 0;
 }
@@ -236,15 +268,19 @@ __device__ __forceinline__ int find_cell(const uint64_t* __restrict__ ukey, int 
 }
 
 // For every occupied cell the sorted-position ranges of its 27 neighbour
-// cells (itself included), empty ones as (0, 0).
+// cells of the same set (itself included), empty ones as (0, 0).
 __global__ void __launch_bounds__(kGT) k_g_nbr(const uint64_t* __restrict__ ukey, const int* __restrict__ ustart,
-                                               int nu, int64_t N, GridDims g, int2* __restrict__ nb) {
+                                               int nu, int64_t N, const GridDims* __restrict__ gd,
+                                               int2* __restrict__ nb) {
     const int u = blockIdx.x * kGT + threadIdx.x;
     if (u >= nu) return;
     const uint64_t key = ukey[u];
-    const int64_t cx = (int64_t)(key % (uint64_t)g.nx);
-    const int64_t cy = (int64_t)((key / (uint64_t)g.nx) % (uint64_t)g.ny);
-    const int64_t cz = (int64_t)(key / ((uint64_t)g.nx * (uint64_t)g.ny));
+    const int set = (int)(key >> kSetShift);
+    const GridDims g = gd[set];
+    const uint64_t lin = key & kCellMask;
+    const int64_t cx = (int64_t)(lin % (uint64_t)g.nx);
+    const int64_t cy = (int64_t)((lin / (uint64_t)g.nx) % (uint64_t)g.ny);
+    const int64_t cz = (int64_t)(lin / ((uint64_t)g.nx * (uint64_t)g.ny));
     int o = 0;
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
@@ -252,86 +288,14 @@ __global__ void __launch_bounds__(kGT) k_g_nbr(const uint64_t* __restrict__ ukey
                 const int64_t x = cx + dx, y = cy + dy, z = cz + dz;
                 int2 r = make_int2(0, 0);
                 if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
-                    const int c = find_cell(ukey, nu, (uint64_t)((z * g.ny + y) * g.nx + x));
+                    const int c = find_cell(ukey, nu, cell_key(set, g, x, y, z));
                     if (c >= 0) r = make_int2(ustart[c], c + 1 < nu ? ustart[c + 1] : (int)N);
                 }
                 nb[27 * (size_t)u + o] = r;
             }
 }
 
-// ---------------------------------------------------------------- node selection
-
-// One round over the undecided points (cell order).  state: 0 undecided,
-// 1 node, 2 covered.  Reads of other points' states may see the value of
-// the previous round or of this one; both are final or undecided, so a
-// decision taken is always the sequential pass's.
-__global__ void __launch_bounds__(kGT) k_g_round(const double4* __restrict__ Ps, const int* __restrict__ rs,
-                                                 const int* __restrict__ us, const int2* __restrict__ nb,
-                                                 int* state, int64_t N, double R2, int* __restrict__ remaining) {
-    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    bool undecided = false;
-    if (s < N && __hip_atomic_load(&state[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        const double4 q = Ps[s];
-        const int rq = rs[s];
-        const int2* cells = nb + 27 * (size_t)us[s];
-        bool covered = false, pending = false;
-        for (int o = 0; o < 27 && !covered; ++o) {
-            const int2 r = cells[o];
-            for (int t = r.x; t < r.y; ++t) {
-                if (rs[t] >= rq) continue;
-                if (!(gd2(Ps[t], q) < R2)) continue;
-                const int st = __hip_atomic_load(&state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (st == 1) {
-                    covered = true;
-                    break;
-                }
-                if (st == 0) pending = true;
-            }
-        }
-        if (covered)
-            __hip_atomic_store(&state[s], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else if (!pending)
-            __hip_atomic_store(&state[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            undecided = true;
-    }
-    const int cnt = __syncthreads_count(undecided);
-    if (threadIdx.x == 0 && cnt) atomicAdd(remaining, cnt);
-}
-
-// Axis order -> node flag (for the node numbering scan).
-__global__ void __launch_bounds__(kGT) k_g_nodeflag(const int* __restrict__ rs, const int* __restrict__ state,
-                                                    int64_t N, int* __restrict__ flag_by_rank,
-                                                    int* __restrict__ pos_by_rank) {
-    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    if (s >= N) return;
-    flag_by_rank[rs[s]] = state[s] == 1 ? 1 : 0;
-    pos_by_rank[rs[s]] = (int)s;
-}
-
-// exclusive = inclusive - own flag
-__global__ void __launch_bounds__(kGT) k_g_excl_from_incl(const int* __restrict__ incl, const int* __restrict__ flag,
-                                                          int64_t N, int* __restrict__ excl) {
-    const int64_t r = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    if (r < N) excl[r] = incl[r] - flag[r];
-}
-
-__global__ void __launch_bounds__(kGT) k_g_nodeid(const int* __restrict__ flag_by_rank,
-                                                  const int* __restrict__ nid_by_rank,
-                                                  const int* __restrict__ pos_by_rank, const int* __restrict__ cp,
-                                                  int64_t N, int* __restrict__ nid_s, int* __restrict__ node_src) {
-    const int64_t r = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    if (r >= N) return;
-    const int s = pos_by_rank[r];
-    if (flag_by_rank[r]) {
-        nid_s[s] = nid_by_rank[r];
-        node_src[nid_by_rank[r]] = cp[s];
-    } else {
-        nid_s[s] = -1;
-    }
-}
-
-// ---------------------------------------------------------------- influence sets
+// ---------------------------------------------------------------- mean edge length
 
 // (d, id) ordered by distance, then id.
 __device__ __forceinline__ bool before(double d1, int i1, double d2, int i2) {
@@ -360,129 +324,23 @@ __device__ __forceinline__ void topk_insert(double (&bd)[kMaxK], int (&bi)[kMaxK
         }
 }
 
-// Per point (cell order): its k nearest nodes within R, weights of Eq. (3)
-// normalized over them, the pair keys of its kept nodes (for the edges),
-// and block partials of the capped count and the largest count.
-template <typename TW>
-__global__ void __launch_bounds__(kGT) k_g_influence(const double4* __restrict__ Ps, const int* __restrict__ us,
-                                                     const int2* __restrict__ nb, const int* __restrict__ nid_s,
-                                                     const int* __restrict__ cp, int64_t N, int64_t n_nodes,
-                                                     double R2, int k, int* __restrict__ infl_idx,
-                                                     TW* __restrict__ infl_w, uint64_t* __restrict__ pair_key,
-                                                     int* __restrict__ stats) {
-    __shared__ double sh[kGT];
-    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    double capped = 0, most = 0;
-    if (s < N) {
-        const double4 q = Ps[s];
-        const int2* cells = nb + 27 * (size_t)us[s];
-        double bd[kMaxK];
-        int bi[kMaxK];
-#pragma unroll
-        for (int a = 0; a < kMaxK; ++a) {
-            bd[a] = __builtin_inf();
-            bi[a] = INT32_MAX;
-        }
-        int cnt = 0;
-        for (int o = 0; o < 27; ++o) {
-            const int2 r = cells[o];
-            for (int t = r.x; t < r.y; ++t) {
-                const int id = nid_s[t];
-                if (id < 0) continue;
-                const double d = gd2(Ps[t], q);
-                if (!(d < R2)) continue;
-                ++cnt;
-                topk_insert(bd, bi, k, d, id);
-            }
-        }
-        capped = cnt > k ? 1.0 : 0.0;
-        most = (double)cnt;
-        const int kept = cnt < k ? cnt : k;
-        double w[kMaxK];
-        double sw = 0;
-#pragma unroll
-        for (int a = 0; a < kMaxK; ++a) {
-            double x;
-            {
-#pragma clang fp contract(off)
-                x = 1.0 - bd[a] / R2;
-                x = x * x * x;
-            }
-            w[a] = a < kept ? x : 0.0;
-            sw += w[a];
-        }
-        const int i = cp[s];
-        for (int a = 0; a < k; ++a) {
-            double wa = 0;
-            int ia = -1;
-#pragma unroll
-            for (int b = 0; b < kMaxK; ++b)
-                if (b == a) {
-                    wa = w[b];
-                    ia = b < kept ? bi[b] : -1;
-                }
-            infl_idx[(size_t)i * k + a] = ia;
-            infl_w[(size_t)i * k + a] = (TW)(ia >= 0 ? wa / sw : 0.0);
-        }
-        // node pairs through kept slots: key = lo * n_nodes + hi
-        const int npair = k * (k - 1) / 2;
-        int t = 0;
-#pragma unroll
-        for (int a = 0; a < kMaxK; ++a)
-#pragma unroll
-            for (int b = a + 1; b < kMaxK; ++b) {
-                if (b < k) {
-                    uint64_t key = kNoKey;
-                    if (b < kept) {
-                        const int lo = bi[a] < bi[b] ? bi[a] : bi[b];
-                        const int hi = bi[a] < bi[b] ? bi[b] : bi[a];
-                        key = (uint64_t)lo * (uint64_t)n_nodes + (uint64_t)hi;
-                    }
-                    pair_key[(size_t)i * npair + t] = key;
-                    ++t;
-                }
-            }
-    }
-    const double c = bsum<kGT>(capped, sh);
-    const double m = bext<kGT, true>(most, sh);
-    if (threadIdx.x == 0) {
-        atomicAdd(&stats[0], (int)c);
-        atomicMax(&stats[1], (int)m);
-    }
-}
-
-// Unique sorted keys -> (lo, hi) edges.
-__global__ void __launch_bounds__(kGT) k_g_headflag(const uint64_t* __restrict__ key, int64_t M,
-                                                    int* __restrict__ flag) {
-    const int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    if (e >= M) return;
-    const uint64_t v = key[e];
-    flag[e] = (v != kNoKey && (e == 0 || v != key[e - 1])) ? 1 : 0;
-}
-
-__global__ void __launch_bounds__(kGT) k_g_edges(const uint64_t* __restrict__ key, const int* __restrict__ flag,
-                                                 const int* __restrict__ incl, int64_t M, int64_t n_nodes,
-                                                 int* __restrict__ edges) {
-    const int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    if (e >= M || !flag[e]) return;
-    const int o = incl[e] - 1;
-    edges[2 * (size_t)o] = (int)(key[e] / (uint64_t)n_nodes);
-    edges[2 * (size_t)o + 1] = (int)(key[e] % (uint64_t)n_nodes);
-}
-
-// ---------------------------------------------------------------- mean edge length
-
-// kKnn nearest other points (ties to the lower source index) by growing
-// shells of cells: after the shell at Chebyshev distance r every point
-// within r*h of the query has been seen, so the search stops once the
-// kKnn-th distance is below (r*h)^2 or every cell is covered.
+// kKnn nearest other points of the same set (ties to the lower index) by
+// growing shells of cells: after the shell at Chebyshev distance r every
+// point within r*h of the query has been seen, so the search stops once the
+// kKnn-th distance is below (r*h)^2 or every cell is covered.  Writes the
+// undirected pair keys lo * N + hi (global indices).
 __global__ void __launch_bounds__(kGT) k_g_knn(const double4* __restrict__ Ps, const int* __restrict__ cp,
-                                               const uint64_t* __restrict__ ukey, const int* __restrict__ ustart,
-                                               int nu, int64_t N, GridDims g, uint64_t* __restrict__ pair_key) {
+                                               const int* __restrict__ ss, const uint64_t* __restrict__ ukey,
+                                               const int* __restrict__ ustart, int nu, int64_t N,
+                                               const GridDims* __restrict__ gd, const int64_t* __restrict__ off,
+                                               uint64_t* __restrict__ pair_key) {
     const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
     if (s >= N) return;
     const double4 q = Ps[s];
     const int self = cp[s];
+    const int set = ss[s];
+    const GridDims g = gd[set];
+    const int64_t n_set = off[set + 1] - off[set];
     const int64_t cx = cell_coord(q.x, g.x0, g.h, g.nx), cy = cell_coord(q.y, g.y0, g.h, g.ny),
                   cz = cell_coord(q.z, g.z0, g.h, g.nz);
     double bd[kMaxK];
@@ -492,7 +350,7 @@ __global__ void __launch_bounds__(kGT) k_g_knn(const double4* __restrict__ Ps, c
         bd[a] = __builtin_inf();
         bi[a] = INT32_MAX;
     }
-    const int want = N - 1 < kKnn ? (int)(N - 1) : kKnn;
+    const int want = n_set - 1 < kKnn ? (int)(n_set - 1) : kKnn;
     int cnt = 0;
     const int64_t rmax = g.nx > g.ny ? (g.nx > g.nz ? g.nx : g.nz) : (g.ny > g.nz ? g.ny : g.nz);
     for (int64_t r = 0; r <= rmax; ++r) {
@@ -504,7 +362,7 @@ __global__ void __launch_bounds__(kGT) k_g_knn(const double4* __restrict__ Ps, c
                     if (ring != r) continue;
                     const int64_t x = cx + dx, y = cy + dy, z = cz + dz;
                     if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) continue;
-                    const int c = find_cell(ukey, nu, (uint64_t)((z * g.ny + y) * g.nx + x));
+                    const int c = find_cell(ukey, nu, cell_key(set, g, x, y, z));
                     if (c < 0) continue;
                     const int e = c + 1 < nu ? ustart[c + 1] : (int)N;
                     for (int t = ustart[c]; t < e; ++t) {
@@ -529,25 +387,247 @@ __global__ void __launch_bounds__(kGT) k_g_knn(const double4* __restrict__ Ps, c
     }
 }
 
-// Per block: sum of the lengths of the unique edges it holds (sorted keys).
-__global__ void __launch_bounds__(kGT) k_g_edge_len(const uint64_t* __restrict__ key, const int* __restrict__ flag,
-                                                    int64_t M, int64_t N, const double4* __restrict__ P,
-                                                    double* __restrict__ part) {
-    __shared__ double sh[kGT];
+__global__ void __launch_bounds__(kGT) k_g_headflag(const uint64_t* __restrict__ key, int64_t M,
+                                                    int* __restrict__ flag) {
     const int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x;
-    double len = 0;
-    if (e < M && flag[e]) {
-        const int a = (int)(key[e] / (uint64_t)N), b = (int)(key[e] % (uint64_t)N);
-        len = sqrt(gd2(P[a], P[b]));
+    if (e >= M) return;
+    const uint64_t v = key[e];
+    flag[e] = (v != kNoKey && (e == 0 || v != key[e - 1])) ? 1 : 0;
+}
+
+// Per set, the first sorted position whose key is >= bound[s] (the key
+// ranges of the sets are contiguous and ordered).
+__global__ void __launch_bounds__(kGT) k_g_bounds(const uint64_t* __restrict__ key, int64_t M,
+                                                  const uint64_t* __restrict__ bound, int nb,
+                                                  int64_t* __restrict__ at) {
+    const int s = blockIdx.x * kGT + threadIdx.x;
+    if (s >= nb) return;
+    const uint64_t b = bound[s];
+    int64_t lo = 0, hi = M;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] < b)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    const double t = bsum<kGT>(len, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    at[s] = lo;
+}
+
+// One block per set: sum of the lengths of its unique edges and their count,
+// over its range of the sorted keys, in a fixed order.
+__global__ void __launch_bounds__(kGT) k_g_edge_len(const uint64_t* __restrict__ key, const int* __restrict__ flag,
+                                                    const int64_t* __restrict__ at, int64_t N,
+                                                    const double4* __restrict__ P, double* __restrict__ out) {
+    __shared__ double sh[kGT];
+    const int s = blockIdx.x;
+    double len = 0, cnt = 0;
+    for (int64_t e = at[s] + threadIdx.x; e < at[s + 1]; e += kGT) {
+        if (!flag[e]) continue;
+        const int a = (int)(key[e] / (uint64_t)N), b = (int)(key[e] % (uint64_t)N);
+        len += sqrt(gd2(P[a], P[b]));
+        cnt += 1;
+    }
+    const double tl = bsum<kGT>(len, sh);
+    const double tc = bsum<kGT>(cnt, sh);
+    if (threadIdx.x == 0) {
+        out[2 * s] = tl;
+        out[2 * s + 1] = tc;
+    }
+}
+
+// ---------------------------------------------------------------- node selection
+
+// One round over the undecided points (cell order).  state: 0 undecided,
+// 1 node, 2 covered.  Reads of other points' states may see the value of
+// the previous round or of this one; both are final or undecided, so a
+// decision taken is always the sequential pass's.
+__global__ void __launch_bounds__(kGT) k_g_round(const double4* __restrict__ Ps, const int* __restrict__ rs,
+                                                 const int* __restrict__ ss, const int* __restrict__ us,
+                                                 const int2* __restrict__ nb, int* state, int64_t N,
+                                                 const double* __restrict__ R2s, int* __restrict__ remaining) {
+    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    bool undecided = false;
+    if (s < N && __hip_atomic_load(&state[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        const double4 q = Ps[s];
+        const int rq = rs[s];
+        const double R2 = R2s[ss[s]];
+        const int2* cells = nb + 27 * (size_t)us[s];
+        bool covered = false, pending = false;
+        for (int o = 0; o < 27 && !covered; ++o) {
+            const int2 r = cells[o];
+            for (int t = r.x; t < r.y; ++t) {
+                if (rs[t] >= rq) continue;
+                if (!(gd2(Ps[t], q) < R2)) continue;
+                const int st = __hip_atomic_load(&state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (st == 1) {
+                    covered = true;
+                    break;
+                }
+                if (st == 0) pending = true;
+            }
+        }
+        if (covered)
+            __hip_atomic_store(&state[s], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else if (!pending)
+            __hip_atomic_store(&state[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            undecided = true;
+    }
+    const int cnt = __syncthreads_count(undecided);
+    if (threadIdx.x == 0 && cnt) atomicAdd(remaining, cnt);
+}
+
+// Axis order -> node flag and cell-order position.
+__global__ void __launch_bounds__(kGT) k_g_nodeflag(const int* __restrict__ rs, const int* __restrict__ state,
+                                                    int64_t N, int* __restrict__ flag_by_rank,
+                                                    int* __restrict__ pos_by_rank) {
+    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (s >= N) return;
+    flag_by_rank[rs[s]] = state[s] == 1 ? 1 : 0;
+    pos_by_rank[rs[s]] = (int)s;
+}
+
+// Per set: global id of its first node (the nodes before it), and the
+// total at the end.  Ranks of set s are off[s] .. off[s+1]-1.
+__global__ void __launch_bounds__(kGT) k_g_setnodes(const int* __restrict__ incl, const int* __restrict__ flag,
+                                                    const int64_t* __restrict__ off, int n_sets,
+                                                    int64_t* __restrict__ node_off) {
+    const int s = blockIdx.x * kGT + threadIdx.x;
+    if (s > n_sets) return;
+    const int64_t r = off[s];
+    node_off[s] = s < n_sets ? (int64_t)(incl[r] - flag[r]) : (int64_t)incl[r - 1];
+}
+
+// Node ids: global in cell order (-1 for non-nodes), the node's source
+// point as an index within its set, and the node's set.
+__global__ void __launch_bounds__(kGT) k_g_nodeid(const int* __restrict__ flag_by_rank, const int* __restrict__ incl,
+                                                  const int* __restrict__ pos_by_rank, const int* __restrict__ cp,
+                                                  const int* __restrict__ ss, const int64_t* __restrict__ off,
+                                                  int64_t N, int* __restrict__ nid_s, int* __restrict__ node_src,
+                                                  int* __restrict__ nset) {
+    const int64_t r = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (r >= N) return;
+    const int s = pos_by_rank[r];
+    if (flag_by_rank[r]) {
+        const int g = incl[r] - 1;
+        const int set = ss[s];
+        nid_s[s] = g;
+        node_src[g] = (int)(cp[s] - off[set]);
+        nset[g] = set;
+    } else {
+        nid_s[s] = -1;
+    }
+}
+
+// ---------------------------------------------------------------- influence sets
+
+// Per point (cell order): its k nearest nodes within R, weights of Eq. (3)
+// normalized over them, the pair keys lo * n_nodes + hi (global node ids)
+// of its kept nodes, and per set the number of points with more than k
+// nodes within R and the largest such number.  Node ids written are
+// local to the set.
+template <typename TW>
+__global__ void __launch_bounds__(kGT) k_g_influence(const double4* __restrict__ Ps, const int* __restrict__ ss,
+                                                     const int* __restrict__ us, const int2* __restrict__ nb,
+                                                     const int* __restrict__ nid_s, const int* __restrict__ cp,
+                                                     const int64_t* __restrict__ node_off,
+                                                     const double* __restrict__ R2s, int64_t N, int64_t n_nodes,
+                                                     int k, int* __restrict__ infl_idx, TW* __restrict__ infl_w,
+                                                     uint64_t* __restrict__ pair_key, int* __restrict__ stats) {
+    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (s >= N) return;
+    const double4 q = Ps[s];
+    const int set = ss[s];
+    const double R2 = R2s[set];
+    const int2* cells = nb + 27 * (size_t)us[s];
+    double bd[kMaxK];
+    int bi[kMaxK];
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a) {
+        bd[a] = __builtin_inf();
+        bi[a] = INT32_MAX;
+    }
+    int cnt = 0;
+    for (int o = 0; o < 27; ++o) {
+        const int2 r = cells[o];
+        for (int t = r.x; t < r.y; ++t) {
+            const int id = nid_s[t];
+            if (id < 0) continue;
+            const double d = gd2(Ps[t], q);
+            if (!(d < R2)) continue;
+            ++cnt;
+            topk_insert(bd, bi, k, d, id);
+        }
+    }
+    if (cnt > k) atomicAdd(&stats[2 * set], 1);
+    atomicMax(&stats[2 * set + 1], cnt);
+    const int kept = cnt < k ? cnt : k;
+    double w[kMaxK];
+    double sw = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a) {
+        double x;
+        {
+#pragma clang fp contract(off)
+            x = 1.0 - bd[a] / R2;
+            x = x * x * x;
+        }
+        w[a] = a < kept ? x : 0.0;
+        sw += w[a];
+    }
+    const int i = cp[s];
+    const int base = (int)node_off[set];
+    for (int a = 0; a < k; ++a) {
+        double wa = 0;
+        int ia = -1;
+#pragma unroll
+        for (int b = 0; b < kMaxK; ++b)
+            if (b == a) {
+                wa = w[b];
+                ia = b < kept ? bi[b] - base : -1;
+            }
+        infl_idx[(size_t)i * k + a] = ia;
+        infl_w[(size_t)i * k + a] = (TW)(ia >= 0 ? wa / sw : 0.0);
+    }
+    const int npair = k * (k - 1) / 2;
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a)
+#pragma unroll
+        for (int b = a + 1; b < kMaxK; ++b) {
+            if (b < k) {
+                uint64_t key = kNoKey;
+                if (b < kept) {
+                    const int lo = bi[a] < bi[b] ? bi[a] : bi[b];
+                    const int hi = bi[a] < bi[b] ? bi[b] : bi[a];
+                    key = (uint64_t)lo * (uint64_t)n_nodes + (uint64_t)hi;
+                }
+                pair_key[(size_t)i * npair + t] = key;
+                ++t;
+            }
+        }
+}
+
+// Unique sorted keys -> edges with node ids local to their set.
+__global__ void __launch_bounds__(kGT) k_g_edges(const uint64_t* __restrict__ key, const int* __restrict__ flag,
+                                                 const int* __restrict__ incl, int64_t M, int64_t n_nodes,
+                                                 const int* __restrict__ nset, const int64_t* __restrict__ node_off,
+                                                 uint64_t* __restrict__ ukey, int* __restrict__ edges) {
+    const int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (e >= M || !flag[e]) return;
+    const int o = incl[e] - 1;
+    const int lo = (int)(key[e] / (uint64_t)n_nodes), hi = (int)(key[e] % (uint64_t)n_nodes);
+    const int base = (int)node_off[nset[lo]];
+    ukey[o] = key[e];
+    edges[2 * (size_t)o] = lo - base;
+    edges[2 * (size_t)o + 1] = hi - base;
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kGT - 1) / kGT); }
 
 // Eigenvector of the largest eigenvalue of a symmetric 3x3 matrix by cyclic
-// Jacobi rotations.
+// Jacobi rotations, its largest component made positive.
 void sym3_top_eigvec(const double C[3][3], double out[3]) {
     double A[3][3], V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     for (int r = 0; r < 3; ++r)
@@ -617,15 +697,15 @@ struct Scratch {
 };
 
 template <typename K, typename V>
-hipError_t sort_pairs(Scratch& sc, const K* kin, K* kout, const V* vin, V* vout, int64_t n, hipStream_t st) {
+hipError_t sort_pairs(Scratch& sc, const K* kin, K* kout, const V* vin, V* vout, int64_t n, hipStream_t st,
+                      int end_bit = 8 * sizeof(K)) {
     size_t bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0,
-                                                      (int)(8 * sizeof(K)), st);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, st);
     if (e != hipSuccess) return e;
     void* tmp = nullptr;
     e = sc.bytes(tmp, bytes);
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kin, kout, vin, vout, (int)n, 0, (int)(8 * sizeof(K)), st);
+    return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, st);
 }
 
 hipError_t sort_keys(Scratch& sc, const uint64_t* kin, uint64_t* kout, int64_t n, hipStream_t st) {
@@ -648,8 +728,7 @@ hipError_t incl_sum(Scratch& sc, const int* in, int* out, int64_t n, hipStream_t
     return hipcub::DeviceScan::InclusiveSum(tmp, bytes, in, out, (int)n, st);
 }
 
-GridDims grid_for(const double lo[3], const double hi[3], double h) {
-    GridDims g;
+bool grid_for(const double lo[3], const double hi[3], double h, GridDims& g) {
     g.x0 = lo[0];
     g.y0 = lo[1];
     g.z0 = lo[2];
@@ -657,16 +736,18 @@ GridDims grid_for(const double lo[3], const double hi[3], double h) {
     g.nx = (int64_t)std::floor((hi[0] - lo[0]) / h) + 1;
     g.ny = (int64_t)std::floor((hi[1] - lo[1]) / h) + 1;
     g.nz = (int64_t)std::floor((hi[2] - lo[2]) / h) + 1;
-    return g;
+    const double cells = (double)g.nx * (double)g.ny * (double)g.nz;
+    return cells < (double)kCellMask;
 }
 
-// Points sorted by grid cell: cell keys and source ids in cell order, the
-// occupied cells' keys and first positions, each point's cell, positions
-// (and axis ranks when given) in cell order.
+// Points sorted by (set, grid cell): cell keys and source ids in cell
+// order, the occupied cells' keys and first positions, each point's cell,
+// set, position, and axis rank when given.
 struct CellGrid {
     uint64_t* ck = nullptr;
     int* cp = nullptr;
     double4* Ps = nullptr;
+    int* ss = nullptr;
     int* rs = nullptr;
     int* us = nullptr;
     uint64_t* ukey = nullptr;
@@ -674,8 +755,8 @@ struct CellGrid {
     int nu = 0;
 };
 
-amm_status build_cells(Scratch& sc, const double4* P, const int* rank, int64_t N, const GridDims& g,
-                       hipStream_t st, CellGrid& G, std::string& err) {
+amm_status build_cells(Scratch& sc, const double4* P, const int* sid, const int* rank, int64_t N,
+                       const GridDims* gd_dev, hipStream_t st, CellGrid& G, std::string& err) {
     uint64_t* key = nullptr;
     int* val = nullptr;
     int *head = nullptr, *incl = nullptr;
@@ -684,13 +765,15 @@ amm_status build_cells(Scratch& sc, const double4* P, const int* rank, int64_t N
     GCHK(sc.get(G.ck, N));
     GCHK(sc.get(G.cp, N));
     GCHK(sc.get(G.Ps, N));
+    GCHK(sc.get(G.ss, N));
     if (rank) GCHK(sc.get(G.rs, N));
     GCHK(sc.get(G.us, N));
     GCHK(sc.get(head, N));
     GCHK(sc.get(incl, N));
-    hipLaunchKernelGGL(k_g_cellkey, dim3(nblk(N)), dim3(kGT), 0, st, P, N, g, key, val);
+    hipLaunchKernelGGL(k_g_cellkey, dim3(nblk(N)), dim3(kGT), 0, st, P, sid, gd_dev, N, key, val);
     GCHK(sort_pairs(sc, key, G.ck, val, G.cp, N, st));
-    hipLaunchKernelGGL(k_g_gather, dim3(nblk(N)), dim3(kGT), 0, st, G.ck, G.cp, P, rank, N, G.Ps, G.rs, head);
+    hipLaunchKernelGGL(k_g_gather, dim3(nblk(N)), dim3(kGT), 0, st, G.ck, G.cp, P, sid, rank, N, G.Ps, G.ss, G.rs,
+                       head);
     GCHK(incl_sum(sc, head, incl, N, st));
     int nu = 0;
     GCHK(hipMemcpyAsync(&nu, incl + (N - 1), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -703,13 +786,21 @@ amm_status build_cells(Scratch& sc, const double4* P, const int* rank, int64_t N
     return AMM_OK;
 }
 
+template <typename T>
+hipError_t upload(Scratch& sc, const std::vector<T>& v, T*& out, hipStream_t st) {
+    hipError_t e = sc.get(out, v.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+}
+
 }  // namespace
 
 struct GraphBuild {
-    int64_t N = 0;
+    int n_sets = 0;
     int k = 0;
     amm_dtype dtype = AMM_F64;
-    amm_graph_info info{};
+    std::vector<int64_t> pt_off, node_off, edge_off;
+    std::vector<amm_graph_info> info;
     int* node_src = nullptr;
     int* infl_idx = nullptr;
     void* infl_w = nullptr;
@@ -724,122 +815,173 @@ struct GraphBuild {
 
 void graph_release(GraphBuild* g) { delete g; }
 
-amm_status graph_build(void* stream, const amm_graph_in& in, amm_graph_info* info_out, GraphBuild** out,
+amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_graph_info* info_out, GraphBuild** out,
                        std::string& err) {
     const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int64_t N = in.n_src;
-    const int k = in.k;
-    if (!in.src_xyz || N < 2 || N > (int64_t)INT32_MAX / 32 || k < 1 || k > kMaxK ||
-        (in.dtype != AMM_F32 && in.dtype != AMM_F64)) {
-        err = "graph: bad source pointer, size, k or dtype";
+    if (n_sets < 1 || n_sets > kMaxSets) {
+        err = "graph: bad number of point sets";
+        return AMM_ERR_INVALID_ARG;
+    }
+    const int k = in[0].k;
+    const amm_dtype dt = in[0].dtype;
+    std::vector<int64_t> off(n_sets + 1, 0);
+    for (int s = 0; s < n_sets; ++s) {
+        const amm_graph_in& g = in[s];
+        if (!g.src_xyz || g.n_src < 2 || g.k != k || k < 1 || k > kMaxK || g.dtype != dt ||
+            (dt != AMM_F32 && dt != AMM_F64)) {
+            err = "graph: bad source pointer, size, k or dtype (k and dtype must agree over the sets)";
+            return AMM_ERR_INVALID_ARG;
+        }
+        off[s + 1] = off[s] + g.n_src;
+    }
+    const int64_t N = off[n_sets];
+    if (N > (int64_t)INT32_MAX / 32) {
+        err = "graph: too many points";
         return AMM_ERR_INVALID_ARG;
     }
     Scratch sc;
-    double4* P = nullptr;
-    double* part = nullptr;
     const unsigned nb1 = nblk(N);
+    double4* P = nullptr;
+    int64_t* off_d = nullptr;
+    int* sid = nullptr;
+    double* stats = nullptr;
     GCHK(sc.get(P, N));
-    GCHK(sc.get(part, 10 * (size_t)nb1));
-    if (in.dtype == AMM_F64)
-        hipLaunchKernelGGL(k_g_load<double>, dim3(nb1), dim3(kGT), 0, st, (const double*)in.src_xyz, P, N, part);
-    else
-        hipLaunchKernelGGL(k_g_load<float>, dim3(nb1), dim3(kGT), 0, st, (const float*)in.src_xyz, P, N, part);
-    std::vector<double> hp(10 * (size_t)nb1);
-    GCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
-    GCHK(hipStreamSynchronize(st));
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, sum[3] = {0, 0, 0};
-    double bad = 0;
-    for (unsigned b = 0; b < nb1; ++b) {
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = std::min(lo[c], hp[10 * b + c]);
-            hi[c] = std::max(hi[c], hp[10 * b + 3 + c]);
-            sum[c] += hp[10 * b + 6 + c];
-        }
-        bad += hp[10 * b + 9];
+    GCHK(sc.get(sid, N));
+    GCHK(sc.get(stats, 15 * (size_t)n_sets));
+    GCHK(upload(sc, off, off_d, st));
+    for (int s = 0; s < n_sets; ++s) {
+        if (dt == AMM_F64)
+            hipLaunchKernelGGL(k_g_load<double>, dim3(nblk(in[s].n_src)), dim3(kGT), 0, st,
+                               (const double*)in[s].src_xyz, P + off[s], in[s].n_src);
+        else
+            hipLaunchKernelGGL(k_g_load<float>, dim3(nblk(in[s].n_src)), dim3(kGT), 0, st,
+                               (const float*)in[s].src_xyz, P + off[s], in[s].n_src);
     }
-    if (bad > 0) {
-        err = "graph: non-finite source coordinate";
-        return AMM_ERR_NONFINITE;
-    }
-    const double mean[3] = {sum[0] / (double)N, sum[1] / (double)N, sum[2] / (double)N};
-    hipLaunchKernelGGL(k_g_cov, dim3(nb1), dim3(kGT), 0, st, P, N, mean[0], mean[1], mean[2], part);
-    GCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * 6 * nb1, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_g_setid, dim3(nb1), dim3(kGT), 0, st, off_d, n_sets, N, sid);
+    hipLaunchKernelGGL(k_g_setstats, dim3(n_sets), dim3(kGT), 0, st, P, off_d, stats);
+    std::vector<double> hs(15 * (size_t)n_sets);
+    GCHK(hipMemcpyAsync(hs.data(), stats, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
     GCHK(hipStreamSynchronize(st));
-    double cs[6] = {0, 0, 0, 0, 0, 0};
-    for (unsigned b = 0; b < nb1; ++b)
-        for (int m = 0; m < 6; ++m) cs[m] += hp[6 * b + m];
-    const double C[3][3] = {{cs[0] / N, cs[1] / N, cs[2] / N},
-                            {cs[1] / N, cs[3] / N, cs[4] / N},
-                            {cs[2] / N, cs[4] / N, cs[5] / N}};
-    double ax[3];
-    sym3_top_eigvec(C, ax);
 
-    // order along the axis
+    // per set: axis, bounding box, the k-NN grid
+    std::vector<double> ax(6 * (size_t)n_sets);
+    std::vector<GridDims> gk(n_sets);
+    std::vector<double> lo3(3 * (size_t)n_sets), hi3(3 * (size_t)n_sets), diag(n_sets);
+    for (int s = 0; s < n_sets; ++s) {
+        const double* o = &hs[15 * (size_t)s];
+        for (int q = 0; q < 15; ++q)
+            if (!std::isfinite(o[q])) {
+                err = "graph: non-finite source coordinate";
+                return AMM_ERR_NONFINITE;
+            }
+        const double n = (double)in[s].n_src;
+        const double C[3][3] = {{o[9] / n, o[10] / n, o[11] / n},
+                                {o[10] / n, o[12] / n, o[13] / n},
+                                {o[11] / n, o[13] / n, o[14] / n}};
+        double a[3];
+        sym3_top_eigvec(C, a);
+        for (int q = 0; q < 3; ++q) {
+            ax[6 * s + q] = o[6 + q] / n;
+            ax[6 * s + 3 + q] = a[q];
+            lo3[3 * s + q] = o[q];
+            hi3[3 * s + q] = o[3 + q];
+        }
+        const double ex = o[3] - o[0], ey = o[4] - o[1], ez = o[5] - o[2];
+        if (!(std::max({ex, ey, ez}) > 0)) {
+            err = "graph: all source points of a set coincide";
+            return AMM_ERR_INVALID_ARG;
+        }
+        diag[s] = std::sqrt(ex * ex + ey * ey + ez * ez);
+        if (!grid_for(&lo3[3 * s], &hi3[3 * s], diag[s] / std::cbrt(n), gk[s])) {
+            err = "graph: grid too fine";
+            return AMM_ERR_INVALID_ARG;
+        }
+    }
+    double* ax_d = nullptr;
+    GCHK(upload(sc, ax, ax_d, st));
+
+    // order along each set's axis: by projection, then (stably) by set
     double *tk = nullptr, *tks = nullptr;
-    int *tv = nullptr, *order = nullptr, *rank = nullptr;
+    int *tv = nullptr, *o1 = nullptr, *s1 = nullptr, *s2 = nullptr, *order = nullptr, *rank = nullptr;
     GCHK(sc.get(tk, N));
     GCHK(sc.get(tks, N));
     GCHK(sc.get(tv, N));
+    GCHK(sc.get(o1, N));
+    GCHK(sc.get(s1, N));
+    GCHK(sc.get(s2, N));
     GCHK(sc.get(order, N));
     GCHK(sc.get(rank, N));
-    hipLaunchKernelGGL(k_g_project, dim3(nb1), dim3(kGT), 0, st, P, N, mean[0], mean[1], mean[2], ax[0], ax[1],
-                       ax[2], tk, tv);
-    GCHK(sort_pairs(sc, tk, tks, tv, order, N, st));
+    hipLaunchKernelGGL(k_g_project, dim3(nb1), dim3(kGT), 0, st, P, sid, ax_d, N, tk, tv);
+    GCHK(sort_pairs(sc, tk, tks, tv, o1, N, st));
+    hipLaunchKernelGGL(k_g_take, dim3(nb1), dim3(kGT), 0, st, o1, sid, N, s1);
+    int set_bits = 1;
+    while ((1 << set_bits) < n_sets) ++set_bits;
+    GCHK(sort_pairs(sc, s1, s2, o1, order, N, st, set_bits));
     hipLaunchKernelGGL(k_g_invert, dim3(nb1), dim3(kGT), 0, st, order, rank, N);
 
-    const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
-    const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
-                                  (hi[2] - lo[2]) * (hi[2] - lo[2]));
-    if (!(ext > 0)) {
-        err = "graph: all source points coincide";
-        return AMM_ERR_INVALID_ARG;
-    }
+    // host copies of uploaded bounds live until the function returns (the
+    // uploads are asynchronous)
+    std::vector<uint64_t> knn_bounds(n_sets + 1), edge_bounds(n_sets + 1);
 
-    // mean edge length of the 6-NN graph
-    double lbar = 0;
+    // mean edge length per set (6-NN graph)
+    std::vector<double> lbar(n_sets);
     {
-        const double h = diag / std::cbrt((double)N);
-        const GridDims g = grid_for(lo, hi, h);
+        GridDims* gk_d = nullptr;
+        GCHK(upload(sc, gk, gk_d, st));
         CellGrid G;
-        TRY_STATUS(build_cells(sc, P, nullptr, N, g, st, G, err));
+        TRY_STATUS(build_cells(sc, P, sid, nullptr, N, gk_d, st, G, err));
         const int64_t M = N * kKnn;
-        uint64_t *pk = nullptr, *pks = nullptr;
-        int *flag = nullptr, *incl = nullptr;
+        uint64_t *pk = nullptr, *pks = nullptr, *bnd = nullptr;
+        int* flag = nullptr;
+        int64_t* at = nullptr;
         double* lp = nullptr;
         GCHK(sc.get(pk, M));
         GCHK(sc.get(pks, M));
         GCHK(sc.get(flag, M));
-        GCHK(sc.get(incl, M));
-        GCHK(sc.get(lp, nblk(M)));
-        hipLaunchKernelGGL(k_g_knn, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.cp, G.ukey, G.ustart, G.nu, N, g, pk);
+        GCHK(sc.get(at, n_sets + 1));
+        GCHK(sc.get(lp, 2 * (size_t)n_sets));
+        for (int s = 0; s <= n_sets; ++s) knn_bounds[s] = (uint64_t)off[s] * (uint64_t)N;
+        GCHK(upload(sc, knn_bounds, bnd, st));
+        hipLaunchKernelGGL(k_g_knn, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.cp, G.ss, G.ukey, G.ustart, G.nu, N, gk_d,
+                           off_d, pk);
         GCHK(sort_keys(sc, pk, pks, M, st));
         hipLaunchKernelGGL(k_g_headflag, dim3(nblk(M)), dim3(kGT), 0, st, pks, M, flag);
-        GCHK(incl_sum(sc, flag, incl, M, st));
-        hipLaunchKernelGGL(k_g_edge_len, dim3(nblk(M)), dim3(kGT), 0, st, pks, flag, M, N, P, lp);
-        int ne = 0;
-        std::vector<double> hl(nblk(M));
-        GCHK(hipMemcpyAsync(&ne, incl + (M - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_g_bounds, dim3(nblk(n_sets + 1)), dim3(kGT), 0, st, pks, M, bnd, n_sets + 1, at);
+        hipLaunchKernelGGL(k_g_edge_len, dim3(n_sets), dim3(kGT), 0, st, pks, flag, at, N, P, lp);
+        std::vector<double> hl(2 * (size_t)n_sets);
         GCHK(hipMemcpyAsync(hl.data(), lp, sizeof(double) * hl.size(), hipMemcpyDeviceToHost, st));
         GCHK(hipStreamSynchronize(st));
-        double tot = 0;
-        for (double v : hl) tot += v;
-        lbar = ne > 0 ? tot / ne : 0.0;
+        for (int s = 0; s < n_sets; ++s) lbar[s] = hl[2 * s + 1] > 0 ? hl[2 * s] / hl[2 * s + 1] : 0.0;
     }
-    const double R = in.radius > 0 ? in.radius : (in.radius_factor > 0 ? in.radius_factor : 5.0) * lbar;
-    if (!(R > 0) || !std::isfinite(R)) {
-        err = "graph: radius is not positive";
-        return AMM_ERR_INVALID_ARG;
-    }
-    const double R2 = R * R;
 
-    // grid of cell size R (slightly enlarged, so that rounding in the cell
-    // index never hides a point within R from the 27 neighbour cells)
-    const GridDims g = grid_for(lo, hi, R * (1.0 + 1e-9));
+    // per set: R and the grid of cell size R (slightly enlarged, so that
+    // rounding in the cell index never hides a point within R from the 27
+    // neighbour cells)
+    std::vector<double> Rs(n_sets), R2s(n_sets);
+    std::vector<GridDims> gr(n_sets);
+    for (int s = 0; s < n_sets; ++s) {
+        const double R = in[s].radius > 0 ? in[s].radius
+                                          : (in[s].radius_factor > 0 ? in[s].radius_factor : 5.0) * lbar[s];
+        if (!(R > 0) || !std::isfinite(R)) {
+            err = "graph: radius is not positive";
+            return AMM_ERR_INVALID_ARG;
+        }
+        Rs[s] = R;
+        R2s[s] = R * R;
+        if (!grid_for(&lo3[3 * s], &hi3[3 * s], R * (1.0 + 1e-9), gr[s])) {
+            err = "graph: grid too fine for R";
+            return AMM_ERR_INVALID_ARG;
+        }
+    }
+    GridDims* gr_d = nullptr;
+    double* R2_d = nullptr;
+    GCHK(upload(sc, gr, gr_d, st));
+    GCHK(upload(sc, R2s, R2_d, st));
     CellGrid G;
-    TRY_STATUS(build_cells(sc, P, rank, N, g, st, G, err));
+    TRY_STATUS(build_cells(sc, P, sid, rank, N, gr_d, st, G, err));
     int2* nb = nullptr;
     GCHK(sc.get(nb, 27 * (size_t)G.nu));
-    hipLaunchKernelGGL(k_g_nbr, dim3(nblk(G.nu)), dim3(kGT), 0, st, G.ukey, G.ustart, G.nu, N, g, nb);
+    hipLaunchKernelGGL(k_g_nbr, dim3(nblk(G.nu)), dim3(kGT), 0, st, G.ukey, G.ustart, G.nu, N, gr_d, nb);
 
     // node selection in rounds
     int *state = nullptr, *remaining = nullptr;
@@ -852,7 +994,7 @@ amm_status graph_build(void* stream, const amm_graph_in& in, amm_graph_info* inf
         // a few rounds per read-back; extra rounds after the last decision do nothing
         for (int r = 0; r < 4; ++r) {
             GCHK(hipMemsetAsync(remaining, 0, sizeof(int), st));
-            hipLaunchKernelGGL(k_g_round, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.rs, G.us, nb, state, N, R2,
+            hipLaunchKernelGGL(k_g_round, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.rs, G.ss, G.us, nb, state, N, R2_d,
                                remaining);
             ++rounds;
         }
@@ -865,52 +1007,57 @@ amm_status graph_build(void* stream, const amm_graph_in& in, amm_graph_info* inf
         }
     }
 
-    // node ids in axis order
+    // node ids in axis order (global over the sets, then local)
     int *flag_r = nullptr, *pos_r = nullptr, *nid_r = nullptr, *nid_s = nullptr;
+    int64_t* node_off_d = nullptr;
     GCHK(sc.get(flag_r, N));
     GCHK(sc.get(pos_r, N));
     GCHK(sc.get(nid_r, N));
     GCHK(sc.get(nid_s, N));
+    GCHK(sc.get(node_off_d, n_sets + 1));
     hipLaunchKernelGGL(k_g_nodeflag, dim3(nb1), dim3(kGT), 0, st, G.rs, state, N, flag_r, pos_r);
     GCHK(incl_sum(sc, flag_r, nid_r, N, st));
-    int n_nodes = 0;
-    GCHK(hipMemcpyAsync(&n_nodes, nid_r + (N - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_g_setnodes, dim3(nblk(n_sets + 1)), dim3(kGT), 0, st, nid_r, flag_r, off_d, n_sets,
+                       node_off_d);
+    std::vector<int64_t> node_off(n_sets + 1);
+    GCHK(hipMemcpyAsync(node_off.data(), node_off_d, sizeof(int64_t) * (n_sets + 1), hipMemcpyDeviceToHost, st));
     GCHK(hipStreamSynchronize(st));
-    // inclusive sums -> ids: a node's id is the count before it
-    auto res = new GraphBuild();
-    std::unique_ptr<GraphBuild> keep(res);
-    res->N = N;
+    const int64_t n_nodes = node_off[n_sets];
+    auto res = std::make_unique<GraphBuild>();
+    res->n_sets = n_sets;
     res->k = k;
-    res->dtype = in.dtype;
-    GCHK(hipMalloc((void**)&res->node_src, sizeof(int) * std::max(n_nodes, 1)));
+    res->dtype = dt;
+    res->pt_off = off;
+    res->node_off = node_off;
+    int* nset = nullptr;
+    GCHK(sc.get(nset, std::max<int64_t>(n_nodes, 1)));
+    GCHK(hipMalloc((void**)&res->node_src, sizeof(int) * std::max<int64_t>(n_nodes, 1)));
     GCHK(hipMalloc((void**)&res->infl_idx, sizeof(int) * (size_t)N * k));
-    GCHK(hipMalloc(&res->infl_w, (in.dtype == AMM_F64 ? 8 : 4) * (size_t)N * k));
-    {
-        int* nid_excl = nullptr;
-        GCHK(sc.get(nid_excl, N));
-        hipLaunchKernelGGL(k_g_excl_from_incl, dim3(nb1), dim3(kGT), 0, st, nid_r, flag_r, N, nid_excl);
-        hipLaunchKernelGGL(k_g_nodeid, dim3(nb1), dim3(kGT), 0, st, flag_r, nid_excl, pos_r, G.cp, N, nid_s,
-                           res->node_src);
-    }
+    GCHK(hipMalloc(&res->infl_w, (dt == AMM_F64 ? 8 : 4) * (size_t)N * k));
+    hipLaunchKernelGGL(k_g_nodeid, dim3(nb1), dim3(kGT), 0, st, flag_r, nid_r, pos_r, G.cp, G.ss, off_d, N, nid_s,
+                       res->node_src, nset);
 
     // influence sets, weights, node pairs
     const int npair = k * (k - 1) / 2;
     const int64_t M = N * npair;
     uint64_t *pk = nullptr, *pks = nullptr;
-    int* stats = nullptr;
-    GCHK(sc.get(stats, 2));
-    GCHK(hipMemsetAsync(stats, 0, 2 * sizeof(int), st));
+    int* gst = nullptr;
+    GCHK(sc.get(gst, 2 * (size_t)n_sets));
+    GCHK(hipMemsetAsync(gst, 0, 2 * sizeof(int) * n_sets, st));
     GCHK(sc.get(pk, std::max<int64_t>(M, 1)));
     GCHK(sc.get(pks, std::max<int64_t>(M, 1)));
-    if (in.dtype == AMM_F64)
-        hipLaunchKernelGGL(k_g_influence<double>, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.us, nb, nid_s, G.cp, N,
-                           (int64_t)n_nodes, R2, k, res->infl_idx, (double*)res->infl_w, pk, stats);
+    if (dt == AMM_F64)
+        hipLaunchKernelGGL(k_g_influence<double>, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.ss, G.us, nb, nid_s, G.cp,
+                           node_off_d, R2_d, N, n_nodes, k, res->infl_idx, (double*)res->infl_w, pk, gst);
     else
-        hipLaunchKernelGGL(k_g_influence<float>, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.us, nb, nid_s, G.cp, N,
-                           (int64_t)n_nodes, R2, k, res->infl_idx, (float*)res->infl_w, pk, stats);
+        hipLaunchKernelGGL(k_g_influence<float>, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.ss, G.us, nb, nid_s, G.cp,
+                           node_off_d, R2_d, N, n_nodes, k, res->infl_idx, (float*)res->infl_w, pk, gst);
+    std::vector<int64_t> edge_off(n_sets + 1, 0);
     int n_edges = 0;
     if (M > 0) {
         int *flag = nullptr, *incl = nullptr;
+        uint64_t *ukey = nullptr, *bnd = nullptr;
+        int64_t* at = nullptr;
         GCHK(sc.get(flag, M));
         GCHK(sc.get(incl, M));
         GCHK(sort_keys(sc, pk, pks, M, st));
@@ -918,40 +1065,62 @@ amm_status graph_build(void* stream, const amm_graph_in& in, amm_graph_info* inf
         GCHK(incl_sum(sc, flag, incl, M, st));
         GCHK(hipMemcpyAsync(&n_edges, incl + (M - 1), sizeof(int), hipMemcpyDeviceToHost, st));
         GCHK(hipStreamSynchronize(st));
+        GCHK(sc.get(ukey, std::max(n_edges, 1)));
         GCHK(hipMalloc((void**)&res->edges, sizeof(int) * 2 * std::max(n_edges, 1)));
-        hipLaunchKernelGGL(k_g_edges, dim3(nblk(M)), dim3(kGT), 0, st, pks, flag, incl, M, (int64_t)n_nodes,
-                           res->edges);
+        hipLaunchKernelGGL(k_g_edges, dim3(nblk(M)), dim3(kGT), 0, st, pks, flag, incl, M, n_nodes, nset,
+                           node_off_d, ukey, res->edges);
+        for (int s = 0; s <= n_sets; ++s) edge_bounds[s] = (uint64_t)node_off[s] * (uint64_t)n_nodes;
+        GCHK(upload(sc, edge_bounds, bnd, st));
+        GCHK(sc.get(at, n_sets + 1));
+        hipLaunchKernelGGL(k_g_bounds, dim3(nblk(n_sets + 1)), dim3(kGT), 0, st, ukey, (int64_t)n_edges, bnd,
+                           n_sets + 1, at);
+        GCHK(hipMemcpyAsync(edge_off.data(), at, sizeof(int64_t) * (n_sets + 1), hipMemcpyDeviceToHost, st));
     } else {
         GCHK(hipMalloc((void**)&res->edges, sizeof(int) * 2));
     }
-    int hs[2] = {0, 0};
-    GCHK(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+    std::vector<int> hg(2 * (size_t)n_sets);
+    GCHK(hipMemcpyAsync(hg.data(), gst, sizeof(int) * hg.size(), hipMemcpyDeviceToHost, st));
     GCHK(hipStreamSynchronize(st));
     GCHK(hipGetLastError());
-    amm_graph_info& info = res->info;
-    info.n_nodes = n_nodes;
-    info.n_edges = n_edges;
-    info.radius = R;
-    info.mean_edge_len = lbar;
-    info.n_capped = hs[0];
-    info.max_influences = hs[1];
-    info.rounds = rounds;
-    if (info_out) *info_out = info;
-    *out = keep.release();
+    edge_off[n_sets] = n_edges;
+    res->edge_off = edge_off;
+    res->info.resize(n_sets);
+    for (int s = 0; s < n_sets; ++s) {
+        amm_graph_info& fo = res->info[s];
+        fo.n_nodes = node_off[s + 1] - node_off[s];
+        fo.n_edges = edge_off[s + 1] - edge_off[s];
+        fo.radius = Rs[s];
+        fo.mean_edge_len = lbar[s];
+        fo.n_capped = hg[2 * s];
+        fo.max_influences = hg[2 * s + 1];
+        fo.rounds = rounds;
+        if (info_out) info_out[s] = fo;
+    }
+    *out = res.release();
     return AMM_OK;
 }
 
-amm_status graph_copy(const GraphBuild* g, void* stream, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w,
-                      int32_t* edges, std::string& err) {
+amm_status graph_copy(const GraphBuild* g, void* stream, int set, int32_t* node_src_idx, int32_t* infl_idx,
+                      void* infl_w, int32_t* edges, std::string& err) {
     const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (set < 0 || set >= g->n_sets) {
+        err = "graph: set out of range";
+        return AMM_ERR_INVALID_ARG;
+    }
     const size_t ws = g->dtype == AMM_F64 ? 8 : 4;
-    if (node_src_idx)
-        GCHK(hipMemcpyAsync(node_src_idx, g->node_src, sizeof(int) * g->info.n_nodes, hipMemcpyDeviceToDevice, st));
+    const int64_t p0 = g->pt_off[set], np = g->pt_off[set + 1] - p0;
+    const int64_t n0 = g->node_off[set], nn = g->node_off[set + 1] - n0;
+    const int64_t e0 = g->edge_off[set], ne = g->edge_off[set + 1] - e0;
+    if (node_src_idx && nn)
+        GCHK(hipMemcpyAsync(node_src_idx, g->node_src + n0, sizeof(int) * nn, hipMemcpyDeviceToDevice, st));
     if (infl_idx)
-        GCHK(hipMemcpyAsync(infl_idx, g->infl_idx, sizeof(int) * (size_t)g->N * g->k, hipMemcpyDeviceToDevice, st));
-    if (infl_w) GCHK(hipMemcpyAsync(infl_w, g->infl_w, ws * (size_t)g->N * g->k, hipMemcpyDeviceToDevice, st));
-    if (edges && g->info.n_edges)
-        GCHK(hipMemcpyAsync(edges, g->edges, sizeof(int) * 2 * g->info.n_edges, hipMemcpyDeviceToDevice, st));
+        GCHK(hipMemcpyAsync(infl_idx, g->infl_idx + (size_t)p0 * g->k, sizeof(int) * (size_t)np * g->k,
+                            hipMemcpyDeviceToDevice, st));
+    if (infl_w)
+        GCHK(hipMemcpyAsync(infl_w, (char*)g->infl_w + ws * (size_t)p0 * g->k, ws * (size_t)np * g->k,
+                            hipMemcpyDeviceToDevice, st));
+    if (edges && ne)
+        GCHK(hipMemcpyAsync(edges, g->edges + 2 * e0, sizeof(int) * 2 * ne, hipMemcpyDeviceToDevice, st));
     return AMM_OK;
 }
 

@@ -139,10 +139,10 @@ void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out);
 // amm_build_graph and amm_graph_copy.  stream is a hipStream_t.
 struct GraphBuild;
 void graph_release(GraphBuild* g);
-amm_status graph_build(void* stream, const amm_graph_in& in, amm_graph_info* info, GraphBuild** out,
+amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_graph_info* info, GraphBuild** out,
                        std::string& err);
-amm_status graph_copy(const GraphBuild* g, void* stream, int32_t* node_src_idx, int32_t* infl_idx, void* infl_w,
-                      int32_t* edges, std::string& err);
+amm_status graph_copy(const GraphBuild* g, void* stream, int set, int32_t* node_src_idx, int32_t* infl_idx,
+                      void* infl_w, int32_t* edges, std::string& err);
 constexpr int kMaxK = 8;
 constexpr int kCoarseMaxAgg = 32;    // aggregates per pair (coarse order <= 128)
 constexpr int kAggMinShift = 6;      // at least 64 nodes (4 node tiles) per aggregate

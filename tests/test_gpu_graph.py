@@ -144,3 +144,27 @@ def test_registration_on_a_built_graph():
     assert st["iters"] == res["total"]
     assert st["energy"] == pytest.approx(res["E"], rel=1e-5)
     assert math.sqrt(((v - res["vhat"]) ** 2).sum(1).mean()) < 1e-5
+
+
+def test_graphs_of_many_sets_in_one_build_equal_single_builds():
+    """Several point sets of different sizes and densities built in one
+    pass give, set by set, exactly the single-set builds."""
+    _announce("test_graphs_of_many_sets_in_one_build_equal_single_builds")
+    sets = [synth.torus_pair(1000 + 11 * b, n_src=n, n_tgt=10, n_nodes=20, k=4, e=6).src * sc
+            for b, (n, sc) in enumerate(((700, 1.0), (1500, 0.5), (2600, 2.0), (300, 1.0)))]
+    srcs = [torch.tensor(V, device="cuda:0") for V in sets]
+    h = _handle()
+    try:
+        many = amm.build_graphs(h, srcs, 4)
+        torch.cuda.synchronize()
+        single = [amm.build_graph(h, sp, 4) for sp in srcs]
+        torch.cuda.synchronize()
+    finally:
+        amm.amm_destroy(h)
+    for (im, *tm), (is_, *ts) in zip(many, single):
+        for key in ("n_nodes", "n_edges", "radius", "mean_edge_len", "n_capped", "max_influences"):
+            assert im[key] == is_[key], key
+        for a, b in zip(tm, ts):
+            assert torch.equal(a, b)
+    # and set 2 against the oracle
+    _check_against_oracle(sets[2], 4, many[2])
