@@ -8,10 +8,11 @@
 // set of the graph "distance < R" under this order, which is unique: a
 // point's decision depends only on the decisions of the earlier points
 // within R.  It is computed here in rounds over all points of all sets: a
-// point becomes covered as soon as an earlier neighbour is a node, and a
-// node as soon as all its earlier neighbours are covered.  Each round
-// decides at least the earliest undecided point of every set, and the
-// result equals the sequential pass exactly.
+// point becomes covered as soon as an earlier neighbour is a node (the new
+// node marks its later neighbours), and a node as soon as all its earlier
+// neighbours are covered.  Each round decides at least the earliest
+// undecided point of every set, and the result equals the sequential pass
+// exactly.
 //
 // Neighbour queries use a uniform grid per set, stored as points sorted by
 // (set, cell) keys (a stable radix sort), with each occupied cell's 27
@@ -100,6 +101,14 @@ struct GridDims {
     double x0, y0, z0, h;
     int64_t nx, ny, nz;
 };
+
+// Block b of G -> a block index such that each of the 8 XCDs (blocks are
+// dealt round-robin over them) covers one contiguous range.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int per = G >> 3, rem = G & 7;
+    const int x = b & 7, q = b >> 3;
+    return x * per + min(x, rem) + q;
+}
 
 // ---------------------------------------------------------------- per-set statistics
 
@@ -441,38 +450,73 @@ __global__ void __launch_bounds__(kGT) k_g_edge_len(const uint64_t* __restrict__
 // One round over the undecided points (cell order).  state: 0 undecided,
 // 1 node, 2 covered.  Reads of other points' states may see the value of
 // the previous round or of this one; both are final or undecided, so a
-// decision taken is always the sequential pass's.
+// decision taken is always the sequential pass's.  A new node marks the
+// later points within R of it covered (`cov`) at once, so coverage needs
+// no scan; and a point remembers the earlier neighbour that kept it
+// undecided (`wait`) and skips its scan while that one is undecided (it
+// cannot become a node before).  No ordering across XCDs is needed inside
+// a round (every state seen is either final or undecided), so the state
+// accesses are workgroup-scope atomics that stay in the caches; with blocks
+// on contiguous ranges per XCD most neighbours' updates still show within
+// the round, and a launch boundary shows all of them to the next.
 __global__ void __launch_bounds__(kGT) k_g_round(const double4* __restrict__ Ps, const int* __restrict__ rs,
                                                  const int* __restrict__ ss, const int* __restrict__ us,
-                                                 const int2* __restrict__ nb, int* state, int64_t N,
-                                                 const double* __restrict__ R2s, int* __restrict__ remaining) {
-    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
+                                                 const int2* __restrict__ nb, int* state, int* cov,
+                                                 int* __restrict__ wait, int64_t N, const double* __restrict__ R2s,
+                                                 int* __restrict__ remaining) {
+    // blocks take contiguous ranges of the cell order per XCD, so that most
+    // neighbours' states sit in the same L2
+    const int64_t s = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGT + threadIdx.x;
     bool undecided = false;
-    if (s < N && __hip_atomic_load(&state[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    bool open = s < N && __hip_atomic_load(&state[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0;
+    if (open && __hip_atomic_load(&cov[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+        __hip_atomic_store(&state[s], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        open = false;
+    }
+    if (open) {
+        const int wt = wait[s];
+        if (wt >= 0 && __hip_atomic_load(&state[wt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+            undecided = true;
+            open = false;
+        }
+    }
+    if (open) {
         const double4 q = Ps[s];
         const int rq = rs[s];
         const double R2 = R2s[ss[s]];
         const int2* cells = nb + 27 * (size_t)us[s];
-        bool covered = false, pending = false;
+        // every candidate's rank, position and state are loaded up front (no
+        // load waits on an earlier test), so the loads of consecutive
+        // candidates are in flight together
+        bool covered = false;
+        int pending = -1;
         for (int o = 0; o < 27 && !covered; ++o) {
             const int2 r = cells[o];
+#pragma unroll 8
             for (int t = r.x; t < r.y; ++t) {
-                if (rs[t] >= rq) continue;
-                if (!(gd2(Ps[t], q) < R2)) continue;
-                const int st = __hip_atomic_load(&state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (st == 1) {
-                    covered = true;
-                    break;
+                const int rt = rs[t];
+                const double4 pt = Ps[t];
+                const int st = __hip_atomic_load(&state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (rt < rq && gd2(pt, q) < R2) {
+                    covered = covered || st == 1;
+                    if (st == 0 && pending < 0) pending = t;
                 }
-                if (st == 0) pending = true;
             }
         }
-        if (covered)
-            __hip_atomic_store(&state[s], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else if (!pending)
-            __hip_atomic_store(&state[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
+        if (covered) {
+            __hip_atomic_store(&state[s], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else if (pending < 0) {
+            __hip_atomic_store(&state[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int o = 0; o < 27; ++o) {
+                const int2 r = cells[o];
+                for (int t = r.x; t < r.y; ++t)
+                    if (rs[t] > rq && gd2(Ps[t], q) < R2)
+                        __hip_atomic_store(&cov[t], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        } else {
+            wait[s] = pending;
             undecided = true;
+        }
     }
     const int cnt = __syncthreads_count(undecided);
     if (threadIdx.x == 0 && cnt) atomicAdd(remaining, cnt);
@@ -984,18 +1028,22 @@ amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_gra
     hipLaunchKernelGGL(k_g_nbr, dim3(nblk(G.nu)), dim3(kGT), 0, st, G.ukey, G.ustart, G.nu, N, gr_d, nb);
 
     // node selection in rounds
-    int *state = nullptr, *remaining = nullptr;
+    int *state = nullptr, *remaining = nullptr, *wait = nullptr, *cov = nullptr;
     GCHK(sc.get(state, N));
+    GCHK(sc.get(wait, N));
+    GCHK(sc.get(cov, N));
+    GCHK(hipMemsetAsync(cov, 0, sizeof(int) * N, st));
     GCHK(sc.get(remaining, 1));
     GCHK(hipMemsetAsync(state, 0, sizeof(int) * N, st));
+    GCHK(hipMemsetAsync(wait, 0xff, sizeof(int) * N, st));   // -1: nothing to wait for
     int rounds = 0;
     for (;;) {
         int left = 0;
         // a few rounds per read-back; extra rounds after the last decision do nothing
         for (int r = 0; r < 4; ++r) {
             GCHK(hipMemsetAsync(remaining, 0, sizeof(int), st));
-            hipLaunchKernelGGL(k_g_round, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.rs, G.ss, G.us, nb, state, N, R2_d,
-                               remaining);
+            hipLaunchKernelGGL(k_g_round, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.rs, G.ss, G.us, nb, state, cov, wait,
+                               N, R2_d, remaining);
             ++rounds;
         }
         GCHK(hipMemcpyAsync(&left, remaining, sizeof(int), hipMemcpyDeviceToHost, st));
