@@ -106,12 +106,13 @@ def load_pair(name):
     return pair
 
 
-def gpu_problem(amm, torch, pair):
+def gpu_problem(amm, torch, pair, dtype=None):
     dev = "cuda:0"
+    dtype = dtype or torch.float64
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    return amm.make_problem(t(pair.src, torch.float64), t(pair.tgt, torch.float64),
+    return amm.make_problem(t(pair.src, dtype), t(pair.tgt, dtype),
                             t(pair.node_idx, torch.int32), t(pair.infl_idx, torch.int32),
-                            t(pair.infl_w, torch.float64), t(pair.edges, torch.int32),
+                            t(pair.infl_w, dtype), t(pair.edges, torch.int32),
                             pair.mean_edge_len)
 
 
@@ -425,6 +426,93 @@ def variants_run(amm, torch, h, pair, steps, aa_m):
     return out
 
 
+def torus_end_to_end(amm, torch, with_cpu):
+    """The 2,000-point torus workload, plain FP64 (30 MM iterations,
+    Anderson m = 5): whole-solve wall time on the GPU (median of 5, the
+    problem already uploaded), and with the CPU leg the oracle's own solve
+    of the same workload, with both final energies."""
+    from paper_2206_03410_amd import synth
+    pair = synth.make_workload("torus2k")
+    h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        amm.amm_set_problems(h, [gpu_problem(amm, torch, pair)])
+        X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float64, device="cuda:0")
+        prm = amm.amm_params_default(aa_m=5, max_total_iters=30, precision=amm.AMM_FP64_PLAIN)
+        amm.amm_solve(h, prm, X)
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = amm.amm_solve(h, prm, X)[0]
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+    finally:
+        amm.amm_destroy(h)
+    out = {"workload": "torus2k: 2,000 source / 2,100 target points, 80 nodes, k=4, 30 MM iterations, m=5, FP64",
+           "gpu_s": float(np.median(ts)), "gpu_iters": st["iters"], "gpu_energy": st["energy"]}
+    if with_cpu:
+        from oracle import amm_oracle as O
+        t = time.perf_counter()
+        res = O.solve(O.from_pair(pair), O.Params(aa_m=5, max_total_iters=30))
+        out["cpu_oracle_s"] = time.perf_counter() - t
+        out["cpu_oracle_iters"] = res["total"]
+        out["cpu_oracle_energy"] = res["E"]
+    return out
+
+
+def gradient_timing(amm, torch, with_cpu):
+    """The 100,000-point gradient workload (2,000 nodes, k = 4): energy and
+    adjoint with respect to X and the source points at X = I + delta, per
+    call on the GPU (FP32 and FP64, median of 10); with the CPU leg the
+    oracle's analytic gradient at the same point, its closest points from
+    scipy's exact k-d tree."""
+    from paper_2206_03410_amd import synth
+    from scipy.spatial import cKDTree
+    pair = synth.make_workload("grad100k")
+    Xn = synth.perturbed_transforms(pair.n_nodes, 5005, 0.01, 0.001)
+    out = {"workload": "grad100k: 100,000 points, 2,000 nodes, k=4, gradient w.r.t. X (12 per node) and "
+                       "the source points, Sec. 3.3.3 start values of nu and Eq. 26 weights"}
+    tree = cKDTree(pair.tgt)
+
+    def nn(q, _tgt):
+        d, i = tree.query(q, k=2)
+        return i[:, 0].astype(np.int64), d[:, 0] ** 2, d[:, 1] ** 2
+    # the scalars are the solver's start values, computed here with scipy's
+    # exact closest points (the same definitions the solver applies)
+    d0 = nn(pair.src, None)[1]
+    l = pair.mean_edge_len
+    nu_a = max(float(np.sqrt(np.median(d0))), l / np.sqrt(3.0))
+    nu_r = 3.0 * l
+    prm = amm.amm_params_default()
+    alpha = prm.k_alpha * pair.n_src / pair.n_edges * (nu_r / nu_a) ** 2      # Eq. 26
+    beta = prm.k_beta * pair.n_src / pair.n_nodes / (2.0 * nu_a * nu_a)
+    for dt, name in ((torch.float32, "gpu_fp32_ms"), (torch.float64, "gpu_fp64_ms")):
+        h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
+        try:
+            amm.amm_set_problems(h, [gpu_problem(amm, torch, pair, dt)])
+            X = torch.as_tensor(Xn, dtype=dt, device="cuda:0")
+            V = torch.as_tensor(pair.src, dtype=dt, device="cuda:0")
+            gX, gV = torch.empty_like(X), torch.empty_like(V)
+            amm.amm_energy_grad(h, X, V, nu_a, nu_r, alpha, beta, gX, gV)
+            ts = []
+            for _ in range(10):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                amm.amm_energy_grad(h, X, V, nu_a, nu_r, alpha, beta, gX, gV)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            out[name] = 1e3 * float(np.median(ts))
+        finally:
+            amm.amm_destroy(h)
+    if with_cpu:
+        from oracle import amm_oracle as O
+        prob = O.from_pair(pair)
+        t = time.perf_counter()
+        O.energy_grad(prob, Xn, nu_a, nu_r, alpha, beta, ev=O.evaluate(prob, Xn, nu_a, nu_r, alpha, beta, nn=nn))
+        out["cpu_oracle_ms"] = 1e3 * (time.perf_counter() - t)
+    return out
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling the HBM traffic
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run: each of the 5
@@ -569,6 +657,11 @@ def main():
         out["batched"] = batched_run(amm, torch, args.batched, 5)
     if args.sequence:
         out["tracking"] = sequence_run(amm, torch, args.sequence)
+    out["torus_end_to_end"] = torus_end_to_end(amm, torch, not args.no_cpu)
+    out["gradient"] = gradient_timing(amm, torch, not args.no_cpu)
+    log(f"[bench] torus2k FP64 end to end {out['torus_end_to_end']['gpu_s'] * 1e3:.1f} ms on the GPU; "
+        f"gradient at 100k points {out['gradient']['gpu_fp32_ms']:.2f} ms FP32, "
+        f"{out['gradient']['gpu_fp64_ms']:.2f} ms FP64")
     if not args.no_cpu:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(pair)

@@ -31,24 +31,26 @@ def _kdtree_nn(tgt):
     return nn
 
 
-def test_sh200k_step_sampled_against_oracle():
-    """One float32 + refinement MM step on the 200,000-point workload at
-    X = I + delta: energy within 1e-5 relative of the oracle's FP64 energy;
-    closest points of 2,000 sampled queries equal the oracle's brute force
+@pytest.mark.parametrize("case", ["sh50k", "sh200k"])
+def test_step_sampled_against_oracle(case):
+    """One float32 + refinement MM step on the 50,000-point (k = 4) and
+    200,000-point (k = 6) workloads at X = I + delta: energy within 1e-5
+    relative of the oracle's FP64 energy; closest points of 2,000 sampled queries equal the oracle's brute force
     on the library's own warped points wherever the best and second-best
     distances differ by more than 1e-6 relative; the deformed points of the
     surrogate minimizer within 1e-4 (bounding-box diagonal units) RMS of the
     oracle's sparse-LU minimizer."""
-    _announce("test_sh200k_step_sampled_against_oracle")
-    pair = synth.make_workload("sh200k")
+    _announce(f"test_step_sampled_against_oracle {case}")
+    pair = synth.make_workload(case)
     pr = rounded(pair, np.float32)
     prob = O.from_pair(pr)
     nn = _kdtree_nn(prob.tgt)
-    p = O.Params(aa_m=6)
+    p = O.Params()
     _, d2i, _ = nn(prob.src, prob.tgt)
     nu_a, _, nu_r = O.initial_nu(prob, p, d2i)
     alpha, beta = O.term_weights(prob, p, nu_a, nu_r)
-    X = synth.perturbed_transforms(prob.n_nodes, 7007, 0.01, 0.001).astype(np.float32).astype(np.float64)
+    seed = 7007 if case == "sh200k" else 7017
+    X = synth.perturbed_transforms(prob.n_nodes, seed, 0.01, 0.001).astype(np.float32).astype(np.float64)
     n, N = prob.n_nodes, prob.n_src
     with Session(pr, torch.float32) as s:
         dev = "cuda:0"
