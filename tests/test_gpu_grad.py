@@ -180,7 +180,17 @@ def test_gradient_grad100k_at_converged_transforms():
     accumulation errors scale with the parts: the bound is 1e-4 of the sum of
     the parts' norms (each part from the oracle with the other weights set to
     zero; the gradient is linear in alpha and beta).  dE/dV has no such
-    cancellation and keeps the plain normwise 1e-4."""
+    cancellation and keeps the plain normwise 1e-4.
+
+    At X* many source points sit within ~1e-3 of the target, so a point's
+    best and second-best targets can be closer than float32 warping resolves
+    (warped coordinates carry ~1e-7 absolute error).  There either
+    correspondence is a valid float32 result and the point's term differs
+    at O(1).  A float32 warped point is within delta = (k + 2) 2^-24 max|v|
+    of the FP64 one, so the two searches can only disagree where the
+    oracle's best and second-best distances are within 2 delta: such points
+    (a few dozen in 100,000) are left out of the dE/dV comparison, and the
+    nodes they influence out of the dE/dX comparison."""
     _announce("test_gradient_grad100k_at_converged_transforms")
     pair = synth.make_workload("grad100k")
     pr = rounded(pair, np.float32)
@@ -200,10 +210,20 @@ def test_gradient_grad100k_at_converged_transforms():
     g_reg = O.energy_grad(prob, Xs, nu_a, nu_r, alpha, 0.0, src=pr.src, ev=ev)[0] - g_align
     g_rot = O.energy_grad(prob, Xs, nu_a, nu_r, 0.0, beta, src=pr.src, ev=ev)[0] - g_align
     scale = np.linalg.norm(g_align) + np.linalg.norm(g_reg) + np.linalg.norm(g_rot)
-    ex = np.linalg.norm(gX - gXo) / scale
-    evv = np.linalg.norm(gV - gVo) / np.linalg.norm(gVo)
+    # correspondences float32 cannot resolve (see above)
+    vh = O.warp(prob, Xs)
+    _, d1, d2 = nn(vh, prob.tgt)
+    delta = (pr.infl_idx.shape[1] + 2) * 2.0 ** -24 * np.abs(vh).max()
+    amb = np.sqrt(d2) - np.sqrt(d1) <= 2 * delta
+    touched = np.unique(pr.infl_idx[amb][pr.infl_idx[amb] >= 0])
+    keep_n = np.ones(prob.n_nodes, bool)
+    keep_n[touched] = False
+    ex = np.linalg.norm((gX - gXo)[keep_n]) / scale
+    evv = np.linalg.norm((gV - gVo)[~amb]) / np.linalg.norm(gVo[~amb])
     print(f"[grad at X*] iters {st['iters']} converged {st['converged']} E {E} vs {ev.E} "
           f"|gX| {np.linalg.norm(gXo):.4e} parts {scale:.4e} err/parts {ex:.3e}  "
-          f"|gV| {np.linalg.norm(gVo):.4e} rel {evv:.3e}", file=sys.stderr, flush=True)
+          f"|gV| {np.linalg.norm(gVo):.4e} rel {evv:.3e}; unresolved points {amb.sum()}, "
+          f"nodes left out {len(touched)}", file=sys.stderr, flush=True)
+    assert amb.sum() <= 1e-3 * prob.n_src
     assert E == pytest.approx(ev.E, rel=1e-5)
     assert ex <= 1e-4 and evv <= 1e-4
