@@ -41,11 +41,10 @@ namespace {
 constexpr int kCgThreads = 16 * kNodeTile;
 constexpr int kSlotCap = 8;   // coarse aggregates per tile whose A_c^{-1} rows are staged in LDS
 
+// wave sums land in lane 63 (DPP reduction)
 template <typename T>
 __device__ __forceinline__ T wsum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return wave_total63(v);
 }
 
 // u = D_l^{-1} r for one node (r, u: [4][3]; Di row-major 4x4)
@@ -184,7 +183,7 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
         }
 #pragma unroll
         for (int m = 0; m < 12; ++m) v[m] = wsum(v[m]);
-        if ((tid & 63) == 0)
+        if ((tid & 63) == 63)
 #pragma unroll
             for (int m = 0; m < 12; ++m) wred[tid >> 6][m] = v[m];
     }
@@ -396,8 +395,7 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
                     acc = fma(rw[4 * bq + 3], gcur[bq][9 + c], acc);
                 }
             }
-            acc += __shfl_xor(acc, 1, 4);
-            acc += __shfl_xor(acc, 2, 4);
+            acc = quad_sum(acc);
             if (part == 0) cco[ag][m] = acc;
         }
         __syncthreads();
@@ -479,9 +477,7 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
         block(l, rn, a.Dinv + 16 * (size_t)l, kv, rel);
     }
 #pragma unroll
-    for (int m = 0; m < 12; ++m)
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) y[m] += __shfl_xor(y[m], o, 16);
+    for (int m = 0; m < 12; ++m) y[m] = row_sum(y[m]);
     if (lane == 0)
 #pragma unroll
         for (int m = 0; m < 12; ++m) ys[row][m] = y[m];
@@ -544,7 +540,7 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
     if (START)
 #pragma unroll
         for (int c = 0; c < 3; ++c) bn[c] = wsum(bn[c]);
-    if ((tid & 63) == 0) {
+    if ((tid & 63) == 63) {
 #pragma unroll
         for (int m = 0; m < kCgPart; ++m) wp[tid >> 6][m] = pc[m];
         if (START)

@@ -54,6 +54,47 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Cross-lane moves by DPP (a modifier of ordinary VALU moves: no LDS round
+// trip, unlike the permutes behind __shfl_xor).  CTRL: 0xB1 quad_perm
+// [1,0,3,2], 0x4E quad_perm [2,3,0,1], 0x141 row_half_mirror, 0x140
+// row_mirror, 0x142 row_bcast:15, 0x143 row_bcast:31.  Rows outside RMASK
+// (and lanes without a source) receive 0.
+template <int CTRL, int RMASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RMASK, 0xf, false));
+}
+template <int CTRL, int RMASK = 0xf>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, RMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RMASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over each aligned group of 4 lanes, in all 4 (fixed order).
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {
+    v += dpp_mov<0xB1>(v);
+    return v + dpp_mov<0x4E>(v);
+}
+
+// Sum over each row of 16 lanes, in all 16 (fixed order per lane).
+template <typename T>
+__device__ __forceinline__ T row_sum(T v) {
+    v = quad_sum(v);
+    v += dpp_mov<0x141>(v);
+    return v + dpp_mov<0x140>(v);
+}
+
+// Sum over the 64 lanes of a wave, valid in lane 63 (fixed order).  Every
+// lane of the wave must be active.
+template <typename T>
+__device__ __forceinline__ T wave_total63(T v) {
+    v = row_sum(v);
+    v += dpp_mov<0x142, 0xa>(v);
+    return v + dpp_mov<0x143, 0xc>(v);
+}
+
 // Inverse of a symmetric positive definite 4x4 block through its Cholesky
 // factor, fully unrolled.  Returns false on a non-positive pivot, and then
 // writes the inverse of the diagonal instead.
