@@ -47,12 +47,6 @@ __device__ __forceinline__ T block_max(T v, T* sh) {
     return r;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // Cross-lane moves by DPP (a modifier of ordinary VALU moves: no LDS round
 // trip, unlike the permutes behind __shfl_xor).  CTRL: 0xB1 quad_perm
@@ -93,6 +87,23 @@ __device__ __forceinline__ T wave_total63(T v) {
     v = row_sum(v);
     v += dpp_mov<0x142, 0xa>(v);
     return v + dpp_mov<0x143, 0xc>(v);
+}
+
+__device__ __forceinline__ float lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave, in every lane (fixed order).  Every lane
+// of the wave must be active.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    return lane63(wave_total63(v));
 }
 
 // Inverse of a symmetric positive definite 4x4 block through its Cholesky
