@@ -192,6 +192,10 @@ struct Dev {
     int4* aggs;
     int* tile_agg_ptr;
     int* tile_agg;
+    int* tile_cols;
+    int* tile_ncols;
+    int* tile_rowl;
+    uint16_t* K_lcol;
     PairInfo* info;
     PairDyn* dyn;        // slot of dyn_ring used by the next launches
     PairDyn* dyn_ring;   // [kDynRing][P]
@@ -228,6 +232,10 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(v.aggs, (size_t)L.nagg);
     c.take(v.tile_agg_ptr, nnd + 1);
     c.take(v.tile_agg, L.tile_agg.size());
+    c.take(v.tile_cols, L.tile_cols.size());
+    c.take(v.tile_ncols, L.tile_ncols.size());
+    c.take(v.tile_rowl, L.tile_rowl.size());
+    c.take(v.K_lcol, L.K_lcol.size());
     c.take(v.info, L.P);
     c.take(v.dyn_ring, (size_t)kDynRing * L.P);
     v.dyn = v.dyn_ring;
@@ -442,13 +450,8 @@ amm_status push_dyn(amm_handle* h) {
     const int P = h->L.P;
     const int slot = (h->dyn_slot + 1) % kDynRing;
     PairDyn* ds = h->v.dyn_ring + (size_t)slot * P;
-    for (int b = 0; b < P; b += kDynPerLaunch) {
-        DynPack pk;
-        pk.n = std::min(kDynPerLaunch, P - b);
-        std::memcpy(pk.d, h->dyn.data() + b, sizeof(PairDyn) * pk.n);
-        pk.dst = ds + b;
-        launch_dyn_set(pk, h->stream);
-    }
+    for (int b = 0; b < P; b += kDynPerLaunch)
+        launch_dyn_set(h->dyn.data() + b, std::min(kDynPerLaunch, P - b), ds + b, h->stream);
     HIPC(hipGetLastError());
     h->dyn_slot = slot;
     h->v.dyn = ds;
@@ -612,6 +615,10 @@ CgArgs<T> cg_args(amm_handle* h, const T* b, const T* bnorm, double rtol) {
     a.node_rel = statics<T>(h).node_rel;
     a.tile_agg_ptr = h->v.tile_agg_ptr;
     a.tile_agg = h->v.tile_agg;
+    a.tile_cols = h->v.tile_cols;
+    a.tile_ncols = h->v.tile_ncols;
+    a.tile_rowl = h->v.tile_rowl;
+    a.K_lcol = h->v.K_lcol;
     a.prog = h->prog_dev;
     return a;
 }
@@ -1494,6 +1501,10 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up(h, reinterpret_cast<int32_t*>(v.aggs), Lr.aggs));
     TRY(up(h, v.tile_agg_ptr, Lr.tile_agg_ptr));
     TRY(up(h, v.tile_agg, Lr.tile_agg));
+    TRY(up(h, v.tile_cols, Lr.tile_cols));
+    TRY(up(h, v.tile_ncols, Lr.tile_ncols));
+    TRY(up(h, v.tile_rowl, Lr.tile_rowl));
+    TRY(up(h, v.K_lcol, Lr.K_lcol));
     h->has_problem = true;
     return AMM_OK;
 }

@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
     // rows read together fall in different LDS banks)
     __shared__ T ainv_s[COARSE && kEarly ? 4 * kSlotCap : 1][NCM + 1];
     __shared__ int tl[COARSE ? kCoarseMaxAgg : 1];          // this tile's aggregates
+    __shared__ T us[START ? 1 : kTileColCap][12];              // u' of the tile's column nodes
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int4 td = a.nd_tiles[tile];
@@ -206,12 +207,56 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
         }
     }
     // Issued after the loads the scalars need (a wave waits for its loads in
-    // issue order): the first column block of this lane, its K block and the
-    // previous step's vectors of its node, consumed once the scalars are known
+    // issue order).  A step forms u' of each distinct column node of the
+    // tile once, in LDS (at most two tasks per thread: node e / 3, column
+    // e % 3): here the previous step's r, w, s of those columns, the nodes'
+    // diagonal inverses and positions, and this lane's first two K blocks
+    // with their local column indices.  A tile with more column nodes than
+    // fit recomputes u' for every block instead.
+    static_assert(2 * kCgThreads >= 3 * kTileColCap, "two shared-u' tasks per thread");
+    bool shr = false;
+    int nct = 0, hl[2] = {0, 0}, slc[2] = {0, 0}, rowl = 0;
+    T h_r[2][4], h_w[2][4], h_s[2][4], h_d[2][16], sk[2][16];
+    V h_rel[2] = {};
+    if (!START) {
+        nct = a.tile_ncols[tile];
+        shr = nct <= kTileColCap;
+    }
+    if (!START && shr) {
+        rowl = a.tile_rowl[(size_t)tile * kNodeTile + row];
+#pragma unroll
+        for (int k2 = 0; k2 < 2; ++k2) {
+            const int e = tid + kCgThreads * k2;
+            if (e < 3 * nct) {
+                const int li = e / 3, c = e - 3 * li;
+                const int l = a.tile_cols[(size_t)tile * kTileColCap + li];
+                hl[k2] = l;
+                const size_t ol = 12 * (size_t)l + c;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    h_r[k2][k] = a.r[par][ol + 3 * k];
+                    h_w[k2][k] = a.w[par][ol + 3 * k];
+                    h_s[k2][k] = a.s[par][ol + 3 * k];
+                }
+#pragma unroll
+                for (int m = 0; m < 16; ++m) h_d[k2][m] = a.Dinv[16 * (size_t)l + m];
+                if (COARSE) h_rel[k2] = a.node_rel[l];
+            }
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < 2; ++k2) {
+            const int pos = kb + 16 * k2;
+            if (pos < ke) {
+                slc[k2] = a.K_lcol[pos];
+#pragma unroll
+                for (int m = 0; m < 16; ++m) sk[k2][m] = a.Kval[16 * (size_t)pos + m];
+            }
+        }
+    }
     int l0 = -1;
     T f_r[12], f_w[12], f_s[12], f_d[16], f_k[16];
     V f_rel{};
-    if (kEarly && !START && kb < ke) {
+    if (kEarly && !START && !shr && kb < ke) {
         l0 = a.K_col[kb];
         const size_t ol = 12 * (size_t)l0;
 #pragma unroll
@@ -401,6 +446,42 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
         __syncthreads();
     }
 
+    // ---- u' of the tile's column nodes, once each (the arithmetic of the
+    // per-block recomputation below, so both give identical values)
+    if (!START && shr) {
+#pragma unroll
+        for (int k2 = 0; k2 < 2; ++k2) {
+            const int e = tid + kCgThreads * k2;
+            if (e < 3 * nct) {
+                const int li = e / 3, c = e - 3 * li;
+                const T alc = pick3(al, c), bec = pick3(be, c);
+                const bool ac = pick3(act, c);
+                T rn[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) rn[k] = new_r(h_r[k2][k], h_w[k2][k], h_s[k2][k], alc, bec, ac, first);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    T v = h_d[k2][4 * q] * rn[0];
+                    v = fma(h_d[k2][4 * q + 1], rn[1], v);
+                    v = fma(h_d[k2][4 * q + 2], rn[2], v);
+                    v = fma(h_d[k2][4 * q + 3], rn[3], v);
+                    if (COARSE) {
+                        const T* cc = cco[(hl[k2] - (int)pi.node_off) >> pi.agg_shift];
+                        if (q < 3) {
+                            v += cc[3 * q + c];
+                        } else {
+                            T t = fma(h_rel[k2].x, cc[c], cc[9 + c]);
+                            t = fma(h_rel[k2].y, cc[3 + c], t);
+                            t = fma(h_rel[k2].z, cc[6 + c], t);
+                            v += t;
+                        }
+                    }
+                    us[li][3 * q + c] = v;
+                }
+            }
+        }
+    }
+
     // ---- own rows: p, s, x, r
     if (live && lane < 12) {
         const size_t o = 12 * (size_t)j + lane;
@@ -447,7 +528,31 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
             }
     };
     int pos0 = kb;
-    if (!START && l0 >= 0) {
+    if (!START && shr) {
+        __syncthreads();   // us complete
+        auto sblock = [&](const T* kv, int li) {
+            const T* ul = us[li];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T acc = y[3 * q + c];
+                    acc = fma(kv[4 * q], ul[c], acc);
+                    acc = fma(kv[4 * q + 1], ul[3 + c], acc);
+                    acc = fma(kv[4 * q + 2], ul[6 + c], acc);
+                    y[3 * q + c] = fma(kv[4 * q + 3], ul[9 + c], acc);
+                }
+        };
+        if (kb < ke) sblock(sk[0], slc[0]);
+        if (kb + 16 < ke) sblock(sk[1], slc[1]);
+        for (int pos = kb + 32; pos < ke; pos += 16) {
+            T kv[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) kv[m] = a.Kval[16 * (size_t)pos + m];
+            sblock(kv, a.K_lcol[pos]);
+        }
+        pos0 = ke;
+    } else if (!START && l0 >= 0) {
         T rn[12];
 #pragma unroll
         for (int m = 0; m < 12; ++m)
@@ -491,19 +596,22 @@ __global__ void __launch_bounds__(kCgThreads) k_cg(CgArgs<T> a, int it) {
     if (live && lane < 12) {
         const size_t o = 12 * (size_t)j + lane;
         const int c = lane % 3;
-        T rrow[12], urow[12];
-#pragma unroll
-        for (int m = 0; m < 12; ++m) rrow[m] = rs[row][m];
-        apply_dinv(a.Dinv + 16 * (size_t)j, rrow, urow);
         V dj{};
-        if (COARSE) {
-            dj = a.node_rel[j];
-            prolong_add(dj, cco[(j - (int)pi.node_off) >> pi.agg_shift], urow);
-        }
-        T un = urow[0];
+        if (COARSE) dj = a.node_rel[j];
+        T un;
+        if (!START && shr) {
+            un = us[rowl][lane];   // the row's own node in the shared table
+        } else {
+            T rrow[12], urow[12];
 #pragma unroll
-        for (int m = 1; m < 12; ++m)
-            if (lane == m) un = urow[m];
+            for (int m = 0; m < 12; ++m) rrow[m] = rs[row][m];
+            apply_dinv(a.Dinv + 16 * (size_t)j, rrow, urow);
+            if (COARSE) prolong_add(dj, cco[(j - (int)pi.node_off) >> pi.agg_shift], urow);
+            un = urow[0];
+#pragma unroll
+            for (int m = 1; m < 12; ++m)
+                if (lane == m) un = urow[m];
+        }
         const T wn = ys[row][lane];
         a.u[nxt][o] = un;
         a.w[nxt][o] = wn;

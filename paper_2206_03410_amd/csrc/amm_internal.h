@@ -116,6 +116,12 @@ struct Layout {
     std::vector<int32_t> aggs;       // [nagg][4]
     std::vector<double> node_rel;    // [ntot][4]
     std::vector<int32_t> tile_agg_ptr, tile_agg;
+    // per node tile, the distinct column nodes of its rows of K (sorted;
+    // [tiles][kTileColCap], padded with the first), their count (a tile with
+    // more than kTileColCap has no list), the local index of every K block's
+    // column in its tile's list, and of every row's own node
+    std::vector<int32_t> tile_cols, tile_ncols, tile_rowl;
+    std::vector<uint16_t> K_lcol;
 };
 
 constexpr int kPointTile = 256;
@@ -145,6 +151,7 @@ amm_status graph_copy(const GraphBuild* g, void* stream, int set, int32_t* node_
                       void* infl_w, int32_t* edges, std::string& err);
 constexpr int kMaxK = 8;
 constexpr int kCoarseMaxAgg = 32;    // aggregates per pair (coarse order <= 128)
+constexpr int kTileColCap = 160;     // distinct column nodes of a solver tile shared in LDS
 constexpr int kAggMinShift = 6;      // at least 64 nodes (4 node tiles) per aggregate
 
 amm_status validate_pair(const HostPair& hp, std::string& err);

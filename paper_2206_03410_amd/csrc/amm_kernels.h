@@ -152,6 +152,10 @@ struct CgArgs {
     const V* node_rel;       // node position minus its aggregate's centroid
     const int* tile_agg_ptr; // aggregates (pair-local) each tile's rows of K touch
     const int* tile_agg;
+    const int* tile_cols;    // [tiles][kTileColCap] distinct column nodes of each tile
+    const int* tile_ncols;   // [tiles] their count (> kTileColCap: no list)
+    const int* tile_rowl;    // [tiles][kNodeTile] local index of each row's node
+    const uint16_t* K_lcol;  // [nnzb] local index of each block's column
     T* gr[2];                // [nagg][12] P^T r per aggregate
     T* gs[2];                // [nagg][12] P^T s per aggregate
     // host-visible [P][2]: last step reported; at convergence one 64-bit word
@@ -246,14 +250,16 @@ struct GradArgs {
 };
 
 // Per-pair parameters carried to the device in the kernel arguments of a
-// small copy kernel (no host-memory access by the GPU, no blit).
+// small copy kernel (no host-memory access by the GPU, no blit), in packs of
+// 1, 8 or 32 so that the arguments are no larger than the pairs sent.
 constexpr int kDynPerLaunch = 32;
+template <int N>
 struct DynPack {
-    PairDyn d[kDynPerLaunch];
+    PairDyn d[N];
     PairDyn* dst;
     int n;
 };
-void launch_dyn_set(const DynPack& pk, hipStream_t s);
+void launch_dyn_set(const PairDyn* src, int n, PairDyn* dst, hipStream_t s);
 
 template <typename T>
 void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_tiles, const FinalArgs& f,

@@ -1083,7 +1083,8 @@ void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_cast_static<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
 
-__global__ void __launch_bounds__(64) k_dyn_set(DynPack pk) {
+template <int N>
+__global__ void __launch_bounds__(64) k_dyn_set(DynPack<N> pk) {
     static_assert(sizeof(PairDyn) % 4 == 0, "PairDyn is copied in 32-bit words");
     const int words = pk.n * (int)(sizeof(PairDyn) / 4);
     const unsigned* src = reinterpret_cast<const unsigned*>(pk.d);
@@ -1091,9 +1092,24 @@ __global__ void __launch_bounds__(64) k_dyn_set(DynPack pk) {
     for (int i = threadIdx.x; i < words; i += 64) dst[i] = src[i];
 }
 
-void launch_dyn_set(const DynPack& pk, hipStream_t s) {
-    hipLaunchKernelGGL(k_dyn_set, dim3(1), dim3(64), 0, s, pk);
+template <int N>
+void dyn_set_pack(const PairDyn* src, int n, PairDyn* dst, hipStream_t s) {
+    DynPack<N> pk;
+    for (int i = 0; i < n; ++i) pk.d[i] = src[i];
+    pk.dst = dst;
+    pk.n = n;
+    hipLaunchKernelGGL(k_dyn_set<N>, dim3(1), dim3(64), 0, s, pk);
 }
+
+void launch_dyn_set(const PairDyn* src, int n, PairDyn* dst, hipStream_t s) {
+    if (n <= 1)
+        dyn_set_pack<1>(src, n, dst, s);
+    else if (n <= 8)
+        dyn_set_pack<8>(src, n, dst, s);
+    else
+        dyn_set_pack<kDynPerLaunch>(src, n, dst, s);
+}
+
 
 #define AMM_INSTANTIATE(T)                                                                                     \
     template void launch_eval<T>(const EvalArgs<T>&, int, int, int, const FinalArgs&, int, hipStream_t,        \

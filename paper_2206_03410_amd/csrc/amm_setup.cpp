@@ -482,6 +482,27 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.adj_ptr[L.ntot] = (int32_t)ao;
     L.K_ptr[L.ntot] = (int32_t)L.K_col.size();
     L.pj_ptr[L.ntot] = (int32_t)L.pj_ent.size();
+    L.tile_cols.assign((size_t)L.n_nd_tiles * kTileColCap, 0);
+    L.tile_ncols.assign(L.n_nd_tiles, 0);
+    L.tile_rowl.assign((size_t)L.n_nd_tiles * kNodeTile, 0);
+    L.K_lcol.assign(L.K_col.size(), 0);
+    for (int t = 0; t < L.n_nd_tiles; ++t) {
+        const int32_t j0 = L.nd_tiles[4 * (size_t)t + 1], j1 = L.nd_tiles[4 * (size_t)t + 2];
+        std::vector<int32_t> cols(L.K_col.begin() + L.K_ptr[j0], L.K_col.begin() + L.K_ptr[j1]);
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        L.tile_ncols[t] = (int32_t)cols.size();
+        if ((int)cols.size() > kTileColCap) continue;
+        int32_t* dst = &L.tile_cols[(size_t)t * kTileColCap];
+        for (int q = 0; q < kTileColCap; ++q) dst[q] = cols[q < (int)cols.size() ? q : 0];
+        auto local = [&](int32_t node) {
+            return (int32_t)(std::lower_bound(cols.begin(), cols.end(), node) - cols.begin());
+        };
+        for (int32_t j = j0; j < j1; ++j) {
+            L.tile_rowl[(size_t)t * kNodeTile + (j - j0)] = local(j);
+            for (int32_t e = L.K_ptr[j]; e < L.K_ptr[j + 1]; ++e) L.K_lcol[e] = (uint16_t)local(L.K_col[e]);
+        }
+    }
     L.nnzb = (int64_t)L.K_col.size();
     L.tree_nodes = tree;
     L.pj_entries = (int64_t)L.pj_ent.size();
