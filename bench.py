@@ -211,8 +211,15 @@ def cpu_baseline(pair, sample=40000):
                 break
     except OSError:
         pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
+    except Exception:
+        pass
     return {
         "value": 1.0 / per_iter, "unit": "MM iterations/s", "cores": threads, "kind": "oracle",
+        "blas_threads": blas,
         "sample": (f"one FP64 oracle MM iteration on the same 200k workload: warp, Welsch terms, "
                    f"rotations, sparse-LU surrogate solve and Anderson step in full; brute-force "
                    f"closest points on {sample} of {prob.n_src} queries, scaled x{prob.n_src // sample}"),

@@ -31,7 +31,12 @@ thread_local std::string g_last_error;
 
 const char* kVersion = "amm-gfx950 0.1";
 constexpr int kDynRing = 16;
-constexpr int kCgLookahead = 10;  // CG steps in flight ahead of the last one reported (every 4th)
+// CG steps in flight ahead of the last one reported.  Steps report every
+// 4th step (3, 7, ...) and the host starts from "step -2 reported", so the
+// first report (step 3) is launched only if the lookahead is at least 5;
+// each step queued past convergence costs an early-exit launch.
+constexpr int kCgLookahead = 6;
+static_assert(kCgLookahead >= 5, "the first progress report (step 3) must be launchable");
 
 struct EventTimer final : KernelTimer {
     struct Rec {
