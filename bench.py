@@ -307,7 +307,8 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
     a separate, untimed solve) against the eval_points kernel's measured
     average launch time.  Candidate traffic per launch = queries x (12 B
     warped query + 8 B outputs) + box tests x 32 B (two float4 corners) +
-    distance evaluations x 16 B (one float4 target)."""
+    grid cell lookups x 8 B (two cell bounds) + distance evaluations x 16 B
+    (one float4 target)."""
     amm.amm_count_nn_work(h, True)
     try:
         run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, steps, aa_m)
@@ -315,22 +316,23 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
     finally:
         amm.amm_count_nn_work(h, False)
     launches = max(1, round(w["queries"] / pair.n_src))
-    q, bx, de = (w[k] / launches for k in ("queries", "box_tests", "distance_evals"))
+    q, bx, de, cl = (w[k] / launches for k in ("queries", "box_tests", "distance_evals", "cell_lookups"))
     t = eval_ms / eval_launches * 1e-3
-    cand = q * (12 + 8) + bx * 32 + de * 16
+    cand = q * (12 + 8) + bx * 32 + cl * 8 + de * 16
     comp = pair.n_src * (12 + 4 + 4) + 12 * pair.n_tgt
     flops = 8 * de + 12 * bx
     return {"kernel": "eval_points", "avg_launch_us": t * 1e6, "queries_per_launch": q,
-            "box_tests_per_query": bx / q, "distance_evals_per_query": de / q,
+            "box_tests_per_query": bx / q, "cell_lookups_per_query": cl / q,
+            "distance_evals_per_query": de / q,
             "compulsory_GBps": comp / t / 1e9,
             "candidate_traffic_GBps": cand / t / 1e9,
             "candidate_traffic_frac": cand / t / 1e9 / HBM_PEAK_GBS,
             "distance_evals_per_s": de / t,
             "search_flops_frac_fp32_valu": flops / t / 157.3e12,
             "definition": "candidate traffic = queries x (12 B warped point + 8 B closest index and "
-                          "squared distance) + box lower-bound tests x 32 B + target distance "
-                          "evaluations x 16 B, per launch, over the kernel's average launch time; "
-                          "flops: 8 per distance evaluation, 12 per box test"}
+                          "squared distance) + box lower-bound tests x 32 B + grid cell lookups x 8 B + "
+                          "target distance evaluations x 16 B, per launch, over the kernel's average "
+                          "launch time; flops: 8 per distance evaluation, 12 per box test"}
 
 
 def graph_build_report(amm, torch, h, pair, k, with_cpu):
@@ -605,7 +607,8 @@ def main():
         _, _, _, kt_e = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m,
                                   timing="eval_points")
         nn = nn_search_report(amm, torch, h, pair, aa_m, args.steps, *kt_e["eval_points"])
-        log(f"[bench] closest points: {nn['box_tests_per_query']:.1f} box tests and "
+        log(f"[bench] closest points: {nn['box_tests_per_query']:.1f} box tests, "
+            f"{nn['cell_lookups_per_query']:.1f} grid cells and "
             f"{nn['distance_evals_per_query']:.1f} distance evaluations per query; candidate traffic "
             f"{nn['candidate_traffic_GBps']:.0f} GB/s")
         copy_gbs = copy_bandwidth(torch)

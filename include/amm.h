@@ -206,7 +206,7 @@ amm_status amm_check_problem(const amm_problem* p);
 /* Replaces the target points of pair `pair` (0-based within the last
  * amm_set_problems batch) by n_tgt new ones of the same count, keeping the
  * source side (graph, pattern of K, point lists, coarse aggregates) as it
- * is; only the pair's search tree is rebuilt.  For registering one template
+ * is; only the pair's search structures (tree and grid) are rebuilt.  For registering one template
  * to a sequence of frames (Sec. 4's sequences) without a new upload.  The
  * result equals a new amm_set_problems with the new targets.  Pointers are
  * device pointers when on_device = 1.  Errors: AMM_ERR_STATE before a
@@ -229,8 +229,9 @@ amm_status amm_set_workspace(amm_handle* h, void* ptr, size_t bytes);
 /* Validates and uploads a batch of independent registration problems
  * (n_pairs >= 1, all with the same k).  Computes the edge weights r_ij of
  * Eq. (8), a spatial ordering of points and nodes, the block pattern of K,
- * and the nearest-neighbour structure over each target set (a bounding-box
- * tree over Morton-ordered targets).  Replaces any previous problems. */
+ * and the nearest-neighbour structures over each target set (a bounding-box
+ * tree over Morton-ordered targets, and a uniform grid over the same order
+ * for warm-started searches).  Replaces any previous problems. */
 amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_pairs);
 amm_status amm_set_problem(amm_handle* h, const amm_problem* p);
 
@@ -274,11 +275,13 @@ amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, i
  * which is slower; 0 switches back and frees them.  amm_set_problems also
  * switches counting off.  amm_nn_work returns, since counting was switched
  * on: the queries searched, the bounding-box lower-bound tests (each reads
- * two box corners) and the target distance evaluations (each reads one
- * target).  Errors: AMM_ERR_STATE before a problem is set, or when
- * counting is off. */
+ * two box corners), the target distance evaluations (each reads one
+ * target) and, if cell_lookups is not null, the grid cell lookups of
+ * warm-started searches (each reads two cell bounds).  Errors:
+ * AMM_ERR_STATE before a problem is set, or when counting is off. */
 amm_status amm_count_nn_work(amm_handle* h, int32_t enable);
-amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals);
+amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals,
+                       int64_t* cell_lookups);
 
 /* ---------------------------------------------------------------- graph construction */
 

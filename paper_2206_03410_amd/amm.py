@@ -125,7 +125,7 @@ def lib():
             "amm_graph_copy": ([vp, vp, vp, vp, vp], C.c_int),
             "amm_build_graphs": ([vp, C.POINTER(amm_graph_in), i32, C.POINTER(amm_graph_info)], C.c_int),
             "amm_graph_copy_set": ([vp, i32, vp, vp, vp, vp], C.c_int),
-            "amm_nn_work": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
+            "amm_nn_work": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
             "amm_autotune": ([vp, C.POINTER(amm_problem), i32, C.POINTER(i32), i32, C.POINTER(i32),
                               C.POINTER(dbl)], C.c_int),
             "amm_solve": ([vp, C.POINTER(amm_params), vp, vp, C.POINTER(amm_stats)], C.c_int),
@@ -345,10 +345,10 @@ def amm_count_nn_work(handle, enable: bool) -> None:
 
 def amm_nn_work(handle) -> dict:
     """Totals since counting was switched on: queries, box tests, distance
-    evaluations of the closest-point search."""
-    q, b, d = C.c_int64(), C.c_int64(), C.c_int64()
-    _check(lib().amm_nn_work(handle, C.byref(q), C.byref(b), C.byref(d)), handle)
-    return dict(queries=q.value, box_tests=b.value, distance_evals=d.value)
+    evaluations and grid cell lookups of the closest-point search."""
+    q, b, d, g = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().amm_nn_work(handle, C.byref(q), C.byref(b), C.byref(d), C.byref(g)), handle)
+    return dict(queries=q.value, box_tests=b.value, distance_evals=d.value, cell_lookups=g.value)
 
 
 def amm_autotune(handle, problems: Sequence[amm_problem], candidates=None):

@@ -197,6 +197,7 @@ struct Dev {
     int4* aggs;
     int* tile_agg_ptr;
     int* tile_agg;
+    int* grid_cells;
     int* tile_cols;
     int* tile_ncols;
     int* tile_rowl;
@@ -237,6 +238,7 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(v.aggs, (size_t)L.nagg);
     c.take(v.tile_agg_ptr, nnd + 1);
     c.take(v.tile_agg, L.tile_agg.size());
+    c.take(v.grid_cells, L.grid_cells.size());
     c.take(v.tile_cols, L.tile_cols.size());
     c.take(v.tile_ncols, L.tile_ncols.size());
     c.take(v.tile_rowl, L.tile_rowl.size());
@@ -313,6 +315,10 @@ struct amm_handle {
     void* ws_own = nullptr;
     size_t ws_own_bytes = 0;
     bool has_problem = false;
+    // closest points of evaluation set 0 of pair 0 hold valid target
+    // positions (an evaluation wrote them since the last upload): energy and
+    // step evaluations then seed their searches with them
+    bool rho_set0 = false;
     Layout L;
     Dev v{};
     std::vector<double> lbar;
@@ -332,7 +338,7 @@ struct amm_handle {
     bool timing = false;
     bool cg_coarse = true;           // two-level CG preconditioner
     int leaf = 8;                    // targets per leaf of the closest-point tree (next upload)
-    long long* nn_work = nullptr;    // [n_pt_tiles][3] search counters while counting is on
+    long long* nn_work = nullptr;    // [n_pt_tiles][4] search counters while counting is on
     int nn_work_tiles = 0;
     GraphBuild* graph = nullptr;     // last amm_build_graph result
     EventTimer timer;
@@ -516,6 +522,7 @@ EvalArgs<T> eval_args(amm_handle* h, bool use_override = false) {
     a.tgt = s.tgt;
     a.blo = s.blo;
     a.bhi = s.bhi;
+    a.grid = h->v.grid_cells;
     a.adj_row = h->v.adj_row;
     a.adj_nbr = h->v.adj_nbr;
     a.adj_r = s.adj_r;
@@ -667,6 +674,7 @@ amm_status evaluate(amm_handle* h, bool use_override = false) {
     TRY(push_dyn(h));
     launch_eval<T>(eval_args<T>(h, use_override), h->L.n_pt_tiles, h->L.n_eg_tiles, h->L.n_nd_tiles,
                    final_args(h), h->L.P, h->stream, tmr(h));
+    if ((h->dyn[0].flags & PF_EVAL) && h->dyn[0].eval_dst == 0) h->rho_set0 = true;
     return pull_out(h);
 }
 
@@ -1207,6 +1215,8 @@ amm_status energy_impl(amm_handle* h, const void* X, const void* src, double nu_
     PairDyn& dy = h->dyn[0];
     dy = PairDyn{};
     dy.flags = PF_EVAL;
+    dy.has_prev = h->rho_set0 ? 1 : 0;   // seeds only: the search is exact either way
+    dy.use_grid = 1;
     set_scalars(dy, nu_a, nu_r, alpha, beta);
     TRY(evaluate<T>(h, src != nullptr));
     if (energy) {
@@ -1270,6 +1280,8 @@ amm_status step_impl(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     PairDyn& dy = h->dyn[0];
     dy = PairDyn{};
     dy.flags = PF_EVAL;
+    dy.has_prev = h->rho_set0 ? 1 : 0;   // seeds only: the search is exact either way
+    dy.use_grid = 1;
     set_scalars(dy, in->nu_a, in->nu_r, in->alpha, in->beta, in->robust);
     TRY(evaluate<T>(h));
     out->energy[0] = h->h_out[0].E;
@@ -1506,11 +1518,13 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up(h, reinterpret_cast<int32_t*>(v.aggs), Lr.aggs));
     TRY(up(h, v.tile_agg_ptr, Lr.tile_agg_ptr));
     TRY(up(h, v.tile_agg, Lr.tile_agg));
+    TRY(up(h, v.grid_cells, Lr.grid_cells));
     TRY(up(h, v.tile_cols, Lr.tile_cols));
     TRY(up(h, v.tile_ncols, Lr.tile_ncols));
     TRY(up(h, v.tile_rowl, Lr.tile_rowl));
     TRY(up(h, v.K_lcol, Lr.K_lcol));
     h->has_problem = true;
+    h->rho_set0 = false;
     return AMM_OK;
 }
 
@@ -1668,7 +1682,17 @@ amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const v
     std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + pi.tgt_off);
     std::copy(tl.box_lo.begin(), tl.box_lo.end(), L.box_lo.begin() + 4 * pi.tree_off);
     std::copy(tl.box_hi.begin(), tl.box_hi.end(), L.box_hi.begin() + 4 * pi.tree_off);
+    if (tl.grid_bits != pi.grid_bits) return fail(h, AMM_ERR_STATE, "target grid shape changed");
+    std::copy(tl.cells.begin(), tl.cells.end(), L.grid_cells.begin() + pi.grid_off);
+    for (int c = 0; c < 3; ++c) {
+        pi.glo[c] = tl.glo[c];
+        pi.gscale[c] = tl.gscale[c];
+    }
+    pi.gpad = tl.gpad;
     Dev& v = h->v;
+    HIPC(hipMemcpyAsync(v.grid_cells + pi.grid_off, tl.cells.data(), sizeof(int32_t) * tl.cells.size(),
+                        hipMemcpyHostToDevice, h->stream));
+    HIPC(hipMemcpyAsync(v.info + pair, &pi, sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
     HIPC(hipMemcpyAsync(v.tgt_user + pi.tgt_off, tl.tgt_user.data(), sizeof(int32_t) * n_tgt,
                         hipMemcpyHostToDevice, h->stream));
     auto put = [&](float* df, double* dd, const std::vector<double>& src) -> amm_status {
@@ -1728,7 +1752,7 @@ amm_status amm_count_nn_work(amm_handle* h, int32_t enable) {
     h->nn_work = nullptr;
     h->nn_work_tiles = 0;
     if (!enable) return AMM_OK;
-    const size_t bytes = sizeof(long long) * 3 * std::max(h->L.n_pt_tiles, 1);
+    const size_t bytes = sizeof(long long) * 4 * std::max(h->L.n_pt_tiles, 1);
     if (hipMalloc((void**)&h->nn_work, bytes) != hipSuccess) {
         h->nn_work = nullptr;
         return fail(h, AMM_ERR_OOM, "search counters");
@@ -1739,22 +1763,25 @@ amm_status amm_count_nn_work(amm_handle* h, int32_t enable) {
     return AMM_OK;
 }
 
-amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals) {
+amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals,
+                       int64_t* cell_lookups) {
     if (!h || !queries || !box_tests || !distance_evals) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
     if (!h->nn_work) return fail(h, AMM_ERR_STATE, "search counting is off");
     HIPC(hipSetDevice(h->device));
-    std::vector<long long> c(3 * (size_t)h->nn_work_tiles);
+    std::vector<long long> c(4 * (size_t)h->nn_work_tiles);
     HIPC(hipMemcpyAsync(c.data(), h->nn_work, sizeof(long long) * c.size(), hipMemcpyDeviceToHost, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
-    long long q = 0, b = 0, d = 0;
+    long long q = 0, b = 0, d = 0, g = 0;
     for (int t = 0; t < h->nn_work_tiles; ++t) {
-        q += c[3 * t];
-        b += c[3 * t + 1];
-        d += c[3 * t + 2];
+        q += c[4 * t];
+        b += c[4 * t + 1];
+        d += c[4 * t + 2];
+        g += c[4 * t + 3];
     }
     *queries = q;
     *box_tests = b;
     *distance_evals = d;
+    if (cell_lookups) *cell_lookups = g;
     return AMM_OK;
 }
 

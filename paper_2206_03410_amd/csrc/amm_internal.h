@@ -30,6 +30,15 @@ struct PairInfo {
     // 4 nagg) starts at ainv_off
     int32_t agg0, nagg, agg_shift;
     int64_t ainv_off;
+    // closest-point grid over the targets: cell (cx, cy, cz) holds the
+    // targets whose 10-bit quantized coordinates (x - glo) gscale have those
+    // top grid_bits bits; the cells are Morton prefixes of the targets' sort
+    // order, cell m spans sorted targets [cells[grid_off + m],
+    // cells[grid_off + m + 1]).  gpad: a distance margin covering rounding in
+    // the cell bounds (1e-6 of the largest extent)
+    int64_t grid_off;
+    int32_t grid_bits, pad_g;
+    double glo[3], gscale[3], gpad;
 };
 
 // Dynamic per-pair state the host writes before launches.
@@ -49,6 +58,8 @@ struct PairDyn {
     int32_t aa_slot[11];     // ring slots: [0] = newest (k), [1] = k-1, ...
     int32_t has_prev;        // closest-point warm start available in set `cur`
     int32_t robust;          // amm_robust
+    int32_t use_grid;        // warm-started searches may scan the target grid
+    int32_t pad_d;
     double cg_rtol;          // CG stopping tolerance of this pair (0: the launch's)
 };
 
@@ -116,6 +127,7 @@ struct Layout {
     std::vector<int32_t> aggs;       // [nagg][4]
     std::vector<double> node_rel;    // [ntot][4]
     std::vector<int32_t> tile_agg_ptr, tile_agg;
+    std::vector<int32_t> grid_cells;   // per pair, the target grid's cell starts
     // per node tile, the distinct column nodes of its rows of K (sorted;
     // [tiles][kTileColCap], padded with the first), their count (a tile with
     // more than kTileColCap has no list), the local index of every K block's
@@ -138,6 +150,9 @@ struct TargetLayout {
     std::vector<double> tgt4, box_lo, box_hi;
     std::vector<int32_t> tgt_user;
     int32_t L = 0;
+    int32_t grid_bits = 0;
+    double glo[3] = {0, 0, 0}, gscale[3] = {0, 0, 0}, gpad = 0;
+    std::vector<int32_t> cells;      // [8^grid_bits + 1]
 };
 void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out);
 

@@ -57,6 +57,7 @@ struct EvalArgs {
     const V* tgt;
     const V* blo;
     const V* bhi;
+    const int* grid;         // per pair, the target grid's cell starts (PairInfo.grid_off)
     const int* adj_row;
     const int* adj_nbr;
     const T* adj_r;

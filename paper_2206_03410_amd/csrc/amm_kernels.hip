@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     using V = typename V4Of<T>::type;
     __shared__ T sh[kPointTile];
     __shared__ long long shc[COUNT ? kPointTile : 1];
-    NnWork wk{0, 0};
+    NnWork wk{0, 0, 0};
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int4 td = a.pt_tiles[tile];
     const int p = td.x;
@@ -69,7 +69,14 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
         const int prev = dy.has_prev ? a.rho[cur][i] - (int)pi.tgt_off : -1;
         int bpos;
         T d2;
-        nn_search<T, V, COUNT>(pi, a.tgt, a.blo, a.bhi, vx, vy, vz, prev, bpos, d2, &wk);
+        // seeded by an exact previous answer (energy, gradient, step calls):
+        // scan the grid cells its distance covers; the tree where that range
+        // is wide, for cold searches, and inside solves (there the seeds are
+        // looser and the far points' tree searches, in nearly every wave,
+        // would run after the grid scan)
+        const bool in_grid = dy.use_grid && prev >= 0 &&
+                             grid_search<T, V, COUNT>(pi, a.grid, a.tgt, vx, vy, vz, prev, bpos, d2, &wk);
+        if (!in_grid) nn_search<T, V, COUNT>(pi, a.tgt, a.blo, a.bhi, vx, vy, vz, prev, bpos, d2, &wk);
         const V u = a.tgt[pi.tgt_off + bpos];
         // e_i = v_hat_i - u_rho(i)
         //     = sum_j w_ij ((A_j - I) d_ij + t_j) + (v_i - u) + (sum_j w_ij - 1) v_i
@@ -120,12 +127,14 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     if constexpr (COUNT) {
         const long long nb = block_sum<long long, kPointTile>(wk.boxes, shc);
         const long long np = block_sum<long long, kPointTile>(wk.points, shc);
+        const long long nc = block_sum<long long, kPointTile>(wk.cells, shc);
         if (threadIdx.x == 0) {
             // one block per tile and launch, launches in stream order
-            long long* c = a.nn_work + 3 * (size_t)tile;
+            long long* c = a.nn_work + 4 * (size_t)tile;
             c[0] += td.z - td.y;
             c[1] += nb;
             c[2] += np;
+            c[3] += nc;
         }
     }
 }

@@ -37,10 +37,11 @@ __host__ __device__ inline T box_d2(const V& lo, const V& hi, T qx, T qy, T qz) 
 // ---------------------------------------------------------------- closest point
 
 // Work of one search, counted only where asked for (COUNT = true): box
-// lower-bound tests and target distance evaluations.
+// lower-bound tests, target distance evaluations and grid cell lookups.
 struct NnWork {
     int boxes;
     int points;
+    int cells;
 };
 
 // Exact closest target of query q among the pair's targets, by depth-first
@@ -120,6 +121,84 @@ __host__ __device__ inline void nn_search(const PairInfo& pi, const V* __restric
     // a non-finite query matches nothing; keep the index in range
     best_pos = bpos < 0 ? 0 : bpos;
     best_d2 = bd;
+}
+
+// ---------------------------------------------------------------- grid
+
+__host__ __device__ inline uint32_t nn_spread10(uint32_t x) {
+    x &= 0x3ff;
+    x = (x | (x << 16)) & 0x030000ff;
+    x = (x | (x << 8)) & 0x0300f00f;
+    x = (x | (x << 4)) & 0x030c30c3;
+    x = (x | (x << 2)) & 0x09249249;
+    return x;
+}
+
+constexpr int kGridMaxCells = 32;
+
+// Cell range of one axis covered by [q - r, q + r] (clamped to the grid).
+template <typename T>
+__host__ __device__ inline void grid_axis(T q, T r, double glo, double gscale, int sh, int& lo, int& hi) {
+    const T o = (T)glo, s = (T)gscale;
+    T a = (q - r - o) * s, b = (q + r - o) * s;
+    a = fmin(fmax(a, T(0)), T(1023));
+    b = fmin(fmax(b, T(0)), T(1023));
+    lo = (int)floor(a) >> sh;
+    hi = (int)floor(b) >> sh;
+}
+
+// Exact closest target of q when a target position `prev` bounds it: every
+// target at computed squared distance <= bd = |u_prev - q|^2 lies within
+// sqrt(bd) (times 1 + 3 ulp) of q on each axis, hence in the grid cells that
+// [q - r, q + r] covers, r = sqrt(bd) widened by a relative 1e-5 and by
+// pi.gpad (the cell bounds' rounding).  Those cells are scanned with the
+// tree search's distance shape and tie rule (the lowest user index), and
+// the lexicographic minimum of (distance, index) does not depend on the
+// order of visits, so the result is the tree search's.  Returns false,
+// leaving the outputs alone, when the range covers more than kGridMaxCells
+// cells or the bound is not finite (then the tree is searched).
+template <typename T, typename V, bool COUNT = false>
+__host__ __device__ inline bool grid_search(const PairInfo& pi, const int* __restrict__ cells,
+                                            const V* __restrict__ tgt, T qx, T qy, T qz, int prev,
+                                            int& best_pos, T& best_d2, NnWork* work = nullptr) {
+    const V* tg = tgt + pi.tgt_off;
+    const V u = tg[prev];
+    T bd = sq3(u.x - qx, u.y - qy, u.z - qz);
+    if (!(bd < nn_inf<T>())) return false;
+    const T r = sqrt(bd) * T(1.00001) + (T)pi.gpad;
+    const int sh = 10 - pi.grid_bits;
+    int x0, x1, y0, y1, z0, z1;
+    grid_axis<T>(qx, r, pi.glo[0], pi.gscale[0], sh, x0, x1);
+    grid_axis<T>(qy, r, pi.glo[1], pi.gscale[1], sh, y0, y1);
+    grid_axis<T>(qz, r, pi.glo[2], pi.gscale[2], sh, z0, z1);
+    if ((x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1) > kGridMaxCells) return false;
+    const int* cl = cells + pi.grid_off;
+    int bid = (int)u.w, bpos = prev;
+    for (int cz = z0; cz <= z1; ++cz)
+        for (int cy = y0; cy <= y1; ++cy)
+            for (int cx = x0; cx <= x1; ++cx) {
+                const uint32_t m = (nn_spread10((uint32_t)cx) << 2) | (nn_spread10((uint32_t)cy) << 1) |
+                                   nn_spread10((uint32_t)cz);
+                const int s0 = cl[m], s1 = cl[m + 1];
+                if constexpr (COUNT) {
+                    work->cells += 1;
+                    work->points += s1 - s0;
+                }
+                for (int t = s0; t < s1; ++t) {
+                    const V w = tg[t];
+                    const T d = sq3(w.x - qx, w.y - qy, w.z - qz);
+                    const int id = (int)w.w;
+                    if (d < bd || (d == bd && id < bid)) {
+                        bd = d;
+                        bid = id;
+                        bpos = t;
+                    }
+                }
+            }
+    if constexpr (COUNT) work->points += 1;   // the bound's own target
+    best_pos = bpos;
+    best_d2 = bd;
+    return true;
 }
 
 }  // namespace amm

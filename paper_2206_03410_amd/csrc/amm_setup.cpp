@@ -45,6 +45,13 @@ uint32_t morton(const double* p, const Box& b) {
     return (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
 }
 
+// Bits per axis of a target grid of M points: about two cells per target
+// over the bounding box (8^bits ~ 2M), between 2 and 7.
+int grid_bits_for(int64_t M) {
+    const double b = std::floor(std::log2((double)std::max<int64_t>(M, 1)) / 3.0 + 0.5);
+    return (int)std::min(7.0, std::max(2.0, b));
+}
+
 std::vector<int32_t> morton_order(const double* pts, int64_t cnt, const Box& b) {
     std::vector<uint32_t> code(cnt);
     for (int64_t i = 0; i < cnt; ++i) code[i] = morton(pts + 3 * i, b);
@@ -412,6 +419,14 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
             pi.tree_off = tree;
             pi.L = tl.L;
             pi.leaf = leaf;
+            pi.grid_off = (int64_t)L.grid_cells.size();
+            pi.grid_bits = tl.grid_bits;
+            for (int c = 0; c < 3; ++c) {
+                pi.glo[c] = tl.glo[c];
+                pi.gscale[c] = tl.gscale[c];
+            }
+            pi.gpad = tl.gpad;
+            L.grid_cells.insert(L.grid_cells.end(), tl.cells.begin(), tl.cells.end());
             L.box_lo.insert(L.box_lo.end(), tl.box_lo.begin(), tl.box_lo.end());
             L.box_hi.insert(L.box_hi.end(), tl.box_hi.begin(), tl.box_hi.end());
             tree += 2 * (int64_t)tl.L;
@@ -543,6 +558,26 @@ void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out) {
             out.box_hi[4 * b + c] = std::max(out.box_hi[4 * c0 + c], out.box_hi[4 * c1 + c]);
         }
     }
+    // grid: cell = top grid_bits bits of each quantized coordinate, i.e. the
+    // top 3 grid_bits bits of the Morton code the targets are sorted by
+    const int G = grid_bits_for(M);
+    out.grid_bits = G;
+    double emax = 0;
+    for (int c = 0; c < 3; ++c) {
+        const double ext = bb.hi[c] - bb.lo[c];
+        out.glo[c] = bb.lo[c];
+        out.gscale[c] = ext > 0 ? 1023.999 / ext : 0.0;
+        emax = std::max(emax, ext);
+    }
+    out.gpad = 1e-6 * emax;
+    const size_t ncell = (size_t)1 << (3 * G);
+    out.cells.assign(ncell + 1, 0);
+    std::vector<int32_t> cnt(ncell, 0);
+    for (int64_t q = 0; q < M; ++q) {
+        const uint32_t code = morton(&tgt[3 * (size_t)tord[q]], bb) >> (3 * (10 - G));
+        ++cnt[code];
+    }
+    for (size_t m = 0; m < ncell; ++m) out.cells[m + 1] = out.cells[m] + cnt[m];
 }
 
 }  // namespace amm

@@ -77,6 +77,51 @@ def test_step_sampled_against_oracle(case):
     assert np.sqrt(((vo - vg) ** 2).sum(1).mean()) < 1e-4
 
 
+def test_seeded_search_equals_cold_search_sh200k():
+    """Closest points of the 200,000-point workload (float32) at X1 = X0 +
+    small step, searched with the closest points at X0 as seeds (the grid
+    path for most queries), equal bitwise those of a cold search at X1 in a
+    fresh session, and so does the energy; 2,000 sampled queries equal the
+    oracle's brute force on the library's warped points wherever the best
+    and second-best distances differ by more than 1e-6 relative."""
+    _announce("test_seeded_search_equals_cold_search_sh200k")
+    pair = synth.make_workload("sh200k")
+    pr = rounded(pair, np.float32)
+    n, N = pr.n_nodes, pr.n_src
+    X0 = synth.perturbed_transforms(n, 9009, 0.01, 0.001).astype(np.float32)
+    X1 = X0 + (1e-3 * np.random.default_rng(9010).standard_normal(X0.shape)).astype(np.float32)
+    sc = (0.02, 0.05, 10.0, 100.0)
+    dev = "cuda:0"
+    got = []
+    for seeded in (True, False):
+        with Session(pr, torch.float32) as s:
+            if seeded:
+                amm.amm_energy(s.h, torch.tensor(X0, device=dev), None, *sc)
+                amm.amm_count_nn_work(s.h, True)
+            rho = torch.empty(N, dtype=torch.int32, device=dev)
+            vh = torch.empty(N, 3, dtype=torch.float32, device=dev)
+            e = amm.amm_energy(s.h, torch.tensor(X1, device=dev), None, *sc, rho=rho)
+            if seeded:
+                w = amm.amm_nn_work(s.h)
+                amm.amm_count_nn_work(s.h, False)
+            out = amm.amm_step(s.h, torch.tensor(X1, device=dev), *sc, amm.AMM_FP32_REFINE, v_hat=vh)
+            torch.cuda.synchronize()
+            got.append((e, rho.cpu().numpy(), vh.cpu().numpy().astype(np.float64), out["energy"]))
+    (es, rs, vs, ss), (ec, rc, vc, sc2) = got
+    print(f"seeded search at 200k: {w['cell_lookups'] / N:.2f} grid cells, {w['box_tests'] / N:.1f} box tests, "
+          f"{w['distance_evals'] / N:.1f} distance evaluations per query", file=sys.stderr)
+    assert w["cell_lookups"] > N // 2          # most queries took the grid
+    assert es == ec and ss == sc2
+    assert np.array_equal(rs, rc)
+    assert np.array_equal(vs, vc)
+    prob = O.from_pair(pr)
+    idx = np.random.default_rng(9011).choice(N, 2000, replace=False)
+    rq, dq, dqs = O.nearest(vs[idx], prob.tgt, threads=8)
+    ok = margin_ok(dq, dqs)
+    assert ok.mean() > 0.99
+    assert np.array_equal(rs[idx][ok], rq[ok])
+
+
 def test_batch64_equals_single_solves():
     """The 64-pair batch (uneven sizes, float32 + refinement, Alg. 2's own
     termination): every pair converges, and sampled pairs solved inside the

@@ -358,7 +358,9 @@ def test_leaf_size_and_autotune_leave_results_unchanged():
 def test_nn_work_counters(pair):
     """Counting the search's work leaves every result unchanged (bitwise),
     counts each query once per evaluation, examines at least one target per
-    query and never more than all targets, and is reproducible."""
+    query and never more than all targets, and is reproducible.  The counted
+    evaluations are seeded by the first one (same X): their closest points
+    equal the cold search's."""
     _announce("test_nn_work_counters")
     prob = O.from_pair(pair)
     X = torch.tensor(synth.perturbed_transforms(prob.n_nodes, 61, 0.01, 0.001), device="cuda:0")
@@ -382,4 +384,6 @@ def test_nn_work_counters(pair):
     assert w2["box_tests"] == 2 * w1["box_tests"]
     assert w2["distance_evals"] == 2 * w1["distance_evals"]
     assert N <= w1["distance_evals"] <= N * pair.n_tgt
-    assert w1["box_tests"] >= 2 * N
+    # seeded by the first evaluation: every query looks up grid cells or
+    # tests boxes (a cold search tests at least the root's two children)
+    assert w1["box_tests"] + w1["cell_lookups"] >= N
