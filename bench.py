@@ -32,28 +32,28 @@ HBM_PEAK_GBS = 8000.0
 # known size (profiles/sh200k_hbm_traffic_counters.txt).  Valid only for the
 # kernel sources they were taken on: a change to those files voids them.
 MEASURED_TRAFFIC = {
-    "cg_step": {"fetch_kib": 3839.9, "fetch_per_byte": 131084.4 / 262144.0,
-                "write_kib": 962.4, "write_per_byte": 262144.0 / 262144.0,
+    "cg_step": {"fetch_kib": 4627.1, "fetch_per_byte": 131084.4 / 262144.0,
+                "write_kib": 1160.1, "write_per_byte": 262144.0 / 262144.0,
                 "sources": {
                             "paper_2206_03410_amd/csrc/amm_cg.hip": "ef6981b89508e89e",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
-                            "paper_2206_03410_amd/csrc/amm_kernels.h": "30716e1a93e33c52",
-                            "paper_2206_03410_amd/csrc/amm_internal.h": "aa7629a5d5676dcd"}},
-    "eval_points": {"fetch_kib": 10098.3, "fetch_per_byte": 131084.4 / 262144.0,
+                            "paper_2206_03410_amd/csrc/amm_kernels.h": "ac086c4e124eaca7",
+                            "paper_2206_03410_amd/csrc/amm_internal.h": "20be0a24a403b073"}},
+    "eval_points": {"fetch_kib": 10749.0, "fetch_per_byte": 131084.4 / 262144.0,
                     "write_kib": 7519.8, "write_per_byte": 262144.0 / 262144.0,
                     "sources": {
-                            "paper_2206_03410_amd/csrc/amm_kernels.hip": "5c746e78bd119812",
-                            "paper_2206_03410_amd/csrc/amm_nn.h": "bcfb64e4adaec57e",
+                            "paper_2206_03410_amd/csrc/amm_kernels.hip": "ecb7b53d33d3672a",
+                            "paper_2206_03410_amd/csrc/amm_nn.h": "18cea587112f0105",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
-                            "paper_2206_03410_amd/csrc/amm_kernels.h": "30716e1a93e33c52",
-                            "paper_2206_03410_amd/csrc/amm_internal.h": "aa7629a5d5676dcd"}},
-    "assemble": {"fetch_kib": 16832.3, "fetch_per_byte": 131084.4 / 262144.0,
-                 "write_kib": 6404.4, "write_per_byte": 262144.0 / 262144.0,
+                            "paper_2206_03410_amd/csrc/amm_kernels.h": "ac086c4e124eaca7",
+                            "paper_2206_03410_amd/csrc/amm_internal.h": "20be0a24a403b073"}},
+    "assemble": {"fetch_kib": 16835.5, "fetch_per_byte": 131084.4 / 262144.0,
+                 "write_kib": 6403.8, "write_per_byte": 262144.0 / 262144.0,
                  "sources": {
-                            "paper_2206_03410_amd/csrc/amm_kernels.hip": "5c746e78bd119812",
+                            "paper_2206_03410_amd/csrc/amm_kernels.hip": "ecb7b53d33d3672a",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
-                            "paper_2206_03410_amd/csrc/amm_kernels.h": "30716e1a93e33c52",
-                            "paper_2206_03410_amd/csrc/amm_internal.h": "aa7629a5d5676dcd"}},
+                            "paper_2206_03410_amd/csrc/amm_kernels.h": "ac086c4e124eaca7",
+                            "paper_2206_03410_amd/csrc/amm_internal.h": "20be0a24a403b073"}},
 }
 
 
@@ -587,7 +587,7 @@ def main():
             f"{tot32['solves']} solve(s), cg {tot32['cg_iters']} refine {tot32['refine_steps']}")
         # the dominant kernel's own duration (events on its dispatches) and the
         # deformed points for the error comparison, one more (untimed) solve
-        _, _, v32, kt32 = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m, timing=dom)
+        st_d, _, v32, kt32 = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m, timing=dom)
         plain = None
         if not args.no_plain:
             w64, st64, tot64 = timed_steps(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.steps, aa_m, repeats)
@@ -624,11 +624,15 @@ def main():
     ab = algorithmic_bytes(pair, T)
     ms_tot, nl = kt32[dom]
     avg_s = ms_tot / nl * 1e-3
-    achieved = ab[dom] / avg_s / 1e9
+    # CG steps queued past convergence return at once and move no data: the
+    # algorithmic bytes are those of the working steps (the solve's CG
+    # iteration count), spread over every launch's time
+    working = min(nl, int(st_d["cg_iters"])) if dom == "cg_step" else nl
+    achieved = ab[dom] * working / nl / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6, "launches": nl,
-                "attainable_copy_GBps": copy_gbs}
+                "working_launches": working, "attainable_copy_GBps": copy_gbs}
     abw = ab
     stages = {}
     for k, v in kt_w.items():
