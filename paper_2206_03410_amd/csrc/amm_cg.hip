@@ -31,6 +31,7 @@
 // (small) coarse vectors of its pair itself, in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include "amm_coarse_inv.h"
 #include "amm_device.h"
 #include "amm_kernels.h"
 
@@ -824,166 +825,12 @@ __global__ void __launch_bounds__(256) k_coarse_sum(CoarseArgs<T> a) {
     }
 }
 
-// Inverse of a symmetric positive definite 4x4 matrix (lower triangle of K
-// read) by its 2x2 block partition [[A, B], [B^T, D]]: with the Schur
-// complement S = D - B^T A^-1 B, the inverse is
-//   [[A^-1 + A^-1 B S^-1 B^T A^-1, -A^-1 B S^-1], [-S^-1 B^T A^-1, S^-1]].
-// False when A or S is not positive definite in floating point.
-__device__ __forceinline__ bool spd_inverse4_schur(const double K[4][4], double out[16]) {
-    const double a = K[0][0], b = K[1][0], c = K[1][1];
-    const double da = a * c - b * b;
-    bool ok = a > 0.0 && da > 0.0;
-    const double ia = 1.0 / da;
-    const double a00 = c * ia, a01 = -b * ia, a11 = a * ia;          // A^-1
-    const double b00 = K[2][0], b01 = K[3][0], b10 = K[2][1], b11 = K[3][1];   // B = K[0:2][2:4]
-    const double g00 = a00 * b00 + a01 * b10, g01 = a00 * b01 + a01 * b11;     // G = A^-1 B
-    const double g10 = a01 * b00 + a11 * b10, g11 = a01 * b01 + a11 * b11;
-    const double s00 = K[2][2] - (b00 * g00 + b10 * g10);
-    const double s01 = K[3][2] - (b00 * g01 + b10 * g11);
-    const double s11 = K[3][3] - (b01 * g01 + b11 * g11);
-    const double ds = s00 * s11 - s01 * s01;
-    ok = ok && s00 > 0.0 && ds > 0.0;
-    const double is = 1.0 / ds;
-    const double t00 = s11 * is, t01 = -s01 * is, t11 = s00 * is;    // S^-1
-    const double h00 = g00 * t00 + g01 * t01, h01 = g00 * t01 + g01 * t11;     // H = G S^-1
-    const double h10 = g10 * t00 + g11 * t01, h11 = g10 * t01 + g11 * t11;
-    out[0] = a00 + (h00 * g00 + h01 * g01);
-    out[1] = a01 + (h00 * g10 + h01 * g11);
-    out[5] = a11 + (h10 * g10 + h11 * g11);
-    out[4] = out[1];
-    out[2] = -h00;
-    out[3] = -h01;
-    out[6] = -h10;
-    out[7] = -h11;
-    out[8] = -h00;
-    out[9] = -h10;
-    out[12] = -h01;
-    out[13] = -h11;
-    out[10] = t00;
-    out[11] = t01;
-    out[14] = t01;
-    out[15] = t11;
-    return ok;
-}
-
-// In-place block Gauss-Jordan inversion of each pair's A_c (symmetric
-// positive definite: no pivoting), float64, pivoting on the 4x4 diagonal
-// block of one aggregate at a time.  Step K, with P = A[K][K]:
-//   A[K][K] = P^-1,  A[K][J] = P^-1 A[K][J],  A[I][K] = -A[I][K] P^-1,
-//   A[I][J] -= A[I][K] P^-1 A[K][J].
-// One block of 1024 threads per pair with the whole matrix in registers:
-// thread t holds column t % nc of the rows t / nc + R m (R = 1024 / nc, at
-// most 16 elements).  Each step publishes the pivot rows and columns to LDS,
-// one wave forms P^-1 (2x2 block Schur complement inverse), and every thread
-// updates its elements.
-// A pivot block that is not positive definite in floating point disables
-// the coarse level of that pair (its inverse is stored as zero).
-// NCT: the coarse order at compile time (0: read at run time)
-template <typename T, int NCT>
-__device__ __forceinline__ void coarse_invert_body(const CoarseArgs<T>& a, const PairInfo& pi) {
-    constexpr int NT = 1024;
-    constexpr int NC = 4 * kCoarseMaxAgg;
-    constexpr int RMAX = NC * NC / NT;   // matrix elements per thread at order NC
-    __shared__ double rowK[4][NC];       // rows k0..k0+3 before the step
-    __shared__ double colK[NC][4];       // columns k0..k0+3 before the step
-    __shared__ double Pi[4][4];          // inverse of the pivot block
-    __shared__ int bad;
-    const int nc = NCT > 0 ? NCT : 4 * pi.nagg;
-    const int R = NT / nc;               // threads per column
-    const int tid = threadIdx.x;
-    const int jc = tid % nc, r0 = tid / nc;
-    const bool own = r0 < R;
-    const int c = jc & 3;
-    // this thread's elements (rows r0, r0 + R, ... of column jc) in registers
-    double m[RMAX];
-    const double* in = a.Ac + pi.ainv_off;
-#pragma unroll
-    for (int t = 0; t < RMAX; ++t) {
-        const int i = r0 + R * t;
-        m[t] = own && i < nc ? in[(size_t)i * nc + jc] : 0.0;
-    }
-    if (tid == 0) bad = 0;
-    for (int K = 0; K < nc / 4; ++K) {
-        const int k0 = 4 * K;
-        const bool cj = (jc >> 2) == K;
-        // publish the pivot rows and columns
-        if (own)
-#pragma unroll
-            for (int t = 0; t < RMAX; ++t) {
-                const int i = r0 + R * t;
-                if (i < nc) {
-                    if ((i >> 2) == K) rowK[i & 3][jc] = m[t];
-                    if (cj) colK[i][c] = m[t];
-                }
-            }
-        __syncthreads();
-        // the pivot block's inverse (symmetric positive definite in exact
-        // arithmetic: the Schur complement of an SPD matrix), by one wave
-        if (tid < 64) {
-            double Kb[4][4], Pv[16];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int q = 0; q <= r; ++q) Kb[r][q] = rowK[r][k0 + q];
-            bool ok = spd_inverse4_schur(Kb, Pv);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) ok = ok && fabs(Pv[e]) < 1e300;
-            if (tid == 0) {
-#pragma unroll
-                for (int e = 0; e < 16; ++e) Pi[e >> 2][e & 3] = Pv[e];
-                if (!ok) bad = 1;
-            }
-        }
-        __syncthreads();
-        if (own) {
-            // column jc of Pi times the pivot rows
-            double rp[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                rp[q] = Pi[q][0] * rowK[0][jc] + Pi[q][1] * rowK[1][jc] + Pi[q][2] * rowK[2][jc] +
-                        Pi[q][3] * rowK[3][jc];
-            const double pc0 = Pi[0][c], pc1 = Pi[1][c], pc2 = Pi[2][c], pc3 = Pi[3][c];
-#pragma unroll
-            for (int t = 0; t < RMAX; ++t) {
-                const int i = r0 + R * t;
-                if (i >= nc) continue;
-                const double c0 = colK[i][0], c1 = colK[i][1], c2 = colK[i][2], c3 = colK[i][3];
-                if ((i >> 2) == K) {
-                    const int q = i & 3;
-                    const double rq = q == 0 ? rp[0] : (q == 1 ? rp[1] : (q == 2 ? rp[2] : rp[3]));
-                    m[t] = cj ? Pi[q][c] : rq;
-                } else if (cj) {
-                    m[t] = -(c0 * pc0 + c1 * pc1 + c2 * pc2 + c3 * pc3);
-                } else {
-                    m[t] -= c0 * rp[0] + c1 * rp[1] + c2 * rp[2] + c3 * rp[3];
-                }
-                // at most four rows of LDS reads in flight (register bound)
-                if ((t & 3) == 3) asm volatile("" ::: "memory");
-            }
-        }
-        __syncthreads();
-    }
-    T* out = a.Ainv + pi.ainv_off;
-    const bool zero = bad != 0;
-    if (own)
-#pragma unroll
-        for (int t = 0; t < RMAX; ++t) {
-            const int i = r0 + R * t;
-            if (i < nc) out[(size_t)i * nc + jc] = zero ? T(0) : (T)m[t];
-        }
-}
-
 template <typename T>
-__global__ void __launch_bounds__(1024) k_coarse_invert(CoarseArgs<T> a) {
+__global__ void __launch_bounds__(kCinvThreads) k_coarse_invert(CoarseArgs<T> a) {
     const int p = blockIdx.x;
     if (!(a.dyn[p].flags & PF_SOLVE)) return;
     const PairInfo& pi = a.info[p];
-    if (pi.nagg == 32)
-        coarse_invert_body<T, 128>(a, pi);
-    else if (pi.nagg == 16)
-        coarse_invert_body<T, 64>(a, pi);
-    else
-        coarse_invert_body<T, 0>(a, pi);
+    coarse_invert_mfma<T>(a.Ac + pi.ainv_off, a.Ainv + pi.ainv_off, pi.nagg);
 }
 
 template <typename T>
@@ -1013,7 +860,7 @@ void launch_coarse(const CoarseArgs<T>& a, int n_nd_tiles, int64_t nagg, int P, 
     hipLaunchKernelGGL(k_coarse_sum<T>, dim3((unsigned)nagg), dim3(256), 0, s, a);
     if (tm) tm->end(s);
     if (tm) tm->begin("coarse_invert", s);
-    hipLaunchKernelGGL(k_coarse_invert<T>, dim3(P), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_coarse_invert<T>, dim3(P), dim3(kCinvThreads), 0, s, a);
     if (tm) tm->end(s);
 }
 
