@@ -35,7 +35,7 @@ MEASURED_TRAFFIC = {
     "cg_step": {"fetch_kib": 4627.1, "fetch_per_byte": 131084.4 / 262144.0,
                 "write_kib": 1160.1, "write_per_byte": 262144.0 / 262144.0,
                 "sources": {
-                            "paper_2206_03410_amd/csrc/amm_cg.hip": "ef6981b89508e89e",
+                            "paper_2206_03410_amd/csrc/amm_cg.hip": "bebb23c05d5f0cbb",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
                             "paper_2206_03410_amd/csrc/amm_kernels.h": "ac086c4e124eaca7",
                             "paper_2206_03410_amd/csrc/amm_internal.h": "20be0a24a403b073"}},
@@ -47,8 +47,8 @@ MEASURED_TRAFFIC = {
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
                             "paper_2206_03410_amd/csrc/amm_kernels.h": "ac086c4e124eaca7",
                             "paper_2206_03410_amd/csrc/amm_internal.h": "20be0a24a403b073"}},
-    "assemble": {"fetch_kib": 16835.5, "fetch_per_byte": 131084.4 / 262144.0,
-                 "write_kib": 6403.8, "write_per_byte": 262144.0 / 262144.0,
+    "assemble": {"fetch_kib": 16835.6, "fetch_per_byte": 131084.4 / 262144.0,
+                 "write_kib": 6403.7, "write_per_byte": 262144.0 / 262144.0,
                  "sources": {
                             "paper_2206_03410_amd/csrc/amm_kernels.hip": "ecb7b53d33d3672a",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
