@@ -1,0 +1,100 @@
+"""Host build of the library's closest-point search (the target layout of
+the set-up code and the tree search the kernels run): against brute force
+over every target, the closest target's index must match exactly, ties
+(duplicate targets, queries on grid points) going to the lowest user index,
+cold and seeded by an arbitrary previous answer, for trees of 1 to 20,000
+targets and leaf sizes 1 to 8."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+PROGRAM = r'''
+#include <cmath>
+#include <cstdio>
+#include <random>
+#include <vector>
+#include "amm_internal.h"
+#include "amm_nn.h"
+using namespace amm;
+struct D4 { double x, y, z, w; };
+int main() {
+    std::mt19937_64 g(3);
+    std::uniform_real_distribution<double> u(-1, 1);
+    int fails = 0;
+    long long searches = 0;
+    for (int M : {1, 3, 4, 5, 17, 64, 100, 1000, 4097, 20000}) {
+        for (int leaf : {1, 2, 4, 8}) {
+            // a height field on a 1/16 grid: many exact duplicates
+            std::vector<double> tgt(3 * (size_t)M);
+            for (int i = 0; i < M; ++i) {
+                tgt[3 * i] = std::round(u(g) * 16) / 16;
+                tgt[3 * i + 1] = std::round(u(g) * 16) / 16;
+                tgt[3 * i + 2] = 0.25 * std::sin(3 * tgt[3 * i]);
+            }
+            TargetLayout tl;
+            target_layout(tgt.data(), M, leaf, tl);
+            PairInfo pi{};
+            pi.M = M;
+            pi.L = tl.L;
+            pi.leaf = leaf;
+            std::vector<D4> t4(M), lo(2 * (size_t)tl.L), hi(2 * (size_t)tl.L);
+            for (int i = 0; i < M; ++i) t4[i] = {tl.tgt4[4 * i], tl.tgt4[4 * i + 1], tl.tgt4[4 * i + 2], tl.tgt4[4 * i + 3]};
+            for (int i = 0; i < 2 * tl.L; ++i) {
+                lo[i] = {tl.box_lo[4 * i], tl.box_lo[4 * i + 1], tl.box_lo[4 * i + 2], 0};
+                hi[i] = {tl.box_hi[4 * i], tl.box_hi[4 * i + 1], tl.box_hi[4 * i + 2], 0};
+            }
+            for (int q = 0; q < 300; ++q) {
+                double qx, qy, qz;
+                if (q % 4 == 0) {
+                    const int k = (int)(g() % M);
+                    qx = tgt[3 * k]; qy = tgt[3 * k + 1]; qz = tgt[3 * k + 2];
+                } else {
+                    qx = 1.5 * u(g); qy = 1.5 * u(g); qz = 0.5 * u(g);
+                }
+                if (q % 7 == 0) { qx = std::round(qx * 32) / 32; qy = std::round(qy * 32) / 32; }
+                double bd = INFINITY;
+                int bid = 0x7fffffff;
+                for (int t = 0; t < M; ++t) {
+                    const double d = sq3(t4[t].x - qx, t4[t].y - qy, t4[t].z - qz);
+                    const int id = (int)t4[t].w;
+                    if (d < bd || (d == bd && id < bid)) { bd = d; bid = id; }
+                }
+                for (int seed = -1; seed < 2; ++seed) {
+                    const int prev = seed < 0 ? -1 : (int)(g() % M);
+                    int pos;
+                    double d2;
+                    nn_search<double, D4>(pi, t4.data(), lo.data(), hi.data(), qx, qy, qz, prev, pos, d2);
+                    ++searches;
+                    if (d2 != bd || (int)t4[pos].w != bid) {
+                        if (fails < 10)
+                            std::printf("M %d leaf %d query %d seed %d: index %d d2 %.17g, brute force %d %.17g\n", M,
+                                        leaf, q, prev, (int)t4[pos].w, d2, bid, bd);
+                        ++fails;
+                    }
+                }
+            }
+        }
+    }
+    std::printf("%d failures over %lld searches\n", fails, searches);
+    return fails != 0;
+}
+'''
+
+
+def test_tree_search_equals_brute_force(tmp_path):
+    hipcc = shutil.which("hipcc") or ("/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else None)
+    if hipcc is None:
+        pytest.skip("no hipcc")
+    src = tmp_path / "nn.hip"
+    src.write_text(PROGRAM)
+    exe = tmp_path / "nn"
+    csrc = os.path.join(ROOT, "paper_2206_03410_amd", "csrc")
+    subprocess.run([hipcc, "-std=c++17", "-O2", "--offload-host-only", "-I", csrc, "-I", os.path.join(ROOT, "include"),
+                    "-x", "hip", str(src), os.path.join(csrc, "amm_setup.cpp"), "-o", str(exe)],
+                   check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout
