@@ -77,6 +77,49 @@ def test_step_sampled_against_oracle(case):
     assert np.sqrt(((vo - vg) ** 2).sum(1).mean()) < 1e-4
 
 
+def test_fp64_step_sampled_against_oracle_sh200k():
+    """One plain float64 MM step on the 200,000-point workload (the other
+    precision the benchmark times) at X = I + delta: energy within 1e-10
+    relative of the oracle's; closest points of 2,000 sampled queries equal
+    the oracle's brute force wherever the best and second-best distances
+    differ by more than 1e-6 relative; the CG solve reaches a relative
+    residual below 1e-10, and the deformed points of the minimizer lie within
+    1e-6 (bounding-box diagonal units) RMS of the oracle's sparse-LU
+    minimizer (the residual bound times the system's conditioning)."""
+    _announce("test_fp64_step_sampled_against_oracle_sh200k")
+    pair = synth.make_workload("sh200k")
+    prob = O.from_pair(pair)
+    nn = _kdtree_nn(prob.tgt)
+    p = O.Params()
+    _, d2i, _ = nn(prob.src, prob.tgt)
+    nu_a, _, nu_r = O.initial_nu(prob, p, d2i)
+    alpha, beta = O.term_weights(prob, p, nu_a, nu_r)
+    X = synth.perturbed_transforms(prob.n_nodes, 7027, 0.01, 0.001)
+    n, N = prob.n_nodes, prob.n_src
+    with Session(pair, torch.float64) as s:
+        dev = "cuda:0"
+        Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+        rho = torch.empty(N, dtype=torch.int32, device=dev)
+        vh = torch.empty(N, 3, dtype=torch.float64, device=dev)
+        Xn = torch.empty(n, 4, 3, dtype=torch.float64, device=dev)
+        out = amm.amm_step(s.h, Xt, nu_a, nu_r, alpha, beta, amm.AMM_FP64_PLAIN, rho=rho, v_hat=vh, X_next=Xn)
+        torch.cuda.synchronize()
+        rho, vh, Xn = rho.cpu().numpy(), vh.cpu().numpy(), Xn.cpu().numpy()
+    ev = O.evaluate(prob, X, nu_a, nu_r, alpha, beta, nn=nn)
+    assert out["energy"][0] == pytest.approx(ev.E, rel=1e-10)
+    assert out["rel_residual"] < 1e-10
+    idx = np.random.default_rng(7028).choice(N, 2000, replace=False)
+    rq, dq, dqs = O.nearest(vh[idx], prob.tgt, threads=8)
+    ok = margin_ok(dq, dqs)
+    assert ok.mean() > 0.99
+    assert np.array_equal(rho[idx][ok], rq[ok])
+    Xo = np.asarray(O.mm_update(prob, ev, nu_a, nu_r, alpha, beta)[0])
+    rms = np.sqrt(((O.warp(prob, Xo) - O.warp(prob, Xn)) ** 2).sum(1).mean())
+    print(f"sh200k FP64 step: E {out['energy'][0]:.12e} vs {ev.E:.12e}, rms {rms:.2e}, cg {out['cg_iters']}",
+          file=sys.stderr)
+    assert rms < 1e-6
+
+
 def test_seeded_search_equals_cold_search_sh200k():
     """Closest points of the 200,000-point workload (float32) at X1 = X0 +
     small step, searched with the closest points at X0 as seeds (the grid
