@@ -802,14 +802,18 @@ __global__ void __launch_bounds__(256) k_coarse_sum(CoarseArgs<T> a) {
             const int o = threadIdx.x + 256 * h;
             if (o >= pi.nagg * 16) continue;
             const int b = o >> 4, m = o & 15;
+            // unrolled so that the tiles' loads are in flight together; a tile
+            // without a slot for b adds +0.0, which leaves the sum's bits alone
+            // (it starts at +0 and an in-order sum never turns into -0)
             double v = 0;
+#pragma unroll 8
             for (int t = 0; t < nt; ++t) {
                 const int cnt = lst[t][0];
+                int sl = -1;
                 for (int s2 = 0; s2 < cnt; ++s2)
-                    if (lst[t][1 + s2] == b) {
-                        v += a.Ac_tile[(size_t)(tb + t) * kCoarseMaxAgg * 16 + 16 * s2 + m];
-                        break;
-                    }
+                    if (sl < 0 && lst[t][1 + s2] == b) sl = s2;
+                const double x = sl >= 0 ? a.Ac_tile[(size_t)(tb + t) * kCoarseMaxAgg * 16 + 16 * sl + m] : 0.0;
+                v += x;
             }
             if (h == 0) acc0 += v;
             else acc1 += v;

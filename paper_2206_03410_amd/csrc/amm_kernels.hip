@@ -325,11 +325,15 @@ __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
     if (!(dy.flags & PF_EVAL)) return;
     const PairInfo pi = a.info[p];
     double sa = 0, sr = 0, so = 0, mx = 0;
+    // unrolled so that several partials are loaded before their (in-order) sum
+#pragma unroll 8
     for (int t = threadIdx.x; t < pi.pt_ntile; t += 64) {
         sa += a.pt_part[pi.pt_tile0 + t];
         mx = fmax(mx, a.pt_max[pi.pt_tile0 + t]);
     }
+#pragma unroll 4
     for (int t = threadIdx.x; t < pi.eg_ntile; t += 64) sr += a.eg_part[pi.eg_tile0 + t];
+#pragma unroll 4
     for (int t = threadIdx.x; t < pi.nd_ntile; t += 64) so += a.nd_part[pi.nd_tile0 + t];
     sa = wave_sum(sa);
     sr = wave_sum(sr);
@@ -737,7 +741,9 @@ __global__ void __launch_bounds__(512) k_aa_solve(AaSolveArgs a) {
     for (int e = threadIdx.x; e < NG * kAaParts; e += 512) {
         const int grp = e / kAaParts, g = e - grp * kAaParts;
         double s = 0;
+        // unrolled so that several partials are loaded before their (in-order) sum
         if (g < ng)
+#pragma unroll 8
             for (int t = grp; t < pi.nd_ntile; t += NG) s += a.part[(size_t)(pi.nd_tile0 + t) * kAaParts + g];
         vg[grp][g] = s;
     }
