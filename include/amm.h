@@ -167,6 +167,10 @@ typedef struct {
     double max_disp;             /* last max displacement */
     double max_rel_residual;     /* worst final relative residual over all solves */
     double time_ms;              /* wall time of the solve for this pair */
+    /* surrogate solves whose final relative residual stayed above cg_rtol
+     * (float32 refinement stopped improving, or the CG step budget ran out);
+     * 0 when every solve of Eq. (21) met its tolerance */
+    int32_t solves_above_rtol;
 } amm_stats;
 
 /* One MM iteration (one surrogate solve) of one pair, as decided by Alg. 2. */
@@ -234,6 +238,15 @@ amm_status amm_set_workspace(amm_handle* h, void* ptr, size_t bytes);
  * for warm-started searches).  Replaces any previous problems. */
 amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_pairs);
 amm_status amm_set_problem(amm_handle* h, const amm_problem* p);
+
+/* Sizes of the batch set on the handle (host outputs, each nullable): the
+ * pair count (the length of the stats array amm_solve fills), and the totals
+ * over pairs of source points (rows of v_out and of gV), graph nodes (rows
+ * of X_inout, of X and of gX) and target points, and k.  For pair 0 alone
+ * (amm_step, amm_energy, amm_energy_grad) use n_pairs = 1 batches.
+ * AMM_ERR_STATE before a problem is set. */
+amm_status amm_get_sizes(const amm_handle* h, int32_t* n_pairs, int64_t* n_src_total, int64_t* n_nodes_total,
+                         int64_t* n_tgt_total, int32_t* k);
 
 /* Targets per leaf of the closest-point tree (1..256, default 8) used by the
  * next amm_workspace_size / amm_set_problems.  Smaller leaves make the

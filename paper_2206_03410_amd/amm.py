@@ -51,7 +51,8 @@ class amm_stats(C.Structure):
                 ("energy", C.c_double), ("e_align", C.c_double), ("e_reg", C.c_double),
                 ("e_rot", C.c_double), ("nu_a", C.c_double), ("nu_r", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("max_disp", C.c_double),
-                ("max_rel_residual", C.c_double), ("time_ms", C.c_double)]
+                ("max_rel_residual", C.c_double), ("time_ms", C.c_double),
+                ("solves_above_rtol", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -131,6 +132,8 @@ def lib():
             "amm_solve": ([vp, C.POINTER(amm_params), vp, vp, C.POINTER(amm_stats)], C.c_int),
             "amm_step": ([vp, C.POINTER(amm_step_in), C.POINTER(amm_step_out)], C.c_int),
             "amm_k_nnzb": ([vp, C.POINTER(i64)], C.c_int),
+            "amm_get_sizes": ([vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                               C.POINTER(i32)], C.c_int),
             "amm_iter_log": ([vp, C.POINTER(amm_iter_record), i32, C.POINTER(i32)], C.c_int),
             "amm_energy": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, C.POINTER(dbl), vp, vp], C.c_int),
             "amm_energy_grad": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, vp, vp, C.POINTER(dbl)],
@@ -155,7 +158,7 @@ EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
             "amm_set_leaf_size", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
             "amm_build_graph", "amm_graph_copy", "amm_set_targets", "amm_build_graphs", "amm_graph_copy_set",
-            "amm_solve", "amm_step", "amm_k_nnzb", "amm_iter_log", "amm_energy", "amm_energy_grad",
+            "amm_solve", "amm_step", "amm_k_nnzb", "amm_get_sizes", "amm_iter_log", "amm_energy", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
 
@@ -182,6 +185,24 @@ def _ptr(a):
     if not a.is_contiguous():
         raise ValueError("tensors must be contiguous")
     return a.data_ptr()
+
+
+def _device_buffer(name, a, dtype_code, numel):
+    """Checks a device buffer before its raw pointer goes to the library:
+    a contiguous tensor on a GPU with the element type and the element count
+    that the call writes or reads (None passes)."""
+    if a is None:
+        return
+    if isinstance(a, np.ndarray) or not getattr(a, "is_cuda", False):
+        raise TypeError(f"{name} must be a tensor on the GPU")
+    if not a.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype_code is not None:
+        want = {AMM_F32: "float32", AMM_F64: "float64", "int32": "int32"}[dtype_code]
+        if str(a.dtype).split(".")[-1] != want:
+            raise TypeError(f"{name} must be {want}, got {a.dtype}")
+    if a.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {a.numel()}")
 
 
 def _dtype_code(a):
@@ -372,8 +393,31 @@ def amm_set_problem(handle, problem: amm_problem) -> None:
     _check(lib().amm_set_problem(handle, C.byref(problem)), handle)
 
 
-def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: int = 1,
+def amm_get_sizes(handle) -> dict:
+    """Sizes of the batch set on the handle: pairs, and the totals of source
+    points, graph nodes and target points over the pairs, and k."""
+    P, k = C.c_int32(), C.c_int32()
+    N, n, M = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().amm_get_sizes(handle, C.byref(P), C.byref(N), C.byref(n), C.byref(M), C.byref(k)), handle)
+    return dict(n_pairs=P.value, n_src=N.value, n_nodes=n.value, n_tgt=M.value, k=k.value)
+
+
+def _precision_dtype(precision):
+    return AMM_F32 if precision == AMM_FP32_REFINE else AMM_F64
+
+
+def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: Optional[int] = None,
               force_accept=None, force_stage_end=None) -> List[dict]:
+    """Alg. 2 for every pair on the handle; returns one stats dict per pair.
+    X_inout ([nodes][4][3] over all pairs) and v_out ([points][3]) are GPU
+    tensors of the precision's type (float32 for AMM_FP32_REFINE, float64
+    for AMM_FP64_PLAIN), checked against the handle's sizes."""
+    sz = amm_get_sizes(handle)
+    if n_pairs is not None and n_pairs != sz["n_pairs"]:
+        raise ValueError(f"n_pairs={n_pairs} but the handle holds {sz['n_pairs']} pairs")
+    dt = _precision_dtype(params.precision)
+    _device_buffer("X_inout", X_inout, dt, 12 * sz["n_nodes"])
+    _device_buffer("v_out", v_out, dt, 3 * sz["n_src"])
     keep = []
     if force_accept is not None or force_stage_end is not None:
         n = max(len(force_accept or []), len(force_stage_end or []))
@@ -387,7 +431,7 @@ def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: int
         params.force_accept = fa.ctypes.data
         params.force_stage_end = fs.ctypes.data
         params.force_len = n
-    stats = (amm_stats * n_pairs)()
+    stats = (amm_stats * sz["n_pairs"])()
     _check(lib().amm_solve(handle, C.byref(params), _ptr(X_inout), _ptr(v_out), stats), handle)
     del keep
     return [s.as_dict() for s in stats]
@@ -396,6 +440,22 @@ def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: int
 def amm_step(handle, X, nu_a, nu_r, alpha, beta, precision, cg_rtol=1e-10, cg_maxit=0,
              cg_precond=AMM_PRECOND_TWO_LEVEL, rho=None, d2=None, v_hat=None, X_next=None, K_blocks=None, K_row=None, K_col=None,
              B=None, robust=AMM_ROBUST_WELSCH) -> dict:
+    sz = amm_get_sizes(handle)
+    dt = _precision_dtype(precision)
+    n, N = sz["n_nodes"], sz["n_src"]
+    _device_buffer("X", X, dt, 12 * n)
+    if X is None:
+        raise ValueError("X is required")
+    _device_buffer("rho", rho, "int32", N)
+    _device_buffer("d2", d2, dt, N)
+    _device_buffer("v_hat", v_hat, dt, 3 * N)
+    _device_buffer("X_next", X_next, dt, 12 * n)
+    _device_buffer("B", B, dt, 12 * n)
+    if K_blocks is not None or K_row is not None or K_col is not None:
+        nnzb = amm_k_nnzb(handle)
+        _device_buffer("K_blocks", K_blocks, dt, 16 * nnzb)
+        _device_buffer("K_row", K_row, "int32", nnzb)
+        _device_buffer("K_col", K_col, "int32", nnzb)
     sin = amm_step_in(X=_ptr(X), nu_a=nu_a, nu_r=nu_r, alpha=alpha, beta=beta,
                       precision=precision, cg_rtol=cg_rtol, cg_maxit=cg_maxit, cg_precond=cg_precond,
                       robust=robust)
@@ -419,7 +479,22 @@ def amm_k_nnzb(handle) -> int:
     return n.value
 
 
+def _energy_buffers(handle, X, src, rho=None, d2=None, gX=None, gV=None):
+    if X is None:
+        raise ValueError("X is required")
+    sz = amm_get_sizes(handle)
+    dt = _dtype_code(X)
+    n, N = sz["n_nodes"], sz["n_src"]
+    _device_buffer("X", X, dt, 12 * n)
+    _device_buffer("src", src, dt, 3 * N)
+    _device_buffer("rho", rho, "int32", N)
+    _device_buffer("d2", d2, dt, N)
+    _device_buffer("gX", gX, dt, 12 * n)
+    _device_buffer("gV", gV, dt, 3 * N)
+
+
 def amm_energy(handle, X, src=None, nu_a=1.0, nu_r=1.0, alpha=0.0, beta=0.0, rho=None, d2=None):
+    _energy_buffers(handle, X, src, rho=rho, d2=d2)
     e = (C.c_double * 4)()
     _check(lib().amm_energy(handle, _dtype_code(X), _ptr(X), _ptr(src), nu_a, nu_r, alpha, beta, e,
                             _ptr(rho), _ptr(d2)), handle)
@@ -427,6 +502,9 @@ def amm_energy(handle, X, src=None, nu_a=1.0, nu_r=1.0, alpha=0.0, beta=0.0, rho
 
 
 def amm_energy_grad(handle, X, src, nu_a, nu_r, alpha, beta, gX, gV=None):
+    if gX is None:
+        raise ValueError("gX is required")
+    _energy_buffers(handle, X, src, gX=gX, gV=gV)
     e = (C.c_double * 4)()
     _check(lib().amm_energy_grad(handle, _dtype_code(X), _ptr(X), _ptr(src), nu_a, nu_r, alpha, beta,
                                  _ptr(gX), _ptr(gV), e), handle)

@@ -1118,6 +1118,7 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
             st.st.cg_iters += rep.cg_iters[p];
             st.st.refine_steps += rep.refine[p];
             st.st.max_rel_residual = std::max(st.st.max_rel_residual, rep.rel[p]);
+            if (!(rep.rel[p] <= rtol)) st.st.solves_above_rtol += 1;
             rec[p].energy_after = o.E;
             rec[p].max_disp = o.maxdisp;
             h->iter_log.push_back(rec[p]);
@@ -1789,6 +1790,22 @@ amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, i
     if (!h || !count) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
     *count = (int32_t)h->iter_log.size();
     for (int32_t i = 0; i < *count && i < capacity && out; ++i) out[i] = h->iter_log[i];
+    return AMM_OK;
+}
+
+amm_status amm_get_sizes(const amm_handle* h, int32_t* n_pairs, int64_t* n_src_total, int64_t* n_nodes_total,
+                         int64_t* n_tgt_total, int32_t* k) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    if (!h->has_problem) {
+        g_last_error = "no problem set";
+        const_cast<amm_handle*>(h)->err = g_last_error;
+        return AMM_ERR_STATE;
+    }
+    if (n_pairs) *n_pairs = h->L.P;
+    if (n_src_total) *n_src_total = h->L.Ntot;
+    if (n_nodes_total) *n_nodes_total = h->L.ntot;
+    if (n_tgt_total) *n_tgt_total = h->L.Mtot;
+    if (k) *k = h->L.k;
     return AMM_OK;
 }
 

@@ -236,3 +236,44 @@ def test_null_handle_calls_are_rejected():
     assert L.amm_k_nnzb(None, C.byref(n)) == amm.AMM_ERR_INVALID_ARG
     p = amm.amm_params_default()
     assert L.amm_solve(None, C.byref(p), None, None, None) == amm.AMM_ERR_INVALID_ARG
+
+
+def test_size_query_needs_a_handle():
+    L = amm.lib()
+    P, k = C.c_int32(), C.c_int32()
+    N, n, M = C.c_int64(), C.c_int64(), C.c_int64()
+    assert L.amm_get_sizes(None, C.byref(P), C.byref(N), C.byref(n), C.byref(M), C.byref(k)) == \
+        amm.AMM_ERR_INVALID_ARG
+
+
+def test_binding_rejects_mismatched_device_buffers():
+    """Raw pointers reach the library only for GPU tensors of the element
+    type and count the call uses: a host array, a CPU tensor, a wrong dtype,
+    a wrong size or a non-contiguous view raise before any call."""
+    import torch
+    with pytest.raises(TypeError):
+        amm._device_buffer("X", np.zeros(12, np.float32), amm.AMM_F32, 12)
+    with pytest.raises(TypeError):
+        amm._device_buffer("X", torch.zeros(12, dtype=torch.float32), amm.AMM_F32, 12)
+    amm._device_buffer("X", None, amm.AMM_F32, 12)   # optional buffers pass
+
+    class FakeCuda:
+        is_cuda = True
+
+        def __init__(self, dtype, n, contiguous=True):
+            self.dtype, self.n, self.c = dtype, n, contiguous
+
+        def is_contiguous(self):
+            return self.c
+
+        def numel(self):
+            return self.n
+    amm._device_buffer("X", FakeCuda(torch.float32, 12), amm.AMM_F32, 12)
+    with pytest.raises(TypeError):
+        amm._device_buffer("X", FakeCuda(torch.float64, 12), amm.AMM_F32, 12)
+    with pytest.raises(ValueError):
+        amm._device_buffer("X", FakeCuda(torch.float32, 24), amm.AMM_F32, 12)
+    with pytest.raises(ValueError):
+        amm._device_buffer("X", FakeCuda(torch.float32, 12, contiguous=False), amm.AMM_F32, 12)
+    with pytest.raises(TypeError):
+        amm._device_buffer("rho", FakeCuda(torch.int64, 5), "int32", 5)

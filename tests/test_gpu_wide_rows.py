@@ -62,7 +62,7 @@ def test_wide_rows_follow_the_oracle():
 def test_wide_rows_fp32_step_matches_oracle_step():
     """One float32 + refinement step at X = I + delta against the oracle's
     sparse-LU step at the same X: deformed points of the surrogate
-    minimizer within 1e-5 RMS, relative residual below 1e-9."""
+    minimizer within 1e-5 RMS, relative residual at most 1e-10."""
     _announce("test_wide_rows_fp32_step_matches_oracle_step")
     pair = _wide_pair()
     pr = dataclasses.replace(pair, src=pair.src.astype(np.float32).astype(np.float64),
@@ -84,5 +84,5 @@ def test_wide_rows_fp32_step_matches_oracle_step():
     Xo = np.asarray(O.mm_update(prob, ev, nu_a, nu_r, alpha, beta)[0])
     rms = math.sqrt(((O.warp(prob, Xo) - O.warp(prob, Xn)) ** 2).sum(1).mean())
     print(f"wide rows fp32 step: rms {rms:.3e}, rel residual {out['rel_residual']:.3e}", file=sys.stderr)
-    assert out["rel_residual"] < 1e-9
+    assert out["rel_residual"] <= 1e-10
     assert rms < 1e-5

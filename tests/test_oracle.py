@@ -363,6 +363,61 @@ def test_large_nu_limit_is_l2_least_squares(small_prob):
     assert np.abs(Xl - Xn.reshape(-1, 3)).max() < 1e-7
 
 
+def _line_problem(mean_edge_len):
+    """Ten source points on a line, five nodes joined as a path (four
+    undirected edges), one influence per point: only the counts |V| = 10,
+    |V_G| = 5, |E_G| = 4 and l matter to the parameter rules."""
+    src = np.stack([np.arange(10.0), np.zeros(10), np.zeros(10)], 1)
+    node_idx = np.array([0, 2, 4, 6, 8])
+    infl_idx = (np.arange(10) // 2)[:, None]
+    infl_w = np.ones((10, 1))
+    edges = np.array([[0, 1], [1, 2], [2, 3], [3, 4]])
+    return O.Problem(src, src.copy(), node_idx, infl_idx, infl_w, edges, mean_edge_len)
+
+
+def test_term_weights_hand_values_unequal_nu():
+    """Eq. (26) by hand at nu_a = 0.1, nu_r = 0.3 (k_alpha = 100, k_beta = 1):
+    alpha = 100 * (10/4) * (0.3/0.1)^2 = 2250 and beta = (10/5) / (2 * 0.1^2)
+    = 100.  An inverted nu_r^2/nu_a^2 ratio would give 250/9, a missing one
+    250; nu_r in place of nu_a in beta would give 11.1."""
+    prob = _line_problem(1.0)
+    alpha, beta = O.term_weights(prob, O.Params(), 0.1, 0.3)
+    assert alpha == pytest.approx(2250.0, rel=1e-13)
+    assert beta == pytest.approx(100.0, rel=1e-13)
+    # the ratio is what scales alpha: halving both (a stage change) keeps it
+    a2, b2 = O.term_weights(prob, O.Params(), 0.05, 0.15)
+    assert a2 == pytest.approx(2250.0, rel=1e-13)
+    assert b2 == pytest.approx(400.0, rel=1e-13)
+    a3, b3 = O.term_weights(prob, O.Params(k_alpha=7.0, k_beta=3.0), 0.2, 0.1)
+    assert a3 == pytest.approx(7.0 * 2.5 * 0.25, rel=1e-13)
+    assert b3 == pytest.approx(3.0 * 2.0 / 0.08, rel=1e-13)
+
+
+@pytest.mark.parametrize("d2,lbar,want_nu_a", [
+    # odd count: the middle distance 0.3 (the mean would be 0.72)
+    ([0.04, 4.0, 0.01, 1.0, 0.09], 0.1, 0.3),
+    # even count: the mean of the two middle distances, (2 + 3)/2 = 2.5; the
+    # square root of the median of d^2 would be sqrt(6.5) = 2.55, the mean 4
+    ([100.0, 1.0, 9.0, 4.0], 0.1, 2.5),
+    # median below the bound: clamped to l/sqrt(3) = sqrt(3)
+    ([0.04, 4.0, 0.01, 1.0, 0.09], 3.0, math.sqrt(3.0)),
+])
+def test_initial_nu_hand_values(d2, lbar, want_nu_a):
+    """Sec. 3.3.3: nu_a starts at the median closest-point distance (not of
+    the squared distances, not the mean), is never below l/sqrt(3), and
+    nu_r starts at 3 l."""
+    prob = _line_problem(lbar)
+    nu_a, nu_min, nu_r = O.initial_nu(prob, O.Params(), np.array(d2))
+    assert nu_a == pytest.approx(want_nu_a, rel=1e-14)
+    assert nu_min == pytest.approx(lbar / math.sqrt(3.0), rel=1e-14)
+    assert nu_r == pytest.approx(3.0 * lbar, rel=1e-14)
+    # explicit start values override the rules, the bound still applies
+    a2, m2, r2 = O.initial_nu(prob, O.Params(nu_a0=5.0, nu_r0=0.7, nu_a_min=0.2), np.array(d2))
+    assert (a2, m2, r2) == (5.0, 0.2, 0.7)
+    a3, _, _ = O.initial_nu(prob, O.Params(nu_a0=0.01, nu_a_min=0.2), np.array(d2))
+    assert a3 == 0.2
+
+
 # --------------------------------------------------------------------------
 # Sec. 4.1 variants: squared norms and fixed nu
 # --------------------------------------------------------------------------
