@@ -143,6 +143,29 @@ def run_solve(amm, torch, h, pair, prec, iters, aa_m, timing=None):
     return st, wall, v.cpu().numpy().astype(np.float64), kt
 
 
+def replayed_precision_error(amm, torch, h, pair, steps, aa_m, v64, st64):
+    """Error of the FP32 + refinement path against the plain FP64 path along
+    the same trajectory: the FP32 solve replays the FP64 run's Anderson
+    accept/reject decisions and stage ends (free runs of the two part at the
+    first decision either takes differently, and Anderson mixing then
+    amplifies the difference), so what remains is the precision's own error.
+    Deformed points as RMS over the bounding-box diagonal, energy relative."""
+    log64 = amm.amm_iter_log(h)
+    fa = [bool(r["accepted"]) if r["aa_used"] else None for r in log64]
+    fs = [1 if (b is None or b["stage"] != a["stage"]) else 0 for a, b in zip(log64, log64[1:] + [None])]
+    X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")
+    v = torch.empty(pair.n_src, 3, dtype=torch.float32, device="cuda:0")
+    prm = amm.amm_params_default(aa_m=aa_m, max_total_iters=steps, precision=amm.AMM_FP32_REFINE)
+    st = amm.amm_solve(h, prm, X, v, force_accept=fa, force_stage_end=fs)[0]
+    torch.cuda.synchronize()
+    v32 = v.cpu().numpy().astype(np.float64)
+    diag = float(np.linalg.norm(pair.tgt.max(0) - pair.tgt.min(0)))
+    return {"iters": st["iters"], "iters_fp64": st64["iters"],
+            "vhat_rms_over_diag": math.sqrt(((v32 - v64) ** 2).sum(1).mean()) / diag,
+            "energy_rel": abs(st["energy"] - st64["energy"]) / abs(st64["energy"]),
+            "solves_above_rtol": st["solves_above_rtol"]}
+
+
 def timed_steps(amm, torch, h, pair, prec, steps, aa_m, repeats):
     """Exactly `steps` MM iterations per timed region: solves from X = I run
     back to back (a solve that converges early is followed by another, the
@@ -356,9 +379,10 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
     a separate, untimed solve) against the eval_points kernel's measured
     average launch time.  Headline candidate traffic per launch = queries x
     (12 B warped query + 8 B outputs) + target points examined x 16 B (one
-    float4 each).  The search structure's own reads (box corners, cell
-    bounds) are reported apart: they are mostly cache hits, not HBM
-    traffic."""
+    float4 each).  The search structure's own reads (nine 4-byte run starts
+    per octree cell expansion read from memory) are reported apart: they
+    are mostly cache hits, not HBM traffic; cell lower-bound tests read
+    nothing (the cell's box follows from its coordinates)."""
     amm.amm_count_nn_work(h, True)
     try:
         run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, steps, aa_m)
@@ -369,11 +393,11 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
     q, bx, de, cl = (w[k] / launches for k in ("queries", "box_tests", "distance_evals", "cell_lookups"))
     t = eval_ms / eval_launches * 1e-3
     cand = q * (12 + 8) + de * 16
-    struct = bx * 32 + cl * 8
+    struct = cl * 36
     comp = pair.n_src * (12 + 4 + 4) + 12 * pair.n_tgt
-    flops = 8 * de + 12 * bx
+    flops = 8 * de + 14 * bx
     return {"kernel": "eval_points", "avg_launch_us": t * 1e6, "queries_per_launch": q,
-            "box_tests_per_query": bx / q, "cell_lookups_per_query": cl / q,
+            "cell_bound_tests_per_query": bx / q, "cell_expansions_from_memory_per_query": cl / q,
             "distance_evals_per_query": de / q,
             "compulsory_GBps": comp / t / 1e9,
             "compulsory_frac": comp / t / 1e9 / HBM_PEAK_GBS,
@@ -384,9 +408,9 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
             "search_flops_frac_fp32_valu": flops / t / 157.3e12,
             "definition": "candidate traffic = queries x (12 B warped point + 8 B closest index and "
                           "squared distance) + target points examined x 16 B, per launch, over the "
-                          "kernel's average launch time; structure reads (box lower-bound tests x 32 B + "
-                          "grid cell lookups x 8 B) are cache traffic, reported apart; flops: 8 per "
-                          "distance evaluation, 12 per box test"}
+                          "kernel's average launch time; structure reads (octree cell expansions read "
+                          "from memory x 36 B; the upper four levels are in LDS) are cache traffic, "
+                          "reported apart; flops: 8 per distance evaluation, 14 per cell bound test"}
 
 
 def graph_build_report(amm, torch, h, pair, k, with_cpu):
@@ -648,6 +672,7 @@ def main():
         if not args.no_plain:
             w64, st64, tot64 = timed_steps(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.steps, aa_m, repeats)
             st64d, _, v64, _ = run_solve(amm, torch, h, pair, amm.AMM_FP64_PLAIN, args.steps, aa_m)
+            rep = replayed_precision_error(amm, torch, h, pair, args.steps, aa_m, v64, st64d)
             wall64 = float(np.median(w64))
             log(f"[bench] fp64 plain: {args.steps} iters, median {wall64:.4f}s; {tot64['solves']} solve(s), "
                 f"cg {tot64['cg_iters']}")
@@ -660,18 +685,19 @@ def main():
                      "rmse_gt_fp32": rm32, "rmse_gt_fp64": rm64,
                      "equal_error": abs(rm32 - rm64) <= max(1e-4, 0.01 * rm64),
                      "speedup_fp32_refine": wall64 / wall32,
-                     # the FP32 + refinement result against the FP64 path's after the same
+                     # free runs (each path takes its own Anderson decisions): the FP32 result against the FP64 one after the same
                      # number of MM iterations: deformed points (RMS over the target bounding-box
                      # diagonal) and the final energy
-                     "vhat_rms_fp32_vs_fp64_over_diag": math.sqrt(((v32 - v64) ** 2).sum(1).mean()) / diag,
-                     "energy_rel_diff_fp32_vs_fp64": abs(st_d["energy"] - st64d["energy"]) / abs(st64d["energy"]),
-                     "solves_above_rtol": [st_d["solves_above_rtol"], st64d["solves_above_rtol"]]}
+                     "free_run_vhat_rms_fp32_vs_fp64_over_diag": math.sqrt(((v32 - v64) ** 2).sum(1).mean()) / diag,
+                     "free_run_energy_rel_diff_fp32_vs_fp64": abs(st_d["energy"] - st64d["energy"]) / abs(st64d["energy"]),
+                     "solves_above_rtol": [st_d["solves_above_rtol"], st64d["solves_above_rtol"]],
+                     "fp32_replayed_vs_fp64": rep}
         # the search's average launch time over the same solve that is counted
         _, _, _, kt_e = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m,
                                   timing="eval_points")
         nn = nn_search_report(amm, torch, h, pair, aa_m, args.steps, *kt_e["eval_points"])
-        log(f"[bench] closest points: {nn['box_tests_per_query']:.1f} box tests, "
-            f"{nn['cell_lookups_per_query']:.1f} grid cells and "
+        log(f"[bench] closest points: {nn['cell_bound_tests_per_query']:.1f} cell bound tests, "
+            f"{nn['cell_expansions_from_memory_per_query']:.1f} cell expansions from memory and "
             f"{nn['distance_evals_per_query']:.1f} distance evaluations per query; candidate traffic "
             f"{nn['candidate_traffic_GBps']:.0f} GB/s")
         copy_gbs = copy_bandwidth(torch)

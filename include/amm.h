@@ -139,13 +139,16 @@ typedef struct {
     /* Replay of decisions (host arrays, may be NULL): entry t applies to the
      * t-th surrogate solve.  force_accept: -1 decide, 0 reject the Anderson
      * candidate, 1 accept it.  force_stage_end: -1 decide, 0 continue the
-     * stage, 1 end it. */
+     * stage, 1 end it.  With force_per_pair = 0 every pair reads the same
+     * force_len entries; with 1 the arrays hold one row of force_len
+     * entries per pair (row p for pair p). */
     const int8_t* force_accept;
     const int8_t* force_stage_end;
     int32_t force_len;
     int32_t cg_precond;           /* amm_precond (0 = two-level, the default) */
     int32_t robust;               /* amm_robust (0 = Welsch, the method) */
     int32_t nu_mode;              /* amm_nu_mode (0 = dynamic, the method) */
+    int32_t force_per_pair;
 } amm_params;
 
 #define AMM_MAX_AA_M 10
@@ -248,13 +251,18 @@ amm_status amm_set_problem(amm_handle* h, const amm_problem* p);
 amm_status amm_get_sizes(const amm_handle* h, int32_t* n_pairs, int64_t* n_src_total, int64_t* n_nodes_total,
                          int64_t* n_tgt_total, int32_t* k);
 
-/* Targets per leaf of the closest-point tree (1..256, default 8) used by the
- * next amm_workspace_size / amm_set_problems.  Smaller leaves make the
- * search deeper, larger ones scan more targets per leaf. */
+/* Cell size of the closest-point search structure, as the mean number of
+ * targets per occupied leaf cell (1..256, default 8), used by the next
+ * amm_workspace_size / amm_set_problems.  Each pair's targets are sorted
+ * along a Morton curve and covered by an implicit octree of cells
+ * (Morton prefixes); the pair's depth is the smallest in 2..8 whose
+ * occupied leaf cells hold at most this many targets on average.  Smaller
+ * values make the octree deeper (more cells read per search), larger ones
+ * scan more targets per leaf. */
 amm_status amm_set_leaf_size(amm_handle* h, int32_t leaf);
 
 /* Autotuner: uploads the problems once per candidate leaf size (candidates
- * NULL: 4, 8, 16, 32), times a warm-started float32 evaluation (warp,
+ * NULL: 2, 4, 8, 16), times a warm-started float32 evaluation (warp,
  * closest points, Welsch terms, the per-iteration search of Alg. 2) of
  * every pair at X = I with HIP events, and leaves the handle set up with the
  * fastest.  best_leaf and best_ms (host, nullable) receive the choice and
@@ -287,10 +295,11 @@ amm_status amm_iter_log(amm_handle* h, amm_iter_record* out, int32_t capacity, i
  * evaluation (solve, step, energy) to a counting variant of its kernel,
  * which is slower; 0 switches back and frees them.  amm_set_problems also
  * switches counting off.  amm_nn_work returns, since counting was switched
- * on: the queries searched, the bounding-box lower-bound tests (each reads
- * two box corners), the target distance evaluations (each reads one
- * target) and, if cell_lookups is not null, the grid cell lookups of
- * warm-started searches (each reads two cell bounds).  Errors:
+ * on: the queries searched, the cell lower-bound tests (computed from the
+ * cell's coordinates, no memory read), the target distance evaluations
+ * (each reads one target) and, if cell_lookups is not null, the cell
+ * expansions that read their children's nine run starts from memory (the
+ * upper levels, kept in LDS, are not counted).  Errors:
  * AMM_ERR_STATE before a problem is set, or when counting is off. */
 amm_status amm_count_nn_work(amm_handle* h, int32_t enable);
 amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int64_t* distance_evals,

@@ -532,7 +532,8 @@ def fixed_nu(nu_a, nu_min, nu_r, mode):
 # --------------------------------------------------------------------------
 
 def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
-          force: Optional[List[Optional[bool]]] = None, log_evals: bool = False):
+          force: Optional[List[Optional[bool]]] = None, log_evals: bool = False,
+          force_stage_end: Optional[List[Optional[bool]]] = None, step_noise=None):
     """Alg. 2: nu continuation around MM iterations accelerated by Anderson
     acceleration with the energy-decrease safeguard.
 
@@ -553,7 +554,11 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
     * Sec. 4.1 variants: a fixed nu_mode holds (nu_a, nu_r) at fixed_nu's
       values for one stage; "l2" has no parameter to update and runs one
       stage; "l2r" follows the dynamic update of nu_a like the method.
-    `force[t]` overrides the accept/reject decision of solve t (replay)."""
+    `force[t]` overrides the accept/reject decision of solve t and
+    `force_stage_end[t]` whether a stage ends after it (replay).
+    `step_noise` = (seed, sigma) adds seeded N(0, sigma^2) noise to every
+    surrogate minimizer, to measure how the trajectory responds to an
+    inexact step (a sensitivity probe for the tests, not part of Alg. 2)."""
     rb = p.robust
     X = identity(prob.n_nodes) if X0 is None else np.array(X0, np.float64)
     ev0 = evaluate(prob, X, 1.0, 1.0, 0.0, 0.0, nn=nn)
@@ -568,12 +573,15 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
     log = []
     total = 0
     stage = 0
+    noise_rng = np.random.default_rng(step_noise[0]) if step_noise is not None else None
     while True:
         hist_G: List[np.ndarray] = []
         hist_F: List[np.ndarray] = []
         it = 0
         while True:
             Xn, _, _ = mm_update(prob, ev, nu_a, nu_r, alpha, beta, rb)
+            if noise_rng is not None:
+                Xn = Xn + step_noise[1] * noise_rng.standard_normal(Xn.shape)
             hist_G.append(Xn.reshape(-1).copy())
             hist_F.append((Xn - X).reshape(-1))
             if len(hist_G) > p.aa_m + 1:
@@ -607,7 +615,11 @@ def solve(prob: Problem, p: Params, X0: Optional[np.ndarray] = None, nn=None,
             it += 1
             total += 1
             budget = p.max_total_iters > 0 and total >= p.max_total_iters
-            if disp < p.eps or it >= p.imax or budget:
+            end = disp < p.eps or it >= p.imax
+            if force_stage_end is not None and total - 1 < len(force_stage_end) \
+                    and force_stage_end[total - 1] is not None:
+                end = bool(force_stage_end[total - 1])
+            if end or budget:
                 break
         if nu_a == nu_min or (p.max_total_iters > 0 and total >= p.max_total_iters):
             break

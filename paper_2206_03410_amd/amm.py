@@ -41,7 +41,7 @@ class amm_params(C.Structure):
                 ("init_identity", C.c_int32),
                 ("force_accept", C.c_void_p), ("force_stage_end", C.c_void_p),
                 ("force_len", C.c_int32), ("cg_precond", C.c_int32), ("robust", C.c_int32),
-                ("nu_mode", C.c_int32)]
+                ("nu_mode", C.c_int32), ("force_per_pair", C.c_int32)]
 
 
 class amm_stats(C.Structure):
@@ -407,11 +407,13 @@ def _precision_dtype(precision):
 
 
 def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: Optional[int] = None,
-              force_accept=None, force_stage_end=None) -> List[dict]:
+              force_accept=None, force_stage_end=None, per_pair: bool = False) -> List[dict]:
     """Alg. 2 for every pair on the handle; returns one stats dict per pair.
     X_inout ([nodes][4][3] over all pairs) and v_out ([points][3]) are GPU
     tensors of the precision's type (float32 for AMM_FP32_REFINE, float64
-    for AMM_FP64_PLAIN), checked against the handle's sizes."""
+    for AMM_FP64_PLAIN), checked against the handle's sizes.  Replayed
+    decisions (None = decide) are one list for all pairs, or with per_pair
+    one list per pair."""
     sz = amm_get_sizes(handle)
     if n_pairs is not None and n_pairs != sz["n_pairs"]:
         raise ValueError(f"n_pairs={n_pairs} but the handle holds {sz['n_pairs']} pairs")
@@ -420,17 +422,27 @@ def amm_solve(handle, params: amm_params, X_inout=None, v_out=None, n_pairs: Opt
     _device_buffer("v_out", v_out, dt, 3 * sz["n_src"])
     keep = []
     if force_accept is not None or force_stage_end is not None:
-        n = max(len(force_accept or []), len(force_stage_end or []))
-        fa = np.full(n, -1, np.int8)
-        fs = np.full(n, -1, np.int8)
-        if force_accept is not None:
-            fa[:len(force_accept)] = [-1 if v is None else int(v) for v in force_accept]
-        if force_stage_end is not None:
-            fs[:len(force_stage_end)] = [-1 if v is None else int(v) for v in force_stage_end]
+        # one list for every pair, or (per_pair) one list per pair
+        rows_a = force_accept if per_pair else [force_accept]
+        rows_s = force_stage_end if per_pair else [force_stage_end]
+        R = sz["n_pairs"] if per_pair else 1
+        rows_a = rows_a if rows_a is not None else [None] * R
+        rows_s = rows_s if rows_s is not None else [None] * R
+        if len(rows_a) != R or len(rows_s) != R:
+            raise ValueError(f"per-pair decision lists need {R} rows")
+        n = max([len(r or []) for r in rows_a] + [len(r or []) for r in rows_s] + [1])
+        fa = np.full((R, n), -1, np.int8)
+        fs = np.full((R, n), -1, np.int8)
+        for q in range(R):
+            if rows_a[q] is not None:
+                fa[q, :len(rows_a[q])] = [-1 if v is None else int(v) for v in rows_a[q]]
+            if rows_s[q] is not None:
+                fs[q, :len(rows_s[q])] = [-1 if v is None else int(v) for v in rows_s[q]]
         keep = [fa, fs]
         params.force_accept = fa.ctypes.data
         params.force_stage_end = fs.ctypes.data
         params.force_len = n
+        params.force_per_pair = 1 if per_pair else 0
     stats = (amm_stats * sz["n_pairs"])()
     _check(lib().amm_solve(handle, C.byref(params), _ptr(X_inout), _ptr(v_out), stats), handle)
     del keep

@@ -132,8 +132,6 @@ struct StaticT {
     T* iw_pt = nullptr;
     typename V4Of<T>::type* nodes = nullptr;
     typename V4Of<T>::type* tgt = nullptr;
-    typename V4Of<T>::type* blo = nullptr;
-    typename V4Of<T>::type* bhi = nullptr;
     T* adj_r = nullptr;
     typename V4Of<T>::type* node_rel = nullptr;
 };
@@ -214,7 +212,7 @@ struct Dev {
 };
 
 void plan(const Layout& L, Carver& c, Dev& v) {
-    const size_t N = L.Ntot, M = L.Mtot, n = L.ntot, na = L.nadj, nb = L.nnzb, tn = L.tree_nodes;
+    const size_t N = L.Ntot, M = L.Mtot, n = L.ntot, na = L.nadj, nb = L.nnzb;
     const size_t npt = L.n_pt_tiles, nnd = L.n_nd_tiles, neg = L.n_eg_tiles;
     const size_t k = L.k;
     c.take(v.iidx, k * N);
@@ -248,7 +246,7 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     v.dyn = v.dyn_ring;
     c.take(v.out, L.P);
     c.take(v.state, 2 * (size_t)L.P);
-    size_t stage = std::max({4 * N, 4 * M, 4 * tn, (size_t)kMaxK * N, 4 * n, na});
+    size_t stage = std::max({4 * N, 4 * M, (size_t)kMaxK * N, 4 * n, na});
     c.take(v.staging, stage);
     auto statics = [&](auto& s) {
         c.take(s.src, N);
@@ -256,8 +254,6 @@ void plan(const Layout& L, Carver& c, Dev& v) {
         c.take(s.iw_pt, (size_t)kMaxK * N);
         c.take(s.nodes, n);
         c.take(s.tgt, M);
-        c.take(s.blo, tn);
-        c.take(s.bhi, tn);
         c.take(s.adj_r, na);
         c.take(s.node_rel, n);
     };
@@ -337,7 +333,7 @@ struct amm_handle {
     size_t h_cap = 0;
     bool timing = false;
     bool cg_coarse = true;           // two-level CG preconditioner
-    int leaf = 8;                    // targets per leaf of the closest-point tree (next upload)
+    int leaf = 8;                    // mean targets per occupied octree leaf cell (next upload)
     long long* nn_work = nullptr;    // [n_pt_tiles][4] search counters while counting is on
     int nn_work_tiles = 0;
     GraphBuild* graph = nullptr;     // last amm_build_graph result
@@ -520,8 +516,6 @@ EvalArgs<T> eval_args(amm_handle* h, bool use_override = false) {
     a.Ntot = h->L.Ntot;
     a.nodes = s.nodes;
     a.tgt = s.tgt;
-    a.blo = s.blo;
-    a.bhi = s.bhi;
     a.grid = h->v.grid_cells;
     a.adj_row = h->v.adj_row;
     a.adj_nbr = h->v.adj_nbr;
@@ -1084,8 +1078,9 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
             bool acc = true;
             if (o.aa_used != 0) {
                 acc = o.E < st.E_cur;
-                if (prm.force_accept && st.total < prm.force_len && prm.force_accept[st.total] >= 0)
-                    acc = prm.force_accept[st.total] != 0;
+                const int64_t fo = (prm.force_per_pair ? (int64_t)p * prm.force_len : 0) + st.total;
+                if (prm.force_accept && st.total < prm.force_len && prm.force_accept[fo] >= 0)
+                    acc = prm.force_accept[fo] != 0;
                 (acc ? st.st.aa_accepted : st.st.aa_rejected) += 1;
             }
             r.accepted = o.aa_used != 0 ? (acc ? 1 : 0) : -1;
@@ -1126,8 +1121,9 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
             const bool budget = prm.max_total_iters > 0 && st.total >= prm.max_total_iters;
             bool end = o.maxdisp < prm.eps || st.it >= prm.imax || budget;
             const int t = st.total - 1;
-            if (prm.force_stage_end && t < prm.force_len && prm.force_stage_end[t] >= 0)
-                end = prm.force_stage_end[t] != 0;
+            const int64_t fo = (prm.force_per_pair ? (int64_t)p * prm.force_len : 0) + t;
+            if (prm.force_stage_end && t < prm.force_len && prm.force_stage_end[fo] >= 0)
+                end = prm.force_stage_end[fo] != 0;
             if (!end) continue;
             if (st.nu_a == st.nu_min || budget) {
                 st.done = true;
@@ -1217,7 +1213,6 @@ amm_status energy_impl(amm_handle* h, const void* X, const void* src, double nu_
     dy = PairDyn{};
     dy.flags = PF_EVAL;
     dy.has_prev = h->rho_set0 ? 1 : 0;   // seeds only: the search is exact either way
-    dy.use_grid = 1;
     set_scalars(dy, nu_a, nu_r, alpha, beta);
     TRY(evaluate<T>(h, src != nullptr));
     if (energy) {
@@ -1282,7 +1277,6 @@ amm_status step_impl(amm_handle* h, const amm_step_in* in, amm_step_out* out) {
     dy = PairDyn{};
     dy.flags = PF_EVAL;
     dy.has_prev = h->rho_set0 ? 1 : 0;   // seeds only: the search is exact either way
-    dy.use_grid = 1;
     set_scalars(dy, in->nu_a, in->nu_r, in->alpha, in->beta, in->robust);
     TRY(evaluate<T>(h));
     out->energy[0] = h->h_out[0].E;
@@ -1512,8 +1506,6 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up_real(h, v.sf.iw_pt, v.sd.iw_pt, Lr.iw_pt));
     TRY(up_real(h, v.sf.nodes, v.sd.nodes, Lr.nodes4));
     TRY(up_real(h, v.sf.tgt, v.sd.tgt, Lr.tgt4));
-    TRY(up_real(h, v.sf.blo, v.sd.blo, Lr.box_lo));
-    TRY(up_real(h, v.sf.bhi, v.sd.bhi, Lr.box_hi));
     TRY(up_real(h, v.sf.adj_r, v.sd.adj_r, Lr.adj_r));
     TRY(up_real(h, v.sf.node_rel, v.sd.node_rel, Lr.node_rel));
     TRY(up(h, reinterpret_cast<int32_t*>(v.aggs), Lr.aggs));
@@ -1585,7 +1577,7 @@ amm_status time_warm_eval(amm_handle* h, double& ms) {
 amm_status amm_autotune(amm_handle* h, const amm_problem* probs, int32_t n_pairs, const int32_t* candidates,
                         int32_t n_candidates, int32_t* best_leaf, double* best_ms) {
     if (!h || !probs) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
-    static const int32_t kDefault[] = {4, 8, 16, 32};
+    static const int32_t kDefault[] = {2, 4, 8, 16};
     if (!candidates) {
         candidates = kDefault;
         n_candidates = 4;
@@ -1675,19 +1667,17 @@ amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const v
                          : (double)reinterpret_cast<const float*>(raw.data())[i];
         if (!std::isfinite(tgt[i])) return fail(h, AMM_ERR_NONFINITE, "non-finite target coordinate");
     }
+    // the octree keeps the pair's depth, so its tables keep their size
     TargetLayout tl;
-    target_layout(tgt.data(), n_tgt, pi.leaf, tl);
-    if (tl.L != pi.L) return fail(h, AMM_ERR_STATE, "target tree shape changed");
+    target_layout(tgt.data(), n_tgt, h->leaf, tl, pi.grid_bits);
     Layout& L = h->L;
     std::copy(tl.tgt4.begin(), tl.tgt4.end(), L.tgt4.begin() + 4 * pi.tgt_off);
     std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + pi.tgt_off);
-    std::copy(tl.box_lo.begin(), tl.box_lo.end(), L.box_lo.begin() + 4 * pi.tree_off);
-    std::copy(tl.box_hi.begin(), tl.box_hi.end(), L.box_hi.begin() + 4 * pi.tree_off);
-    if (tl.grid_bits != pi.grid_bits) return fail(h, AMM_ERR_STATE, "target grid shape changed");
     std::copy(tl.cells.begin(), tl.cells.end(), L.grid_cells.begin() + pi.grid_off);
     for (int c = 0; c < 3; ++c) {
         pi.glo[c] = tl.glo[c];
         pi.gscale[c] = tl.gscale[c];
+        pi.cs[c] = tl.cs[c];
     }
     pi.gpad = tl.gpad;
     Dev& v = h->v;
@@ -1705,10 +1695,6 @@ amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const v
     };
     TRY(put(reinterpret_cast<float*>(v.sf.tgt + pi.tgt_off), reinterpret_cast<double*>(v.sd.tgt + pi.tgt_off),
             tl.tgt4));
-    TRY(put(reinterpret_cast<float*>(v.sf.blo + pi.tree_off), reinterpret_cast<double*>(v.sd.blo + pi.tree_off),
-            tl.box_lo));
-    TRY(put(reinterpret_cast<float*>(v.sf.bhi + pi.tree_off), reinterpret_cast<double*>(v.sd.bhi + pi.tree_off),
-            tl.box_hi));
     return AMM_OK;
 }
 

@@ -17,9 +17,6 @@ struct PairInfo {
     int64_t tgt_off, M;      // target points (sorted by Morton code)
     int64_t node_off, n;     // graph nodes (internal, Morton order)
     int64_t adj_off, nadj;   // directed adjacency entries (2 |E_G|)
-    int64_t tree_off;        // offset of this pair's box array (heap layout, 2L entries)
-    int32_t L;               // leaves of the implicit tree (power of two)
-    int32_t leaf;            // targets per leaf
     int32_t pt_tile0, pt_ntile;   // point tiles
     int32_t nd_tile0, nd_ntile;   // node tiles (solver rows)
     int32_t eg_tile0, eg_ntile;   // edge tiles
@@ -30,15 +27,17 @@ struct PairInfo {
     // 4 nagg) starts at ainv_off
     int32_t agg0, nagg, agg_shift;
     int64_t ainv_off;
-    // closest-point grid over the targets: cell (cx, cy, cz) holds the
-    // targets whose 10-bit quantized coordinates (x - glo) gscale have those
-    // top grid_bits bits; the cells are Morton prefixes of the targets' sort
-    // order, cell m spans sorted targets [cells[grid_off + m],
-    // cells[grid_off + m + 1]).  gpad: a distance margin covering rounding in
-    // the cell bounds (1e-6 of the largest extent)
+    // closest-point octree over the targets: a cell of level l holds the
+    // targets whose 10-bit quantized coordinates floor((x - glo) gscale)
+    // share their top l bits on every axis, i.e. a Morton prefix of the
+    // targets' sort order.  Level l's 8^l + 1 run starts begin at grid_off +
+    // oct_level_off(l), for l = 0..grid_bits (the leaf level).  cs: the root
+    // cell's size per axis, 1024 / gscale (0 on a flat axis); gpad: a
+    // distance margin covering the rounding of cell bounds and of the
+    // targets' stored coordinates
     int64_t grid_off;
     int32_t grid_bits, pad_g;
-    double glo[3], gscale[3], gpad;
+    double glo[3], gscale[3], cs[3], gpad;
 };
 
 // Dynamic per-pair state the host writes before launches.
@@ -58,8 +57,7 @@ struct PairDyn {
     int32_t aa_slot[11];     // ring slots: [0] = newest (k), [1] = k-1, ...
     int32_t has_prev;        // closest-point warm start available in set `cur`
     int32_t robust;          // amm_robust
-    int32_t use_grid;        // warm-started searches may scan the target grid
-    int32_t pad_d;
+    int32_t pad_c, pad_d;
     double cg_rtol;          // CG stopping tolerance of this pair (0: the launch's)
 };
 
@@ -94,7 +92,7 @@ struct HostPair {
 // Everything set_problems uploads (built on the host).
 struct Layout {
     int P = 0, k = 0;
-    int64_t Ntot = 0, Mtot = 0, ntot = 0, nadj = 0, nnzb = 0, tree_nodes = 0, pj_entries = 0;
+    int64_t Ntot = 0, Mtot = 0, ntot = 0, nadj = 0, nnzb = 0, pj_entries = 0;
     int n_pt_tiles = 0, n_nd_tiles = 0, n_eg_tiles = 0;
     std::vector<PairInfo> info;
     std::vector<double> src4;        // [Ntot][4] internal order
@@ -117,7 +115,6 @@ struct Layout {
     std::vector<uint64_t> pj_pos;
     std::vector<double> tgt4;        // [Mtot][4] sorted; w = user index within the pair
     std::vector<int32_t> tgt_user;   // sorted position -> user index within the pair
-    std::vector<double> box_lo, box_hi;    // [tree_nodes][4]
     std::vector<int32_t> pt_tiles, nd_tiles, eg_tiles;   // [tiles][4] = pair, start, end, 0
     int max_row_cols = 0;
     // coarse level: per aggregate (pair, first node, end node, pair-local id),
@@ -127,7 +124,7 @@ struct Layout {
     std::vector<int32_t> aggs;       // [nagg][4]
     std::vector<double> node_rel;    // [ntot][4]
     std::vector<int32_t> tile_agg_ptr, tile_agg;
-    std::vector<int32_t> grid_cells;   // per pair, the target grid's cell starts
+    std::vector<int32_t> grid_cells;   // per pair, the target octree's run-start tables
     // per node tile, the distinct column nodes of its rows of K (sorted;
     // [tiles][kTileColCap], padded with the first), their count (a tile with
     // more than kTileColCap has no list), the local index of every K block's
@@ -143,18 +140,28 @@ constexpr int kMaxCols = 192;        // K blocks per row supported by the assemb
 static_assert(kMaxCols < 255, "column positions are stored in one byte");
 constexpr unsigned kPosUnused = 255;  // column byte of an unused influence slot
 
+// Offset of level l's run-start table within a pair's concatenated octree
+// tables: the sum over j < l of (8^j + 1).
+constexpr int64_t oct_level_off(int l) { return ((int64_t(1) << (3 * l)) - 1) / 7 + l; }
+// Levels whose tables a block of the evaluation kernel copies to LDS
+// (levels 0..4: 4,686 starts, 18.7 KB); deeper tables are read from memory.
+constexpr int kOctLdsLevels = 4;
+constexpr int kOctLdsInts = (int)oct_level_off(kOctLdsLevels + 1);
+constexpr int kOctMaxDepth = 8;
+
 // One pair's targets in search order: [M][4] (w = user index), the user
-// index per position, and the implicit complete box tree over leaf-sized
-// buckets ([2L][4], node 1 the root).
+// index per position, and the octree's run-start tables of levels
+// 0..grid_bits, concatenated.  The depth is the smallest in 2..8 whose
+// occupied leaf cells hold at most `leaf` targets on average (8 if none),
+// unless `depth` (2..8) fixes it.
 struct TargetLayout {
-    std::vector<double> tgt4, box_lo, box_hi;
+    std::vector<double> tgt4;
     std::vector<int32_t> tgt_user;
-    int32_t L = 0;
     int32_t grid_bits = 0;
-    double glo[3] = {0, 0, 0}, gscale[3] = {0, 0, 0}, gpad = 0;
-    std::vector<int32_t> cells;      // [8^grid_bits + 1]
+    double glo[3] = {0, 0, 0}, gscale[3] = {0, 0, 0}, cs[3] = {0, 0, 0}, gpad = 0;
+    std::vector<int32_t> cells;      // sum over l <= grid_bits of (8^l + 1)
 };
-void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out);
+void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out, int depth = 0);
 
 // Device-built deformation graph (Alg. 1), kept by a handle between
 // amm_build_graph and amm_graph_copy.  stream is a hipStream_t.

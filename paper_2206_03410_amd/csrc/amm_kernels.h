@@ -55,9 +55,7 @@ struct EvalArgs {
     int64_t Ntot;
     const V* nodes;
     const V* tgt;
-    const V* blo;
-    const V* bhi;
-    const int* grid;         // per pair, the target grid's cell starts (PairInfo.grid_off)
+    const int* grid;         // per pair, the target octree's run-start tables (PairInfo.grid_off)
     const int* adj_row;
     const int* adj_nbr;
     const T* adj_r;
@@ -73,7 +71,8 @@ struct EvalArgs {
     double* pt_max;
     double* eg_part;
     double* nd_part;
-    long long* nn_work;      // per point tile: queries, box tests, distance evaluations (or null)
+    long long* nn_work;      // per point tile: queries, cell bound tests, distance evaluations,
+                             // cell expansions read from memory (or null)
 };
 
 struct FinalArgs {

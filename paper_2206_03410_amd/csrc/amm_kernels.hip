@@ -29,6 +29,7 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     using V = typename V4Of<T>::type;
     __shared__ T sh[kPointTile];
     __shared__ long long shc[COUNT ? kPointTile : 1];
+    __shared__ int oct[kOctLdsInts];
     NnWork wk{0, 0, 0};
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int4 td = a.pt_tiles[tile];
@@ -36,6 +37,13 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     const PairDyn dy = a.dyn[p];
     if (!(dy.flags & PF_EVAL)) return;                 // uniform over the block
     const PairInfo pi = a.info[p];
+    // the octree's upper levels (every search starts there) into LDS
+    const int* cells = a.grid + pi.grid_off;
+    {
+        const int nl = (int)oct_level_off(min(pi.grid_bits, kOctLdsLevels) + 1);
+        for (int q = (int)threadIdx.x; q < nl; q += kPointTile) oct[q] = cells[q];
+        __syncthreads();
+    }
     const int i = td.y + (int)threadIdx.x;
     const int dst = dy.eval_dst, cur = dy.cur;
     const T* X = a.X[dy.eval_x];
@@ -69,14 +77,7 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
         const int prev = dy.has_prev ? a.rho[cur][i] - (int)pi.tgt_off : -1;
         int bpos;
         T d2;
-        // seeded by an exact previous answer (energy, gradient, step calls):
-        // scan the grid cells its distance covers; the tree where that range
-        // is wide, for cold searches, and inside solves (there the seeds are
-        // looser and the far points' tree searches, in nearly every wave,
-        // would run after the grid scan)
-        const bool in_grid = dy.use_grid && prev >= 0 &&
-                             grid_search<T, V, COUNT>(pi, a.grid, a.tgt, vx, vy, vz, prev, bpos, d2, &wk);
-        if (!in_grid) nn_search<T, V, COUNT>(pi, a.tgt, a.blo, a.bhi, vx, vy, vz, prev, bpos, d2, &wk);
+        oct_search<T, V, COUNT>(pi, cells, oct, a.tgt, vx, vy, vz, prev, bpos, d2, &wk);
         const V u = a.tgt[pi.tgt_off + bpos];
         // e_i = v_hat_i - u_rho(i)
         //     = sum_j w_ij ((A_j - I) d_ij + t_j) + (v_i - u) + (sum_j w_ij - 1) v_i

@@ -1,5 +1,14 @@
-// Exact closest-point search over the implicit box tree (shared by the
-// kernels and host-side checks; plain arithmetic only).
+// Exact closest-point search over an implicit octree of the targets (shared
+// by the kernels and host-side checks; plain arithmetic only).
+//
+// The targets of a pair are sorted by a 30-bit Morton code (10 bits per axis
+// of the coordinate quantized over the targets' bounding box).  A cell of
+// level l (0 = the whole box, G = the leaves) is a prefix of 3 l code bits,
+// so its targets are one contiguous run of the sorted array.  Level l keeps
+// a table of 8^l + 1 run starts (cell m spans [T_l[m], T_l[m + 1])), and the
+// eight children of cell m are cells 8 m .. 8 m + 7 of level l + 1: one
+// contiguous read of nine starts gives every child's occupancy.  A cell's
+// box is not stored: it is computed from the cell's integer coordinates.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,10 +23,11 @@ namespace amm {
 template <typename T> __host__ __device__ inline T nn_inf() { return (T)INFINITY; }
 
 // Squared length with one fixed evaluation shape (explicit fma chain).  The
-// point distance and the box lower bound use the same shape, so the computed
-// box bound never exceeds the computed distance of a point inside the box
-// (every step is monotone in |dx|, |dy|, |dz|): pruning with `box > best`
-// is therefore exact in floating point.
+// point distance and the cell lower bound use the same shape, and every
+// step is monotone in |dx|, |dy|, |dz|, so a cell bound that does not exceed
+// the per-axis distances of the cell's targets does not exceed their
+// computed squared distances either: pruning with `bound > best` is exact in
+// floating point.
 template <typename T>
 __host__ __device__ inline T sq3(T dx, T dy, T dz) {
     T s = dz * dz;
@@ -26,179 +36,207 @@ __host__ __device__ inline T sq3(T dx, T dy, T dz) {
     return s;
 }
 
-template <typename T, typename V>
-__host__ __device__ inline T box_d2(const V& lo, const V& hi, T qx, T qy, T qz) {
-    T dx = fmax(fmax(lo.x - qx, qx - hi.x), T(0));
-    T dy = fmax(fmax(lo.y - qy, qy - hi.y), T(0));
-    T dz = fmax(fmax(lo.z - qz, qz - hi.z), T(0));
-    return sq3(dx, dy, dz);
-}
 
 // ---------------------------------------------------------------- closest point
 
-// Work of one search, counted only where asked for (COUNT = true): box
-// lower-bound tests, target distance evaluations and grid cell lookups.
+// Work of one search, counted only where asked for (COUNT = true): cell
+// lower-bound tests (arithmetic only), target distance evaluations (each
+// reads one target) and cell expansions that read nine run starts from
+// memory (expansions served from the LDS copy are not counted).
 struct NnWork {
     int boxes;
     int points;
     int cells;
 };
 
-// Exact closest target of query q among the pair's targets, by depth-first
-// traversal of the implicit complete binary tree of boxes (heap layout: node
-// 1 is the root, children 2i and 2i+1, leaves L..2L-1 each holding `leaf`
-// consecutive Morton-sorted targets).  Near child first; pending far
-// children are kept as one bit per level (no stack).  `prev` (a target
-// position from the previous evaluation, or -1) seeds the bound.  Ties in
-// distance go to the lowest user target index (stored in .w).  With COUNT,
-// `work` accumulates the box tests and distance evaluations.
+// Lower bound of the distance from q to the cell of integer coordinate j
+// (a float holding an integer) along one axis, for cells of size s:
+// a = glo - pad - q and b = q - glo - pad, so the cell spans
+// [glo + j s, glo + (j + 1) s] widened by pad (which covers the rounding of
+// these products and of the targets' stored coordinates).
+template <typename T>
+__host__ __device__ inline T oct_axis(T a, T b, T s, T j) {
+    return (T)fmax(fmax((T)fma(j, s, a), (T)fma(-(j + T(1)), s, b)), T(0));
+}
+
+// Exact closest target of q among the pair's targets: depth-first search of
+// the octree.  Expanding a cell reads its children's nine run starts and
+// keeps the occupied children whose lower bound does not exceed the best
+// squared distance so far; they are visited in the order of their octant
+// relative to the query (its own octant first, the opposite one last), and
+// a child's bound is tested again when its turn comes (the best distance
+// only shrinks).  `prev` (a sorted target position from an earlier
+// evaluation, or -1) seeds the bound.  Ties in distance go to the lowest
+// user target index (stored in .w), and the minimum of (distance, index)
+// does not depend on the visiting order, so the result is that of a
+// brute-force scan with the same distance shape.
+//
+// cells: this pair's tables (levels 0..G); near: a copy of levels
+// 0..min(G, kOctLdsLevels) (LDS on the device, or `cells` itself).  The
+// children still to visit are one byte per level of a 64-bit mask (bit j =
+// child j ^ octant), the query's octant three bits per level, so the
+// search keeps no stack.
 template <typename T, typename V, bool COUNT = false>
-__host__ __device__ inline void nn_search(const PairInfo& pi, const V* __restrict__ tgt,
-                                          const V* __restrict__ blo,
-                                          const V* __restrict__ bhi, T qx, T qy,
-                                          T qz, int prev, int& best_pos, T& best_d2,
-                                          NnWork* work = nullptr) {
-    const V* lo = blo + pi.tree_off;
-    const V* hi = bhi + pi.tree_off;
+__host__ __device__ inline void oct_search(const PairInfo& pi, const int* __restrict__ cells,
+                                           const int* __restrict__ near, const V* __restrict__ tgt, T qx, T qy,
+                                           T qz, int prev, int& best_pos, T& best_d2, NnWork* work = nullptr) {
     const V* tg = tgt + pi.tgt_off;
-    const unsigned L = (unsigned)pi.L;
-    const int LB = pi.leaf;
-    const int M = (int)pi.M;
     T bd = nn_inf<T>();
     int bid = INT_MAX, bpos = -1;
     if (prev >= 0) {
-        V u = tg[prev];
+        const V u = tg[prev];
         bd = sq3(u.x - qx, u.y - qy, u.z - qz);
         bid = (int)u.w;
         bpos = prev;
         if constexpr (COUNT) work->points += 1;
     }
-    unsigned node = 1, trail = 0;
-    int depth = 0;
+    const int G = pi.grid_bits;
+    const T pad = (T)pi.gpad;
+    const T ax = ((T)pi.glo[0] - pad) - qx, bx = qx - ((T)pi.glo[0] + pad);
+    const T ay = ((T)pi.glo[1] - pad) - qy, by = qy - ((T)pi.glo[1] + pad);
+    const T az = ((T)pi.glo[2] - pad) - qz, bz = qz - ((T)pi.glo[2] + pad);
+    // the query's coordinates in units of the root cell (for its octant)
+    const T ux = pi.cs[0] > 0 ? (qx - (T)pi.glo[0]) / (T)pi.cs[0] : T(0);
+    const T uy = pi.cs[1] > 0 ? (qy - (T)pi.glo[1]) / (T)pi.cs[1] : T(0);
+    const T uz = pi.cs[2] > 0 ? (qz - (T)pi.glo[2]) / (T)pi.cs[2] : T(0);
+    // children's size at the current level (halved on the way down, doubled
+    // on the way up: powers of two, exact); children's first coordinate 2 c
+    T sx = (T)pi.cs[0] * T(0.5), sy = (T)pi.cs[1] * T(0.5), sz = (T)pi.cs[2] * T(0.5);
+    T jx = 0, jy = 0, jz = 0;         // 2 x the current cell's coordinates
+    int l = 0;                        // level of the current cell
+    uint32_t m = 0;                   // its Morton index
+    uint64_t pend = 0;                // children still to visit, one byte per level
+    uint32_t oct = 0;                 // the query's octant, three bits per level
+    // run starts of the current level G - 1 cell's children
+    int ls0 = 0, ls1 = 0, ls2 = 0, ls3 = 0, ls4 = 0, ls5 = 0, ls6 = 0, ls7 = 0, ls8 = 0;
+    bool expand = true;
     while (true) {
-        if (node < L) {
-            const unsigned c0 = node << 1, c1 = c0 | 1u;
-            const T d0 = box_d2<T>(lo[c0], hi[c0], qx, qy, qz);
-            const T d1 = box_d2<T>(lo[c1], hi[c1], qx, qy, qz);
-            if constexpr (COUNT) work->boxes += 2;
-            const bool first0 = d0 <= d1;
-            const T dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
-            if (dn <= bd) {
-                if (df <= bd) trail |= 1u << (depth + 1);
-                node = first0 ? c0 : c1;
-                ++depth;
-                continue;
+        if (expand) {
+            // (two branches, so each read keeps its own address space)
+            const int64_t o = oct_level_off(l + 1) + 8 * (int64_t)m;
+            int st[9];
+            if (l < kOctLdsLevels) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) st[q] = near[o + q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) st[q] = cells[o + q];
+                if constexpr (COUNT) work->cells += 1;
             }
-        } else {
-            const int s = (int)(node - L) * LB;
-            const int e = min(s + LB, M);
+            if (l == G - 1) {
+                ls0 = st[0];
+                ls1 = st[1];
+                ls2 = st[2];
+                ls3 = st[3];
+                ls4 = st[4];
+                ls5 = st[5];
+                ls6 = st[6];
+                ls7 = st[7];
+                ls8 = st[8];
+            }
+            // the eight children's bounds from two values per axis
+            const T dx0 = oct_axis(ax, bx, sx, jx), dx1 = oct_axis(ax, bx, sx, jx + T(1));
+            const T dy0 = oct_axis(ay, by, sy, jy), dy1 = oct_axis(ay, by, sy, jy + T(1));
+            const T dz0 = oct_axis(az, bz, sz, jz), dz1 = oct_axis(az, bz, sz, jz + T(1));
+            const T z0 = dz0 * dz0, z1 = dz1 * dz1;
+            const T y00 = (T)fma(dy0, dy0, z0), y01 = (T)fma(dy0, dy0, z1), y10 = (T)fma(dy1, dy1, z0),
+                    y11 = (T)fma(dy1, dy1, z1);
+            const T cb[8] = {(T)fma(dx0, dx0, y00), (T)fma(dx0, dx0, y01), (T)fma(dx0, dx0, y10),
+                             (T)fma(dx0, dx0, y11), (T)fma(dx1, dx1, y00), (T)fma(dx1, dx1, y01),
+                             (T)fma(dx1, dx1, y10), (T)fma(dx1, dx1, y11)};
+            // the query's octant in this cell: which half of each axis
+            const T half = ldexp(T(1), -(l + 1));
+            const uint32_t qo = (ux >= (jx + T(1)) * half ? 4u : 0u) | (uy >= (jy + T(1)) * half ? 2u : 0u) |
+                                (uz >= (jz + T(1)) * half ? 1u : 0u);
+            uint32_t keep = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) keep |= (st[c + 1] > st[c] && cb[c] <= bd ? 1u : 0u) << c;
+            // bit j of the visiting mask = child j ^ qo
+            keep = (qo & 4u) ? ((keep >> 4) | (keep << 4)) & 0xffu : keep;
+            keep = (qo & 2u) ? ((keep >> 2) & 0x33u) | ((keep << 2) & 0xccu) : keep;
+            keep = (qo & 1u) ? ((keep >> 1) & 0x55u) | ((keep << 1) & 0xaau) : keep;
+            if constexpr (COUNT) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) work->boxes += st[c + 1] > st[c] ? 1 : 0;
+            }
+            pend = (pend & ~(0xffull << (8 * l))) | ((uint64_t)keep << (8 * l));
+            oct = (oct & ~(7u << (3 * l))) | (qo << (3 * l));
+        }
+        const uint32_t pm = (uint32_t)(pend >> (8 * l)) & 0xffu;
+        if (pm == 0) {
+            if (l == 0) break;
+            m >>= 3;
+            jx = T(2) * floor(jx * T(0.25));
+            jy = T(2) * floor(jy * T(0.25));
+            jz = T(2) * floor(jz * T(0.25));
+            sx *= T(2);
+            sy *= T(2);
+            sz *= T(2);
+            --l;
+            expand = false;
+            continue;
+        }
+        const int j = __builtin_ctz(pm);
+        pend &= ~(1ull << (8 * l + j));
+        const uint32_t c = (uint32_t)j ^ ((oct >> (3 * l)) & 7u);
+        const T cjx = jx + (T)((c >> 2) & 1u), cjy = jy + (T)((c >> 1) & 1u), cjz = jz + (T)(c & 1u);
+        const T cbd = sq3(oct_axis(ax, bx, sx, cjx), oct_axis(ay, by, sy, cjy), oct_axis(az, bz, sz, cjz));
+        if (cbd > bd) {
+            expand = false;
+            continue;
+        }
+        if (l == G - 1) {
+            // the child is a leaf: scan its run (starts kept from this
+            // cell's expansion; selects, not an indexed array, so they stay
+            // in registers), then go on at this level
+            const int s = c < 4 ? (c < 2 ? (c == 0 ? ls0 : ls1) : (c == 2 ? ls2 : ls3))
+                                : (c < 6 ? (c == 4 ? ls4 : ls5) : (c == 6 ? ls6 : ls7));
+            const int e = c < 4 ? (c < 2 ? (c == 0 ? ls1 : ls2) : (c == 2 ? ls3 : ls4))
+                                : (c < 6 ? (c == 4 ? ls5 : ls6) : (c == 6 ? ls7 : ls8));
             if constexpr (COUNT) work->points += e - s;
-            for (int t = s; t < e; ++t) {
-                V u = tg[t];
-                T d = sq3(u.x - qx, u.y - qy, u.z - qz);
-                int id = (int)u.w;
+            int t = s;
+            for (; t + 1 < e; t += 2) {
+                const V u0 = tg[t], u1 = tg[t + 1];
+                const T d0 = sq3(u0.x - qx, u0.y - qy, u0.z - qz);
+                const T d1 = sq3(u1.x - qx, u1.y - qy, u1.z - qz);
+                const int i0 = (int)u0.w, i1 = (int)u1.w;
+                if (d0 < bd || (d0 == bd && i0 < bid)) {
+                    bd = d0;
+                    bid = i0;
+                    bpos = t;
+                }
+                if (d1 < bd || (d1 == bd && i1 < bid)) {
+                    bd = d1;
+                    bid = i1;
+                    bpos = t + 1;
+                }
+            }
+            if (t < e) {
+                const V u = tg[t];
+                const T d = sq3(u.x - qx, u.y - qy, u.z - qz);
+                const int id = (int)u.w;
                 if (d < bd || (d == bd && id < bid)) {
                     bd = d;
                     bid = id;
                     bpos = t;
                 }
             }
+            expand = false;
+            continue;
         }
-        bool next = false;
-        while (trail) {
-            const int lvl = 31 - __builtin_clz(trail);
-            trail &= ~(1u << lvl);
-            node = (node >> (depth - lvl)) ^ 1u;
-            depth = lvl;
-            if constexpr (COUNT) work->boxes += 1;
-            if (box_d2<T>(lo[node], hi[node], qx, qy, qz) <= bd) {
-                next = true;
-                break;
-            }
-        }
-        if (!next) break;
+        m = 8 * m + c;
+        jx = T(2) * cjx;
+        jy = T(2) * cjy;
+        jz = T(2) * cjz;
+        sx *= T(0.5);
+        sy *= T(0.5);
+        sz *= T(0.5);
+        ++l;
+        expand = true;
     }
     // a non-finite query matches nothing; keep the index in range
     best_pos = bpos < 0 ? 0 : bpos;
     best_d2 = bd;
-}
-
-// ---------------------------------------------------------------- grid
-
-__host__ __device__ inline uint32_t nn_spread10(uint32_t x) {
-    x &= 0x3ff;
-    x = (x | (x << 16)) & 0x030000ff;
-    x = (x | (x << 8)) & 0x0300f00f;
-    x = (x | (x << 4)) & 0x030c30c3;
-    x = (x | (x << 2)) & 0x09249249;
-    return x;
-}
-
-constexpr int kGridMaxCells = 32;
-
-// Cell range of one axis covered by [q - r, q + r] (clamped to the grid).
-template <typename T>
-__host__ __device__ inline void grid_axis(T q, T r, double glo, double gscale, int sh, int& lo, int& hi) {
-    const T o = (T)glo, s = (T)gscale;
-    T a = (q - r - o) * s, b = (q + r - o) * s;
-    a = fmin(fmax(a, T(0)), T(1023));
-    b = fmin(fmax(b, T(0)), T(1023));
-    lo = (int)floor(a) >> sh;
-    hi = (int)floor(b) >> sh;
-}
-
-// Exact closest target of q when a target position `prev` bounds it: every
-// target at computed squared distance <= bd = |u_prev - q|^2 lies within
-// sqrt(bd) (times 1 + 3 ulp) of q on each axis, hence in the grid cells that
-// [q - r, q + r] covers, r = sqrt(bd) widened by a relative 1e-5 and by
-// pi.gpad (the cell bounds' rounding).  Those cells are scanned with the
-// tree search's distance shape and tie rule (the lowest user index), and
-// the lexicographic minimum of (distance, index) does not depend on the
-// order of visits, so the result is the tree search's.  Returns false,
-// leaving the outputs alone, when the range covers more than kGridMaxCells
-// cells or the bound is not finite (then the tree is searched).
-template <typename T, typename V, bool COUNT = false>
-__host__ __device__ inline bool grid_search(const PairInfo& pi, const int* __restrict__ cells,
-                                            const V* __restrict__ tgt, T qx, T qy, T qz, int prev,
-                                            int& best_pos, T& best_d2, NnWork* work = nullptr) {
-    const V* tg = tgt + pi.tgt_off;
-    const V u = tg[prev];
-    T bd = sq3(u.x - qx, u.y - qy, u.z - qz);
-    if (!(bd < nn_inf<T>())) return false;
-    const T r = sqrt(bd) * T(1.00001) + (T)pi.gpad;
-    const int sh = 10 - pi.grid_bits;
-    int x0, x1, y0, y1, z0, z1;
-    grid_axis<T>(qx, r, pi.glo[0], pi.gscale[0], sh, x0, x1);
-    grid_axis<T>(qy, r, pi.glo[1], pi.gscale[1], sh, y0, y1);
-    grid_axis<T>(qz, r, pi.glo[2], pi.gscale[2], sh, z0, z1);
-    if ((x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1) > kGridMaxCells) return false;
-    const int* cl = cells + pi.grid_off;
-    int bid = (int)u.w, bpos = prev;
-    for (int cz = z0; cz <= z1; ++cz)
-        for (int cy = y0; cy <= y1; ++cy)
-            for (int cx = x0; cx <= x1; ++cx) {
-                const uint32_t m = (nn_spread10((uint32_t)cx) << 2) | (nn_spread10((uint32_t)cy) << 1) |
-                                   nn_spread10((uint32_t)cz);
-                const int s0 = cl[m], s1 = cl[m + 1];
-                if constexpr (COUNT) {
-                    work->cells += 1;
-                    work->points += s1 - s0;
-                }
-                for (int t = s0; t < s1; ++t) {
-                    const V w = tg[t];
-                    const T d = sq3(w.x - qx, w.y - qy, w.z - qz);
-                    const int id = (int)w.w;
-                    if (d < bd || (d == bd && id < bid)) {
-                        bd = d;
-                        bid = id;
-                        bpos = t;
-                    }
-                }
-            }
-    if constexpr (COUNT) work->points += 1;   // the bound's own target
-    best_pos = bpos;
-    best_d2 = bd;
-    return true;
 }
 
 }  // namespace amm

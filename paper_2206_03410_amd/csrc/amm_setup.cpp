@@ -1,6 +1,6 @@
 // Host-side validation of registration problems and construction of the
 // device layout: spatial (Morton) ordering of points, nodes and targets, the
-// bounding-box tree over each target set, the node adjacency with the edge
+// octree run-start tables over each target set, the node adjacency with the edge
 // weights of Eq. (8), the block pattern of K (Eq. 21) and the per-node lists
 // of influenced points used by the row-wise assembly.
 #include <algorithm>
@@ -43,13 +43,6 @@ uint32_t morton(const double* p, const Box& b) {
         q[c] = (uint32_t)std::min(1023, std::max(0, v));
     }
     return (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-}
-
-// Bits per axis of a target grid of M points: about two cells per target
-// over the bounding box (8^bits ~ 2M), between 2 and 7.
-int grid_bits_for(int64_t M) {
-    const double b = std::floor(std::log2((double)std::max<int64_t>(M, 1)) / 3.0 + 0.5);
-    return (int)std::min(7.0, std::max(2.0, b));
 }
 
 std::vector<int32_t> morton_order(const double* pts, int64_t cnt, const Box& b) {
@@ -243,7 +236,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.tgt4.assign(4 * L.Mtot, 0.0);
     L.tgt_user.resize(L.Mtot);
 
-    int64_t so = 0, to = 0, no = 0, ao = 0, tree = 0;
+    int64_t so = 0, to = 0, no = 0, ao = 0;
     for (int p = 0; p < L.P; ++p) {
         const HostPair& hp = pairs[p];
         PairInfo pi{};
@@ -410,26 +403,21 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
             }
         }
 
-        // targets: Morton order, implicit complete tree of `leaf`-sized buckets
+        // targets: Morton order and the octree's run-start tables
         {
             TargetLayout tl;
             target_layout(hp.tgt.data(), hp.M, leaf, tl);
             std::copy(tl.tgt4.begin(), tl.tgt4.end(), L.tgt4.begin() + 4 * to);
             std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + to);
-            pi.tree_off = tree;
-            pi.L = tl.L;
-            pi.leaf = leaf;
             pi.grid_off = (int64_t)L.grid_cells.size();
             pi.grid_bits = tl.grid_bits;
             for (int c = 0; c < 3; ++c) {
                 pi.glo[c] = tl.glo[c];
                 pi.gscale[c] = tl.gscale[c];
+                pi.cs[c] = tl.cs[c];
             }
             pi.gpad = tl.gpad;
             L.grid_cells.insert(L.grid_cells.end(), tl.cells.begin(), tl.cells.end());
-            L.box_lo.insert(L.box_lo.end(), tl.box_lo.begin(), tl.box_lo.end());
-            L.box_hi.insert(L.box_hi.end(), tl.box_hi.begin(), tl.box_hi.end());
-            tree += 2 * (int64_t)tl.L;
         }
 
         // tiles
@@ -519,14 +507,17 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         }
     }
     L.nnzb = (int64_t)L.K_col.size();
-    L.tree_nodes = tree;
     L.pj_entries = (int64_t)L.pj_ent.size();
     return AMM_OK;
 }
 
-void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out) {
+void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out, int depth) {
     const Box bb = bounds(tgt, M);
-    std::vector<int32_t> tord = morton_order(tgt, M, bb);
+    std::vector<uint32_t> code(M);
+    for (int64_t i = 0; i < M; ++i) code[i] = morton(tgt + 3 * i, bb);
+    std::vector<int32_t> tord(M);
+    std::iota(tord.begin(), tord.end(), 0);
+    std::stable_sort(tord.begin(), tord.end(), [&](int32_t a, int32_t c) { return code[a] < code[c]; });
     out.tgt4.assign(4 * (size_t)M, 0.0);
     out.tgt_user.resize(M);
     for (int64_t q = 0; q < M; ++q) {
@@ -535,49 +526,49 @@ void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out) {
         out.tgt4[4 * q + 3] = (double)u;
         out.tgt_user[q] = (int32_t)u;
     }
-    const int64_t nleaf = (M + leaf - 1) / leaf;
-    int64_t Lp = 1;
-    while (Lp < nleaf) Lp <<= 1;
-    out.L = (int32_t)Lp;
-    const double INF = std::numeric_limits<double>::infinity();
-    out.box_lo.assign(4 * 2 * (size_t)Lp, INF);
-    out.box_hi.assign(4 * 2 * (size_t)Lp, -INF);
-    for (int64_t q = 0; q < Lp; ++q) {
-        const int64_t b = Lp + q;
-        for (int64_t t = q * leaf; t < std::min<int64_t>((q + 1) * leaf, M); ++t)
-            for (int c = 0; c < 3; ++c) {
-                const double v = out.tgt4[4 * t + c];
-                out.box_lo[4 * b + c] = std::min(out.box_lo[4 * b + c], v);
-                out.box_hi[4 * b + c] = std::max(out.box_hi[4 * b + c], v);
+    // depth: the smallest whose occupied leaf cells average at most `leaf`
+    // targets (occupied cells counted as distinct code prefixes)
+    int G = depth;
+    if (G < 2 || G > kOctMaxDepth) {
+        G = kOctMaxDepth;
+        for (int g = 2; g < kOctMaxDepth; ++g) {
+            const int sh = 3 * (10 - g);
+            int64_t occ = 0;
+            for (int64_t q = 0; q < M; ++q)
+                if (q == 0 || (code[tord[q]] >> sh) != (code[tord[q - 1]] >> sh)) ++occ;
+            if (occ > 0 && (double)M <= (double)leaf * (double)occ) {
+                G = g;
+                break;
             }
-    }
-    for (int64_t q = Lp - 1; q >= 1; --q) {
-        const int64_t b = q, c0 = 2 * q, c1 = c0 + 1;
-        for (int c = 0; c < 3; ++c) {
-            out.box_lo[4 * b + c] = std::min(out.box_lo[4 * c0 + c], out.box_lo[4 * c1 + c]);
-            out.box_hi[4 * b + c] = std::max(out.box_hi[4 * c0 + c], out.box_hi[4 * c1 + c]);
         }
     }
-    // grid: cell = top grid_bits bits of each quantized coordinate, i.e. the
-    // top 3 grid_bits bits of the Morton code the targets are sorted by
-    const int G = grid_bits_for(M);
     out.grid_bits = G;
-    double emax = 0;
+    double emax = 0, amax = 0;
     for (int c = 0; c < 3; ++c) {
         const double ext = bb.hi[c] - bb.lo[c];
         out.glo[c] = bb.lo[c];
         out.gscale[c] = ext > 0 ? 1023.999 / ext : 0.0;
+        // root cell: quantized coordinates 0..1023 span 1024 / gscale
+        out.cs[c] = ext > 0 ? 1024.0 / out.gscale[c] : 0.0;
         emax = std::max(emax, ext);
+        amax = std::max({amax, std::fabs(bb.lo[c]), std::fabs(bb.hi[c])});
     }
-    out.gpad = 1e-6 * emax;
-    const size_t ncell = (size_t)1 << (3 * G);
-    out.cells.assign(ncell + 1, 0);
-    std::vector<int32_t> cnt(ncell, 0);
-    for (int64_t q = 0; q < M; ++q) {
-        const uint32_t code = morton(&tgt[3 * (size_t)tord[q]], bb) >> (3 * (10 - G));
-        ++cnt[code];
+    // the cell bounds are formed in the search's precision (float32 on the
+    // FP32 path) from coordinates up to amax: a relative 1e-6 of the extent
+    // plus 16 float32 ulps of the largest coordinate covers their rounding
+    // and that of the stored targets
+    out.gpad = 1e-6 * emax + 16.0 * std::ldexp(amax, -24);
+    // leaf-level run starts by counting, coarser levels by sampling them
+    const size_t nleaf = (size_t)1 << (3 * G);
+    std::vector<int32_t> leafst(nleaf + 1, 0);
+    for (int64_t q = 0; q < M; ++q) ++leafst[(code[tord[q]] >> (3 * (10 - G))) + 1];
+    for (size_t m = 0; m < nleaf; ++m) leafst[m + 1] += leafst[m];
+    out.cells.assign((size_t)oct_level_off(G + 1), 0);
+    for (int l = 0; l <= G; ++l) {
+        int32_t* tab = out.cells.data() + oct_level_off(l);
+        const size_t nc = (size_t)1 << (3 * l);
+        for (size_t m = 0; m <= nc; ++m) tab[m] = leafst[m << (3 * (G - l))];
     }
-    for (size_t m = 0; m < ncell; ++m) out.cells[m + 1] = out.cells[m] + cnt[m];
 }
 
 }  // namespace amm

@@ -122,8 +122,8 @@ def test_fp64_step_sampled_against_oracle_sh200k():
 
 def test_seeded_search_equals_cold_search_sh200k():
     """Closest points of the 200,000-point workload (float32) at X1 = X0 +
-    small step, searched with the closest points at X0 as seeds (the grid
-    path for most queries), equal bitwise those of a cold search at X1 in a
+    small step, searched with the closest points at X0 as seeds, equal
+    bitwise those of a cold search at X1 in a
     fresh session, and so does the energy; 2,000 sampled queries equal the
     oracle's brute force on the library's warped points wherever the best
     and second-best distances differ by more than 1e-6 relative."""
@@ -151,9 +151,10 @@ def test_seeded_search_equals_cold_search_sh200k():
             torch.cuda.synchronize()
             got.append((e, rho.cpu().numpy(), vh.cpu().numpy().astype(np.float64), out["energy"]))
     (es, rs, vs, ss), (ec, rc, vc, sc2) = got
-    print(f"seeded search at 200k: {w['cell_lookups'] / N:.2f} grid cells, {w['box_tests'] / N:.1f} box tests, "
-          f"{w['distance_evals'] / N:.1f} distance evaluations per query", file=sys.stderr)
-    assert w["cell_lookups"] > N // 2          # most queries took the grid
+    print(f"seeded search at 200k: {w['cell_lookups'] / N:.2f} cell expansions from memory, "
+          f"{w['box_tests'] / N:.1f} cell bound tests, {w['distance_evals'] / N:.1f} distance evaluations "
+          f"per query", file=sys.stderr)
+    assert w["box_tests"] >= N                 # every search tests the root's occupied children
     assert es == ec and ss == sc2
     assert np.array_equal(rs, rc)
     assert np.array_equal(vs, vc)

@@ -332,13 +332,14 @@ def test_single_node_no_edges():
 
 def test_leaf_size_and_autotune_leave_results_unchanged():
     """The closest-point search is exact with ties to the lowest index, so the
-    tree's leaf size changes no result: whole solves with leaf sizes 4 and 32
-    agree bitwise, and the autotuner's choice is one of its candidates."""
+    octree's leaf occupancy (hence its depth) changes no result: whole solves
+    with leaf sizes 1, 4 and 32 agree bitwise, and the autotuner's choice is
+    one of its candidates."""
     _announce("test_leaf_size_and_autotune_leave_results_unchanged")
     pair = synth.torus_pair(1000, n_src=900, n_tgt=950, n_nodes=45, k=4, e=6)
     outs = []
     with Session(pair, torch.float32) as s:
-        for leaf in (4, 32):
+        for leaf in (1, 4, 32):
             amm.amm_set_leaf_size(s.h, leaf)
             amm.amm_set_problems(s.h, s.problems)
             X = torch.empty(pair.n_nodes, 4, 3, dtype=torch.float32, device="cuda:0")

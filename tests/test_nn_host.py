@@ -1,9 +1,10 @@
 """Host build of the library's closest-point search (the target layout of
-the set-up code and the tree search the kernels run): against brute force
+the set-up code and the octree search the kernels run): against brute force
 over every target, the closest target's index must match exactly, ties
 (duplicate targets, queries on grid points) going to the lowest user index,
-cold and seeded by an arbitrary previous answer, for trees of 1 to 20,000
-targets and leaf sizes 1 to 8."""
+cold and seeded by an arbitrary previous answer, for 1 to 20,000 targets,
+leaf occupancies 1 to 8 and forced depths 2 to 6, including a flat target
+set (one axis of zero extent) and coordinates far from the origin."""
 import os
 import shutil
 import subprocess
@@ -21,41 +22,58 @@ PROGRAM = r'''
 #include "amm_nn.h"
 using namespace amm;
 struct D4 { double x, y, z, w; };
+struct F4 { float x, y, z, w; };
 int main() {
     std::mt19937_64 g(3);
     std::uniform_real_distribution<double> u(-1, 1);
     int fails = 0;
     long long searches = 0;
     for (int M : {1, 3, 4, 5, 17, 64, 100, 1000, 4097, 20000}) {
-        for (int leaf : {1, 2, 4, 8}) {
+        for (int variant = 0; variant < 9; ++variant) {
+            // variants 0-3: occupancy rule with leaf 1, 2, 4, 8; 4-6: forced
+            // depths 2, 4, 6; 7: flat set (z = 0); 8: offset far from the origin
+            const int leaf = variant < 4 ? (1 << variant) : 8;
+            const int depth = variant == 4 ? 2 : variant == 5 ? 4 : variant == 6 ? 6 : 0;
+            const double off = variant == 8 ? 37.0 : 0.0;
             // a height field on a 1/16 grid: many exact duplicates
             std::vector<double> tgt(3 * (size_t)M);
             for (int i = 0; i < M; ++i) {
-                tgt[3 * i] = std::round(u(g) * 16) / 16;
+                tgt[3 * i] = std::round(u(g) * 16) / 16 + off;
                 tgt[3 * i + 1] = std::round(u(g) * 16) / 16;
-                tgt[3 * i + 2] = 0.25 * std::sin(3 * tgt[3 * i]);
+                tgt[3 * i + 2] = variant == 7 ? 0.0 : 0.25 * std::sin(3 * tgt[3 * i]);
             }
             TargetLayout tl;
-            target_layout(tgt.data(), M, leaf, tl);
+            target_layout(tgt.data(), M, leaf, tl, depth);
             PairInfo pi{};
             pi.M = M;
-            pi.L = tl.L;
-            pi.leaf = leaf;
-            std::vector<D4> t4(M), lo(2 * (size_t)tl.L), hi(2 * (size_t)tl.L);
-            for (int i = 0; i < M; ++i) t4[i] = {tl.tgt4[4 * i], tl.tgt4[4 * i + 1], tl.tgt4[4 * i + 2], tl.tgt4[4 * i + 3]};
-            for (int i = 0; i < 2 * tl.L; ++i) {
-                lo[i] = {tl.box_lo[4 * i], tl.box_lo[4 * i + 1], tl.box_lo[4 * i + 2], 0};
-                hi[i] = {tl.box_hi[4 * i], tl.box_hi[4 * i + 1], tl.box_hi[4 * i + 2], 0};
+            pi.grid_bits = tl.grid_bits;
+            for (int c = 0; c < 3; ++c) {
+                pi.glo[c] = tl.glo[c];
+                pi.gscale[c] = tl.gscale[c];
+                pi.cs[c] = tl.cs[c];
             }
+            pi.gpad = tl.gpad;
+            std::vector<D4> t4(M);
+            for (int i = 0; i < M; ++i) t4[i] = {tl.tgt4[4 * i], tl.tgt4[4 * i + 1], tl.tgt4[4 * i + 2], tl.tgt4[4 * i + 3]};
+            std::vector<F4> f4(M);
+            for (int i = 0; i < M; ++i) f4[i] = {(float)t4[i].x, (float)t4[i].y, (float)t4[i].z, (float)t4[i].w};
             for (int q = 0; q < 300; ++q) {
                 double qx, qy, qz;
                 if (q % 4 == 0) {
                     const int k = (int)(g() % M);
                     qx = tgt[3 * k]; qy = tgt[3 * k + 1]; qz = tgt[3 * k + 2];
                 } else {
-                    qx = 1.5 * u(g); qy = 1.5 * u(g); qz = 0.5 * u(g);
+                    qx = 1.5 * u(g) + off; qy = 1.5 * u(g); qz = 0.5 * u(g);
                 }
                 if (q % 7 == 0) { qx = std::round(qx * 32) / 32; qy = std::round(qy * 32) / 32; }
+                const float fx = (float)qx, fy = (float)qy, fz = (float)qz;
+                float fbd = INFINITY;
+                int fbid = 0x7fffffff;
+                for (int t = 0; t < M; ++t) {
+                    const float d = sq3(f4[t].x - fx, f4[t].y - fy, f4[t].z - fz);
+                    const int id = (int)f4[t].w;
+                    if (d < fbd || (d == fbd && id < fbid)) { fbd = d; fbid = id; }
+                }
                 double bd = INFINITY;
                 int bid = 0x7fffffff;
                 for (int t = 0; t < M; ++t) {
@@ -67,12 +85,21 @@ int main() {
                     const int prev = seed < 0 ? -1 : (int)(g() % M);
                     int pos;
                     double d2;
-                    nn_search<double, D4>(pi, t4.data(), lo.data(), hi.data(), qx, qy, qz, prev, pos, d2);
+                    oct_search<double, D4>(pi, tl.cells.data(), tl.cells.data(), t4.data(), qx, qy, qz, prev, pos, d2);
                     ++searches;
                     if (d2 != bd || (int)t4[pos].w != bid) {
                         if (fails < 10)
-                            std::printf("M %d leaf %d query %d seed %d: index %d d2 %.17g, brute force %d %.17g\n", M,
-                                        leaf, q, prev, (int)t4[pos].w, d2, bid, bd);
+                            std::printf("f64 M %d variant %d depth %d query %d seed %d: index %d d2 %.17g, brute force %d %.17g\n",
+                                        M, variant, pi.grid_bits, q, prev, (int)t4[pos].w, d2, bid, bd);
+                        ++fails;
+                    }
+                    float fd2;
+                    oct_search<float, F4>(pi, tl.cells.data(), tl.cells.data(), f4.data(), fx, fy, fz, prev, pos, fd2);
+                    ++searches;
+                    if (fd2 != fbd || (int)f4[pos].w != fbid) {
+                        if (fails < 10)
+                            std::printf("f32 M %d variant %d depth %d query %d seed %d: index %d d2 %.9g, brute force %d %.9g\n",
+                                        M, variant, pi.grid_bits, q, prev, (int)f4[pos].w, fd2, fbid, fbd);
                         ++fails;
                     }
                 }
@@ -85,7 +112,7 @@ int main() {
 '''
 
 
-def test_tree_search_equals_brute_force(tmp_path):
+def test_octree_search_equals_brute_force(tmp_path):
     hipcc = shutil.which("hipcc") or ("/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else None)
     if hipcc is None:
         pytest.skip("no hipcc")

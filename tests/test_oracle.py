@@ -659,6 +659,29 @@ def test_solver_forced_rejections_keep_monotone(small_pair):
         assert e["E_after"] <= e["E_before"] * (1 + 1e-12)
 
 
+def test_solver_replaying_its_own_decisions_reproduces_it(small_pair):
+    """Replay: forcing a run's own Anderson decisions and stage ends gives the
+    same run bitwise (solve count, stages, transforms), and forcing a stage
+    end earlier than eps would ends the stage there (here the only stage:
+    its nu_a starts at the lower bound, so the solve ends)."""
+    prob = O.from_pair(small_pair)
+    p = O.Params(aa_m=5)
+    res = O.solve(prob, p)
+    log = res["log"]
+    fa = [e["accepted"] if e["aa_used"] else None for e in log]
+    fs = [b is None or b["stage"] != a["stage"] for a, b in zip(log, log[1:] + [None])]
+    rep = O.solve(prob, p, force=fa, force_stage_end=fs)
+    assert rep["total"] == res["total"] and rep["stages"] == res["stages"]
+    assert np.array_equal(rep["X"], res["X"])
+    assert res["stages"] == 1 and res["total"] > 4
+    early = [None] * len(fs)
+    early[3] = True                       # end the stage after the fourth solve
+    r2 = O.solve(prob, p, force_stage_end=early)
+    assert r2["total"] == 4
+    r3 = O.solve(prob, O.Params(aa_m=5, max_total_iters=4))
+    assert np.array_equal(r2["X"], r3["X"])
+
+
 def test_anderson_trajectory_amplifies_perturbations_plain_mm_damps_them(small_pair):
     """Sensitivity of Alg. 2 itself (not of any implementation): with the
     same accept/reject decisions replayed, a 1e-7 perturbation of the start
