@@ -136,6 +136,7 @@ def lib():
                                C.POINTER(i32)], C.c_int),
             "amm_iter_log": ([vp, C.POINTER(amm_iter_record), i32, C.POINTER(i32)], C.c_int),
             "amm_energy": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, C.POINTER(dbl), vp, vp], C.c_int),
+            "amm_energy_noalloc": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, C.POINTER(dbl), vp, vp], C.c_int),
             "amm_energy_grad": ([vp, C.c_int, vp, vp, dbl, dbl, dbl, dbl, vp, vp, C.POINTER(dbl)],
                                 C.c_int),
             "amm_status_string": ([C.c_int], C.c_char_p),
@@ -158,7 +159,8 @@ EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
             "amm_set_leaf_size", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
             "amm_build_graph", "amm_graph_copy", "amm_set_targets", "amm_build_graphs", "amm_graph_copy_set",
-            "amm_solve", "amm_step", "amm_k_nnzb", "amm_get_sizes", "amm_iter_log", "amm_energy", "amm_energy_grad",
+            "amm_solve", "amm_step", "amm_k_nnzb", "amm_get_sizes", "amm_iter_log", "amm_energy",
+            "amm_energy_noalloc", "amm_energy_grad",
             "amm_status_string", "amm_last_error", "amm_kernel_times", "amm_enable_timing",
             "amm_version", "amm_params_default"]
 
@@ -510,6 +512,16 @@ def amm_energy(handle, X, src=None, nu_a=1.0, nu_r=1.0, alpha=0.0, beta=0.0, rho
     e = (C.c_double * 4)()
     _check(lib().amm_energy(handle, _dtype_code(X), _ptr(X), _ptr(src), nu_a, nu_r, alpha, beta, e,
                             _ptr(rho), _ptr(d2)), handle)
+    return list(e)
+
+
+def amm_energy_noalloc(handle, X, src=None, nu_a=1.0, nu_r=1.0, alpha=0.0, beta=0.0, rho=None, d2=None):
+    """amm_energy with every per-call buffer in the library's static device
+    scratch (no allocation); calls overlapping on one GPU race."""
+    _energy_buffers(handle, X, src, rho=rho, d2=d2)
+    e = (C.c_double * 4)()
+    _check(lib().amm_energy_noalloc(handle, _dtype_code(X), _ptr(X), _ptr(src), nu_a, nu_r, alpha, beta, e,
+                                    _ptr(rho), _ptr(d2)), handle)
     return list(e)
 
 

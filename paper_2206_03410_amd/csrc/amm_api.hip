@@ -7,6 +7,8 @@
 // device-to-host copy of the pair energies per MM iteration.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -1340,6 +1342,133 @@ amm_status analyse(amm_handle* h, const amm_problem* probs, int32_t n_pairs, Lay
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free energy
+
+namespace amm {
+namespace {
+
+// Scratch of amm_energy_noalloc: a file-scope device array, one copy per
+// GPU, held from the code object's load until the process ends.  Host code
+// never uses the array's name as an address (in host code it stands for a
+// host-side shadow): the device address of each GPU's copy is looked up
+// once, in amm_create with that GPU current, and kept in g_scratch_dev.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+void* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+amm_status scratch_lookup(amm_handle* h, int device) {
+    if (device >= kMaxDevices) return AMM_OK;   // amm_energy_noalloc then refuses on this device
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return AMM_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(h, AMM_ERR_HIP, std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                        hipGetErrorString(e));
+    g_scratch_dev[device] = ptr;
+    return AMM_OK;
+}
+
+// Carves the scratch into 256-byte aligned arrays; false when they do not fit.
+struct ScratchCarver {
+    unsigned char* base;
+    size_t off = 0;
+    bool ok = true;
+    template <typename P>
+    P* take(size_t n) {
+        off = (off + 255) & ~size_t(255);
+        P* r = reinterpret_cast<P*>(base + off);
+        off += sizeof(P) * std::max<size_t>(n, 1);
+        if (off > kNoAllocScratchBytes) ok = false;
+        return r;
+    }
+};
+
+template <typename T>
+amm_status energy_noalloc_impl(amm_handle* h, const void* X, const void* src, double nu_a, double nu_r,
+                               double alpha, double beta, double* energy, int32_t* rho, void* d2) {
+    using V = typename V4Of<T>::type;
+    const Layout& L = h->L;
+    void* base = h->device < kMaxDevices ? g_scratch_dev[h->device] : nullptr;
+    if (!base) return fail(h, AMM_ERR_STATE, "no scratch address for this device (amm_create not run on it)");
+    // per-call arrays: transforms, source override, one evaluation set,
+    // tile partials, the pair's parameters and outputs
+    ScratchCarver c{reinterpret_cast<unsigned char*>(base)};
+    const size_t N = L.Ntot, n = L.ntot, na = L.nadj;
+    T* sX = c.take<T>(12 * n);
+    V* s_src = src ? c.take<V>(N) : nullptr;
+    V* s_vhat = c.take<V>(N);
+    int* s_rho = c.take<int>(N);
+    T* s_d2 = c.take<T>(N);
+    V* s_qw = c.take<V>(N);
+    T* s_wr = c.take<T>(na);
+    V* s_Dres = c.take<V>(na);
+    T* s_R = c.take<T>(9 * n);
+    double* s_pt_part = c.take<double>(L.n_pt_tiles);
+    double* s_pt_max = c.take<double>(L.n_pt_tiles);
+    double* s_eg_part = c.take<double>(L.n_eg_tiles);
+    double* s_nd_part = c.take<double>(L.n_nd_tiles);
+    PairOut* s_out = c.take<PairOut>(1);
+    PairDyn* s_dyn = c.take<PairDyn>(1);
+    if (!c.ok)
+        return fail(h, AMM_ERR_INVALID_ARG,
+                    "problem too large for the allocation-free scratch (" + std::to_string(c.off) +
+                        " bytes needed, " + std::to_string(kNoAllocScratchBytes) + " available)");
+    launch_x_import<T, T>(reinterpret_cast<const T*>(X), sX, h->v.node_user, L.ntot, h->stream);
+    if (src) launch_src_import<T, T>(reinterpret_cast<const T*>(src), reinterpret_cast<T*>(s_src), h->v.src_user,
+                                     L.Ntot, h->stream);
+    // a cold search (no warm start: the scratch's last contents may belong
+    // to another problem); every array the kernels read is written first
+    PairDyn dy{};
+    dy.flags = PF_EVAL;
+    set_scalars(dy, nu_a, nu_r, alpha, beta);
+    launch_dyn_set(&dy, 1, s_dyn, h->stream);
+    EvalArgs<T> a = eval_args<T>(h, false);
+    a.dyn = s_dyn;
+    a.src_override = s_src;
+    for (int q = 0; q < 3; ++q) a.X[q] = sX;
+    for (int q = 0; q < 2; ++q) {
+        a.vhat[q] = s_vhat;
+        a.rho[q] = s_rho;
+        a.d2[q] = s_d2;
+        a.qw[q] = s_qw;
+        a.wr[q] = s_wr;
+        a.Dres[q] = s_Dres;
+        a.R[q] = s_R;
+    }
+    a.pt_part = s_pt_part;
+    a.pt_max = s_pt_max;
+    a.eg_part = s_eg_part;
+    a.nd_part = s_nd_part;
+    a.nn_work = nullptr;
+    FinalArgs f = final_args(h);
+    f.dyn = s_dyn;
+    f.out = s_out;
+    f.pt_part = s_pt_part;
+    f.pt_max = s_pt_max;
+    f.eg_part = s_eg_part;
+    f.nd_part = s_nd_part;
+    launch_eval<T>(a, L.n_pt_tiles, L.n_eg_tiles, L.n_nd_tiles, f, L.P, h->stream, nullptr);
+    if (rho || d2)
+        launch_nn_export<T, T>(s_rho, s_d2, h->v.src_user, h->v.tgt_user, rho, reinterpret_cast<T*>(d2), L.Ntot,
+                               h->stream);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(h->h_out, s_out, sizeof(PairOut), hipMemcpyDeviceToHost, h->stream));
+    TRY(sync_spin(h));
+    if (energy) {
+        energy[0] = h->h_out[0].E;
+        energy[1] = h->h_out[0].Ea;
+        energy[2] = h->h_out[0].Er;
+        energy[3] = h->h_out[0].Eo;
+    }
+    return AMM_OK;
+}
+
+}  // namespace
+}  // namespace amm
+
 extern "C" {
 
 void amm_params_default(amm_params* p) {
@@ -1386,6 +1515,11 @@ amm_status amm_create(amm_handle** out, int device, void* stream) {
     amm_handle* h = new amm_handle();
     h->device = device;
     h->stream = reinterpret_cast<hipStream_t>(stream);
+    const amm_status st = scratch_lookup(h, device);
+    if (st != AMM_OK) {
+        delete h;
+        return st;
+    }
     *out = h;
     return AMM_OK;
 }
@@ -1824,6 +1958,18 @@ amm_status amm_energy_grad(amm_handle* h, amm_dtype dtype, const void* X, const 
                            double alpha, double beta, void* gX, void* gV, double* energy) {
     if (!gX) return fail(h, AMM_ERR_INVALID_ARG, "gX must not be null");
     return energy_entry(h, dtype, X, src, nu_a, nu_r, alpha, beta, energy, nullptr, nullptr, gX, gV);
+}
+
+amm_status amm_energy_noalloc(amm_handle* h, amm_dtype dtype, const void* X, const void* src, double nu_a,
+                              double nu_r, double alpha, double beta, double* energy, int32_t* rho, void* d2) {
+    if (!h || !X) return fail(h, AMM_ERR_INVALID_ARG, "null argument");
+    if (!h->has_problem) return fail(h, AMM_ERR_STATE, "no problem set");
+    if (h->L.P != 1) return fail(h, AMM_ERR_STATE, "energy needs exactly one pair");
+    if (!(nu_a > 0) || !(nu_r > 0)) return fail(h, AMM_ERR_INVALID_ARG, "nu_a and nu_r must be > 0");
+    HIPC(hipSetDevice(h->device));
+    if (dtype == AMM_F32) return energy_noalloc_impl<float>(h, X, src, nu_a, nu_r, alpha, beta, energy, rho, d2);
+    if (dtype == AMM_F64) return energy_noalloc_impl<double>(h, X, src, nu_a, nu_r, alpha, beta, energy, rho, d2);
+    return fail(h, AMM_ERR_INVALID_ARG, "bad dtype");
 }
 
 amm_status amm_enable_timing(amm_handle* h, int32_t on, const char* only) {
