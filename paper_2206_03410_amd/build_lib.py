@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code
 HIP_FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops", "-fPIC", "-I", INCLUDE, "-I", CSRC]
-CXX_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-I", INCLUDE, "-I", CSRC]
+CXX_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
 HIP_SOURCES = ["amm_kernels.hip", "amm_cg.hip", "amm_graph.hip", "amm_api.hip"]
 CXX_SOURCES = ["amm_setup.cpp"]
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     objs = [os.path.join(BUILD, s + ".o") for s in HIP_SOURCES + CXX_SOURCES]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs, verbose)
+    _run([HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -409,9 +409,6 @@ amm_status read_pair(amm_handle* h, const amm_problem& p, HostPair& hp) {
          fetch(p.infl_idx, 4 * (size_t)hp.k * hp.N, hp.infl_idx.data()) &&
          fetch(p.edges, 8 * (size_t)hp.E, hp.edges.data());
     if (!ok) return fail(h, AMM_ERR_HIP, "could not read the problem arrays");
-    std::string err;
-    amm_status s = validate_pair(hp, err);
-    if (s != AMM_OK) return fail(h, s, err);
     return AMM_OK;
 }
 
@@ -972,24 +969,24 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
                               L.ntot, h->stream);
     }
     TRY(evaluate<T>(h));
-    // start of nu_a: median closest-point distance at the initial transforms
-    TRY(pinned_scratch(h, sizeof(T) * L.Ntot));
-    const T* d2h = reinterpret_cast<const T*>(h->h_scratch);
-    HIPC(hipMemcpyAsync(h->h_scratch, d.d2[0], sizeof(T) * L.Ntot, hipMemcpyDeviceToHost, h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
-    std::vector<double> dist;
+    // start of nu_a: median closest-point distance at the initial
+    // transforms (the mean of the two middle ones for even N), from the two
+    // middle squared distances selected on the device (the square root
+    // keeps the order)
+    T* mid2 = reinterpret_cast<T*>(d.cg[0]);   // free until the first solve
+    if (!(prm.nu_a0 > 0)) launch_select_mid<T>(reinterpret_cast<const T*>(d.d2[0]), h->v.info, P, mid2, h->stream);
+    TRY(pinned_scratch(h, sizeof(T) * 2 * P));
+    const T* m2h = reinterpret_cast<const T*>(h->h_scratch);
+    if (!(prm.nu_a0 > 0)) {
+        HIPC(hipMemcpyAsync(h->h_scratch, mid2, sizeof(T) * 2 * P, hipMemcpyDeviceToHost, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+    }
     for (int p = 0; p < P; ++p) {
         const PairInfo& pi = L.info[p];
-        // median of the distances (the mean of the two middle ones for even
-        // N) by selection on d^2: the square root keeps the order
         double med = 0.0;
         if (!(prm.nu_a0 > 0)) {
-            dist.assign(d2h + pi.src_off, d2h + pi.src_off + pi.N);
-            const int64_t mid = pi.N / 2;
-            std::nth_element(dist.begin(), dist.begin() + mid, dist.end());
-            const double hi = std::sqrt(dist[mid]);
-            med = hi;
-            if (pi.N % 2 == 0) med = 0.5 * (std::sqrt(*std::max_element(dist.begin(), dist.begin() + mid)) + hi);
+            const double hi = std::sqrt((double)m2h[2 * p + 1]);
+            med = pi.N % 2 == 0 ? 0.5 * (std::sqrt((double)m2h[2 * p]) + hi) : hi;
         }
         PairState& st = ps[p];
         st.nu_min = prm.nu_a_min > 0 ? prm.nu_a_min : h->lbar[p] / std::sqrt(3.0);
@@ -1335,7 +1332,9 @@ amm_status analyse(amm_handle* h, const amm_problem* probs, int32_t n_pairs, Lay
         lbar[p] = hps[p].lbar;
     }
     std::string err;
-    amm_status s = build_layout(hps, h->leaf, L, err);
+    amm_status s = validate_pairs(hps, err);
+    if (s != AMM_OK) return fail(h, s, err);
+    s = build_layout(hps, h->leaf, L, err);
     if (s != AMM_OK) return fail(h, s, err);
     return AMM_OK;
 }
@@ -1549,7 +1548,11 @@ amm_status amm_check_problem(const amm_problem* p) {
     if (!p) return fail(nullptr, AMM_ERR_INVALID_ARG, "null problem");
     if (p->on_device) return fail(nullptr, AMM_ERR_INVALID_ARG, "amm_check_problem takes host pointers");
     HostPair hp;
-    return read_pair(nullptr, *p, hp);
+    TRY(read_pair(nullptr, *p, hp));
+    std::string err;
+    const amm_status s = validate_pair(hp, err);
+    if (s != AMM_OK) return fail(nullptr, s, err);
+    return AMM_OK;
 }
 
 amm_status amm_workspace_size(amm_handle* h, const amm_problem* probs, int32_t n_pairs, size_t* bytes) {

@@ -177,6 +177,11 @@ constexpr int kTileColCap = 160;     // distinct column nodes of a solver tile s
 constexpr int kAggMinShift = 6;      // at least 64 nodes (4 node tiles) per aggregate
 
 amm_status validate_pair(const HostPair& hp, std::string& err);
+// validate_pair for every pair on host threads; the first failing pair's
+// error, prefixed with its index
+amm_status validate_pairs(const std::vector<HostPair>& pairs, std::string& err);
+// The device layout of a batch; pairs are laid out on host threads and
+// merged in order (the result does not depend on the thread count).
 amm_status build_layout(const std::vector<HostPair>& pairs, int leaf_size, Layout& L,
                         std::string& err);
 

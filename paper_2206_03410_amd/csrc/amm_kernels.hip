@@ -10,6 +10,7 @@
 #include <cfloat>
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "amm_device.h"
 #include "amm_kernels.h"
@@ -1007,6 +1008,62 @@ __global__ void k_nn_export(const int* __restrict__ rho, const T* __restrict__ d
     if (d2_u) d2_u[u] = (U)d2[i];
 }
 
+// Exact selection of the two middle squared distances of every pair (ranks
+// N/2 - 1 and N/2 of its points in increasing order; for odd N the first is
+// unused), for the median start rule of nu_a: a radix select over the
+// values' bit patterns, which order non-negative floats like their values.
+// Block (2 p + r) finds rank N/2 - 1 + r of pair p, 8 bits per pass from
+// the top, counting in LDS the points whose higher bits match the prefix
+// chosen so far.  The result is the element itself, bitwise.
+template <typename T>
+__global__ void __launch_bounds__(256) k_select_mid(const T* __restrict__ d2, const PairInfo* __restrict__ info,
+                                                    T* __restrict__ out) {
+    using U = typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned>::type;
+    constexpr int kBits = 8 * (int)sizeof(T);
+    __shared__ unsigned hist[256];
+    __shared__ U s_prefix;
+    __shared__ long long s_k;
+    const int p = blockIdx.x >> 1, r = blockIdx.x & 1;
+    const PairInfo pi = info[p];
+    const T* v = d2 + pi.src_off;
+    const int64_t N = pi.N;
+    if (threadIdx.x == 0) {
+        s_prefix = 0;
+        s_k = N / 2 - 1 + r < 0 ? 0 : N / 2 - 1 + r;
+    }
+    U mask = 0;
+    for (int shift = kBits - 8; shift >= 0; shift -= 8) {
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        const U prefix = s_prefix;
+        for (int64_t i = threadIdx.x; i < N; i += 256) {
+            U u;
+            const T x = v[i];
+            __builtin_memcpy(&u, &x, sizeof u);
+            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long long k = s_k, cum = 0;
+            int b = 0;
+            for (; b < 255; ++b) {
+                if (cum + hist[b] > k) break;
+                cum += hist[b];
+            }
+            s_k = k - cum;
+            s_prefix = prefix | ((U)b << shift);
+        }
+        mask |= (U)255 << shift;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const U u = s_prefix;
+        T x;
+        __builtin_memcpy(&x, &u, sizeof x);
+        out[blockIdx.x] = x;
+    }
+}
+
 template <typename T>
 __global__ void k_cast_static(const double* __restrict__ in, T* __restrict__ out, int64_t n) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1127,7 +1184,13 @@ void launch_dyn_set(const PairDyn* src, int n, PairDyn* dst, hipStream_t s) {
 }
 
 
+template <typename T>
+void launch_select_mid(const T* d2, const PairInfo* info, int P, T* out, hipStream_t s) {
+    if (P > 0) hipLaunchKernelGGL(k_select_mid<T>, dim3(2 * P), dim3(256), 0, s, d2, info, out);
+}
+
 #define AMM_INSTANTIATE(T)                                                                                     \
+    template void launch_select_mid<T>(const T*, const PairInfo*, int, T*, hipStream_t);                       \
     template void launch_eval<T>(const EvalArgs<T>&, int, int, int, const FinalArgs&, int, hipStream_t,        \
                                  KernelTimer*);                                                               \
     template void launch_assemble<T>(const AsmArgs<T>&, int64_t, hipStream_t, KernelTimer*);                   \

@@ -4,10 +4,13 @@
 // weights of Eq. (8), the block pattern of K (Eq. 21) and the per-node lists
 // of influenced points used by the row-wise assembly.
 #include <algorithm>
+#include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <limits>
 #include <numeric>
+#include <thread>
 
 #include "amm_internal.h"
 
@@ -198,21 +201,302 @@ amm_status validate_pair(const HostPair& hp, std::string& err) {
     return AMM_OK;
 }
 
+namespace {
+
+// Runs f(i) for i in [0, n) on up to `threads` host threads (work taken in
+// index order from a shared counter).
+template <typename F>
+void parallel_for(int64_t n, int threads, F&& f) {
+    threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, n));
+    if (threads == 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t)
+        pool.emplace_back([&] {
+            for (int64_t i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+        });
+    for (auto& th : pool) th.join();
+}
+
+int host_threads() {
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::min(16u, std::max(1u, hc));
+}
+
+// The variable-length parts of one pair's layout, indexed from the pair's
+// own start (row pointers local; node ids, point ids and adjacency indices
+// already global), concatenated by build_layout in pair order.
+struct PairPart {
+    PairInfo pi{};
+    std::vector<int32_t> K_rowptr;   // [n + 1] local offsets into K_col
+    std::vector<int32_t> K_diag;     // [n] local positions of the diagonal blocks
+    std::vector<int32_t> K_col, K_adj;
+    std::vector<int32_t> pj_rowptr;  // [n + 1] local offsets into pj_ent
+    std::vector<int32_t> pj_ent;
+    std::vector<uint64_t> pj_pos;
+    std::vector<int32_t> cells;      // octree run-start tables
+    std::vector<int32_t> aggs;       // [nagg][4]
+    std::vector<int32_t> tile_agg_cnt, tile_agg;
+    int max_row_cols = 0;
+};
+
+// Everything of pair p: the fixed-size arrays are written in place at the
+// pair's offsets (so, to, no, ao), the rest goes to `part`.
+amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, int64_t to, int64_t no, int64_t ao,
+                      Layout& L, PairPart& part, std::string& err) {
+    PairInfo& pi = part.pi;
+    pi.src_off = so;
+    pi.N = hp.N;
+    pi.tgt_off = to;
+    pi.M = hp.M;
+    pi.node_off = no;
+    pi.n = hp.n;
+    pi.adj_off = ao;
+    pi.nadj = 2 * hp.E;
+    pi.n_undirected = (int32_t)hp.E;
+
+    // sources and nodes are ordered within the sources' box, targets
+    // within their own (so that new targets leave the source side as is)
+    const Box bb = bounds(hp.src.data(), hp.N);
+
+    // source points in Morton order
+    std::vector<int32_t> sord = morton_order(hp.src.data(), hp.N, bb);
+    // nodes in Morton order of their positions
+    std::vector<double> npos(3 * hp.n);
+    for (int64_t j = 0; j < hp.n; ++j)
+        for (int c = 0; c < 3; ++c) npos[3 * j + c] = hp.src[3 * hp.node_idx[j] + c];
+    std::vector<int32_t> nord = morton_order(npos.data(), hp.n, bb);
+    std::vector<int32_t> n_inv(hp.n);
+    for (int64_t q = 0; q < hp.n; ++q) n_inv[nord[q]] = (int32_t)q;
+
+    for (int64_t q = 0; q < hp.N; ++q) {
+        int64_t u = sord[q];
+        for (int c = 0; c < 3; ++c) L.src4[4 * (so + q) + c] = hp.src[3 * u + c];
+        L.src_user[so + q] = (int32_t)(so + u);
+        L.src_internal[so + u] = (int32_t)(so + q);
+        // an unused slot points at the point's first influencing node with
+        // weight 0, so the kernels read valid data and add nothing; it takes
+        // no part in K's pattern or the node point lists
+        int a0 = 0;
+        while (hp.infl_idx[u * k + a0] == -1) ++a0;
+        for (int a = 0; a < k; ++a) {
+            const bool pad = hp.infl_idx[u * k + a] == -1;
+            const int32_t j = hp.infl_idx[u * k + (pad ? a0 : a)];
+            const double w = pad ? 0.0 : hp.infl_w[u * k + a];
+            L.iidx[(size_t)a * L.Ntot + so + q] = (int32_t)(no + n_inv[j]);
+            L.ipad[(size_t)a * L.Ntot + so + q] = pad ? 1 : 0;
+            L.iw[(size_t)a * L.Ntot + so + q] = w;
+            L.iw_pt[(size_t)(so + q) * kMaxK + a] = w;
+        }
+    }
+    for (int64_t q = 0; q < hp.n; ++q) {
+        int64_t u = nord[q];
+        for (int c = 0; c < 3; ++c) L.nodes4[4 * (no + q) + c] = npos[3 * u + c];
+        L.node_user[no + q] = (int32_t)(no + u);
+        L.node_internal[no + u] = (int32_t)(no + q);
+        L.node_pair[no + q] = p;
+    }
+
+    // adjacency (directed), r_ij of Eq. (8)
+    std::vector<std::vector<int32_t>> nb(hp.n);
+    for (int64_t e = 0; e < hp.E; ++e) {
+        int32_t a = n_inv[hp.edges[2 * e]], b = n_inv[hp.edges[2 * e + 1]];
+        nb[a].push_back(b);
+        nb[b].push_back(a);
+    }
+    long double inv_sum = 0.0L;
+    for (int64_t e = 0; e < hp.E; ++e) {
+        const double* pa = &npos[3 * hp.edges[2 * e]];
+        const double* pb = &npos[3 * hp.edges[2 * e + 1]];
+        double d = std::sqrt((pa[0] - pb[0]) * (pa[0] - pb[0]) +
+                             (pa[1] - pb[1]) * (pa[1] - pb[1]) +
+                             (pa[2] - pb[2]) * (pa[2] - pb[2]));
+        if (!(d > 0)) {
+            err = "node edge of zero length";
+            return AMM_ERR_GRAPH;
+        }
+        inv_sum += 1.0L / d;
+    }
+    int64_t at = ao;
+    for (int64_t q = 0; q < hp.n; ++q) {
+        std::sort(nb[q].begin(), nb[q].end());
+        L.adj_ptr[no + q] = (int32_t)at;
+        for (int32_t b : nb[q]) {
+            L.adj_nbr[at] = (int32_t)(no + b);
+            L.adj_row[at] = (int32_t)(no + q);
+            const double* pa = &L.nodes4[4 * (no + q)];
+            const double* pb = &L.nodes4[4 * (no + b)];
+            double d = std::sqrt((pa[0] - pb[0]) * (pa[0] - pb[0]) +
+                                 (pa[1] - pb[1]) * (pa[1] - pb[1]) +
+                                 (pa[2] - pb[2]) * (pa[2] - pb[2]));
+            // 2|E| d^-1 / (sum over ordered pairs of d^-1) = |E| d^-1 / sum over edges
+            L.adj_r[at] = (double)((long double)hp.E / (long double)d / inv_sum);
+            ++at;
+        }
+    }
+    for (int64_t e = ao; e < at; ++e) {
+        int32_t a = L.adj_row[e], b = L.adj_nbr[e];
+        auto beg = L.adj_nbr.begin() + L.adj_ptr[b];
+        auto end = beg + (int64_t)nb[b - no].size();
+        auto it = std::lower_bound(beg, end, a);
+        L.adj_rev[e] = (int32_t)(L.adj_ptr[b] + (it - beg));
+    }
+
+    // block pattern of K: co-influence pairs, edges, diagonal
+    std::vector<std::vector<int32_t>> cols(hp.n);
+    for (int64_t q = 0; q < hp.n; ++q) cols[q].push_back((int32_t)(no + q));
+    for (int64_t q = 0; q < hp.N; ++q)
+        for (int a = 0; a < k; ++a) {
+            if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
+            int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
+            for (int b = 0; b < k; ++b)
+                if (!L.ipad[(size_t)b * L.Ntot + so + q]) cols[ja].push_back(L.iidx[(size_t)b * L.Ntot + so + q]);
+        }
+    for (int64_t q = 0; q < hp.n; ++q)
+        for (int32_t b : nb[q]) cols[q].push_back((int32_t)(no + b));
+    part.K_rowptr.assign(hp.n + 1, 0);
+    part.K_diag.assign(hp.n, 0);
+    for (int64_t q = 0; q < hp.n; ++q) {
+        auto& c = cols[q];
+        std::sort(c.begin(), c.end());
+        c.erase(std::unique(c.begin(), c.end()), c.end());
+        if ((int)c.size() > kMaxCols) {
+            err = fmt("a node is coupled to %lld others (limit %lld)", (long long)c.size(), kMaxCols);
+            return AMM_ERR_INVALID_ARG;
+        }
+        part.max_row_cols = std::max(part.max_row_cols, (int)c.size());
+        part.K_rowptr[q] = (int32_t)part.K_col.size();
+        for (size_t t = 0; t < c.size(); ++t) {
+            int32_t col = c[t];
+            if (col == no + q) part.K_diag[q] = (int32_t)part.K_col.size();
+            int32_t adj = -1;
+            if (col != no + q) {
+                auto beg = L.adj_nbr.begin() + L.adj_ptr[no + q];
+                auto end = beg + (int64_t)nb[q].size();
+                auto it = std::lower_bound(beg, end, col);
+                if (it != end && *it == col) adj = (int32_t)(it - L.adj_nbr.begin());
+            }
+            part.K_col.push_back(col);
+            part.K_adj.push_back(adj);
+        }
+    }
+    part.K_rowptr[hp.n] = (int32_t)part.K_col.size();
+    // points influenced by each node
+    std::vector<std::vector<int32_t>> pj(hp.n);
+    for (int64_t q = 0; q < hp.N; ++q)
+        for (int a = 0; a < k; ++a) {
+            if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
+            int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
+            pj[ja].push_back((int32_t)(((so + q) << 3) | a));
+        }
+    part.pj_rowptr.assign(hp.n + 1, 0);
+    for (int64_t q = 0; q < hp.n; ++q) {
+        part.pj_rowptr[q] = (int32_t)part.pj_ent.size();
+        part.pj_ent.insert(part.pj_ent.end(), pj[q].begin(), pj[q].end());
+        const auto& c = cols[q];
+        for (int32_t ent : pj[q]) {
+            const int64_t i = ent >> 3;
+            uint64_t pos = 0;
+            for (int b = 0; b < k; ++b) {
+                uint64_t bpos = kPosUnused;
+                if (!L.ipad[(size_t)b * L.Ntot + i]) {
+                    const int32_t nid = L.iidx[(size_t)b * L.Ntot + i];
+                    bpos = (uint64_t)(std::lower_bound(c.begin(), c.end(), nid) - c.begin());
+                }
+                pos |= bpos << (8 * b);
+            }
+            part.pj_pos.push_back(pos);
+        }
+    }
+    part.pj_rowptr[hp.n] = (int32_t)part.pj_ent.size();
+
+    // targets: Morton order and the octree's run-start tables
+    {
+        TargetLayout tl;
+        target_layout(hp.tgt.data(), hp.M, leaf, tl);
+        std::copy(tl.tgt4.begin(), tl.tgt4.end(), L.tgt4.begin() + 4 * to);
+        std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + to);
+        pi.grid_bits = tl.grid_bits;
+        for (int c = 0; c < 3; ++c) {
+            pi.glo[c] = tl.glo[c];
+            pi.gscale[c] = tl.gscale[c];
+            pi.cs[c] = tl.cs[c];
+        }
+        pi.gpad = tl.gpad;
+        part.cells = std::move(tl.cells);
+    }
+
+    // coarse aggregates: the fewest power-of-two runs of whole node tiles
+    // that leave at most kCoarseMaxAgg of them
+    int shift = kAggMinShift;
+    while (((hp.n + (int64_t(1) << shift) - 1) >> shift) > kCoarseMaxAgg) ++shift;
+    const int64_t per = int64_t(1) << shift;
+    pi.agg_shift = shift;
+    pi.nagg = (int32_t)((hp.n + per - 1) / per);
+    for (int32_t a = 0; a < pi.nagg; ++a) {
+        const int64_t s0 = a * per, s1 = std::min<int64_t>(s0 + per, hp.n);
+        double ctr[3] = {0, 0, 0};
+        for (int64_t q = s0; q < s1; ++q)
+            for (int c = 0; c < 3; ++c) ctr[c] += L.nodes4[4 * (no + q) + c];
+        for (int c = 0; c < 3; ++c) ctr[c] /= (double)(s1 - s0);
+        for (int64_t q = s0; q < s1; ++q)
+            for (int c = 0; c < 3; ++c) L.node_rel[4 * (no + q) + c] = L.nodes4[4 * (no + q) + c] - ctr[c];
+        part.aggs.insert(part.aggs.end(), {p, (int32_t)(no + s0), (int32_t)(no + s1), a});
+    }
+    // per node tile, the sorted pair-local aggregates its rows of K touch
+    const int64_t ntile = (hp.n + kNodeTile - 1) / kNodeTile;
+    for (int64_t t = 0; t < ntile; ++t) {
+        std::vector<int32_t> ag;
+        const int64_t q0 = t * kNodeTile, q1 = std::min<int64_t>(q0 + kNodeTile, hp.n);
+        for (int32_t e = part.K_rowptr[q0]; e < part.K_rowptr[q1]; ++e)
+            ag.push_back((int32_t)((part.K_col[e] - no) >> shift));
+        std::sort(ag.begin(), ag.end());
+        ag.erase(std::unique(ag.begin(), ag.end()), ag.end());
+        part.tile_agg.insert(part.tile_agg.end(), ag.begin(), ag.end());
+        part.tile_agg_cnt.push_back((int32_t)ag.size());
+    }
+    return AMM_OK;
+}
+
+}  // namespace
+
+amm_status validate_pairs(const std::vector<HostPair>& pairs, std::string& err) {
+    const int64_t P = (int64_t)pairs.size();
+    std::vector<amm_status> sts(P, AMM_OK);
+    std::vector<std::string> errs(P);
+    parallel_for(P, host_threads(), [&](int64_t p) { sts[p] = validate_pair(pairs[p], errs[p]); });
+    for (int64_t p = 0; p < P; ++p)
+        if (sts[p] != AMM_OK) {
+            err = fmt("problem %lld: ", p) + errs[p];
+            return sts[p];
+        }
+    return AMM_OK;
+}
+
 amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
                         std::string& err) {
     L = Layout();
     L.P = (int)pairs.size();
     L.k = pairs.empty() ? 0 : pairs[0].k;
-    for (const auto& hp : pairs) {
+    std::vector<int64_t> so(L.P + 1, 0), to(L.P + 1, 0), no(L.P + 1, 0), ao(L.P + 1, 0);
+    for (int p = 0; p < L.P; ++p) {
+        const HostPair& hp = pairs[p];
         if (hp.k != L.k) {
             err = "all pairs of a batch must have the same k";
             return AMM_ERR_INVALID_ARG;
         }
-        L.Ntot += hp.N;
-        L.Mtot += hp.M;
-        L.ntot += hp.n;
-        L.nadj += 2 * hp.E;
+        so[p + 1] = so[p] + hp.N;
+        to[p + 1] = to[p] + hp.M;
+        no[p + 1] = no[p] + hp.n;
+        ao[p + 1] = ao[p] + 2 * hp.E;
     }
+    L.Ntot = so[L.P];
+    L.Mtot = to[L.P];
+    L.ntot = no[L.P];
+    L.nadj = ao[L.P];
     const int k = L.k;
     L.src4.assign(4 * L.Ntot, 0.0);
     L.src_user.resize(L.Ntot);
@@ -225,6 +509,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.node_user.resize(L.ntot);
     L.node_internal.resize(L.ntot);
     L.node_pair.resize(L.ntot);
+    L.node_rel.assign(4 * L.ntot, 0.0);
     L.adj_ptr.assign(L.ntot + 1, 0);
     L.adj_nbr.resize(L.nadj);
     L.adj_row.resize(L.nadj);
@@ -236,266 +521,111 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.tgt4.assign(4 * L.Mtot, 0.0);
     L.tgt_user.resize(L.Mtot);
 
-    int64_t so = 0, to = 0, no = 0, ao = 0;
+    // pairs in parallel (each writes its own ranges), then merged in order
+    std::vector<PairPart> parts(L.P);
+    std::vector<amm_status> sts(L.P, AMM_OK);
+    std::vector<std::string> errs(L.P);
+    parallel_for(L.P, host_threads(), [&](int64_t p) {
+        sts[p] = build_pair(pairs[p], (int)p, k, leaf, so[p], to[p], no[p], ao[p], L, parts[p], errs[p]);
+    });
+    for (int p = 0; p < L.P; ++p)
+        if (sts[p] != AMM_OK) {
+            err = errs[p];
+            return sts[p];
+        }
+    // offsets of every pair's variable-length parts, then the copies (in
+    // parallel: disjoint ranges)
+    std::vector<int64_t> kb(L.P + 1, 0), pb(L.P + 1, 0), cb(L.P + 1, 0), gb(L.P + 1, 0), tb(L.P + 1, 0);
     for (int p = 0; p < L.P; ++p) {
-        const HostPair& hp = pairs[p];
-        PairInfo pi{};
-        pi.src_off = so;
-        pi.N = hp.N;
-        pi.tgt_off = to;
-        pi.M = hp.M;
-        pi.node_off = no;
-        pi.n = hp.n;
-        pi.adj_off = ao;
-        pi.nadj = 2 * hp.E;
-        pi.n_undirected = (int32_t)hp.E;
-
-        // sources and nodes are ordered within the sources' box, targets
-        // within their own (so that new targets leave the source side as is)
-        const Box bb = bounds(hp.src.data(), hp.N);
-
-        // source points in Morton order
-        std::vector<int32_t> sord = morton_order(hp.src.data(), hp.N, bb);
-        std::vector<int32_t> s_inv(hp.N);
-        for (int64_t q = 0; q < hp.N; ++q) s_inv[sord[q]] = (int32_t)q;
-        // nodes in Morton order of their positions
-        std::vector<double> npos(3 * hp.n);
-        for (int64_t j = 0; j < hp.n; ++j)
-            for (int c = 0; c < 3; ++c) npos[3 * j + c] = hp.src[3 * hp.node_idx[j] + c];
-        std::vector<int32_t> nord = morton_order(npos.data(), hp.n, bb);
-        std::vector<int32_t> n_inv(hp.n);
-        for (int64_t q = 0; q < hp.n; ++q) n_inv[nord[q]] = (int32_t)q;
-
-        for (int64_t q = 0; q < hp.N; ++q) {
-            int64_t u = sord[q];
-            for (int c = 0; c < 3; ++c) L.src4[4 * (so + q) + c] = hp.src[3 * u + c];
-            L.src_user[so + q] = (int32_t)(so + u);
-            L.src_internal[so + u] = (int32_t)(so + q);
-            // an unused slot points at the point's first influencing node with
-            // weight 0, so the kernels read valid data and add nothing; it takes
-            // no part in K's pattern or the node point lists
-            int a0 = 0;
-            while (hp.infl_idx[u * k + a0] == -1) ++a0;
-            for (int a = 0; a < k; ++a) {
-                const bool pad = hp.infl_idx[u * k + a] == -1;
-                const int32_t j = hp.infl_idx[u * k + (pad ? a0 : a)];
-                const double w = pad ? 0.0 : hp.infl_w[u * k + a];
-                L.iidx[(size_t)a * L.Ntot + so + q] = (int32_t)(no + n_inv[j]);
-                L.ipad[(size_t)a * L.Ntot + so + q] = pad ? 1 : 0;
-                L.iw[(size_t)a * L.Ntot + so + q] = w;
-                L.iw_pt[(size_t)(so + q) * kMaxK + a] = w;
-            }
+        kb[p + 1] = kb[p] + (int64_t)parts[p].K_col.size();
+        pb[p + 1] = pb[p] + (int64_t)parts[p].pj_ent.size();
+        cb[p + 1] = cb[p] + (int64_t)parts[p].cells.size();
+        gb[p + 1] = gb[p] + (int64_t)parts[p].aggs.size();
+        tb[p + 1] = tb[p] + (int64_t)parts[p].tile_agg.size();
+    }
+    if (kb[L.P] >= INT32_MAX || pb[L.P] >= INT32_MAX) {
+        err = "the batch's blocks of K or point lists exceed 32-bit indexing";
+        return AMM_ERR_INVALID_ARG;
+    }
+    L.K_col.resize(kb[L.P]);
+    L.K_adj.resize(kb[L.P]);
+    L.pj_ent.resize(pb[L.P]);
+    L.pj_pos.resize(pb[L.P]);
+    L.grid_cells.resize(cb[L.P]);
+    L.aggs.resize(gb[L.P]);
+    L.tile_agg.resize(tb[L.P]);
+    parallel_for(L.P, host_threads(), [&](int64_t p) {
+        const PairPart& part = parts[p];
+        const int64_t n = pairs[p].n;
+        for (int64_t q = 0; q < n; ++q) {
+            L.K_ptr[no[p] + q] = (int32_t)(kb[p] + part.K_rowptr[q]);
+            L.K_diag[no[p] + q] = (int32_t)(kb[p] + part.K_diag[q]);
+            L.pj_ptr[no[p] + q] = (int32_t)(pb[p] + part.pj_rowptr[q]);
         }
-        for (int64_t q = 0; q < hp.n; ++q) {
-            int64_t u = nord[q];
-            for (int c = 0; c < 3; ++c) L.nodes4[4 * (no + q) + c] = npos[3 * u + c];
-            L.node_user[no + q] = (int32_t)(no + u);
-            L.node_internal[no + u] = (int32_t)(no + q);
-            L.node_pair[no + q] = p;
-        }
-
-        // adjacency (directed), r_ij of Eq. (8)
-        std::vector<std::vector<int32_t>> nb(hp.n);
-        for (int64_t e = 0; e < hp.E; ++e) {
-            int32_t a = n_inv[hp.edges[2 * e]], b = n_inv[hp.edges[2 * e + 1]];
-            nb[a].push_back(b);
-            nb[b].push_back(a);
-        }
-        long double inv_sum = 0.0L;
-        for (int64_t e = 0; e < hp.E; ++e) {
-            const double* pa = &npos[3 * hp.edges[2 * e]];
-            const double* pb = &npos[3 * hp.edges[2 * e + 1]];
-            double d = std::sqrt((pa[0] - pb[0]) * (pa[0] - pb[0]) +
-                                 (pa[1] - pb[1]) * (pa[1] - pb[1]) +
-                                 (pa[2] - pb[2]) * (pa[2] - pb[2]));
-            if (!(d > 0)) {
-                err = "node edge of zero length";
-                return AMM_ERR_GRAPH;
-            }
-            inv_sum += 1.0L / d;
-        }
-        int64_t a0 = ao;
-        for (int64_t q = 0; q < hp.n; ++q) {
-            std::sort(nb[q].begin(), nb[q].end());
-            L.adj_ptr[no + q] = (int32_t)ao;
-            for (int32_t b : nb[q]) {
-                L.adj_nbr[ao] = (int32_t)(no + b);
-                L.adj_row[ao] = (int32_t)(no + q);
-                const double* pa = &L.nodes4[4 * (no + q)];
-                const double* pb = &L.nodes4[4 * (no + b)];
-                double d = std::sqrt((pa[0] - pb[0]) * (pa[0] - pb[0]) +
-                                     (pa[1] - pb[1]) * (pa[1] - pb[1]) +
-                                     (pa[2] - pb[2]) * (pa[2] - pb[2]));
-                // 2|E| d^-1 / (sum over ordered pairs of d^-1) = |E| d^-1 / sum over edges
-                L.adj_r[ao] = (double)((long double)hp.E / (long double)d / inv_sum);
-                ++ao;
-            }
-        }
-        for (int64_t e = a0; e < ao; ++e) {
-            int32_t a = L.adj_row[e], b = L.adj_nbr[e];
-            auto beg = L.adj_nbr.begin() + L.adj_ptr[b];
-            auto end = beg + (int64_t)nb[b - no].size();
-            auto it = std::lower_bound(beg, end, a);
-            L.adj_rev[e] = (int32_t)(L.adj_ptr[b] + (it - beg));
-        }
-
-        // block pattern of K: co-influence pairs, edges, diagonal
-        std::vector<std::vector<int32_t>> cols(hp.n);
-        for (int64_t q = 0; q < hp.n; ++q) cols[q].push_back((int32_t)(no + q));
-        for (int64_t q = 0; q < hp.N; ++q)
-            for (int a = 0; a < k; ++a) {
-                if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
-                int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
-                for (int b = 0; b < k; ++b)
-                    if (!L.ipad[(size_t)b * L.Ntot + so + q]) cols[ja].push_back(L.iidx[(size_t)b * L.Ntot + so + q]);
-            }
-        for (int64_t q = 0; q < hp.n; ++q)
-            for (int32_t b : nb[q]) cols[q].push_back((int32_t)(no + b));
-        for (int64_t q = 0; q < hp.n; ++q) {
-            auto& c = cols[q];
-            std::sort(c.begin(), c.end());
-            c.erase(std::unique(c.begin(), c.end()), c.end());
-            if ((int)c.size() > kMaxCols) {
-                err = fmt("a node is coupled to %lld others (limit %lld)", (long long)c.size(),
-                          kMaxCols);
-                return AMM_ERR_INVALID_ARG;
-            }
-            L.max_row_cols = std::max(L.max_row_cols, (int)c.size());
-            L.K_ptr[no + q] = (int32_t)L.K_col.size();
-            for (size_t t = 0; t < c.size(); ++t) {
-                int32_t col = c[t];
-                if (col == no + q) L.K_diag[no + q] = (int32_t)L.K_col.size();
-                int32_t adj = -1;
-                if (col != no + q) {
-                    auto beg = L.adj_nbr.begin() + L.adj_ptr[no + q];
-                    auto end = beg + (int64_t)nb[q].size();
-                    auto it = std::lower_bound(beg, end, col);
-                    if (it != end && *it == col) adj = (int32_t)(it - L.adj_nbr.begin());
-                }
-                L.K_col.push_back(col);
-                L.K_adj.push_back(adj);
-            }
-        }
-        // points influenced by each node
-        std::vector<std::vector<int32_t>> pj(hp.n);
-        for (int64_t q = 0; q < hp.N; ++q)
-            for (int a = 0; a < k; ++a) {
-                if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
-                int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
-                pj[ja].push_back((int32_t)(((so + q) << 3) | a));
-            }
-        for (int64_t q = 0; q < hp.n; ++q) {
-            L.pj_ptr[no + q] = (int32_t)L.pj_ent.size();
-            L.pj_ent.insert(L.pj_ent.end(), pj[q].begin(), pj[q].end());
-            const auto& c = cols[q];
-            for (int32_t ent : pj[q]) {
-                const int64_t i = ent >> 3;
-                uint64_t pos = 0;
-                for (int b = 0; b < k; ++b) {
-                    uint64_t at = kPosUnused;
-                    if (!L.ipad[(size_t)b * L.Ntot + i]) {
-                        const int32_t nid = L.iidx[(size_t)b * L.Ntot + i];
-                        at = (uint64_t)(std::lower_bound(c.begin(), c.end(), nid) - c.begin());
-                    }
-                    pos |= at << (8 * b);
-                }
-                L.pj_pos.push_back(pos);
-            }
-        }
-
-        // targets: Morton order and the octree's run-start tables
-        {
-            TargetLayout tl;
-            target_layout(hp.tgt.data(), hp.M, leaf, tl);
-            std::copy(tl.tgt4.begin(), tl.tgt4.end(), L.tgt4.begin() + 4 * to);
-            std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + to);
-            pi.grid_off = (int64_t)L.grid_cells.size();
-            pi.grid_bits = tl.grid_bits;
-            for (int c = 0; c < 3; ++c) {
-                pi.glo[c] = tl.glo[c];
-                pi.gscale[c] = tl.gscale[c];
-                pi.cs[c] = tl.cs[c];
-            }
-            pi.gpad = tl.gpad;
-            L.grid_cells.insert(L.grid_cells.end(), tl.cells.begin(), tl.cells.end());
-        }
-
+        std::copy(part.K_col.begin(), part.K_col.end(), L.K_col.begin() + kb[p]);
+        std::copy(part.K_adj.begin(), part.K_adj.end(), L.K_adj.begin() + kb[p]);
+        std::copy(part.pj_ent.begin(), part.pj_ent.end(), L.pj_ent.begin() + pb[p]);
+        std::copy(part.pj_pos.begin(), part.pj_pos.end(), L.pj_pos.begin() + pb[p]);
+        std::copy(part.cells.begin(), part.cells.end(), L.grid_cells.begin() + cb[p]);
+        std::copy(part.aggs.begin(), part.aggs.end(), L.aggs.begin() + gb[p]);
+        std::copy(part.tile_agg.begin(), part.tile_agg.end(), L.tile_agg.begin() + tb[p]);
+    });
+    L.tile_agg_ptr.push_back(0);
+    for (int p = 0; p < L.P; ++p) {
+        const PairPart& part = parts[p];
+        PairInfo pi = part.pi;
+        const int64_t n = pairs[p].n, N = pairs[p].N, E = pairs[p].E;
+        L.max_row_cols = std::max(L.max_row_cols, part.max_row_cols);
+        pi.grid_off = cb[p];
         // tiles
         pi.pt_tile0 = L.n_pt_tiles;
-        for (int64_t s = 0; s < hp.N; s += kPointTile) {
+        for (int64_t s = 0; s < N; s += kPointTile) {
             L.pt_tiles.insert(L.pt_tiles.end(),
-                              {p, (int32_t)(so + s), (int32_t)(so + std::min<int64_t>(s + kPointTile, hp.N)), 0});
+                              {p, (int32_t)(so[p] + s), (int32_t)(so[p] + std::min<int64_t>(s + kPointTile, N)), 0});
             ++L.n_pt_tiles;
         }
         pi.pt_ntile = L.n_pt_tiles - pi.pt_tile0;
         pi.nd_tile0 = L.n_nd_tiles;
-        for (int64_t s = 0; s < hp.n; s += kNodeTile) {
+        for (int64_t s = 0; s < n; s += kNodeTile) {
             L.nd_tiles.insert(L.nd_tiles.end(),
-                              {p, (int32_t)(no + s), (int32_t)(no + std::min<int64_t>(s + kNodeTile, hp.n)), 0});
+                              {p, (int32_t)(no[p] + s), (int32_t)(no[p] + std::min<int64_t>(s + kNodeTile, n)), 0});
             ++L.n_nd_tiles;
         }
         pi.nd_ntile = L.n_nd_tiles - pi.nd_tile0;
-
-        // coarse aggregates: the fewest power-of-two runs of whole node tiles
-        // that leave at most kCoarseMaxAgg of them
-        int shift = kAggMinShift;
-        while (((hp.n + (int64_t(1) << shift) - 1) >> shift) > kCoarseMaxAgg) ++shift;
-        const int64_t per = int64_t(1) << shift;
-        pi.agg_shift = shift;
-        pi.nagg = (int32_t)((hp.n + per - 1) / per);
+        // coarse level
         pi.agg0 = (int32_t)L.nagg;
         pi.ainv_off = L.ainv_size;
         L.ainv_size += (int64_t)(4 * pi.nagg) * (4 * pi.nagg);
-        L.node_rel.resize(4 * L.ntot, 0.0);
-        for (int32_t a = 0; a < pi.nagg; ++a) {
-            const int64_t s0 = a * per, s1 = std::min<int64_t>(s0 + per, hp.n);
-            double ctr[3] = {0, 0, 0};
-            for (int64_t q = s0; q < s1; ++q)
-                for (int c = 0; c < 3; ++c) ctr[c] += L.nodes4[4 * (no + q) + c];
-            for (int c = 0; c < 3; ++c) ctr[c] /= (double)(s1 - s0);
-            for (int64_t q = s0; q < s1; ++q)
-                for (int c = 0; c < 3; ++c) L.node_rel[4 * (no + q) + c] = L.nodes4[4 * (no + q) + c] - ctr[c];
-            L.aggs.insert(L.aggs.end(), {p, (int32_t)(no + s0), (int32_t)(no + s1), a});
-        }
         L.nagg += pi.nagg;
-        for (int32_t t = 0; t < pi.nd_ntile; ++t) {
-            if (L.tile_agg_ptr.empty()) L.tile_agg_ptr.push_back(0);
-            std::vector<int32_t> ag;
-            for (int64_t q = (int64_t)t * kNodeTile; q < std::min<int64_t>((int64_t)(t + 1) * kNodeTile, hp.n); ++q)
-                for (int32_t e = L.K_ptr[no + q]; e < (q + 1 < hp.n ? L.K_ptr[no + q + 1] : (int32_t)L.K_col.size()); ++e)
-                    ag.push_back((int32_t)((L.K_col[e] - no) >> shift));
-            std::sort(ag.begin(), ag.end());
-            ag.erase(std::unique(ag.begin(), ag.end()), ag.end());
-            L.tile_agg.insert(L.tile_agg.end(), ag.begin(), ag.end());
-            L.tile_agg_ptr.push_back((int32_t)L.tile_agg.size());
+        int64_t o = tb[p];
+        for (int32_t c : part.tile_agg_cnt) {
+            o += c;
+            L.tile_agg_ptr.push_back((int32_t)o);
         }
         pi.eg_tile0 = L.n_eg_tiles;
-        for (int64_t s = 0; s < 2 * hp.E; s += kEdgeTile) {
-            L.eg_tiles.insert(L.eg_tiles.end(),
-                              {p, (int32_t)(a0 + s), (int32_t)(a0 + std::min<int64_t>(s + kEdgeTile, 2 * hp.E)), 0});
+        for (int64_t s = 0; s < 2 * E; s += kEdgeTile) {
+            L.eg_tiles.insert(L.eg_tiles.end(), {p, (int32_t)(ao[p] + s),
+                                                 (int32_t)(ao[p] + std::min<int64_t>(s + kEdgeTile, 2 * E)), 0});
             ++L.n_eg_tiles;
         }
         pi.eg_ntile = L.n_eg_tiles - pi.eg_tile0;
-
         L.info.push_back(pi);
-        so += hp.N;
-        to += hp.M;
-        no += hp.n;
     }
-    L.adj_ptr[L.ntot] = (int32_t)ao;
+    parts.clear();
+    L.adj_ptr[L.ntot] = (int32_t)L.nadj;
     L.K_ptr[L.ntot] = (int32_t)L.K_col.size();
     L.pj_ptr[L.ntot] = (int32_t)L.pj_ent.size();
     L.tile_cols.assign((size_t)L.n_nd_tiles * kTileColCap, 0);
     L.tile_ncols.assign(L.n_nd_tiles, 0);
     L.tile_rowl.assign((size_t)L.n_nd_tiles * kNodeTile, 0);
     L.K_lcol.assign(L.K_col.size(), 0);
-    for (int t = 0; t < L.n_nd_tiles; ++t) {
+    parallel_for(L.n_nd_tiles, host_threads(), [&](int64_t t) {
         const int32_t j0 = L.nd_tiles[4 * (size_t)t + 1], j1 = L.nd_tiles[4 * (size_t)t + 2];
         std::vector<int32_t> cols(L.K_col.begin() + L.K_ptr[j0], L.K_col.begin() + L.K_ptr[j1]);
         std::sort(cols.begin(), cols.end());
         cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
         L.tile_ncols[t] = (int32_t)cols.size();
-        if ((int)cols.size() > kTileColCap) continue;
+        if ((int)cols.size() > kTileColCap) return;
         int32_t* dst = &L.tile_cols[(size_t)t * kTileColCap];
         for (int q = 0; q < kTileColCap; ++q) dst[q] = cols[q < (int)cols.size() ? q : 0];
         auto local = [&](int32_t node) {
@@ -505,7 +635,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
             L.tile_rowl[(size_t)t * kNodeTile + (j - j0)] = local(j);
             for (int32_t e = L.K_ptr[j]; e < L.K_ptr[j + 1]; ++e) L.K_lcol[e] = (uint16_t)local(L.K_col[e]);
         }
-    }
+    });
     L.nnzb = (int64_t)L.K_col.size();
     L.pj_entries = (int64_t)L.pj_ent.size();
     return AMM_OK;
