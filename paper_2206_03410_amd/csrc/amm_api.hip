@@ -173,6 +173,7 @@ struct Dyn {
     double* gpt;       // 4 per point
     double* src_ovr;   // 4 per point
     double* pts_out;   // 4 per point
+    double* sel;       // work of the median selection
 };
 
 struct Dev {
@@ -299,6 +300,7 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(d.gpt, 4 * N);
     c.take(d.src_ovr, 4 * N);
     c.take(d.pts_out, 4 * N);
+    c.take(d.sel, (select_mid_work_bytes(L.P) + 7) / 8);
 }
 
 }  // namespace
@@ -974,7 +976,9 @@ amm_status solve_impl(amm_handle* h, const amm_params& prm, void* X_inout, void*
     // middle squared distances selected on the device (the square root
     // keeps the order)
     T* mid2 = reinterpret_cast<T*>(d.cg[0]);   // free until the first solve
-    if (!(prm.nu_a0 > 0)) launch_select_mid<T>(reinterpret_cast<const T*>(d.d2[0]), h->v.info, P, mid2, h->stream);
+    if (!(prm.nu_a0 > 0))
+        launch_select_mid<T>(reinterpret_cast<const T*>(d.d2[0]), h->v.info, h->v.pt_tiles, L.n_pt_tiles, P, mid2,
+                             d.sel, h->stream);
     TRY(pinned_scratch(h, sizeof(T) * 2 * P));
     const T* m2h = reinterpret_cast<const T*>(h->h_scratch);
     if (!(prm.nu_a0 > 0)) {

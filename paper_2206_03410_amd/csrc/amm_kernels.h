@@ -297,8 +297,11 @@ void launch_nn_export(const int* rho, const T* d2, const int* src_user, const in
                       U* d2_u, int64_t Ntot, hipStream_t s);
 template <typename T>
 void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s);
-// out[2 p + r] = the (N_p / 2 - 1 + r)-th smallest of pair p's d2 values (exact)
+// out[2 p + r] = the (N_p / 2 - 1 + r)-th smallest of pair p's d2 values
+// (exact); work: device memory of select_mid_work_bytes(P)
 template <typename T>
-void launch_select_mid(const T* d2, const PairInfo* info, int P, T* out, hipStream_t s);
+void launch_select_mid(const T* d2, const PairInfo* info, const int4* pt_tiles, int n_pt_tiles, int P, T* out,
+                       void* work, hipStream_t s);
+size_t select_mid_work_bytes(int P);
 
 }  // namespace amm

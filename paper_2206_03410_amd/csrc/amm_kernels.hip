@@ -1011,57 +1011,97 @@ __global__ void k_nn_export(const int* __restrict__ rho, const T* __restrict__ d
 // Exact selection of the two middle squared distances of every pair (ranks
 // N/2 - 1 and N/2 of its points in increasing order; for odd N the first is
 // unused), for the median start rule of nu_a: a radix select over the
-// values' bit patterns, which order non-negative floats like their values.
-// Block (2 p + r) finds rank N/2 - 1 + r of pair p, 8 bits per pass from
-// the top, counting in LDS the points whose higher bits match the prefix
-// chosen so far.  The result is the element itself, bitwise.
+// values' bit patterns, which order non-negative floats like their values,
+// 8 bits per pass from the top.  Per pass, every point tile counts its
+// points whose higher bits match the prefix chosen so far into 256 bins
+// (one per-wave vote per distinct bin, then one global atomic per bin and
+// tile: integer counts, exact in any order), and one thread per (pair,
+// rank) then picks the bin holding the rank.  The result is the element
+// itself, bitwise.
 template <typename T>
-__global__ void __launch_bounds__(256) k_select_mid(const T* __restrict__ d2, const PairInfo* __restrict__ info,
-                                                    T* __restrict__ out) {
-    using U = typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned>::type;
-    constexpr int kBits = 8 * (int)sizeof(T);
-    __shared__ unsigned hist[256];
-    __shared__ U s_prefix;
-    __shared__ long long s_k;
-    const int p = blockIdx.x >> 1, r = blockIdx.x & 1;
-    const PairInfo pi = info[p];
-    const T* v = d2 + pi.src_off;
-    const int64_t N = pi.N;
-    if (threadIdx.x == 0) {
-        s_prefix = 0;
-        s_k = N / 2 - 1 + r < 0 ? 0 : N / 2 - 1 + r;
+struct SelUint {
+    using type = typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned>::type;
+};
+
+struct SelState {
+    unsigned long long prefix;
+    long long k;
+};
+
+__global__ void k_sel_init(const PairInfo* __restrict__ info, int P, SelState* __restrict__ st,
+                           unsigned* __restrict__ hist) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 2 * P * 256) hist[e] = 0;
+    if (e < 2 * P) {
+        const long long N = info[e >> 1].N, k = N / 2 - 1 + (e & 1);
+        st[e].prefix = 0;
+        st[e].k = k < 0 ? 0 : k;
     }
-    U mask = 0;
-    for (int shift = kBits - 8; shift >= 0; shift -= 8) {
-        hist[threadIdx.x] = 0;
-        __syncthreads();
-        const U prefix = s_prefix;
-        for (int64_t i = threadIdx.x; i < N; i += 256) {
-            U u;
-            const T x = v[i];
-            __builtin_memcpy(&u, &x, sizeof u);
-            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPointTile) k_sel_hist(const T* __restrict__ d2, const int4* __restrict__ tiles,
+                                                         const SelState* __restrict__ st, int shift,
+                                                         unsigned* __restrict__ hist) {
+    using U = typename SelUint<T>::type;
+    __shared__ unsigned h[2][256];
+    const int4 td = tiles[blockIdx.x];
+    const int p = td.x;
+    h[0][threadIdx.x] = 0;
+    h[1][threadIdx.x] = 0;
+    __syncthreads();
+    const U mask = shift + 8 >= 8 * (int)sizeof(T) ? U(0) : (~U(0)) << (shift + 8);
+    const int i = td.y + (int)threadIdx.x;
+    U u = 0;
+    const bool live = i < td.z;
+    if (live) {
+        const T x = d2[i];
+        __builtin_memcpy(&u, &x, sizeof u);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const U prefix = (U)st[2 * p + r].prefix;
+        int bin = live && (u & mask) == prefix ? (int)((u >> shift) & 255u) : -1;
+        while (true) {
+            const unsigned long long want = __ballot(bin >= 0);
+            if (!want) break;
+            const int lead = __ffsll((long long)want) - 1;
+            const int b = __shfl(bin, lead);
+            const unsigned long long same = __ballot(bin == b);
+            if ((int)(threadIdx.x & 63) == lead) atomicAdd(&h[r][b], (unsigned)__popcll(same));
+            if (bin == b) bin = -1;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            long long k = s_k, cum = 0;
-            int b = 0;
-            for (; b < 255; ++b) {
-                if (cum + hist[b] > k) break;
-                cum += hist[b];
-            }
-            s_k = k - cum;
-            s_prefix = prefix | ((U)b << shift);
-        }
-        mask |= (U)255 << shift;
-        __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const U u = s_prefix;
-        T x;
-        __builtin_memcpy(&x, &u, sizeof x);
-        out[blockIdx.x] = x;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (h[r][threadIdx.x]) atomicAdd(&hist[(2 * p + r) * 256 + threadIdx.x], h[r][threadIdx.x]);
+}
+
+__global__ void k_sel_scan(int P, int shift, SelState* __restrict__ st, unsigned* __restrict__ hist) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * P) return;
+    unsigned* h = hist + 256 * (size_t)e;
+    long long k = st[e].k, cum = 0;
+    int b = 0;
+    for (; b < 255; ++b) {
+        if (cum + h[b] > k) break;
+        cum += h[b];
     }
+    st[e].k = k - cum;
+    st[e].prefix |= (unsigned long long)b << shift;
+    for (int q = 0; q < 256; ++q) h[q] = 0;
+}
+
+template <typename T>
+__global__ void k_sel_out(int P, const SelState* __restrict__ st, T* __restrict__ out) {
+    using U = typename SelUint<T>::type;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * P) return;
+    const U u = (U)st[e].prefix;
+    T x;
+    __builtin_memcpy(&x, &u, sizeof x);
+    out[e] = x;
 }
 
 template <typename T>
@@ -1185,12 +1225,25 @@ void launch_dyn_set(const PairDyn* src, int n, PairDyn* dst, hipStream_t s) {
 
 
 template <typename T>
-void launch_select_mid(const T* d2, const PairInfo* info, int P, T* out, hipStream_t s) {
-    if (P > 0) hipLaunchKernelGGL(k_select_mid<T>, dim3(2 * P), dim3(256), 0, s, d2, info, out);
+void launch_select_mid(const T* d2, const PairInfo* info, const int4* pt_tiles, int n_pt_tiles, int P, T* out,
+                       void* work, hipStream_t s) {
+    if (P <= 0) return;
+    SelState* st = reinterpret_cast<SelState*>(work);
+    unsigned* hist = reinterpret_cast<unsigned*>(st + 2 * P);
+    hipLaunchKernelGGL(k_sel_init, dim3(blocks_for(2 * (int64_t)P * 256, 256)), dim3(256), 0, s, info, P, st, hist);
+    for (int shift = 8 * (int)sizeof(T) - 8; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_sel_hist<T>, dim3(n_pt_tiles), dim3(kPointTile), 0, s, d2, pt_tiles,
+                           (const SelState*)st, shift, hist);
+        hipLaunchKernelGGL(k_sel_scan, dim3(blocks_for(2 * (int64_t)P, 64)), dim3(64), 0, s, P, shift, st, hist);
+    }
+    hipLaunchKernelGGL(k_sel_out<T>, dim3(blocks_for(2 * (int64_t)P, 64)), dim3(64), 0, s, P, (const SelState*)st,
+                       out);
 }
 
+size_t select_mid_work_bytes(int P) { return (sizeof(SelState) + 256 * sizeof(unsigned)) * 2 * (size_t)P; }
+
 #define AMM_INSTANTIATE(T)                                                                                     \
-    template void launch_select_mid<T>(const T*, const PairInfo*, int, T*, hipStream_t);                       \
+    template void launch_select_mid<T>(const T*, const PairInfo*, const int4*, int, int, T*, void*, hipStream_t); \
     template void launch_eval<T>(const EvalArgs<T>&, int, int, int, const FinalArgs&, int, hipStream_t,        \
                                  KernelTimer*);                                                               \
     template void launch_assemble<T>(const AsmArgs<T>&, int64_t, hipStream_t, KernelTimer*);                   \
