@@ -1,5 +1,7 @@
 """FP64 CPU oracle for the deformation-graph construction of Sec. 3.1
-(Alg. 1) with Euclidean distance in place of the geodesic one.
+(Alg. 1), with Euclidean distance in place of the geodesic one
+(build_graph) and with the geodesic distance of Eq. (1) on a point cloud
+(build_graph_geodesic).
 
 TEST INFRASTRUCTURE ONLY.  This module is the plain, slow reference the HIP
 graph builder is checked against.  Only the test-suite and the benchmark's
@@ -31,10 +33,20 @@ Readings (the paper is silent on them):
 * The mean edge length is that of the symmetrized, deduplicated 6-nearest-
   neighbour graph of the source points (the paper's point clouds have no
   mesh edges).
+* Geodesic distance on a point cloud (Sec. 3 builds the edge set of a point
+  cloud from each point's nearest neighbours): the length of the shortest
+  path over the symmetrized, deduplicated 6-nearest-neighbour graph (ties to
+  the lower index), each edge as long as its Euclidean length sqrt(((dx*dx +
+  dy*dy) + dz*dz)).  Alg. 1's breadth-first neighbourhood and exact geodesic
+  step become one shortest-path search from the new node, bounded by R: a
+  path shorter than R never leaves the Euclidean ball of radius R, so the
+  bound loses nothing.  Eq. (3) takes D^2 = D * D of that distance.
 """
 from __future__ import annotations
 
 import numpy as np
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import dijkstra
 from scipy.spatial import cKDTree
 
 
@@ -128,3 +140,83 @@ def mean_edge_length(V: np.ndarray, k: int = 6) -> float:
     key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
     i, j = key // n, key % n
     return float(np.mean(np.sqrt(d2_rows(V[i], V[j]))))
+
+
+def knn_edges(V: np.ndarray, k: int = 6):
+    """The symmetrized, deduplicated k-nearest-neighbour graph of V: each
+    point's k nearest other points (ties to the lower index) give undirected
+    edges (i, j), i < j, sorted, with their Euclidean lengths."""
+    V = np.asarray(V, np.float64)
+    n = V.shape[0]
+    kk = min(k + 5, n)
+    _, nb = cKDTree(V).query(V, kk)
+    nb = np.asarray(nb, np.int64).reshape(n, kk)
+    a, b = [], []
+    for q in range(n):
+        c = nb[q][nb[q] != q]
+        d2 = d2_rows(V[c], V[q][None, :])
+        keep = c[np.lexsort((c, d2))][:min(k, n - 1)]
+        a.extend([q] * len(keep))
+        b.extend(keep.tolist())
+    a, b = np.asarray(a, np.int64), np.asarray(b, np.int64)
+    key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+    i, j = key // n, key % n
+    return i, j, np.sqrt(d2_rows(V[i], V[j]))
+
+
+def geodesic_graph(V: np.ndarray, k: int = 6):
+    """The point cloud's edge graph as a symmetric sparse matrix of edge
+    lengths."""
+    n = np.asarray(V).shape[0]
+    i, j, L = knn_edges(V, k)
+    return csr_matrix((np.concatenate([L, L]), (np.concatenate([i, j]), np.concatenate([j, i]))), shape=(n, n))
+
+
+def geodesic_ball(Gm, src: int, R: float):
+    """Points at geodesic distance < R from point `src` and those distances
+    (shortest paths over the edge graph, searched up to R)."""
+    d = dijkstra(Gm, directed=False, indices=int(src), limit=R)
+    q = np.nonzero(d < R)[0]
+    return q, d[q]
+
+
+def build_graph_geodesic(V: np.ndarray, R: float, k: int, k_edges: int = 6):
+    """Alg. 1 with the geodesic distance of Eq. (1) on the point cloud's
+    edge graph.  Same outputs as build_graph."""
+    V = np.asarray(V, np.float64)
+    N = V.shape[0]
+    R2 = R * R
+    Gm = geodesic_graph(V, k_edges)
+    order = pca_order(V)
+    nodes = []
+    infl = [[] for _ in range(N)]          # (node id, geodesic distance), in insertion order
+    for i in order:
+        if not nodes or not infl[i]:
+            j = len(nodes)
+            nodes.append(int(i))
+            q, d = geodesic_ball(Gm, i, R)
+            for qq, dd in zip(q, d):
+                infl[qq].append((j, float(dd)))
+    node_idx = np.asarray(nodes, np.int64)
+    infl_idx = np.full((N, k), -1, np.int64)
+    infl_w = np.zeros((N, k))
+    n_capped = 0
+    max_infl = 0
+    pairs = set()
+    for q in range(N):
+        js = np.asarray([e[0] for e in infl[q]], np.int64)
+        D = np.asarray([e[1] for e in infl[q]], np.float64)
+        max_infl = max(max_infl, len(js))
+        if len(js) > k:
+            n_capped += 1
+        keep = np.lexsort((js, D))[:k]      # nearest first, ties to the lower node id
+        js, D = js[keep], D[keep]
+        w = (1.0 - (D * D) / R2) ** 3       # Eq. (3), numerator
+        infl_idx[q, :len(js)] = js
+        infl_w[q, :len(js)] = w / w.sum()
+        for a in range(len(js)):
+            for b in range(a + 1, len(js)):
+                pairs.add((min(js[a], js[b]), max(js[a], js[b])))
+    edges = np.asarray(sorted(pairs), np.int64).reshape(-1, 2)
+    return dict(node_idx=node_idx, infl_idx=infl_idx, infl_w=infl_w, edges=edges,
+                n_capped=n_capped, max_influences=max_infl)

@@ -99,12 +99,46 @@ __host__ __device__ inline void oct_search(const PairInfo& pi, const int* __rest
     const T ux = pi.cs[0] > 0 ? (qx - (T)pi.glo[0]) / (T)pi.cs[0] : T(0);
     const T uy = pi.cs[1] > 0 ? (qy - (T)pi.glo[1]) / (T)pi.cs[1] : T(0);
     const T uz = pi.cs[2] > 0 ? (qz - (T)pi.glo[2]) / (T)pi.cs[2] : T(0);
+    // Start cell: every target whose computed distance does not exceed the
+    // seed's lies within r of q on each axis (r = the seed distance widened
+    // by a relative 1e-5 and by pad, which cover the rounding of the squared
+    // distance, of its root and of the quantization below), so its
+    // quantized coordinates lie in [lo, hi] per axis, and the deepest cell
+    // holding that whole box (the common leading bits of lo and hi) holds
+    // every target the search can accept: the search starts there, at most
+    // at level G - 1 (a cold search starts at the root).
+    int l0 = 0;
+    uint32_t c0x = 0, c0y = 0, c0z = 0;
+    if (prev >= 0 && bd < nn_inf<T>()) {
+        const T r = sqrt(bd) * T(1.00001) + pad;
+        int lz = G - 1;
+        uint32_t lo3[3], hi3[3];
+        const T qv[3] = {qx, qy, qz};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T gl = (T)pi.glo[c], gs = (T)pi.gscale[c];
+            T a = (qv[c] - r - gl) * gs, b = (qv[c] + r - gl) * gs;
+            a = fmin(fmax(a, T(0)), T(1023));
+            b = fmin(fmax(b, T(0)), T(1023));
+            lo3[c] = (uint32_t)floor(a);
+            hi3[c] = (uint32_t)floor(b);
+            const uint32_t x = lo3[c] ^ hi3[c];
+            const int common = x == 0 ? 10 : __builtin_clz(x) - 22;
+            lz = common < lz ? common : lz;
+        }
+        l0 = lz < 0 ? 0 : lz;
+        c0x = lo3[0] >> (10 - l0);
+        c0y = lo3[1] >> (10 - l0);
+        c0z = lo3[2] >> (10 - l0);
+    }
     // children's size at the current level (halved on the way down, doubled
     // on the way up: powers of two, exact); children's first coordinate 2 c
-    T sx = (T)pi.cs[0] * T(0.5), sy = (T)pi.cs[1] * T(0.5), sz = (T)pi.cs[2] * T(0.5);
-    T jx = 0, jy = 0, jz = 0;         // 2 x the current cell's coordinates
-    int l = 0;                        // level of the current cell
+    T sx = ldexp((T)pi.cs[0], -(l0 + 1)), sy = ldexp((T)pi.cs[1], -(l0 + 1)), sz = ldexp((T)pi.cs[2], -(l0 + 1));
+    T jx = T(2 * c0x), jy = T(2 * c0y), jz = T(2 * c0z);   // 2 x the current cell's coordinates
+    int l = l0;                       // level of the current cell
     uint32_t m = 0;                   // its Morton index
+    for (int b = l0 - 1; b >= 0; --b)
+        m = (m << 3) | (((c0x >> b) & 1u) << 2) | (((c0y >> b) & 1u) << 1) | ((c0z >> b) & 1u);
     uint64_t pend = 0;                // children still to visit, one byte per level
     uint32_t oct = 0;                 // the query's octant, three bits per level
     // run starts of the current level G - 1 cell's children
@@ -164,7 +198,7 @@ __host__ __device__ inline void oct_search(const PairInfo& pi, const int* __rest
         }
         const uint32_t pm = (uint32_t)(pend >> (8 * l)) & 0xffu;
         if (pm == 0) {
-            if (l == 0) break;
+            if (l == l0) break;
             m >>= 3;
             jx = T(2) * floor(jx * T(0.25));
             jy = T(2) * floor(jy * T(0.25));
@@ -194,12 +228,17 @@ __host__ __device__ inline void oct_search(const PairInfo& pi, const int* __rest
             const int e = c < 4 ? (c < 2 ? (c == 0 ? ls1 : ls2) : (c == 2 ? ls3 : ls4))
                                 : (c < 6 ? (c == 4 ? ls5 : ls6) : (c == 6 ? ls7 : ls8));
             if constexpr (COUNT) work->points += e - s;
-            int t = s;
-            for (; t + 1 < e; t += 2) {
-                const V u0 = tg[t], u1 = tg[t + 1];
+            // four targets per round: the loads are independent and issued
+            // together (indices past the run repeat its last target, whose
+            // second visit changes nothing)
+            for (int t = s; t < e; t += 4) {
+                const int t1 = min(t + 1, e - 1), t2 = min(t + 2, e - 1), t3 = min(t + 3, e - 1);
+                const V u0 = tg[t], u1 = tg[t1], u2 = tg[t2], u3 = tg[t3];
                 const T d0 = sq3(u0.x - qx, u0.y - qy, u0.z - qz);
                 const T d1 = sq3(u1.x - qx, u1.y - qy, u1.z - qz);
-                const int i0 = (int)u0.w, i1 = (int)u1.w;
+                const T d2 = sq3(u2.x - qx, u2.y - qy, u2.z - qz);
+                const T d3 = sq3(u3.x - qx, u3.y - qy, u3.z - qz);
+                const int i0 = (int)u0.w, i1 = (int)u1.w, i2 = (int)u2.w, i3 = (int)u3.w;
                 if (d0 < bd || (d0 == bd && i0 < bid)) {
                     bd = d0;
                     bid = i0;
@@ -208,17 +247,17 @@ __host__ __device__ inline void oct_search(const PairInfo& pi, const int* __rest
                 if (d1 < bd || (d1 == bd && i1 < bid)) {
                     bd = d1;
                     bid = i1;
-                    bpos = t + 1;
+                    bpos = t1;
                 }
-            }
-            if (t < e) {
-                const V u = tg[t];
-                const T d = sq3(u.x - qx, u.y - qy, u.z - qz);
-                const int id = (int)u.w;
-                if (d < bd || (d == bd && id < bid)) {
-                    bd = d;
-                    bid = id;
-                    bpos = t;
+                if (d2 < bd || (d2 == bd && i2 < bid)) {
+                    bd = d2;
+                    bid = i2;
+                    bpos = t2;
+                }
+                if (d3 < bd || (d3 == bd && i3 < bid)) {
+                    bd = d3;
+                    bid = i3;
+                    bpos = t3;
                 }
             }
             expand = false;

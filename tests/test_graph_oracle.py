@@ -106,3 +106,149 @@ def test_mean_edge_length_by_brute_force():
             e.add((min(i, j), max(i, j)))
     want = np.mean([math.sqrt(D2[i, j]) for i, j in e])
     assert G.mean_edge_length(V) == pytest.approx(want, rel=1e-13)
+
+
+# ---------------------------------------------------------------- geodesic (Eq. 1)
+
+def _floyd_warshall(W):
+    """All-pairs shortest paths of a dense matrix of edge lengths (inf = no
+    edge), plain loops over the intermediate point."""
+    D = W.copy()
+    np.fill_diagonal(D, 0.0)
+    for m in range(D.shape[0]):
+        D = np.minimum(D, D[:, m:m + 1] + D[m:m + 1, :])
+    return D
+
+
+def test_geodesic_ball_against_floyd_warshall():
+    """The bounded shortest-path search equals brute-force all-pairs shortest
+    paths over the same edge graph: the same points within R (away from the
+    boundary) at the same distances; geodesic >= Euclidean distance."""
+    rng = np.random.default_rng(11)
+    V = rng.uniform(-1, 1, size=(70, 3)) * np.array([1.0, 1.0, 0.2])
+    i, j, L = G.knn_edges(V, 6)
+    W = np.full((70, 70), np.inf)
+    W[i, j] = L
+    W[j, i] = L
+    FW = _floyd_warshall(W)
+    Gm = G.geodesic_graph(V, 6)
+    R = 0.7
+    for src in range(70):
+        q, d = G.geodesic_ball(Gm, src, R)
+        far = np.abs(FW[src] - R) > 1e-9
+        assert set(q.tolist()) == set(np.nonzero((FW[src] < R) & far)[0].tolist()) | set(
+            x for x in q.tolist() if not far[x])
+        assert np.allclose(d, FW[src, q], rtol=0, atol=1e-12)
+        assert np.all(d >= np.sqrt(G.d2_rows(V[q], V[src][None, :])) - 1e-12)
+
+
+def test_knn_edges_by_brute_force():
+    """Each point's 6 nearest other points by the full distance matrix (ties to
+    the lower index), symmetrized and deduplicated."""
+    rng = np.random.default_rng(12)
+    V = np.round(rng.uniform(-1, 1, size=(40, 3)) * 4) / 4     # many exact ties
+    n = len(V)
+    pairs = set()
+    for q in range(n):
+        d2 = G.d2_rows(V, V[q][None, :])
+        c = [x for x in np.lexsort((np.arange(n), d2)) if x != q][:6]
+        pairs |= {(min(q, x), max(q, x)) for x in c}
+    i, j, L = G.knn_edges(V, 6)
+    assert sorted(pairs) == list(zip(i.tolist(), j.tolist()))
+    assert np.array_equal(L, np.sqrt(G.d2_rows(V[i], V[j])))
+
+
+def test_geodesic_graph_on_a_line_equals_euclidean():
+    """Evenly spaced points on a line at dyadic positions, each joined to its
+    two nearest (its neighbours on both sides): every path sum is exact and
+    equals the Euclidean distance, so the geodesic build equals the
+    Euclidean one bitwise."""
+    rng = np.random.default_rng(13)
+    x = np.arange(120) / 64.0
+    V = np.stack([x, np.zeros_like(x), np.zeros_like(x)], 1)
+    V = V[rng.permutation(len(V))]
+    a = G.build_graph(V, 0.4, 4)
+    b = G.build_graph_geodesic(V, 0.4, 4, k_edges=2)
+    for key in ("node_idx", "infl_idx", "edges"):
+        assert np.array_equal(a[key], b[key])
+    assert np.array_equal(a["infl_w"], b["infl_w"])
+
+
+def _folded_strip(n_per_arm=300, gap=0.1, seed=14):
+    """A U-shaped strip: two parallel arms `gap` apart along x in [0, 1],
+    joined by a half circle at x = 1 (one arm at y = 0, the other at
+    y = gap), width 0.05 in z."""
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0, 1, n_per_arm)
+    z = rng.uniform(0, 0.05, n_per_arm)
+    arm0 = np.stack([t, np.zeros_like(t), z], 1)
+    t = rng.uniform(0, 1, n_per_arm)
+    z = rng.uniform(0, 0.05, n_per_arm)
+    arm1 = np.stack([t, np.full_like(t, gap), z], 1)
+    th = rng.uniform(-np.pi / 2, np.pi / 2, n_per_arm // 6)
+    z = rng.uniform(0, 0.05, len(th))
+    bend = np.stack([1 + 0.5 * gap * np.cos(th), 0.5 * gap + 0.5 * gap * np.sin(th), z], 1)
+    V = np.concatenate([arm0, arm1, bend])
+    arm = np.concatenate([np.zeros(n_per_arm), np.ones(n_per_arm), np.full(len(th), 2)])
+    return V, arm
+
+
+def test_geodesic_influence_stays_on_its_arm():
+    """Folded strip with R larger than the gap between the arms: with
+    Euclidean distance, points of one arm take nodes of the other; with the
+    geodesic distance, a point more than R (along the strip) from the fold
+    is influenced only by nodes of its own arm, and the nodes of each arm
+    cover it on their own (so there are more nodes)."""
+    V, arm = _folded_strip()
+    R = 0.25
+    e = G.build_graph(V, R, 6)
+    g = G.build_graph_geodesic(V, R, 6)
+    far = V[:, 0] < 1 - R - 0.05
+    def crossings(res):
+        na = arm[res["node_idx"]]
+        n = 0
+        for q in np.nonzero(far & (arm < 2))[0]:
+            js = res["infl_idx"][q]
+            js = js[js >= 0]
+            n += int(np.any(na[js] != arm[q]))
+        return n
+    assert crossings(e) > 0
+    assert crossings(g) == 0
+    assert len(g["node_idx"]) > len(e["node_idx"])
+    # every point keeps at least one influencing node; weights sum to 1
+    assert np.all(g["infl_idx"][:, 0] >= 0)
+    assert np.allclose(g["infl_w"].sum(1), 1.0)
+
+
+def test_geodesic_greedy_invariants_by_brute_force():
+    """Against all-pairs shortest paths: nodes are pairwise at geodesic
+    distance >= R, every point is within R of a node, node j is the first
+    point in axis order not within R of nodes 0..j-1, and each point's kept
+    nodes are its nearest by geodesic distance with Eq. (3) weights."""
+    rng = np.random.default_rng(15)
+    th = rng.uniform(0, 2 * np.pi, 150)
+    V = np.stack([np.cos(th), np.sin(th), rng.uniform(0, 0.3, 150)], 1)
+    R, k = 0.6, 4
+    g = G.build_graph_geodesic(V, R, k)
+    i, j, L = G.knn_edges(V, 6)
+    W = np.full((150, 150), np.inf)
+    W[i, j] = L
+    W[j, i] = L
+    FW = _floyd_warshall(W)
+    nodes = g["node_idx"]
+    sub = FW[np.ix_(nodes, nodes)]
+    assert np.all(sub[~np.eye(len(nodes), dtype=bool)] >= R - 1e-12)
+    assert np.all(FW[nodes].min(0) < R)
+    order = G.pca_order(V)
+    rank = np.empty(150, np.int64)
+    rank[order] = np.arange(150)
+    assert np.all(np.diff(rank[nodes]) > 0)
+    for q in range(150):
+        js = g["infl_idx"][q]
+        js = js[js >= 0]
+        D = FW[nodes[js], q]
+        within = np.nonzero(FW[nodes, q] < R)[0]
+        best = within[np.lexsort((within, FW[nodes[within], q]))][:k]
+        assert np.array_equal(js, best)
+        w = (1 - D * D / (R * R)) ** 3
+        assert np.allclose(g["infl_w"][q, :len(js)], w / w.sum(), rtol=1e-12)

@@ -2,7 +2,9 @@
 the set-up code and the octree search the kernels run): against brute force
 over every target, the closest target's index must match exactly, ties
 (duplicate targets, queries on grid points) going to the lowest user index,
-cold and seeded by an arbitrary previous answer, for 1 to 20,000 targets,
+cold, seeded by an arbitrary previous answer and by the closest target
+itself or its neighbour in the sort order (the search then starts deep in
+the octree), for 1 to 20,000 targets,
 leaf occupancies 1 to 8 and forced depths 2 to 6, including a flat target
 set (one axis of zero extent) and coordinates far from the origin."""
 import os
@@ -68,21 +70,26 @@ int main() {
                 if (q % 7 == 0) { qx = std::round(qx * 32) / 32; qy = std::round(qy * 32) / 32; }
                 const float fx = (float)qx, fy = (float)qy, fz = (float)qz;
                 float fbd = INFINITY;
-                int fbid = 0x7fffffff;
+                int fbid = 0x7fffffff, fbpos = 0;
                 for (int t = 0; t < M; ++t) {
                     const float d = sq3(f4[t].x - fx, f4[t].y - fy, f4[t].z - fz);
                     const int id = (int)f4[t].w;
-                    if (d < fbd || (d == fbd && id < fbid)) { fbd = d; fbid = id; }
+                    if (d < fbd || (d == fbd && id < fbid)) { fbd = d; fbid = id; fbpos = t; }
                 }
                 double bd = INFINITY;
-                int bid = 0x7fffffff;
+                int bid = 0x7fffffff, bpos = 0;
                 for (int t = 0; t < M; ++t) {
                     const double d = sq3(t4[t].x - qx, t4[t].y - qy, t4[t].z - qz);
                     const int id = (int)t4[t].w;
-                    if (d < bd || (d == bd && id < bid)) { bd = d; bid = id; }
+                    if (d < bd || (d == bd && id < bid)) { bd = d; bid = id; bpos = t; }
                 }
-                for (int seed = -1; seed < 2; ++seed) {
-                    const int prev = seed < 0 ? -1 : (int)(g() % M);
+                // seeds: none, two random targets, the closest target itself
+                // (the tightest bound: the search starts deepest), and a
+                // target next to it in the sorted order
+                for (int seed = -1; seed < 4; ++seed) {
+                    int prev = seed < 0 ? -1 : (int)(g() % M);
+                    if (seed == 2) prev = bpos;
+                    if (seed == 3) prev = (bpos + 1) % M;
                     int pos;
                     double d2;
                     oct_search<double, D4>(pi, tl.cells.data(), tl.cells.data(), t4.data(), qx, qy, qz, prev, pos, d2);
@@ -94,6 +101,7 @@ int main() {
                         ++fails;
                     }
                     float fd2;
+                    if (seed == 2) prev = fbpos;
                     oct_search<float, F4>(pi, tl.cells.data(), tl.cells.data(), f4.data(), fx, fy, fz, prev, pos, fd2);
                     ++searches;
                     if (fd2 != fbd || (int)f4[pos].w != fbid) {
@@ -105,6 +113,62 @@ int main() {
                 }
             }
         }
+    }
+    // exact ties across cell boundaries: a lattice of targets, queries at the
+    // midpoints between two lattice neighbours, each seeded with the tie
+    // partner of the higher user index: the search must widen its start
+    // box to the tie distance to find the lower index across the boundary
+    for (int variant = 0; variant < 2; ++variant) {
+        const int S = 12, M = S * S * S;
+        std::vector<double> tgt(3 * (size_t)M);
+        std::vector<int> perm(M);
+        for (int i = 0; i < M; ++i) perm[i] = i;
+        for (int i = M - 1; i > 0; --i) std::swap(perm[i], perm[(int)(g() % (i + 1))]);
+        for (int i = 0; i < M; ++i) {
+            const int c = perm[i];
+            tgt[3 * i] = 0.125 * (c % S);
+            tgt[3 * i + 1] = 0.125 * ((c / S) % S);
+            tgt[3 * i + 2] = 0.125 * (c / (S * S));
+        }
+        TargetLayout tl;
+        target_layout(tgt.data(), M, variant == 0 ? 1 : 2, tl);
+        PairInfo pi{};
+        pi.M = M;
+        pi.grid_bits = tl.grid_bits;
+        for (int c = 0; c < 3; ++c) {
+            pi.glo[c] = tl.glo[c];
+            pi.gscale[c] = tl.gscale[c];
+            pi.cs[c] = tl.cs[c];
+        }
+        pi.gpad = tl.gpad;
+        std::vector<F4> f4(M);
+        std::vector<int> pos_of(M);
+        for (int i = 0; i < M; ++i) {
+            f4[i] = {(float)tl.tgt4[4 * i], (float)tl.tgt4[4 * i + 1], (float)tl.tgt4[4 * i + 2], (float)tl.tgt4[4 * i + 3]};
+            pos_of[tl.tgt_user[i]] = i;
+        }
+        for (int a = 0; a < M; ++a)
+            for (int ax = 0; ax < 3; ++ax) {
+                double q[3] = {tgt[3 * a], tgt[3 * a + 1], tgt[3 * a + 2]};
+                q[ax] += 0.0625;
+                if (q[ax] > 0.125 * (S - 1)) continue;
+                int b = -1;   // the lattice neighbour across the midpoint
+                for (int t = 0; t < M; ++t)
+                    if (tgt[3 * t + ax] == q[ax] + 0.0625 && tgt[3 * t + (ax + 1) % 3] == q[(ax + 1) % 3] &&
+                        tgt[3 * t + (ax + 2) % 3] == q[(ax + 2) % 3]) b = t;
+                const int lo_id = std::min(a, b), hi_id = std::max(a, b);
+                int pos;
+                float fd2;
+                oct_search<float, F4>(pi, tl.cells.data(), tl.cells.data(), f4.data(), (float)q[0], (float)q[1],
+                                      (float)q[2], pos_of[hi_id], pos, fd2);
+                ++searches;
+                if ((int)f4[pos].w != lo_id || fd2 != (float)(0.0625 * 0.0625)) {
+                    if (fails < 10)
+                        std::printf("lattice tie: query between %d and %d gave %d (%.9g)\n", lo_id, hi_id,
+                                    (int)f4[pos].w, fd2);
+                    ++fails;
+                }
+            }
     }
     std::printf("%d failures over %lld searches\n", fails, searches);
     return fails != 0;
