@@ -308,7 +308,8 @@ amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int6
 /* ---------------------------------------------------------------- graph construction */
 
 /* Deformation graph of Sec. 3.1 (Alg. 1) built on the device, with
- * Euclidean distance in place of the geodesic one: the source points are
+ * Euclidean distance or with the geodesic distance D of Eq. (1) (field
+ * `geodesic`): the source points are
  * ordered along their principal axis (largest eigenvalue of the covariance;
  * the axis component of largest magnitude taken positive, equal projections
  * in index order); in that order a point becomes a node when no earlier node
@@ -319,7 +320,13 @@ amm_status amm_nn_work(amm_handle* h, int64_t* queries, int64_t* box_tests, int6
  * id) with the weights renormalized over them, so that the result feeds
  * amm_problem directly; unused slots are -1 with weight 0, and edges come
  * from kept slots.  The mean edge length l (Sec. 3.3.3) is that of the
- * symmetrized, deduplicated 6-nearest-neighbour graph of the source points. */
+ * symmetrized, deduplicated 6-nearest-neighbour graph of the source points.
+ * Geodesic distance on a point cloud (whose edge set Sec. 3 builds from each
+ * point's nearest neighbours): the shortest path over that same 6-NN graph
+ * (ties to the lower index), each edge as long as its Euclidean length; the
+ * search from a point stays inside its Euclidean ball of radius R (which a
+ * path shorter than R never leaves), at most 1024 points (larger balls are
+ * refused with AMM_ERR_INVALID_ARG); Eq. (3) takes D^2 = D * D. */
 typedef struct {
     amm_dtype dtype;          /* type of src_xyz and of the weights amm_graph_copy writes */
     const void* src_xyz;      /* DEVICE pointer, [n_src][3] */
@@ -327,6 +334,7 @@ typedef struct {
     double radius;            /* R; <= 0 selects radius_factor * l */
     double radius_factor;     /* used when radius <= 0; <= 0 selects 5 (Sec. 4.1) */
     int32_t k;                /* influence slots per point, 1 <= k <= 8 */
+    int32_t geodesic;         /* 0: Euclidean distance; 1: geodesic distance (Eq. 1); equal over sets */
 } amm_graph_in;
 
 typedef struct {

@@ -72,7 +72,7 @@ class amm_iter_record(C.Structure):
 
 class amm_graph_in(C.Structure):
     _fields_ = [("dtype", C.c_int), ("src_xyz", C.c_void_p), ("n_src", C.c_int64), ("radius", C.c_double),
-                ("radius_factor", C.c_double), ("k", C.c_int32)]
+                ("radius_factor", C.c_double), ("k", C.c_int32), ("geodesic", C.c_int32)]
 
 
 class amm_graph_info(C.Structure):
@@ -300,12 +300,13 @@ def amm_set_targets(handle, pair: int, tgt) -> None:
     _check(lib().amm_set_targets(handle, int(pair), _dtype_code(tgt), _ptr(tgt), tgt.shape[0], on_dev), handle)
 
 
-def amm_build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0) -> dict:
+def amm_build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0,
+                    geodesic: bool = False) -> dict:
     """Alg. 1 on the device for the source points `src` (a cuda tensor
-    [N][3], float32 or float64); returns the build's info.  Fetch the graph
-    with amm_graph_copy."""
+    [N][3], float32 or float64), Euclidean or geodesic distance; returns the
+    build's info.  Fetch the graph with amm_graph_copy."""
     gin = amm_graph_in(dtype=_dtype_code(src), src_xyz=_ptr(src), n_src=src.shape[0], radius=radius,
-                       radius_factor=radius_factor, k=k)
+                       radius_factor=radius_factor, k=k, geodesic=1 if geodesic else 0)
     info = amm_graph_info()
     _check(lib().amm_build_graph(handle, C.byref(gin), C.byref(info)), handle)
     return info.as_dict()
@@ -315,12 +316,14 @@ def amm_graph_copy(handle, node_src_idx=None, infl_idx=None, infl_w=None, edges=
     _check(lib().amm_graph_copy(handle, _ptr(node_src_idx), _ptr(infl_idx), _ptr(infl_w), _ptr(edges)), handle)
 
 
-def amm_build_graphs(handle, srcs, k: int, radius: float = 0.0, radius_factor: float = 0.0) -> list:
+def amm_build_graphs(handle, srcs, k: int, radius: float = 0.0, radius_factor: float = 0.0,
+                     geodesic: bool = False) -> list:
     """Alg. 1 for several point sets (cuda tensors [N_s][3], one dtype) in one
     pass; returns one info dict per set."""
     n = len(srcs)
     gin = (amm_graph_in * n)(*[amm_graph_in(dtype=_dtype_code(sp), src_xyz=_ptr(sp), n_src=sp.shape[0],
-                                            radius=radius, radius_factor=radius_factor, k=k) for sp in srcs])
+                                            radius=radius, radius_factor=radius_factor, k=k,
+                                            geodesic=1 if geodesic else 0) for sp in srcs])
     info = (amm_graph_info * n)()
     _check(lib().amm_build_graphs(handle, gin, n, info), handle)
     return [i.as_dict() for i in info]
@@ -331,11 +334,11 @@ def amm_graph_copy_set(handle, set_index: int, node_src_idx=None, infl_idx=None,
                                     _ptr(edges)), handle)
 
 
-def build_graphs(handle, srcs, k: int, radius: float = 0.0, radius_factor: float = 0.0):
+def build_graphs(handle, srcs, k: int, radius: float = 0.0, radius_factor: float = 0.0, geodesic: bool = False):
     """amm_build_graphs + per-set copies into new tensors: a list of
     (info, node_src_idx, infl_idx, infl_w, edges)."""
     import torch
-    infos = amm_build_graphs(handle, srcs, k, radius, radius_factor)
+    infos = amm_build_graphs(handle, srcs, k, radius, radius_factor, geodesic)
     out = []
     for s, (sp, info) in enumerate(zip(srcs, infos)):
         dev = sp.device
@@ -348,11 +351,11 @@ def build_graphs(handle, srcs, k: int, radius: float = 0.0, radius_factor: float
     return out
 
 
-def build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0):
+def build_graph(handle, src, k: int, radius: float = 0.0, radius_factor: float = 0.0, geodesic: bool = False):
     """amm_build_graph + amm_graph_copy into new tensors on src's device:
     (info, node_src_idx [n], infl_idx [N][k], infl_w [N][k], edges [E][2])."""
     import torch
-    info = amm_build_graph(handle, src, k, radius, radius_factor)
+    info = amm_build_graph(handle, src, k, radius, radius_factor, geodesic)
     dev = src.device
     node = torch.empty(info["n_nodes"], dtype=torch.int32, device=dev)
     idx = torch.empty(src.shape[0], k, dtype=torch.int32, device=dev)

@@ -1,6 +1,7 @@
 // Deformation-graph construction of Sec. 3.1 (Alg. 1) on the device, with
-// Euclidean distance in place of the geodesic one, for one or many point
-// sets (independent registration pairs) at once.
+// Euclidean distance or the geodesic distance of Eq. (1) over the point
+// cloud's nearest-neighbour edges, for one or many point sets (independent
+// registration pairs) at once.
 //
 // Alg. 1 walks a set's source points in the order of their projection onto
 // the principal axis and makes a point a node when no earlier node lies
@@ -668,6 +669,302 @@ __global__ void __launch_bounds__(kGT) k_g_edges(const uint64_t* __restrict__ ke
     edges[2 * (size_t)o + 1] = hi - base;
 }
 
+// ---------------------------------------------------------------- geodesic distance (Eq. 1)
+//
+// On a point cloud the edge set is the symmetrized k-NN graph (kKnn
+// neighbours, ties to the lower index), an edge as long as its Euclidean
+// length, and the geodesic distance is the shortest path over it.  A path
+// shorter than R stays inside the Euclidean ball of radius R around its
+// start, so each point's geodesic neighbourhood is found inside that ball:
+// the ball's points go to LDS and the shortest paths from the point follow
+// by relaxing every edge inside the ball until nothing changes (the fixed
+// point d(v) = min over edges (u, v) of d(u) + |uv|, which is what a
+// label-setting search computes: each value is the left-to-right sum along
+// a shortest path, so both agree bitwise).
+
+constexpr int kGeoThreads = 64;   // one wave per point
+constexpr int kGeoCap = 1024;     // points of one Euclidean ball held in LDS
+constexpr int kGeoHash = 2048;    // open-addressing slots, power of two
+
+// Directed entries a -> b and b -> a (key a << 32 | b) of the unique
+// undirected k-NN edges (sorted keys lo * N + hi with head flags).
+__global__ void __launch_bounds__(kGT) k_g_directed(const uint64_t* __restrict__ key, const int* __restrict__ flag,
+                                                    const int* __restrict__ incl, int64_t M, int64_t N,
+                                                    uint64_t* __restrict__ dkey) {
+    const int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (e >= M || !flag[e]) return;
+    const int64_t o = incl[e] - 1;
+    const uint64_t a = key[e] / (uint64_t)N, b = key[e] % (uint64_t)N;
+    dkey[2 * o] = (a << 32) | b;
+    dkey[2 * o + 1] = (b << 32) | a;
+}
+
+// Adjacency rows of the sorted directed entries: row[a] = the first entry
+// whose source is >= a (a binary search, so a point without entries gets an
+// empty row), for a = 0..N; col = the entries' targets.
+__global__ void __launch_bounds__(kGT) k_g_rows(const uint64_t* __restrict__ dkey, int64_t E2, int64_t N,
+                                                int* __restrict__ row, int* __restrict__ col) {
+    const int64_t i = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (i < E2) col[i] = (int)(dkey[i] & 0xffffffffull);
+    if (i > N) return;
+    const uint64_t b = (uint64_t)i << 32;
+    int64_t lo = 0, hi = E2;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (dkey[mid] < b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    row[i] = (int)lo;
+}
+
+__device__ __forceinline__ unsigned geo_hash(int g) { return ((unsigned)g * 2654435761u) & (kGeoHash - 1); }
+
+// Geodesic neighbourhood of point s (cell order of the R grid): the points
+// at geodesic distance < R (s itself included, at 0).  COUNT: their number
+// into cnt[s]; else their cell positions and distances at off[s], in the
+// order the ball was gathered (the 27 neighbour cells, then cell order).
+template <bool COUNT>
+__global__ void __launch_bounds__(kGeoThreads) k_g_geoball(
+    const double4* __restrict__ Ps, const double4* __restrict__ P, const int* __restrict__ cp,
+    const int* __restrict__ ss, const int* __restrict__ us, const int2* __restrict__ nb, const int* __restrict__ row,
+    const int* __restrict__ col, const double* __restrict__ R2s, const double* __restrict__ Rs,
+    int* __restrict__ cnt, const int* __restrict__ off, int* __restrict__ gpos, double* __restrict__ gdist,
+    int* __restrict__ overflow) {
+    __shared__ int lpos[kGeoCap], lgid[kGeoCap];
+    __shared__ unsigned long long ldist[kGeoCap];
+    __shared__ int hkey[kGeoHash], hval[kGeoHash];
+    __shared__ int s_n;
+    const int64_t s = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double4 q = Ps[s];
+    const int set = ss[s];
+    const double R2 = R2s[set], R = Rs[set];
+    constexpr unsigned long long kInf = 0x7ff0000000000000ull;   // +inf
+    for (int i = lane; i < kGeoHash; i += kGeoThreads) hkey[i] = -1;
+    if (lane == 0) s_n = 0;
+    __syncthreads();
+    // the Euclidean ball, compacted in gathering order
+    const int2* cells = nb + 27 * (size_t)us[s];
+    for (int o = 0; o < 27; ++o) {
+        const int2 r = cells[o];
+        for (int t0 = r.x; t0 < r.y; t0 += kGeoThreads) {
+            const int t = t0 + lane;
+            const bool in = t < r.y && gd2(Ps[t], q) < R2;
+            const unsigned long long m = __ballot(in);
+            const int base = s_n;
+            if (in) {
+                const int i = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+                if (i < kGeoCap) {
+                    lpos[i] = t;
+                    lgid[i] = cp[t];
+                }
+            }
+            __syncthreads();
+            if (lane == 0) s_n = base + (int)__popcll(m);
+            __syncthreads();
+        }
+    }
+    const int n = s_n;
+    if (n > kGeoCap) {   // uniform over the block
+        if (lane == 0) {
+            atomicOr(overflow, 1);
+            if (COUNT) cnt[s] = 0;
+        }
+        return;
+    }
+    for (int i = lane; i < n; i += kGeoThreads) {
+        const int g = lgid[i];
+        unsigned h = geo_hash(g);
+        while (atomicCAS(&hkey[h], -1, g) != -1) h = (h + 1) & (kGeoHash - 1);
+        hval[h] = i;
+        ldist[i] = lpos[i] == (int)s ? 0ull : kInf;
+    }
+    __syncthreads();
+    // relax every edge inside the ball until nothing changes
+    while (true) {
+        int changed = 0;
+        for (int u = lane; u < n; u += kGeoThreads) {
+            const unsigned long long bu = ldist[u];
+            if (bu == kInf) continue;
+            const double du = __longlong_as_double((long long)bu);
+            const int g = lgid[u];
+            const double4 pu = P[g];
+            for (int e = row[g]; e < row[g + 1]; ++e) {
+                const int v = col[e];
+                unsigned h = geo_hash(v);
+                int lv = -1;
+                while (true) {
+                    const int key = hkey[h];
+                    if (key == v) {
+                        lv = hval[h];
+                        break;
+                    }
+                    if (key == -1) break;
+                    h = (h + 1) & (kGeoHash - 1);
+                }
+                if (lv < 0) continue;   // outside the ball: no path shorter than R passes there
+                const double nd = du + sqrt(gd2(pu, P[v]));
+                if (nd < R) {
+                    const unsigned long long nbits = (unsigned long long)__double_as_longlong(nd);
+                    if (nbits < ldist[lv]) {
+                        atomicMin(&ldist[lv], nbits);
+                        changed = 1;
+                    }
+                }
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    if (COUNT) {
+        int c = 0;
+        for (int i = lane; i < n; i += kGeoThreads) c += ldist[i] != kInf ? 1 : 0;
+        for (int w = 32; w > 0; w >>= 1) c += __shfl_xor(c, w);
+        if (lane == 0) cnt[s] = c;
+    } else {
+        int o = off[s];
+        for (int i0 = 0; i0 < n; i0 += kGeoThreads) {
+            const int i = i0 + lane;
+            const bool in = i < n && ldist[i] != kInf;
+            const unsigned long long m = __ballot(in);
+            if (in) {
+                const int w = o + (int)__popcll(m & ((1ull << lane) - 1ull));
+                gpos[w] = lpos[i];
+                gdist[w] = __longlong_as_double((long long)ldist[i]);
+            }
+            o += (int)__popcll(m);
+        }
+    }
+}
+
+// One round of the node selection over the geodesic neighbourhoods (the
+// same decisions as k_g_round, with "within R" read from the lists).
+__global__ void __launch_bounds__(kGT) k_g_round_geo(const int* __restrict__ rs, const int* __restrict__ goff,
+                                                     const int* __restrict__ gpos, int* state, int* cov,
+                                                     int* __restrict__ wait, int64_t N, int* __restrict__ remaining) {
+    const int64_t s = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGT + threadIdx.x;
+    bool undecided = false;
+    bool open = s < N && __hip_atomic_load(&state[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0;
+    if (open && __hip_atomic_load(&cov[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+        __hip_atomic_store(&state[s], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        open = false;
+    }
+    if (open) {
+        const int wt = wait[s];
+        if (wt >= 0 && __hip_atomic_load(&state[wt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+            undecided = true;
+            open = false;
+        }
+    }
+    if (open) {
+        const int rq = rs[s];
+        const int e0 = goff[s], e1 = goff[s + 1];
+        bool covered = false;
+        int pending = -1;
+        for (int e = e0; e < e1 && !covered; ++e) {
+            const int t = gpos[e];
+            const int st = __hip_atomic_load(&state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (rs[t] < rq) {
+                covered = covered || st == 1;
+                if (st == 0 && pending < 0) pending = t;
+            }
+        }
+        if (covered) {
+            __hip_atomic_store(&state[s], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else if (pending < 0) {
+            __hip_atomic_store(&state[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int e = e0; e < e1; ++e) {
+                const int t = gpos[e];
+                if (rs[t] > rq) __hip_atomic_store(&cov[t], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        } else {
+            wait[s] = pending;
+            undecided = true;
+        }
+    }
+    const int cnt = __syncthreads_count(undecided);
+    if (threadIdx.x == 0 && cnt) atomicAdd(remaining, cnt);
+}
+
+// Influence sets from the geodesic neighbourhoods: as k_g_influence with
+// the geodesic distance D (kept nodes the k nearest by D, ties to the lower
+// node id; Eq. (3) with D^2 = D * D).
+template <typename TW>
+__global__ void __launch_bounds__(kGT) k_g_influence_geo(const int* __restrict__ ss, const int* __restrict__ goff,
+                                                         const int* __restrict__ gpos,
+                                                         const double* __restrict__ gdist,
+                                                         const int* __restrict__ nid_s, const int* __restrict__ cp,
+                                                         const int64_t* __restrict__ node_off,
+                                                         const double* __restrict__ R2s, int64_t N, int64_t n_nodes,
+                                                         int k, int* __restrict__ infl_idx, TW* __restrict__ infl_w,
+                                                         uint64_t* __restrict__ pair_key, int* __restrict__ stats) {
+    const int64_t s = (int64_t)blockIdx.x * kGT + threadIdx.x;
+    if (s >= N) return;
+    const int set = ss[s];
+    const double R2 = R2s[set];
+    double bd[kMaxK];
+    int bi[kMaxK];
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a) {
+        bd[a] = __builtin_inf();
+        bi[a] = INT32_MAX;
+    }
+    int cnt = 0;
+    for (int e = goff[s]; e < goff[s + 1]; ++e) {
+        const int id = nid_s[gpos[e]];
+        if (id < 0) continue;
+        ++cnt;
+        topk_insert(bd, bi, k, gdist[e], id);
+    }
+    if (cnt > k) atomicAdd(&stats[2 * set], 1);
+    atomicMax(&stats[2 * set + 1], cnt);
+    const int kept = cnt < k ? cnt : k;
+    double w[kMaxK];
+    double sw = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a) {
+        double x;
+        {
+#pragma clang fp contract(off)
+            x = 1.0 - (bd[a] * bd[a]) / R2;
+            x = x * x * x;
+        }
+        w[a] = a < kept ? x : 0.0;
+        sw += w[a];
+    }
+    const int i = cp[s];
+    const int base = (int)node_off[set];
+    for (int a = 0; a < k; ++a) {
+        double wa = 0;
+        int ia = -1;
+#pragma unroll
+        for (int b = 0; b < kMaxK; ++b)
+            if (b == a) {
+                wa = w[b];
+                ia = b < kept ? bi[b] - base : -1;
+            }
+        infl_idx[(size_t)i * k + a] = ia;
+        infl_w[(size_t)i * k + a] = (TW)(ia >= 0 ? wa / sw : 0.0);
+    }
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a)
+#pragma unroll
+        for (int b = a + 1; b < kMaxK; ++b) {
+            if (b < k) {
+                uint64_t key = kNoKey;
+                if (b < kept) {
+                    const int lo = bi[a] < bi[b] ? bi[a] : bi[b];
+                    const int hi = bi[a] < bi[b] ? bi[b] : bi[a];
+                    key = (uint64_t)lo * (uint64_t)n_nodes + (uint64_t)hi;
+                }
+                pair_key[(size_t)i * (k * (k - 1) / 2) + t] = key;
+                ++t;
+            }
+        }
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kGT - 1) / kGT); }
 
 // Eigenvector of the largest eigenvalue of a symmetric 3x3 matrix by cyclic
@@ -872,8 +1169,8 @@ amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_gra
     for (int s = 0; s < n_sets; ++s) {
         const amm_graph_in& g = in[s];
         if (!g.src_xyz || g.n_src < 2 || g.k != k || k < 1 || k > kMaxK || g.dtype != dt ||
-            (dt != AMM_F32 && dt != AMM_F64)) {
-            err = "graph: bad source pointer, size, k or dtype (k and dtype must agree over the sets)";
+            (dt != AMM_F32 && dt != AMM_F64) || (g.geodesic != 0) != (in[0].geodesic != 0)) {
+            err = "graph: bad source pointer, size, k or dtype (k, dtype and the distance must agree over the sets)";
             return AMM_ERR_INVALID_ARG;
         }
         off[s + 1] = off[s] + g.n_src;
@@ -967,8 +1264,13 @@ amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_gra
     // uploads are asynchronous)
     std::vector<uint64_t> knn_bounds(n_sets + 1), edge_bounds(n_sets + 1);
 
-    // mean edge length per set (6-NN graph)
+    // mean edge length per set (6-NN graph); its sorted unique keys stay
+    // for the geodesic build
     std::vector<double> lbar(n_sets);
+    const bool geo = in[0].geodesic != 0;
+    uint64_t* knn_keys = nullptr;
+    int* knn_flag = nullptr;
+    const int64_t knn_M = N * kKnn;
     {
         GridDims* gk_d = nullptr;
         GCHK(upload(sc, gk, gk_d, st));
@@ -996,6 +1298,8 @@ amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_gra
         GCHK(hipMemcpyAsync(hl.data(), lp, sizeof(double) * hl.size(), hipMemcpyDeviceToHost, st));
         GCHK(hipStreamSynchronize(st));
         for (int s = 0; s < n_sets; ++s) lbar[s] = hl[2 * s + 1] > 0 ? hl[2 * s] / hl[2 * s + 1] : 0.0;
+        knn_keys = pks;
+        knn_flag = flag;
     }
 
     // per set: R and the grid of cell size R (slightly enlarged, so that
@@ -1027,6 +1331,53 @@ amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_gra
     GCHK(sc.get(nb, 27 * (size_t)G.nu));
     hipLaunchKernelGGL(k_g_nbr, dim3(nblk(G.nu)), dim3(kGT), 0, st, G.ukey, G.ustart, G.nu, N, gr_d, nb);
 
+    // geodesic neighbourhoods (Eq. 1): the k-NN edge graph as adjacency
+    // rows over the points' global ids, then each point's points within R
+    int *goff = nullptr, *gpos = nullptr;
+    double* gdist = nullptr;
+    if (geo) {
+        int *incl = nullptr, *row = nullptr, *col = nullptr, *cnt = nullptr, *ovf = nullptr;
+        uint64_t *dkey = nullptr, *dkey_s = nullptr;
+        double* Rs_d = nullptr;
+        GCHK(sc.get(incl, knn_M));
+        GCHK(incl_sum(sc, knn_flag, incl, knn_M, st));
+        int n_und = 0;
+        GCHK(hipMemcpyAsync(&n_und, incl + (knn_M - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+        GCHK(hipStreamSynchronize(st));
+        const int64_t E2 = 2 * (int64_t)n_und;
+        GCHK(sc.get(dkey, E2));
+        GCHK(sc.get(dkey_s, E2));
+        GCHK(sc.get(row, N + 1));
+        GCHK(sc.get(col, E2));
+        hipLaunchKernelGGL(k_g_directed, dim3(nblk(knn_M)), dim3(kGT), 0, st, knn_keys, knn_flag, incl, knn_M, N,
+                           dkey);
+        GCHK(sort_keys(sc, dkey, dkey_s, E2, st));
+        hipLaunchKernelGGL(k_g_rows, dim3(nblk(std::max<int64_t>(E2, N + 1))), dim3(kGT), 0, st, dkey_s, E2, N, row,
+                           col);
+        GCHK(upload(sc, Rs, Rs_d, st));
+        GCHK(sc.get(cnt, N));
+        GCHK(sc.get(ovf, 1));
+        GCHK(hipMemsetAsync(ovf, 0, sizeof(int), st));
+        hipLaunchKernelGGL(k_g_geoball<true>, dim3((unsigned)N), dim3(kGeoThreads), 0, st, G.Ps, P, G.cp, G.ss,
+                           G.us, nb, row, col, R2_d, Rs_d, cnt, nullptr, nullptr, nullptr, ovf);
+        GCHK(sc.get(goff, N + 1));
+        GCHK(hipMemsetAsync(goff, 0, sizeof(int), st));
+        GCHK(incl_sum(sc, cnt, goff + 1, N, st));
+        int total = 0, over = 0;
+        GCHK(hipMemcpyAsync(&total, goff + N, sizeof(int), hipMemcpyDeviceToHost, st));
+        GCHK(hipMemcpyAsync(&over, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
+        GCHK(hipStreamSynchronize(st));
+        if (over) {
+            err = "graph: more than 1024 points within R of a point (geodesic build)";
+            return AMM_ERR_INVALID_ARG;
+        }
+        GCHK(sc.get(gpos, std::max(total, 1)));
+        GCHK(sc.get(gdist, std::max(total, 1)));
+        hipLaunchKernelGGL(k_g_geoball<false>, dim3((unsigned)N), dim3(kGeoThreads), 0, st, G.Ps, P, G.cp, G.ss,
+                           G.us, nb, row, col, R2_d, Rs_d, cnt, goff, gpos, gdist, ovf);
+        GCHK(hipGetLastError());
+    }
+
     // node selection in rounds
     int *state = nullptr, *remaining = nullptr, *wait = nullptr, *cov = nullptr;
     GCHK(sc.get(state, N));
@@ -1042,8 +1393,12 @@ amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_gra
         // a few rounds per read-back; extra rounds after the last decision do nothing
         for (int r = 0; r < 4; ++r) {
             GCHK(hipMemsetAsync(remaining, 0, sizeof(int), st));
-            hipLaunchKernelGGL(k_g_round, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.rs, G.ss, G.us, nb, state, cov, wait,
-                               N, R2_d, remaining);
+            if (geo)
+                hipLaunchKernelGGL(k_g_round_geo, dim3(nb1), dim3(kGT), 0, st, G.rs, goff, gpos, state, cov, wait, N,
+                                   remaining);
+            else
+                hipLaunchKernelGGL(k_g_round, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.rs, G.ss, G.us, nb, state, cov,
+                                   wait, N, R2_d, remaining);
             ++rounds;
         }
         GCHK(hipMemcpyAsync(&left, remaining, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1094,7 +1449,13 @@ amm_status graph_build(void* stream, const amm_graph_in* in, int n_sets, amm_gra
     GCHK(hipMemsetAsync(gst, 0, 2 * sizeof(int) * n_sets, st));
     GCHK(sc.get(pk, std::max<int64_t>(M, 1)));
     GCHK(sc.get(pks, std::max<int64_t>(M, 1)));
-    if (dt == AMM_F64)
+    if (geo && dt == AMM_F64)
+        hipLaunchKernelGGL(k_g_influence_geo<double>, dim3(nb1), dim3(kGT), 0, st, G.ss, goff, gpos, gdist, nid_s,
+                           G.cp, node_off_d, R2_d, N, n_nodes, k, res->infl_idx, (double*)res->infl_w, pk, gst);
+    else if (geo)
+        hipLaunchKernelGGL(k_g_influence_geo<float>, dim3(nb1), dim3(kGT), 0, st, G.ss, goff, gpos, gdist, nid_s,
+                           G.cp, node_off_d, R2_d, N, n_nodes, k, res->infl_idx, (float*)res->infl_w, pk, gst);
+    else if (dt == AMM_F64)
         hipLaunchKernelGGL(k_g_influence<double>, dim3(nb1), dim3(kGT), 0, st, G.Ps, G.ss, G.us, nb, nid_s, G.cp,
                            node_off_d, R2_d, N, n_nodes, k, res->infl_idx, (double*)res->infl_w, pk, gst);
     else

@@ -168,3 +168,88 @@ def test_graphs_of_many_sets_in_one_build_equal_single_builds():
             assert torch.equal(a, b)
     # and set 2 against the oracle
     _check_against_oracle(sets[2], 4, many[2])
+
+
+def _check_geodesic_against_oracle(V, k, got, radius):
+    info, node, idx, w, edges = got
+    ref = G.build_graph_geodesic(V, radius, k)
+    assert info["radius"] == pytest.approx(radius, rel=1e-15)
+    assert np.array_equal(node.cpu().numpy(), ref["node_idx"])
+    assert np.array_equal(idx.cpu().numpy(), ref["infl_idx"])
+    assert np.abs(w.cpu().numpy().astype(np.float64) - ref["infl_w"]).max() <= 1e-12
+    assert np.array_equal(edges.cpu().numpy(), ref["edges"])
+    assert info["n_capped"] == ref["n_capped"]
+    assert info["max_influences"] == ref["max_influences"]
+    return ref
+
+
+@pytest.mark.parametrize("case", ["torus700_k4", "strip_k6", "sh50k_k4"])
+def test_geodesic_graph_matches_oracle(case):
+    """Alg. 1 with the geodesic distance of Eq. (1) over the symmetrized 6-NN
+    edge graph: nodes, influence indices and edges bit-exact against the
+    oracle's shortest-path build, weights within 1e-12; on the folded strip
+    the influence sets of points away from the fold stay on their own arm."""
+    _announce(f"test_geodesic_graph_matches_oracle {case}")
+    arm = None
+    if case == "torus700_k4":
+        V, k = synth.torus_pair(1000, n_src=700, n_tgt=10, n_nodes=20, k=4, e=6).src, 4
+        R = 5.0 * G.mean_edge_length(V)
+    elif case == "strip_k6":
+        rng = np.random.default_rng(21)
+        n, gap = 800, 0.1                   # at most ~800 points within R of a point
+        t0, t1 = rng.uniform(0, 1, n), rng.uniform(0, 1, n)
+        th = rng.uniform(-np.pi / 2, np.pi / 2, n // 6)
+        V = np.concatenate([np.stack([t0, np.zeros(n), rng.uniform(0, 0.05, n)], 1),
+                            np.stack([t1, np.full(n, gap), rng.uniform(0, 0.05, n)], 1),
+                            np.stack([1 + 0.5 * gap * np.cos(th), 0.5 * gap + 0.5 * gap * np.sin(th),
+                                      rng.uniform(0, 0.05, len(th))], 1)])
+        arm = np.concatenate([np.zeros(n), np.ones(n), np.full(len(th), 2)])
+        k, R = 6, 0.25
+    else:
+        V, k = synth.make_workload("sh50k").src, 4
+        R = 5.0 * G.mean_edge_length(V)
+    assert _axis_margin(V) > 1e-12
+    h = _handle()
+    try:
+        got = amm.build_graph(h, torch.tensor(V, device="cuda:0"), k, radius=R, geodesic=True)
+        torch.cuda.synchronize()
+    finally:
+        amm.amm_destroy(h)
+    print(f"{case} geodesic: {got[0]}", file=sys.stderr)
+    ref = _check_geodesic_against_oracle(V, k, got, R)
+    if arm is not None:
+        na = arm[ref["node_idx"]]
+        far = (V[:, 0] < 1 - R - 0.05) & (arm < 2)
+        idx = got[2].cpu().numpy()
+        for q in np.nonzero(far)[0]:
+            js = idx[q][idx[q] >= 0]
+            assert np.all(na[js] == arm[q])
+
+
+def test_geodesic_graph_registration():
+    """A registration run on a graph built with the geodesic distance: the
+    50,000-point pair's graph from the device build feeds amm_problem and
+    Alg. 2 converges, with a registration error close to the Euclidean
+    graph's (Eq. 25, both against the generator's ground truth)."""
+    _announce("test_geodesic_graph_registration")
+    pair = synth.make_workload("sh50k")
+    dev = "cuda:0"
+    rm = {}
+    for geo in (False, True):
+        h = _handle()
+        try:
+            info, node, idx, w, edges = amm.build_graph(h, torch.tensor(pair.src, device=dev), 4, geodesic=geo)
+            t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+            prob = amm.make_problem(t(pair.src, torch.float32), t(pair.tgt, torch.float32), node, idx,
+                                    w.to(torch.float32), edges, info["mean_edge_len"])
+            amm.amm_set_problem(h, prob)
+            v = torch.empty(pair.n_src, 3, dtype=torch.float32, device=dev)
+            st = amm.amm_solve(h, amm.amm_params_default(aa_m=5), None, v)[0]
+            torch.cuda.synchronize()
+            rm[geo] = math.sqrt(((v.cpu().numpy().astype(np.float64) - pair.gt) ** 2).sum(1).mean())
+            print(f"geodesic={geo}: {info['n_nodes']} nodes, {st['iters']} MM iterations, rmse {rm[geo]:.4e}",
+                  file=sys.stderr)
+            assert st["iters"] > 0 and math.isfinite(st["energy"])
+        finally:
+            amm.amm_destroy(h)
+    assert rm[True] < 1.5 * rm[False]
