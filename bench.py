@@ -414,10 +414,11 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
 
 
 def graph_build_report(amm, torch, h, pair, k, with_cpu):
-    """Device construction of the deformation graph (Alg. 1, Euclidean R =
-    5 l) on the workload's source points: wall time of amm_build_graph (it
-    synchronizes internally), median of 3 after one untimed build; with the
-    CPU leg, the oracle's sequential pass on the same points."""
+    """Device construction of the deformation graph (Alg. 1, R = 5 l) on the
+    workload's source points, with Euclidean and with geodesic distance:
+    wall time of amm_build_graph (it synchronizes internally), median of 3
+    after one untimed build; with the CPU leg, the oracle's sequential
+    Euclidean pass on the same points."""
     src = torch.tensor(pair.src, device="cuda:0")
     amm.amm_build_graph(h, src, k)
     ts = []
@@ -428,6 +429,16 @@ def graph_build_report(amm, torch, h, pair, k, with_cpu):
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t)
     out = {"gpu_ms": 1e3 * float(np.median(ts)), "k": k, **info}
+    # the same build with the geodesic distance over the 6-NN edge graph
+    amm.amm_build_graph(h, src, k, geodesic=True)
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ginfo = amm.amm_build_graph(h, src, k, geodesic=True)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    out["geodesic"] = {"gpu_ms": 1e3 * float(np.median(ts)), **ginfo}
     if with_cpu:
         from oracle import graph_oracle as G
         t = time.perf_counter()
@@ -705,7 +716,9 @@ def main():
         variants = variants_run(amm, torch, h, pair, args.steps, aa_m)
         graph = graph_build_report(amm, torch, h, pair, pair.k, not args.no_cpu)
         log(f"[bench] graph build (Alg. 1): {graph['gpu_ms']:.1f} ms on the GPU, {graph['n_nodes']} nodes, "
-            f"{graph['rounds']} rounds" + (f"; oracle {graph['cpu_oracle_s']:.1f} s" if 'cpu_oracle_s' in graph else ""))
+            f"{graph['rounds']} rounds; geodesic {graph['geodesic']['gpu_ms']:.1f} ms, "
+            f"{graph['geodesic']['n_nodes']} nodes"
+            + (f"; oracle {graph['cpu_oracle_s']:.1f} s" if 'cpu_oracle_s' in graph else ""))
     finally:
         amm.amm_destroy(h)
 

@@ -213,10 +213,14 @@ amm_status amm_check_problem(const amm_problem* p);
 /* Replaces the target points of pair `pair` (0-based within the last
  * amm_set_problems batch) by n_tgt new ones of the same count, keeping the
  * source side (graph, pattern of K, point lists, coarse aggregates) as it
- * is; only the pair's search structures (tree and grid) are rebuilt.  For registering one template
- * to a sequence of frames (Sec. 4's sequences) without a new upload.  The
- * result equals a new amm_set_problems with the new targets.  Pointers are
- * device pointers when on_device = 1.  Errors: AMM_ERR_STATE before a
+ * is; only the pair's closest-point structure (the targets in Morton order
+ * and the octree's run-start tables, at the pair's octree depth) is rebuilt,
+ * on the device (the coordinates of host inputs are copied there first).
+ * For registering one template to a sequence of frames (Sec. 4's sequences)
+ * without a new upload.  The result equals a new amm_set_problems with the
+ * new targets.  Pointers are device pointers when on_device = 1; the call
+ * synchronizes the device before reading them and returns once the new
+ * structure is in place.  Errors: AMM_ERR_STATE before a
  * problem is set, AMM_ERR_INVALID_ARG (pair, count, dtype, null),
  * AMM_ERR_NONFINITE. */
 amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const void* tgt_xyz, int64_t n_tgt,

@@ -23,7 +23,7 @@ HIP_FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-Xclang", "-target-f
              "-packed-fp32-ops", "-fPIC", "-I", INCLUDE, "-I", CSRC]
 CXX_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
-HIP_SOURCES = ["amm_kernels.hip", "amm_cg.hip", "amm_graph.hip", "amm_api.hip"]
+HIP_SOURCES = ["amm_kernels.hip", "amm_cg.hip", "amm_graph.hip", "amm_targets.hip", "amm_api.hip"]
 CXX_SOURCES = ["amm_setup.cpp"]
 
 

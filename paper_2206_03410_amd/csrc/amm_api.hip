@@ -341,6 +341,7 @@ struct amm_handle {
     long long* nn_work = nullptr;    // [n_pt_tiles][4] search counters while counting is on
     int nn_work_tiles = 0;
     GraphBuild* graph = nullptr;     // last amm_build_graph result
+    DeviceTargetWork tw;             // work buffer of the device target layout (amm_set_targets)
     EventTimer timer;
     std::vector<amm_iter_record> iter_log;
 };
@@ -1534,6 +1535,7 @@ void amm_destroy(amm_handle* h) {
     if (h->prog) (void)hipHostFree(h->prog);
     if (h->nn_work) (void)hipFree(h->nn_work);
     if (h->graph) graph_release(h->graph);
+    if (h->tw.buf) (void)hipFree(h->tw.buf);
     if (h->h_scratch) (void)hipHostFree(h->h_scratch);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
     if (h->ws_own) (void)hipFree(h->ws_own);
@@ -1794,48 +1796,33 @@ amm_status amm_set_targets(amm_handle* h, int32_t pair, amm_dtype dtype, const v
     if (n_tgt != pi.M) return fail(h, AMM_ERR_INVALID_ARG, "n_tgt must equal the pair's target count");
     HIPC(hipSetDevice(h->device));
     HIPC(hipStreamSynchronize(h->stream));   // nothing may still read the old targets
-    std::vector<double> tgt(3 * (size_t)n_tgt);
     const size_t es = dtype == AMM_F32 ? 4 : 8;
-    std::vector<char> raw(es * tgt.size());
-    if (on_device) {
-        HIPC(hipDeviceSynchronize());
-        HIPC(hipMemcpy(raw.data(), tgt_xyz, raw.size(), hipMemcpyDeviceToHost));
-    } else {
-        std::memcpy(raw.data(), tgt_xyz, raw.size());
-    }
-    for (size_t i = 0; i < tgt.size(); ++i) {
-        tgt[i] = es == 8 ? reinterpret_cast<const double*>(raw.data())[i]
-                         : (double)reinterpret_cast<const float*>(raw.data())[i];
-        if (!std::isfinite(tgt[i])) return fail(h, AMM_ERR_NONFINITE, "non-finite target coordinate");
-    }
-    // the octree keeps the pair's depth, so its tables keep their size
-    TargetLayout tl;
-    target_layout(tgt.data(), n_tgt, h->leaf, tl, pi.grid_bits);
-    Layout& L = h->L;
-    std::copy(tl.tgt4.begin(), tl.tgt4.end(), L.tgt4.begin() + 4 * pi.tgt_off);
-    std::copy(tl.tgt_user.begin(), tl.tgt_user.end(), L.tgt_user.begin() + pi.tgt_off);
-    std::copy(tl.cells.begin(), tl.cells.end(), L.grid_cells.begin() + pi.grid_off);
-    for (int c = 0; c < 3; ++c) {
-        pi.glo[c] = tl.glo[c];
-        pi.gscale[c] = tl.gscale[c];
-        pi.cs[c] = tl.cs[c];
-    }
-    pi.gpad = tl.gpad;
     Dev& v = h->v;
-    HIPC(hipMemcpyAsync(v.grid_cells + pi.grid_off, tl.cells.data(), sizeof(int32_t) * tl.cells.size(),
-                        hipMemcpyHostToDevice, h->stream));
+    const void* src = tgt_xyz;
+    if (on_device) {
+        HIPC(hipDeviceSynchronize());        // the caller's writes to tgt_xyz, on any stream
+    } else {
+        // the raw coordinates into the float64 staging area (4 M values)
+        HIPC(hipMemcpyAsync(v.staging, tgt_xyz, es * 3 * (size_t)n_tgt, hipMemcpyHostToDevice, h->stream));
+        src = v.staging;
+    }
+    // the search structure is rebuilt on the device, bit for bit the host
+    // layout's, at the pair's depth (so its tables keep their size); the
+    // host copies of the target arrays keep the set-up values
+    TargetLayout frame;
+    std::string err;
+    const amm_status st = device_target_layout(h->stream, h->tw, dtype == AMM_F64, src, n_tgt, pi.grid_bits,
+                                               v.sf.tgt + pi.tgt_off, v.sd.tgt + pi.tgt_off,
+                                               v.tgt_user + pi.tgt_off, v.grid_cells + pi.grid_off, frame, err);
+    if (st != AMM_OK) return fail(h, st, err);
+    for (int c = 0; c < 3; ++c) {
+        pi.glo[c] = frame.glo[c];
+        pi.gscale[c] = frame.gscale[c];
+        pi.cs[c] = frame.cs[c];
+    }
+    pi.gpad = frame.gpad;
     HIPC(hipMemcpyAsync(v.info + pair, &pi, sizeof(PairInfo), hipMemcpyHostToDevice, h->stream));
-    HIPC(hipMemcpyAsync(v.tgt_user + pi.tgt_off, tl.tgt_user.data(), sizeof(int32_t) * n_tgt,
-                        hipMemcpyHostToDevice, h->stream));
-    auto put = [&](float* df, double* dd, const std::vector<double>& src) -> amm_status {
-        HIPC(hipMemcpyAsync(v.staging, src.data(), src.size() * 8, hipMemcpyHostToDevice, h->stream));
-        launch_cast_static<float>(v.staging, df, (int64_t)src.size(), h->stream);
-        launch_cast_static<double>(v.staging, dd, (int64_t)src.size(), h->stream);
-        HIPC(hipStreamSynchronize(h->stream));
-        return AMM_OK;
-    };
-    TRY(put(reinterpret_cast<float*>(v.sf.tgt + pi.tgt_off), reinterpret_cast<double*>(v.sd.tgt + pi.tgt_off),
-            tl.tgt4));
+    HIPC(hipStreamSynchronize(h->stream));
     return AMM_OK;
 }
 

@@ -162,6 +162,21 @@ struct TargetLayout {
     std::vector<int32_t> cells;      // sum over l <= grid_bits of (8^l + 1)
 };
 void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out, int depth = 0);
+// glo, gscale, cs and gpad of a target set with bounding box [lo, hi]
+void target_frame(const double lo[3], const double hi[3], TargetLayout& out);
+
+// The same layout built on the device for a target set whose octree depth is
+// already fixed (a pair's targets replaced): tgt (float32 or float64 by
+// dtype_f64, M points, device memory) -> sorted targets in both precisions,
+// their user indices, the run-start tables (levels 0..depth) and the frame
+// fields of `frame`.  The work buffer grows as needed (freed by the caller).
+struct DeviceTargetWork {
+    void* buf = nullptr;
+    size_t bytes = 0;
+};
+amm_status device_target_layout(void* stream, DeviceTargetWork& w, bool dtype_f64, const void* tgt, int64_t M,
+                                int depth, void* tgt_f4, void* tgt_d4, int32_t* tgt_user, int32_t* cells,
+                                TargetLayout& frame, std::string& err);
 
 // Device-built deformation graph (Alg. 1), kept by a handle between
 // amm_build_graph and amm_graph_copy.  stream is a hipStream_t.

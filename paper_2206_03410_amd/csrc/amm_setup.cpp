@@ -641,6 +641,24 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     return AMM_OK;
 }
 
+void target_frame(const double lo[3], const double hi[3], TargetLayout& out) {
+    double emax = 0, amax = 0;
+    for (int c = 0; c < 3; ++c) {
+        const double ext = hi[c] - lo[c];
+        out.glo[c] = lo[c];
+        out.gscale[c] = ext > 0 ? 1023.999 / ext : 0.0;
+        // root cell: quantized coordinates 0..1023 span 1024 / gscale
+        out.cs[c] = ext > 0 ? 1024.0 / out.gscale[c] : 0.0;
+        emax = std::max(emax, ext);
+        amax = std::max({amax, std::fabs(lo[c]), std::fabs(hi[c])});
+    }
+    // the cell bounds are formed in the search's precision (float32 on the
+    // FP32 path) from coordinates up to amax: a relative 1e-6 of the extent
+    // plus 16 float32 ulps of the largest coordinate covers their rounding
+    // and that of the stored targets
+    out.gpad = 1e-6 * emax + 16.0 * std::ldexp(amax, -24);
+}
+
 void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out, int depth) {
     const Box bb = bounds(tgt, M);
     std::vector<uint32_t> code(M);
@@ -673,21 +691,7 @@ void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out, in
         }
     }
     out.grid_bits = G;
-    double emax = 0, amax = 0;
-    for (int c = 0; c < 3; ++c) {
-        const double ext = bb.hi[c] - bb.lo[c];
-        out.glo[c] = bb.lo[c];
-        out.gscale[c] = ext > 0 ? 1023.999 / ext : 0.0;
-        // root cell: quantized coordinates 0..1023 span 1024 / gscale
-        out.cs[c] = ext > 0 ? 1024.0 / out.gscale[c] : 0.0;
-        emax = std::max(emax, ext);
-        amax = std::max({amax, std::fabs(bb.lo[c]), std::fabs(bb.hi[c])});
-    }
-    // the cell bounds are formed in the search's precision (float32 on the
-    // FP32 path) from coordinates up to amax: a relative 1e-6 of the extent
-    // plus 16 float32 ulps of the largest coordinate covers their rounding
-    // and that of the stored targets
-    out.gpad = 1e-6 * emax + 16.0 * std::ldexp(amax, -24);
+    target_frame(bb.lo, bb.hi, out);
     // leaf-level run starts by counting, coarser levels by sampling them
     const size_t nleaf = (size_t)1 << (3 * G);
     std::vector<int32_t> leafst(nleaf + 1, 0);

@@ -133,3 +133,60 @@ def test_set_targets_arguments_are_validated(seq):
         assert ei.value.status == amm.AMM_ERR_STATE
     finally:
         amm.amm_destroy(h)
+
+
+def test_set_targets_from_host_float32(seq):
+    """New targets given as float32 coordinates in host memory: the solve
+    equals, bitwise, that of a new upload of the same (float32-valued)
+    coordinates."""
+    _announce("test_set_targets_from_host_float32")
+    t32 = np.ascontiguousarray(seq.frames[3], np.float32)
+    n = seq.template.n_nodes
+    res = []
+    for swap in (False, True):
+        pair = _frame_pair(seq, 0) if swap else dataclasses.replace(_frame_pair(seq, 3), tgt=t32.astype(np.float64))
+        with Session(pair, torch.float64) as s:
+            if swap:
+                amm.amm_set_targets(s.h, 0, t32)
+            X = torch.empty(n, 4, 3, dtype=torch.float64, device="cuda:0")
+            st = amm.amm_solve(s.h, amm.amm_params_default(aa_m=5, max_total_iters=8,
+                                                           precision=amm.AMM_FP64_PLAIN), X)[0]
+            torch.cuda.synchronize()
+            res.append((X.cpu().numpy(), st))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][1]["energy"] == res[1][1]["energy"]
+
+
+def test_set_targets_permuted_200k():
+    """The 200,000 targets of the large pair handed back in a shuffled
+    order (a new Morton sort and new octree tables, built on the device):
+    every closest distance equals the set-up structure's bitwise, and the
+    closest target is the same point wherever the best and second-best
+    distances differ by more than 1e-6 relative."""
+    _announce("test_set_targets_permuted_200k")
+    from scipy.spatial import cKDTree
+    from tests.helpers import margin_ok, rounded
+    pair = rounded(synth.make_workload("sh200k"), np.float32)
+    N, n = pair.n_src, pair.n_nodes
+    X = torch.tensor(synth.perturbed_transforms(n, 7111, 0.01, 0.001).astype(np.float32), device="cuda:0")
+    perm = np.random.default_rng(7112).permutation(pair.n_tgt)
+    out = []
+    with Session(pair, torch.float32) as s:
+        for swap in (False, True):
+            if swap:
+                amm.amm_set_targets(s.h, 0, torch.tensor(pair.tgt[perm], dtype=torch.float32, device="cuda:0"))
+            rho = torch.empty(N, dtype=torch.int32, device="cuda:0")
+            d2 = torch.empty(N, dtype=torch.float32, device="cuda:0")
+            vh = torch.empty(N, 3, dtype=torch.float32, device="cuda:0")
+            amm.amm_step(s.h, X, 0.02, 0.05, 10.0, 100.0, amm.AMM_FP32_REFINE, rho=rho, d2=d2, v_hat=vh)
+            torch.cuda.synchronize()
+            out.append((rho.cpu().numpy(), d2.cpu().numpy(), vh.cpu().numpy().astype(np.float64)))
+    (r0, d0, v0), (r1, d1, v1) = out
+    assert np.array_equal(v0, v1)
+    assert np.array_equal(d0, d1)
+    dk, _ = cKDTree(pair.tgt).query(v0, k=2)
+    ok = margin_ok(dk[:, 0] ** 2, dk[:, 1] ** 2)
+    print(f"sh200k permuted targets: {ok.sum()} of {N} above the margin, "
+          f"{int((perm[r1][ok] != r0[ok]).sum())} differ", file=sys.stderr)
+    assert ok.mean() > 0.99
+    assert np.array_equal(perm[r1][ok], r0[ok])
