@@ -33,27 +33,27 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: a change to those files voids them.
 MEASURED_TRAFFIC = {
     "cg_step": {"fetch_kib": 4627.1, "fetch_per_byte": 131084.5 / 262144.0,
-                "write_kib": 1129.7, "write_per_byte": 262144.0 / 262144.0,
+                "write_kib": 1141.3, "write_per_byte": 262144.0 / 262144.0,
                 "sources": {
                             "paper_2206_03410_amd/csrc/amm_cg.hip": "041f80b3acd36689",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
                             "paper_2206_03410_amd/csrc/amm_kernels.h": "a863928bec2572a6",
-                            "paper_2206_03410_amd/csrc/amm_internal.h": "52cb82b556b6efb6"}},
-    "eval_points": {"fetch_kib": 11442.6, "fetch_per_byte": 131084.5 / 262144.0,
+                            "paper_2206_03410_amd/csrc/amm_internal.h": "951794fcfb7e2853"}},
+    "eval_points": {"fetch_kib": 10064.8, "fetch_per_byte": 131084.5 / 262144.0,
                     "write_kib": 7519.8, "write_per_byte": 262144.0 / 262144.0,
                     "sources": {
                             "paper_2206_03410_amd/csrc/amm_kernels.hip": "9b0cac661aa65163",
-                            "paper_2206_03410_amd/csrc/amm_nn.h": "0a90030f28ac067e",
+                            "paper_2206_03410_amd/csrc/amm_nn.h": "522ec283e04e5f34",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
                             "paper_2206_03410_amd/csrc/amm_kernels.h": "a863928bec2572a6",
-                            "paper_2206_03410_amd/csrc/amm_internal.h": "52cb82b556b6efb6"}},
-    "assemble": {"fetch_kib": 16840.7, "fetch_per_byte": 131084.5 / 262144.0,
-                 "write_kib": 6404.7, "write_per_byte": 262144.0 / 262144.0,
+                            "paper_2206_03410_amd/csrc/amm_internal.h": "951794fcfb7e2853"}},
+    "assemble": {"fetch_kib": 16839.4, "fetch_per_byte": 131084.5 / 262144.0,
+                 "write_kib": 6404.0, "write_per_byte": 262144.0 / 262144.0,
                  "sources": {
                             "paper_2206_03410_amd/csrc/amm_kernels.hip": "9b0cac661aa65163",
                             "paper_2206_03410_amd/csrc/amm_device.h": "b6148a4b3f8d8557",
                             "paper_2206_03410_amd/csrc/amm_kernels.h": "a863928bec2572a6",
-                            "paper_2206_03410_amd/csrc/amm_internal.h": "52cb82b556b6efb6"}},
+                            "paper_2206_03410_amd/csrc/amm_internal.h": "951794fcfb7e2853"}},
 }
 
 
