@@ -374,10 +374,12 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / float(np.median(ts)) / 1e9
 
 
-def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
+def nn_search_report(amm, torch, h, pair, aa_m, steps, kt):
     """Work of the exact closest-point search over one FP32 solve (counted in
-    a separate, untimed solve) against the eval_points kernel's measured
-    average launch time.  Headline candidate traffic per launch = queries x
+    a separate, untimed solve) against the measured time of the point
+    evaluation per evaluation: the budgeted searches (eval_points), the
+    deferred ones (eval_far) and the tile sums (eval_sums), from HIP events
+    on their dispatches.  Headline candidate traffic per launch = queries x
     (12 B warped query + 8 B outputs) + target points examined x 16 B (one
     float4 each).  The search structure's own reads (nine 4-byte run starts
     per octree cell expansion read from memory) are reported apart: they
@@ -391,12 +393,16 @@ def nn_search_report(amm, torch, h, pair, aa_m, steps, eval_ms, eval_launches):
         amm.amm_count_nn_work(h, False)
     launches = max(1, round(w["queries"] / pair.n_src))
     q, bx, de, cl = (w[k] / launches for k in ("queries", "box_tests", "distance_evals", "cell_lookups"))
-    t = eval_ms / eval_launches * 1e-3
+    n_eval = kt["eval_points"][1]
+    part_us = {g: 1e3 * kt[g][0] / n_eval for g in ("eval_points", "eval_far", "eval_sums") if g in kt}
+    t = sum(part_us.values()) * 1e-6
     cand = q * (12 + 8) + de * 16
     struct = cl * 36
     comp = pair.n_src * (12 + 4 + 4) + 12 * pair.n_tgt
     flops = 8 * de + 14 * bx
-    return {"kernel": "eval_points", "avg_launch_us": t * 1e6, "queries_per_launch": q,
+    return {"kernel": "eval_points + eval_far + eval_sums", "avg_launch_us": t * 1e6,
+            "per_kernel_us": part_us, "search_step_budget": amm.amm_get_search_budget(h),
+            "queries_per_launch": q,
             "cell_bound_tests_per_query": bx / q, "cell_expansions_from_memory_per_query": cl / q,
             "distance_evals_per_query": de / q,
             "compulsory_GBps": comp / t / 1e9,
@@ -659,7 +665,9 @@ def main():
     try:
         prob = gpu_problem(amm, torch, pair)
         leaf, leaf_ms = amm.amm_autotune(h, [prob])
-        log(f"[bench] autotuned closest-point leaf size {leaf} (warm evaluation {leaf_ms:.3f} ms)")
+        budget = amm.amm_get_search_budget(h)
+        log(f"[bench] autotuned closest-point leaf size {leaf}, search step budget {budget} "
+            f"(warm evaluation {leaf_ms:.3f} ms)")
         pair.nnzb = amm.amm_k_nnzb(h)
         # first use of every kernel (code objects load lazily), untimed
         for prec in (amm.AMM_FP32_REFINE, amm.AMM_FP64_PLAIN):
@@ -704,10 +712,11 @@ def main():
                      "solves_above_rtol": [st_d["solves_above_rtol"], st64d["solves_above_rtol"]],
                      "fp32_replayed_vs_fp64": rep}
         # the search's average launch time over the same solve that is counted
-        _, _, _, kt_e = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m,
-                                  timing="eval_points")
-        nn = nn_search_report(amm, torch, h, pair, aa_m, args.steps, *kt_e["eval_points"])
-        log(f"[bench] closest points: {nn['cell_bound_tests_per_query']:.1f} cell bound tests, "
+        _, _, _, kt_e = run_solve(amm, torch, h, pair, amm.AMM_FP32_REFINE, args.steps, aa_m, timing="")
+        nn = nn_search_report(amm, torch, h, pair, aa_m, args.steps, kt_e)
+        log(f"[bench] closest points: {nn['avg_launch_us']:.1f} us per evaluation ("
+            + ", ".join(f"{k} {v:.1f}" for k, v in nn["per_kernel_us"].items()) + f"); "
+            f"{nn['cell_bound_tests_per_query']:.1f} cell bound tests, "
             f"{nn['cell_expansions_from_memory_per_query']:.1f} cell expansions from memory and "
             f"{nn['distance_evals_per_query']:.1f} distance evaluations per query; candidate traffic "
             f"{nn['candidate_traffic_GBps']:.0f} GB/s")

@@ -265,12 +265,28 @@ amm_status amm_get_sizes(const amm_handle* h, int32_t* n_pairs, int64_t* n_src_t
  * scan more targets per leaf. */
 amm_status amm_set_leaf_size(amm_handle* h, int32_t leaf);
 
+/* Step budget of one point's closest-point search (the rho(i) of Eq. 5,
+ * Sec. 3.2) inside an evaluation, in search steps (cell expansions and cell
+ * visits; 0..1000000, default 64; 0 = unlimited).  Searches that exceed it
+ * stop with their best target so far and are finished afterwards by an
+ * exact search that spreads each point over a whole wavefront, so that a
+ * few far points (outliers, uncovered regions) do not hold up the waves of
+ * near ones.  Results do not depend on the budget (the search is exact,
+ * ties to the lowest target index), only the time does.  Takes effect at
+ * the next evaluation.  Errors: AMM_ERR_INVALID_ARG outside the range. */
+amm_status amm_set_search_budget(amm_handle* h, int32_t steps);
+
+/* The step budget in use (set, or picked by amm_autotune). */
+amm_status amm_get_search_budget(const amm_handle* h, int32_t* steps);
+
 /* Autotuner: uploads the problems once per candidate leaf size (candidates
- * NULL: 2, 4, 8, 16), times a warm-started float32 evaluation (warp,
- * closest points, Welsch terms, the per-iteration search of Alg. 2) of
- * every pair at X = I with HIP events, and leaves the handle set up with the
- * fastest.  best_leaf and best_ms (host, nullable) receive the choice and
- * its time.  With a caller workspace, candidates that do not fit it are
+ * NULL: 2, 4, 8, 16) and, for each, times a warm-started float32 evaluation
+ * (warp, closest points, Welsch terms, the per-iteration search of Alg. 2)
+ * of every pair at X = I with HIP events under search step budgets of 32,
+ * 48, 64, 96, 128 and unlimited (amm_set_search_budget); leaves the handle
+ * set up with the fastest leaf size and budget.  best_leaf and best_ms
+ * (host, nullable) receive the leaf size and the time; the budget is read
+ * with amm_get_search_budget.  With a caller workspace, candidates that do not fit it are
  * skipped.  Replaces any previous problems, like amm_set_problems. */
 amm_status amm_autotune(amm_handle* h, const amm_problem* probs, int32_t n_pairs, const int32_t* candidates,
                         int32_t n_candidates, int32_t* best_leaf, double* best_ms);

@@ -120,6 +120,8 @@ def lib():
             "amm_set_problems": ([vp, C.POINTER(amm_problem), i32], C.c_int),
             "amm_set_problem": ([vp, C.POINTER(amm_problem)], C.c_int),
             "amm_set_leaf_size": ([vp, i32], C.c_int),
+            "amm_set_search_budget": ([vp, i32], C.c_int),
+            "amm_get_search_budget": ([vp, C.POINTER(i32)], C.c_int),
             "amm_count_nn_work": ([vp, i32], C.c_int),
             "amm_build_graph": ([vp, C.POINTER(amm_graph_in), C.POINTER(amm_graph_info)], C.c_int),
             "amm_set_targets": ([vp, i32, C.c_int, vp, i64, i32], C.c_int),
@@ -157,7 +159,7 @@ def lib():
 
 EXPORTED = ["amm_create", "amm_destroy", "amm_set_stream", "amm_check_problem",
             "amm_workspace_size", "amm_set_workspace", "amm_set_problems", "amm_set_problem",
-            "amm_set_leaf_size", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
+            "amm_set_leaf_size", "amm_set_search_budget", "amm_get_search_budget", "amm_autotune", "amm_count_nn_work", "amm_nn_work",
             "amm_build_graph", "amm_graph_copy", "amm_set_targets", "amm_build_graphs", "amm_graph_copy_set",
             "amm_solve", "amm_step", "amm_k_nnzb", "amm_get_sizes", "amm_iter_log", "amm_energy",
             "amm_energy_noalloc", "amm_energy_grad",
@@ -293,6 +295,16 @@ def amm_set_leaf_size(handle, leaf: int) -> None:
     _check(lib().amm_set_leaf_size(handle, int(leaf)), handle)
 
 
+def amm_set_search_budget(handle, steps: int) -> None:
+    _check(lib().amm_set_search_budget(handle, int(steps)), handle)
+
+
+def amm_get_search_budget(handle) -> int:
+    v = C.c_int32(0)
+    _check(lib().amm_get_search_budget(handle, C.byref(v)), handle)
+    return int(v.value)
+
+
 def amm_set_targets(handle, pair: int, tgt) -> None:
     """New target points (same count) for one pair of the handle's batch; tgt
     is a cuda tensor or a numpy array [M][3]."""
@@ -378,8 +390,9 @@ def amm_nn_work(handle) -> dict:
 
 
 def amm_autotune(handle, problems: Sequence[amm_problem], candidates=None):
-    """Picks the closest-point leaf size by timing a warm evaluation per
-    candidate; returns (leaf, ms).  The handle is left set up with it."""
+    """Picks the closest-point leaf size and search step budget by timing a
+    warm evaluation per candidate; returns (leaf, ms).  The handle is left
+    set up with them (the budget: amm_get_search_budget)."""
     arr = (amm_problem * len(problems))(*problems)
     cand = None if candidates is None else (C.c_int32 * len(candidates))(*candidates)
     best = C.c_int32()

@@ -38,6 +38,7 @@ constexpr int kDynRing = 16;
 // first report (step 3) is launched only if the lookahead is at least 5;
 // each step queued past convergence costs an early-exit launch.
 constexpr int kCgLookahead = 6;
+constexpr int kNnBudgetDefault = 64;
 static_assert(kCgLookahead >= 5, "the first progress report (step 3) must be launchable");
 
 struct EventTimer final : KernelTimer {
@@ -174,6 +175,11 @@ struct Dyn {
     double* src_ovr;   // 4 per point
     double* pts_out;   // 4 per point
     double* sel;       // work of the median selection
+    int* far_count;    // deferred closest-point searches (zero between evaluations)
+    int2* far_list;
+    int* far_seed;
+    double* pt_psi;    // per point: alignment term and displacement (T)
+    double* pt_disp;
 };
 
 struct Dev {
@@ -301,6 +307,11 @@ void plan(const Layout& L, Carver& c, Dev& v) {
     c.take(d.src_ovr, 4 * N);
     c.take(d.pts_out, 4 * N);
     c.take(d.sel, (select_mid_work_bytes(L.P) + 7) / 8);
+    c.take(d.far_count, 1);
+    c.take(d.far_list, N);
+    c.take(d.far_seed, N);
+    c.take(d.pt_psi, N);
+    c.take(d.pt_disp, N);
 }
 
 }  // namespace
@@ -338,6 +349,7 @@ struct amm_handle {
     bool timing = false;
     bool cg_coarse = true;           // two-level CG preconditioner
     int leaf = 8;                    // mean targets per occupied octree leaf cell (next upload)
+    int nn_budget = kNnBudgetDefault;   // closest-point search steps before a point goes to the wave search
     long long* nn_work = nullptr;    // [n_pt_tiles][4] search counters while counting is on
     int nn_work_tiles = 0;
     GraphBuild* graph = nullptr;     // last amm_build_graph result
@@ -537,6 +549,12 @@ EvalArgs<T> eval_args(amm_handle* h, bool use_override = false) {
     a.eg_part = d.eg_part;
     a.nd_part = d.nd_part;
     a.nn_work = h->nn_work;
+    a.nn_budget = h->nn_budget;
+    a.far_count = d.far_count;
+    a.far_list = d.far_list;
+    a.far_seed = d.far_seed;
+    a.pt_psi = reinterpret_cast<T*>(d.pt_psi);
+    a.pt_disp = reinterpret_cast<T*>(d.pt_disp);
     return a;
 }
 
@@ -1401,6 +1419,9 @@ amm_status energy_noalloc_impl(amm_handle* h, const void* X, const void* src, do
     // tile partials, the pair's parameters and outputs
     ScratchCarver c{reinterpret_cast<unsigned char*>(base)};
     const size_t N = L.Ntot, n = L.ntot, na = L.nadj;
+    // first, so that it sits at the same place for every problem: zero at
+    // load, and every evaluation leaves it at zero
+    int* s_far_count = c.take<int>(1);
     T* sX = c.take<T>(12 * n);
     V* s_src = src ? c.take<V>(N) : nullptr;
     V* s_vhat = c.take<V>(N);
@@ -1416,6 +1437,10 @@ amm_status energy_noalloc_impl(amm_handle* h, const void* X, const void* src, do
     double* s_nd_part = c.take<double>(L.n_nd_tiles);
     PairOut* s_out = c.take<PairOut>(1);
     PairDyn* s_dyn = c.take<PairDyn>(1);
+    int2* s_far_list = c.take<int2>(N);
+    int* s_far_seed = c.take<int>(N);
+    T* s_psi = c.take<T>(N);
+    T* s_disp = c.take<T>(N);
     if (!c.ok)
         return fail(h, AMM_ERR_INVALID_ARG,
                     "problem too large for the allocation-free scratch (" + std::to_string(c.off) +
@@ -1447,6 +1472,11 @@ amm_status energy_noalloc_impl(amm_handle* h, const void* X, const void* src, do
     a.eg_part = s_eg_part;
     a.nd_part = s_nd_part;
     a.nn_work = nullptr;
+    a.far_count = s_far_count;
+    a.far_list = s_far_list;
+    a.far_seed = s_far_seed;
+    a.pt_psi = s_psi;
+    a.pt_disp = s_disp;
     FinalArgs f = final_args(h);
     f.dyn = s_dyn;
     f.out = s_out;
@@ -1659,6 +1689,9 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up(h, v.tile_ncols, Lr.tile_ncols));
     TRY(up(h, v.tile_rowl, Lr.tile_rowl));
     TRY(up(h, v.K_lcol, Lr.K_lcol));
+    // the deferred-search count starts at zero (each evaluation leaves it so)
+    HIPC(hipMemsetAsync(v.d.far_count, 0, sizeof(int), h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
     h->has_problem = true;
     h->rho_set0 = false;
     return AMM_OK;
@@ -1670,6 +1703,19 @@ amm_status amm_set_leaf_size(amm_handle* h, int32_t leaf) {
     if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
     if (leaf < 1 || leaf > 256) return fail(h, AMM_ERR_INVALID_ARG, "leaf size must be in 1..256");
     h->leaf = leaf;
+    return AMM_OK;
+}
+
+amm_status amm_set_search_budget(amm_handle* h, int32_t steps) {
+    if (!h) return fail(nullptr, AMM_ERR_INVALID_ARG, "null handle");
+    if (steps < 0 || steps > 1000000) return fail(h, AMM_ERR_INVALID_ARG, "search budget must be in 0..1000000");
+    h->nn_budget = steps;
+    return AMM_OK;
+}
+
+amm_status amm_get_search_budget(const amm_handle* h, int32_t* steps) {
+    if (!h || !steps) return fail(nullptr, AMM_ERR_INVALID_ARG, "null argument");
+    *steps = h->nn_budget;
     return AMM_OK;
 }
 
@@ -1726,7 +1772,10 @@ amm_status amm_autotune(amm_handle* h, const amm_problem* probs, int32_t n_pairs
         n_candidates = 4;
     }
     if (n_candidates < 1) return fail(h, AMM_ERR_INVALID_ARG, "no candidate leaf sizes");
-    int32_t best = -1;
+    // with each leaf size, the search budgets (the point at which a search is
+    // left to the wave-wide one) are timed too
+    static const int32_t kBudgets[] = {32, 48, 64, 96, 128, 0};
+    int32_t best = -1, best_budget = kNnBudgetDefault;
     double best_t = 1e30;
     for (int32_t c = 0; c < n_candidates; ++c) {
         if (candidates[c] < 1 || candidates[c] > 256) return fail(h, AMM_ERR_INVALID_ARG, "candidate leaf size out of range");
@@ -1734,15 +1783,20 @@ amm_status amm_autotune(amm_handle* h, const amm_problem* probs, int32_t n_pairs
         const amm_status st = amm_set_problems(h, probs, n_pairs);
         if (st == AMM_ERR_OOM && h->ws_user) continue;   // does not fit the caller's workspace
         if (st != AMM_OK) return st;
-        double t = 0;
-        TRY(time_warm_eval(h, t));
-        if (t < best_t) {
-            best_t = t;
-            best = candidates[c];
+        for (const int32_t b : kBudgets) {
+            h->nn_budget = b;
+            double t = 0;
+            TRY(time_warm_eval(h, t));
+            if (t < best_t) {
+                best_t = t;
+                best = candidates[c];
+                best_budget = b;
+            }
         }
     }
     if (best < 0) return fail(h, AMM_ERR_OOM, "no candidate leaf size fits the workspace");
     h->leaf = best;
+    h->nn_budget = best_budget;
     TRY(amm_set_problems(h, probs, n_pairs));
     if (best_leaf) *best_leaf = best;
     if (best_ms) *best_ms = best_t;

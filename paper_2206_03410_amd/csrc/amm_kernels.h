@@ -73,6 +73,12 @@ struct EvalArgs {
     double* nd_part;
     long long* nn_work;      // per point tile: queries, cell bound tests, distance evaluations,
                              // cell expansions read from memory (or null)
+    int nn_budget;           // search steps before a point is deferred (0: never)
+    int2* far_list;          // [Ntot] deferred points (point, pair)
+    int* far_seed;           // [Ntot] a deferred point's best target so far (sorted position, or -1)
+    int* far_count;          // zero between evaluations
+    T* pt_psi;               // [Ntot] each point's alignment term
+    T* pt_disp;              // [Ntot] each point's displacement
 };
 
 struct FinalArgs {

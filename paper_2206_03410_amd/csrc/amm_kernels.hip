@@ -20,15 +20,91 @@ namespace amm {
 
 // ---------------------------------------------------------------- evaluation
 
+// Warp of source point i (Eq. 2): v_hat (absolute, for the search) and, for
+// the residual, the small parts s = sum_j w_ij ((A_j - I)(v_i - p_j) + t_j)
+// and sw1 = sum_j w_ij - 1 (the weights' sum in float64: exact for k <= 8
+// terms).
+template <typename T, typename V>
+__device__ __forceinline__ void warp_point(const EvalArgs<T>& a, const T* __restrict__ X, int i, const V& v, T& vx,
+                                           T& vy, T& vz, T& sx, T& sy, T& sz, T& sw1) {
+    vx = vy = vz = sx = sy = sz = 0;
+    double sw = 0;
+    for (int s = 0; s < a.k; ++s) {
+        const int j = a.iidx[(size_t)s * a.Ntot + i];
+        const T w = a.iw[(size_t)s * a.Ntot + i];
+        const V pj = a.nodes[j];
+        const T* Xj = X + 12 * (size_t)j;
+        const T dx = v.x - pj.x, dyy = v.y - pj.y, dz = v.z - pj.z;
+        const T gx = dx * (Xj[0] - T(1)) + dyy * Xj[3] + dz * Xj[6] + Xj[9];
+        const T gy = dx * Xj[1] + dyy * (Xj[4] - T(1)) + dz * Xj[7] + Xj[10];
+        const T gz = dx * Xj[2] + dyy * Xj[5] + dz * (Xj[8] - T(1)) + Xj[11];
+        vx += w * (dx * Xj[0] + dyy * Xj[3] + dz * Xj[6] + Xj[9] + pj.x);
+        vy += w * (dx * Xj[1] + dyy * Xj[4] + dz * Xj[7] + Xj[10] + pj.y);
+        vz += w * (dx * Xj[2] + dyy * Xj[5] + dz * Xj[8] + Xj[11] + pj.z);
+        sx += w * gx;
+        sy += w * gy;
+        sz += w * gz;
+        sw += (double)w;
+    }
+    sw1 = (T)(sw - 1.0);
+}
+
+// Everything of point i that follows its closest target (sorted position
+// bpos of pair p): the residual e_i, the alignment term and weight, the
+// outputs, and the point's energy term and displacement for the tile sums.
+template <typename T, typename V>
+__device__ __forceinline__ void finish_point(const EvalArgs<T>& a, const PairDyn& dy, const PairInfo& pi, int i,
+                                             const V& v, T vx, T vy, T vz, T sx, T sy, T sz, T sw1, int bpos) {
+    const int dst = dy.eval_dst, cur = dy.cur;
+    const V u = a.tgt[pi.tgt_off + bpos];
+    // e_i = v_hat_i - u_rho(i)
+    //     = sum_j w_ij ((A_j - I) d_ij + t_j) + (v_i - u) + (sum_j w_ij - 1) v_i
+    // (Eq. 2 rearranged): every operand is small, so e_i keeps its relative
+    // accuracy where v_hat_i - u would cancel; d^2 is taken from it
+    V q;
+    q.x = sx + (v.x - u.x) + sw1 * v.x;
+    q.y = sy + (v.y - u.y) + sw1 * v.y;
+    q.z = sz + (v.z - u.z) + sw1 * v.z;
+    const T d2 = sq3(q.x, q.y, q.z);
+    T wa, psi;
+    if (dy.robust == AMM_ROBUST_WELSCH) {
+        const T inv = T(1) / (T(2) * (T)dy.nu_a * (T)dy.nu_a);
+        const T t = d2 * inv;
+        psi = -expm1(-t);
+        wa = exp(-t) * inv;
+    } else if (dy.robust == AMM_ROBUST_L2) {
+        psi = d2;
+        wa = T(1);
+    } else {
+        // truncated quadratic: weight 1 inside 3 nu_a, constant outside
+        const T tau2 = T(9) * (T)dy.nu_a * (T)dy.nu_a;
+        const bool in = d2 < tau2;
+        psi = in ? d2 : tau2;
+        wa = in ? T(1) : T(0);
+    }
+    q.w = wa;
+    a.qw[dst][i] = q;
+    a.rho[dst][i] = (int)pi.tgt_off + bpos;
+    a.d2[dst][i] = d2;
+    T disp = 0;
+    if (dy.has_prev) {
+        const V o = a.vhat[cur][i];
+        disp = sqrt(sq3(vx - o.x, vy - o.y, vz - o.z));
+    }
+    a.pt_psi[i] = psi;
+    a.pt_disp[i] = disp;
+}
+
 // Per source point: warp (Eq. 2), closest target, Welsch value and weight
 // (Eqs. 5, 6 and the weight w_a of Eq. 16) or those of a squared-norm
 // variant of Sec. 4.1, the alignment residual e_i = v_hat_i - u_rho(i), and
 // the max displacement against the accepted iterate.  One thread per point.
+// A search that exceeds the step budget (a.nn_budget) leaves its point to
+// k_eval_far (one wave per point); the tile sums follow in k_eval_sums.
 // COUNT adds the search's work to the tile's counters (reporting only).
 template <typename T, bool COUNT>
 __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
     using V = typename V4Of<T>::type;
-    __shared__ T sh[kPointTile];
     __shared__ long long shc[COUNT ? kPointTile : 1];
     __shared__ int oct[kOctLdsInts];
     NnWork wk{0, 0, 0};
@@ -46,85 +122,43 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
         __syncthreads();
     }
     const int i = td.y + (int)threadIdx.x;
-    const int dst = dy.eval_dst, cur = dy.cur;
+    const int dst = dy.eval_dst;
     const T* X = a.X[dy.eval_x];
     const V* src = a.src_override ? (const V*)a.src_override : (const V*)a.src;
-    T psi = 0, disp = 0;
+    bool far = false;
     if (i < td.z) {
         const V v = src[i];
-        // v_hat (absolute, for the search) and, for the residual, the small
-        // parts sum_j w_ij ((A_j - I)(v_i - p_j) + t_j) and sum_j w_ij - 1
-        // (the weights' sum in float64: exact for k <= 8 terms)
-        T vx = 0, vy = 0, vz = 0, sx = 0, sy = 0, sz = 0;
-        double sw = 0;
-        for (int s = 0; s < a.k; ++s) {
-            const int j = a.iidx[(size_t)s * a.Ntot + i];
-            const T w = a.iw[(size_t)s * a.Ntot + i];
-            const V pj = a.nodes[j];
-            const T* Xj = X + 12 * (size_t)j;
-            const T dx = v.x - pj.x, dyy = v.y - pj.y, dz = v.z - pj.z;
-            const T gx = dx * (Xj[0] - T(1)) + dyy * Xj[3] + dz * Xj[6] + Xj[9];
-            const T gy = dx * Xj[1] + dyy * (Xj[4] - T(1)) + dz * Xj[7] + Xj[10];
-            const T gz = dx * Xj[2] + dyy * Xj[5] + dz * (Xj[8] - T(1)) + Xj[11];
-            vx += w * (dx * Xj[0] + dyy * Xj[3] + dz * Xj[6] + Xj[9] + pj.x);
-            vy += w * (dx * Xj[1] + dyy * Xj[4] + dz * Xj[7] + Xj[10] + pj.y);
-            vz += w * (dx * Xj[2] + dyy * Xj[5] + dz * Xj[8] + Xj[11] + pj.z);
-            sx += w * gx;
-            sy += w * gy;
-            sz += w * gz;
-            sw += (double)w;
-        }
-        const T sw1 = (T)(sw - 1.0);
-        const int prev = dy.has_prev ? a.rho[cur][i] - (int)pi.tgt_off : -1;
-        int bpos;
-        T d2;
-        oct_search<T, V, COUNT>(pi, cells, oct, a.tgt, vx, vy, vz, prev, bpos, d2, &wk);
-        const V u = a.tgt[pi.tgt_off + bpos];
-        // e_i = v_hat_i - u_rho(i)
-        //     = sum_j w_ij ((A_j - I) d_ij + t_j) + (v_i - u) + (sum_j w_ij - 1) v_i
-        // (Eq. 2 rearranged): every operand is small, so e_i keeps its relative
-        // accuracy where v_hat_i - u would cancel; d^2 is taken from it
-        V q;
-        q.x = sx + (v.x - u.x) + sw1 * v.x;
-        q.y = sy + (v.y - u.y) + sw1 * v.y;
-        q.z = sz + (v.z - u.z) + sw1 * v.z;
-        d2 = sq3(q.x, q.y, q.z);
-        T wa;
-        if (dy.robust == AMM_ROBUST_WELSCH) {
-            const T inv = T(1) / (T(2) * (T)dy.nu_a * (T)dy.nu_a);
-            const T t = d2 * inv;
-            psi = -expm1(-t);
-            wa = exp(-t) * inv;
-        } else if (dy.robust == AMM_ROBUST_L2) {
-            psi = d2;
-            wa = T(1);
-        } else {
-            // truncated quadratic: weight 1 inside 3 nu_a, constant outside
-            const T tau2 = T(9) * (T)dy.nu_a * (T)dy.nu_a;
-            const bool in = d2 < tau2;
-            psi = in ? d2 : tau2;
-            wa = in ? T(1) : T(0);
-        }
-        q.w = wa;
-        a.qw[dst][i] = q;
-        a.rho[dst][i] = (int)pi.tgt_off + bpos;
-        a.d2[dst][i] = d2;
+        T vx, vy, vz, sx, sy, sz, sw1;
+        warp_point<T, V>(a, X, i, v, vx, vy, vz, sx, sy, sz, sw1);
         V vh;
         vh.x = vx;
         vh.y = vy;
         vh.z = vz;
         vh.w = 0;
-        if (dy.has_prev) {
-            const V o = a.vhat[cur][i];
-            disp = sqrt(sq3(vx - o.x, vy - o.y, vz - o.z));
+        const int prev = dy.has_prev ? a.rho[dy.cur][i] - (int)pi.tgt_off : -1;
+        int bpos;
+        T d2;
+        const bool done = oct_search<T, V, COUNT>(pi, cells, oct, a.tgt, vx, vy, vz, prev, bpos, d2, &wk, a.nn_budget);
+        if (done) {
+            finish_point<T, V>(a, dy, pi, i, v, vx, vy, vz, sx, sy, sz, sw1, bpos);
+            a.vhat[dst][i] = vh;   // after the displacement has read set cur
+        } else {
+            // the best target so far seeds the wave-wide search, which
+            // finishes the point (v_hat included)
+            far = true;
+            a.far_seed[i] = d2 < nn_inf<T>() ? bpos : -1;
         }
-        a.vhat[dst][i] = vh;
     }
-    const T tot = block_sum<T, kPointTile>(psi, sh);
-    const T mx = block_max<T, kPointTile>(disp, sh);
-    if (threadIdx.x == 0) {
-        a.pt_part[tile] = (double)tot;
-        a.pt_max[tile] = (double)mx;
+    // deferred points, appended wave by wave (the order does not matter:
+    // each is finished on its own)
+    const unsigned long long fm = __ballot(far);
+    if (fm) {
+        const int lane = (int)(threadIdx.x & 63);
+        int base = 0;
+        if (lane == __ffsll((long long)fm) - 1) base = atomicAdd(a.far_count, (int)__popcll(fm));
+        base = __shfl(base, __ffsll((long long)fm) - 1);
+        const int slot = base + (int)__popcll(fm & ((1ull << lane) - 1ull));
+        if (far && slot < a.Ntot) a.far_list[slot] = make_int2(i, p);
     }
     if constexpr (COUNT) {
         const long long nb = block_sum<long long, kPointTile>(wk.boxes, shc);
@@ -138,6 +172,286 @@ __global__ void __launch_bounds__(kPointTile) k_eval_points(EvalArgs<T> a) {
             c[2] += np;
             c[3] += nc;
         }
+    }
+}
+
+// ---------------------------------------------------------------- deferred closest points
+
+constexpr int kFarWaves = 4;       // waves per block of k_eval_far
+constexpr int kFarGroup = 16;      // lanes per deferred point
+constexpr int kFarPts = 64 / kFarGroup;   // points per wave
+constexpr int kFarCap = 128;       // cells per frontier level (per point)
+constexpr int kFarRuns = 8 * kFarGroup;   // leaf runs per scan round (one cell per lane, 8 children)
+
+__device__ __forceinline__ uint32_t compact3(uint32_t x) {
+    x &= 0x09249249u;
+    x = (x ^ (x >> 2)) & 0x030c30c3u;
+    x = (x ^ (x >> 4)) & 0x0300f00fu;
+    x = (x ^ (x >> 8)) & 0xff0000ffu;
+    x = (x ^ (x >> 16)) & 0x000003ffu;
+    return x;
+}
+
+// orders one wave's shared-memory accesses across its lanes (the waves of
+// a k_eval_far block work on different points and do not meet)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// exclusive prefix sum over a group of kFarGroup lanes, and the group's total
+__device__ __forceinline__ int group_excl_scan(int v, int gl, int& total) {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kFarGroup; o <<= 1) {
+        const int y = __shfl_up(x, o, kFarGroup);
+        if (gl >= o) x += y;
+    }
+    total = __shfl(x, kFarGroup - 1, kFarGroup);
+    return x - v;
+}
+
+// The points whose search ran past the step budget, kFarGroup lanes per
+// point (kFarPts points per wave): the same exact search as oct_search (same
+// bounds, same distance shape, ties to the lowest user index), but
+// breadth-first, the group's lanes working on the cells of a level together
+// and scanning the leaves' targets together, pruned by the best distance so
+// far (seeded by the budgeted search's best).  A level with more cells than
+// the frontier holds falls back to one lane running oct_search from the
+// best so far.  The point is then finished as in k_eval_points.
+template <typename T, bool COUNT>
+__global__ void __launch_bounds__(64 * kFarWaves) k_eval_far(EvalArgs<T> a) {
+    using V = typename V4Of<T>::type;
+    __shared__ uint32_t fr[kFarWaves * kFarPts][2][kFarCap];
+    __shared__ int2 runs[kFarWaves * kFarPts][kFarRuns];
+    const int lane = (int)threadIdx.x & 63;
+    const int gl = lane & (kFarGroup - 1);
+    const int g = (int)threadIdx.x / kFarGroup;    // group slot in the block
+    const int nfar = (int)min((int64_t)*a.far_count, a.Ntot);
+    const V* src = a.src_override ? (const V*)a.src_override : (const V*)a.src;
+    const int stride = (int)gridDim.x * kFarWaves * kFarPts;
+    for (int h = (int)blockIdx.x * kFarWaves * kFarPts + g; h < nfar; h += stride) {
+        const int2 e = a.far_list[h];
+        const int i = e.x, p = e.y;
+        const PairDyn dy = a.dyn[p];
+        const PairInfo pi = a.info[p];
+        const int* cells = a.grid + pi.grid_off;
+        const V* tg = a.tgt + pi.tgt_off;
+        const V v = src[i];
+        T vx, vy, vz, sx, sy, sz, sw1;
+        warp_point<T, V>(a, a.X[dy.eval_x], i, v, vx, vy, vz, sx, sy, sz, sw1);
+        long long n_box = 0, n_pts = 0, n_cells = 0;
+        // the seed: the budgeted search's best
+        const int seed = a.far_seed[i];
+        T bd = nn_inf<T>();
+        int bid = INT_MAX, bpos = -1;
+        if (seed >= 0) {
+            const V u = tg[seed];
+            bd = sq3(u.x - vx, u.y - vy, u.z - vz);
+            bid = (int)u.w;
+            bpos = seed;
+        }
+        const int G = pi.grid_bits;
+        const T pad = (T)pi.gpad;
+        const T ax = ((T)pi.glo[0] - pad) - vx, bx = vx - ((T)pi.glo[0] + pad);
+        const T ay = ((T)pi.glo[1] - pad) - vy, by = vy - ((T)pi.glo[1] + pad);
+        const T az = ((T)pi.glo[2] - pad) - vz, bz = vz - ((T)pi.glo[2] + pad);
+        // start cell: the deepest holding the seed's box (as oct_search)
+        int l0 = 0;
+        uint32_t m0 = 0;
+        if (bd < nn_inf<T>()) {
+            const T r = sqrt(bd) * T(1.00001) + pad;
+            int lz = G - 1;
+            uint32_t lo3[3];
+            const T qv[3] = {vx, vy, vz};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T gl0 = (T)pi.glo[c], gs = (T)pi.gscale[c];
+                T lo = (qv[c] - r - gl0) * gs, hi = (qv[c] + r - gl0) * gs;
+                lo = fmin(fmax(lo, T(0)), T(1023));
+                hi = fmin(fmax(hi, T(0)), T(1023));
+                lo3[c] = (uint32_t)floor(lo);
+                const uint32_t x = lo3[c] ^ (uint32_t)floor(hi);
+                const int common = x == 0 ? 10 : __builtin_clz(x) - 22;
+                lz = common < lz ? common : lz;
+            }
+            l0 = lz < 0 ? 0 : lz;
+            for (int b = l0 - 1; b >= 0; --b)
+                m0 = (m0 << 3) | ((((lo3[0] >> (10 - l0)) >> b) & 1u) << 2) |
+                     ((((lo3[1] >> (10 - l0)) >> b) & 1u) << 1) | (((lo3[2] >> (10 - l0)) >> b) & 1u);
+        }
+        if (gl == 0) fr[g][0][0] = m0;
+        wave_sync();
+        int n = 1, cur = 0;
+        bool overflow = false;
+        for (int l = l0; l < G && n > 0 && !overflow; ++l) {
+            const T sxl = ldexp((T)pi.cs[0], -(l + 1)), syl = ldexp((T)pi.cs[1], -(l + 1)),
+                    szl = ldexp((T)pi.cs[2], -(l + 1));
+            const int64_t toff = oct_level_off(l + 1);
+            const bool leaves = l == G - 1;
+            int nn = 0;
+            for (int base = 0; base < n && !overflow; base += kFarGroup) {
+                const int k = base + gl;
+                uint32_t keep = 0, m = 0;
+                int st[9];
+                if (k < n) {
+                    m = fr[g][cur][k];
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) st[q] = cells[toff + 8 * (int64_t)m + q];
+                    const T jx = T(2 * compact3(m >> 2)), jy = T(2 * compact3(m >> 1)), jz = T(2 * compact3(m));
+                    const T dx0 = oct_axis(ax, bx, sxl, jx), dx1 = oct_axis(ax, bx, sxl, jx + T(1));
+                    const T dy0 = oct_axis(ay, by, syl, jy), dy1 = oct_axis(ay, by, syl, jy + T(1));
+                    const T dz0 = oct_axis(az, bz, szl, jz), dz1 = oct_axis(az, bz, szl, jz + T(1));
+                    const T z0 = dz0 * dz0, z1 = dz1 * dz1;
+                    const T y00 = (T)fma(dy0, dy0, z0), y01 = (T)fma(dy0, dy0, z1), y10 = (T)fma(dy1, dy1, z0),
+                            y11 = (T)fma(dy1, dy1, z1);
+                    const T cb[8] = {(T)fma(dx0, dx0, y00), (T)fma(dx0, dx0, y01), (T)fma(dx0, dx0, y10),
+                                     (T)fma(dx0, dx0, y11), (T)fma(dx1, dx1, y00), (T)fma(dx1, dx1, y01),
+                                     (T)fma(dx1, dx1, y10), (T)fma(dx1, dx1, y11)};
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        keep |= (st[c + 1] > st[c] && cb[c] <= bd ? 1u : 0u) << c;
+                        if constexpr (COUNT) n_box += st[c + 1] > st[c] ? 1 : 0;
+                    }
+                    if constexpr (COUNT) n_cells += 1;
+                }
+                int tot = 0;
+                const int off = group_excl_scan((int)__popc(keep), gl, tot);
+                if (!leaves) {
+                    if (nn + tot > kFarCap) {
+                        overflow = true;   // uniform over the group
+                        break;
+                    }
+                    int o = nn + off;
+                    for (uint32_t km = keep; km; km &= km - 1) fr[g][cur ^ 1][o++] = 8 * m + (uint32_t)__builtin_ctz(km);
+                    nn += tot;
+                } else {
+                    // the kept leaves' runs, then their targets across the group
+                    int o = off;
+                    for (uint32_t km = keep; km; km &= km - 1) {
+                        const int c = __builtin_ctz(km);
+                        int s0 = st[0], s1 = st[1];
+#pragma unroll
+                        for (int q = 1; q < 8; ++q)
+                            if (c == q) {
+                                s0 = st[q];
+                                s1 = st[q + 1];
+                            }
+                        runs[g][o++] = make_int2(s0, s1);
+                    }
+                    wave_sync();
+                    // each lane scans whole runs, four targets per round (the
+                    // loads issued together; indices past a run repeat its
+                    // last target, whose second visit changes nothing)
+                    T ld = nn_inf<T>();
+                    int lid = INT_MAX, lpos = -1;
+                    for (int r = gl; r < tot; r += kFarGroup) {
+                        const int s0 = runs[g][r].x, s1 = runs[g][r].y;
+                        if constexpr (COUNT) n_pts += s1 - s0;
+                        for (int t = s0; t < s1; t += 4) {
+                            const int t1 = min(t + 1, s1 - 1), t2 = min(t + 2, s1 - 1), t3 = min(t + 3, s1 - 1);
+                            const V u0 = tg[t], u1 = tg[t1], u2 = tg[t2], u3 = tg[t3];
+                            const T d0 = sq3(u0.x - vx, u0.y - vy, u0.z - vz);
+                            const T d1 = sq3(u1.x - vx, u1.y - vy, u1.z - vz);
+                            const T d2 = sq3(u2.x - vx, u2.y - vy, u2.z - vz);
+                            const T d3 = sq3(u3.x - vx, u3.y - vy, u3.z - vz);
+                            const int i0 = (int)u0.w, i1 = (int)u1.w, i2 = (int)u2.w, i3 = (int)u3.w;
+                            if (d0 < ld || (d0 == ld && i0 < lid)) {
+                                ld = d0;
+                                lid = i0;
+                                lpos = t;
+                            }
+                            if (d1 < ld || (d1 == ld && i1 < lid)) {
+                                ld = d1;
+                                lid = i1;
+                                lpos = t1;
+                            }
+                            if (d2 < ld || (d2 == ld && i2 < lid)) {
+                                ld = d2;
+                                lid = i2;
+                                lpos = t2;
+                            }
+                            if (d3 < ld || (d3 == ld && i3 < lid)) {
+                                ld = d3;
+                                lid = i3;
+                                lpos = t3;
+                            }
+                        }
+                    }
+                    // group minimum of (distance, user index)
+#pragma unroll
+                    for (int o2 = kFarGroup / 2; o2 > 0; o2 >>= 1) {
+                        const T od = __shfl_xor(ld, o2, kFarGroup);
+                        const int oid = __shfl_xor(lid, o2, kFarGroup), opos = __shfl_xor(lpos, o2, kFarGroup);
+                        if (od < ld || (od == ld && oid < lid)) {
+                            ld = od;
+                            lid = oid;
+                            lpos = opos;
+                        }
+                    }
+                    if (ld < bd || (ld == bd && lid < bid)) {
+                        bd = ld;
+                        bid = lid;
+                        bpos = lpos;
+                    }
+                    wave_sync();
+                }
+            }
+            wave_sync();
+            n = nn;
+            cur ^= 1;
+        }
+        if (overflow) {
+            // one lane finishes the search from the best so far
+            int fp = bpos;
+            T fd = bd;
+            if (gl == 0) oct_search<T, V, false>(pi, cells, cells, a.tgt, vx, vy, vz, bpos, fp, fd);
+            bpos = __shfl(fp, 0, kFarGroup);
+        }
+        if (bpos < 0) bpos = 0;   // a non-finite query matches nothing
+        if (gl == 0) {
+            finish_point<T, V>(a, dy, pi, i, v, vx, vy, vz, sx, sy, sz, sw1, bpos);
+            V vh;
+            vh.x = vx;
+            vh.y = vy;
+            vh.z = vz;
+            vh.w = 0;
+            a.vhat[dy.eval_dst][i] = vh;   // after the displacement has read set cur
+        }
+        if constexpr (COUNT) {
+            // the group's work into tile 0's counters (totals over tiles are reported)
+            for (int o2 = kFarGroup / 2; o2 > 0; o2 >>= 1) {
+                n_box += __shfl_xor(n_box, o2, kFarGroup);
+                n_pts += __shfl_xor(n_pts, o2, kFarGroup);
+                n_cells += __shfl_xor(n_cells, o2, kFarGroup);
+            }
+            if (gl == 0) {
+                atomicAdd((unsigned long long*)&a.nn_work[1], (unsigned long long)n_box);
+                atomicAdd((unsigned long long*)&a.nn_work[2], (unsigned long long)n_pts);
+                atomicAdd((unsigned long long*)&a.nn_work[3], (unsigned long long)n_cells);
+            }
+        }
+    }
+}
+
+// Tile sums of the points' energy terms and displacements (the same tree as
+// a fused per-tile sum), after every point is finished; resets the count of
+// deferred points for the next evaluation.
+template <typename T>
+__global__ void __launch_bounds__(kPointTile) k_eval_sums(EvalArgs<T> a) {
+    __shared__ T sh[kPointTile];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.far_count = 0;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int4 td = a.pt_tiles[tile];
+    if (!(a.dyn[td.x].flags & PF_EVAL)) return;        // uniform over the block
+    const int i = td.y + (int)threadIdx.x;
+    const T psi = i < td.z ? a.pt_psi[i] : T(0);
+    const T disp = i < td.z ? a.pt_disp[i] : T(0);
+    const T tot = block_sum<T, kPointTile>(psi, sh);
+    const T mx = block_max<T, kPointTile>(disp, sh);
+    if (threadIdx.x == 0) {
+        a.pt_part[tile] = (double)tot;
+        a.pt_max[tile] = (double)mx;
     }
 }
 
@@ -1118,10 +1432,18 @@ template <typename T>
 void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_tiles, const FinalArgs& f,
                  int P, hipStream_t s, KernelTimer* tm) {
     if (n_pt_tiles) {
-        if (a.nn_work)
+        // budgeted searches, then the deferred points one wave each, then the
+        // tile sums (the deferred points' count is only known on the device:
+        // a fixed grid strides over it)
+        const int far_blocks = (int)std::min<int64_t>(1024, (a.Ntot + kFarWaves * kFarPts - 1) / (kFarWaves * kFarPts));
+        if (a.nn_work) {
             launch_one(tm, "eval_points", k_eval_points<T, true>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
-        else
+            launch_one(tm, "eval_far", k_eval_far<T, true>, dim3(far_blocks), dim3(64 * kFarWaves), s, a);
+        } else {
             launch_one(tm, "eval_points", k_eval_points<T, false>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
+            launch_one(tm, "eval_far", k_eval_far<T, false>, dim3(far_blocks), dim3(64 * kFarWaves), s, a);
+        }
+        launch_one(tm, "eval_sums", k_eval_sums<T>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
     }
     if (n_eg_tiles) {
         launch_one(tm, "eval_edges", k_eval_edges<T>, dim3(n_eg_tiles), dim3(kEdgeTile), s, a);

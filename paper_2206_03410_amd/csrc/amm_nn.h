@@ -76,10 +76,15 @@ __host__ __device__ inline T oct_axis(T a, T b, T s, T j) {
 // children still to visit are one byte per level of a 64-bit mask (bit j =
 // child j ^ octant), the query's octant three bits per level, so the
 // search keeps no stack.
+//
+// budget > 0 bounds the search's steps (expansions and visits): past it the
+// search stops and returns false, best_pos / best_d2 holding the best
+// target found so far (an upper bound to hand to another search).
 template <typename T, typename V, bool COUNT = false>
-__host__ __device__ inline void oct_search(const PairInfo& pi, const int* __restrict__ cells,
+__host__ __device__ inline bool oct_search(const PairInfo& pi, const int* __restrict__ cells,
                                            const int* __restrict__ near, const V* __restrict__ tgt, T qx, T qy,
-                                           T qz, int prev, int& best_pos, T& best_d2, NnWork* work = nullptr) {
+                                           T qz, int prev, int& best_pos, T& best_d2, NnWork* work = nullptr,
+                                           int budget = 0) {
     const V* tg = tgt + pi.tgt_off;
     T bd = nn_inf<T>();
     int bid = INT_MAX, bpos = -1;
@@ -144,7 +149,13 @@ __host__ __device__ inline void oct_search(const PairInfo& pi, const int* __rest
     // run starts of the current level G - 1 cell's children
     int ls0 = 0, ls1 = 0, ls2 = 0, ls3 = 0, ls4 = 0, ls5 = 0, ls6 = 0, ls7 = 0, ls8 = 0;
     bool expand = true;
+    bool finished = true;
+    int steps = 0;
     while (true) {
+        if (budget > 0 && ++steps > budget) {
+            finished = false;
+            break;
+        }
         if (expand) {
             // (two branches, so each read keeps its own address space)
             const int64_t o = oct_level_off(l + 1) + 8 * (int64_t)m;
@@ -276,6 +287,7 @@ __host__ __device__ inline void oct_search(const PairInfo& pi, const int* __rest
     // a non-finite query matches nothing; keep the index in range
     best_pos = bpos < 0 ? 0 : bpos;
     best_d2 = bd;
+    return finished;
 }
 
 }  // namespace amm
