@@ -427,8 +427,8 @@ amm_status read_pair(amm_handle* h, const amm_problem& p, HostPair& hp) {
     return AMM_OK;
 }
 
-template <typename P>
-amm_status up(amm_handle* h, P* dst, const std::vector<P>& src) {
+template <typename P, typename A>
+amm_status up(amm_handle* h, P* dst, const std::vector<P, A>& src) {
     if (src.empty()) return AMM_OK;
     HIPC(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(P), hipMemcpyHostToDevice, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
@@ -436,8 +436,8 @@ amm_status up(amm_handle* h, P* dst, const std::vector<P>& src) {
 }
 
 // uploads a float64 host array and writes its float32 and float64 copies
-template <typename PF, typename PD>
-amm_status up_real(amm_handle* h, PF* dst_f, PD* dst_d, const std::vector<double>& src) {
+template <typename PF, typename PD, typename A>
+amm_status up_real(amm_handle* h, PF* dst_f, PD* dst_d, const std::vector<double, A>& src) {
     if (src.empty()) return AMM_OK;
     HIPC(hipMemcpyAsync(h->v.staging, src.data(), src.size() * 8, hipMemcpyHostToDevice, h->stream));
     launch_cast_static<float>(h->v.staging, reinterpret_cast<float*>(dst_f), (int64_t)src.size(), h->stream);
@@ -1676,7 +1676,9 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     TRY(up(h, reinterpret_cast<int32_t*>(v.eg_tiles), Lr.eg_tiles));
     TRY(up_real(h, v.sf.src, v.sd.src, Lr.src4));
     TRY(up_real(h, v.sf.iw, v.sd.iw, Lr.iw));
-    TRY(up_real(h, v.sf.iw_pt, v.sd.iw_pt, Lr.iw_pt));
+    // the point-major copy of the weights, formed on the device
+    launch_weights_point_major<float>(v.sf.iw, Lr.k, Lr.Ntot, v.sf.iw_pt, h->stream);
+    launch_weights_point_major<double>(v.sd.iw, Lr.k, Lr.Ntot, v.sd.iw_pt, h->stream);
     TRY(up_real(h, v.sf.nodes, v.sd.nodes, Lr.nodes4));
     TRY(up_real(h, v.sf.tgt, v.sd.tgt, Lr.tgt4));
     TRY(up_real(h, v.sf.adj_r, v.sd.adj_r, Lr.adj_r));

@@ -3,6 +3,8 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -89,19 +91,41 @@ struct HostPair {
     double lbar = 0.0;
 };
 
+// std::vector whose resize leaves new elements uninitialised: large host
+// arrays that the set-up writes in full, from parallel threads (which then
+// also take the pages' first-touch cost, instead of one zero-filling thread)
+template <typename T>
+struct UninitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <typename U>
+    UninitAlloc(const UninitAlloc<U>&) {}
+    template <typename U, typename... A>
+    void construct(U* p, A&&... a) {
+        if constexpr (sizeof...(A) == 0)
+            ::new ((void*)p) U;
+        else
+            ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <typename T>
+using hvec = std::vector<T, UninitAlloc<T>>;
+
 // Everything set_problems uploads (built on the host).
 struct Layout {
     int P = 0, k = 0;
     int64_t Ntot = 0, Mtot = 0, ntot = 0, nadj = 0, nnzb = 0, pj_entries = 0;
     int n_pt_tiles = 0, n_nd_tiles = 0, n_eg_tiles = 0;
     std::vector<PairInfo> info;
-    std::vector<double> src4;        // [Ntot][4] internal order
-    std::vector<int32_t> src_user;   // internal point -> user index (concatenated)
-    std::vector<int32_t> src_internal;  // user index -> internal point
-    std::vector<int32_t> iidx;       // [k][Ntot] internal node ids
-    std::vector<double> iw;          // [k][Ntot]
-    std::vector<double> iw_pt;       // [Ntot][kMaxK] the same weights point-major, zero padded
-    std::vector<uint8_t> ipad;       // [k][Ntot] 1 = unused slot (host only)
+    hvec<double> src4;        // [Ntot][4] internal order
+    hvec<int32_t> src_user;   // internal point -> user index (concatenated)
+    hvec<int32_t> src_internal;  // user index -> internal point
+    hvec<int32_t> iidx;       // [k][Ntot] internal node ids
+    hvec<double> iw;          // [k][Ntot]
+    hvec<uint8_t> ipad;       // [k][Ntot] 1 = unused slot (host only)
     std::vector<double> nodes4;      // [ntot][4]
     std::vector<int32_t> node_user;  // internal node -> user node (concatenated)
     std::vector<int32_t> node_internal;
@@ -113,8 +137,8 @@ struct Layout {
     // per point-list entry of row j: byte b = position, within row j's column
     // list, of the point's influence b
     std::vector<uint64_t> pj_pos;
-    std::vector<double> tgt4;        // [Mtot][4] sorted; w = user index within the pair
-    std::vector<int32_t> tgt_user;   // sorted position -> user index within the pair
+    hvec<double> tgt4;        // [Mtot][4] sorted; w = user index within the pair
+    hvec<int32_t> tgt_user;   // sorted position -> user index within the pair
     std::vector<int32_t> pt_tiles, nd_tiles, eg_tiles;   // [tiles][4] = pair, start, end, 0
     int max_row_cols = 0;
     // coarse level: per aggregate (pair, first node, end node, pair-local id),

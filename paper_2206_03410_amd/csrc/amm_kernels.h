@@ -309,5 +309,9 @@ template <typename T>
 void launch_select_mid(const T* d2, const PairInfo* info, const int4* pt_tiles, int n_pt_tiles, int P, T* out,
                        void* work, hipStream_t s);
 size_t select_mid_work_bytes(int P);
+// out[i][a] = iw[a][i] for a < k, 0 for k <= a < kMaxK (the influence
+// weights point-major, for the assembly)
+template <typename T>
+void launch_weights_point_major(const T* iw, int k, int64_t N, T* out, hipStream_t s);
 
 }  // namespace amm

@@ -1514,6 +1514,20 @@ void launch_nn_export(const int* rho, const T* d2, const int* src_user, const in
                        tgt_user, rho_u, d2_u, Ntot);
 }
 template <typename T>
+__global__ void __launch_bounds__(256) k_weights_point_major(const T* __restrict__ iw, int k, int64_t N,
+                                                            T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int a = 0; a < kMaxK; ++a) out[(size_t)kMaxK * i + a] = a < k ? iw[(size_t)a * N + i] : T(0);
+}
+
+template <typename T>
+void launch_weights_point_major(const T* iw, int k, int64_t N, T* out, hipStream_t s) {
+    if (N) hipLaunchKernelGGL(k_weights_point_major<T>, dim3(blocks_for(N, 256)), dim3(256), 0, s, iw, k, N, out);
+}
+
+template <typename T>
 void launch_cast_static(const double* in, T* out, int64_t n, hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_cast_static<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
@@ -1575,6 +1589,7 @@ size_t select_mid_work_bytes(int P) { return (sizeof(SelState) + 256 * sizeof(un
     template void launch_aa<T>(const AaArgs<T>&, const AaSolveArgs&, int, hipStream_t, KernelTimer*);          \
     template void launch_grad<T>(const GradArgs<T>&, int, int64_t, hipStream_t);                              \
     template void launch_cast_static<T>(const double*, T*, int64_t, hipStream_t);                              \
+    template void launch_weights_point_major<T>(const T*, int, int64_t, T*, hipStream_t);                      \
     template void launch_x_import<T, float>(const float*, T*, const int*, int64_t, hipStream_t);              \
     template void launch_x_import<T, double>(const double*, T*, const int*, int64_t, hipStream_t);            \
     template void launch_x_export<T, float>(const T*, float*, const int*, int64_t, hipStream_t);              \

@@ -48,14 +48,29 @@ uint32_t morton(const double* p, const Box& b) {
     return (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
 }
 
+// Indices 0..n-1 ordered by their 30-bit codes, equal codes in index order
+// (a stable least-significant-digit radix sort, three 10-bit passes: the
+// order std::stable_sort gives).
+std::vector<int32_t> code_order(const std::vector<uint32_t>& code) {
+    const int64_t n = (int64_t)code.size();
+    std::vector<int32_t> a(n), b(n);
+    std::iota(a.begin(), a.end(), 0);
+    std::vector<int64_t> cnt(1025);
+    for (int pass = 0; pass < 3; ++pass) {
+        const int sh = 10 * pass;
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int64_t i = 0; i < n; ++i) ++cnt[((code[a[i]] >> sh) & 1023u) + 1];
+        for (int d = 0; d < 1024; ++d) cnt[d + 1] += cnt[d];
+        for (int64_t i = 0; i < n; ++i) b[cnt[(code[a[i]] >> sh) & 1023u]++] = a[i];
+        a.swap(b);
+    }
+    return a;
+}
+
 std::vector<int32_t> morton_order(const double* pts, int64_t cnt, const Box& b) {
     std::vector<uint32_t> code(cnt);
     for (int64_t i = 0; i < cnt; ++i) code[i] = morton(pts + 3 * i, b);
-    std::vector<int32_t> ord(cnt);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int32_t a, int32_t c) { return code[a] < code[c]; });
-    return ord;
+    return code_order(code);
 }
 
 Box bounds(const double* pts, int64_t cnt) {
@@ -275,6 +290,7 @@ amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, in
     for (int64_t q = 0; q < hp.N; ++q) {
         int64_t u = sord[q];
         for (int c = 0; c < 3; ++c) L.src4[4 * (so + q) + c] = hp.src[3 * u + c];
+        L.src4[4 * (so + q) + 3] = 0.0;
         L.src_user[so + q] = (int32_t)(so + u);
         L.src_internal[so + u] = (int32_t)(so + q);
         // an unused slot points at the point's first influencing node with
@@ -289,7 +305,6 @@ amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, in
             L.iidx[(size_t)a * L.Ntot + so + q] = (int32_t)(no + n_inv[j]);
             L.ipad[(size_t)a * L.Ntot + so + q] = pad ? 1 : 0;
             L.iw[(size_t)a * L.Ntot + so + q] = w;
-            L.iw_pt[(size_t)(so + q) * kMaxK + a] = w;
         }
     }
     for (int64_t q = 0; q < hp.n; ++q) {
@@ -345,73 +360,81 @@ amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, in
         L.adj_rev[e] = (int32_t)(L.adj_ptr[b] + (it - beg));
     }
 
-    // block pattern of K: co-influence pairs, edges, diagonal
-    std::vector<std::vector<int32_t>> cols(hp.n);
-    for (int64_t q = 0; q < hp.n; ++q) cols[q].push_back((int32_t)(no + q));
+    // points influenced by each node (entries (point << 3) | slot, in point
+    // order), by counting
+    part.pj_rowptr.assign(hp.n + 1, 0);
     for (int64_t q = 0; q < hp.N; ++q)
-        for (int a = 0; a < k; ++a) {
-            if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
-            int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
-            for (int b = 0; b < k; ++b)
-                if (!L.ipad[(size_t)b * L.Ntot + so + q]) cols[ja].push_back(L.iidx[(size_t)b * L.Ntot + so + q]);
-        }
-    for (int64_t q = 0; q < hp.n; ++q)
-        for (int32_t b : nb[q]) cols[q].push_back((int32_t)(no + b));
+        for (int a = 0; a < k; ++a)
+            if (!L.ipad[(size_t)a * L.Ntot + so + q]) ++part.pj_rowptr[L.iidx[(size_t)a * L.Ntot + so + q] - no + 1];
+    for (int64_t q = 0; q < hp.n; ++q) part.pj_rowptr[q + 1] += part.pj_rowptr[q];
+    part.pj_ent.resize(part.pj_rowptr[hp.n]);
+    {
+        std::vector<int32_t> fill(part.pj_rowptr.begin(), part.pj_rowptr.end() - 1);
+        for (int64_t q = 0; q < hp.N; ++q)
+            for (int a = 0; a < k; ++a) {
+                if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
+                const int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
+                part.pj_ent[fill[ja]++] = (int32_t)(((so + q) << 3) | a);
+            }
+    }
+    // block pattern of K, row by row: the diagonal, the nodes that share an
+    // influenced point with the row's node, and its graph neighbours
+    // (distinct, sorted); then each point entry's k column positions
     part.K_rowptr.assign(hp.n + 1, 0);
     part.K_diag.assign(hp.n, 0);
-    for (int64_t q = 0; q < hp.n; ++q) {
-        auto& c = cols[q];
-        std::sort(c.begin(), c.end());
-        c.erase(std::unique(c.begin(), c.end()), c.end());
-        if ((int)c.size() > kMaxCols) {
-            err = fmt("a node is coupled to %lld others (limit %lld)", (long long)c.size(), kMaxCols);
-            return AMM_ERR_INVALID_ARG;
-        }
-        part.max_row_cols = std::max(part.max_row_cols, (int)c.size());
-        part.K_rowptr[q] = (int32_t)part.K_col.size();
-        for (size_t t = 0; t < c.size(); ++t) {
-            int32_t col = c[t];
-            if (col == no + q) part.K_diag[q] = (int32_t)part.K_col.size();
-            int32_t adj = -1;
-            if (col != no + q) {
-                auto beg = L.adj_nbr.begin() + L.adj_ptr[no + q];
-                auto end = beg + (int64_t)nb[q].size();
-                auto it = std::lower_bound(beg, end, col);
-                if (it != end && *it == col) adj = (int32_t)(it - L.adj_nbr.begin());
+    part.pj_pos.resize(part.pj_ent.size());
+    {
+        std::vector<int32_t> mark(hp.n, -1), posof(hp.n, 0), c;
+        c.reserve(256);
+        for (int64_t q = 0; q < hp.n; ++q) {
+            c.clear();
+            auto add = [&](int32_t col) {
+                if (mark[col - no] != (int32_t)q) {
+                    mark[col - no] = (int32_t)q;
+                    c.push_back(col);
+                }
+            };
+            add((int32_t)(no + q));
+            for (int32_t e = part.pj_rowptr[q]; e < part.pj_rowptr[q + 1]; ++e) {
+                const int64_t i = part.pj_ent[e] >> 3;
+                for (int b = 0; b < k; ++b)
+                    if (!L.ipad[(size_t)b * L.Ntot + i]) add(L.iidx[(size_t)b * L.Ntot + i]);
             }
-            part.K_col.push_back(col);
-            part.K_adj.push_back(adj);
+            for (int32_t b : nb[q]) add((int32_t)(no + b));
+            std::sort(c.begin(), c.end());
+            if ((int)c.size() > kMaxCols) {
+                err = fmt("a node is coupled to %lld others (limit %lld)", (long long)c.size(), kMaxCols);
+                return AMM_ERR_INVALID_ARG;
+            }
+            part.max_row_cols = std::max(part.max_row_cols, (int)c.size());
+            part.K_rowptr[q] = (int32_t)part.K_col.size();
+            for (size_t t = 0; t < c.size(); ++t) {
+                const int32_t col = c[t];
+                posof[col - no] = (int32_t)t;
+                if (col == no + q) part.K_diag[q] = (int32_t)part.K_col.size();
+                int32_t adj = -1;
+                if (col != no + q) {
+                    auto beg = L.adj_nbr.begin() + L.adj_ptr[no + q];
+                    auto end = beg + (int64_t)nb[q].size();
+                    auto it = std::lower_bound(beg, end, col);
+                    if (it != end && *it == col) adj = (int32_t)(it - L.adj_nbr.begin());
+                }
+                part.K_col.push_back(col);
+                part.K_adj.push_back(adj);
+            }
+            for (int32_t e = part.pj_rowptr[q]; e < part.pj_rowptr[q + 1]; ++e) {
+                const int64_t i = part.pj_ent[e] >> 3;
+                uint64_t pos = 0;
+                for (int b = 0; b < k; ++b) {
+                    uint64_t bpos = kPosUnused;
+                    if (!L.ipad[(size_t)b * L.Ntot + i]) bpos = (uint64_t)posof[L.iidx[(size_t)b * L.Ntot + i] - no];
+                    pos |= bpos << (8 * b);
+                }
+                part.pj_pos[e] = pos;
+            }
         }
     }
     part.K_rowptr[hp.n] = (int32_t)part.K_col.size();
-    // points influenced by each node
-    std::vector<std::vector<int32_t>> pj(hp.n);
-    for (int64_t q = 0; q < hp.N; ++q)
-        for (int a = 0; a < k; ++a) {
-            if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
-            int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
-            pj[ja].push_back((int32_t)(((so + q) << 3) | a));
-        }
-    part.pj_rowptr.assign(hp.n + 1, 0);
-    for (int64_t q = 0; q < hp.n; ++q) {
-        part.pj_rowptr[q] = (int32_t)part.pj_ent.size();
-        part.pj_ent.insert(part.pj_ent.end(), pj[q].begin(), pj[q].end());
-        const auto& c = cols[q];
-        for (int32_t ent : pj[q]) {
-            const int64_t i = ent >> 3;
-            uint64_t pos = 0;
-            for (int b = 0; b < k; ++b) {
-                uint64_t bpos = kPosUnused;
-                if (!L.ipad[(size_t)b * L.Ntot + i]) {
-                    const int32_t nid = L.iidx[(size_t)b * L.Ntot + i];
-                    bpos = (uint64_t)(std::lower_bound(c.begin(), c.end(), nid) - c.begin());
-                }
-                pos |= bpos << (8 * b);
-            }
-            part.pj_pos.push_back(pos);
-        }
-    }
-    part.pj_rowptr[hp.n] = (int32_t)part.pj_ent.size();
 
     // targets: Morton order and the octree's run-start tables
     {
@@ -498,13 +521,13 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.ntot = no[L.P];
     L.nadj = ao[L.P];
     const int k = L.k;
-    L.src4.assign(4 * L.Ntot, 0.0);
+    // (written in full by the pairs' threads)
+    L.src4.resize(4 * L.Ntot);
     L.src_user.resize(L.Ntot);
     L.src_internal.resize(L.Ntot);
     L.iidx.resize((size_t)k * L.Ntot);
     L.iw.resize((size_t)k * L.Ntot);
-    L.ipad.assign((size_t)k * L.Ntot, 0);
-    L.iw_pt.assign((size_t)kMaxK * L.Ntot, 0.0);
+    L.ipad.resize((size_t)k * L.Ntot);
     L.nodes4.assign(4 * L.ntot, 0.0);
     L.node_user.resize(L.ntot);
     L.node_internal.resize(L.ntot);
@@ -518,7 +541,7 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.K_ptr.assign(L.ntot + 1, 0);
     L.K_diag.resize(L.ntot);
     L.pj_ptr.assign(L.ntot + 1, 0);
-    L.tgt4.assign(4 * L.Mtot, 0.0);
+    L.tgt4.resize(4 * L.Mtot);
     L.tgt_user.resize(L.Mtot);
 
     // pairs in parallel (each writes its own ranges), then merged in order
@@ -663,9 +686,7 @@ void target_layout(const double* tgt, int64_t M, int leaf, TargetLayout& out, in
     const Box bb = bounds(tgt, M);
     std::vector<uint32_t> code(M);
     for (int64_t i = 0; i < M; ++i) code[i] = morton(tgt + 3 * i, bb);
-    std::vector<int32_t> tord(M);
-    std::iota(tord.begin(), tord.end(), 0);
-    std::stable_sort(tord.begin(), tord.end(), [&](int32_t a, int32_t c) { return code[a] < code[c]; });
+    const std::vector<int32_t> tord = code_order(code);
     out.tgt4.assign(4 * (size_t)M, 0.0);
     out.tgt_user.resize(M);
     for (int64_t q = 0; q < M; ++q) {
