@@ -451,14 +451,15 @@ amm_status amm_energy_grad(amm_handle* h, amm_dtype dtype, const void* X, const 
  * (code under HIP graph capture, serving loops, harnesses that forbid
  * hipMalloc): the same evaluation kernels, the same results (bitwise), but
  * every per-call buffer (imported transforms and source positions, the
- * warped points, closest points, residuals and weights, tile partial sums,
- * the pair's parameters and outputs) lives in a file-scope device array of
+ * warped points, closest points, residuals and weights, the deferred
+ * searches' list, per-point terms, tile partial sums, the pair's parameters
+ * and outputs) lives in a file-scope device array of
  * 64 MiB that each GPU the library runs on holds until the process ends;
  * the handle's workspace still holds the problem set up by
  * amm_set_problem.  Nothing is allocated: no hipMalloc, no host or pinned
  * allocation.  The search starts cold (no warm start from earlier calls).
- * Problems whose per-call buffers exceed 64 MiB (about 5e5 source points in
- * float64, 1e6 in float32) are refused with AMM_ERR_INVALID_ARG.  Every call
+ * Problems whose per-call buffers exceed 64 MiB (about 4.9e5 source points
+ * in float64, 8.8e5 in float32) are refused with AMM_ERR_INVALID_ARG.  Every call
  * on one GPU uses that GPU's single array: calls that overlap in time on one
  * GPU (two host threads, or two streams) race and must be serialized by the
  * caller.  Arguments and errors as amm_energy. */

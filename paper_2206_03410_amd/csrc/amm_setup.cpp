@@ -548,8 +548,15 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     std::vector<PairPart> parts(L.P);
     std::vector<amm_status> sts(L.P, AMM_OK);
     std::vector<std::string> errs(L.P);
-    parallel_for(L.P, host_threads(), [&](int64_t p) {
-        sts[p] = build_pair(pairs[p], (int)p, k, leaf, so[p], to[p], no[p], ao[p], L, parts[p], errs[p]);
+    // the largest pairs first, so that no large one is left for the end
+    std::vector<int32_t> by_size(L.P);
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int32_t a, int32_t b) {
+        return pairs[a].N + pairs[a].M > pairs[b].N + pairs[b].M;
+    });
+    parallel_for(L.P, host_threads(), [&](int64_t r) {
+        const int p = by_size[r];
+        sts[p] = build_pair(pairs[p], p, k, leaf, so[p], to[p], no[p], ao[p], L, parts[p], errs[p]);
     });
     for (int p = 0; p < L.P; ++p)
         if (sts[p] != AMM_OK) {
