@@ -669,30 +669,106 @@ __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
 // ---------------------------------------------------------------- assembly
 
 
+// The 16 x 16 x 4 matrix-core product used by the assembly, D = A B + C with
+// A 16 x 4 and B 4 x 16: lane l supplies A(l % 16, l / 16) and B(l / 16,
+// l % 16), and its accumulator value r is D(row(l, r), l % 16).
+template <typename T>
+struct AsmMfma;
+template <>
+struct AsmMfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float x, float y, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+    // row stride of the staged columns, 4 words past a multiple of 64: the
+    // 16-byte reads of 16 lanes from 16 rows hit distinct banks
+    static constexpr int kStride = 68;
+};
+template <>
+struct AsmMfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double x, double y, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * r + (l >> 4); }
+    static constexpr int kStride = 66;
+};
+
+constexpr int kAsmGroup = 32;   // column blocks per pass of the assembly (two 16-column tiles)
+// an unused influence slot (column byte 255) lands outside every pass's columns
+static_assert(kMaxCols <= (int)kPosUnused + 1 - kAsmGroup, "column bytes of unused slots");
+// a padding row of the staged weights per influence slot takes the slots
+// outside the pass
+constexpr int kAsmWRows = kAsmGroup + kMaxK;
+
+// Eight consecutive staged values of one row, as 16-byte reads.
+__device__ __forceinline__ void asm_load8(const float* r, float (&v)[8]) {
+    const float4 x = reinterpret_cast<const float4*>(r)[0], y = reinterpret_cast<const float4*>(r)[1];
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+}
+__device__ __forceinline__ void asm_load8(const double* r, double (&v)[8]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const double2 x = reinterpret_cast<const double2*>(r)[u];
+        v[2 * u] = x.x;
+        v[2 * u + 1] = x.y;
+    }
+}
+
 // Row j of K and B (Eq. 21) and of the residual r = B - K X^k, one wave per
 // node.  Alignment blocks K_jl = sum_i w_a,i w_ij w_il [v_i - p_j; 1]
 // [v_i - p_l; 1]^T are formed as moments anchored at p_j,
-// M_jl = sum c_i w_il x x^T with x = [v_i - p_j; 1], then shifted:
-// K_jl = M_jl S^T, S = [[I, p_j - p_l], [0, 1]].  Lanes first own points
-// (stage moments in LDS), then own columns of the row (gather in a fixed
-// order).  Edge blocks follow Eqs. (7), (14) and the matrix H; the rotation
-// term adds beta J^T J.  The residual is assembled from the residuals at
-// X^k themselves -- r = -sum w_a F^T e - alpha sum w_r H^T D + beta J(Z - X^k)
-// -- instead of as the difference B - K X^k of two large rounded
-// quantities, so its relative accuracy does not degrade as the iteration
-// converges; B = r + K X^k.  The inverse of the 4x4 diagonal block
-// (block-Jacobi preconditioner) is written alongside.
+// M_jl = sum c_i w_il x x^T with x = [v_i - p_j; 1] and c_i = w_a,i w_ij,
+// then shifted: K_jl = M_jl S^T, S = [[I, p_j - p_l], [0, 1]].  The ten
+// distinct moments of all column blocks of the row are one product
+// W^T Mom over the row's points: W (points x columns) holds w_il in the
+// column of each influence l of point i and zero elsewhere, Mom (points x
+// 10) holds c_i times the products of the entries of x.  Chunks of 64
+// points are staged in LDS (a point per lane) and multiplied on the matrix
+// cores, four points per instruction, in a fixed order; rows coupled to
+// more than 32 nodes take one pass per 32 columns.  Lanes then own the
+// columns of the row and shift, add the edge and rotation blocks
+// (Eqs. (7), (14), the matrix H and beta J^T J) and write them.  The
+// residual is assembled from the residuals at X^k themselves --
+// r = -sum w_a F^T e - alpha sum w_r H^T D + beta J(Z - X^k) -- instead of
+// as the difference B - K X^k of two large rounded quantities, so its
+// relative accuracy does not degrade as the iteration converges;
+// B = r + K X^k.  The inverse of the 4x4 diagonal block (block-Jacobi
+// preconditioner) is written alongside.
+template <typename T>
+struct AsmPoint {
+    using V = typename V4Of<T>::type;
+    V v, q, w0, w1;   // point, (e, w_a), influence weights 0-3 and 4-7
+};
+
+template <typename T>
+__device__ __forceinline__ void asm_gather(const AsmArgs<T>& a, const typename V4Of<T>::type* qw, int ent,
+                                           AsmPoint<T>& g) {
+    using V = typename V4Of<T>::type;
+    if (ent < 0) return;
+    const int i = ent >> 3;
+    g.v = a.src[i];
+    g.q = qw[i];
+    const V* wp = reinterpret_cast<const V*>(a.iw_pt + (size_t)kMaxK * i);
+    g.w0 = wp[0];
+    g.w1 = wp[1];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     using V = typename V4Of<T>::type;
-    __shared__ int scol[kMaxCols];            // the row's column node ids (sorted)
-    __shared__ T sacc[kMaxCols + 1][10];      // moment sums per column block (+ a sink row)
-    __shared__ T smom[64][10];
-    __shared__ int spos[64][kMaxK];           // column position of each influence of a staged point
-    __shared__ T swgt[64][kMaxK];
+    using M = AsmMfma<T>;
+    using acc_t = typename M::acc_t;
+    __shared__ int scol[kMaxCols];                                   // the row's column node ids (sorted)
+    __shared__ __align__(16) T swT[kAsmWRows][M::kStride];           // W^T of the staged points
+    __shared__ __align__(16) T smomT[10][M::kStride];                // Mom^T of the staged points
+    __shared__ T sacc[kAsmGroup][10];                                // this pass's moment sums per column block
     // neighbouring nodes share most of their points: keep them on one XCD
     const int j = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
+    const int lr = lane & 15, lq = lane >> 4;
     const int p = a.node_pair[j];
     const PairDyn dy = a.dyn[p];
     if (!(dy.flags & PF_SOLVE)) return;
@@ -703,168 +779,269 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     const int kb = a.K_ptr[j], ke = a.K_ptr[j + 1];
     const int ncol = ke - kb;
     const int k = a.k;
-    for (int c = lane; c < ncol; c += 64) {
-        scol[c] = a.K_col[kb + c];
-#pragma unroll
-        for (int m = 0; m < 10; ++m) sacc[c][m] = 0;
-    }
-    // lane l scatters moment m = l % 10 of influence b = l / 10 (60 lanes for k = 6)
-    const int my_b = lane / 10, my_m = lane % 10;
-    T racc[12];
-#pragma unroll
-    for (int m = 0; m < 12; ++m) racc[m] = 0;
-    const int e0 = a.pj_ptr[j], e1 = a.pj_ptr[j + 1];
-    __syncthreads();
-    for (int base = e0; base < e1; base += 64) {
-        const int e = base + lane;
-        if (e < e1) {
-            const int ent = a.pj_ent[e];
-            const uint64_t pos = a.pj_pos[e];
-            const int i = ent >> 3, s = ent & 7;
-            const V v = a.src[i];
-            const V q = qw[i];
-            const V* wp = reinterpret_cast<const V*>(a.iw_pt + (size_t)kMaxK * i);
-            const V w0 = wp[0], w1 = wp[1];
-            const T wv[kMaxK] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-            T ws = wv[0];
-#pragma unroll
-            for (int b = 1; b < kMaxK; ++b) ws = s == b ? wv[b] : ws;
-            const T c = q.w * ws;
-            const T dx = v.x - pj.x, dyy = v.y - pj.y, dz = v.z - pj.z;
-            smom[lane][0] = c * dx * dx;
-            smom[lane][1] = c * dx * dyy;
-            smom[lane][2] = c * dx * dz;
-            smom[lane][3] = c * dx;
-            smom[lane][4] = c * dyy * dyy;
-            smom[lane][5] = c * dyy * dz;
-            smom[lane][6] = c * dyy;
-            smom[lane][7] = c * dz * dz;
-            smom[lane][8] = c * dz;
-            smom[lane][9] = c;
-            // alignment part of -r: c [v_i - p_j; 1] e_i^T
-            const T ax = c * dx, ay = c * dyy, az = c * dz;
-            racc[0] += ax * q.x;
-            racc[1] += ax * q.y;
-            racc[2] += ax * q.z;
-            racc[3] += ay * q.x;
-            racc[4] += ay * q.y;
-            racc[5] += ay * q.z;
-            racc[6] += az * q.x;
-            racc[7] += az * q.y;
-            racc[8] += az * q.z;
-            racc[9] += c * q.x;
-            racc[10] += c * q.y;
-            racc[11] += c * q.z;
-#pragma unroll
-            for (int b = 0; b < kMaxK; ++b) {
-                // an unused slot (weight 0) adds into the sink row, never read
-                const unsigned cb = (unsigned)(pos >> (8 * b)) & 255u;
-                spos[lane][b] = cb == kPosUnused ? kMaxCols : (int)cb;
-                swgt[lane][b] = wv[b];
-            }
-        }
-        __syncthreads();
-        // scatter, one staged point after the other: for a fixed point the k
-        // influences land in k distinct column blocks, so the 10k lanes write
-        // distinct cells; the order over points is fixed.  A wave's LDS
-        // operations complete in issue order, so the read of a cell in step
-        // t + 1 sees the write of step t.
-        const int cnt = min(64, e1 - base);
-        if (my_b < k) {
-            for (int t = 0; t < cnt; ++t) {
-                T* cell = &sacc[spos[t][my_b]][my_m];
-                *cell += swgt[t][my_b] * smom[t][my_m];
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int m = 0; m < 12; ++m) racc[m] = wave_sum(racc[m]);
-
     const T alpha = (T)dy.alpha, beta = (T)dy.beta;
     const int ab = a.adj_ptr[j], ae = a.adj_ptr[j + 1];
     const T* Xk = a.X[cur];
+    const int e0 = a.pj_ptr[j], e1 = a.pj_ptr[j + 1];
+    // the first two chunks' entries and the first chunk's points are loaded
+    // before anything else, and every chunk loads the next one's while it is
+    // multiplied
+    int entA = -1, entB = -1;
+    uint64_t posA = ~0ull, posB = ~0ull;   // ~0: every slot unused
+    if (e0 + lane < e1) {
+        entA = a.pj_ent[e0 + lane];
+        posA = a.pj_pos[e0 + lane];
+    }
+    if (e0 + 64 + lane < e1) {
+        entB = a.pj_ent[e0 + 64 + lane];
+        posB = a.pj_pos[e0 + 64 + lane];
+    }
+    AsmPoint<T> gA = {};
+    asm_gather(a, qw, entA, gA);
+    for (int c = lane; c < ncol; c += 64) scol[c] = a.K_col[kb + c];
+#pragma unroll
+    for (int c = 0; c < kAsmWRows; ++c) swT[c][lane] = 0;   // each lane keeps its own point's column zero
+
+    // Edge terms of the row, a lane per edge of node j, summed over the wave:
+    // the diagonal block's sum over edges (j, l2) of the entry l2->j's weight
+    // times [p_l2 - p_j; 1][p_l2 - p_j; 1]^T plus the entry j->l2's weight in
+    // its last element (ed, upper triangle row-major), and the edges' part of
+    // -r (re): -f1 [p_l2 - p_j; 1] D_l2j^T, and f2 D_jl2^T in the last row.
+    T ed[10], re[12];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) ed[m] = 0;
+#pragma unroll
+    for (int m = 0; m < 12; ++m) re[m] = 0;
+    {
+        const V* Dr = a.Dres[cur];
+        for (int e = ab + lane; e < ae; e += 64) {
+            const int l2 = a.adj_nbr[e], rev = a.adj_rev[e];
+            const T rr = a.adj_r[e];
+            const T we = wr[e], wv = wr[rev];
+            const V q2 = a.nodes[l2];
+            const V D1 = Dr[rev], D2 = Dr[e];
+            const T om_e = alpha * we * rr * rr;
+            const T om_r = alpha * wv * rr * rr;
+            const T x[4] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z, T(1)};
+            int m = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c2 = r; c2 < 4; ++c2) ed[m++] += om_r * x[r] * x[c2];
+            ed[9] += om_e;
+            const T f1 = alpha * wv * rr;
+            const T f2 = alpha * we * rr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                re[3 * r + 0] -= f1 * x[r] * D1.x;
+                re[3 * r + 1] -= f1 * x[r] * D1.y;
+                re[3 * r + 2] -= f1 * x[r] * D1.z;
+            }
+            re[9] += f2 * D2.x;
+            re[10] += f2 * D2.y;
+            re[11] += f2 * D2.z;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 10; ++m) ed[m] = wave_sum(ed[m]);
+#pragma unroll
+    for (int m = 0; m < 12; ++m) re[m] = wave_sum(re[m]);
+
+    T racc[12];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) racc[m] = 0;
     T kx[12];
 #pragma unroll
     for (int m = 0; m < 12; ++m) kx[m] = 0;
-    for (int cp = lane; cp < ncol; cp += 64) {
-        const int pos = kb + cp;
-        const int l = scol[cp];
-        const V pl = a.nodes[l];
-        const T* m = sacc[cp];
-        const T S[4][4] = {{m[0], m[1], m[2], m[3]},
-                           {m[1], m[4], m[5], m[6]},
-                           {m[2], m[5], m[7], m[8]},
-                           {m[3], m[6], m[8], m[9]}};
-        const T del[3] = {pj.x - pl.x, pj.y - pl.y, pj.z - pl.z};
-        T Kb[4][4];
-        for (int r = 0; r < 4; ++r) {
-            for (int s = 0; s < 3; ++s) Kb[r][s] = S[r][s] + S[r][3] * del[s];
-            Kb[r][3] = S[r][3];
-        }
-        const int adj = a.K_adj[pos];
-        if (adj >= 0) {
-            // D_jl (entry j->l, transform of l) and D_lj (entry l->j, transform of j)
-            const int rev = a.adj_rev[adj];
-            const T rr = a.adj_r[adj];
-            const T om_e = alpha * wr[adj] * rr * rr;
-            const T om_r = alpha * wr[rev] * rr * rr;
-            const T ext[4] = {-del[0], -del[1], -del[2], T(1)};   // [p_l - p_j; 1]
-            const T exj[4] = {del[0], del[1], del[2], T(1)};      // [p_j - p_l; 1]
-            for (int r = 0; r < 4; ++r) Kb[r][3] -= om_r * ext[r];
-            for (int s = 0; s < 4; ++s) Kb[3][s] -= om_e * exj[s];
-        }
-        if (l == j) {
-            for (int e = ab; e < ae; ++e) {
-                const int l2 = a.adj_nbr[e], rev = a.adj_rev[e];
-                const T rr = a.adj_r[e];
-                const T om_e = alpha * wr[e] * rr * rr;
-                const T om_r = alpha * wr[rev] * rr * rr;
-                const V q2 = a.nodes[l2];
-                const T ext[4] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z, T(1)};
-                for (int r = 0; r < 4; ++r)
-                    for (int s = 0; s < 4; ++s) Kb[r][s] += om_r * ext[r] * ext[s];
-                Kb[3][3] += om_e;
+    __syncthreads();
+    for (int g0 = 0; g0 < ncol; g0 += kAsmGroup) {
+        // this lane's column block of the pass: its node, edge weights and X
+        const int cp = g0 + lane;
+        const bool own = lane < kAsmGroup && cp < ncol;
+        int l = 0;
+        V pl = {};
+        T om_e = 0, om_r = 0;
+        bool edge = false;
+        T Xl[12];
+#pragma unroll
+        for (int m = 0; m < 12; ++m) Xl[m] = 0;
+        if (own) {
+            l = scol[cp];
+            pl = a.nodes[l];
+            const int adj = a.K_adj[kb + cp];
+            if (adj >= 0) {
+                // D_jl (entry j->l, transform of l) and D_lj (entry l->j, transform of j)
+                const int rev = a.adj_rev[adj];
+                const T rr = a.adj_r[adj];
+                om_e = alpha * wr[adj] * rr * rr;
+                om_r = alpha * wr[rev] * rr * rr;
+                edge = true;
             }
-            for (int s = 0; s < 3; ++s) Kb[s][s] += beta;
-            spd_inverse4<T>(Kb, a.Dinv + 16 * (size_t)j);
+            const T* xp = Xk + 12 * (size_t)l;
+#pragma unroll
+            for (int m = 0; m < 12; ++m) Xl[m] = xp[m];
         }
-        T* Ko = a.Kval + 16 * (size_t)pos;
-        for (int r = 0; r < 4; ++r)
-            for (int s = 0; s < 4; ++s) Ko[4 * r + s] = Kb[r][s];
-        // (K X^k)_j contribution of this column block
-        const T* Xl = Xk + 12 * (size_t)l;
-        for (int r = 0; r < 4; ++r)
-            for (int c2 = 0; c2 < 3; ++c2)
-                kx[3 * r + c2] += Kb[r][0] * Xl[c2] + Kb[r][1] * Xl[3 + c2] + Kb[r][2] * Xl[6 + c2] +
-                                  Kb[r][3] * Xl[9 + c2];
+        if (g0 > 0) {
+            // a later pass reads the row's entries again from the start
+            entA = entB = -1;
+            posA = posB = ~0ull;
+            if (e0 + lane < e1) {
+                entA = a.pj_ent[e0 + lane];
+                posA = a.pj_pos[e0 + lane];
+            }
+            if (e0 + 64 + lane < e1) {
+                entB = a.pj_ent[e0 + 64 + lane];
+                posB = a.pj_pos[e0 + 64 + lane];
+            }
+            asm_gather(a, qw, entA, gA);
+        }
+        acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        for (int base = e0; base < e1; base += 64) {
+            // this chunk's entry and point; then the next chunk's loads
+            const int ent = entA;
+            const uint64_t pos = posA;
+            const AsmPoint<T> g = gA;
+            asm_gather(a, qw, entB, gA);
+            entA = entB;
+            posA = posB;
+            entB = -1;
+            posB = ~0ull;
+            if (base + 128 + lane < e1) {
+                entB = a.pj_ent[base + 128 + lane];
+                posB = a.pj_pos[base + 128 + lane];
+            }
+            T mom[10];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) mom[m] = 0;
+            const T wv[kMaxK] = {g.w0.x, g.w0.y, g.w0.z, g.w0.w, g.w1.x, g.w1.y, g.w1.z, g.w1.w};
+            if (ent >= 0) {
+                const int s = ent & 7;
+                T ws = wv[0];
+#pragma unroll
+                for (int b = 1; b < kMaxK; ++b) ws = s == b ? wv[b] : ws;
+                const T c = g.q.w * ws;
+                const T dx = g.v.x - pj.x, dyy = g.v.y - pj.y, dz = g.v.z - pj.z;
+                mom[0] = c * dx * dx;
+                mom[1] = c * dx * dyy;
+                mom[2] = c * dx * dz;
+                mom[3] = c * dx;
+                mom[4] = c * dyy * dyy;
+                mom[5] = c * dyy * dz;
+                mom[6] = c * dyy;
+                mom[7] = c * dz * dz;
+                mom[8] = c * dz;
+                mom[9] = c;
+                if (g0 == 0) {
+                    // alignment part of -r: c [v_i - p_j; 1] e_i^T
+                    const T ax = c * dx, ay = c * dyy, az = c * dz;
+                    racc[0] += ax * g.q.x;
+                    racc[1] += ax * g.q.y;
+                    racc[2] += ax * g.q.z;
+                    racc[3] += ay * g.q.x;
+                    racc[4] += ay * g.q.y;
+                    racc[5] += ay * g.q.z;
+                    racc[6] += az * g.q.x;
+                    racc[7] += az * g.q.y;
+                    racc[8] += az * g.q.z;
+                    racc[9] += c * g.q.x;
+                    racc[10] += c * g.q.y;
+                    racc[11] += c * g.q.z;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 10; ++m) smomT[m][lane] = mom[m];
+            // an influence's column within this pass; slots outside it (unused
+            // ones have byte 255) write the padding rows, which are never read
+            unsigned col[kMaxK];
+#pragma unroll
+            for (int b = 0; b < kMaxK; ++b) {
+                const unsigned cb = ((unsigned)(pos >> (8 * b)) & 255u) - (unsigned)g0;
+                col[b] = b < k && cb < (unsigned)kAsmGroup ? cb : (unsigned)(kAsmGroup + b);
+                swT[col[b]][lane] = wv[b];
+            }
+            __syncthreads();
+            // step u multiplies the staged points u, 16 + u, 32 + u and 48 + u
+            // (lane group lq supplies point 16 lq + u), in a fixed order; points
+            // past the row's end are zero
+            const T* mrow = smomT[lr < 10 ? lr : 0] + 16 * lq;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                T bv[8], a0[8];
+                asm_load8(mrow + 8 * h, bv);
+                asm_load8(swT[lr] + 16 * lq + 8 * h, a0);
+                // both tiles are multiplied whatever the row's width (a
+                // second tile past the row's columns multiplies zero rows):
+                // the products run unconditionally, with no branch around
+                // the matrix-core accumulators, which this compiler has been
+                // seen to get wrong
+                T a1[8];
+                asm_load8(swT[16 + lr] + 16 * lq + 8 * h, a1);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const T b = lr < 10 ? bv[u] : T(0);
+                    acc0 = M::mma(a0[u], b, acc0);
+                    acc1 = M::mma(a1[u], b, acc1);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < kMaxK; ++b) swT[col[b]][lane] = 0;
+        }
+        if (lr < 10) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sacc[M::row(lane, r)][lr] = acc0[r];
+                sacc[16 + M::row(lane, r)][lr] = acc1[r];
+            }
+        }
+        __syncthreads();
+        if (own) {
+            const T* m = sacc[lane];
+            const T S[4][4] = {{m[0], m[1], m[2], m[3]},
+                               {m[1], m[4], m[5], m[6]},
+                               {m[2], m[5], m[7], m[8]},
+                               {m[3], m[6], m[8], m[9]}};
+            const T del[3] = {pj.x - pl.x, pj.y - pl.y, pj.z - pl.z};
+            T Kb[4][4];
+            for (int r = 0; r < 4; ++r) {
+                for (int s = 0; s < 3; ++s) Kb[r][s] = S[r][s] + S[r][3] * del[s];
+                Kb[r][3] = S[r][3];
+            }
+            if (edge) {
+                const T ext[4] = {-del[0], -del[1], -del[2], T(1)};   // [p_l - p_j; 1]
+                const T exj[4] = {del[0], del[1], del[2], T(1)};      // [p_j - p_l; 1]
+                for (int r = 0; r < 4; ++r) Kb[r][3] -= om_r * ext[r];
+                for (int s = 0; s < 4; ++s) Kb[3][s] -= om_e * exj[s];
+            }
+            if (l == j) {
+                int m2 = 0;
+                for (int r = 0; r < 4; ++r)
+                    for (int c2 = r; c2 < 4; ++c2) {
+                        Kb[r][c2] += ed[m2];
+                        if (c2 != r) Kb[c2][r] += ed[m2];
+                        ++m2;
+                    }
+                for (int s = 0; s < 3; ++s) Kb[s][s] += beta;
+                spd_inverse4<T>(Kb, a.Dinv + 16 * (size_t)j);
+            }
+            T* Ko = a.Kval + 16 * (size_t)(kb + cp);
+            for (int r = 0; r < 4; ++r)
+                for (int s = 0; s < 4; ++s) Ko[4 * r + s] = Kb[r][s];
+            // (K X^k)_j contribution of this column block
+            for (int r = 0; r < 4; ++r)
+                for (int c2 = 0; c2 < 3; ++c2)
+                    kx[3 * r + c2] += Kb[r][0] * Xl[c2] + Kb[r][1] * Xl[3 + c2] + Kb[r][2] * Xl[6 + c2] +
+                                      Kb[r][3] * Xl[9 + c2];
+        }
+        __syncthreads();   // sacc is rewritten by the next pass
     }
+#pragma unroll
+    for (int m = 0; m < 12; ++m) racc[m] = wave_sum(racc[m]);
 #pragma unroll
     for (int m = 0; m < 12; ++m) kx[m] = wave_sum(kx[m]);
     if (lane == 0) {
         T rj[12];
-        for (int m2 = 0; m2 < 12; ++m2) rj[m2] = -racc[m2];
-        const typename V4Of<T>::type* Dr = a.Dres[cur];
-        for (int e = ab; e < ae; ++e) {
-            const int l2 = a.adj_nbr[e], rev = a.adj_rev[e];
-            const T rr = a.adj_r[e];
-            const V q2 = a.nodes[l2];
-            const T ext[4] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z, T(1)};   // [p_l - p_j; 1]
-            // D_lj (entry rev): H block of j is r [p_l - p_j; 1]
-            const V D1 = Dr[rev];
-            const T f1 = alpha * wr[rev] * rr;
-            for (int r = 0; r < 4; ++r) {
-                rj[3 * r + 0] -= f1 * ext[r] * D1.x;
-                rj[3 * r + 1] -= f1 * ext[r] * D1.y;
-                rj[3 * r + 2] -= f1 * ext[r] * D1.z;
-            }
-            // D_jl (entry e): H block of j is -r e4
-            const V D2 = Dr[e];
-            const T f2 = alpha * wr[e] * rr;
-            rj[9] += f2 * D2.x;
-            rj[10] += f2 * D2.y;
-            rj[11] += f2 * D2.z;
-        }
+        for (int m2 = 0; m2 < 12; ++m2) rj[m2] = re[m2] - racc[m2];
         // rotation term: beta J (Z - X^k), row r of block j = beta (proj(A_j) - A_j)^T
         const T* Rd = a.R[cur] + 9 * (size_t)j;
         for (int r = 0; r < 3; ++r)
