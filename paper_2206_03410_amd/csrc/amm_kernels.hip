@@ -698,9 +698,13 @@ struct AsmMfma<double> {
 constexpr int kAsmGroup = 32;   // column blocks per pass of the assembly (two 16-column tiles)
 // an unused influence slot (column byte 255) lands outside every pass's columns
 static_assert(kMaxCols <= (int)kPosUnused + 1 - kAsmGroup, "column bytes of unused slots");
-// a padding row of the staged weights per influence slot takes the slots
-// outside the pass
-constexpr int kAsmWRows = kAsmGroup + kMaxK;
+// the staged rows hold 64 points and at least two padding columns (where
+// influence slots outside the pass write), and the pass's sums per column
+// block (kAsmGroup x 10) fit in the first five moment rows
+static_assert(AsmMfma<float>::kStride >= 66 && AsmMfma<double>::kStride >= 66, "padding columns");
+static_assert(5 * AsmMfma<float>::kStride >= 10 * kAsmGroup && 5 * AsmMfma<double>::kStride >= 10 * kAsmGroup,
+              "per-pass sums in the moment rows");
+static_assert(kMaxK <= kAsmGroup, "padding rows of the influence slots");
 
 // Eight consecutive staged values of one row, as 16-byte reads.
 __device__ __forceinline__ void asm_load8(const float* r, float (&v)[8]) {
@@ -715,6 +719,26 @@ __device__ __forceinline__ void asm_load8(const double* r, double (&v)[8]) {
         v[2 * u] = x.x;
         v[2 * u + 1] = x.y;
     }
+}
+
+// A staged point: loaded for the chunk after the one being multiplied.
+template <typename T>
+struct AsmPoint {
+    using V = typename V4Of<T>::type;
+    V v, q, w0, w1;   // point, (e, w_a), influence weights 0-3 and 4-7
+};
+
+template <typename T>
+__device__ __forceinline__ void asm_gather(const AsmArgs<T>& a, const typename V4Of<T>::type* qw, int ent,
+                                           AsmPoint<T>& g) {
+    using V = typename V4Of<T>::type;
+    if (ent < 0) return;
+    const int i = ent >> 3;
+    g.v = a.src[i];
+    g.q = qw[i];
+    const V* wp = reinterpret_cast<const V*>(a.iw_pt + (size_t)kMaxK * i);
+    g.w0 = wp[0];
+    g.w1 = wp[1];
 }
 
 // Row j of K and B (Eq. 21) and of the residual r = B - K X^k, one wave per
@@ -738,33 +762,17 @@ __device__ __forceinline__ void asm_load8(const double* r, double (&v)[8]) {
 // B = r + K X^k.  The inverse of the 4x4 diagonal block (block-Jacobi
 // preconditioner) is written alongside.
 template <typename T>
-struct AsmPoint {
-    using V = typename V4Of<T>::type;
-    V v, q, w0, w1;   // point, (e, w_a), influence weights 0-3 and 4-7
-};
-
-template <typename T>
-__device__ __forceinline__ void asm_gather(const AsmArgs<T>& a, const typename V4Of<T>::type* qw, int ent,
-                                           AsmPoint<T>& g) {
-    using V = typename V4Of<T>::type;
-    if (ent < 0) return;
-    const int i = ent >> 3;
-    g.v = a.src[i];
-    g.q = qw[i];
-    const V* wp = reinterpret_cast<const V*>(a.iw_pt + (size_t)kMaxK * i);
-    g.w0 = wp[0];
-    g.w1 = wp[1];
-}
-
-template <typename T>
 __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     using V = typename V4Of<T>::type;
     using M = AsmMfma<T>;
     using acc_t = typename M::acc_t;
-    __shared__ int scol[kMaxCols];                                   // the row's column node ids (sorted)
-    __shared__ __align__(16) T swT[kAsmWRows][M::kStride];           // W^T of the staged points
-    __shared__ __align__(16) T smomT[10][M::kStride];                // Mom^T of the staged points
-    __shared__ T sacc[kAsmGroup][10];                                // this pass's moment sums per column block
+    __shared__ int scol[kMaxCols];                             // the row's column node ids (sorted)
+    __shared__ __align__(16) T swT[kAsmGroup][M::kStride];     // W^T of the staged points
+    // Mom^T of the staged points in rows 0-9, zero rows 10-15 (the product's
+    // unused moment columns); after a pass's products rows 0-4 hold its sums
+    // per column block (sacc)
+    __shared__ __align__(16) T smomT[16][M::kStride];
+    T* const sacc = &smomT[0][0];
     // neighbouring nodes share most of their points: keep them on one XCD
     const int j = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
@@ -775,6 +783,7 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     const int cur = dy.cur;
     const V* qw = a.qw[cur];
     const T* wr = a.wr[cur];
+    const V* Dr = a.Dres[cur];
     const V pj = a.nodes[j];
     const int kb = a.K_ptr[j], ke = a.K_ptr[j + 1];
     const int ncol = ke - kb;
@@ -783,9 +792,8 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     const int ab = a.adj_ptr[j], ae = a.adj_ptr[j + 1];
     const T* Xk = a.X[cur];
     const int e0 = a.pj_ptr[j], e1 = a.pj_ptr[j + 1];
-    // the first two chunks' entries and the first chunk's points are loaded
-    // before anything else, and every chunk loads the next one's while it is
-    // multiplied
+    // the first two chunks' entries and the first chunk's points, then every
+    // chunk loads the next one's while it is multiplied
     int entA = -1, entB = -1;
     uint64_t posA = ~0ull, posB = ~0ull;   // ~0: every slot unused
     if (e0 + lane < e1) {
@@ -800,47 +808,44 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
     asm_gather(a, qw, entA, gA);
     for (int c = lane; c < ncol; c += 64) scol[c] = a.K_col[kb + c];
 #pragma unroll
-    for (int c = 0; c < kAsmWRows; ++c) swT[c][lane] = 0;   // each lane keeps its own point's column zero
+    for (int c = 0; c < kAsmGroup; ++c) swT[c][lane] = 0;   // each lane keeps its own point's column zero
+#pragma unroll
+    for (int m = 10; m < 16; ++m) smomT[m][lane] = 0;
 
-    // Edge terms of the row, a lane per edge of node j, summed over the wave:
-    // the diagonal block's sum over edges (j, l2) of the entry l2->j's weight
-    // times [p_l2 - p_j; 1][p_l2 - p_j; 1]^T plus the entry j->l2's weight in
-    // its last element (ed, upper triangle row-major), and the edges' part of
-    // -r (re): -f1 [p_l2 - p_j; 1] D_l2j^T, and f2 D_jl2^T in the last row.
+    // Edge terms of the row, summed over the wave: the diagonal block's sum
+    // over edges (j, l2) of the entry l2->j's weight times [p_l2 - p_j; 1]
+    // [p_l2 - p_j; 1]^T plus the entry j->l2's weight in its last element
+    // (ed, upper triangle row-major), and the edges' part of -r (re):
+    // -f1 [p_l2 - p_j; 1] D_l2j^T, and f2 D_jl2^T in the last row.
     T ed[10], re[12];
+    auto add_edge = [&](T rr, T we, T wv, V q2, V D1, V D2) {
+        const T om_e = alpha * we * rr * rr;
+        const T om_r = alpha * wv * rr * rr;
+        const T x[4] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z, T(1)};
+        int m = 0;
 #pragma unroll
-    for (int m = 0; m < 10; ++m) ed[m] = 0;
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int m = 0; m < 12; ++m) re[m] = 0;
-    {
-        const V* Dr = a.Dres[cur];
-        for (int e = ab + lane; e < ae; e += 64) {
-            const int l2 = a.adj_nbr[e], rev = a.adj_rev[e];
-            const T rr = a.adj_r[e];
-            const T we = wr[e], wv = wr[rev];
-            const V q2 = a.nodes[l2];
-            const V D1 = Dr[rev], D2 = Dr[e];
-            const T om_e = alpha * we * rr * rr;
-            const T om_r = alpha * wv * rr * rr;
-            const T x[4] = {q2.x - pj.x, q2.y - pj.y, q2.z - pj.z, T(1)};
-            int m = 0;
+            for (int c2 = r; c2 < 4; ++c2) ed[m++] += om_r * x[r] * x[c2];
+        ed[9] += om_e;
+        const T f1 = alpha * wv * rr;
+        const T f2 = alpha * we * rr;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c2 = r; c2 < 4; ++c2) ed[m++] += om_r * x[r] * x[c2];
-            ed[9] += om_e;
-            const T f1 = alpha * wv * rr;
-            const T f2 = alpha * we * rr;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                re[3 * r + 0] -= f1 * x[r] * D1.x;
-                re[3 * r + 1] -= f1 * x[r] * D1.y;
-                re[3 * r + 2] -= f1 * x[r] * D1.z;
-            }
-            re[9] += f2 * D2.x;
-            re[10] += f2 * D2.y;
-            re[11] += f2 * D2.z;
+        for (int r = 0; r < 4; ++r) {
+            re[3 * r + 0] -= f1 * x[r] * D1.x;
+            re[3 * r + 1] -= f1 * x[r] * D1.y;
+            re[3 * r + 2] -= f1 * x[r] * D1.z;
         }
+        re[9] += f2 * D2.x;
+        re[10] += f2 * D2.y;
+        re[11] += f2 * D2.z;
+    };
+
+    for (int m = 0; m < 10; ++m) ed[m] = 0;
+    for (int m = 0; m < 12; ++m) re[m] = 0;
+    for (int e = ab + lane; e < ae; e += 64) {
+        const int rev = a.adj_rev[e];
+        add_edge(a.adj_r[e], wr[e], wr[rev], a.nodes[a.adj_nbr[e]], Dr[rev], Dr[e]);
     }
 #pragma unroll
     for (int m = 0; m < 10; ++m) ed[m] = wave_sum(ed[m]);
@@ -951,52 +956,53 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
 #pragma unroll
             for (int m = 0; m < 10; ++m) smomT[m][lane] = mom[m];
             // an influence's column within this pass; slots outside it (unused
-            // ones have byte 255) write the padding rows, which are never read
-            unsigned col[kMaxK];
+            // ones have byte 255) write a padding column past the 64 points,
+            // which is never read
+            T* const swf = &swT[0][0];
+            int woff[kMaxK];
 #pragma unroll
             for (int b = 0; b < kMaxK; ++b) {
                 const unsigned cb = ((unsigned)(pos >> (8 * b)) & 255u) - (unsigned)g0;
-                col[b] = b < k && cb < (unsigned)kAsmGroup ? cb : (unsigned)(kAsmGroup + b);
-                swT[col[b]][lane] = wv[b];
+                const bool in = b < k && cb < (unsigned)kAsmGroup;
+                woff[b] = in ? (int)cb * M::kStride + lane : b * M::kStride + 64 + (lane & 1);
+                swf[woff[b]] = wv[b];
             }
             __syncthreads();
             // step u multiplies the staged points u, 16 + u, 32 + u and 48 + u
             // (lane group lq supplies point 16 lq + u), in a fixed order; points
-            // past the row's end are zero
-            const T* mrow = smomT[lr < 10 ? lr : 0] + 16 * lq;
+            // past the row's end are zero.  Both tiles are multiplied whatever
+            // the row's width (a second tile past the row's columns multiplies
+            // zero rows): the products run unconditionally, with no branch
+            // around the matrix-core accumulators, which this compiler has
+            // been seen to get wrong.
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                T bv[8], a0[8];
-                asm_load8(mrow + 8 * h, bv);
+                T bv[8], a0[8], a1[8];
+                asm_load8(smomT[lr] + 16 * lq + 8 * h, bv);
                 asm_load8(swT[lr] + 16 * lq + 8 * h, a0);
-                // both tiles are multiplied whatever the row's width (a
-                // second tile past the row's columns multiplies zero rows):
-                // the products run unconditionally, with no branch around
-                // the matrix-core accumulators, which this compiler has been
-                // seen to get wrong
-                T a1[8];
                 asm_load8(swT[16 + lr] + 16 * lq + 8 * h, a1);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const T b = lr < 10 ? bv[u] : T(0);
-                    acc0 = M::mma(a0[u], b, acc0);
-                    acc1 = M::mma(a1[u], b, acc1);
+                    acc0 = M::mma(a0[u], bv[u], acc0);
+                    acc1 = M::mma(a1[u], bv[u], acc1);
                 }
             }
             __syncthreads();
 #pragma unroll
-            for (int b = 0; b < kMaxK; ++b) swT[col[b]][lane] = 0;
+            for (int b = 0; b < kMaxK; ++b) swf[woff[b]] = 0;
         }
+        // the pass's moment sums per column block (rows 0-9 of smomT are free:
+        // the last products' reads completed before the barrier above)
         if (lr < 10) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                sacc[M::row(lane, r)][lr] = acc0[r];
-                sacc[16 + M::row(lane, r)][lr] = acc1[r];
+                sacc[10 * M::row(lane, r) + lr] = acc0[r];
+                sacc[10 * (16 + M::row(lane, r)) + lr] = acc1[r];
             }
         }
         __syncthreads();
         if (own) {
-            const T* m = sacc[lane];
+            const T* m = sacc + 10 * lane;
             const T S[4][4] = {{m[0], m[1], m[2], m[3]},
                                {m[1], m[4], m[5], m[6]},
                                {m[2], m[5], m[7], m[8]},
@@ -1033,7 +1039,7 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
                     kx[3 * r + c2] += Kb[r][0] * Xl[c2] + Kb[r][1] * Xl[3 + c2] + Kb[r][2] * Xl[6 + c2] +
                                       Kb[r][3] * Xl[9 + c2];
         }
-        __syncthreads();   // sacc is rewritten by the next pass
+        __syncthreads();   // rows 0-9 of smomT are staged again by the next pass
     }
 #pragma unroll
     for (int m = 0; m < 12; ++m) racc[m] = wave_sum(racc[m]);
