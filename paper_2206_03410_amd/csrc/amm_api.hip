@@ -342,22 +342,6 @@ struct amm_handle {
     // three columns had converged (-1 while not)
     long long* prog = nullptr;
     long long* prog_dev = nullptr;
-    // Results the host waits on, written by the kernel that produces them
-    // straight into coherent pinned host memory, each followed by a stamp
-    // (the per-pair energies and, per solver tile, the residual sums of the
-    // refinement): the host polls the stamps instead of copying and waiting
-    // for the stream.  Stamps count up per handle.
-    PairOut* out_live = nullptr;
-    PairOut* out_live_dev = nullptr;
-    long long* out_seq = nullptr;
-    long long* out_seq_dev = nullptr;
-    long long out_want = 0;
-    double* res_live = nullptr;
-    double* res_live_dev = nullptr;
-    long long* res_seq = nullptr;
-    long long* res_seq_dev = nullptr;
-    size_t res_cap = 0;
-    long long seq_ctr = 0;
     double* h_scratch = nullptr;     // pinned, grown on demand (small read-backs)
     hipEvent_t sync_ev = nullptr;    // recorded to wait for the stream by polling
     size_t h_scratch_cap = 0;
@@ -468,22 +452,13 @@ amm_status ensure_host(amm_handle* h, size_t P) {
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);
     if (h->prog) (void)hipHostFree(h->prog);
-    if (h->out_live) (void)hipHostFree(h->out_live);
-    if (h->out_seq) (void)hipHostFree(h->out_seq);
     h->h_out = nullptr;
     h->h_state = nullptr;
     h->prog = nullptr;
-    h->out_live = nullptr;
-    h->out_seq = nullptr;
     HIPC(hipHostMalloc((void**)&h->prog, sizeof(long long) * 2 * P, hipHostMallocMapped | hipHostMallocCoherent));
     HIPC(hipHostGetDevicePointer((void**)&h->prog_dev, h->prog, 0));
     HIPC(hipHostMalloc((void**)&h->h_out, sizeof(PairOut) * P));
     HIPC(hipHostMalloc((void**)&h->h_state, sizeof(CgState) * 2 * P));
-    HIPC(hipHostMalloc((void**)&h->out_live, sizeof(PairOut) * P, hipHostMallocMapped | hipHostMallocCoherent));
-    HIPC(hipHostGetDevicePointer((void**)&h->out_live_dev, h->out_live, 0));
-    HIPC(hipHostMalloc((void**)&h->out_seq, sizeof(long long) * P, hipHostMallocMapped | hipHostMallocCoherent));
-    HIPC(hipHostGetDevicePointer((void**)&h->out_seq_dev, h->out_seq, 0));
-    for (size_t p = 0; p < P; ++p) h->out_seq[p] = -1;
     h->h_cap = P;
     return AMM_OK;
 }
@@ -521,37 +496,9 @@ amm_status sync_spin(amm_handle* h) {
     return AMM_OK;
 }
 
-// Waits until the stamps seq[0..n) all equal `want`.  Polls for up to 2 ms,
-// then waits for the stream (which reports a failed kernel) and checks again.
-amm_status wait_stamps(amm_handle* h, const long long* seq, int n, long long want) {
-    const volatile long long* sv = seq;
-    int i = 0;
-    const auto t0 = std::chrono::steady_clock::now();
-    while (true) {
-        while (i < n && sv[i] == want) ++i;
-        if (i == n) break;
-        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
-            TRY(sync_spin(h));
-            while (i < n && sv[i] == want) ++i;
-            if (i < n) return fail(h, AMM_ERR_HIP, "a kernel's results did not reach host memory");
-            break;
-        }
-    }
-    std::atomic_thread_fence(std::memory_order_acquire);
-    return AMM_OK;
-}
-
-// The per-pair energies of the evaluation just launched (its energy kernel
-// writes them with their stamps into host memory).
 amm_status pull_out(amm_handle* h) {
-    const int P = h->L.P;
-    if (h->out_want > 0) {
-        TRY(wait_stamps(h, h->out_seq, P, h->out_want));
-        std::memcpy(h->h_out, h->out_live, sizeof(PairOut) * P);
-    } else {
-        HIPC(hipMemcpyAsync(h->h_out, h->v.out, sizeof(PairOut) * P, hipMemcpyDeviceToHost, h->stream));
-        TRY(sync_spin(h));
-    }
+    HIPC(hipMemcpyAsync(h->h_out, h->v.out, sizeof(PairOut) * h->L.P, hipMemcpyDeviceToHost, h->stream));
+    TRY(sync_spin(h));
     HIPC(hipGetLastError());
     if (h->timing) h->timer.collect();
     return AMM_OK;
@@ -620,10 +567,6 @@ FinalArgs final_args(amm_handle* h) {
     f.pt_max = h->v.d.pt_max;
     f.eg_part = h->v.d.eg_part;
     f.nd_part = h->v.d.nd_part;
-    f.host_out = h->out_live_dev;
-    f.host_seq = h->out_seq_dev;
-    f.seq = ++h->seq_ctr;
-    h->out_want = h->out_live_dev ? f.seq : 0;
     return f;
 }
 
@@ -863,38 +806,21 @@ amm_status pinned_scratch(amm_handle* h, size_t bytes) {
     return AMM_OK;
 }
 
-// Coherent pinned host buffers for the refinement's tile sums and stamps.
-amm_status residual_live(amm_handle* h, int nt) {
-    if (h->res_cap >= (size_t)nt) return AMM_OK;
-    if (h->res_live) (void)hipHostFree(h->res_live);
-    if (h->res_seq) (void)hipHostFree(h->res_seq);
-    h->res_live = nullptr;
-    h->res_seq = nullptr;
-    h->res_cap = 0;
-    HIPC(hipHostMalloc((void**)&h->res_live, sizeof(double) * 6 * nt, hipHostMallocMapped | hipHostMallocCoherent));
-    HIPC(hipHostGetDevicePointer((void**)&h->res_live_dev, h->res_live, 0));
-    HIPC(hipHostMalloc((void**)&h->res_seq, sizeof(long long) * nt, hipHostMallocMapped | hipHostMallocCoherent));
-    HIPC(hipHostGetDevicePointer((void**)&h->res_seq_dev, h->res_seq, 0));
-    for (int t = 0; t < nt; ++t) h->res_seq[t] = -1;
-    h->res_cap = (size_t)nt;
-    return AMM_OK;
-}
-
 template <typename T>
 amm_status true_residual(amm_handle* h, T* rhs_out, std::vector<double>& rel) {
     const Layout& L = h->L;
     Dyn& d = h->v.d;
     const int nt = L.n_nd_tiles;
     CgArgs<T> a = cg_args<T>(h, nullptr, nullptr, 0);
-    TRY(residual_live(h, nt));
-    const long long want = ++h->seq_ctr;
     launch_residual64<T>(a, nt, reinterpret_cast<const T*>(d.rvec), reinterpret_cast<const T*>(d.B), d.x64, rhs_out,
-                         d.part_rr64, d.part_bb64, h->res_live_dev, h->res_seq_dev, want, h->stream, tmr(h));
-    // the tile sums arrive in pinned host memory with their stamps
-    TRY(wait_stamps(h, h->res_seq, nt, want));
-    HIPC(hipGetLastError());
-    const double* rr = h->res_live;
-    const double* bb = h->res_live + 3 * nt;
+                         d.part_rr64, d.part_bb64, h->stream, tmr(h));
+    // read back into pinned memory (a pageable destination makes the copy
+    // synchronous and staged)
+    TRY(pinned_scratch(h, sizeof(double) * 6 * nt));
+    double* rr = h->h_scratch;
+    double* bb = h->h_scratch + 3 * nt;
+    HIPC(hipMemcpyAsync(rr, d.part_rr64, sizeof(double) * 6 * nt, hipMemcpyDeviceToHost, h->stream));
+    TRY(sync_spin(h));
     rel.assign(L.P, 0.0);
     for (int p = 0; p < L.P; ++p) {
         if (!(h->dyn[p].flags & PF_SOLVE)) continue;
@@ -1552,9 +1478,6 @@ amm_status energy_noalloc_impl(amm_handle* h, const void* X, const void* src, do
     a.pt_psi = s_psi;
     a.pt_disp = s_disp;
     FinalArgs f = final_args(h);
-    f.host_out = nullptr;   // read back below from the static array
-    f.host_seq = nullptr;
-    h->out_want = 0;
     f.dyn = s_dyn;
     f.out = s_out;
     f.pt_part = s_pt_part;
@@ -1648,10 +1571,6 @@ void amm_destroy(amm_handle* h) {
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->h_state) (void)hipHostFree(h->h_state);
-    if (h->out_live) (void)hipHostFree(h->out_live);
-    if (h->out_seq) (void)hipHostFree(h->out_seq);
-    if (h->res_live) (void)hipHostFree(h->res_live);
-    if (h->res_seq) (void)hipHostFree(h->res_seq);
     delete h;
 }
 
@@ -1834,7 +1753,6 @@ amm_status time_warm_eval(amm_handle* h, double& ms) {
                            h->stream, nullptr);
         HIPC(hipEventRecord(e1, h->stream));
         TRY(pull_out(h));
-        HIPC(hipEventSynchronize(e1));
         float t = 0;
         HIPC(hipEventElapsedTime(&t, e0, e1));
         ms = std::min(ms, (double)t);

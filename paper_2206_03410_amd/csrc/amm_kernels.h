@@ -89,12 +89,6 @@ struct FinalArgs {
     const double* pt_max;
     const double* eg_part;
     const double* nd_part;
-    // when not null: every pair's record is copied to host_out (coherent
-    // pinned host memory) and host_seq[p] = seq is written after it, so the
-    // host can wait on the stamps instead of the stream
-    PairOut* host_out;
-    long long* host_seq;
-    long long seq;
 };
 
 template <typename T>
@@ -287,13 +281,9 @@ void launch_cg_iter(const CgArgs<T>& a, int n_nd_tiles, int it, hipStream_t s, K
 // Coarse matrices A_c = P^T K P and their inverses for the pairs flagged PF_SOLVE.
 template <typename T>
 void launch_coarse(const CoarseArgs<T>& a, int n_nd_tiles, int64_t nagg, int P, hipStream_t s, KernelTimer* tm);
-// The float64 residual and its per-tile sums, also copied (when host_part is
-// not null) to coherent pinned host memory -- (r,r) of tile t at 3t + c, (n,n)
-// at 3 n_nd_tiles + 3t + c -- with host_seq[t] = seq written after them.
 template <typename T>
 void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const T* Bn, const double* x64,
-                       T* rhs_out, double* part_rr, double* part_bb, double* host_part, long long* host_seq,
-                       long long seq, hipStream_t s, KernelTimer* tm);
+                       T* rhs_out, double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm);
 template <typename T>
 void launch_node_vec_op(const NodeVecArgs<T>& a, int n_nd_tiles, hipStream_t s);
 template <typename T>

@@ -638,40 +638,31 @@ __global__ void __launch_bounds__(kNodeTile) k_eval_nodes(EvalArgs<T> a) {
 __global__ void __launch_bounds__(64) k_energy_final(FinalArgs a) {
     const int p = blockIdx.x;
     const PairDyn dy = a.dyn[p];
-    if (dy.flags & PF_EVAL) {
-        const PairInfo pi = a.info[p];
-        double sa = 0, sr = 0, so = 0, mx = 0;
-        // unrolled so that several partials are loaded before their (in-order) sum
+    if (!(dy.flags & PF_EVAL)) return;
+    const PairInfo pi = a.info[p];
+    double sa = 0, sr = 0, so = 0, mx = 0;
+    // unrolled so that several partials are loaded before their (in-order) sum
 #pragma unroll 8
-        for (int t = threadIdx.x; t < pi.pt_ntile; t += 64) {
-            sa += a.pt_part[pi.pt_tile0 + t];
-            mx = fmax(mx, a.pt_max[pi.pt_tile0 + t]);
-        }
-#pragma unroll 4
-        for (int t = threadIdx.x; t < pi.eg_ntile; t += 64) sr += a.eg_part[pi.eg_tile0 + t];
-#pragma unroll 4
-        for (int t = threadIdx.x; t < pi.nd_ntile; t += 64) so += a.nd_part[pi.nd_tile0 + t];
-        sa = wave_sum(sa);
-        sr = wave_sum(sr);
-        so = wave_sum(so);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (threadIdx.x == 0) {
-            PairOut& out = a.out[p];
-            out.Ea = sa;
-            out.Er = sr;
-            out.Eo = so;
-            out.E = sa + dy.alpha * sr + dy.beta * so;
-            out.maxdisp = mx;
-        }
+    for (int t = threadIdx.x; t < pi.pt_ntile; t += 64) {
+        sa += a.pt_part[pi.pt_tile0 + t];
+        mx = fmax(mx, a.pt_max[pi.pt_tile0 + t]);
     }
-    if (a.host_out && threadIdx.x == 0) {
-        // the whole record (fields other kernels wrote included), then the stamp
-        const double* src = reinterpret_cast<const double*>(a.out + p);
-        double* dst = reinterpret_cast<double*>(a.host_out + p);
-        for (int q = 0; q < (int)(sizeof(PairOut) / sizeof(double)); ++q) dst[q] = src[q];
-        __threadfence_system();
-        *reinterpret_cast<volatile long long*>(a.host_seq + p) = a.seq;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < pi.eg_ntile; t += 64) sr += a.eg_part[pi.eg_tile0 + t];
+#pragma unroll 4
+    for (int t = threadIdx.x; t < pi.nd_ntile; t += 64) so += a.nd_part[pi.nd_tile0 + t];
+    sa = wave_sum(sa);
+    sr = wave_sum(sr);
+    so = wave_sum(so);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (threadIdx.x == 0) {
+        PairOut& out = a.out[p];
+        out.Ea = sa;
+        out.Er = sr;
+        out.Eo = so;
+        out.E = sa + dy.alpha * sr + dy.beta * so;
+        out.maxdisp = mx;
     }
 }
 
@@ -1078,16 +1069,12 @@ __global__ void __launch_bounds__(64) k_assemble(AsmArgs<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(4 * kNodeTile) k_residual64(CgArgs<T> a, const T* B, const T* Bn,
                                                               const double* x64, T* rhs_out, double* part_rr,
-                                                              double* part_bb, double* host_part,
-                                                              long long* host_seq, long long seq) {
+                                                              double* part_bb) {
     __shared__ double sh[4 * kNodeTile];
     const int tile = blockIdx.x;
     const int4 td = a.nd_tiles[tile];
     const int p = td.x;
-    if (!(a.dyn[p].flags & PF_SOLVE)) {
-        if (host_seq && threadIdx.x == 0) *reinterpret_cast<volatile long long*>(host_seq + tile) = seq;
-        return;
-    }
+    if (!(a.dyn[p].flags & PF_SOLVE)) return;
     const int lr = threadIdx.x >> 2, r = threadIdx.x & 3;
     const int j = td.y + lr;
     double rv[3] = {0, 0, 0}, bv[3] = {0, 0, 0};
@@ -1115,15 +1102,7 @@ __global__ void __launch_bounds__(4 * kNodeTile) k_residual64(CgArgs<T> a, const
         if (threadIdx.x == 0) {
             part_rr[3 * tile + c] = s;
             part_bb[3 * tile + c] = s2;
-            if (host_part) {
-                host_part[3 * tile + c] = s;
-                host_part[3 * (size_t)gridDim.x + 3 * tile + c] = s2;
-            }
         }
-    }
-    if (host_seq && threadIdx.x == 0) {
-        __threadfence_system();
-        *reinterpret_cast<volatile long long*>(host_seq + tile) = seq;
     }
 }
 
@@ -1665,11 +1644,10 @@ void launch_assemble(const AsmArgs<T>& a, int64_t ntot, hipStream_t s, KernelTim
 
 template <typename T>
 void launch_residual64(const CgArgs<T>& a, int n_nd_tiles, const T* B, const T* Bn, const double* x64,
-                       T* rhs_out, double* part_rr, double* part_bb, double* host_part, long long* host_seq,
-                       long long seq, hipStream_t s, KernelTimer* tm) {
+                       T* rhs_out, double* part_rr, double* part_bb, hipStream_t s, KernelTimer* tm) {
     if (tm) tm->begin("residual64", s);
     hipLaunchKernelGGL(k_residual64<T>, dim3(n_nd_tiles), dim3(4 * kNodeTile), 0, s, a, B, Bn, x64, rhs_out,
-                       part_rr, part_bb, host_part, host_seq, seq);
+                       part_rr, part_bb);
     if (tm) tm->end(s);
 }
 
@@ -1789,7 +1767,7 @@ size_t select_mid_work_bytes(int P) { return (sizeof(SelState) + 256 * sizeof(un
                                  KernelTimer*);                                                               \
     template void launch_assemble<T>(const AsmArgs<T>&, int64_t, hipStream_t, KernelTimer*);                   \
     template void launch_residual64<T>(const CgArgs<T>&, int, const T*, const T*, const double*, T*, double*,  \
-                                       double*, double*, long long*, long long, hipStream_t, KernelTimer*);   \
+                                       double*, hipStream_t, KernelTimer*);                                   \
     template void launch_node_vec_op<T>(const NodeVecArgs<T>&, int, hipStream_t);                             \
     template void launch_aa<T>(const AaArgs<T>&, const AaSolveArgs&, int, hipStream_t, KernelTimer*);          \
     template void launch_grad<T>(const GradArgs<T>&, int, int64_t, hipStream_t);                              \
