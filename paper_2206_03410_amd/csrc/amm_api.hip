@@ -10,7 +10,9 @@
 #include <mutex>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
+#include <thread>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -343,6 +345,8 @@ struct amm_handle {
     long long* prog = nullptr;
     long long* prog_dev = nullptr;
     double* h_scratch = nullptr;     // pinned, grown on demand (small read-backs)
+    char* rb_pin = nullptr;          // pinned staging of the problem arrays read back at set-up
+    size_t rb_cap = 0;
     hipEvent_t sync_ev = nullptr;    // recorded to wait for the stream by polling
     size_t h_scratch_cap = 0;
     size_t h_cap = 0;
@@ -424,6 +428,123 @@ amm_status read_pair(amm_handle* h, const amm_problem& p, HostPair& hp) {
          fetch(p.infl_idx, 4 * (size_t)hp.k * hp.N, hp.infl_idx.data()) &&
          fetch(p.edges, 8 * (size_t)hp.E, hp.edges.data());
     if (!ok) return fail(h, AMM_ERR_HIP, "could not read the problem arrays");
+    return AMM_OK;
+}
+
+// The arrays of one problem in reading order: real arrays in the problem's
+// element type (optional ones may be null), index arrays as int32.
+struct ProblemArray {
+    const void* ptr;
+    size_t count;         // elements
+    bool real;
+    size_t off;           // byte offset in the pinned staging buffer (device arrays)
+};
+
+// Reads the problems into host pairs.  Arrays on the device are copied
+// asynchronously into one pinned staging buffer (kept by the handle) and
+// waited for once; each pair's arrays are then converted or copied into its
+// host vectors on parallel threads.
+amm_status read_pairs(amm_handle* h, const amm_problem* probs, int n_pairs, std::vector<HostPair>& hps) {
+    std::vector<std::array<ProblemArray, 8>> arrs(n_pairs);
+    size_t staged = 0;
+    bool any_device = false;
+    for (int q = 0; q < n_pairs; ++q) {
+        const amm_problem& p = probs[q];
+        HostPair& hp = hps[q];
+        if (p.n_src < 1 || p.n_tgt < 1 || p.n_nodes < 1 || p.k < 1 || p.k > kMaxK || p.n_edges < 0)
+            return fail(h, AMM_ERR_INVALID_ARG, "bad sizes in amm_problem");
+        if (!p.src_xyz || !p.tgt_xyz || !p.node_src_idx || !p.infl_idx || !p.infl_w || (p.n_edges > 0 && !p.edges))
+            return fail(h, AMM_ERR_INVALID_ARG, "null array in amm_problem");
+        if (p.dtype != AMM_F32 && p.dtype != AMM_F64) return fail(h, AMM_ERR_INVALID_ARG, "bad dtype");
+        hp.N = p.n_src;
+        hp.M = p.n_tgt;
+        hp.n = p.n_nodes;
+        hp.E = p.n_edges;
+        hp.k = p.k;
+        hp.lbar = p.mean_edge_len;
+        std::array<ProblemArray, 8>& arr = arrs[q];
+        arr[0] = {p.src_xyz, 3 * (size_t)hp.N, true, 0};
+        arr[1] = {p.tgt_xyz, 3 * (size_t)hp.M, true, 0};
+        arr[2] = {p.src_nrm, p.src_nrm ? 3 * (size_t)hp.N : 0, true, 0};
+        arr[3] = {p.tgt_nrm, p.tgt_nrm ? 3 * (size_t)hp.M : 0, true, 0};
+        arr[4] = {p.infl_w, (size_t)hp.k * hp.N, true, 0};
+        arr[5] = {p.node_src_idx, (size_t)hp.n, false, 0};
+        arr[6] = {p.infl_idx, (size_t)hp.k * hp.N, false, 0};
+        arr[7] = {p.edges, 2 * (size_t)hp.E, false, 0};
+        if (!p.on_device) continue;
+        const size_t es = p.dtype == AMM_F32 ? 4 : 8;
+        for (ProblemArray& a : arr) {
+            if (!a.ptr || !a.count) continue;
+            any_device = true;
+            a.off = staged;
+            staged += (a.count * (a.real ? es : 4) + 255) & ~size_t(255);
+        }
+    }
+    if (any_device) {
+        if (h->rb_cap < staged) {
+            if (h->rb_pin) (void)hipHostFree(h->rb_pin);
+            h->rb_pin = nullptr;
+            h->rb_cap = 0;
+            HIPC(hipHostMalloc((void**)&h->rb_pin, staged));
+            h->rb_cap = staged;
+        }
+        // the arrays may have been written on other streams
+        if (hipDeviceSynchronize() != hipSuccess)
+            return fail(h, AMM_ERR_HIP, "device synchronization failed before reading the problems");
+        for (int q = 0; q < n_pairs; ++q) {
+            if (!probs[q].on_device) continue;
+            const size_t es = probs[q].dtype == AMM_F32 ? 4 : 8;
+            for (const ProblemArray& a : arrs[q]) {
+                if (!a.ptr || !a.count) continue;
+                if (hipMemcpyAsync(h->rb_pin + a.off, a.ptr, a.count * (a.real ? es : 4), hipMemcpyDeviceToHost,
+                                   h->stream) != hipSuccess)
+                    return fail(h, AMM_ERR_HIP, "could not read the problem arrays");
+            }
+        }
+        if (hipStreamSynchronize(h->stream) != hipSuccess)
+            return fail(h, AMM_ERR_HIP, "could not read the problem arrays");
+    }
+    const unsigned hc = std::thread::hardware_concurrency();
+    const int threads = (int)std::min<int64_t>(n_pairs, std::min(16u, std::max(1u, hc)));
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (int q = next.fetch_add(1); q < n_pairs; q = next.fetch_add(1)) {
+            const amm_problem& p = probs[q];
+            HostPair& hp = hps[q];
+            const bool f32 = p.dtype == AMM_F32;
+            std::vector<double>* reals[5] = {&hp.src, &hp.tgt, &hp.src_nrm, &hp.tgt_nrm, &hp.infl_w};
+            std::vector<int32_t>* ints[3] = {&hp.node_idx, &hp.infl_idx, &hp.edges};
+            for (int a = 0; a < 8; ++a) {
+                const ProblemArray& pa = arrs[q][a];
+                const void* from = p.on_device ? (const void*)(h->rb_pin + pa.off) : pa.ptr;
+                if (pa.real) {
+                    std::vector<double>& out = *reals[a];
+                    if (!pa.ptr || !pa.count) {
+                        out.clear();
+                        continue;
+                    }
+                    out.resize(pa.count);
+                    if (f32) {
+                        const float* f = static_cast<const float*>(from);
+                        for (size_t i = 0; i < pa.count; ++i) out[i] = f[i];
+                    } else {
+                        std::memcpy(out.data(), from, pa.count * 8);
+                    }
+                } else {
+                    std::vector<int32_t>& out = *ints[a - 5];
+                    out.resize(pa.count);
+                    if (pa.count) std::memcpy(out.data(), from, pa.count * 4);
+                }
+            }
+        }
+    };
+    if (threads <= 1) {
+        work();
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < threads; ++t) pool.emplace_back(work);
+        for (auto& th : pool) th.join();
+    }
     return AMM_OK;
 }
 
@@ -1350,10 +1471,8 @@ amm_status analyse(amm_handle* h, const amm_problem* probs, int32_t n_pairs, Lay
     if (!probs || n_pairs < 1) return fail(h, AMM_ERR_INVALID_ARG, "need at least one problem");
     std::vector<HostPair> hps(n_pairs);
     lbar.resize(n_pairs);
-    for (int p = 0; p < n_pairs; ++p) {
-        TRY(read_pair(h, probs[p], hps[p]));
-        lbar[p] = hps[p].lbar;
-    }
+    TRY(read_pairs(h, probs, n_pairs, hps));
+    for (int p = 0; p < n_pairs; ++p) lbar[p] = hps[p].lbar;
     std::string err;
     amm_status s = validate_pairs(hps, err);
     if (s != AMM_OK) return fail(h, s, err);
@@ -1567,6 +1686,7 @@ void amm_destroy(amm_handle* h) {
     if (h->graph) graph_release(h->graph);
     if (h->tw.buf) (void)hipFree(h->tw.buf);
     if (h->h_scratch) (void)hipHostFree(h->h_scratch);
+    if (h->rb_pin) (void)hipHostFree(h->rb_pin);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->h_out) (void)hipHostFree(h->h_out);
@@ -1651,7 +1771,13 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     c2.base = base;
     plan(L, c2, v);
     h->v = v;
-    h->L = std::move(L);
+    // the previous layout (hundreds of MB for a large batch) is freed on a
+    // thread of its own, off the set-up's critical path
+    {
+        Layout old = std::move(h->L);
+        h->L = std::move(L);
+        std::thread([o = std::move(old)]() mutable { Layout gone = std::move(o); }).detach();
+    }
     h->lbar = lb;
     const Layout& Lr = h->L;
     TRY(ensure_host(h, Lr.P));

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import amm_oracle as O
 from paper_2206_03410_amd import amm, synth
-from tests.helpers import Session, margin_ok, rounded
+from tests.helpers import Session, gpu_problem, margin_ok, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -265,6 +265,45 @@ def test_batched_equals_single():
             assert np.array_equal(Xb[off:off + pr.n_nodes], Xs)
             off += pr.n_nodes
         outs.append(st)
+
+
+def test_setup_from_host_and_device_arrays_agree():
+    """A batch whose pairs are given partly in host memory (numpy, float64
+    and float32) and partly on the device solves bitwise like the same
+    batch given as device tensors (float32 pairs rounded alike): the set-up
+    reads device arrays through one staged copy and host arrays directly."""
+    _announce("test_setup_from_host_and_device_arrays_agree")
+    pairs = [synth.torus_pair(1200 + 7 * b, n_src=n, n_tgt=n + 30, n_nodes=nn, k=4, e=6)
+             for b, (n, nn) in enumerate([(400, 25), (650, 40), (900, 60)])]
+    dts = [np.float64, np.float32, np.float64]
+
+    def host_problem(pr, dt):
+        c = lambda a, t: np.ascontiguousarray(np.asarray(a, t))
+        return amm.make_problem(c(pr.src, dt), c(pr.tgt, dt), c(pr.node_idx, np.int32), c(pr.infl_idx, np.int32),
+                                c(pr.infl_w, dt), c(pr.edges, np.int32), pr.mean_edge_len)
+
+    def device_problem(pr, dt):
+        tdt = torch.float64 if dt == np.float64 else torch.float32
+        return gpu_problem(pr, tdt)
+
+    tot = sum(p.n_nodes for p in pairs)
+    res = []
+    for mix in ([device_problem] * 3, [host_problem, device_problem, host_problem],
+                [host_problem, host_problem, host_problem]):
+        h = amm.amm_create(0, torch.cuda.current_stream().cuda_stream)
+        try:
+            probs = [f(pr, dt) for f, pr, dt in zip(mix, pairs, dts)]
+            amm.amm_set_problems(h, probs)
+            X = torch.empty(tot, 4, 3, dtype=torch.float64, device="cuda:0")
+            st = amm.amm_solve(h, amm.amm_params_default(aa_m=5, max_total_iters=12, precision=amm.AMM_FP64_PLAIN),
+                               X, n_pairs=3)
+            torch.cuda.synchronize()
+            res.append((X.cpu().numpy(), [x["energy"] for x in st]))
+        finally:
+            amm.amm_destroy(h)
+    for X, E in res[1:]:
+        assert np.array_equal(X, res[0][0])
+        assert E == res[0][1]
 
 
 def test_identical_pair_stays_at_identity():
