@@ -132,11 +132,13 @@ struct Layout {
     std::vector<int32_t> node_pair;  // internal node -> pair
     std::vector<int32_t> adj_ptr, adj_nbr, adj_row, adj_rev;   // directed CSR
     std::vector<double> adj_r;       // r_ij of Eq. (8)
-    std::vector<int32_t> K_ptr, K_col, K_adj, K_diag;
-    std::vector<int32_t> pj_ptr, pj_ent;   // points influenced by each node: (pt << 3) | slot
+    std::vector<int32_t> K_ptr, K_diag;
+    hvec<int32_t> K_col, K_adj;           // written in full by the merge of the pairs' parts
+    std::vector<int32_t> pj_ptr;
+    hvec<int32_t> pj_ent;   // points influenced by each node: (pt << 3) | slot (written by the pairs' threads)
     // per point-list entry of row j: byte b = position, within row j's column
     // list, of the point's influence b
-    std::vector<uint64_t> pj_pos;
+    hvec<uint64_t> pj_pos;
     hvec<double> tgt4;        // [Mtot][4] sorted; w = user index within the pair
     hvec<int32_t> tgt_user;   // sorted position -> user index within the pair
     std::vector<int32_t> pt_tiles, nd_tiles, eg_tiles;   // [tiles][4] = pair, start, end, 0
@@ -148,7 +150,7 @@ struct Layout {
     std::vector<int32_t> aggs;       // [nagg][4]
     std::vector<double> node_rel;    // [ntot][4]
     std::vector<int32_t> tile_agg_ptr, tile_agg;
-    std::vector<int32_t> grid_cells;   // per pair, the target octree's run-start tables
+    hvec<int32_t> grid_cells;   // per pair, the target octree's run-start tables
     // per node tile, the distinct column nodes of its rows of K (sorted;
     // [tiles][kTileColCap], padded with the first), their count (a tile with
     // more than kTileColCap has no list), the local index of every K block's

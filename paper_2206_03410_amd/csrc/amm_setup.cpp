@@ -249,19 +249,19 @@ struct PairPart {
     std::vector<int32_t> K_rowptr;   // [n + 1] local offsets into K_col
     std::vector<int32_t> K_diag;     // [n] local positions of the diagonal blocks
     std::vector<int32_t> K_col, K_adj;
-    std::vector<int32_t> pj_rowptr;  // [n + 1] local offsets into pj_ent
-    std::vector<int32_t> pj_ent;
-    std::vector<uint64_t> pj_pos;
+    std::vector<int32_t> pj_rowptr;  // [n + 1] local offsets into the pair's point lists
     std::vector<int32_t> cells;      // octree run-start tables
     std::vector<int32_t> aggs;       // [nagg][4]
     std::vector<int32_t> tile_agg_cnt, tile_agg;
     int max_row_cols = 0;
 };
 
-// Everything of pair p: the fixed-size arrays are written in place at the
-// pair's offsets (so, to, no, ao), the rest goes to `part`.
+// Everything of pair p: the fixed-size arrays and the point lists (whose
+// length, the pair's influence slots that are not padding, is counted
+// beforehand) are written in place at the pair's offsets (so, to, no, ao,
+// po), the rest goes to `part`.
 amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, int64_t to, int64_t no, int64_t ao,
-                      Layout& L, PairPart& part, std::string& err) {
+                      int64_t po, int64_t pcount, Layout& L, PairPart& part, std::string& err) {
     PairInfo& pi = part.pi;
     pi.src_off = so;
     pi.N = hp.N;
@@ -367,14 +367,19 @@ amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, in
         for (int a = 0; a < k; ++a)
             if (!L.ipad[(size_t)a * L.Ntot + so + q]) ++part.pj_rowptr[L.iidx[(size_t)a * L.Ntot + so + q] - no + 1];
     for (int64_t q = 0; q < hp.n; ++q) part.pj_rowptr[q + 1] += part.pj_rowptr[q];
-    part.pj_ent.resize(part.pj_rowptr[hp.n]);
+    if (part.pj_rowptr[hp.n] != pcount) {
+        err = "point list length differs from the count of influence slots";
+        return AMM_ERR_INVALID_ARG;
+    }
+    int32_t* const pj_ent = L.pj_ent.data() + po;
+    uint64_t* const pj_pos = L.pj_pos.data() + po;
     {
         std::vector<int32_t> fill(part.pj_rowptr.begin(), part.pj_rowptr.end() - 1);
         for (int64_t q = 0; q < hp.N; ++q)
             for (int a = 0; a < k; ++a) {
                 if (L.ipad[(size_t)a * L.Ntot + so + q]) continue;
                 const int64_t ja = L.iidx[(size_t)a * L.Ntot + so + q] - no;
-                part.pj_ent[fill[ja]++] = (int32_t)(((so + q) << 3) | a);
+                pj_ent[fill[ja]++] = (int32_t)(((so + q) << 3) | a);
             }
     }
     // block pattern of K, row by row: the diagonal, the nodes that share an
@@ -382,7 +387,6 @@ amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, in
     // (distinct, sorted); then each point entry's k column positions
     part.K_rowptr.assign(hp.n + 1, 0);
     part.K_diag.assign(hp.n, 0);
-    part.pj_pos.resize(part.pj_ent.size());
     {
         std::vector<int32_t> mark(hp.n, -1), posof(hp.n, 0), c;
         c.reserve(256);
@@ -396,7 +400,7 @@ amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, in
             };
             add((int32_t)(no + q));
             for (int32_t e = part.pj_rowptr[q]; e < part.pj_rowptr[q + 1]; ++e) {
-                const int64_t i = part.pj_ent[e] >> 3;
+                const int64_t i = pj_ent[e] >> 3;
                 for (int b = 0; b < k; ++b)
                     if (!L.ipad[(size_t)b * L.Ntot + i]) add(L.iidx[(size_t)b * L.Ntot + i]);
             }
@@ -423,14 +427,14 @@ amm_status build_pair(const HostPair& hp, int p, int k, int leaf, int64_t so, in
                 part.K_adj.push_back(adj);
             }
             for (int32_t e = part.pj_rowptr[q]; e < part.pj_rowptr[q + 1]; ++e) {
-                const int64_t i = part.pj_ent[e] >> 3;
+                const int64_t i = pj_ent[e] >> 3;
                 uint64_t pos = 0;
                 for (int b = 0; b < k; ++b) {
                     uint64_t bpos = kPosUnused;
                     if (!L.ipad[(size_t)b * L.Ntot + i]) bpos = (uint64_t)posof[L.iidx[(size_t)b * L.Ntot + i] - no];
                     pos |= bpos << (8 * b);
                 }
-                part.pj_pos[e] = pos;
+                pj_pos[e] = pos;
             }
         }
     }
@@ -544,6 +548,23 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     L.tgt4.resize(4 * L.Mtot);
     L.tgt_user.resize(L.Mtot);
 
+    // the point lists' offsets: one entry per influence slot that is not
+    // padding
+    std::vector<int64_t> pb(L.P + 1, 0);
+    parallel_for(L.P, host_threads(), [&](int64_t p) {
+        const HostPair& hp = pairs[p];
+        int64_t c = 0;
+        for (size_t e = 0; e < hp.infl_idx.size(); ++e) c += hp.infl_idx[e] != -1;
+        pb[p + 1] = c;
+    });
+    for (int p = 0; p < L.P; ++p) pb[p + 1] += pb[p];
+    if (pb[L.P] >= INT32_MAX) {
+        err = "the batch's point lists exceed 32-bit indexing";
+        return AMM_ERR_INVALID_ARG;
+    }
+    L.pj_ent.resize(pb[L.P]);
+    L.pj_pos.resize(pb[L.P]);
+
     // pairs in parallel (each writes its own ranges), then merged in order
     std::vector<PairPart> parts(L.P);
     std::vector<amm_status> sts(L.P, AMM_OK);
@@ -556,7 +577,8 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
     });
     parallel_for(L.P, host_threads(), [&](int64_t r) {
         const int p = by_size[r];
-        sts[p] = build_pair(pairs[p], p, k, leaf, so[p], to[p], no[p], ao[p], L, parts[p], errs[p]);
+        sts[p] = build_pair(pairs[p], p, k, leaf, so[p], to[p], no[p], ao[p], pb[p], pb[p + 1] - pb[p], L, parts[p],
+                            errs[p]);
     });
     for (int p = 0; p < L.P; ++p)
         if (sts[p] != AMM_OK) {
@@ -565,27 +587,25 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         }
     // offsets of every pair's variable-length parts, then the copies (in
     // parallel: disjoint ranges)
-    std::vector<int64_t> kb(L.P + 1, 0), pb(L.P + 1, 0), cb(L.P + 1, 0), gb(L.P + 1, 0), tb(L.P + 1, 0);
+    std::vector<int64_t> kb(L.P + 1, 0), cb(L.P + 1, 0), gb(L.P + 1, 0), tb(L.P + 1, 0);
     for (int p = 0; p < L.P; ++p) {
         kb[p + 1] = kb[p] + (int64_t)parts[p].K_col.size();
-        pb[p + 1] = pb[p] + (int64_t)parts[p].pj_ent.size();
         cb[p + 1] = cb[p] + (int64_t)parts[p].cells.size();
         gb[p + 1] = gb[p] + (int64_t)parts[p].aggs.size();
         tb[p + 1] = tb[p] + (int64_t)parts[p].tile_agg.size();
     }
-    if (kb[L.P] >= INT32_MAX || pb[L.P] >= INT32_MAX) {
-        err = "the batch's blocks of K or point lists exceed 32-bit indexing";
+    if (kb[L.P] >= INT32_MAX) {
+        err = "the batch's blocks of K exceed 32-bit indexing";
         return AMM_ERR_INVALID_ARG;
     }
     L.K_col.resize(kb[L.P]);
     L.K_adj.resize(kb[L.P]);
-    L.pj_ent.resize(pb[L.P]);
-    L.pj_pos.resize(pb[L.P]);
     L.grid_cells.resize(cb[L.P]);
     L.aggs.resize(gb[L.P]);
     L.tile_agg.resize(tb[L.P]);
-    parallel_for(L.P, host_threads(), [&](int64_t p) {
-        const PairPart& part = parts[p];
+    parallel_for(L.P, host_threads(), [&](int64_t r) {
+        const int p = by_size[r];
+        PairPart& part = parts[p];
         const int64_t n = pairs[p].n;
         for (int64_t q = 0; q < n; ++q) {
             L.K_ptr[no[p] + q] = (int32_t)(kb[p] + part.K_rowptr[q]);
@@ -594,11 +614,17 @@ amm_status build_layout(const std::vector<HostPair>& pairs, int leaf, Layout& L,
         }
         std::copy(part.K_col.begin(), part.K_col.end(), L.K_col.begin() + kb[p]);
         std::copy(part.K_adj.begin(), part.K_adj.end(), L.K_adj.begin() + kb[p]);
-        std::copy(part.pj_ent.begin(), part.pj_ent.end(), L.pj_ent.begin() + pb[p]);
-        std::copy(part.pj_pos.begin(), part.pj_pos.end(), L.pj_pos.begin() + pb[p]);
         std::copy(part.cells.begin(), part.cells.end(), L.grid_cells.begin() + cb[p]);
         std::copy(part.aggs.begin(), part.aggs.end(), L.aggs.begin() + gb[p]);
         std::copy(part.tile_agg.begin(), part.tile_agg.end(), L.tile_agg.begin() + tb[p]);
+        // the copied parts are released here, in parallel
+        std::vector<int32_t>().swap(part.K_rowptr);
+        std::vector<int32_t>().swap(part.K_diag);
+        std::vector<int32_t>().swap(part.K_col);
+        std::vector<int32_t>().swap(part.K_adj);
+        std::vector<int32_t>().swap(part.pj_rowptr);
+        std::vector<int32_t>().swap(part.cells);
+        std::vector<int32_t>().swap(part.tile_agg);
     });
     L.tile_agg_ptr.push_back(0);
     for (int p = 0; p < L.P; ++p) {
