@@ -548,11 +548,14 @@ amm_status read_pairs(amm_handle* h, const amm_problem* probs, int n_pairs, std:
     return AMM_OK;
 }
 
+// Uploads of the layout: stream-ordered, with no wait of their own (the
+// layout's host arrays outlive them: amm_set_problems waits for the stream
+// before it returns, and the uploads through the device staging buffer
+// follow one another on the stream).
 template <typename P, typename A>
 amm_status up(amm_handle* h, P* dst, const std::vector<P, A>& src) {
     if (src.empty()) return AMM_OK;
     HIPC(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(P), hipMemcpyHostToDevice, h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
     return AMM_OK;
 }
 
@@ -563,7 +566,7 @@ amm_status up_real(amm_handle* h, PF* dst_f, PD* dst_d, const std::vector<double
     HIPC(hipMemcpyAsync(h->v.staging, src.data(), src.size() * 8, hipMemcpyHostToDevice, h->stream));
     launch_cast_static<float>(h->v.staging, reinterpret_cast<float*>(dst_f), (int64_t)src.size(), h->stream);
     launch_cast_static<double>(h->v.staging, reinterpret_cast<double*>(dst_d), (int64_t)src.size(), h->stream);
-    HIPC(hipStreamSynchronize(h->stream));
+    HIPC(hipGetLastError());
     return AMM_OK;
 }
 
