@@ -764,9 +764,26 @@ __global__ void __launch_bounds__(256) k_coarse_tiles(CoarseArgs<T> a) {
             const int o = tid + 256 * h;
             const int s2 = o >> 4, m = o & 15;
             if (s2 < ns) {
+                // entries in order; one of another slot adds +0.0, which
+                // leaves the sum's bits as skipping it would (the sum only
+                // reaches acc0/acc1, which never hold -0), and lets eight
+                // reads be in flight together
                 double v = 0;
-                for (int t = 0; t < cnt; ++t)
-                    if (slot_of[t] == s2) v += contrib[t][m];
+                int t = 0;
+                for (; t + 8 <= cnt; t += 8) {
+                    double x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const double c = contrib[t + u][m];
+                        x[u] = slot_of[t + u] == s2 ? c : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v += x[u];
+                }
+                for (; t < cnt; ++t) {
+                    const double c = contrib[t][m];
+                    v += slot_of[t] == s2 ? c : 0.0;
+                }
                 if (h == 0) acc0 += v;
                 else acc1 += v;
             }
