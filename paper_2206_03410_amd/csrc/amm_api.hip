@@ -348,6 +348,7 @@ struct amm_handle {
     char* rb_pin = nullptr;          // pinned staging of the problem arrays read back at set-up
     size_t rb_cap = 0;
     hipEvent_t sync_ev = nullptr;    // recorded to wait for the stream by polling
+    std::thread freer;               // frees the previous layout after a new set-up
     size_t h_scratch_cap = 0;
     size_t h_cap = 0;
     bool timing = false;
@@ -1682,6 +1683,7 @@ amm_status amm_create(amm_handle** out, int device, void* stream) {
 
 void amm_destroy(amm_handle* h) {
     if (!h) return;
+    if (h->freer.joinable()) h->freer.join();
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
     if (h->prog) (void)hipHostFree(h->prog);
@@ -1775,11 +1777,13 @@ amm_status amm_set_problems(amm_handle* h, const amm_problem* probs, int32_t n_p
     plan(L, c2, v);
     h->v = v;
     // the previous layout (hundreds of MB for a large batch) is freed on a
-    // thread of its own, off the set-up's critical path
+    // thread of its own, off the set-up's critical path; the handle joins it
+    // at the next set-up or when it is destroyed
     {
+        if (h->freer.joinable()) h->freer.join();
         Layout old = std::move(h->L);
         h->L = std::move(L);
-        std::thread([o = std::move(old)]() mutable { Layout gone = std::move(o); }).detach();
+        h->freer = std::thread([o = std::move(old)]() mutable { Layout gone = std::move(o); });
     }
     h->lbar = lb;
     const Layout& Lr = h->L;
