@@ -219,17 +219,38 @@ __device__ __forceinline__ int group_excl_scan(int v, int gl, int& total) {
 // far (seeded by the budgeted search's best).  A level with more cells than
 // the frontier holds falls back to one lane running oct_search from the
 // best so far.  The point is then finished as in k_eval_points.
+template <typename T>
+__device__ void eval_edges_tile(const EvalArgs<T>& a, int tile);
+template <typename T>
+__device__ void eval_nodes_group(const EvalArgs<T>& a, int tile, int gl, int n_nd_tiles);
+constexpr int kNodeGroups = 64 * kFarWaves / kNodeTile;   // node tiles per block of k_eval_far
+static_assert(64 * kFarWaves == kEdgeTile, "an edge tile is one block of k_eval_far");
+
+// Blocks past the first far_blocks evaluate the regularization terms (one
+// edge tile per block, then kNodeGroups node tiles per block): they depend
+// on the transforms only, and run on the compute units that the few long
+// deferred searches leave idle.
 template <typename T, bool COUNT>
-__global__ void __launch_bounds__(64 * kFarWaves) k_eval_far(EvalArgs<T> a) {
+__global__ void __launch_bounds__(64 * kFarWaves) k_eval_far(EvalArgs<T> a, int far_blocks, int n_eg_tiles,
+                                                              int n_nd_tiles) {
     using V = typename V4Of<T>::type;
     __shared__ uint32_t fr[kFarWaves * kFarPts][2][kFarCap];
     __shared__ int2 runs[kFarWaves * kFarPts][kFarRuns];
+    if ((int)blockIdx.x >= far_blocks) {
+        const int b = (int)blockIdx.x - far_blocks;
+        if (b < n_eg_tiles)
+            eval_edges_tile<T>(a, b);
+        else
+            eval_nodes_group<T>(a, (b - n_eg_tiles) * kNodeGroups + (int)threadIdx.x / kNodeTile,
+                                (int)threadIdx.x % kNodeTile, n_nd_tiles);
+        return;
+    }
     const int lane = (int)threadIdx.x & 63;
     const int gl = lane & (kFarGroup - 1);
     const int g = (int)threadIdx.x / kFarGroup;    // group slot in the block
     const int nfar = (int)min((int64_t)*a.far_count, a.Ntot);
     const V* src = a.src_override ? (const V*)a.src_override : (const V*)a.src;
-    const int stride = (int)gridDim.x * kFarWaves * kFarPts;
+    const int stride = far_blocks * kFarWaves * kFarPts;
     for (int h = (int)blockIdx.x * kFarWaves * kFarPts + g; h < nfar; h += stride) {
         const int2 e = a.far_list[h];
         const int i = e.x, p = e.y;
@@ -459,11 +480,11 @@ __global__ void __launch_bounds__(kPointTile) k_eval_sums(EvalArgs<T> a) {
 // p_a), Welsch value and weight (Eqs. 9, 14).  Evaluated as
 // r ((A_b - I)(p_a - p_b) + t_b - t_a), equal to Eq. (7) and free of the
 // cancellation between p_a and p_b.
+// (one block of kEdgeTile threads per edge tile)
 template <typename T>
-__global__ void __launch_bounds__(kEdgeTile) k_eval_edges(EvalArgs<T> a) {
+__device__ void eval_edges_tile(const EvalArgs<T>& a, int tile) {
     using V = typename V4Of<T>::type;
     __shared__ T sh[kEdgeTile];
-    const int tile = blockIdx.x;
     const int4 td = a.eg_tiles[tile];
     const int p = td.x;
     const PairDyn dy = a.dyn[p];
@@ -500,6 +521,11 @@ __global__ void __launch_bounds__(kEdgeTile) k_eval_edges(EvalArgs<T> a) {
     }
     const T tot = block_sum<T, kEdgeTile>(psi, sh);
     if (threadIdx.x == 0) a.eg_part[tile] = (double)tot;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kEdgeTile) k_eval_edges(EvalArgs<T> a) {
+    eval_edges_tile<T>(a, (int)blockIdx.x);
 }
 
 // Closest rotation to a 3x3 matrix A (rotation term, Sec. 3.2): one-sided
@@ -631,6 +657,36 @@ __global__ void __launch_bounds__(kNodeTile) k_eval_nodes(EvalArgs<T> a) {
     }
     const double tot = block_sum<double, kNodeTile>(er, sh);
     if (threadIdx.x == 0) a.nd_part[tile] = tot;
+}
+
+// k_eval_nodes for one node tile on a group of kNodeTile lanes of a wider
+// block (lane gl of the group on node gl of the tile): the same terms, and
+// the tile's sum by shuffles in block_sum's order (lane i adds lane i + 8,
+// then i + 4, i + 2, i + 1), so nd_part is bitwise the same.
+template <typename T>
+__device__ void eval_nodes_group(const EvalArgs<T>& a, int tile, int gl, int n_nd_tiles) {
+    static_assert(kNodeTile == 16, "the shuffle tree below is written for 16 lanes");
+    if (tile >= n_nd_tiles) return;   // uniform over the group
+    const int4 td = a.nd_tiles[tile];
+    const PairDyn dy = a.dyn[td.x];
+    if (!(dy.flags & PF_EVAL)) return;
+    const int j = td.y + gl;
+    const T* X = a.X[dy.eval_x];
+    double er = 0;
+    if (j < td.z) {
+        double A[3][3], R[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) A[c][r] = (double)X[12 * (size_t)j + 3 * r + c];
+        er = proj_rot<double>(A, R);
+        T* Ro = a.R[dy.eval_dst] + 9 * (size_t)j;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Ro[3 * r + c] = (T)(R[r][c] - A[r][c]);
+    }
+    er += __shfl_down(er, 8, kNodeTile);
+    er += __shfl_down(er, 4, kNodeTile);
+    er += __shfl_down(er, 2, kNodeTile);
+    er += __shfl_down(er, 1, kNodeTile);
+    if (gl == 0) a.nd_part[tile] = er;
 }
 
 // Per pair: E = E_align + alpha E_reg + beta E_rot (Eq. 4) from the tile
@@ -1618,21 +1674,22 @@ void launch_eval(const EvalArgs<T>& a, int n_pt_tiles, int n_eg_tiles, int n_nd_
         // budgeted searches, then the deferred points one wave each, then the
         // tile sums (the deferred points' count is only known on the device:
         // a fixed grid strides over it)
+        // (the edge and node terms ride on the deferred searches' launch)
         const int far_blocks = (int)std::min<int64_t>(1024, (a.Ntot + kFarWaves * kFarPts - 1) / (kFarWaves * kFarPts));
+        const unsigned grid = (unsigned)(far_blocks + n_eg_tiles + (n_nd_tiles + kNodeGroups - 1) / kNodeGroups);
         if (a.nn_work) {
             launch_one(tm, "eval_points", k_eval_points<T, true>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
-            launch_one(tm, "eval_far", k_eval_far<T, true>, dim3(far_blocks), dim3(64 * kFarWaves), s, a);
+            launch_one(tm, "eval_far", k_eval_far<T, true>, dim3(grid), dim3(64 * kFarWaves), s, a, far_blocks,
+                       n_eg_tiles, n_nd_tiles);
         } else {
             launch_one(tm, "eval_points", k_eval_points<T, false>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
-            launch_one(tm, "eval_far", k_eval_far<T, false>, dim3(far_blocks), dim3(64 * kFarWaves), s, a);
+            launch_one(tm, "eval_far", k_eval_far<T, false>, dim3(grid), dim3(64 * kFarWaves), s, a, far_blocks,
+                       n_eg_tiles, n_nd_tiles);
         }
         launch_one(tm, "eval_sums", k_eval_sums<T>, dim3(n_pt_tiles), dim3(kPointTile), s, a);
-    }
-    if (n_eg_tiles) {
-        launch_one(tm, "eval_edges", k_eval_edges<T>, dim3(n_eg_tiles), dim3(kEdgeTile), s, a);
-    }
-    if (n_nd_tiles) {
-        launch_one(tm, "eval_nodes", k_eval_nodes<T>, dim3(n_nd_tiles), dim3(kNodeTile), s, a);
+    } else {
+        if (n_eg_tiles) launch_one(tm, "eval_edges", k_eval_edges<T>, dim3(n_eg_tiles), dim3(kEdgeTile), s, a);
+        if (n_nd_tiles) launch_one(tm, "eval_nodes", k_eval_nodes<T>, dim3(n_nd_tiles), dim3(kNodeTile), s, a);
     }
     launch_one(tm, "energy_final", k_energy_final, dim3(P), dim3(64), s, f);
 }
